@@ -1,0 +1,212 @@
+"""FP64 CPU oracle of the multilevel summation method (test infrastructure only).
+
+Only the test suite, the package smoke check and the benchmark's CPU-baseline
+leg may import this package.  The GPU product path does not import it, and the
+two share no code; only the seeded input generators feed both.
+
+The arithmetic lives in ``msm_oracle.c`` (plain C, double precision, OpenMP
+over independent outputs), which follows Sec. 2.3 of the thesis stage by
+stage.  This module loads it with ctypes and marshals numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "msm_oracle.c")
+_LIB = os.path.join(_HERE, "libmsm_oracle.so")
+
+ERRORS = {0: "ok", -1: "invalid argument", -2: "atom outside box", -3: "non-finite input",
+          -7: "coincident atoms"}
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code):
+        super().__init__(f"oracle error {code}: {ERRORS.get(code, '?')}")
+        self.code = code
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_double), ("h", ctypes.c_double), ("order", ctypes.c_int),
+                ("m", ctypes.c_int), ("levels", ctypes.c_int), ("lo", ctypes.c_double * 3),
+                ("len", ctypes.c_double * 3), ("ke", ctypes.c_double)]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-ffp-contract=off",
+                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _LIB if os.path.exists(_LIB) else build()
+        L = ctypes.CDLL(path)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.oracle_msm.restype = ctypes.c_int
+        L.oracle_msm.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, dp, dp, dp, dp, dp, dp, dp,
+                                 dp, dp, dp, dp, dp, dp, dp, ip, ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_int]
+        L.oracle_layout.restype = ctypes.c_int
+        L.oracle_layout.argtypes = [ctypes.POINTER(_Params), ip, ip, ip]
+        L.oracle_direct.restype = ctypes.c_int
+        L.oracle_direct.argtypes = [ctypes.c_int, dp, dp, dp, dp, ctypes.c_double, dp, dp, dp, dp,
+                                    dp, ctypes.c_int]
+        for name in ("oracle_gamma", "oracle_dgamma"):
+            getattr(L, name).restype = ctypes.c_double
+            getattr(L, name).argtypes = [ctypes.c_int, ctypes.c_double]
+        for name in ("oracle_Phi", "oracle_dPhi"):
+            getattr(L, name).restype = ctypes.c_double
+            getattr(L, name).argtypes = [ctypes.c_int, ctypes.c_double]
+        L.oracle_split_kernel.restype = ctypes.c_double
+        L.oracle_split_kernel.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, ctypes.c_double]
+        L.oracle_gamma_coeffs.restype = None
+        L.oracle_gamma_coeffs.argtypes = [ctypes.c_int, dp]
+        _lib = L
+    return _lib
+
+
+def _params(cutoff, spacing, order=4, split_m=0, levels=0, box_lo=(0, 0, 0), box_len=(1, 1, 1),
+            ke=1.0, **_):
+    p = _Params()
+    p.a, p.h, p.order, p.m, p.levels = float(cutoff), float(spacing), int(order), int(split_m), int(levels)
+    for d in range(3):
+        p.lo[d] = float(box_lo[d])
+        p.len[d] = float(box_len[d])
+    p.ke = float(ke)
+    return p
+
+
+def _dptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def layout(**params):
+    """Level count and per-level node ranges: (levels, lo[L,3], n[L,3])."""
+    p = _params(**params)
+    lo = np.zeros(3 * 16, dtype=np.int32)
+    n = np.zeros(3 * 16, dtype=np.int32)
+    lv = ctypes.c_int(0)
+    ip = ctypes.POINTER(ctypes.c_int)
+    rc = lib().oracle_layout(ctypes.byref(p), ctypes.byref(lv), lo.ctypes.data_as(ip), n.ctypes.data_as(ip))
+    if rc:
+        raise OracleError(rc)
+    L = lv.value
+    return L, lo[:3 * L].reshape(L, 3).copy(), n[:3 * L].reshape(L, 3).copy()
+
+
+def split_grids(flat, n):
+    """Cut a concatenated level array into per-level [nz, ny, nx] views."""
+    out, off = [], 0
+    for k in range(n.shape[0]):
+        cnt = int(np.prod(n[k]))
+        out.append(flat[off:off + cnt].reshape(int(n[k][2]), int(n[k][1]), int(n[k][0])))
+        off += cnt
+    return out
+
+
+def msm(x, y, z, q, *, cutoff, spacing, order=4, split_m=0, levels=0, box_lo=(0, 0, 0),
+        box_len=(1, 1, 1), ke=1.0, grids=False, sample=None, short_mode=0, threads=0):
+    """Run the FP64 oracle.
+
+    Returns a dict with energy, forces f[3,N], potentials phi[N], virial[3,3],
+    the short-range potential phis[N] and (grids=True) the per-level grids
+    q (charges), ucut (lattice-cutoff / top-level sums) and u (prolongated).
+    With ``sample`` (atom indices) only those atoms' outputs are computed;
+    energy and virial are then absent.
+    """
+    x, y, z, q = _f64(x), _f64(y), _f64(z), _f64(q)
+    n = int(x.shape[0])
+    prm = dict(cutoff=cutoff, spacing=spacing, order=order, split_m=split_m, levels=levels,
+               box_lo=box_lo, box_len=box_len, ke=ke)
+    p = _params(**prm)
+    L, glo, gn = layout(**prm)
+    ng = int(sum(int(np.prod(v)) for v in gn))
+    fx, fy, fz = np.zeros(n), np.zeros(n), np.zeros(n)
+    phi, phis = np.zeros(n), np.zeros(n)
+    e = np.zeros(1)
+    w = np.zeros(9)
+    qg = np.zeros(ng) if grids else None
+    uc = np.zeros(ng) if grids else None
+    ug = np.zeros(ng) if grids else None
+    if sample is not None:
+        smp = np.ascontiguousarray(np.asarray(sample, dtype=np.int32))
+        sptr, ns = smp.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), int(smp.shape[0])
+    else:
+        sptr, ns = None, n
+    rc = lib().oracle_msm(ctypes.byref(p), n, _dptr(x), _dptr(y), _dptr(z), _dptr(q), _dptr(fx),
+                          _dptr(fy), _dptr(fz), _dptr(phi), _dptr(e), _dptr(w), _dptr(qg), _dptr(uc),
+                          _dptr(ug), _dptr(phis), sptr, ns, int(short_mode), int(threads))
+    if rc:
+        raise OracleError(rc)
+    out = dict(f=np.stack([fx, fy, fz]), phi=phi, phis=phis, levels=L, glo=glo, gn=gn)
+    if sample is None:
+        out["energy"] = float(e[0])
+        out["virial"] = w.reshape(3, 3)
+    if grids:
+        out["q"] = split_grids(qg, gn)
+        out["ucut"] = split_grids(uc, gn)
+        out["u"] = split_grids(ug, gn)
+    return out
+
+
+def direct(x, y, z, q, ke=1.0, threads=0):
+    """Exact direct Coulomb sum over all unordered pairs (eq. coulomb, FP64)."""
+    x, y, z, q = _f64(x), _f64(y), _f64(z), _f64(q)
+    n = int(x.shape[0])
+    fx, fy, fz, phi, e = np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(1)
+    rc = lib().oracle_direct(n, _dptr(x), _dptr(y), _dptr(z), _dptr(q), float(ke), _dptr(fx),
+                             _dptr(fy), _dptr(fz), _dptr(phi), _dptr(e), int(threads))
+    if rc:
+        raise OracleError(rc)
+    return dict(f=np.stack([fx, fy, fz]), phi=phi, energy=float(e[0]))
+
+
+def gamma(m, rho):
+    return lib().oracle_gamma(int(m), float(rho))
+
+
+def dgamma(m, rho):
+    return lib().oracle_dgamma(int(m), float(rho))
+
+
+def gamma_coeffs(m):
+    c = np.zeros(m + 1)
+    lib().oracle_gamma_coeffs(int(m), _dptr(c))
+    return c
+
+
+def Phi(order, u):
+    return lib().oracle_Phi(int(order), float(u))
+
+
+def dPhi(order, u):
+    return lib().oracle_dPhi(int(order), float(u))
+
+
+def split_kernel(k, r, **params):
+    """g* (k = -1) or g^k (k >= 0) at distance r."""
+    p = _params(**params)
+    return lib().oracle_split_kernel(ctypes.byref(p), int(k), float(r))
+
+
+def system_msm(sys_, **kw):
+    """Oracle on an inputs.System (float32 inputs widened to float64)."""
+    return msm(sys_.x, sys_.y, sys_.z, sys_.q, **sys_.params(), **kw)
