@@ -1,0 +1,154 @@
+/*
+ * msm.h -- C ABI of the MI355X (gfx950) multilevel summation method (MSM)
+ * library, libmsm.so.
+ *
+ * The library evaluates the electrostatic energy, per-atom forces and per-atom
+ * potentials of N point charges by the multilevel summation method as stated
+ * in Sec. 2.3 "Multilevel Summation Method" of the thesis:
+ *   - 1/r is split into a short-range part g* (zero beyond the cutoff a) and
+ *     smooth parts g^0 .. g^{l-1} carried by grids of spacing 2^k h
+ *     (eq. split, eq. msmgrid, Taylor smoothing gamma);
+ *   - u_i^short = sum_j g*(r_i, r_j) q_j over link cells (Sec. 2.1, link cells);
+ *   - anterpolation, restriction, lattice cutoff, top level, prolongation,
+ *     interpolation (the itemised MSM algorithm of Sec. 2.3);
+ *   - U_i ~ (u_i^short + u_i^long)/(4 pi eps0) (potential display) and
+ *     F_i = -dU/dr_i (Sec. 2.1 "Simulation loop").
+ * Free-space (non-periodic) boundaries; the self term q_i gamma(0)/a is
+ * removed from every potential; no bonded exclusions.
+ *
+ * Conventions shared by every entry point:
+ *   - Every call returns msm_status; nothing throws across the ABI.
+ *     msm_last_error() gives a thread-local message for the last failure.
+ *   - Pointers named "device" are HIP device pointers; "host" are host memory.
+ *   - All device work is enqueued on the caller's stream; no entry point
+ *     synchronises except msm_status_query.  No entry point allocates device
+ *     memory: the caller owns every device buffer, including the workspace.
+ *   - Atom arrays are structure-of-arrays, float32, length n_atoms, in the
+ *     caller's atom order; outputs are written in the same order.
+ *   - Data errors (non-finite input, atom outside the box, coincident atoms)
+ *     are detected on the device and recorded in a status word inside the
+ *     workspace; msm_status_query reports them.  With such an error the
+ *     outputs are undefined (but every kernel stays in bounds).
+ */
+#ifndef MSM_H
+#define MSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* msm_stream_t;   /* a hipStream_t; NULL = default stream */
+
+typedef enum {
+  MSM_OK = 0,
+  MSM_ERR_INVALID_ARG = -1,   /* bad parameter, size or pointer */
+  MSM_ERR_OUT_OF_BOX = -2,    /* some atom lies outside [box_lo, box_lo + box_len] */
+  MSM_ERR_NONFINITE = -3,     /* NaN or Inf in a position or charge */
+  MSM_ERR_WORKSPACE = -4,     /* workspace missing, too small or not initialised */
+  MSM_ERR_HIP = -5,           /* a HIP runtime call failed */
+  MSM_ERR_UNSUPPORTED = -6,   /* valid request outside what this build supports */
+  MSM_ERR_COINCIDENT = -7     /* two atoms at exactly the same position */
+} msm_status;
+
+/* Method parameters (thesis Sec. 2.3: cutoff a, finest spacing h, number of
+ * levels l, interpolation degree p = order - 1, smoothing degree m). */
+typedef struct {
+  double cutoff;          /* a > 0, Angstrom: short-range cutoff, level k carries 2^k a */
+  double spacing;         /* h > 0, Angstrom: finest grid spacing; level k has 2^k h */
+  int32_t order;          /* 4 = cubic C1 basis, 6 = quintic C1 basis */
+  int32_t split_m;        /* Taylor smoothing degree m (gamma has degree 2m); 0 -> order/2 */
+  int32_t levels;         /* l >= 1 grid levels; 0 -> fewest levels whose top interior
+                             spans at most 8 nodes per dimension */
+  int32_t reserved;       /* must be 0 */
+  double box_lo[3];       /* box lower corner; also the grid origin */
+  double box_len[3];      /* box edge lengths > 0; atoms must lie in [lo, lo + len] */
+  double coulomb_k;       /* prefactor 1/(4 pi eps0) in the caller's units; 0 -> 1 (e^2/A) */
+} msm_params;
+
+typedef struct msm_plan msm_plan;   /* host object; immutable after creation */
+
+/* Create a plan for systems of exactly n_atoms atoms (n_atoms >= 0).
+ * Validates the parameters, derives the grid hierarchy (level k node mu sits
+ * at box_lo + 2^k h mu; each level spans every node with a non-zero weight)
+ * and the cell decomposition.  *out receives the plan (host memory owned by
+ * the library; free with msm_plan_destroy).
+ * Errors: MSM_ERR_INVALID_ARG, MSM_ERR_UNSUPPORTED (grid or stencil beyond
+ * this build's limits). */
+msm_status msm_plan_create(const msm_params* params, int32_t n_atoms, msm_plan** out);
+msm_status msm_plan_destroy(msm_plan* plan);
+
+/* Grid hierarchy of a plan: *levels, and per level k the lowest node index
+ * grid_lo[3k+d] and node count grid_n[3k+d] along dimension d (host arrays of
+ * at least 3 * 16 entries). */
+msm_status msm_plan_info(const msm_plan* plan, int32_t* levels, int32_t* grid_lo, int32_t* grid_n);
+
+/* Device workspace size in bytes for this plan (256-byte aligned sections). */
+msm_status msm_workspace_bytes(const msm_plan* plan, size_t* bytes);
+
+/* Initialise a workspace: uploads the lattice-cutoff stencil weights and the
+ * FP64 top-level kernel table (computed on the host in double precision).
+ * Must be called once per workspace before any evaluation; enqueued on
+ * `stream`.  ws: device, at least msm_workspace_bytes bytes. */
+msm_status msm_workspace_init(const msm_plan* plan, void* ws, size_t ws_bytes, msm_stream_t stream);
+
+/* Full evaluation (energy, forces, potentials).
+ * x, y, z, q : device float32 [n_atoms]  positions (A) and charges (e)
+ * fx, fy, fz : device float32 [n_atoms]  forces F_i = -dE/dr_i (nullable: all three or none)
+ * phi        : device float32 [n_atoms]  potentials phi_i = dE/dq_i (nullable)
+ * energy     : device float64 [1]        E = 1/2 sum_i q_i phi_i (nullable)
+ * virial     : device float64 [9]        W_ab = sum_i (r_i - lo)_a F_i,b (nullable)
+ * Energy and virial are reduced in float64 in a fixed order; all other
+ * arithmetic is float32 except the top-level grid sum (float64).
+ * Results are bitwise reproducible for identical inputs. */
+msm_status msm_compute(const msm_plan* plan, void* ws, size_t ws_bytes, msm_stream_t stream,
+                       const float* x, const float* y, const float* z, const float* q,
+                       float* fx, float* fy, float* fz, float* phi, double* energy,
+                       double* virial);
+
+/* Synchronise `stream` and return the data-error status recorded by the last
+ * evaluation on this workspace (MSM_OK, MSM_ERR_OUT_OF_BOX, MSM_ERR_NONFINITE
+ * or MSM_ERR_COINCIDENT).  *device_flags (nullable) receives the raw bit set. */
+msm_status msm_status_query(const msm_plan* plan, const void* ws, msm_stream_t stream,
+                            int32_t* device_flags);
+
+/* Graph of one full evaluation.  msm_graph_capture records the kernels of
+ * msm_compute for these exact buffers (same argument meaning, device
+ * pointers baked into the graph) into a HIP graph and instantiates it;
+ * nothing is executed.  msm_graph_launch replays it on `stream`: each replay
+ * is a complete evaluation of the current contents of x, y, z, q.  The plan,
+ * workspace and buffers must outlive the graph; replays on one workspace
+ * must not overlap.  Free with msm_graph_destroy. */
+typedef struct msm_graph msm_graph;
+msm_status msm_graph_capture(const msm_plan* plan, void* ws, size_t ws_bytes, const float* x,
+                             const float* y, const float* z, const float* q, float* fx, float* fy,
+                             float* fz, float* phi, double* energy, double* virial, msm_graph** out);
+msm_status msm_graph_launch(const msm_graph* graph, msm_stream_t stream);
+msm_status msm_graph_destroy(msm_graph* graph);
+
+/* Byte offset and size of an internal workspace section, for stage-by-stage
+ * checks.  section: 0 level grids of charges q^k (float32, levels
+ * concatenated, x fastest), 1 lattice-cutoff/top-level sums u^{k,cut}
+ * (same layout), 2 prolongated potentials u^k (same layout), 3 cell-sorted
+ * atoms (float4 x,y,z,q), 4 sorted-to-input permutation (int32), 5 short-range
+ * results per sorted atom (float4 Fx,Fy,Fz,phi, without the prefactor). */
+msm_status msm_workspace_section(const msm_plan* plan, int32_t section, size_t* offset, size_t* bytes);
+
+/* Diagnostics: per-stage timing.  While enabled, msm_compute records HIP
+ * events (created on the current device by this call) on its stream at the
+ * boundaries of its 9 stages: binning, short range, anterpolation,
+ * restriction, lattice cutoff, top level, prolongation, interpolation,
+ * reduction.  msm_profile_read waits for the last evaluation and writes the
+ * 9 stage durations in milliseconds to ms[0..8] (host). */
+msm_status msm_profile_enable(msm_plan* plan, int32_t enable);
+msm_status msm_profile_read(const msm_plan* plan, float* ms, int32_t* n_stages);
+
+const char* msm_status_string(msm_status status);
+const char* msm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSM_H */

@@ -1,0 +1,517 @@
+// Host side of libmsm: parameter validation, grid hierarchy, stencil and
+// top-level tables (double precision on the host), workspace layout, and the
+// C ABI declared in include/msm.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "msm_internal.hpp"
+
+using msm::Geom;
+using msm::Layout;
+
+struct msm_plan {
+  msm_params p;
+  Geom g;
+  std::vector<msm::StencilRow> rows;
+  std::vector<float> weights;
+  std::vector<double> top;
+  int n_restrict = 0;
+  int restrict_j[12];
+  float restrict_w[12];
+  float prolong_w[11];
+  int n_partials = 1;
+  Layout lay;
+  // optional stage timing (diagnostics); mutable state of an otherwise fixed plan
+  bool profile = false;
+  hipEvent_t ev[msm::kStageCount + 1] = {};
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+msm_status fail(msm_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+msm_status hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return MSM_ERR_HIP;
+}
+
+// Taylor smoothing (Sec. 2.3): gamma(rho) = sum_k c_k rho^{2k}, rho < 1, with c_k
+// the coefficients of the degree-m Taylor polynomial of s^{-1/2} at s = 1,
+// collected in powers of s.
+void taylor_coeffs(int m, double* c) {
+  for (int k = 0; k <= m; ++k) c[k] = 0.0;
+  double tj = 1.0;                                   // binom(-1/2, j)
+  for (int j = 0; j <= m; ++j) {
+    if (j > 0) tj *= (-0.5 - (j - 1)) / j;
+    double bjk = 1.0;                                // binom(j, k)
+    for (int k = 0; k <= j; ++k) {
+      if (k > 0) bjk = bjk * (j - k + 1) / k;
+      c[k] += tj * bjk * (((j - k) % 2) ? -1.0 : 1.0);
+    }
+  }
+}
+
+double gamma_h(const double* c, int m, double rho) {
+  if (rho >= 1.0) return 1.0 / rho;
+  double s = rho * rho, v = c[m];
+  for (int k = m - 1; k >= 0; --k) v = v * s + c[k];
+  return v;
+}
+
+// C1 numerical-Hermite basis Phi (cubic: support 2, quintic: support 3).
+double phi_h(int order, double u) {
+  double t = std::fabs(u);
+  if (order == 4) {
+    if (t <= 1.0) return (1.0 - t) * (1.0 + t - 1.5 * t * t);
+    if (t <= 2.0) return -0.5 * (t - 1.0) * (2.0 - t) * (2.0 - t);
+    return 0.0;
+  }
+  if (t <= 1.0) return (1.0 - t * t) * (2.0 - t) * (6.0 + 3.0 * t - 5.0 * t * t) / 12.0;
+  if (t <= 2.0) return (1.0 - t) * (2.0 - t) * (3.0 - t) * (4.0 + 9.0 * t - 5.0 * t * t) / 24.0;
+  if (t <= 3.0) return (t - 1.0) * (t - 2.0) * (t - 3.0) * (t - 3.0) * (4.0 - t) / 24.0;
+  return 0.0;
+}
+
+int floor_div2(int v) { return v >= 0 ? v / 2 : -((-v + 1) / 2); }
+int ceil_div2(int v) { return -floor_div2(-v); }
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+}  // namespace
+
+extern "C" {
+
+const char* msm_status_string(msm_status s) {
+  switch (s) {
+    case MSM_OK: return "ok";
+    case MSM_ERR_INVALID_ARG: return "invalid argument";
+    case MSM_ERR_OUT_OF_BOX: return "atom outside the box";
+    case MSM_ERR_NONFINITE: return "non-finite position or charge";
+    case MSM_ERR_WORKSPACE: return "workspace missing or too small";
+    case MSM_ERR_HIP: return "HIP runtime error";
+    case MSM_ERR_UNSUPPORTED: return "unsupported configuration";
+    case MSM_ERR_COINCIDENT: return "coincident atoms";
+  }
+  return "unknown status";
+}
+
+const char* msm_last_error(void) { return g_last_error.c_str(); }
+
+msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** out) {
+  if (!prm || !out) return fail(MSM_ERR_INVALID_ARG, "null params or output pointer");
+  *out = nullptr;
+  const msm_params& p = *prm;
+  if (!finite_pos(p.cutoff)) return fail(MSM_ERR_INVALID_ARG, "cutoff must be finite and > 0");
+  if (!finite_pos(p.spacing)) return fail(MSM_ERR_INVALID_ARG, "spacing must be finite and > 0");
+  if (p.order != 4 && p.order != 6) return fail(MSM_ERR_INVALID_ARG, "order must be 4 or 6");
+  if (p.split_m < 0 || p.split_m > 7) return fail(MSM_ERR_INVALID_ARG, "split_m must be in [0, 7]");
+  if (p.levels < 0 || p.levels > msm::kMaxLevels)
+    return fail(MSM_ERR_INVALID_ARG, "levels must be in [0, 12]");
+  if (p.reserved != 0) return fail(MSM_ERR_INVALID_ARG, "reserved field must be 0");
+  if (n_atoms < 0) return fail(MSM_ERR_INVALID_ARG, "n_atoms must be >= 0");
+  if (!std::isfinite(p.coulomb_k)) return fail(MSM_ERR_INVALID_ARG, "coulomb_k must be finite");
+  for (int d = 0; d < 3; ++d) {
+    if (!finite_pos(p.box_len[d])) return fail(MSM_ERR_INVALID_ARG, "box_len must be finite and > 0");
+    if (!std::isfinite(p.box_lo[d])) return fail(MSM_ERR_INVALID_ARG, "box_lo must be finite");
+  }
+
+  msm_plan* P = new (std::nothrow) msm_plan();
+  if (!P) return fail(MSM_ERR_INVALID_ARG, "out of host memory");
+  P->p = p;
+  Geom& g = P->g;
+  std::memset(&g, 0, sizeof(g));
+  const double a = p.cutoff, h = p.spacing;
+  g.n_atoms = n_atoms;
+  g.order = p.order;
+  g.half = p.order / 2;
+  g.h = (float)h;
+  g.inv_h = (float)(1.0 / h);
+  g.m = p.split_m ? p.split_m : p.order / 2;
+  g.ke = p.coulomb_k != 0.0 ? p.coulomb_k : 1.0;
+  double maxlen = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    g.lo[d] = p.box_lo[d];
+    g.hi[d] = p.box_lo[d] + p.box_len[d];
+    g.lo_f[d] = (float)p.box_lo[d];
+    double fm = std::floor(p.box_len[d] / h);
+    if (fm > 1.0e6) {
+      delete P;
+      return fail(MSM_ERR_UNSUPPORTED, "grid too fine for the box (more than 1e6 nodes per side)");
+    }
+    g.fmax[d] = (int)fm;
+    maxlen = std::max(maxlen, p.box_len[d]);
+  }
+
+  // levels: given, or the fewest whose top interior spans <= 8 nodes per side
+  int L = p.levels;
+  if (L == 0) {
+    L = msm::kMaxLevels;
+    for (int l = 1; l <= msm::kMaxLevels; ++l)
+      if ((int)std::ceil(maxlen / std::ldexp(h, l - 1)) + 1 <= 8) {
+        L = l;
+        break;
+      }
+  }
+  g.levels = L;
+  // level 0 spans the nodes atoms in the box touch; level k+1 the nodes level k restricts to
+  long long off = 0;
+  for (int k = 0; k < L; ++k) {
+    msm::Level& lv = g.lv[k];
+    for (int d = 0; d < 3; ++d) {
+      int lo, hi;
+      if (k == 0) {
+        lo = -(g.half - 1);
+        hi = g.fmax[d] + g.half;
+      } else {
+        const msm::Level& pv = g.lv[k - 1];
+        lo = ceil_div2(pv.lo[d] - (p.order - 1));
+        hi = floor_div2(pv.lo[d] + pv.n[d] - 1 + (p.order - 1));
+      }
+      lv.lo[d] = lo;
+      lv.n[d] = hi - lo + 1;
+    }
+    long long cnt = (long long)lv.n[0] * lv.n[1] * lv.n[2];
+    if (off + cnt > (1LL << 28)) {
+      delete P;
+      return fail(MSM_ERR_UNSUPPORTED, "grid hierarchy exceeds 2^28 nodes");
+    }
+    lv.off = (int)off;
+    lv.count = (int)cnt;
+    off += cnt;
+  }
+  g.total_nodes = (int)off;
+  if (g.lv[L - 1].count > msm::kMaxTopNodes) {
+    delete P;
+    return fail(MSM_ERR_UNSUPPORTED, "top level too large for the all-pairs sum; use more levels");
+  }
+
+  // smoothing constants
+  double c[9];
+  taylor_coeffs(g.m, c);
+  for (int k = 0; k <= g.m; ++k) {
+    g.gcoef[k] = (float)(c[k] / a);
+    g.dcoef[k] = (float)(2.0 * k * c[k] / (a * a * a));
+  }
+  g.self = (float)(c[0] / a);
+  g.a2 = (float)(a * a);
+  g.inv_a2 = (float)(1.0 / (a * a));
+
+  // link cells: edge >= a / reach (with a margin for float rounding of cell ids)
+  const double amargin = a * (1.0 + 1e-4);
+  auto set_cells = [&](int reach, double edge_min) {
+    g.reach = reach;
+    long long tot = 1;
+    for (int d = 0; d < 3; ++d) {
+      int nc = (int)std::floor(p.box_len[d] / edge_min);
+      nc = std::max(1, std::min(nc, 1 << 10));
+      g.nc[d] = nc;
+      g.inv_cs[d] = (float)(nc / p.box_len[d]);
+      tot *= nc;
+    }
+    return tot;
+  };
+  long long cap = 8LL * std::max(n_atoms, 1) + 4096;
+  long long nct = set_cells(2, amargin / 2.0);
+  if (nct > cap) nct = set_cells(1, amargin);
+  if (nct > cap) {
+    double vol = p.box_len[0] * p.box_len[1] * p.box_len[2];
+    nct = set_cells(1, std::max(amargin, std::cbrt(vol / (double)cap)));
+  }
+  g.n_cells = (int)nct;
+  double per_cell = (double)n_atoms / (double)g.n_cells;
+  int w = (int)std::lround(48.0 / std::max(per_cell, 1e-3));
+  g.run_w = std::max(1, std::min(w, g.nc[0]));
+  g.runs_x = (g.nc[0] + g.run_w - 1) / g.run_w;
+
+  // lattice-cutoff stencil: W(n) = g^0(h |n|) for h |n| < 2a, rows along z
+  if (L > 1) {
+    const double rad = 2.0 * a / h;
+    if (rad > 48.0) {
+      delete P;
+      return fail(MSM_ERR_UNSUPPORTED, "stencil radius 2a/h above 48 nodes");
+    }
+    int Rn = (int)std::ceil(rad);
+    for (int nx = -Rn; nx <= Rn; ++nx)
+      for (int ny = -Rn; ny <= Rn; ++ny) {
+        int zr = -1;
+        for (int nz = 0; nz <= Rn; ++nz) {
+          double dist = h * std::sqrt((double)(nx * nx + ny * ny + nz * nz));
+          if (dist < 2.0 * a) zr = nz;
+        }
+        if (zr < 0) continue;
+        msm::StencilRow row{nx, ny, zr, (int)P->weights.size()};
+        for (int nz = -zr; nz <= zr; ++nz) {
+          double dist = h * std::sqrt((double)(nx * nx + ny * ny + nz * nz));
+          double w0 = gamma_h(c, g.m, dist / a) / a - gamma_h(c, g.m, dist / (2.0 * a)) / (2.0 * a);
+          P->weights.push_back((float)w0);
+        }
+        P->rows.push_back(row);
+      }
+  }
+  // top level (float64): T(d) = g^{l-1}(2^{l-1} h |d|) = gamma(r / A) / A, A = 2^{l-1} a
+  {
+    const msm::Level& T = g.lv[L - 1];
+    const double A = std::ldexp(a, L - 1), hk = std::ldexp(h, L - 1);
+    P->top.resize((size_t)T.count);
+    for (int dz = 0; dz < T.n[2]; ++dz)
+      for (int dy = 0; dy < T.n[1]; ++dy)
+        for (int dx = 0; dx < T.n[0]; ++dx) {
+          double r = hk * std::sqrt((double)(dx * dx + dy * dy + dz * dz));
+          P->top[((size_t)dz * T.n[1] + dy) * T.n[0] + dx] = gamma_h(c, g.m, r / A) / A;
+        }
+  }
+  // restriction offsets j with Phi(j/2) != 0, and prolongation weights Phi(j/2)
+  const int R = p.order - 1;
+  for (int j = -R; j <= R; ++j) {
+    double wv = phi_h(p.order, 0.5 * j);
+    P->prolong_w[j + R] = (float)wv;
+    if (wv != 0.0) {
+      P->restrict_j[P->n_restrict] = j;
+      P->restrict_w[P->n_restrict] = (float)wv;
+      ++P->n_restrict;
+    }
+  }
+  P->n_partials = msm::interp_partials(g);
+
+  // workspace layout
+  Layout& lay = P->lay;
+  size_t n = (size_t)std::max(n_atoms, 1);
+  size_t nodes = (size_t)g.total_nodes;
+  lay.bytes[msm::kSecQGrid] = nodes * sizeof(float);
+  lay.bytes[msm::kSecUCut] = nodes * sizeof(float);
+  lay.bytes[msm::kSecU] = nodes * sizeof(float);
+  lay.bytes[msm::kSecSorted] = n * sizeof(float4);
+  lay.bytes[msm::kSecPerm] = n * sizeof(int);
+  lay.bytes[msm::kSecShort] = n * sizeof(float4);
+  lay.bytes[msm::kSecStatus] = 64 * sizeof(int);
+  lay.bytes[msm::kSecCounts] = ((size_t)g.n_cells + 1) * sizeof(int);
+  lay.bytes[msm::kSecCellStart] = ((size_t)g.n_cells + 1) * sizeof(int);
+  lay.bytes[msm::kSecCursor] = (size_t)g.n_cells * sizeof(int);
+  lay.bytes[msm::kSecCellOf] = n * sizeof(int);
+  lay.bytes[msm::kSecTmp] = n * sizeof(int);
+  lay.bytes[msm::kSecRows] = std::max<size_t>(P->rows.size(), 1) * sizeof(msm::StencilRow);
+  lay.bytes[msm::kSecWeights] = std::max<size_t>(P->weights.size(), 1) * sizeof(float);
+  lay.bytes[msm::kSecTop] = P->top.size() * sizeof(double);
+  lay.bytes[msm::kSecPartials] = 10 * (size_t)P->n_partials * sizeof(double);
+  size_t o = 0;
+  for (int s = 0; s < msm::kSecCount; ++s) {
+    lay.off[s] = o;
+    o += align256(lay.bytes[s]);
+  }
+  lay.total = o;
+  *out = P;
+  return MSM_OK;
+}
+
+msm_status msm_plan_destroy(msm_plan* plan) {
+  if (plan)
+    for (auto& e : plan->ev)
+      if (e) (void)hipEventDestroy(e);
+  delete plan;
+  return MSM_OK;
+}
+
+msm_status msm_profile_enable(msm_plan* P, int32_t enable) {
+  if (!P) return fail(MSM_ERR_INVALID_ARG, "null plan");
+  if (enable && !P->ev[0])
+    for (auto& e : P->ev) {
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return hip_fail(r, "create timing events");
+    }
+  P->profile = enable != 0;
+  return MSM_OK;
+}
+
+msm_status msm_profile_read(const msm_plan* P, float* ms, int32_t* n_stages) {
+  if (!P || !ms || !n_stages) return fail(MSM_ERR_INVALID_ARG, "null argument");
+  if (!P->profile) return fail(MSM_ERR_INVALID_ARG, "profiling is not enabled on this plan");
+  hipError_t r = hipEventSynchronize(P->ev[msm::kStageCount]);
+  if (r != hipSuccess) return hip_fail(r, "wait for timing events");
+  for (int i = 0; i < msm::kStageCount; ++i) {
+    r = hipEventElapsedTime(&ms[i], P->ev[i], P->ev[i + 1]);
+    if (r != hipSuccess) return hip_fail(r, "read timing events");
+  }
+  *n_stages = msm::kStageCount;
+  return MSM_OK;
+}
+
+msm_status msm_plan_info(const msm_plan* P, int32_t* levels, int32_t* grid_lo, int32_t* grid_n) {
+  if (!P || !levels) return fail(MSM_ERR_INVALID_ARG, "null plan or levels pointer");
+  *levels = P->g.levels;
+  for (int k = 0; k < P->g.levels; ++k)
+    for (int d = 0; d < 3; ++d) {
+      if (grid_lo) grid_lo[3 * k + d] = P->g.lv[k].lo[d];
+      if (grid_n) grid_n[3 * k + d] = P->g.lv[k].n[d];
+    }
+  return MSM_OK;
+}
+
+msm_status msm_workspace_bytes(const msm_plan* P, size_t* bytes) {
+  if (!P || !bytes) return fail(MSM_ERR_INVALID_ARG, "null plan or bytes pointer");
+  *bytes = P->lay.total;
+  return MSM_OK;
+}
+
+msm_status msm_workspace_section(const msm_plan* P, int32_t section, size_t* offset, size_t* bytes) {
+  if (!P || section < 0 || section > msm::kSecShort)
+    return fail(MSM_ERR_INVALID_ARG, "null plan or unknown section");
+  if (offset) *offset = P->lay.off[section];
+  if (bytes) *bytes = P->lay.bytes[section];
+  return MSM_OK;
+}
+
+msm_status msm_workspace_init(const msm_plan* P, void* ws, size_t ws_bytes, msm_stream_t stream) {
+  if (!P) return fail(MSM_ERR_INVALID_ARG, "null plan");
+  if (!ws || ws_bytes < P->lay.total) return fail(MSM_ERR_WORKSPACE, "workspace missing or too small");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  hipError_t e;
+  if (!P->rows.empty()) {
+    e = hipMemcpyAsync(base + P->lay.off[msm::kSecRows], P->rows.data(),
+                       P->rows.size() * sizeof(msm::StencilRow), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "upload stencil rows");
+    e = hipMemcpyAsync(base + P->lay.off[msm::kSecWeights], P->weights.data(),
+                       P->weights.size() * sizeof(float), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "upload stencil weights");
+  }
+  e = hipMemcpyAsync(base + P->lay.off[msm::kSecTop], P->top.data(), P->top.size() * sizeof(double),
+                     hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "upload top-level table");
+  // pageable-memory copies are staged before returning; the plan may be destroyed afterwards
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "workspace init");
+  return MSM_OK;
+}
+
+static msm::DevPtrs dev_ptrs(const msm_plan* P, void* ws) {
+  char* b = static_cast<char*>(ws);
+  const size_t* o = P->lay.off;
+  msm::DevPtrs d;
+  d.qgrid = reinterpret_cast<float*>(b + o[msm::kSecQGrid]);
+  d.ucut = reinterpret_cast<float*>(b + o[msm::kSecUCut]);
+  d.u = reinterpret_cast<float*>(b + o[msm::kSecU]);
+  d.sorted = reinterpret_cast<float4*>(b + o[msm::kSecSorted]);
+  d.perm = reinterpret_cast<int*>(b + o[msm::kSecPerm]);
+  d.fshort = reinterpret_cast<float4*>(b + o[msm::kSecShort]);
+  d.status = reinterpret_cast<int*>(b + o[msm::kSecStatus]);
+  d.counts = reinterpret_cast<int*>(b + o[msm::kSecCounts]);
+  d.cell_start = reinterpret_cast<int*>(b + o[msm::kSecCellStart]);
+  d.cursor = reinterpret_cast<int*>(b + o[msm::kSecCursor]);
+  d.cell_of = reinterpret_cast<int*>(b + o[msm::kSecCellOf]);
+  d.tmp = reinterpret_cast<int*>(b + o[msm::kSecTmp]);
+  d.rows = reinterpret_cast<const msm::StencilRow*>(b + o[msm::kSecRows]);
+  d.weights = reinterpret_cast<const float*>(b + o[msm::kSecWeights]);
+  d.top = reinterpret_cast<const double*>(b + o[msm::kSecTop]);
+  d.partials = reinterpret_cast<double*>(b + o[msm::kSecPartials]);
+  return d;
+}
+
+msm_status msm_compute(const msm_plan* P, void* ws, size_t ws_bytes, msm_stream_t stream,
+                       const float* x, const float* y, const float* z, const float* q, float* fx,
+                       float* fy, float* fz, float* phi, double* energy, double* virial) {
+  if (!P) return fail(MSM_ERR_INVALID_ARG, "null plan");
+  if (!ws || ws_bytes < P->lay.total) return fail(MSM_ERR_WORKSPACE, "workspace missing or too small");
+  if (P->g.n_atoms > 0 && (!x || !y || !z || !q))
+    return fail(MSM_ERR_INVALID_ARG, "null position or charge array");
+  if (!((fx && fy && fz) || (!fx && !fy && !fz)))
+    return fail(MSM_ERR_INVALID_ARG, "force outputs must be all set or all null");
+  msm::DevPtrs d = dev_ptrs(P, ws);
+  hipError_t e = msm::launch_forward(P->g, d, (int)P->rows.size(), P->n_partials, P->restrict_j,
+                                     P->restrict_w, P->n_restrict, P->prolong_w,
+                                     reinterpret_cast<hipStream_t>(stream), x, y, z, q, fx, fy, fz,
+                                     phi, energy, virial,
+                                     P->profile ? const_cast<hipEvent_t*>(P->ev) : nullptr);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return MSM_OK;
+}
+
+struct msm_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+msm_status msm_graph_destroy(msm_graph* G) {
+  if (G) {
+    if (G->exec) (void)hipGraphExecDestroy(G->exec);
+    if (G->graph) (void)hipGraphDestroy(G->graph);
+    delete G;
+  }
+  return MSM_OK;
+}
+
+msm_status msm_graph_capture(const msm_plan* P, void* ws, size_t ws_bytes, const float* x,
+                             const float* y, const float* z, const float* q, float* fx, float* fy,
+                             float* fz, float* phi, double* energy, double* virial, msm_graph** out) {
+  if (!out) return fail(MSM_ERR_INVALID_ARG, "null output pointer");
+  *out = nullptr;
+  if (!P) return fail(MSM_ERR_INVALID_ARG, "null plan");
+  if (!ws || ws_bytes < P->lay.total) return fail(MSM_ERR_WORKSPACE, "workspace missing or too small");
+  if (P->g.n_atoms > 0 && (!x || !y || !z || !q))
+    return fail(MSM_ERR_INVALID_ARG, "null position or charge array");
+  if (!((fx && fy && fz) || (!fx && !fy && !fz)))
+    return fail(MSM_ERR_INVALID_ARG, "force outputs must be all set or all null");
+  msm_graph* G = new (std::nothrow) msm_graph();
+  if (!G) return fail(MSM_ERR_INVALID_ARG, "out of host memory");
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete G;
+    return hip_fail(e, "create capture stream");
+  }
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    msm::DevPtrs d = dev_ptrs(P, ws);
+    hipError_t le = msm::launch_forward(P->g, d, (int)P->rows.size(), P->n_partials, P->restrict_j,
+                                        P->restrict_w, P->n_restrict, P->prolong_w, cs, x, y, z, q,
+                                        fx, fy, fz, phi, energy, virial, nullptr);
+    e = hipStreamEndCapture(cs, &G->graph);
+    if (le != hipSuccess) e = le;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) {
+    msm_graph_destroy(G);
+    return hip_fail(e, "capture evaluation graph");
+  }
+  *out = G;
+  return MSM_OK;
+}
+
+msm_status msm_graph_launch(const msm_graph* G, msm_stream_t stream) {
+  if (!G || !G->exec) return fail(MSM_ERR_INVALID_ARG, "null graph");
+  hipError_t e = hipGraphLaunch(G->exec, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "graph launch");
+  return MSM_OK;
+}
+
+msm_status msm_status_query(const msm_plan* P, const void* ws, msm_stream_t stream,
+                            int32_t* device_flags) {
+  if (!P || !ws) return fail(MSM_ERR_INVALID_ARG, "null plan or workspace");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+  int32_t flags = 0;
+  e = hipMemcpy(&flags, static_cast<const char*>(ws) + P->lay.off[msm::kSecStatus], sizeof(int32_t),
+                hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "read status");
+  if (device_flags) *device_flags = flags;
+  if (flags & msm::kFlagNonFinite) return fail(MSM_ERR_NONFINITE, "non-finite position or charge");
+  if (flags & msm::kFlagOutOfBox) return fail(MSM_ERR_OUT_OF_BOX, "atom outside the box");
+  if (flags & msm::kFlagCoincident) return fail(MSM_ERR_COINCIDENT, "coincident atoms");
+  return MSM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,124 @@
+// Internal declarations of libmsm: geometry descriptors passed to the gfx950
+// kernels by value, workspace section indices and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/msm.h"
+
+namespace msm {
+
+constexpr int kMaxLevels = 12;
+constexpr int kMaxOrder = 6;
+constexpr int kMaxTopNodes = 1 << 17;     // all-pairs FP64 top level stays below ~1e10 pair terms
+constexpr int kRankCap = 2048;            // cells longer than this keep scatter order (see bin_place)
+
+enum DeviceFlag : int { kFlagOutOfBox = 1, kFlagNonFinite = 2, kFlagCoincident = 4 };
+
+struct Level {
+  int lo[3];     // lowest node index per dimension
+  int n[3];      // node count per dimension
+  int off;       // first node of this level in the concatenated grid arrays
+  int count;     // n[0] * n[1] * n[2]
+};
+
+// Everything the kernels need to know about one system.  Plain data, passed
+// by value as a kernel argument.
+struct Geom {
+  int n_atoms;
+  int order, half;                 // interpolation order, order / 2
+  int levels;
+  int total_nodes;
+  float h, inv_h;                  // finest spacing and its reciprocal
+  float lo_f[3];                   // box corner (float) = grid origin
+  double lo[3], hi[3];             // exact box bounds for the in-box test
+  int fmax[3];                     // largest level-0 floor index floor(len / h)
+  // link cells
+  int nc[3];
+  int n_cells;
+  int reach;                       // neighbour cells per side
+  float inv_cs[3];                 // 1 / cell edge
+  int run_w;                       // cells per short-range work item along x
+  int runs_x;                      // work items per cell row
+  // short-range constants
+  float a2;                        // cutoff^2
+  float inv_a2;                    // 1 / a^2
+  float gcoef[8];                  // c_k / a         (gamma(rho)/a = sum gcoef[k] s^k, s = rho^2)
+  float dcoef[8];                  // 2 k c_k / a^3   (gamma'(rho)/(a^2 r) = sum_{k>=1} dcoef[k] s^{k-1})
+  int m;                           // smoothing degree
+  float self;                      // gamma(0) / a
+  double ke;                       // energy prefactor
+  Level lv[kMaxLevels];
+};
+
+// Lattice-cutoff stencil: rows (nx, ny) of taps nz in [-zr, zr].
+struct StencilRow {
+  int nx, ny, zr, woff;
+};
+
+// Workspace sections (in order).  Offsets are 256-byte aligned.
+enum Section : int {
+  kSecQGrid = 0,      // float[total_nodes]
+  kSecUCut = 1,       // float[total_nodes]
+  kSecU = 2,          // float[total_nodes]
+  kSecSorted = 3,     // float4[n]
+  kSecPerm = 4,       // int[n]
+  kSecShort = 5,      // float4[n]
+  kSecStatus,         // int[64]
+  kSecCounts,         // int[n_cells + 1]
+  kSecCellStart,      // int[n_cells + 1]
+  kSecCursor,         // int[n_cells]
+  kSecCellOf,         // int[n]
+  kSecTmp,            // int[n]
+  kSecRows,           // StencilRow[n_rows]
+  kSecWeights,        // float[n_weights]
+  kSecTop,            // double[top table]
+  kSecPartials,       // double[10 * n_partials]: energy, then 9 virial components
+  kSecCount
+};
+
+struct Layout {
+  size_t off[kSecCount];
+  size_t bytes[kSecCount];
+  size_t total;
+};
+
+struct DevPtrs {
+  float* qgrid;
+  float* ucut;
+  float* u;
+  float4* sorted;
+  int* perm;
+  float4* fshort;
+  int* status;
+  int* counts;
+  int* cell_start;
+  int* cursor;
+  int* cell_of;
+  int* tmp;
+  const StencilRow* rows;
+  const float* weights;
+  const double* top;
+  double* partials;
+};
+
+// Stages of one evaluation, in launch order (for optional event timing).
+enum Stage : int {
+  kStageBin = 0, kStageShort, kStageAnterp, kStageRestrict, kStageLattice, kStageTop,
+  kStageProlong, kStageInterp, kStageReduce, kStageCount
+};
+
+// Launchers (msm_kernels.hip).  All enqueue on `s` and return the first HIP error.
+// ev (nullable): kStageCount + 1 events recorded at the stage boundaries.
+hipError_t launch_forward(const Geom& g, const DevPtrs& d, int n_rows, int n_partials,
+                          const int* restrict_j, const float* restrict_w, int n_restrict,
+                          const float* prolong_w, hipStream_t s, const float* x, const float* y,
+                          const float* z, const float* q, float* fx, float* fy, float* fz,
+                          float* phi, double* energy, double* virial, hipEvent_t* ev);
+
+int interp_partials(const Geom& g);      // number of FP64 partial slots the forward pass uses
+
+}  // namespace msm

@@ -1,0 +1,215 @@
+"""ctypes binding of libmsm (include/msm.h), with torch for device memory and streams.
+
+Argument marshalling only: every step of the evaluation runs in the HIP
+kernels of libmsm.so.  If the library is not built, or no GPU is present,
+calls fail loudly; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmsm.so")
+
+OK, ERR_INVALID_ARG, ERR_OUT_OF_BOX, ERR_NONFINITE = 0, -1, -2, -3
+ERR_WORKSPACE, ERR_HIP, ERR_UNSUPPORTED, ERR_COINCIDENT = -4, -5, -6, -7
+
+SECTION_QGRID, SECTION_UCUT, SECTION_U, SECTION_SORTED, SECTION_PERM, SECTION_SHORT = range(6)
+
+# every entry point include/msm.h declares
+EXPORTS = ("msm_plan_create", "msm_plan_destroy", "msm_plan_info", "msm_workspace_bytes",
+           "msm_workspace_init", "msm_compute", "msm_status_query", "msm_workspace_section",
+           "msm_profile_enable", "msm_profile_read", "msm_graph_capture", "msm_graph_launch",
+           "msm_graph_destroy", "msm_status_string", "msm_last_error")
+
+STAGES = ("binning", "short_range", "anterpolation", "restriction", "lattice_cutoff", "top_level",
+          "prolongation", "interpolation", "reduction")
+
+
+class MSMError(RuntimeError):
+    def __init__(self, code, msg=""):
+        super().__init__(f"libmsm status {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("cutoff", ctypes.c_double), ("spacing", ctypes.c_double),
+                ("order", ctypes.c_int32), ("split_m", ctypes.c_int32),
+                ("levels", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("box_lo", ctypes.c_double * 3), ("box_len", ctypes.c_double * 3),
+                ("coulomb_k", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmsm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32
+        L.msm_plan_create.argtypes = [ctypes.POINTER(Params), i32, ctypes.POINTER(vp)]
+        L.msm_plan_destroy.argtypes = [vp]
+        L.msm_plan_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.msm_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+        L.msm_workspace_init.argtypes = [vp, vp, sz, vp]
+        L.msm_compute.argtypes = [vp, vp, sz, vp] + [vp] * 10
+        L.msm_status_query.argtypes = [vp, vp, vp, ctypes.POINTER(i32)]
+        L.msm_workspace_section.argtypes = [vp, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+        L.msm_profile_enable.argtypes = [vp, i32]
+        L.msm_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(i32)]
+        L.msm_graph_capture.argtypes = [vp, vp, sz] + [vp] * 10 + [ctypes.POINTER(vp)]
+        L.msm_graph_launch.argtypes = [vp, vp]
+        L.msm_graph_destroy.argtypes = [vp]
+        L.msm_status_string.argtypes = [i32]
+        L.msm_status_string.restype = ctypes.c_char_p
+        L.msm_last_error.argtypes = []
+        L.msm_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name not in ("msm_status_string", "msm_last_error"):
+                getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != OK:
+        raise MSMError(code, lib().msm_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_params(cutoff, spacing, order=4, split_m=0, levels=0, box_lo=(0.0, 0.0, 0.0),
+                box_len=(1.0, 1.0, 1.0), coulomb_k=1.0) -> Params:
+    p = Params()
+    p.cutoff, p.spacing = float(cutoff), float(spacing)
+    p.order, p.split_m, p.levels, p.reserved = int(order), int(split_m), int(levels), 0
+    for d in range(3):
+        p.box_lo[d] = float(box_lo[d])
+        p.box_len[d] = float(box_len[d])
+    p.coulomb_k = float(coulomb_k)
+    return p
+
+
+class Plan:
+    """A plan plus its device workspace for systems of `n_atoms` atoms."""
+
+    def __init__(self, n_atoms, *, cutoff, spacing, order=4, split_m=0, levels=0,
+                 box_lo=(0.0, 0.0, 0.0), box_len=(1.0, 1.0, 1.0), coulomb_k=1.0, device="cuda"):
+        self.params = make_params(cutoff, spacing, order, split_m, levels, box_lo, box_len, coulomb_k)
+        self.n = int(n_atoms)
+        h = ctypes.c_void_p()
+        _check(lib().msm_plan_create(ctypes.byref(self.params), self.n, ctypes.byref(h)))
+        self._h = h
+        nb = ctypes.c_size_t()
+        _check(lib().msm_workspace_bytes(self._h, ctypes.byref(nb)))
+        self.ws = torch.empty(int(nb.value), dtype=torch.uint8, device=device)
+        _check(lib().msm_workspace_init(self._h, _ptr(self.ws), self.ws.numel(), _stream()))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.msm_plan_destroy(h)
+            self._h = None
+
+    def info(self):
+        lv = ctypes.c_int32()
+        lo = (ctypes.c_int32 * 48)()
+        n = (ctypes.c_int32 * 48)()
+        _check(lib().msm_plan_info(self._h, ctypes.byref(lv), lo, n))
+        L = lv.value
+        return L, [tuple(lo[3 * k:3 * k + 3]) for k in range(L)], [tuple(n[3 * k:3 * k + 3]) for k in range(L)]
+
+    def compute(self, x, y, z, q, *, forces=True, potentials=True, virial=False, out=None):
+        """Energy (float64 [1]), forces [3, N] and potentials [N] on the device."""
+        dev = self.ws.device
+        for t in (x, y, z, q):
+            if t.dtype != torch.float32 or t.device != dev or not t.is_contiguous() or t.numel() != self.n:
+                raise ValueError("x, y, z, q must be contiguous float32 device tensors of length n_atoms")
+        o = out if out is not None else {}
+        if "energy" not in o:
+            o["energy"] = torch.empty(1, dtype=torch.float64, device=dev)
+        if forces and "f" not in o:
+            o["f"] = torch.empty((3, self.n), dtype=torch.float32, device=dev)
+        if potentials and "phi" not in o:
+            o["phi"] = torch.empty(self.n, dtype=torch.float32, device=dev)
+        if virial and "virial" not in o:
+            o["virial"] = torch.empty(9, dtype=torch.float64, device=dev)
+        f = o.get("f") if forces else None
+        fx, fy, fz = (f[0], f[1], f[2]) if f is not None else (None, None, None)
+        _check(lib().msm_compute(self._h, _ptr(self.ws), self.ws.numel(), _stream(), _ptr(x), _ptr(y),
+                                 _ptr(z), _ptr(q), _ptr(fx), _ptr(fy), _ptr(fz),
+                                 _ptr(o.get("phi") if potentials else None), _ptr(o["energy"]),
+                                 _ptr(o.get("virial") if virial else None)))
+        return o
+
+    def status(self):
+        """Synchronise and return (status code, raw device flags) of the last evaluation."""
+        flags = ctypes.c_int32()
+        code = lib().msm_status_query(self._h, _ptr(self.ws), _stream(), ctypes.byref(flags))
+        return code, flags.value
+
+    def check(self):
+        code, _ = self.status()
+        _check(code)
+
+    def profile(self, enable=True):
+        """Record per-stage HIP events inside every following compute()."""
+        _check(lib().msm_profile_enable(self._h, 1 if enable else 0))
+
+    def stage_ms(self):
+        """Stage durations (ms) of the last compute(), keyed by stage name."""
+        ms = (ctypes.c_float * 16)()
+        n = ctypes.c_int32()
+        _check(lib().msm_profile_read(self._h, ms, ctypes.byref(n)))
+        return {STAGES[i]: float(ms[i]) for i in range(n.value)}
+
+    def section(self, idx, dtype=torch.float32):
+        off, nb = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().msm_workspace_section(self._h, int(idx), ctypes.byref(off), ctypes.byref(nb)))
+        return self.ws[off.value:off.value + nb.value].view(dtype)
+
+
+class Graph:
+    """A captured full evaluation of `plan` on fixed device buffers; launch() replays it."""
+
+    def __init__(self, plan, x, y, z, q, out):
+        self.plan, self.keep = plan, (x, y, z, q, out)
+        f = out.get("f")
+        fx, fy, fz = (f[0], f[1], f[2]) if f is not None else (None, None, None)
+        h = ctypes.c_void_p()
+        _check(lib().msm_graph_capture(plan._h, _ptr(plan.ws), plan.ws.numel(), _ptr(x), _ptr(y),
+                                       _ptr(z), _ptr(q), _ptr(fx), _ptr(fy), _ptr(fz),
+                                       _ptr(out.get("phi")), _ptr(out.get("energy")),
+                                       _ptr(out.get("virial")), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self):
+        _check(lib().msm_graph_launch(self._h, _stream()))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.msm_graph_destroy(h)
+            self._h = None
+
+
+def plan_for(system, device="cuda") -> Plan:
+    """Plan for an inputs.System."""
+    return Plan(system.n, device=device, **{**system.params(), "split_m": system.split_m})
+
+
+def to_device(system, device="cuda"):
+    return tuple(torch.from_numpy(a).to(device) for a in (system.x, system.y, system.z, system.q))

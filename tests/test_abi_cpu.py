@@ -1,0 +1,119 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared
+entry point, and its host-side planning agrees with the oracle's grid layout.
+No compute call is made (no GPU here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1402_7216_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "msm.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:msm_status|const char\*)\s+(msm_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_1402_7216_amd import msm
+    return msm
+
+
+def test_library_exports_every_declared_symbol(M):
+    names = _declared()
+    assert len(names) >= 10
+    lib = M.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(M.EXPORTS)
+
+
+def _plan(M, n, **prm):
+    p = M.make_params(**prm)
+    h = ctypes.c_void_p()
+    code = M.lib().msm_plan_create(ctypes.byref(p), n, ctypes.byref(h))
+    return code, h
+
+
+def _info(M, h):
+    lv = ctypes.c_int32()
+    lo = (ctypes.c_int32 * 48)()
+    n = (ctypes.c_int32 * 48)()
+    assert M.lib().msm_plan_info(h, ctypes.byref(lv), lo, n) == 0
+    L = lv.value
+    return L, np.array(lo[:3 * L]).reshape(L, 3), np.array(n[:3 * L]).reshape(L, 3)
+
+
+CASES = [
+    dict(cutoff=8.0, spacing=2.5, order=4, levels=2, box_lo=(0, 0, 0), box_len=(20, 20, 20)),
+    dict(cutoff=12.0, spacing=2.0, order=4, levels=4, box_lo=(0, 0, 0), box_len=(62.1, 62.1, 62.1)),
+    dict(cutoff=12.0, spacing=2.5, order=6, levels=0, box_lo=(0, 0, 0), box_len=(215.44,) * 3),
+    dict(cutoff=12.0, spacing=2.0, order=4, levels=0, box_lo=(0, 0, 0), box_len=(100.0,) * 3),
+    dict(cutoff=10.0, spacing=2.0, order=4, levels=0, box_lo=(-3, 5, 1.5), box_len=(27.1, 40.0, 33.3)),
+    dict(cutoff=5.0, spacing=1.3, order=6, levels=1, box_lo=(0, 0, 0), box_len=(9.0, 7.0, 8.0)),
+]
+
+
+@pytest.mark.parametrize("prm", CASES)
+def test_plan_layout_matches_oracle(M, prm):
+    code, h = _plan(M, 1000, **prm)
+    assert code == 0
+    try:
+        L, lo, n = _info(M, h)
+        oprm = dict(prm)
+        Lo, loo, no = oracle.layout(**{k: v for k, v in oprm.items()})
+        assert L == Lo
+        np.testing.assert_array_equal(lo, loo)
+        np.testing.assert_array_equal(n, no)
+        nb = ctypes.c_size_t()
+        assert M.lib().msm_workspace_bytes(h, ctypes.byref(nb)) == 0 and nb.value > 0
+    finally:
+        M.lib().msm_plan_destroy(h)
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(cutoff=0.0), -1), (dict(cutoff=float("nan")), -1), (dict(spacing=-1.0), -1),
+    (dict(order=5), -1), (dict(levels=13), -1), (dict(split_m=9), -1),
+    (dict(box_len=(0.0, 1.0, 1.0)), -1), (dict(spacing=0.1, levels=1), -6),
+])
+def test_plan_rejects_bad_parameters(M, bad, code):
+    prm = dict(cutoff=8.0, spacing=2.5, order=4, levels=2, box_lo=(0, 0, 0), box_len=(20, 20, 20))
+    prm.update(bad)
+    c, h = _plan(M, 100, **prm)
+    assert c == code
+    assert M.lib().msm_last_error()
+
+
+def test_plan_rejects_negative_atom_count(M):
+    c, _ = _plan(M, -1, cutoff=8.0, spacing=2.5, box_len=(20, 20, 20))
+    assert c == -1
+
+
+def test_workspace_calls_check_sizes_without_touching_device(M):
+    code, h = _plan(M, 10, **CASES[0])
+    assert code == 0
+    try:
+        # a too-small workspace is rejected before any device work is enqueued
+        assert M.lib().msm_workspace_init(h, ctypes.c_void_p(16), 8, None) == -4
+        assert M.lib().msm_compute(h, ctypes.c_void_p(16), 8, None, *([None] * 10)) == -4
+        off, nb = ctypes.c_size_t(), ctypes.c_size_t()
+        assert M.lib().msm_workspace_section(h, 99, ctypes.byref(off), ctypes.byref(nb)) == -1
+        assert M.lib().msm_status_string(-7) == b"coincident atoms"
+    finally:
+        M.lib().msm_plan_destroy(h)
+
+
+def test_named_workload_generators_are_deterministic():
+    a, b = inputs.water_24k(), inputs.water_24k()
+    assert np.array_equal(a.x, b.x) and np.array_equal(a.q, b.q)
+    assert a.n == 24000 and abs(float(a.q.astype(np.float64).sum())) == 0.0
+    sizes = inputs.batch_sizes()
+    assert len(sizes) == 64 and min(sizes) >= 2000 and max(sizes) <= 60000
+    assert all(s % 3 == 0 for s in sizes)
