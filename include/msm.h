@@ -85,6 +85,12 @@ msm_status msm_plan_destroy(msm_plan* plan);
  * at least 3 * 16 entries). */
 msm_status msm_plan_info(const msm_plan* plan, int32_t* levels, int32_t* grid_lo, int32_t* grid_n);
 
+/* Human-readable JSON description of the plan's decomposition (levels, link
+ * cells, stencil taps, lattice-cutoff tile shapes, workspace size) written
+ * into the host buffer buf (NUL-terminated; MSM_ERR_INVALID_ARG if it does
+ * not fit in buf_bytes). */
+msm_status msm_plan_describe(const msm_plan* plan, char* buf, size_t buf_bytes);
+
 /* Device workspace size in bytes for this plan (256-byte aligned sections). */
 msm_status msm_workspace_bytes(const msm_plan* plan, size_t* bytes);
 

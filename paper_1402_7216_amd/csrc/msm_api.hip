@@ -19,6 +19,8 @@ struct msm_plan {
   msm_params p;
   Geom g;
   std::vector<msm::StencilRow> rows;
+  std::vector<int4> rows_c;                  // compact rows of the windowed kernel
+  std::vector<float> weights_c;              // compact weights of the windowed kernel
   std::vector<float> weights;
   std::vector<double> top;
   int n_restrict = 0;
@@ -26,11 +28,42 @@ struct msm_plan {
   float restrict_w[12];
   float prolong_w[11];
   int n_partials = 1;
+  msm::LatLaunch lat;
   Layout lay;
   // optional stage timing (diagnostics); mutable state of an otherwise fixed plan
   bool profile = false;
   hipEvent_t ev[msm::kStageCount + 1] = {};
+  // auxiliary stream for the concurrent short-range pass (created on first use)
+  hipStream_t aux = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  int aux_device = -1;
 };
+
+namespace {
+// Create (once per plan) the auxiliary stream and fork/join events on the
+// current device.  Streams keep the default priority.
+hipError_t ensure_aux(msm_plan* P) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (P->aux && P->aux_device == dev) return hipSuccess;
+  if (P->aux) {
+    (void)hipStreamDestroy(P->aux);
+    (void)hipEventDestroy(P->fork);
+    (void)hipEventDestroy(P->join);
+    P->aux = nullptr;
+  }
+  e = hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&P->fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&P->join, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    P->aux = nullptr;
+    return e;
+  }
+  P->aux_device = dev;
+  return hipSuccess;
+}
+}  // namespace
 
 namespace {
 
@@ -89,6 +122,112 @@ int ceil_div2(int v) { return -floor_div2(-v); }
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Largest number of lanes of one half-wave (32 lanes) whose window offsets
+// fall in the same LDS bank (32 banks of 4 bytes).
+int bank_conflicts(int xl, int ty, int tz, int B, int px, int pp) {
+  int worst = 0;
+  for (int half = 0; half < 2; ++half) {
+    int cnt[32] = {0};
+    for (int l = half * 32; l < half * 32 + 32; ++l) {
+      const int xi = l % xl, yi = (l / xl) % ty, zi = l / (xl * ty);
+      if (zi >= tz) continue;
+      const int off = zi * pp + yi * px + xi * B;
+      worst = std::max(worst, ++cnt[off & 31]);
+    }
+  }
+  return worst;
+}
+
+// Row and plane pitches (floats) of a window tile with the fewest bank
+// conflicts whose window still fits in max_floats.
+void pad_window(msm::LatTile& t, int B, int H, int max_floats) {
+  const int WX = t.xl * B + 2 * H, PY = t.ty + 2 * H;
+  int best = 1 << 30;
+  t.px = WX;
+  t.pp = PY * WX;
+  for (int px = WX; px < WX + 32; ++px)
+    for (int extra = 0; extra < 32; ++extra) {
+      const int pp = PY * px + extra;
+      if ((t.tz + 2 * H) * pp > max_floats) continue;
+      const int c = bank_conflicts(t.xl, t.ty, t.tz, B, px, pp);
+      const int score = c * 4096 + (pp * (t.tz + 2 * H) - WX * PY * (t.tz + 2 * H)) / 64;
+      if (score < best) {
+        best = score;
+        t.px = px;
+        t.pp = pp;
+      }
+    }
+}
+
+// Tile shapes of the windowed lattice-cutoff kernel.  For each candidate B
+// (outputs per lane along x) and each sub-top level, pick (xl, ty, tz) lanes
+// minimising a cost in wave instructions: FMA slots including ragged-tile
+// waste (about half a FMA per tap with mirror-row pairing), plus the window
+// load; then penalise launches with fewer blocks than compute units.
+void choose_lattice_tiles(const Geom& g, int taps, int H_, int tables_bytes, msm::LatLaunch& lat) {
+  const int n_rows = lat.n_rows, n_wc = lat.n_wc;
+  std::memset(&lat, 0, sizeof(lat));
+  lat.H = H_;
+  lat.n_rows = n_rows;
+  lat.n_wc = n_wc;
+  if (g.levels < 2 || H_ > msm::kLatMaxHalo) return;
+  double best = 1e300;
+  msm::LatLaunch cand;
+  const int Bs[3] = {4, 6, 8};
+  for (int bi = 0; bi < 3; ++bi) {
+    const int B = Bs[bi];
+    cand = lat;
+    cand.b = B;
+    cand.n = g.levels - 1;
+    double cost = 0.0;
+    long long blocks = 0;
+    int lds_max = 0;
+    bool ok = true;
+    for (int k = 0; k < g.levels - 1; ++k) {
+      const msm::Level& L = g.lv[k];
+      double lbest = 1e300;
+      msm::LatTile tb{};
+      int tb_lds = 0;
+      for (int tz = 1; tz <= 16; ++tz)
+        for (int ty = 1; ty <= 16; ++ty)
+          for (int xl = 1; xl <= 16; ++xl) {
+            if (xl * ty * tz > 64 || xl * ty * tz < 32) continue;
+            const int WX = xl * B + 2 * H_, PY = ty + 2 * H_, WZ = tz + 2 * H_;
+            const int px = WX;                         // unpadded; padding must fit the budget later
+            const int lds = std::max(tables_bytes + WZ * PY * px * 4, msm::kLatWavesReduce * 64 * B * 8);
+            if (lds > msm::kLatMaxLds) continue;
+            const long long tiles = (long long)((L.n[0] + xl * B - 1) / (xl * B)) *
+                                    ((L.n[1] + ty - 1) / ty) * ((L.n[2] + tz - 1) / tz);
+            const double c = (double)tiles * (0.55 * B * taps + (double)WZ * PY * WX / 16.0);
+            if (c < lbest) {
+              lbest = c;
+              tb = msm::LatTile{k, xl, ty, tz, (L.n[0] + xl * B - 1) / (xl * B), (L.n[1] + ty - 1) / ty,
+                                (L.n[2] + tz - 1) / tz, 0, px};
+              tb_lds = lds;
+            }
+          }
+      if (lbest >= 1e300) {
+        ok = false;
+        break;
+      }
+      pad_window(tb, B, H_, (msm::kLatMaxLds - tables_bytes) / 4);
+      tb_lds = std::max(tables_bytes + (tb.tz + 2 * H_) * tb.pp * 4, msm::kLatWavesReduce * 64 * B * 8);
+      tb.block0 = (int)blocks;
+      blocks += (long long)tb.ntx * tb.nty * tb.ntz;
+      cost += lbest;
+      lds_max = std::max(lds_max, tb_lds);
+      cand.t[k] = tb;
+    }
+    if (!ok) continue;
+    const double est = cost * std::max(1.0, 256.0 / (double)std::max<long long>(blocks, 1));
+    cand.lds_bytes = lds_max;
+    if (est < best) {
+      best = est;
+      lat = cand;
+    }
+  }
+}
 
 }  // namespace
 
@@ -261,6 +400,46 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
         P->rows.push_back(row);
       }
   }
+  // compact stencil for the windowed kernel: for |nz|, ny >= 0 the weights
+  // W(nx) for nx = 0..xr (padded to a multiple of 4); rows for nz in [-H, H]
+  if (L > 1) {
+    int H = 0;
+    for (const auto& r : P->rows) H = std::max(H, std::abs(r.nx));
+    if (H <= msm::kLatMaxHalo) {
+      auto xrow = [&](int az, int ay) {
+        int xr = -1;
+        for (int nx = 0; nx <= H; ++nx)
+          if (h * std::sqrt((double)(nx * nx + ay * ay + az * az)) < 2.0 * a) xr = nx;
+        return xr;
+      };
+      std::vector<int> woff((size_t)(H + 1) * (H + 1), -1);
+      for (int az = 0; az <= H; ++az)
+        for (int ay = 0; ay <= H; ++ay) {
+          const int xr = xrow(az, ay);
+          if (xr < 0) continue;
+          woff[(size_t)az * (H + 1) + ay] = (int)P->weights_c.size();
+          for (int nx = 0; nx <= xr; ++nx) {
+            const double dist = h * std::sqrt((double)(nx * nx + ay * ay + az * az));
+            P->weights_c.push_back((float)(gamma_h(c, g.m, dist / a) / a -
+                                           gamma_h(c, g.m, dist / (2.0 * a)) / (2.0 * a)));
+          }
+          while (P->weights_c.size() % 4) P->weights_c.push_back(0.f);
+        }
+      for (int nz = -H; nz <= H; ++nz)
+        for (int ay = 0; ay <= H; ++ay) {
+          const int az = std::abs(nz);
+          const int xr = xrow(az, ay);
+          if (xr >= 0) P->rows_c.push_back(make_int4(nz, ay, xr, woff[(size_t)az * (H + 1) + ay]));
+        }
+      P->lat.n_rows = (int)P->rows_c.size();
+      P->lat.n_wc = (int)P->weights_c.size();
+      const int tables = P->lat.n_rows * 16 + P->lat.n_wc * 4;
+      choose_lattice_tiles(g, (int)P->weights.size(), H, tables, P->lat);
+    } else {
+      P->lat.b = 0;
+      P->lat.H = H;
+    }
+  }
   // top level (float64): T(d) = g^{l-1}(2^{l-1} h |d|) = gamma(r / A) / A, A = 2^{l-1} a
   {
     const msm::Level& T = g.lv[L - 1];
@@ -304,6 +483,8 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
   lay.bytes[msm::kSecTmp] = n * sizeof(int);
   lay.bytes[msm::kSecRows] = std::max<size_t>(P->rows.size(), 1) * sizeof(msm::StencilRow);
   lay.bytes[msm::kSecWeights] = std::max<size_t>(P->weights.size(), 1) * sizeof(float);
+  lay.bytes[msm::kSecRowsC] = std::max<size_t>(P->rows_c.size(), 1) * sizeof(int4);
+  lay.bytes[msm::kSecWeightsC] = std::max<size_t>(P->weights_c.size(), 1) * sizeof(float);
   lay.bytes[msm::kSecTop] = P->top.size() * sizeof(double);
   lay.bytes[msm::kSecPartials] = 10 * (size_t)P->n_partials * sizeof(double);
   size_t o = 0;
@@ -317,9 +498,15 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
 }
 
 msm_status msm_plan_destroy(msm_plan* plan) {
-  if (plan)
+  if (plan) {
     for (auto& e : plan->ev)
       if (e) (void)hipEventDestroy(e);
+    if (plan->aux) {
+      (void)hipStreamDestroy(plan->aux);
+      (void)hipEventDestroy(plan->fork);
+      (void)hipEventDestroy(plan->join);
+    }
+  }
   delete plan;
   return MSM_OK;
 }
@@ -359,6 +546,30 @@ msm_status msm_plan_info(const msm_plan* P, int32_t* levels, int32_t* grid_lo, i
   return MSM_OK;
 }
 
+msm_status msm_plan_describe(const msm_plan* P, char* buf, size_t buf_bytes) {
+  if (!P || !buf || buf_bytes == 0) return fail(MSM_ERR_INVALID_ARG, "null plan or buffer");
+  const Geom& g = P->g;
+  std::string o = "{";
+  o += "\"levels\": " + std::to_string(g.levels);
+  o += ", \"cells\": [" + std::to_string(g.nc[0]) + ", " + std::to_string(g.nc[1]) + ", " +
+       std::to_string(g.nc[2]) + "], \"reach\": " + std::to_string(g.reach) +
+       ", \"run_w\": " + std::to_string(g.run_w);
+  o += ", \"taps\": " + std::to_string(P->weights.size()) + ", \"halo\": " + std::to_string(P->lat.H);
+  o += ", \"lattice_b\": " + std::to_string(P->lat.b) + ", \"lattice_lds\": " +
+       std::to_string(P->lat.lds_bytes) + ", \"lattice_tiles\": [";
+  for (int k = 0; k < P->lat.n; ++k) {
+    const msm::LatTile& t = P->lat.t[k];
+    if (k) o += ", ";
+    o += "[" + std::to_string(t.xl) + ", " + std::to_string(t.ty) + ", " + std::to_string(t.tz) + ", " +
+         std::to_string(t.ntx * t.nty * t.ntz) + ", " +
+         std::to_string(bank_conflicts(t.xl, t.ty, t.tz, P->lat.b, t.px, t.pp)) + "]";
+  }
+  o += "], \"workspace_bytes\": " + std::to_string(P->lay.total) + "}";
+  std::strncpy(buf, o.c_str(), buf_bytes - 1);
+  buf[buf_bytes - 1] = 0;
+  return o.size() < buf_bytes ? MSM_OK : fail(MSM_ERR_INVALID_ARG, "buffer too small");
+}
+
 msm_status msm_workspace_bytes(const msm_plan* P, size_t* bytes) {
   if (!P || !bytes) return fail(MSM_ERR_INVALID_ARG, "null plan or bytes pointer");
   *bytes = P->lay.total;
@@ -373,6 +584,8 @@ msm_status msm_workspace_section(const msm_plan* P, int32_t section, size_t* off
   return MSM_OK;
 }
 
+static msm::DevPtrs dev_ptrs(const msm_plan* P, void* ws);
+
 msm_status msm_workspace_init(const msm_plan* P, void* ws, size_t ws_bytes, msm_stream_t stream) {
   if (!P) return fail(MSM_ERR_INVALID_ARG, "null plan");
   if (!ws || ws_bytes < P->lay.total) return fail(MSM_ERR_WORKSPACE, "workspace missing or too small");
@@ -386,10 +599,20 @@ msm_status msm_workspace_init(const msm_plan* P, void* ws, size_t ws_bytes, msm_
     e = hipMemcpyAsync(base + P->lay.off[msm::kSecWeights], P->weights.data(),
                        P->weights.size() * sizeof(float), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "upload stencil weights");
+    if (!P->rows_c.empty()) {
+      e = hipMemcpyAsync(base + P->lay.off[msm::kSecRowsC], P->rows_c.data(),
+                         P->rows_c.size() * sizeof(int4), hipMemcpyHostToDevice, s);
+      if (e != hipSuccess) return hip_fail(e, "upload compact stencil rows");
+      e = hipMemcpyAsync(base + P->lay.off[msm::kSecWeightsC], P->weights_c.data(),
+                         P->weights_c.size() * sizeof(float), hipMemcpyHostToDevice, s);
+      if (e != hipSuccess) return hip_fail(e, "upload compact stencil weights");
+    }
   }
   e = hipMemcpyAsync(base + P->lay.off[msm::kSecTop], P->top.data(), P->top.size() * sizeof(double),
                      hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_fail(e, "upload top-level table");
+  e = msm::launch_init(P->g, dev_ptrs(P, ws), s);
+  if (e != hipSuccess) return hip_fail(e, "clear cell counters");
   // pageable-memory copies are staged before returning; the plan may be destroyed afterwards
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "workspace init");
@@ -414,6 +637,8 @@ static msm::DevPtrs dev_ptrs(const msm_plan* P, void* ws) {
   d.tmp = reinterpret_cast<int*>(b + o[msm::kSecTmp]);
   d.rows = reinterpret_cast<const msm::StencilRow*>(b + o[msm::kSecRows]);
   d.weights = reinterpret_cast<const float*>(b + o[msm::kSecWeights]);
+  d.rows_c = reinterpret_cast<const int4*>(b + o[msm::kSecRowsC]);
+  d.weights_c = reinterpret_cast<const float*>(b + o[msm::kSecWeightsC]);
   d.top = reinterpret_cast<const double*>(b + o[msm::kSecTop]);
   d.partials = reinterpret_cast<double*>(b + o[msm::kSecPartials]);
   return d;
@@ -429,11 +654,12 @@ msm_status msm_compute(const msm_plan* P, void* ws, size_t ws_bytes, msm_stream_
   if (!((fx && fy && fz) || (!fx && !fy && !fz)))
     return fail(MSM_ERR_INVALID_ARG, "force outputs must be all set or all null");
   msm::DevPtrs d = dev_ptrs(P, ws);
-  hipError_t e = msm::launch_forward(P->g, d, (int)P->rows.size(), P->n_partials, P->restrict_j,
-                                     P->restrict_w, P->n_restrict, P->prolong_w,
-                                     reinterpret_cast<hipStream_t>(stream), x, y, z, q, fx, fy, fz,
-                                     phi, energy, virial,
-                                     P->profile ? const_cast<hipEvent_t*>(P->ev) : nullptr);
+  msm_plan* M = const_cast<msm_plan*>(P);
+  hipError_t e = ensure_aux(M);
+  if (e != hipSuccess) return hip_fail(e, "create auxiliary stream");
+  e = msm::launch_forward(P->g, d, (int)P->rows.size(), P->lat, P->n_partials,
+                          reinterpret_cast<hipStream_t>(stream), x, y, z, q, fx, fy, fz, phi, energy,
+                          virial, P->profile ? M->ev : nullptr, M->aux, M->fork, M->join);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return MSM_OK;
 }
@@ -471,12 +697,13 @@ msm_status msm_graph_capture(const msm_plan* P, void* ws, size_t ws_bytes, const
     delete G;
     return hip_fail(e, "create capture stream");
   }
-  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  msm_plan* M = const_cast<msm_plan*>(P);
+  if (e == hipSuccess) e = ensure_aux(M);
+  if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     msm::DevPtrs d = dev_ptrs(P, ws);
-    hipError_t le = msm::launch_forward(P->g, d, (int)P->rows.size(), P->n_partials, P->restrict_j,
-                                        P->restrict_w, P->n_restrict, P->prolong_w, cs, x, y, z, q,
-                                        fx, fy, fz, phi, energy, virial, nullptr);
+    hipError_t le = msm::launch_forward(P->g, d, (int)P->rows.size(), P->lat, P->n_partials, cs, x, y, z, q, fx, fy, fz, phi, energy, virial, nullptr,
+                                        M->aux, M->fork, M->join);
     e = hipStreamEndCapture(cs, &G->graph);
     if (le != hipSuccess) e = le;
   }

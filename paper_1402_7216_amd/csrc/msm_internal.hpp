@@ -59,6 +59,30 @@ struct StencilRow {
   int nx, ny, zr, woff;
 };
 
+// Windowed lattice-cutoff launch: one tile shape per sub-top level.
+struct LatTile {
+  int level;
+  int xl, ty, tz;          // lanes along x (B outputs each), y, z
+  int ntx, nty, ntz;       // tiles per dimension
+  int block0;              // first block of this level
+  int px;                  // padded LDS row pitch of the window (floats)
+  int pp;                  // padded LDS plane pitch of the window (floats)
+};
+
+constexpr int kLatMaxHalo = 16;          // windowed kernel handles stencil half-widths up to this
+constexpr int kLatMaxLds = 150 * 1024;   // LDS budget of one windowed block (bytes)
+constexpr int kLatWavesReduce = 16;      // waves per windowed block (their totals meet in LDS)
+
+struct LatLaunch {
+  int b;                   // outputs per lane along x (template), 0 = use the untiled kernel
+  int n;                   // levels in the launch
+  int H;                   // stencil half-width in nodes
+  int lds_bytes;           // dynamic LDS per block
+  int n_rows;              // compact rows (nz in [-H, H], ny >= 0)
+  int n_wc;                // compact weights (floats, each row padded to a multiple of 4)
+  LatTile t[kMaxLevels];
+};
+
 // Workspace sections (in order).  Offsets are 256-byte aligned.
 enum Section : int {
   kSecQGrid = 0,      // float[total_nodes]
@@ -75,6 +99,8 @@ enum Section : int {
   kSecTmp,            // int[n]
   kSecRows,           // StencilRow[n_rows]
   kSecWeights,        // float[n_weights]
+  kSecRowsC,          // int4[n_rows]: compact rows (nz, ny >= 0, xr, weight offset)
+  kSecWeightsC,       // float[n_wc]: W(nx, ny, |nz|) for nx = 0..xr per compact row
   kSecTop,            // double[top table]
   kSecPartials,       // double[10 * n_partials]: energy, then 9 virial components
   kSecCount
@@ -100,6 +126,8 @@ struct DevPtrs {
   int* cell_of;
   int* tmp;
   const StencilRow* rows;
+  const int4* rows_c;
+  const float* weights_c;
   const float* weights;
   const double* top;
   double* partials;
@@ -113,12 +141,17 @@ enum Stage : int {
 
 // Launchers (msm_kernels.hip).  All enqueue on `s` and return the first HIP error.
 // ev (nullable): kStageCount + 1 events recorded at the stage boundaries.
-hipError_t launch_forward(const Geom& g, const DevPtrs& d, int n_rows, int n_partials,
-                          const int* restrict_j, const float* restrict_w, int n_restrict,
-                          const float* prolong_w, hipStream_t s, const float* x, const float* y,
+// aux/fork/join (nullable): run the short-range pass on `aux`, concurrently
+// with the grid chain, joined back before interpolation.
+hipError_t launch_forward(const Geom& g, const DevPtrs& d, int n_rows, const LatLaunch& lat,
+                          int n_partials, hipStream_t s, const float* x, const float* y,
                           const float* z, const float* q, float* fx, float* fy, float* fz,
-                          float* phi, double* energy, double* virial, hipEvent_t* ev);
+                          float* phi, double* energy, double* virial, hipEvent_t* ev,
+                          hipStream_t aux, hipEvent_t fork, hipEvent_t join);
 
-int interp_partials(const Geom& g);      // number of FP64 partial slots the forward pass uses
+int interp_partials(const Geom& g);
+
+// Workspace initialisation on the device (clears the cell counters).
+hipError_t launch_init(const Geom& g, const DevPtrs& d, hipStream_t s);      // number of FP64 partial slots the forward pass uses
 
 }  // namespace msm

@@ -112,12 +112,11 @@ __device__ __forceinline__ float phi_any(float u) {
 // --------------------------------------------------------------------------
 // Link cells (Sec. 2.1): counting sort of atoms by cell, stable in input order.
 // --------------------------------------------------------------------------
-__global__ void k_zero(int* __restrict__ counts, int* __restrict__ cursor, int n_cells,
-                       int* __restrict__ status) {
+// Counts are zero on entry: the workspace is initialised that way and k_scan
+// clears them (with the scatter cursors and the status word) after reading.
+__global__ void k_zero_counts(int* __restrict__ counts, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i <= n_cells) counts[i] = 0;
-  if (i < n_cells) cursor[i] = 0;
-  if (i < 64) status[i] = 0;
+  if (i < n) counts[i] = 0;
 }
 
 __device__ __forceinline__ int cell_index(const Geom& g, float x, float y, float z) {
@@ -133,29 +132,19 @@ __device__ __forceinline__ int cell_index(const Geom& g, float x, float y, float
 }
 
 __global__ void k_bin_count(Geom g, const float* __restrict__ x, const float* __restrict__ y,
-                            const float* __restrict__ z, const float* __restrict__ q,
-                            int* __restrict__ counts, int* __restrict__ cell_of,
-                            int* __restrict__ status) {
+                            const float* __restrict__ z, int* __restrict__ counts,
+                            int* __restrict__ cell_of) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.n_atoms) return;
-  float px = x[i], py = y[i], pz = z[i], pq = q[i];
-  int flags = 0;
-  if (!(isfinite(px) && isfinite(py) && isfinite(pz) && isfinite(pq))) {
-    flags |= kFlagNonFinite;
-  } else {
-    double p[3] = {(double)px, (double)py, (double)pz};
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-      if (p[d] < g.lo[d] || p[d] > g.hi[d]) flags |= kFlagOutOfBox;
-  }
-  if (flags) atomicOr(status, flags);
-  int c = cell_index(g, px, py, pz);
+  int c = cell_index(g, x[i], y[i], z[i]);
   cell_of[i] = c;
   atomicAdd(&counts[c], 1);
 }
 
-// Exclusive scan of counts[0..n) into start[0..n] by one block of 1024 threads.
-__global__ void __launch_bounds__(1024) k_scan(const int* __restrict__ counts, int* __restrict__ start,
+// Exclusive scan of counts[0..n) into start[0..n] by one block of 1024
+// threads; then clears counts, cursors and the status word for this call.
+__global__ void __launch_bounds__(1024) k_scan(int* __restrict__ counts, int* __restrict__ start,
+                                               int* __restrict__ cursor, int* __restrict__ status,
                                                int n) {
   __shared__ int part[1024];
   int t = threadIdx.x;
@@ -175,51 +164,74 @@ __global__ void __launch_bounds__(1024) k_scan(const int* __restrict__ counts, i
   for (int i = b; i < e; ++i) {
     start[i] = run;
     run += counts[i];
+    counts[i] = 0;
+    cursor[i] = 0;
   }
   if (t == 1023) start[n] = part[1023];
+  if (t < 64) status[t] = 0;
 }
 
-__global__ void k_bin_scatter(Geom g, const int* __restrict__ cell_of, const int* __restrict__ start,
-                              int* __restrict__ cursor, int* __restrict__ tmp) {
+// Scatter into cell segments in arrival order (atomic cursors); the atom's
+// index and raw coordinates travel together so the next pass reads each
+// segment contiguously.
+__global__ void k_bin_scatter(Geom g, const float* __restrict__ x, const float* __restrict__ y,
+                              const float* __restrict__ z, const float* __restrict__ q,
+                              const int* __restrict__ cell_of, const int* __restrict__ start,
+                              int* __restrict__ cursor, int* __restrict__ tmp,
+                              float4* __restrict__ tmp4) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.n_atoms) return;
-  int c = cell_of[i];
-  tmp[start[c] + atomicAdd(&cursor[c], 1)] = i;
+  const float4 p = make_float4(x[i], y[i], z[i], q[i]);
+  const int c = cell_of[i];
+  const int slot = start[c] + atomicAdd(&cursor[c], 1);
+  tmp[slot] = i;
+  tmp4[slot] = p;
 }
 
-// Final slot of each atom = cell start + number of atoms of the same cell with a
-// smaller input index (a stable order independent of the scatter's atomics).
-// Also flags coincident atoms and writes sanitised, box-clamped coordinates so
-// every later kernel stays inside the grid even for bad input.
-__global__ void k_bin_place(Geom g, const float* __restrict__ x, const float* __restrict__ y,
-                            const float* __restrict__ z, const float* __restrict__ q,
-                            const int* __restrict__ cell_of, const int* __restrict__ start,
-                            const int* __restrict__ tmp, float4* __restrict__ sorted,
-                            int* __restrict__ perm, int* __restrict__ status) {
+// Final slot of each atom = cell start + number of atoms of the same cell with
+// a smaller input index (a stable order independent of the scatter's atomics).
+// Also validates the input (non-finite, outside the box, coincident atoms) and
+// writes sanitised, box-clamped coordinates so every later kernel stays inside
+// the grid even for bad input.
+__global__ void k_bin_place(Geom g, const int* __restrict__ cell_of, const int* __restrict__ start,
+                            const int* __restrict__ tmp, const float4* __restrict__ tmp4,
+                            float4* __restrict__ sorted, int* __restrict__ perm,
+                            int* __restrict__ status) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= g.n_atoms) return;
-  int i = tmp[s];
-  int c = cell_of[i];
-  int b = start[c], e = start[c + 1];
-  float px = x[i], py = y[i], pz = z[i], pq = q[i];
+  const int i = tmp[s];
+  const float4 p = tmp4[s];
+  const int c = cell_of[i];
+  const int b = start[c], e = start[c + 1];
+  int flags = 0;
+  if (!(isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(p.w))) {
+    flags |= kFlagNonFinite;
+  } else {
+    const double pd[3] = {(double)p.x, (double)p.y, (double)p.z};
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      if (pd[d] < g.lo[d] || pd[d] > g.hi[d]) flags |= kFlagOutOfBox;
+  }
   int dst = s;
   if (e - b <= kRankCap) {
     int rank = 0;
-    bool coincident = false;
+#pragma unroll 4
     for (int t = b; t < e; ++t) {
-      int j = tmp[t];
+      const int j = tmp[t];
+      const float4 o = tmp4[t];
       rank += (j < i);
-      if (j != i && x[j] == px && y[j] == py && z[j] == pz) coincident = true;
+      if (j != i && o.x == p.x && o.y == p.y && o.z == p.z) flags |= kFlagCoincident;
     }
     dst = b + rank;
-    if (coincident) atomicOr(status, kFlagCoincident);
   }
-  float hi[3] = {(float)g.hi[0], (float)g.hi[1], (float)g.hi[2]};
-  px = fminf(fmaxf(px, g.lo_f[0]), hi[0]);
-  py = fminf(fmaxf(py, g.lo_f[1]), hi[1]);
-  pz = fminf(fmaxf(pz, g.lo_f[2]), hi[2]);
-  if (!isfinite(pq)) pq = 0.f;
-  sorted[dst] = make_float4(px, py, pz, pq);
+  if (flags) atomicOr(status, flags);
+  const float hx = (float)g.hi[0], hy = (float)g.hi[1], hz = (float)g.hi[2];
+  float4 o;
+  o.x = fminf(fmaxf(p.x, g.lo_f[0]), hx);
+  o.y = fminf(fmaxf(p.y, g.lo_f[1]), hy);
+  o.z = fminf(fmaxf(p.z, g.lo_f[2]), hz);
+  o.w = isfinite(p.w) ? p.w : 0.f;
+  sorted[dst] = o;
   perm[dst] = i;
 }
 
@@ -238,8 +250,9 @@ __global__ void __launch_bounds__(kBlock) k_short(Geom g, const float4* __restri
                                                   const int* __restrict__ start,
                                                   float4* __restrict__ fshort) {
   __shared__ float4 red[kBlock];
+  __shared__ float4 jbuf[kBlock / kWave][kWave];
   const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int run = blockIdx.x % g.runs_x;
   const int row = blockIdx.x / g.runs_x;
   const int cy = row % g.nc[1], cz = row / g.nc[1];
@@ -250,39 +263,48 @@ __global__ void __launch_bounds__(kBlock) k_short(Geom g, const float4* __restri
   const int R = g.reach, side = 2 * R + 1;
   const int jx0 = max(cx0 - R, 0), jx1 = min(cx1 + R, g.nc[0] - 1);
   const float a2 = g.a2, inv_a2 = g.inv_a2;
+  float4* jb_w = jbuf[wave];
 
   for (int ic = ib; ic < ie; ic += kWave) {
     const int i = ic + lane;
-    float4 pi = (i < ie) ? sorted[i] : make_float4(3.0e30f, 3.0e30f, 3.0e30f, 0.f);
+    const float4 pi = (i < ie) ? sorted[i] : make_float4(3.0e30f, 3.0e30f, 3.0e30f, 0.f);
     float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;
     for (int rr = wave; rr < side * side; rr += kBlock / kWave) {
       const int jy = cy + rr % side - R, jz = cz + rr / side - R;
       if (jy < 0 || jz < 0 || jy >= g.nc[1] || jz >= g.nc[2]) continue;
-      const int jb = (jz * g.nc[1] + jy) * g.nc[0];
-      const int j0 = start[jb + jx0], j1 = start[jb + jx1 + 1];
-      for (int j = j0; j < j1; ++j) {
-        const float4 pj = sorted[j];
-        const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        if (r2 < a2 && r2 > 0.f) {
-          // hardware reciprocal square root plus one Newton step (the raw
-          // instruction's error is biased, which would bias the energy)
-          float ri = __builtin_amdgcn_rsqf(r2);
-          ri = fmaf(0.5f * ri, fmaf(-r2 * ri, ri, 1.f), ri);
-          const float ri2 = ri * ri;
-          const float s = r2 * inv_a2;
-          float gm = g.gcoef[M], dg = g.dcoef[M];
+      const int jrow = (jz * g.nc[1] + jy) * g.nc[0];
+      const int j0 = start[jrow + jx0], j1 = start[jrow + jx1 + 1];
+      for (int jc = j0; jc < j1; jc += kWave) {
+        // stage up to 64 j atoms in this wave's LDS slice (coalesced), then
+        // read them back as wave-wide broadcasts
+        const int nj = min(kWave, j1 - jc);
+        jb_w[lane] = (lane < nj) ? sorted[jc + lane] : make_float4(-3.0e30f, -3.0e30f, -3.0e30f, 0.f);
+        const int nj4 = (nj + 3) & ~3;
+#pragma unroll 4
+        for (int t = 0; t < nj4; ++t) {
+          const float4 pj = jb_w[t];
+          const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+          const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+          if (r2 < a2 && r2 > 0.f) {
+            // hardware reciprocal square root plus one Newton step (the raw
+            // instruction's error is biased, which would bias the energy)
+            float ri = __builtin_amdgcn_rsqf(r2);
+            ri = fmaf(0.5f * ri, fmaf(-r2 * ri, ri, 1.f), ri);
+            const float ri2 = ri * ri;
+            const float s = r2 * inv_a2;
+            float gm = g.gcoef[M], dg = g.dcoef[M];
 #pragma unroll
-          for (int k = M - 1; k >= 0; --k) gm = fmaf(gm, s, g.gcoef[k]);
+            for (int k = M - 1; k >= 0; --k) gm = fmaf(gm, s, g.gcoef[k]);
 #pragma unroll
-          for (int k = M - 1; k >= 1; --k) dg = fmaf(dg, s, g.dcoef[k]);
-          const float gs = ri - gm;                    // g*(r)
-          const float fr = fmaf(ri, ri2, dg);          // -g*'(r)/r
-          ap = fmaf(pj.w, gs, ap);
-          const float wq = pj.w * fr;
-          ax = fmaf(wq, dx, ax);
-          ay = fmaf(wq, dy, ay);
-          az = fmaf(wq, dz, az);
+            for (int k = M - 1; k >= 1; --k) dg = fmaf(dg, s, g.dcoef[k]);
+            const float gs = ri - gm;                    // g*(r)
+            const float fr = fmaf(ri, ri2, dg);          // -g*'(r)/r
+            ap = fmaf(pj.w, gs, ap);
+            const float wq = pj.w * fr;
+            ax = fmaf(wq, dx, ax);
+            ay = fmaf(wq, dy, ay);
+            az = fmaf(wq, dz, az);
+          }
         }
       }
     }
@@ -303,91 +325,216 @@ __global__ void __launch_bounds__(kBlock) k_short(Geom g, const float4* __restri
 }
 
 // --------------------------------------------------------------------------
-// Anterpolation (itemised algorithm): q^0_mu = sum_j phi^0_mu(r_j) q_j, as a
-// gather per level-0 node over the atoms of the cells its support touches.
+// Anterpolation (itemised algorithm): q^0_mu = sum_j phi^0_mu(r_j) q_j.
+// One block owns an 8x8x8 tile of level-0 nodes.  Its threads walk the atoms
+// of the cells whose atoms can touch the tile; each atom computes its basis
+// weights once and adds q_j phi^0_mu(r_j) for the tile's nodes it touches into
+// LDS as 2^-36 fixed-point integers.  Integer addition is associative, so the
+// result does not depend on the order of the atomics.
 // --------------------------------------------------------------------------
+constexpr double kFix = 68719476736.0;            // 2^36
+constexpr double kInvFix = 1.0 / 68719476736.0;
+
+constexpr int kAX = 8, kAY = 8, kAZ = 4;          // anterpolation tile (level-0 nodes)
+
+template <int ORDER>
+__device__ __forceinline__ void anterp_atom(const Geom& g, const int* n0, float4 p,
+                                            unsigned long long* acc) {
+  constexpr int H = ORDER / 2;
+  const float pp[3] = {p.x, p.y, p.z};
+  const int tdim[3] = {kAX, kAY, kAZ};
+  int base[3];
+  float w[3][ORDER], dw[3][ORDER];
+  bool touch = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int f;
+    float off;
+    grid_coord(pp[d], g.lo_f[d], g.h, g.inv_h, g.fmax[d], f, off);
+    base[d] = f - (H - 1) - n0[d];            // tile-local index of the atom's first node
+    touch = touch && (base[d] + ORDER > 0) && (base[d] < tdim[d]);
+    basis<ORDER>(off, w[d], dw[d]);
+  }
+  if (!touch) return;
+#pragma unroll
+  for (int sz = 0; sz < ORDER; ++sz) {
+    const int lz = base[2] + sz;
+    if (lz < 0 || lz >= kAZ) continue;
+    const float qz = p.w * w[2][sz];
+#pragma unroll
+    for (int sy = 0; sy < ORDER; ++sy) {
+      const int ly = base[1] + sy;
+      if (ly < 0 || ly >= kAY) continue;
+      const float qyz = qz * w[1][sy];
+#pragma unroll
+      for (int sx = 0; sx < ORDER; ++sx) {
+        const int lx = base[0] + sx;
+        if (lx < 0 || lx >= kAX) continue;
+        const long long v = __double2ll_rn((double)(qyz * w[0][sx]) * kFix);
+        atomicAdd(&acc[(lz * kAY + ly) * kAX + lx], (unsigned long long)v);
+      }
+    }
+  }
+}
+
 template <int ORDER>
 __global__ void __launch_bounds__(kBlock) k_anterp(Geom g, const float4* __restrict__ sorted,
                                                    const int* __restrict__ start,
                                                    float* __restrict__ qgrid) {
   constexpr int H = ORDER / 2;
+  __shared__ unsigned long long acc[kAX * kAY * kAZ];
+  __shared__ int row_beg[64], row_pre[65];
   const Level L = g.lv[0];
-  int node = blockIdx.x * blockDim.x + threadIdx.x;
-  if (node >= L.count) return;
-  int mu[3] = {node % L.n[0] + L.lo[0], (node / L.n[0]) % L.n[1] + L.lo[1],
-               node / (L.n[0] * L.n[1]) + L.lo[2]};
-  // atoms touching mu have floor index in [mu - H, mu + H - 1]: positions in
-  // [lo + (mu - H) h, lo + (mu + H) h); widen by a small margin for rounding
+  const int ntx = (L.n[0] + kAX - 1) / kAX, nty = (L.n[1] + kAY - 1) / kAY;
+  const int bx = blockIdx.x % ntx, by = (blockIdx.x / ntx) % nty, bz = blockIdx.x / (ntx * nty);
+  const int n0[3] = {L.lo[0] + bx * kAX, L.lo[1] + by * kAY, L.lo[2] + bz * kAZ};
+  const int tdim[3] = {kAX, kAY, kAZ};
+  for (int i = threadIdx.x; i < kAX * kAY * kAZ; i += blockDim.x) acc[i] = 0ull;
+  // atoms touching the tile have floor index f in [n0 - H, n0 + T - 1 + H - 1]:
+  // box-relative positions in [(n0 - H) h, (n0 + T - 1 + H) h)
   int c0[3], c1[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    float xl = ((float)(mu[d] - H) - 0.01f) * g.h, xh = ((float)(mu[d] + H) + 0.01f) * g.h;
+    const float xl = ((float)(n0[d] - H) - 0.01f) * g.h, xh = ((float)(n0[d] + tdim[d] - 1 + H) + 0.01f) * g.h;
     c0[d] = min(g.nc[d] - 1, max(0, (int)floorf(fmaxf(xl, 0.f) * g.inv_cs[d])));
     c1[d] = max(c0[d], min(g.nc[d] - 1, (int)floorf(fmaxf(xh, 0.f) * g.inv_cs[d])));
   }
-  float acc = 0.f;
-  for (int cz = c0[2]; cz <= c1[2]; ++cz)
-    for (int cy = c0[1]; cy <= c1[1]; ++cy) {
-      int rb = (cz * g.nc[1] + cy) * g.nc[0];
-      int jb = start[rb + c0[0]], je = start[rb + c1[0] + 1];
-      for (int j = jb; j < je; ++j) {
-        float4 p = sorted[j];
-        float pp[3] = {p.x, p.y, p.z};
-        float w = p.w;
-        bool in = true;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          int f;
-          float r;
-          grid_coord(pp[d], g.lo_f[d], g.h, g.inv_h, g.fmax[d], f, r);
-          int sidx = mu[d] - (f - (H - 1));
-          in = in && (sidx >= 0) && (sidx < ORDER);
-          w *= phi_any<ORDER>(r + (float)(H - 1 - sidx));
-        }
-        if (in) acc += w;
-      }
+  // candidate atoms: the contiguous sorted ranges of the cell rows in
+  // [c0, c1], taken 64 rows at a time; prefix sums over a chunk's rows let
+  // every thread walk one flat index space (the next atom is loaded while the
+  // current one is processed)
+  const int nry = c1[1] - c0[1] + 1, nrows = nry * (c1[2] - c0[2] + 1);
+  for (int rc0 = 0; rc0 < nrows; rc0 += 64) {
+    const int nr = min(64, nrows - rc0);
+    __syncthreads();                                   // previous chunk is done with the table
+    if (threadIdx.x < nr) {
+      const int rr = rc0 + threadIdx.x;
+      const int cy = c0[1] + rr % nry, cz = c0[2] + rr / nry;
+      const int rb = (cz * g.nc[1] + cy) * g.nc[0];
+      row_beg[threadIdx.x] = start[rb + c0[0]];
+      row_pre[threadIdx.x + 1] = start[rb + c1[0] + 1] - start[rb + c0[0]];
     }
-  qgrid[L.off + node] = acc;
+    if (threadIdx.x == 0) row_pre[0] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int q = 0; q < nr; ++q) row_pre[q + 1] += row_pre[q];
+    __syncthreads();
+    const int ncand = row_pre[nr];
+    int row = 0;
+    int t = threadIdx.x;
+    float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (t < ncand) {
+      while (row_pre[row + 1] <= t) ++row;
+      nxt = sorted[row_beg[row] + (t - row_pre[row])];
+    }
+    while (t < ncand) {
+      const float4 p = nxt;
+      const int tn = t + blockDim.x;
+      if (tn < ncand) {
+        while (row_pre[row + 1] <= tn) ++row;
+        nxt = sorted[row_beg[row] + (tn - row_pre[row])];
+      }
+      anterp_atom<ORDER>(g, n0, p, acc);
+      t = tn;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kAX * kAY * kAZ; i += blockDim.x) {
+    const int lx = i % kAX, ly = (i / kAX) % kAY, lz = i / (kAX * kAY);
+    const int gx = bx * kAX + lx, gy = by * kAY + ly, gz = bz * kAZ + lz;
+    if (gx < L.n[0] && gy < L.n[1] && gz < L.n[2])
+      qgrid[L.off + ((size_t)gz * L.n[1] + gy) * L.n[0] + gx] =
+          (float)((double)(long long)acc[i] * kInvFix);
+  }
 }
 
 // --------------------------------------------------------------------------
 // Restriction (itemised algorithm): q^{k+1}_mu = sum_nu Phi(nu/2 - mu)^3 q^k_nu.
 // Only offsets j = nu - 2 mu with Phi(j/2) != 0 are visited (given as lists).
 // --------------------------------------------------------------------------
-struct RestrictTaps {
-  int n;
-  int j[12];
-  float w[12];
+// Phi at half-integers, evaluated at compile time from the piecewise forms
+// above: the weights of restriction (nu = 2 mu + j) and prolongation.  Phi
+// vanishes at non-zero integers, so only j = 0 and odd j contribute.
+constexpr double phi_half(int order, int j) {
+  const double t = (j < 0 ? -j : j) * 0.5;
+  if (order == 4) {
+    if (t <= 1.0) return (1.0 - t) * (1.0 + t - 1.5 * t * t);
+    if (t <= 2.0) return -0.5 * (t - 1.0) * (2.0 - t) * (2.0 - t);
+    return 0.0;
+  }
+  if (t <= 1.0) return (1.0 - t * t) * (2.0 - t) * (6.0 + 3.0 * t - 5.0 * t * t) / 12.0;
+  if (t <= 2.0) return (1.0 - t) * (2.0 - t) * (3.0 - t) * (4.0 + 9.0 * t - 5.0 * t * t) / 24.0;
+  if (t <= 3.0) return (t - 1.0) * (t - 2.0) * (t - 3.0) * (t - 3.0) * (4.0 - t) / 24.0;
+  return 0.0;
+}
+
+template <int ORDER>
+struct Dyadic {
+  static constexpr int R = ORDER - 1;          // largest |j| with a non-zero weight
+  static constexpr int NT = ORDER + 1;         // taps: 0 and the ORDER odd j in [-R, R]
+  // tap offsets and weights, ascending j
+  static constexpr int j(int t) { return t < ORDER / 2 ? 2 * t - R : (t == ORDER / 2 ? 0 : 2 * (t - ORDER / 2) - 1); }
+  static constexpr float w(int t) { return (float)phi_half(ORDER, j(t)); }
+  // odd fine index m: coarse nu = (m - R)/2 + i, i < ORDER, weight Phi((R - 2i)/2)
+  static_assert(j(0) == -R && j(ORDER / 2) == 0 && j(ORDER) == R, "tap offsets");
+  static constexpr float wodd(int i) { return (float)phi_half(ORDER, R - 2 * i); }
 };
 
-__global__ void __launch_bounds__(kBlock) k_restrict(Geom g, int k, RestrictTaps taps,
-                                                     float* __restrict__ grid) {
+// One block = 8 x 8 x 4 coarse nodes; the fine nodes they read are staged in LDS.
+constexpr int kRX = 8, kRY = 8, kRZ = 4;
+
+template <int ORDER>
+__global__ void __launch_bounds__(kBlock) k_restrict(Geom g, int k, float* __restrict__ grid) {
+  using D = Dyadic<ORDER>;
+  constexpr int R = D::R;
+  constexpr int FX = 2 * kRX - 1 + 2 * R, FY = 2 * kRY - 1 + 2 * R, FZ = 2 * kRZ - 1 + 2 * R;
+  __shared__ float fine[FX * FY * FZ];
   const Level F = g.lv[k], C = g.lv[k + 1];
-  int node = blockIdx.x * blockDim.x + threadIdx.x;
-  if (node >= C.count) return;
-  int mx = node % C.n[0] + C.lo[0], my = (node / C.n[0]) % C.n[1] + C.lo[1],
-      mz = node / (C.n[0] * C.n[1]) + C.lo[2];
+  const int ntx = (C.n[0] + kRX - 1) / kRX, nty = (C.n[1] + kRY - 1) / kRY;
+  const int bx = blockIdx.x % ntx, by = (blockIdx.x / ntx) % nty, bz = blockIdx.x / (ntx * nty);
+  const int c0x = bx * kRX, c0y = by * kRY, c0z = bz * kRZ;          // level-local coarse origin
+  // absolute fine index of local fine (0,0,0): 2 (C.lo + c0) - R
+  const int f0x = 2 * (C.lo[0] + c0x) - R, f0y = 2 * (C.lo[1] + c0y) - R, f0z = 2 * (C.lo[2] + c0z) - R;
   const float* fin = grid + F.off;
-  float acc = 0.f;
-  for (int a = 0; a < taps.n; ++a) {
-    int vz = 2 * mz + taps.j[a] - F.lo[2];
-    if (vz < 0 || vz >= F.n[2]) continue;
-    float wz = taps.w[a];
-    for (int b = 0; b < taps.n; ++b) {
-      int vy = 2 * my + taps.j[b] - F.lo[1];
-      if (vy < 0 || vy >= F.n[1]) continue;
-      float wyz = taps.w[b] * wz;
-      const float* rowp = fin + ((size_t)vz * F.n[1] + vy) * F.n[0];
-      float racc = 0.f;
-      for (int c = 0; c < taps.n; ++c) {
-        int vx = 2 * mx + taps.j[c] - F.lo[0];
-        if (vx < 0 || vx >= F.n[0]) continue;
-        racc = fmaf(taps.w[c], rowp[vx], racc);
+  constexpr int nfine = FX * FY * FZ;
+  for (int i0 = 0; i0 < nfine; i0 += 8 * kBlock) {       // 8 loads in flight per thread
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * kBlock + threadIdx.x;
+      v[u] = 0.f;
+      if (i < nfine) {
+        const int lx = i % FX, ly = (i / FX) % FY, lz = i / (FX * FY);
+        const int vx = f0x + lx - F.lo[0], vy = f0y + ly - F.lo[1], vz = f0z + lz - F.lo[2];
+        if (vx >= 0 && vx < F.n[0] && vy >= 0 && vy < F.n[1] && vz >= 0 && vz < F.n[2])
+          v[u] = fin[((size_t)vz * F.n[1] + vy) * F.n[0] + vx];
       }
-      acc = fmaf(wyz, racc, acc);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * kBlock + threadIdx.x;
+      if (i < nfine) fine[i] = v[u];
     }
   }
-  grid[C.off + node] = acc;
+  __syncthreads();
+  const int tx = threadIdx.x % kRX, ty = (threadIdx.x / kRX) % kRY, tz = threadIdx.x / (kRX * kRY);
+  const int mx = c0x + tx, my = c0y + ty, mz = c0z + tz;
+  if (tz >= kRZ || mx >= C.n[0] || my >= C.n[1] || mz >= C.n[2]) return;
+  float acc = 0.f;
+#pragma unroll
+  for (int a = 0; a < D::NT; ++a) {
+    const int lz = 2 * tz + D::j(a) + R;
+#pragma unroll
+    for (int b = 0; b < D::NT; ++b) {
+      const int ly = 2 * ty + D::j(b) + R;
+      const float* rowp = fine + (lz * FY + ly) * FX + 2 * tx + R;
+      float racc = 0.f;
+#pragma unroll
+      for (int c = 0; c < D::NT; ++c) racc = fmaf(D::w(c), rowp[D::j(c)], racc);
+      acc = fmaf(D::w(b) * D::w(a), racc, acc);
+    }
+  }
+  grid[C.off + ((size_t)mz * C.n[1] + my) * C.n[0] + mx] = acc;
 }
 
 // --------------------------------------------------------------------------
@@ -424,29 +571,199 @@ __global__ void __launch_bounds__(kBlock) k_lattice(Geom g, const StencilRow* __
 }
 
 // --------------------------------------------------------------------------
+// Lattice cutoff, windowed (same sum as k_lattice).  One block = one output
+// tile of one level: xl lanes along x (B consecutive outputs each, kept in
+// registers), ty along y, tz along z.  The block stages its whole input
+// window ((tz + 2H) x (ty + 2H) x (xl B + 2H), zero outside the grid) in LDS
+// once, together with the stencil in compact form, then its 16 waves split a
+// flat list of stencil rows with no further barriers.
+//
+// Compact stencil: W depends on |n| only, so a row (nz, ny) with taps
+// nx in [-xr, xr] stores W for nx = 0..xr, shared by nz and -nz; and rows
+// (nz, +ny), (nz, -ny) are processed together by adding their inputs first
+// (one FMA chain for both).
+// --------------------------------------------------------------------------
+constexpr int kLatThreads = 1024;
+constexpr int kLatWaves = kLatThreads / kWave;
+
+template <int B, int XR, bool PAIR>
+__device__ __forceinline__ void row_win(float* acc, const float* a, const float* b,
+                                        const float* wrow) {
+  float w[XR + 1];
+#pragma unroll
+  for (int t = 0; t <= XR; ++t) w[t] = wrow[t];
+  float v[B + 2 * XR];
+#pragma unroll
+  for (int j = 0; j < B + 2 * XR; ++j) v[j] = PAIR ? a[j] + b[j] : a[j];
+#pragma unroll
+  for (int t = 0; t < 2 * XR + 1; ++t) {
+    const float wt = w[t < XR ? XR - t : t - XR];
+#pragma unroll
+    for (int bb = 0; bb < B; ++bb) acc[bb] = fmaf(wt, v[bb + t], acc[bb]);
+  }
+}
+
+template <int B, bool PAIR>
+__device__ __forceinline__ void row_win_dispatch(int xr, float* acc, const float* a, const float* b,
+                                                 const float* w) {
+  switch (xr) {
+    case 0: row_win<B, 0, PAIR>(acc, a, b, w); break;
+    case 1: row_win<B, 1, PAIR>(acc, a, b, w); break;
+    case 2: row_win<B, 2, PAIR>(acc, a, b, w); break;
+    case 3: row_win<B, 3, PAIR>(acc, a, b, w); break;
+    case 4: row_win<B, 4, PAIR>(acc, a, b, w); break;
+    case 5: row_win<B, 5, PAIR>(acc, a, b, w); break;
+    case 6: row_win<B, 6, PAIR>(acc, a, b, w); break;
+    case 7: row_win<B, 7, PAIR>(acc, a, b, w); break;
+    case 8: row_win<B, 8, PAIR>(acc, a, b, w); break;
+    case 9: row_win<B, 9, PAIR>(acc, a, b, w); break;
+    case 10: row_win<B, 10, PAIR>(acc, a, b, w); break;
+    case 11: row_win<B, 11, PAIR>(acc, a, b, w); break;
+    case 12: row_win<B, 12, PAIR>(acc, a, b, w); break;
+    case 13: row_win<B, 13, PAIR>(acc, a, b, w); break;
+    case 14: row_win<B, 14, PAIR>(acc, a, b, w); break;
+    case 15: row_win<B, 15, PAIR>(acc, a, b, w); break;
+    default: row_win<B, 16, PAIR>(acc, a, b, w); break;
+  }
+}
+
+template <int B>
+__global__ void __launch_bounds__(kLatThreads) k_lattice_win(Geom g, LatLaunch P,
+                                                             const int4* __restrict__ rows_g,
+                                                             const float* __restrict__ wc_g,
+                                                             const float* __restrict__ qgrid,
+                                                             float* __restrict__ ucut) {
+  extern __shared__ float4 lds4[];
+  int4* rows = reinterpret_cast<int4*>(lds4);
+  float* wc = reinterpret_cast<float*>(lds4 + P.n_rows);
+  float* win = wc + P.n_wc;
+  int bid = blockIdx.x, li = 0;
+  while (li + 1 < P.n && bid >= P.t[li + 1].block0) ++li;
+  const LatTile T = P.t[li];
+  const Level Lv = g.lv[T.level];
+  bid -= T.block0;
+  const int bx = bid % T.ntx, by = (bid / T.ntx) % T.nty, bz = bid / (T.ntx * T.nty);
+  const int H = P.H;
+  const int x0 = bx * T.xl * B, y0 = by * T.ty, z0 = bz * T.tz;
+  const int WX = T.xl * B + 2 * H, PY = T.ty + 2 * H, WZ = T.tz + 2 * H, PX = T.px, PP = T.pp;
+  const float* qk = qgrid + Lv.off;
+  const int NX = Lv.n[0], NY = Lv.n[1], NZ = Lv.n[2];
+
+  for (int i = threadIdx.x; i < P.n_rows; i += kLatThreads) rows[i] = rows_g[i];
+  for (int i = threadIdx.x; i < P.n_wc; i += kLatThreads) wc[i] = wc_g[i];
+  const int nwin = WZ * PY * WX;
+  for (int i0 = 0; i0 < nwin; i0 += 8 * kLatThreads) {      // 8 loads in flight per thread
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * kLatThreads + threadIdx.x;
+      v[u] = 0.f;
+      if (i < nwin) {
+        const int xx = i % WX, yy = (i / WX) % PY, zz = i / (WX * PY);
+        const int gx = x0 - H + xx, gy = y0 - H + yy, gz = z0 - H + zz;
+        if (gx >= 0 && gx < NX && gy >= 0 && gy < NY && gz >= 0 && gz < NZ)
+          v[u] = qk[((size_t)gz * NY + gy) * NX + gx];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * kLatThreads + threadIdx.x;
+      if (i < nwin) {
+        const int xx = i % WX, yy = (i / WX) % PY, zz = i / (WX * PY);
+        win[zz * PP + yy * PX + xx] = v[u];
+      }
+    }
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int xi = lane % T.xl, yi = (lane / T.xl) % T.ty, zi = lane / (T.xl * T.ty);
+  const bool active = zi < T.tz;
+  const float* base = win + (zi + H) * PP + (yi + H) * PX + xi * B + H;
+  double tot[B];
+  float acc[B];
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    tot[b] = 0.0;
+    acc[b] = 0.f;
+  }
+  int cnt = 0;
+  int4 row = (wave < P.n_rows) ? rows[wave] : make_int4(0, 0, 0, 0);
+  for (int r = wave; r < P.n_rows; r += kLatWaves) {
+    const int4 cur = row;
+    if (r + kLatWaves < P.n_rows) row = rows[r + kLatWaves];       // next descriptor in flight
+    const int nz = __builtin_amdgcn_readfirstlane(cur.x);
+    const int ny = __builtin_amdgcn_readfirstlane(cur.y);
+    const int xr = __builtin_amdgcn_readfirstlane(cur.z);
+    const int wo = __builtin_amdgcn_readfirstlane(cur.w);
+    if (active) {
+      const float* a = base + nz * PP + ny * PX - xr;
+      if (ny == 0) {
+        row_win_dispatch<B, false>(xr, acc, a, a, wc + wo);
+      } else {
+        const float* b = base + nz * PP - ny * PX - xr;
+        row_win_dispatch<B, true>(xr, acc, a, b, wc + wo);
+      }
+    }
+    if (++cnt == 4) {                                  // float32 groups of 4 rows, float64 total
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        tot[b] += (double)acc[b];
+        acc[b] = 0.f;
+      }
+      cnt = 0;
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < B; ++b) tot[b] += (double)acc[b];
+  __syncthreads();                                     // window no longer needed
+  double* red = reinterpret_cast<double*>(lds4);
+#pragma unroll
+  for (int b = 0; b < B; ++b) red[((size_t)wave * kWave + lane) * B + b] = tot[b];
+  __syncthreads();
+  if (wave == 0 && active) {
+    const int y = y0 + yi, z = z0 + zi;
+    if (y < NY && z < NZ) {
+      float* out = ucut + Lv.off + ((size_t)z * NY + y) * NX;
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        double v = 0.0;
+        for (int w = 0; w < kLatWaves; ++w) v += red[((size_t)w * kWave + lane) * B + b];
+        const int x = x0 + xi * B + b;
+        if (x < NX) out[x] = (float)ldexp(v, -T.level);
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
 // Top level (itemised algorithm), float64: u^{l-1}_mu = sum over every node nu
 // of g^{l-1}(2^{l-1} h |mu - nu|) q^{l-1}_nu, from a table T[|dx|][|dy|][|dz|].
 // --------------------------------------------------------------------------
+// One wave per output node: lanes stride over the input nodes, then a fixed
+// butterfly sums the 64 lane partials.
 __global__ void __launch_bounds__(kBlock) k_top(Geom g, const double* __restrict__ T,
                                                 const float* __restrict__ qgrid,
                                                 float* __restrict__ ucut, float* __restrict__ u) {
   const Level L = g.lv[g.levels - 1];
-  int node = blockIdx.x * blockDim.x + threadIdx.x;
+  const int node = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  const int lane = threadIdx.x & (kWave - 1);
   if (node >= L.count) return;
-  int mx = node % L.n[0], my = (node / L.n[0]) % L.n[1], mz = node / (L.n[0] * L.n[1]);
+  const int mx = node % L.n[0], my = (node / L.n[0]) % L.n[1], mz = node / (L.n[0] * L.n[1]);
   const float* qt = qgrid + L.off;
   double acc = 0.0;
-  for (int vz = 0; vz < L.n[2]; ++vz) {
-    int dz = abs(mz - vz);
-    for (int vy = 0; vy < L.n[1]; ++vy) {
-      int dy = abs(my - vy);
-      const double* trow = T + ((size_t)dz * L.n[1] + dy) * L.n[0];
-      const float* qrow = qt + ((size_t)vz * L.n[1] + vy) * L.n[0];
-      for (int vx = 0; vx < L.n[0]; ++vx) acc = fma(trow[abs(mx - vx)], (double)qrow[vx], acc);
-    }
+  for (int v = lane; v < L.count; v += kWave) {
+    const int vx = v % L.n[0], vy = (v / L.n[0]) % L.n[1], vz = v / (L.n[0] * L.n[1]);
+    const double t = T[((size_t)abs(mz - vz) * L.n[1] + abs(my - vy)) * L.n[0] + abs(mx - vx)];
+    acc = fma(t, (double)qt[v], acc);
   }
-  ucut[L.off + node] = (float)acc;
-  u[L.off + node] = (float)acc;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) {
+    ucut[L.off + node] = (float)acc;
+    u[L.off + node] = (float)acc;
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -454,42 +771,83 @@ __global__ void __launch_bounds__(kBlock) k_top(Geom g, const double* __restrict
 //   u^k_mu = u^{k,cut}_mu + sum_nu Phi(mu/2 - nu)^3 u^{k+1}_nu, |mu - 2 nu| <= order - 1.
 // pw[j + order - 1] = Phi(j/2).
 // --------------------------------------------------------------------------
-struct ProlongW {
-  float w[11];
-};
+// One block = 8 x 8 x 4 fine nodes; the coarse nodes they read are staged in LDS.
+// Per dimension, an even fine index m reads only nu = m/2 (weight Phi(0) = 1);
+// an odd one reads the ORDER coarse nodes nu = (m - R)/2 + i.
+constexpr int kPX = 8, kPY = 8, kPZ = 4;
 
-__global__ void __launch_bounds__(kBlock) k_prolong(Geom g, int k, ProlongW pw,
-                                                    const float* __restrict__ ucut,
+template <int ORDER>
+__global__ void __launch_bounds__(kBlock) k_prolong(Geom g, int k, const float* __restrict__ ucut,
                                                     float* __restrict__ u) {
+  using D = Dyadic<ORDER>;
+  constexpr int R = D::R;
+  constexpr int VX = (kPX - 1 + 2 * R) / 2 + 2, VY = (kPY - 1 + 2 * R) / 2 + 2, VZ = (kPZ - 1 + 2 * R) / 2 + 2;
+  __shared__ float cs[VX * VY * VZ];
   const Level F = g.lv[k], C = g.lv[k + 1];
-  int node = blockIdx.x * blockDim.x + threadIdx.x;
-  if (node >= F.count) return;
-  int m[3] = {node % F.n[0] + F.lo[0], (node / F.n[0]) % F.n[1] + F.lo[1],
-              node / (F.n[0] * F.n[1]) + F.lo[2]};
-  const int R = g.order - 1;
-  int v0[3], v1[3];
+  const int ntx = (F.n[0] + kPX - 1) / kPX, nty = (F.n[1] + kPY - 1) / kPY;
+  const int bx = blockIdx.x % ntx, by = (blockIdx.x / ntx) % nty, bz = blockIdx.x / (ntx * nty);
+  // absolute fine origin of the tile; coarse origin = ceil((m0 - R) / 2)
+  const int m0[3] = {F.lo[0] + bx * kPX, F.lo[1] + by * kPY, F.lo[2] + bz * kPZ};
+  int v0[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    // nu with |m - 2 nu| <= R  ->  nu in [ceil((m - R)/2), floor((m + R)/2)]
-    int lo = m[d] - R, hi = m[d] + R;
-    int a = (lo >= 0) ? (lo + 1) / 2 : -((-lo) / 2);
-    int b = (hi >= 0) ? hi / 2 : -((-hi + 1) / 2);
-    v0[d] = max(a, C.lo[d]);
-    v1[d] = min(b, C.lo[d] + C.n[d] - 1);
+    const int lo = m0[d] - R;
+    v0[d] = (lo >= 0) ? (lo + 1) / 2 : -((-lo) / 2);
   }
   const float* uc = u + C.off;
-  float acc = 0.f;
-  for (int vz = v0[2]; vz <= v1[2]; ++vz) {
-    float wz = pw.w[m[2] - 2 * vz + R];
-    for (int vy = v0[1]; vy <= v1[1]; ++vy) {
-      float wyz = wz * pw.w[m[1] - 2 * vy + R];
-      const float* rowp = uc + ((size_t)(vz - C.lo[2]) * C.n[1] + (vy - C.lo[1])) * C.n[0] - C.lo[0];
-      float racc = 0.f;
-      for (int vx = v0[0]; vx <= v1[0]; ++vx) racc = fmaf(pw.w[m[0] - 2 * vx + R], rowp[vx], racc);
-      acc = fmaf(wyz, racc, acc);
+  const int tx = threadIdx.x % kPX, ty = (threadIdx.x / kPX) % kPY, tz = threadIdx.x / (kPX * kPY);
+  const int fx = bx * kPX + tx, fy = by * kPY + ty, fz = bz * kPZ + tz;      // level-local
+  const bool inside = tz < kPZ && fx < F.n[0] && fy < F.n[1] && fz < F.n[2];
+  const size_t o = F.off + ((size_t)fz * F.n[1] + fy) * F.n[0] + fx;
+  const float own = inside ? ucut[o] : 0.f;                                  // in flight with the staging
+  constexpr int ncs = VX * VY * VZ;
+  float v[(ncs + kBlock - 1) / kBlock];
+#pragma unroll
+  for (int t = 0; t < (ncs + kBlock - 1) / kBlock; ++t) {
+    const int i = threadIdx.x + t * kBlock;
+    v[t] = 0.f;
+    if (i < ncs) {
+      const int lx = i % VX, ly = (i / VX) % VY, lz = i / (VX * VY);
+      const int cx = v0[0] + lx - C.lo[0], cy = v0[1] + ly - C.lo[1], cz = v0[2] + lz - C.lo[2];
+      if (cx >= 0 && cx < C.n[0] && cy >= 0 && cy < C.n[1] && cz >= 0 && cz < C.n[2])
+        v[t] = uc[((size_t)cz * C.n[1] + cy) * C.n[0] + cx];
     }
   }
-  u[F.off + node] = ucut[F.off + node] + acc;
+#pragma unroll
+  for (int t = 0; t < (ncs + kBlock - 1) / kBlock; ++t) {
+    const int i = threadIdx.x + t * kBlock;
+    if (i < ncs) cs[i] = v[t];
+  }
+  __syncthreads();
+  if (!inside) return;
+  const int m[3] = {m0[0] + tx, m0[1] + ty, m0[2] + tz};
+  // per dimension: first local coarse index, and odd/even
+  int b0[3];
+  bool odd[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    odd[d] = (m[d] & 1) != 0;
+    const int first = odd[d] ? (m[d] - R) / 2 : (m[d] >= 0 ? m[d] / 2 : -((-m[d]) / 2));
+    b0[d] = first - v0[d];
+  }
+  float wx[ORDER], wy[ORDER], wz[ORDER];
+#pragma unroll
+  for (int i = 0; i < ORDER; ++i) {
+    wx[i] = odd[0] ? D::wodd(i) : (i == 0 ? 1.f : 0.f);
+    wy[i] = odd[1] ? D::wodd(i) : (i == 0 ? 1.f : 0.f);
+    wz[i] = odd[2] ? D::wodd(i) : (i == 0 ? 1.f : 0.f);
+  }
+  const int nx_ = odd[0] ? ORDER : 1, ny_ = odd[1] ? ORDER : 1, nz_ = odd[2] ? ORDER : 1;
+  float acc = 0.f;
+  for (int c = 0; c < nz_; ++c) {
+    for (int b = 0; b < ny_; ++b) {
+      const float* rowp = cs + ((b0[2] + c) * VY + (b0[1] + b)) * VX + b0[0];
+      float racc = 0.f;
+      for (int a = 0; a < nx_; ++a) racc = fmaf(wx[a], rowp[a], racc);
+      acc = fmaf(wz[c] * wy[b], racc, acc);
+    }
+  }
+  u[o] = own + acc;
 }
 
 // --------------------------------------------------------------------------
@@ -598,28 +956,40 @@ __global__ void __launch_bounds__(kBlock) k_interp(Geom g, const float4* __restr
   }
 }
 
-// Sum the per-block partials in a fixed order (one block).
+// Sum the per-block partials in a fixed order (one block): each thread adds
+// its strided share, then a butterfly per wave and the 4 waves in order.
 __global__ void __launch_bounds__(kBlock) k_reduce(const double* __restrict__ partials, int n_partials,
                                                    double* __restrict__ energy,
                                                    double* __restrict__ virial) {
-  __shared__ double red[kBlock];
+  __shared__ double red[10][kBlock / kWave];
+  double acc[10];
+#pragma unroll
+  for (int t = 0; t < 10; ++t) acc[t] = 0.0;
+  for (int b = threadIdx.x; b < n_partials; b += kBlock) {
+    double v[10];
+#pragma unroll
+    for (int t = 0; t < 10; ++t) v[t] = partials[(size_t)t * n_partials + b];
+#pragma unroll
+    for (int t = 0; t < 10; ++t) acc[t] += v[t];
+  }
+#pragma unroll
   for (int t = 0; t < 10; ++t) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc[t] += __shfl_xor(acc[t], off);
+  }
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  if (lane == 0)
+#pragma unroll
+    for (int t = 0; t < 10; ++t) red[t][wave] = acc[t];
+  __syncthreads();
+  if (threadIdx.x < 10) {
     double v = 0.0;
-    for (int b = threadIdx.x; b < n_partials; b += kBlock) v += partials[(size_t)t * n_partials + b];
-    red[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = kBlock / 2; off >= 1; off >>= 1) {
-      if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-      __syncthreads();
-    }
+    for (int w = 0; w < kBlock / kWave; ++w) v += red[threadIdx.x][w];
     if (threadIdx.x == 0) {
-      if (t == 0) {
-        if (energy) energy[0] = red[0];
-      } else if (virial) {
-        virial[t - 1] = red[0];
-      }
+      if (energy) energy[0] = v;
+    } else if (virial) {
+      virial[threadIdx.x - 1] = v;
     }
-    __syncthreads();
   }
 }
 
@@ -629,74 +999,116 @@ inline int blocks_for(int n, int b = kBlock) { return (n + b - 1) / b; }
 
 int interp_partials(const Geom& g) { return std::max(1, blocks_for(g.n_atoms)); }
 
-hipError_t launch_forward(const Geom& g, const DevPtrs& d, int n_rows, int n_partials,
-                          const int* restrict_j, const float* restrict_w, int n_restrict,
-                          const float* prolong_w, hipStream_t s, const float* x, const float* y,
+hipError_t launch_init(const Geom& g, const DevPtrs& d, hipStream_t s) {
+  k_zero_counts<<<blocks_for(g.n_cells + 1), kBlock, 0, s>>>(d.counts, g.n_cells + 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward(const Geom& g, const DevPtrs& d, int n_rows, const LatLaunch& lat,
+                          int n_partials, hipStream_t s, const float* x, const float* y,
                           const float* z, const float* q, float* fx, float* fy, float* fz,
-                          float* phi, double* energy, double* virial, hipEvent_t* ev) {
+                          float* phi, double* energy, double* virial, hipEvent_t* ev,
+                          hipStream_t aux, hipEvent_t fork, hipEvent_t join) {
   const int n = g.n_atoms;
   auto mark = [&](int stage) {
     if (ev) (void)hipEventRecord(ev[stage], s);
   };
   mark(kStageBin);
-  k_zero<<<blocks_for(std::max(g.n_cells + 1, 64)), kBlock, 0, s>>>(d.counts, d.cursor, g.n_cells,
-                                                                   d.status);
   if (n > 0) {
-    k_bin_count<<<blocks_for(n), kBlock, 0, s>>>(g, x, y, z, q, d.counts, d.cell_of, d.status);
-    k_scan<<<1, 1024, 0, s>>>(d.counts, d.cell_start, g.n_cells);
-    k_bin_scatter<<<blocks_for(n), kBlock, 0, s>>>(g, d.cell_of, d.cell_start, d.cursor, d.tmp);
-    k_bin_place<<<blocks_for(n), kBlock, 0, s>>>(g, x, y, z, q, d.cell_of, d.cell_start, d.tmp,
+    k_bin_count<<<blocks_for(n), kBlock, 0, s>>>(g, x, y, z, d.counts, d.cell_of);
+    k_scan<<<1, 1024, 0, s>>>(d.counts, d.cell_start, d.cursor, d.status, g.n_cells);
+    // the scatter's coordinate copies live in the short-range output buffer
+    // until k_bin_place has consumed them
+    k_bin_scatter<<<blocks_for(n), kBlock, 0, s>>>(g, x, y, z, q, d.cell_of, d.cell_start, d.cursor,
+                                                   d.tmp, d.fshort);
+    k_bin_place<<<blocks_for(n), kBlock, 0, s>>>(g, d.cell_of, d.cell_start, d.tmp, d.fshort,
                                                  d.sorted, d.perm, d.status);
     mark(kStageShort);
+    const bool par = (aux != nullptr && ev == nullptr);
+    hipStream_t ss = s;
+    if (par) {
+      (void)hipEventRecord(fork, s);
+      (void)hipStreamWaitEvent(aux, fork, 0);
+      ss = aux;
+    }
     int items = g.runs_x * g.nc[1] * g.nc[2];
     if (g.m == 1)
-      k_short<1><<<items, kBlock, 0, s>>>(g, d.sorted, d.cell_start, d.fshort);
+      k_short<1><<<items, kBlock, 0, ss>>>(g, d.sorted, d.cell_start, d.fshort);
     else if (g.m == 2)
-      k_short<2><<<items, kBlock, 0, s>>>(g, d.sorted, d.cell_start, d.fshort);
+      k_short<2><<<items, kBlock, 0, ss>>>(g, d.sorted, d.cell_start, d.fshort);
     else if (g.m == 3)
-      k_short<3><<<items, kBlock, 0, s>>>(g, d.sorted, d.cell_start, d.fshort);
+      k_short<3><<<items, kBlock, 0, ss>>>(g, d.sorted, d.cell_start, d.fshort);
     else if (g.m == 4)
-      k_short<4><<<items, kBlock, 0, s>>>(g, d.sorted, d.cell_start, d.fshort);
+      k_short<4><<<items, kBlock, 0, ss>>>(g, d.sorted, d.cell_start, d.fshort);
     else if (g.m == 5)
-      k_short<5><<<items, kBlock, 0, s>>>(g, d.sorted, d.cell_start, d.fshort);
+      k_short<5><<<items, kBlock, 0, ss>>>(g, d.sorted, d.cell_start, d.fshort);
     else if (g.m == 6)
-      k_short<6><<<items, kBlock, 0, s>>>(g, d.sorted, d.cell_start, d.fshort);
+      k_short<6><<<items, kBlock, 0, ss>>>(g, d.sorted, d.cell_start, d.fshort);
     else
-      k_short<7><<<items, kBlock, 0, s>>>(g, d.sorted, d.cell_start, d.fshort);
+      k_short<7><<<items, kBlock, 0, ss>>>(g, d.sorted, d.cell_start, d.fshort);
+    if (par) (void)hipEventRecord(join, aux);
   } else {
-    k_scan<<<1, 1024, 0, s>>>(d.counts, d.cell_start, g.n_cells);
+    k_scan<<<1, 1024, 0, s>>>(d.counts, d.cell_start, d.cursor, d.status, g.n_cells);
     mark(kStageShort);
   }
   mark(kStageAnterp);
   const Level& L0 = g.lv[0];
+  const int ant_blocks = ((L0.n[0] + kAX - 1) / kAX) * ((L0.n[1] + kAY - 1) / kAY) *
+                         ((L0.n[2] + kAZ - 1) / kAZ);
   if (g.order == 4)
-    k_anterp<4><<<blocks_for(L0.count), kBlock, 0, s>>>(g, d.sorted, d.cell_start, d.qgrid);
+    k_anterp<4><<<ant_blocks, kBlock, 0, s>>>(g, d.sorted, d.cell_start, d.qgrid);
   else
-    k_anterp<6><<<blocks_for(L0.count), kBlock, 0, s>>>(g, d.sorted, d.cell_start, d.qgrid);
+    k_anterp<6><<<ant_blocks, kBlock, 0, s>>>(g, d.sorted, d.cell_start, d.qgrid);
   mark(kStageRestrict);
-  RestrictTaps rt{};
-  rt.n = n_restrict;
-  for (int t = 0; t < n_restrict; ++t) {
-    rt.j[t] = restrict_j[t];
-    rt.w[t] = restrict_w[t];
+  for (int k = 0; k + 1 < g.levels; ++k) {
+    const Level& C = g.lv[k + 1];
+    const int nb = ((C.n[0] + kRX - 1) / kRX) * ((C.n[1] + kRY - 1) / kRY) * ((C.n[2] + kRZ - 1) / kRZ);
+    if (g.order == 4)
+      k_restrict<4><<<nb, kBlock, 0, s>>>(g, k, d.qgrid);
+    else
+      k_restrict<6><<<nb, kBlock, 0, s>>>(g, k, d.qgrid);
   }
-  for (int k = 0; k + 1 < g.levels; ++k)
-    k_restrict<<<blocks_for(g.lv[k + 1].count), kBlock, 0, s>>>(g, k, rt, d.qgrid);
   mark(kStageLattice);
   if (g.levels > 1) {
-    int n_lat = g.lv[g.levels - 1].off;   // every node below the top level
-    k_lattice<<<blocks_for(n_lat), kBlock, 0, s>>>(g, d.rows, n_rows, d.weights, d.qgrid, d.ucut,
-                                                   n_lat);
+    if (lat.b > 0) {
+      const int nblk = lat.t[lat.n - 1].block0 + lat.t[lat.n - 1].ntx * lat.t[lat.n - 1].nty *
+                                                     lat.t[lat.n - 1].ntz;
+      if (lat.b == 4) {
+        (void)hipFuncSetAttribute((const void*)k_lattice_win<4>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lat.lds_bytes);
+        k_lattice_win<4><<<nblk, kLatThreads, lat.lds_bytes, s>>>(g, lat, d.rows_c, d.weights_c,
+                                                                 d.qgrid, d.ucut);
+      } else if (lat.b == 6) {
+        (void)hipFuncSetAttribute((const void*)k_lattice_win<6>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lat.lds_bytes);
+        k_lattice_win<6><<<nblk, kLatThreads, lat.lds_bytes, s>>>(g, lat, d.rows_c, d.weights_c,
+                                                                 d.qgrid, d.ucut);
+      } else {
+        (void)hipFuncSetAttribute((const void*)k_lattice_win<8>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lat.lds_bytes);
+        k_lattice_win<8><<<nblk, kLatThreads, lat.lds_bytes, s>>>(g, lat, d.rows_c, d.weights_c,
+                                                                 d.qgrid, d.ucut);
+      }
+    } else {
+      int n_lat = g.lv[g.levels - 1].off;   // every node below the top level
+      k_lattice<<<blocks_for(n_lat), kBlock, 0, s>>>(g, d.rows, n_rows, d.weights, d.qgrid, d.ucut,
+                                                     n_lat);
+    }
   }
   mark(kStageTop);
-  k_top<<<blocks_for(g.lv[g.levels - 1].count), kBlock, 0, s>>>(g, d.top, d.qgrid, d.ucut, d.u);
+  k_top<<<blocks_for(g.lv[g.levels - 1].count * kWave), kBlock, 0, s>>>(g, d.top, d.qgrid, d.ucut, d.u);
   mark(kStageProlong);
-  ProlongW pw{};
-  for (int t = 0; t < 2 * g.order - 1; ++t) pw.w[t] = prolong_w[t];
-  for (int k = g.levels - 2; k >= 0; --k)
-    k_prolong<<<blocks_for(g.lv[k].count), kBlock, 0, s>>>(g, k, pw, d.ucut, d.u);
+  for (int k = g.levels - 2; k >= 0; --k) {
+    const Level& F = g.lv[k];
+    const int nb = ((F.n[0] + kPX - 1) / kPX) * ((F.n[1] + kPY - 1) / kPY) * ((F.n[2] + kPZ - 1) / kPZ);
+    if (g.order == 4)
+      k_prolong<4><<<nb, kBlock, 0, s>>>(g, k, d.ucut, d.u);
+    else
+      k_prolong<6><<<nb, kBlock, 0, s>>>(g, k, d.ucut, d.u);
+  }
   mark(kStageInterp);
   if (n > 0) {
+    if (aux != nullptr && ev == nullptr) (void)hipStreamWaitEvent(s, join, 0);
     if (g.order == 4)
       k_interp<4><<<blocks_for(n), kBlock, 0, s>>>(g, d.sorted, d.perm, d.fshort, d.u, fx, fy, fz,
                                                    phi, d.partials, n_partials);

@@ -20,7 +20,8 @@ ERR_WORKSPACE, ERR_HIP, ERR_UNSUPPORTED, ERR_COINCIDENT = -4, -5, -6, -7
 SECTION_QGRID, SECTION_UCUT, SECTION_U, SECTION_SORTED, SECTION_PERM, SECTION_SHORT = range(6)
 
 # every entry point include/msm.h declares
-EXPORTS = ("msm_plan_create", "msm_plan_destroy", "msm_plan_info", "msm_workspace_bytes",
+EXPORTS = ("msm_plan_create", "msm_plan_destroy", "msm_plan_info", "msm_plan_describe",
+           "msm_workspace_bytes",
            "msm_workspace_init", "msm_compute", "msm_status_query", "msm_workspace_section",
            "msm_profile_enable", "msm_profile_read", "msm_graph_capture", "msm_graph_launch",
            "msm_graph_destroy", "msm_status_string", "msm_last_error")
@@ -57,6 +58,7 @@ def lib():
         L.msm_plan_create.argtypes = [ctypes.POINTER(Params), i32, ctypes.POINTER(vp)]
         L.msm_plan_destroy.argtypes = [vp]
         L.msm_plan_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.msm_plan_describe.argtypes = [vp, ctypes.c_char_p, sz]
         L.msm_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
         L.msm_workspace_init.argtypes = [vp, vp, sz, vp]
         L.msm_compute.argtypes = [vp, vp, sz, vp] + [vp] * 10
@@ -131,6 +133,13 @@ class Plan:
         _check(lib().msm_plan_info(self._h, ctypes.byref(lv), lo, n))
         L = lv.value
         return L, [tuple(lo[3 * k:3 * k + 3]) for k in range(L)], [tuple(n[3 * k:3 * k + 3]) for k in range(L)]
+
+    def describe(self):
+        """The plan's decomposition (cells, tiles, ...) as a dict."""
+        import json
+        buf = ctypes.create_string_buffer(4096)
+        _check(lib().msm_plan_describe(self._h, buf, 4096))
+        return json.loads(buf.value.decode())
 
     def compute(self, x, y, z, q, *, forces=True, potentials=True, virial=False, out=None):
         """Energy (float64 [1]), forces [3, N] and potentials [N] on the device."""
