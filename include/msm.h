@@ -114,6 +114,28 @@ msm_status msm_compute(const msm_plan* plan, void* ws, size_t ws_bytes, msm_stre
                        float* fx, float* fy, float* fz, float* phi, double* energy,
                        double* virial);
 
+/* Energy only: E as msm_compute would return it, evaluated through the grid
+ * form 1/2 sum_k <q^k, u^{k,cut}> of the long-range part (no prolongation,
+ * interpolation or short-range forces).  energy: device float64 [1].
+ * Nothing but the workspace is written; grid potentials are not kept for a
+ * later backward pass (msm_backward recomputes them). */
+msm_status msm_energy(const msm_plan* plan, void* ws, size_t ws_bytes, msm_stream_t stream,
+                      const float* x, const float* y, const float* z, const float* q,
+                      double* energy);
+
+/* Backward pass of the energy: with g = *grad_energy (device float64 scalar,
+ * read on the device, so no host synchronisation),
+ *   dedx, dedy, dedz (device float32 [n], nullable all three) = g dE/dr_i = -g F_i
+ *   dedq            (device float32 [n], nullable)            = g dE/dq_i =  g phi_i.
+ * The grid chain is recomputed from x, y, z, q; interpolation is run in
+ * gradient mode (it is the adjoint of anterpolation), and the short-range
+ * pair terms supply their part.  E is a quadratic form in q with a symmetric
+ * kernel, so phi_i is exactly dE/dq_i and F_i exactly -dE/dr_i. */
+msm_status msm_backward(const msm_plan* plan, void* ws, size_t ws_bytes, msm_stream_t stream,
+                        const float* x, const float* y, const float* z, const float* q,
+                        const double* grad_energy, float* dedx, float* dedy, float* dedz,
+                        float* dedq);
+
 /* Synchronise `stream` and return the data-error status recorded by the last
  * evaluation on this workspace (MSM_OK, MSM_ERR_OUT_OF_BOX, MSM_ERR_NONFINITE
  * or MSM_ERR_COINCIDENT).  *device_flags (nullable) receives the raw bit set. */

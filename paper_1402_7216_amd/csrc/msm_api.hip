@@ -657,11 +657,49 @@ msm_status msm_compute(const msm_plan* P, void* ws, size_t ws_bytes, msm_stream_
   msm_plan* M = const_cast<msm_plan*>(P);
   hipError_t e = ensure_aux(M);
   if (e != hipSuccess) return hip_fail(e, "create auxiliary stream");
-  e = msm::launch_forward(P->g, d, (int)P->rows.size(), P->lat, P->n_partials,
-                          reinterpret_cast<hipStream_t>(stream), x, y, z, q, fx, fy, fz, phi, energy,
-                          virial, P->profile ? M->ev : nullptr, M->aux, M->fork, M->join);
+  e = msm::launch_eval(msm::kModeForces, P->g, d, (int)P->rows.size(), P->lat, P->n_partials,
+                       reinterpret_cast<hipStream_t>(stream), x, y, z, q, fx, fy, fz, phi, energy,
+                       virial, nullptr, P->profile ? M->ev : nullptr, M->aux, M->fork, M->join);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return MSM_OK;
+}
+
+static msm_status eval_mode(int mode, const msm_plan* P, void* ws, size_t ws_bytes,
+                            msm_stream_t stream, const float* x, const float* y, const float* z,
+                            const float* q, float* fx, float* fy, float* fz, float* phi,
+                            double* energy, const double* gscale) {
+  if (!P) return fail(MSM_ERR_INVALID_ARG, "null plan");
+  if (!ws || ws_bytes < P->lay.total) return fail(MSM_ERR_WORKSPACE, "workspace missing or too small");
+  if (P->g.n_atoms > 0 && (!x || !y || !z || !q))
+    return fail(MSM_ERR_INVALID_ARG, "null position or charge array");
+  if (!((fx && fy && fz) || (!fx && !fy && !fz)))
+    return fail(MSM_ERR_INVALID_ARG, "gradient outputs must be all set or all null");
+  msm::DevPtrs d = dev_ptrs(P, ws);
+  msm_plan* M = const_cast<msm_plan*>(P);
+  hipError_t e = ensure_aux(M);
+  if (e != hipSuccess) return hip_fail(e, "create auxiliary stream");
+  e = msm::launch_eval(mode, P->g, d, (int)P->rows.size(), P->lat, P->n_partials,
+                       reinterpret_cast<hipStream_t>(stream), x, y, z, q, fx, fy, fz, phi, energy,
+                       nullptr, gscale, nullptr, M->aux, M->fork, M->join);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return MSM_OK;
+}
+
+msm_status msm_energy(const msm_plan* P, void* ws, size_t ws_bytes, msm_stream_t stream,
+                      const float* x, const float* y, const float* z, const float* q,
+                      double* energy) {
+  if (!energy) return fail(MSM_ERR_INVALID_ARG, "null energy output");
+  return eval_mode(msm::kModeEnergy, P, ws, ws_bytes, stream, x, y, z, q, nullptr, nullptr, nullptr,
+                   nullptr, energy, nullptr);
+}
+
+msm_status msm_backward(const msm_plan* P, void* ws, size_t ws_bytes, msm_stream_t stream,
+                        const float* x, const float* y, const float* z, const float* q,
+                        const double* grad_energy, float* dedx, float* dedy, float* dedz,
+                        float* dedq) {
+  if (!grad_energy) return fail(MSM_ERR_INVALID_ARG, "null grad_energy");
+  return eval_mode(msm::kModeGradient, P, ws, ws_bytes, stream, x, y, z, q, dedx, dedy, dedz, dedq,
+                   nullptr, grad_energy);
 }
 
 struct msm_graph {
@@ -702,8 +740,9 @@ msm_status msm_graph_capture(const msm_plan* P, void* ws, size_t ws_bytes, const
   if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     msm::DevPtrs d = dev_ptrs(P, ws);
-    hipError_t le = msm::launch_forward(P->g, d, (int)P->rows.size(), P->lat, P->n_partials, cs, x, y, z, q, fx, fy, fz, phi, energy, virial, nullptr,
-                                        M->aux, M->fork, M->join);
+    hipError_t le = msm::launch_eval(msm::kModeForces, P->g, d, (int)P->rows.size(), P->lat,
+                                     P->n_partials, cs, x, y, z, q, fx, fy, fz, phi, energy, virial,
+                                     nullptr, nullptr, M->aux, M->fork, M->join);
     e = hipStreamEndCapture(cs, &G->graph);
     if (le != hipSuccess) e = le;
   }

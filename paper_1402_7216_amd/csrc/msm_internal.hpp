@@ -139,15 +139,23 @@ enum Stage : int {
   kStageProlong, kStageInterp, kStageReduce, kStageCount
 };
 
-// Launchers (msm_kernels.hip).  All enqueue on `s` and return the first HIP error.
+// What one evaluation produces.
+enum Mode : int {
+  kModeForces = 0,     // forces, potentials, energy, virial
+  kModeEnergy = 1,     // energy only (grid form; no prolongation or interpolation)
+  kModeGradient = 2    // gscale * dE/dr into fx..fz, gscale * dE/dq into phi
+};
+
+// Launcher (msm_kernels.hip).  Enqueues one evaluation on `s` and returns the
+// first HIP error.
 // ev (nullable): kStageCount + 1 events recorded at the stage boundaries.
 // aux/fork/join (nullable): run the short-range pass on `aux`, concurrently
-// with the grid chain, joined back before interpolation.
-hipError_t launch_forward(const Geom& g, const DevPtrs& d, int n_rows, const LatLaunch& lat,
-                          int n_partials, hipStream_t s, const float* x, const float* y,
-                          const float* z, const float* q, float* fx, float* fy, float* fz,
-                          float* phi, double* energy, double* virial, hipEvent_t* ev,
-                          hipStream_t aux, hipEvent_t fork, hipEvent_t join);
+// with the grid chain, joined back before it is needed.
+hipError_t launch_eval(int mode, const Geom& g, const DevPtrs& d, int n_rows, const LatLaunch& lat,
+                       int n_partials, hipStream_t s, const float* x, const float* y,
+                       const float* z, const float* q, float* fx, float* fy, float* fz,
+                       float* phi, double* energy, double* virial, const double* gscale,
+                       hipEvent_t* ev, hipStream_t aux, hipEvent_t fork, hipEvent_t join);
 
 int interp_partials(const Geom& g);
 

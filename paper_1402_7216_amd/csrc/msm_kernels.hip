@@ -245,7 +245,7 @@ __global__ void k_bin_place(Geom g, const int* __restrict__ cell_of, const int* 
 // split over the 4 waves of the block and the partial sums added in a fixed
 // order through LDS.
 // --------------------------------------------------------------------------
-template <int M>
+template <int M, bool FORCES>
 __global__ void __launch_bounds__(kBlock) k_short(Geom g, const float4* __restrict__ sorted,
                                                   const int* __restrict__ start,
                                                   float4* __restrict__ fshort) {
@@ -298,12 +298,14 @@ __global__ void __launch_bounds__(kBlock) k_short(Geom g, const float4* __restri
 #pragma unroll
             for (int k = M - 1; k >= 1; --k) dg = fmaf(dg, s, g.dcoef[k]);
             const float gs = ri - gm;                    // g*(r)
-            const float fr = fmaf(ri, ri2, dg);          // -g*'(r)/r
             ap = fmaf(pj.w, gs, ap);
-            const float wq = pj.w * fr;
-            ax = fmaf(wq, dx, ax);
-            ay = fmaf(wq, dy, ay);
-            az = fmaf(wq, dz, az);
+            if (FORCES) {
+              const float fr = fmaf(ri, ri2, dg);        // -g*'(r)/r
+              const float wq = pj.w * fr;
+              ax = fmaf(wq, dx, ax);
+              ay = fmaf(wq, dy, ay);
+              az = fmaf(wq, dz, az);
+            }
           }
         }
       }
@@ -856,14 +858,18 @@ __global__ void __launch_bounds__(kBlock) k_prolong(Geom g, int k, const float* 
 //   phi_i = ke (phi^s + phi^L - q_i gamma(0)/a),  F_i = ke (F^s - q_i grad phi^L).
 // Per-block float64 partials of E = 1/2 sum q_i phi_i and W = sum (r_i - lo) F_i.
 // --------------------------------------------------------------------------
-template <int ORDER>
+// MODE 0: forces and potentials, plus per-block energy/virial partials.
+// MODE 1: gradients of the energy scaled by *gscale: fx..fz receive
+//         gscale dE/dr = -gscale F, phi receives gscale dE/dq = gscale phi.
+template <int ORDER, int MODE>
 __global__ void __launch_bounds__(kBlock) k_interp(Geom g, const float4* __restrict__ sorted,
                                                    const int* __restrict__ perm,
                                                    const float4* __restrict__ fshort,
                                                    const float* __restrict__ u,
                                                    float* __restrict__ fx, float* __restrict__ fy,
                                                    float* __restrict__ fz, float* __restrict__ phi,
-                                                   double* __restrict__ partials, int n_partials) {
+                                                   double* __restrict__ partials, int n_partials,
+                                                   const double* __restrict__ gscale) {
   constexpr int H = ORDER / 2;
   __shared__ double red[10][kBlock / kWave];
   const Level L = g.lv[0];
@@ -914,6 +920,17 @@ __global__ void __launch_bounds__(kBlock) k_interp(Geom g, const float4* __restr
     float4 fs = fshort[s];
     double qd = (double)p.w;
     double ph = g.ke * ((double)fs.w + (double)pl - qd * (double)g.self);
+    if (MODE == 1) {
+      const double gsc = *gscale;
+      const int i = perm[s];
+      if (fx) {
+        fx[i] = (float)(-gsc * g.ke * ((double)fs.x - qd * (double)gx));
+        fy[i] = (float)(-gsc * g.ke * ((double)fs.y - qd * (double)gy));
+        fz[i] = (float)(-gsc * g.ke * ((double)fs.z - qd * (double)gz));
+      }
+      if (phi) phi[i] = (float)(gsc * ph);
+      return;
+    }
     float ofx = (float)(g.ke * ((double)fs.x - qd * (double)gx));
     float ofy = (float)(g.ke * ((double)fs.y - qd * (double)gy));
     float ofz = (float)(g.ke * ((double)fs.z - qd * (double)gz));
@@ -953,6 +970,37 @@ __global__ void __launch_bounds__(kBlock) k_interp(Geom g, const float4* __restr
     double v = 0.0;
     for (int w = 0; w < kBlock / kWave; ++w) v += red[threadIdx.x][w];
     partials[(size_t)threadIdx.x * n_partials + blockIdx.x] = v;
+  }
+}
+
+// Energy without prolongation or interpolation (grid form):
+//   E = 1/2 sum_i q_i phi_i^s + 1/2 sum_k <q^k, u^{k,cut}> - gamma(0)/(2a) sum_i q_i^2,
+// since 1/2 q^0.u^0 = 1/2 sum_k <q^k, u^{k,cut}> when prolongation is the
+// transpose of restriction.  One float64 partial per block.
+__global__ void __launch_bounds__(kBlock) k_energy_terms(Geom g, const float4* __restrict__ sorted,
+                                                         const float4* __restrict__ fshort,
+                                                         const float* __restrict__ qgrid,
+                                                         const float* __restrict__ ucut,
+                                                         double* __restrict__ partials) {
+  __shared__ double red[kBlock / kWave];
+  const int stride = gridDim.x * blockDim.x;
+  double e = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g.n_atoms; i += stride) {
+    const double q = (double)sorted[i].w;
+    e += 0.5 * q * ((double)fshort[i].w - q * (double)g.self);
+  }
+  for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < g.total_nodes; m += stride)
+    e += 0.5 * (double)qgrid[m] * (double)ucut[m];
+  e *= g.ke;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) e += __shfl_xor(e, off);
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  if (lane == 0) red[wave] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double v = 0.0;
+    for (int w = 0; w < kBlock / kWave; ++w) v += red[w];
+    partials[blockIdx.x] = v;
   }
 }
 
@@ -1004,16 +1052,18 @@ hipError_t launch_init(const Geom& g, const DevPtrs& d, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_forward(const Geom& g, const DevPtrs& d, int n_rows, const LatLaunch& lat,
-                          int n_partials, hipStream_t s, const float* x, const float* y,
-                          const float* z, const float* q, float* fx, float* fy, float* fz,
-                          float* phi, double* energy, double* virial, hipEvent_t* ev,
-                          hipStream_t aux, hipEvent_t fork, hipEvent_t join) {
+hipError_t launch_eval(int mode, const Geom& g, const DevPtrs& d, int n_rows, const LatLaunch& lat,
+                       int n_partials, hipStream_t s, const float* x, const float* y,
+                       const float* z, const float* q, float* fx, float* fy, float* fz,
+                       float* phi, double* energy, double* virial, const double* gscale,
+                       hipEvent_t* ev, hipStream_t aux, hipEvent_t fork, hipEvent_t join) {
   const int n = g.n_atoms;
+  const bool forces = (mode != kModeEnergy);
   auto mark = [&](int stage) {
     if (ev) (void)hipEventRecord(ev[stage], s);
   };
   mark(kStageBin);
+  const bool par = (n > 0 && aux != nullptr && ev == nullptr);
   if (n > 0) {
     k_bin_count<<<blocks_for(n), kBlock, 0, s>>>(g, x, y, z, d.counts, d.cell_of);
     k_scan<<<1, 1024, 0, s>>>(d.counts, d.cell_start, d.cursor, d.status, g.n_cells);
@@ -1024,28 +1074,30 @@ hipError_t launch_forward(const Geom& g, const DevPtrs& d, int n_rows, const Lat
     k_bin_place<<<blocks_for(n), kBlock, 0, s>>>(g, d.cell_of, d.cell_start, d.tmp, d.fshort,
                                                  d.sorted, d.perm, d.status);
     mark(kStageShort);
-    const bool par = (aux != nullptr && ev == nullptr);
     hipStream_t ss = s;
     if (par) {
       (void)hipEventRecord(fork, s);
       (void)hipStreamWaitEvent(aux, fork, 0);
       ss = aux;
     }
-    int items = g.runs_x * g.nc[1] * g.nc[2];
-    if (g.m == 1)
-      k_short<1><<<items, kBlock, 0, ss>>>(g, d.sorted, d.cell_start, d.fshort);
-    else if (g.m == 2)
-      k_short<2><<<items, kBlock, 0, ss>>>(g, d.sorted, d.cell_start, d.fshort);
-    else if (g.m == 3)
-      k_short<3><<<items, kBlock, 0, ss>>>(g, d.sorted, d.cell_start, d.fshort);
-    else if (g.m == 4)
-      k_short<4><<<items, kBlock, 0, ss>>>(g, d.sorted, d.cell_start, d.fshort);
-    else if (g.m == 5)
-      k_short<5><<<items, kBlock, 0, ss>>>(g, d.sorted, d.cell_start, d.fshort);
-    else if (g.m == 6)
-      k_short<6><<<items, kBlock, 0, ss>>>(g, d.sorted, d.cell_start, d.fshort);
-    else
-      k_short<7><<<items, kBlock, 0, ss>>>(g, d.sorted, d.cell_start, d.fshort);
+    const int items = g.runs_x * g.nc[1] * g.nc[2];
+#define MSM_SHORT(MM)                                                                          \
+  do {                                                                                         \
+    if (forces)                                                                                \
+      k_short<MM, true><<<items, kBlock, 0, ss>>>(g, d.sorted, d.cell_start, d.fshort);        \
+    else                                                                                       \
+      k_short<MM, false><<<items, kBlock, 0, ss>>>(g, d.sorted, d.cell_start, d.fshort);       \
+  } while (0)
+    switch (g.m) {
+      case 1: MSM_SHORT(1); break;
+      case 2: MSM_SHORT(2); break;
+      case 3: MSM_SHORT(3); break;
+      case 4: MSM_SHORT(4); break;
+      case 5: MSM_SHORT(5); break;
+      case 6: MSM_SHORT(6); break;
+      default: MSM_SHORT(7); break;
+    }
+#undef MSM_SHORT
     if (par) (void)hipEventRecord(join, aux);
   } else {
     k_scan<<<1, 1024, 0, s>>>(d.counts, d.cell_start, d.cursor, d.status, g.n_cells);
@@ -1098,6 +1150,15 @@ hipError_t launch_forward(const Geom& g, const DevPtrs& d, int n_rows, const Lat
   mark(kStageTop);
   k_top<<<blocks_for(g.lv[g.levels - 1].count * kWave), kBlock, 0, s>>>(g, d.top, d.qgrid, d.ucut, d.u);
   mark(kStageProlong);
+  if (mode == kModeEnergy) {
+    mark(kStageInterp);
+    if (par) (void)hipStreamWaitEvent(s, join, 0);
+    mark(kStageReduce);
+    k_energy_terms<<<n_partials, kBlock, 0, s>>>(g, d.sorted, d.fshort, d.qgrid, d.ucut, d.partials);
+    k_reduce<<<1, kBlock, 0, s>>>(d.partials, n_partials, energy, nullptr);
+    mark(kStageCount);
+    return hipGetLastError();
+  }
   for (int k = g.levels - 2; k >= 0; --k) {
     const Level& F = g.lv[k];
     const int nb = ((F.n[0] + kPX - 1) / kPX) * ((F.n[1] + kPY - 1) / kPY) * ((F.n[2] + kPZ - 1) / kPZ);
@@ -1108,16 +1169,25 @@ hipError_t launch_forward(const Geom& g, const DevPtrs& d, int n_rows, const Lat
   }
   mark(kStageInterp);
   if (n > 0) {
-    if (aux != nullptr && ev == nullptr) (void)hipStreamWaitEvent(s, join, 0);
-    if (g.order == 4)
-      k_interp<4><<<blocks_for(n), kBlock, 0, s>>>(g, d.sorted, d.perm, d.fshort, d.u, fx, fy, fz,
-                                                   phi, d.partials, n_partials);
-    else
-      k_interp<6><<<blocks_for(n), kBlock, 0, s>>>(g, d.sorted, d.perm, d.fshort, d.u, fx, fy, fz,
-                                                   phi, d.partials, n_partials);
+    if (par) (void)hipStreamWaitEvent(s, join, 0);
+    if (mode == kModeGradient) {
+      if (g.order == 4)
+        k_interp<4, 1><<<blocks_for(n), kBlock, 0, s>>>(g, d.sorted, d.perm, d.fshort, d.u, fx, fy, fz,
+                                                        phi, d.partials, n_partials, gscale);
+      else
+        k_interp<6, 1><<<blocks_for(n), kBlock, 0, s>>>(g, d.sorted, d.perm, d.fshort, d.u, fx, fy, fz,
+                                                        phi, d.partials, n_partials, gscale);
+    } else {
+      if (g.order == 4)
+        k_interp<4, 0><<<blocks_for(n), kBlock, 0, s>>>(g, d.sorted, d.perm, d.fshort, d.u, fx, fy, fz,
+                                                        phi, d.partials, n_partials, nullptr);
+      else
+        k_interp<6, 0><<<blocks_for(n), kBlock, 0, s>>>(g, d.sorted, d.perm, d.fshort, d.u, fx, fy, fz,
+                                                        phi, d.partials, n_partials, nullptr);
+    }
   }
   mark(kStageReduce);
-  if (energy || virial) {
+  if (mode == kModeForces && (energy || virial)) {
     // with no atoms there are no partials and k_reduce writes zeros
     k_reduce<<<1, kBlock, 0, s>>>(d.partials, n > 0 ? n_partials : 0, energy, virial);
   }

@@ -22,7 +22,8 @@ SECTION_QGRID, SECTION_UCUT, SECTION_U, SECTION_SORTED, SECTION_PERM, SECTION_SH
 # every entry point include/msm.h declares
 EXPORTS = ("msm_plan_create", "msm_plan_destroy", "msm_plan_info", "msm_plan_describe",
            "msm_workspace_bytes",
-           "msm_workspace_init", "msm_compute", "msm_status_query", "msm_workspace_section",
+           "msm_workspace_init", "msm_compute", "msm_energy", "msm_backward", "msm_status_query",
+           "msm_workspace_section",
            "msm_profile_enable", "msm_profile_read", "msm_graph_capture", "msm_graph_launch",
            "msm_graph_destroy", "msm_status_string", "msm_last_error")
 
@@ -62,6 +63,8 @@ def lib():
         L.msm_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
         L.msm_workspace_init.argtypes = [vp, vp, sz, vp]
         L.msm_compute.argtypes = [vp, vp, sz, vp] + [vp] * 10
+        L.msm_energy.argtypes = [vp, vp, sz, vp] + [vp] * 5
+        L.msm_backward.argtypes = [vp, vp, sz, vp] + [vp] * 9
         L.msm_status_query.argtypes = [vp, vp, vp, ctypes.POINTER(i32)]
         L.msm_workspace_section.argtypes = [vp, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)]
         L.msm_profile_enable.argtypes = [vp, i32]
@@ -164,6 +167,29 @@ class Plan:
                                  _ptr(o.get("virial") if virial else None)))
         return o
 
+    def _check_inputs(self, x, y, z, q):
+        dev = self.ws.device
+        for t in (x, y, z, q):
+            if t.dtype != torch.float32 or t.device != dev or not t.is_contiguous() or t.numel() != self.n:
+                raise ValueError("x, y, z, q must be contiguous float32 device tensors of length n_atoms")
+
+    def energy(self, x, y, z, q, out=None):
+        """Energy only (float64 [1] on the device), without forces or grids kept."""
+        self._check_inputs(x, y, z, q)
+        e = out if out is not None else torch.empty(1, dtype=torch.float64, device=self.ws.device)
+        _check(lib().msm_energy(self._h, _ptr(self.ws), self.ws.numel(), _stream(), _ptr(x), _ptr(y),
+                                _ptr(z), _ptr(q), _ptr(e)))
+        return e
+
+    def backward(self, x, y, z, q, grad_energy, dpos=None, dq=None):
+        """grad_energy * dE/dr into dpos [3, N] and grad_energy * dE/dq into dq [N] (float32)."""
+        self._check_inputs(x, y, z, q)
+        g = grad_energy.reshape(1).to(device=self.ws.device, dtype=torch.float64).contiguous()
+        dx, dy, dz = (dpos[0], dpos[1], dpos[2]) if dpos is not None else (None, None, None)
+        _check(lib().msm_backward(self._h, _ptr(self.ws), self.ws.numel(), _stream(), _ptr(x), _ptr(y),
+                                  _ptr(z), _ptr(q), _ptr(g), _ptr(dx), _ptr(dy), _ptr(dz), _ptr(dq)))
+        return dpos, dq
+
     def status(self):
         """Synchronise and return (status code, raw device flags) of the last evaluation."""
         flags = ctypes.c_int32()
@@ -213,6 +239,42 @@ class Graph:
         if h is not None and h.value and _lib is not None:
             _lib.msm_graph_destroy(h)
             self._h = None
+
+
+class MSMEnergy(torch.autograd.Function):
+    """E(pos, q) with a hand-written backward.
+
+    forward: msm_energy (energy only, float64 scalar; nothing but pos and q
+             is saved).
+    backward: msm_backward recomputes the grid chain and returns
+              grad * dE/dpos (= -grad * F) and grad * dE/dq (= grad * phi),
+              float32, with the incoming gradient read on the device.
+    pos: float32 [3, N] (rows x, y, z), q: float32 [N], on the plan's device.
+    """
+
+    @staticmethod
+    def forward(ctx, pos, q, plan):
+        pos = pos.contiguous()
+        q = q.contiguous()
+        e = plan.energy(pos[0], pos[1], pos[2], q)
+        ctx.plan = plan
+        ctx.save_for_backward(pos, q)
+        return e.reshape(())
+
+    @staticmethod
+    def backward(ctx, grad):
+        pos, q = ctx.saved_tensors
+        need_pos, need_q = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        dpos = torch.empty_like(pos) if need_pos else None
+        dq = torch.empty_like(q) if need_q else None
+        if need_pos or need_q:
+            ctx.plan.backward(pos[0], pos[1], pos[2], q, grad.detach(), dpos, dq)
+        return dpos, dq, None
+
+
+def energy(plan, pos, q):
+    """Differentiable MSM energy (see MSMEnergy)."""
+    return MSMEnergy.apply(pos, q, plan)
 
 
 def plan_for(system, device="cuda") -> Plan:
