@@ -173,6 +173,64 @@ msm_status msm_workspace_section(const msm_plan* plan, int32_t section, size_t* 
 msm_status msm_profile_enable(msm_plan* plan, int32_t enable);
 msm_status msm_profile_read(const msm_plan* plan, float* ms, int32_t* n_stages);
 
+/* ------------------------------------------------------------------------ */
+/* Tuning.  msm_plan_tune sets the lattice-cutoff outputs per lane (4, 6 or 8;
+ * 0 keeps the current value) and the short-range cells per work item (>= 1;
+ * 0 keeps it), and re-uploads the plan's descriptor to ws (other workspaces
+ * of the plan must be initialised again).  msm_plan_autotune times each
+ * candidate (4, 6, 8) x (1, 2, 3) over `trials` evaluations of the given
+ * device inputs on `stream` with HIP events, applies the fastest and writes
+ * a JSON report (nullable) of the search. */
+msm_status msm_plan_tune(msm_plan* plan, void* ws, size_t ws_bytes, msm_stream_t stream,
+                         int32_t lattice_b, int32_t run_w);
+msm_status msm_plan_autotune(msm_plan* plan, void* ws, size_t ws_bytes, msm_stream_t stream,
+                             const float* x, const float* y, const float* z, const float* q,
+                             int32_t trials, char* report, size_t report_bytes);
+
+/* ------------------------------------------------------------------------ */
+/* Batches: n_sys independent systems (replicas of uneven size) evaluated
+ * together.  Every stage is one launch covering all systems, so a batch costs
+ * the launches of a single evaluation.  System s has params[s] and n_atoms[s]
+ * atoms; its atoms occupy [off[s], off[s] + n_atoms[s]) of the concatenated
+ * SoA arrays, off = exclusive prefix sum of n_atoms (msm_batch_atom_offsets
+ * writes off[0..n_sys]).  All systems must share order and split_m.
+ * Outputs: per-atom arrays concatenated like the inputs; energy[n_sys] and
+ * virial[9 n_sys] (float64, device); grad_energy[n_sys] for the backward. */
+typedef struct msm_batch msm_batch;
+msm_status msm_batch_create(const msm_params* params, const int32_t* n_atoms, int32_t n_sys,
+                            msm_batch** out);
+msm_status msm_batch_destroy(msm_batch* batch);
+msm_status msm_batch_workspace_bytes(const msm_batch* batch, size_t* bytes);
+msm_status msm_batch_atom_offsets(const msm_batch* batch, int32_t* offsets);
+msm_status msm_batch_workspace_init(const msm_batch* batch, void* ws, size_t ws_bytes,
+                                    msm_stream_t stream);
+msm_status msm_batch_compute(const msm_batch* batch, void* ws, size_t ws_bytes, msm_stream_t stream,
+                             const float* x, const float* y, const float* z, const float* q,
+                             float* fx, float* fy, float* fz, float* phi, double* energy,
+                             double* virial);
+msm_status msm_batch_energy(const msm_batch* batch, void* ws, size_t ws_bytes, msm_stream_t stream,
+                            const float* x, const float* y, const float* z, const float* q,
+                            double* energy);
+msm_status msm_batch_backward(const msm_batch* batch, void* ws, size_t ws_bytes, msm_stream_t stream,
+                              const float* x, const float* y, const float* z, const float* q,
+                              const double* grad_energy, float* dedx, float* dedy, float* dedz,
+                              float* dedq);
+/* Graph of one batched evaluation (replay with msm_graph_launch). */
+msm_status msm_batch_graph_capture(const msm_batch* batch, void* ws, size_t ws_bytes, const float* x,
+                                   const float* y, const float* z, const float* q, float* fx,
+                                   float* fy, float* fz, float* phi, double* energy, double* virial,
+                                   msm_graph** out);
+/* Synchronise and OR the data-error flags of every system (per-system raw
+ * flags into flags_per_system[n_sys], nullable). */
+msm_status msm_batch_status(const msm_batch* batch, const void* ws, msm_stream_t stream,
+                            int32_t* flags_per_system);
+msm_status msm_batch_describe(const msm_batch* batch, char* buf, size_t buf_bytes);
+msm_status msm_batch_tune(msm_batch* batch, void* ws, size_t ws_bytes, msm_stream_t stream,
+                          int32_t lattice_b, int32_t run_w);
+msm_status msm_batch_autotune(msm_batch* batch, void* ws, size_t ws_bytes, msm_stream_t stream,
+                              const float* x, const float* y, const float* z, const float* q,
+                              int32_t trials, char* report, size_t report_bytes);
+
 const char* msm_status_string(msm_status status);
 const char* msm_last_error(void);
 

@@ -7,67 +7,15 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <set>
 #include <string>
 #include <vector>
 
-#include "msm_internal.hpp"
-
-using msm::Geom;
-using msm::Layout;
-
-struct msm_plan {
-  msm_params p;
-  Geom g;
-  std::vector<msm::StencilRow> rows;
-  std::vector<int4> rows_c;                  // compact rows of the windowed kernel
-  std::vector<float> weights_c;              // compact weights of the windowed kernel
-  std::vector<float> weights;
-  std::vector<double> top;
-  int n_restrict = 0;
-  int restrict_j[12];
-  float restrict_w[12];
-  float prolong_w[11];
-  int n_partials = 1;
-  msm::LatLaunch lat;
-  Layout lay;
-  // optional stage timing (diagnostics); mutable state of an otherwise fixed plan
-  bool profile = false;
-  hipEvent_t ev[msm::kStageCount + 1] = {};
-  // auxiliary stream for the concurrent short-range pass (created on first use)
-  hipStream_t aux = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
-  int aux_device = -1;
-};
+#include "msm_plan.hpp"
 
 namespace {
-// Create (once per plan) the auxiliary stream and fork/join events on the
-// current device.  Streams keep the default priority.
-hipError_t ensure_aux(msm_plan* P) {
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  if (P->aux && P->aux_device == dev) return hipSuccess;
-  if (P->aux) {
-    (void)hipStreamDestroy(P->aux);
-    (void)hipEventDestroy(P->fork);
-    (void)hipEventDestroy(P->join);
-    P->aux = nullptr;
-  }
-  e = hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&P->fork, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&P->join, hipEventDisableTiming);
-  if (e != hipSuccess) {
-    P->aux = nullptr;
-    return e;
-  }
-  P->aux_device = dev;
-  return hipSuccess;
-}
-}  // namespace
-
-namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
 msm_status fail(msm_status s, const std::string& msg) {
   g_last_error = msg;
@@ -78,6 +26,34 @@ msm_status hip_fail(hipError_t e, const char* what) {
   g_last_error = std::string(what) + ": " + hipGetErrorString(e);
   return MSM_ERR_HIP;
 }
+
+// Create (once per owner) the auxiliary stream and fork/join events on the
+// current device.  Streams keep the default priority.
+hipError_t ensure_aux(AuxStreams& A) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (A.stream && A.device == dev) return hipSuccess;
+  destroy_aux(A);
+  e = hipStreamCreateWithFlags(&A.stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&A.fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&A.join, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    destroy_aux(A);
+    return e;
+  }
+  A.device = dev;
+  return hipSuccess;
+}
+
+void destroy_aux(AuxStreams& A) {
+  if (A.stream) (void)hipStreamDestroy(A.stream);
+  if (A.fork) (void)hipEventDestroy(A.fork);
+  if (A.join) (void)hipEventDestroy(A.join);
+  A = AuxStreams{};
+}
+
+namespace {
 
 // Taylor smoothing (Sec. 2.3): gamma(rho) = sum_k c_k rho^{2k}, rho < 1, with c_k
 // the coefficients of the degree-m Taylor polynomial of s^{-1/2} at s = 1,
@@ -102,19 +78,6 @@ double gamma_h(const double* c, int m, double rho) {
   return v;
 }
 
-// C1 numerical-Hermite basis Phi (cubic: support 2, quintic: support 3).
-double phi_h(int order, double u) {
-  double t = std::fabs(u);
-  if (order == 4) {
-    if (t <= 1.0) return (1.0 - t) * (1.0 + t - 1.5 * t * t);
-    if (t <= 2.0) return -0.5 * (t - 1.0) * (2.0 - t) * (2.0 - t);
-    return 0.0;
-  }
-  if (t <= 1.0) return (1.0 - t * t) * (2.0 - t) * (6.0 + 3.0 * t - 5.0 * t * t) / 12.0;
-  if (t <= 2.0) return (1.0 - t) * (2.0 - t) * (3.0 - t) * (4.0 + 9.0 * t - 5.0 * t * t) / 24.0;
-  if (t <= 3.0) return (t - 1.0) * (t - 2.0) * (t - 3.0) * (t - 3.0) * (4.0 - t) / 24.0;
-  return 0.0;
-}
 
 int floor_div2(int v) { return v >= 0 ? v / 2 : -((-v + 1) / 2); }
 int ceil_div2(int v) { return -floor_div2(-v); }
@@ -165,7 +128,8 @@ void pad_window(msm::LatTile& t, int B, int H, int max_floats) {
 // minimising a cost in wave instructions: FMA slots including ragged-tile
 // waste (about half a FMA per tap with mirror-row pairing), plus the window
 // load; then penalise launches with fewer blocks than compute units.
-void choose_lattice_tiles(const Geom& g, int taps, int H_, int tables_bytes, msm::LatLaunch& lat) {
+void choose_lattice_tiles(const Geom& g, int taps, int H_, int tables_bytes, msm::LatLaunch& lat,
+                          int force_b = 0) {
   const int n_rows = lat.n_rows, n_wc = lat.n_wc;
   std::memset(&lat, 0, sizeof(lat));
   lat.H = H_;
@@ -177,6 +141,7 @@ void choose_lattice_tiles(const Geom& g, int taps, int H_, int tables_bytes, msm
   const int Bs[3] = {4, 6, 8};
   for (int bi = 0; bi < 3; ++bi) {
     const int B = Bs[bi];
+    if (force_b && B != force_b) continue;
     cand = lat;
     cand.b = B;
     cand.n = g.levels - 1;
@@ -230,6 +195,76 @@ void choose_lattice_tiles(const Geom& g, int taps, int H_, int tables_bytes, msm
 }
 
 }  // namespace
+
+void refresh_launch(msm_plan* P) {
+  const Geom& g = P->g;
+  msm::DevPtrs keep = P->desc.d;
+  std::memset(&P->desc, 0, sizeof(P->desc));
+  P->desc.d = keep;
+  P->desc.g = g;
+  P->desc.lat = P->lat;
+  P->desc.atom_off = 0;
+  P->desc.index = 0;
+  P->desc.n_partials = P->n_partials;
+  P->desc.n_rows = (int)P->rows.size();
+  const msm::SysBlocks sb = msm::system_blocks(g, P->lat, P->n_partials);
+  msm::LaunchGeom& lg = P->lg;
+  lg = msm::LaunchGeom{};
+  lg.n_sys = 1;
+  lg.order = g.order;
+  lg.m = g.m;
+  lg.lat_b = P->lat.b;
+  lg.lat_lds = P->lat.lds_bytes;
+  lg.max_levels = g.levels;
+  lg.zero.blocks = sb.zero;
+  lg.atoms.blocks = sb.atoms;
+  lg.one.blocks = 1;
+  lg.shortr.blocks = sb.shortr;
+  lg.anterp.blocks = sb.anterp;
+  lg.lattice.blocks = sb.lattice;
+  lg.top.blocks = sb.top;
+  lg.energy.blocks = sb.energy;
+  for (int k = 0; k + 1 < g.levels; ++k) {
+    lg.restrict_[k].blocks = sb.restrict_[k];
+    lg.prolong[k].blocks = sb.prolong[k];
+  }
+}
+
+void retune(msm_plan* P, int lat_b, int run_w) {
+  if (lat_b && P->lat.b && lat_b != P->lat.b)
+    choose_lattice_tiles(P->g, (int)P->weights.size(), P->lat.H, P->lat_tables, P->lat, lat_b);
+  if (run_w > 0) {
+    Geom& g = P->g;
+    g.run_w = std::max(1, std::min(run_w, g.nc[0]));
+    g.runs_x = (g.nc[0] + g.run_w - 1) / g.run_w;
+  }
+  refresh_launch(P);
+}
+
+msm::DevPtrs dev_ptrs(const msm_plan* P, void* ws) {
+  char* b = static_cast<char*>(ws);
+  const size_t* o = P->lay.off;
+  msm::DevPtrs d;
+  d.qgrid = reinterpret_cast<float*>(b + o[msm::kSecQGrid]);
+  d.ucut = reinterpret_cast<float*>(b + o[msm::kSecUCut]);
+  d.u = reinterpret_cast<float*>(b + o[msm::kSecU]);
+  d.sorted = reinterpret_cast<float4*>(b + o[msm::kSecSorted]);
+  d.perm = reinterpret_cast<int*>(b + o[msm::kSecPerm]);
+  d.fshort = reinterpret_cast<float4*>(b + o[msm::kSecShort]);
+  d.status = reinterpret_cast<int*>(b + o[msm::kSecStatus]);
+  d.counts = reinterpret_cast<int*>(b + o[msm::kSecCounts]);
+  d.cell_start = reinterpret_cast<int*>(b + o[msm::kSecCellStart]);
+  d.cursor = reinterpret_cast<int*>(b + o[msm::kSecCursor]);
+  d.cell_of = reinterpret_cast<int*>(b + o[msm::kSecCellOf]);
+  d.tmp = reinterpret_cast<int*>(b + o[msm::kSecTmp]);
+  d.rows = reinterpret_cast<const msm::StencilRow*>(b + o[msm::kSecRows]);
+  d.weights = reinterpret_cast<const float*>(b + o[msm::kSecWeights]);
+  d.rows_c = reinterpret_cast<const int4*>(b + o[msm::kSecRowsC]);
+  d.weights_c = reinterpret_cast<const float*>(b + o[msm::kSecWeightsC]);
+  d.top = reinterpret_cast<const double*>(b + o[msm::kSecTop]);
+  d.partials = reinterpret_cast<double*>(b + o[msm::kSecPartials]);
+  return d;
+}
 
 extern "C" {
 
@@ -434,6 +469,7 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
       P->lat.n_rows = (int)P->rows_c.size();
       P->lat.n_wc = (int)P->weights_c.size();
       const int tables = P->lat.n_rows * 16 + P->lat.n_wc * 4;
+      P->lat_tables = tables;
       choose_lattice_tiles(g, (int)P->weights.size(), H, tables, P->lat);
     } else {
       P->lat.b = 0;
@@ -451,17 +487,6 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
           double r = hk * std::sqrt((double)(dx * dx + dy * dy + dz * dz));
           P->top[((size_t)dz * T.n[1] + dy) * T.n[0] + dx] = gamma_h(c, g.m, r / A) / A;
         }
-  }
-  // restriction offsets j with Phi(j/2) != 0, and prolongation weights Phi(j/2)
-  const int R = p.order - 1;
-  for (int j = -R; j <= R; ++j) {
-    double wv = phi_h(p.order, 0.5 * j);
-    P->prolong_w[j + R] = (float)wv;
-    if (wv != 0.0) {
-      P->restrict_j[P->n_restrict] = j;
-      P->restrict_w[P->n_restrict] = (float)wv;
-      ++P->n_restrict;
-    }
   }
   P->n_partials = msm::interp_partials(g);
 
@@ -487,12 +512,15 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
   lay.bytes[msm::kSecWeightsC] = std::max<size_t>(P->weights_c.size(), 1) * sizeof(float);
   lay.bytes[msm::kSecTop] = P->top.size() * sizeof(double);
   lay.bytes[msm::kSecPartials] = 10 * (size_t)P->n_partials * sizeof(double);
+  lay.bytes[msm::kSecDesc] = sizeof(msm::SysDesc);
   size_t o = 0;
   for (int s = 0; s < msm::kSecCount; ++s) {
     lay.off[s] = o;
     o += align256(lay.bytes[s]);
   }
   lay.total = o;
+
+  refresh_launch(P);
   *out = P;
   return MSM_OK;
 }
@@ -501,11 +529,7 @@ msm_status msm_plan_destroy(msm_plan* plan) {
   if (plan) {
     for (auto& e : plan->ev)
       if (e) (void)hipEventDestroy(e);
-    if (plan->aux) {
-      (void)hipStreamDestroy(plan->aux);
-      (void)hipEventDestroy(plan->fork);
-      (void)hipEventDestroy(plan->join);
-    }
+    destroy_aux(plan->aux);
   }
   delete plan;
   return MSM_OK;
@@ -584,7 +608,6 @@ msm_status msm_workspace_section(const msm_plan* P, int32_t section, size_t* off
   return MSM_OK;
 }
 
-static msm::DevPtrs dev_ptrs(const msm_plan* P, void* ws);
 
 msm_status msm_workspace_init(const msm_plan* P, void* ws, size_t ws_bytes, msm_stream_t stream) {
   if (!P) return fail(MSM_ERR_INVALID_ARG, "null plan");
@@ -611,55 +634,53 @@ msm_status msm_workspace_init(const msm_plan* P, void* ws, size_t ws_bytes, msm_
   e = hipMemcpyAsync(base + P->lay.off[msm::kSecTop], P->top.data(), P->top.size() * sizeof(double),
                      hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_fail(e, "upload top-level table");
-  e = msm::launch_init(P->g, dev_ptrs(P, ws), s);
+  msm_plan* M = const_cast<msm_plan*>(P);
+  M->desc.d = dev_ptrs(P, ws);
+  e = hipMemcpyAsync(base + P->lay.off[msm::kSecDesc], &M->desc, sizeof(msm::SysDesc),
+                     hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "upload descriptor");
+  msm::LaunchGeom L = P->lg;
+  L.sys = reinterpret_cast<const msm::SysDesc*>(base + P->lay.off[msm::kSecDesc]);
+  e = msm::launch_init(L, s);
   if (e != hipSuccess) return hip_fail(e, "clear cell counters");
   // pageable-memory copies are staged before returning; the plan may be destroyed afterwards
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "workspace init");
+  M->ready.insert(ws);
   return MSM_OK;
 }
 
-static msm::DevPtrs dev_ptrs(const msm_plan* P, void* ws) {
-  char* b = static_cast<char*>(ws);
-  const size_t* o = P->lay.off;
-  msm::DevPtrs d;
-  d.qgrid = reinterpret_cast<float*>(b + o[msm::kSecQGrid]);
-  d.ucut = reinterpret_cast<float*>(b + o[msm::kSecUCut]);
-  d.u = reinterpret_cast<float*>(b + o[msm::kSecU]);
-  d.sorted = reinterpret_cast<float4*>(b + o[msm::kSecSorted]);
-  d.perm = reinterpret_cast<int*>(b + o[msm::kSecPerm]);
-  d.fshort = reinterpret_cast<float4*>(b + o[msm::kSecShort]);
-  d.status = reinterpret_cast<int*>(b + o[msm::kSecStatus]);
-  d.counts = reinterpret_cast<int*>(b + o[msm::kSecCounts]);
-  d.cell_start = reinterpret_cast<int*>(b + o[msm::kSecCellStart]);
-  d.cursor = reinterpret_cast<int*>(b + o[msm::kSecCursor]);
-  d.cell_of = reinterpret_cast<int*>(b + o[msm::kSecCellOf]);
-  d.tmp = reinterpret_cast<int*>(b + o[msm::kSecTmp]);
-  d.rows = reinterpret_cast<const msm::StencilRow*>(b + o[msm::kSecRows]);
-  d.weights = reinterpret_cast<const float*>(b + o[msm::kSecWeights]);
-  d.rows_c = reinterpret_cast<const int4*>(b + o[msm::kSecRowsC]);
-  d.weights_c = reinterpret_cast<const float*>(b + o[msm::kSecWeightsC]);
-  d.top = reinterpret_cast<const double*>(b + o[msm::kSecTop]);
-  d.partials = reinterpret_cast<double*>(b + o[msm::kSecPartials]);
-  return d;
+
+static msm::LaunchGeom launch_geom(const msm_plan* P, void* ws) {
+  msm::LaunchGeom L = P->lg;
+  L.sys = reinterpret_cast<const msm::SysDesc*>(static_cast<char*>(ws) + P->lay.off[msm::kSecDesc]);
+  return L;
+}
+
+static msm_status check_call(const msm_plan* P, const void* ws, size_t ws_bytes, const float* x,
+                             const float* y, const float* z, const float* q, const float* fx,
+                             const float* fy, const float* fz) {
+  if (!P) return fail(MSM_ERR_INVALID_ARG, "null plan");
+  if (!ws || ws_bytes < P->lay.total) return fail(MSM_ERR_WORKSPACE, "workspace missing or too small");
+  if (!P->ready.count(ws)) return fail(MSM_ERR_WORKSPACE, "workspace not initialised for this plan");
+  if (P->g.n_atoms > 0 && (!x || !y || !z || !q))
+    return fail(MSM_ERR_INVALID_ARG, "null position or charge array");
+  if (!((fx && fy && fz) || (!fx && !fy && !fz)))
+    return fail(MSM_ERR_INVALID_ARG, "vector outputs must be all set or all null");
+  return MSM_OK;
 }
 
 msm_status msm_compute(const msm_plan* P, void* ws, size_t ws_bytes, msm_stream_t stream,
                        const float* x, const float* y, const float* z, const float* q, float* fx,
                        float* fy, float* fz, float* phi, double* energy, double* virial) {
-  if (!P) return fail(MSM_ERR_INVALID_ARG, "null plan");
-  if (!ws || ws_bytes < P->lay.total) return fail(MSM_ERR_WORKSPACE, "workspace missing or too small");
-  if (P->g.n_atoms > 0 && (!x || !y || !z || !q))
-    return fail(MSM_ERR_INVALID_ARG, "null position or charge array");
-  if (!((fx && fy && fz) || (!fx && !fy && !fz)))
-    return fail(MSM_ERR_INVALID_ARG, "force outputs must be all set or all null");
-  msm::DevPtrs d = dev_ptrs(P, ws);
+  msm_status st = check_call(P, ws, ws_bytes, x, y, z, q, fx, fy, fz);
+  if (st != MSM_OK) return st;
   msm_plan* M = const_cast<msm_plan*>(P);
-  hipError_t e = ensure_aux(M);
+  hipError_t e = ensure_aux(M->aux);
   if (e != hipSuccess) return hip_fail(e, "create auxiliary stream");
-  e = msm::launch_eval(msm::kModeForces, P->g, d, (int)P->rows.size(), P->lat, P->n_partials,
-                       reinterpret_cast<hipStream_t>(stream), x, y, z, q, fx, fy, fz, phi, energy,
-                       virial, nullptr, P->profile ? M->ev : nullptr, M->aux, M->fork, M->join);
+  const msm::Io io{x, y, z, q, fx, fy, fz, phi, energy, virial, nullptr};
+  e = msm::launch_eval(msm::kModeForces, launch_geom(P, ws), reinterpret_cast<hipStream_t>(stream), io,
+                       P->profile ? M->ev : nullptr, M->aux.stream, M->aux.fork, M->aux.join);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return MSM_OK;
 }
@@ -668,19 +689,14 @@ static msm_status eval_mode(int mode, const msm_plan* P, void* ws, size_t ws_byt
                             msm_stream_t stream, const float* x, const float* y, const float* z,
                             const float* q, float* fx, float* fy, float* fz, float* phi,
                             double* energy, const double* gscale) {
-  if (!P) return fail(MSM_ERR_INVALID_ARG, "null plan");
-  if (!ws || ws_bytes < P->lay.total) return fail(MSM_ERR_WORKSPACE, "workspace missing or too small");
-  if (P->g.n_atoms > 0 && (!x || !y || !z || !q))
-    return fail(MSM_ERR_INVALID_ARG, "null position or charge array");
-  if (!((fx && fy && fz) || (!fx && !fy && !fz)))
-    return fail(MSM_ERR_INVALID_ARG, "gradient outputs must be all set or all null");
-  msm::DevPtrs d = dev_ptrs(P, ws);
+  msm_status st = check_call(P, ws, ws_bytes, x, y, z, q, fx, fy, fz);
+  if (st != MSM_OK) return st;
   msm_plan* M = const_cast<msm_plan*>(P);
-  hipError_t e = ensure_aux(M);
+  hipError_t e = ensure_aux(M->aux);
   if (e != hipSuccess) return hip_fail(e, "create auxiliary stream");
-  e = msm::launch_eval(mode, P->g, d, (int)P->rows.size(), P->lat, P->n_partials,
-                       reinterpret_cast<hipStream_t>(stream), x, y, z, q, fx, fy, fz, phi, energy,
-                       nullptr, gscale, nullptr, M->aux, M->fork, M->join);
+  const msm::Io io{x, y, z, q, fx, fy, fz, phi, energy, nullptr, gscale};
+  e = msm::launch_eval(mode, launch_geom(P, ws), reinterpret_cast<hipStream_t>(stream), io, nullptr,
+                       M->aux.stream, M->aux.fork, M->aux.join);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return MSM_OK;
 }
@@ -702,11 +718,6 @@ msm_status msm_backward(const msm_plan* P, void* ws, size_t ws_bytes, msm_stream
                    nullptr, grad_energy);
 }
 
-struct msm_graph {
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-};
-
 msm_status msm_graph_destroy(msm_graph* G) {
   if (G) {
     if (G->exec) (void)hipGraphExecDestroy(G->exec);
@@ -721,39 +732,19 @@ msm_status msm_graph_capture(const msm_plan* P, void* ws, size_t ws_bytes, const
                              float* fz, float* phi, double* energy, double* virial, msm_graph** out) {
   if (!out) return fail(MSM_ERR_INVALID_ARG, "null output pointer");
   *out = nullptr;
-  if (!P) return fail(MSM_ERR_INVALID_ARG, "null plan");
-  if (!ws || ws_bytes < P->lay.total) return fail(MSM_ERR_WORKSPACE, "workspace missing or too small");
-  if (P->g.n_atoms > 0 && (!x || !y || !z || !q))
-    return fail(MSM_ERR_INVALID_ARG, "null position or charge array");
-  if (!((fx && fy && fz) || (!fx && !fy && !fz)))
-    return fail(MSM_ERR_INVALID_ARG, "force outputs must be all set or all null");
-  msm_graph* G = new (std::nothrow) msm_graph();
-  if (!G) return fail(MSM_ERR_INVALID_ARG, "out of host memory");
-  hipStream_t cs = nullptr;
-  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-  if (e != hipSuccess) {
-    delete G;
-    return hip_fail(e, "create capture stream");
-  }
+  msm_status st = check_call(P, ws, ws_bytes, x, y, z, q, fx, fy, fz);
+  if (st != MSM_OK) return st;
   msm_plan* M = const_cast<msm_plan*>(P);
-  if (e == hipSuccess) e = ensure_aux(M);
-  if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-  if (e == hipSuccess) {
-    msm::DevPtrs d = dev_ptrs(P, ws);
-    hipError_t le = msm::launch_eval(msm::kModeForces, P->g, d, (int)P->rows.size(), P->lat,
-                                     P->n_partials, cs, x, y, z, q, fx, fy, fz, phi, energy, virial,
-                                     nullptr, nullptr, M->aux, M->fork, M->join);
-    e = hipStreamEndCapture(cs, &G->graph);
-    if (le != hipSuccess) e = le;
-  }
-  if (e == hipSuccess) e = hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0);
-  (void)hipStreamDestroy(cs);
-  if (e != hipSuccess) {
-    msm_graph_destroy(G);
-    return hip_fail(e, "capture evaluation graph");
-  }
-  *out = G;
-  return MSM_OK;
+  hipError_t e = ensure_aux(M->aux);
+  if (e != hipSuccess) return hip_fail(e, "create auxiliary stream");
+  const msm::Io io{x, y, z, q, fx, fy, fz, phi, energy, virial, nullptr};
+  const msm::LaunchGeom L = launch_geom(P, ws);
+  return capture_graph(
+      [&](hipStream_t cs) {
+        return msm::launch_eval(msm::kModeForces, L, cs, io, nullptr, M->aux.stream, M->aux.fork,
+                                M->aux.join);
+      },
+      out);
 }
 
 msm_status msm_graph_launch(const msm_graph* G, msm_stream_t stream) {

@@ -1,0 +1,497 @@
+// Batches of independent systems (replicas of uneven size) evaluated together:
+// every stage is one launch whose blocks cover all systems, mapped through a
+// per-stage block -> (system, block) table, so a batch costs the same number
+// of launches as one evaluation.  Also the tuning knobs and the autotuner of
+// plans and batches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "msm_plan.hpp"
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+constexpr int kNumStages = 8 + 2 * msm::kMaxLevels;
+
+}  // namespace
+
+struct msm_batch {
+  int n_sys = 0;
+  std::vector<msm_plan*> plans;
+  std::vector<int32_t> n_atoms;
+  std::vector<int32_t> atom_off;
+  int64_t total_atoms = 0;
+  // workspace layout
+  std::vector<size_t> sub_off;
+  size_t desc_off = 0;
+  size_t map_off[kNumStages] = {};
+  size_t map_cap[kNumStages] = {};        // capacity in int2 entries
+  size_t total = 0;
+  // current stage tables (host)
+  std::vector<int2> map[kNumStages];
+  msm::LaunchGeom lg;                      // pointers set per workspace
+  std::set<const void*> ready;
+  AuxStreams aux;
+};
+
+namespace {
+
+// Stage order inside the map arrays.
+enum : int {
+  kMZero = 0, kMAtoms, kMOne, kMShort, kMAnterp, kMLattice, kMTop, kMEnergy, kMRestrict0,
+  kMProlong0 = kMRestrict0 + msm::kMaxLevels
+};
+
+msm::StageGrid* stage_of(msm::LaunchGeom& L, int st) {
+  switch (st) {
+    case kMZero: return &L.zero;
+    case kMAtoms: return &L.atoms;
+    case kMOne: return &L.one;
+    case kMShort: return &L.shortr;
+    case kMAnterp: return &L.anterp;
+    case kMLattice: return &L.lattice;
+    case kMTop: return &L.top;
+    case kMEnergy: return &L.energy;
+    default:
+      if (st < kMProlong0) return &L.restrict_[st - kMRestrict0];
+      return &L.prolong[st - kMProlong0];
+  }
+}
+
+int blocks_of(const msm::SysBlocks& b, int st) {
+  switch (st) {
+    case kMZero: return b.zero;
+    case kMAtoms: return b.atoms;
+    case kMOne: return 1;
+    case kMShort: return b.shortr;
+    case kMAnterp: return b.anterp;
+    case kMLattice: return b.lattice;
+    case kMTop: return b.top;
+    case kMEnergy: return b.energy;
+    default:
+      if (st < kMProlong0) return b.restrict_[st - kMRestrict0];
+      return b.prolong[st - kMProlong0];
+  }
+}
+
+// Rebuild the host stage tables and the launch geometry from the sub-plans.
+void rebuild_maps(msm_batch* Bt) {
+  msm::LaunchGeom& L = Bt->lg;
+  L = msm::LaunchGeom{};
+  L.n_sys = Bt->n_sys;
+  L.order = Bt->plans[0]->g.order;
+  L.m = Bt->plans[0]->g.m;
+  L.lat_b = 0;
+  for (int st = 0; st < kNumStages; ++st) Bt->map[st].clear();
+  for (int s = 0; s < Bt->n_sys; ++s) {
+    const msm_plan* P = Bt->plans[s];
+    L.max_levels = std::max(L.max_levels, P->g.levels);
+    L.lat_b = std::max(L.lat_b, P->lat.b);
+    L.lat_lds = std::max(L.lat_lds, P->lat.lds_bytes);
+    const msm::SysBlocks sb = msm::system_blocks(P->g, P->lat, P->n_partials);
+    for (int st = 0; st < kNumStages; ++st) {
+      const int nb = blocks_of(sb, st);
+      for (int b = 0; b < nb; ++b) Bt->map[st].push_back(make_int2(s, b));
+    }
+  }
+  for (int st = 0; st < kNumStages; ++st) stage_of(L, st)->blocks = (int)Bt->map[st].size();
+}
+
+void point_into(msm_batch* Bt, void* ws, msm::LaunchGeom& L) {
+  char* base = static_cast<char*>(ws);
+  L.sys = reinterpret_cast<const msm::SysDesc*>(base + Bt->desc_off);
+  for (int st = 0; st < kNumStages; ++st)
+    stage_of(L, st)->map = reinterpret_cast<const int2*>(base + Bt->map_off[st]);
+}
+
+// Upload the descriptor array and the stage tables of the current tuning.
+msm_status upload_tables(msm_batch* Bt, void* ws, hipStream_t s) {
+  char* base = static_cast<char*>(ws);
+  std::vector<msm::SysDesc> descs(Bt->n_sys);
+  for (int i = 0; i < Bt->n_sys; ++i) {
+    msm_plan* P = Bt->plans[i];
+    P->desc.d = dev_ptrs(P, base + Bt->sub_off[i]);
+    descs[i] = P->desc;
+    descs[i].atom_off = Bt->atom_off[i];
+    descs[i].index = i;
+  }
+  hipError_t e = hipMemcpyAsync(base + Bt->desc_off, descs.data(), descs.size() * sizeof(msm::SysDesc),
+                                hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "upload batch descriptors");
+  for (int st = 0; st < kNumStages; ++st) {
+    if (Bt->map[st].size() > Bt->map_cap[st]) return fail(MSM_ERR_WORKSPACE, "stage table exceeds its reserve");
+    if (Bt->map[st].empty()) continue;
+    e = hipMemcpyAsync(base + Bt->map_off[st], Bt->map[st].data(), Bt->map[st].size() * sizeof(int2),
+                       hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "upload stage tables");
+  }
+  e = hipStreamSynchronize(s);   // host vectors are staged before returning
+  if (e != hipSuccess) return hip_fail(e, "upload batch tables");
+  return MSM_OK;
+}
+
+msm_status check_batch(const msm_batch* Bt, const void* ws, size_t ws_bytes) {
+  if (!Bt) return fail(MSM_ERR_INVALID_ARG, "null batch");
+  if (!ws || ws_bytes < Bt->total) return fail(MSM_ERR_WORKSPACE, "workspace missing or too small");
+  if (!Bt->ready.count(ws)) return fail(MSM_ERR_WORKSPACE, "workspace not initialised for this batch");
+  return MSM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+msm_status msm_batch_destroy(msm_batch* Bt) {
+  if (Bt) {
+    for (msm_plan* P : Bt->plans) msm_plan_destroy(P);
+    destroy_aux(Bt->aux);
+    delete Bt;
+  }
+  return MSM_OK;
+}
+
+msm_status msm_batch_create(const msm_params* params, const int32_t* n_atoms, int32_t n_sys,
+                            msm_batch** out) {
+  if (!out) return fail(MSM_ERR_INVALID_ARG, "null output pointer");
+  *out = nullptr;
+  if (!params || !n_atoms || n_sys < 1) return fail(MSM_ERR_INVALID_ARG, "empty batch or null arrays");
+  msm_batch* Bt = new (std::nothrow) msm_batch();
+  if (!Bt) return fail(MSM_ERR_INVALID_ARG, "out of host memory");
+  Bt->n_sys = n_sys;
+  int64_t off = 0;
+  for (int s = 0; s < n_sys; ++s) {
+    msm_plan* P = nullptr;
+    msm_status st = msm_plan_create(&params[s], n_atoms[s], &P);
+    if (st != MSM_OK) {
+      msm_batch_destroy(Bt);
+      return st;
+    }
+    Bt->plans.push_back(P);
+    Bt->n_atoms.push_back(n_atoms[s]);
+    Bt->atom_off.push_back((int32_t)off);
+    off += n_atoms[s];
+    if (off > (int64_t)1 << 31) {
+      msm_batch_destroy(Bt);
+      return fail(MSM_ERR_UNSUPPORTED, "batch exceeds 2^31 atoms");
+    }
+  }
+  Bt->total_atoms = off;
+  const msm_plan* P0 = Bt->plans[0];
+  bool tiled = P0->lat.b > 0 || P0->g.levels == 1;
+  for (const msm_plan* P : Bt->plans) {
+    if (P->g.order != P0->g.order || P->g.m != P0->g.m) {
+      msm_batch_destroy(Bt);
+      return fail(MSM_ERR_UNSUPPORTED, "systems of a batch must share order and split_m");
+    }
+    const bool t = P->lat.b > 0 || P->g.levels == 1;
+    if (t != tiled) {
+      msm_batch_destroy(Bt);
+      return fail(MSM_ERR_UNSUPPORTED, "mixed stencil widths in one batch");
+    }
+  }
+  // common lattice template: the largest system's choice
+  int big = 0;
+  for (int s = 1; s < n_sys; ++s)
+    if (n_atoms[s] > n_atoms[big]) big = s;
+  const int b0 = Bt->plans[big]->lat.b;
+  for (msm_plan* P : Bt->plans) retune(P, b0, 0);
+
+  // stage-table reserves: the most blocks any tuning can ask for
+  // (lattice template 4, one cell per short-range work item)
+  size_t cap[kNumStages] = {};
+  for (msm_plan* P : Bt->plans) {
+    const Geom keep_g = P->g;
+    const msm::LatLaunch keep_l = P->lat;
+    size_t most[kNumStages] = {};
+    for (int b : {4, 6, 8})
+      for (int w : {1, keep_g.run_w}) {
+        if (P->lat.b) retune(P, b, w);
+        else retune(P, 0, w);
+        const msm::SysBlocks sb = msm::system_blocks(P->g, P->lat, P->n_partials);
+        for (int st = 0; st < kNumStages; ++st) most[st] = std::max(most[st], (size_t)blocks_of(sb, st));
+      }
+    P->g = keep_g;
+    P->lat = keep_l;
+    refresh_launch(P);
+    for (int st = 0; st < kNumStages; ++st) cap[st] += most[st];
+  }
+  size_t o = 0;
+  for (msm_plan* P : Bt->plans) {
+    Bt->sub_off.push_back(o);
+    o += align256(P->lay.total);
+  }
+  Bt->desc_off = o;
+  o += align256(n_sys * sizeof(msm::SysDesc));
+  for (int st = 0; st < kNumStages; ++st) {
+    Bt->map_off[st] = o;
+    Bt->map_cap[st] = cap[st];
+    o += align256(std::max<size_t>(cap[st], 1) * sizeof(int2));
+  }
+  Bt->total = o;
+  rebuild_maps(Bt);
+  *out = Bt;
+  return MSM_OK;
+}
+
+msm_status msm_batch_workspace_bytes(const msm_batch* Bt, size_t* bytes) {
+  if (!Bt || !bytes) return fail(MSM_ERR_INVALID_ARG, "null batch or bytes pointer");
+  *bytes = Bt->total;
+  return MSM_OK;
+}
+
+msm_status msm_batch_atom_offsets(const msm_batch* Bt, int32_t* offsets) {
+  if (!Bt || !offsets) return fail(MSM_ERR_INVALID_ARG, "null batch or offsets");
+  for (int s = 0; s < Bt->n_sys; ++s) offsets[s] = Bt->atom_off[s];
+  offsets[Bt->n_sys] = (int32_t)Bt->total_atoms;
+  return MSM_OK;
+}
+
+msm_status msm_batch_workspace_init(const msm_batch* Bt, void* ws, size_t ws_bytes, msm_stream_t stream) {
+  if (!Bt) return fail(MSM_ERR_INVALID_ARG, "null batch");
+  if (!ws || ws_bytes < Bt->total) return fail(MSM_ERR_WORKSPACE, "workspace missing or too small");
+  char* base = static_cast<char*>(ws);
+  for (int s = 0; s < Bt->n_sys; ++s) {
+    const msm_plan* P = Bt->plans[s];
+    msm_status st = msm_workspace_init(P, base + Bt->sub_off[s], P->lay.total, stream);
+    if (st != MSM_OK) return st;
+  }
+  msm_batch* M = const_cast<msm_batch*>(Bt);
+  msm_status st = upload_tables(M, ws, reinterpret_cast<hipStream_t>(stream));
+  if (st != MSM_OK) return st;
+  M->ready.insert(ws);
+  return MSM_OK;
+}
+
+static msm_status batch_eval(int mode, const msm_batch* Bt, void* ws, size_t ws_bytes,
+                             msm_stream_t stream, const msm::Io& io, msm_graph** graph) {
+  msm_status st = check_batch(Bt, ws, ws_bytes);
+  if (st != MSM_OK) return st;
+  if (Bt->total_atoms > 0 && (!io.x || !io.y || !io.z || !io.q))
+    return fail(MSM_ERR_INVALID_ARG, "null position or charge array");
+  if (!((io.fx && io.fy && io.fz) || (!io.fx && !io.fy && !io.fz)))
+    return fail(MSM_ERR_INVALID_ARG, "vector outputs must be all set or all null");
+  msm_batch* M = const_cast<msm_batch*>(Bt);
+  hipError_t e = ensure_aux(M->aux);
+  if (e != hipSuccess) return hip_fail(e, "create auxiliary stream");
+  msm::LaunchGeom L = Bt->lg;
+  point_into(M, ws, L);
+  if (graph)
+    return capture_graph(
+        [&](hipStream_t cs) {
+          return msm::launch_eval(mode, L, cs, io, nullptr, M->aux.stream, M->aux.fork, M->aux.join);
+        },
+        graph);
+  e = msm::launch_eval(mode, L, reinterpret_cast<hipStream_t>(stream), io, nullptr, M->aux.stream,
+                       M->aux.fork, M->aux.join);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return MSM_OK;
+}
+
+msm_status msm_batch_compute(const msm_batch* Bt, void* ws, size_t ws_bytes, msm_stream_t stream,
+                             const float* x, const float* y, const float* z, const float* q,
+                             float* fx, float* fy, float* fz, float* phi, double* energy,
+                             double* virial) {
+  const msm::Io io{x, y, z, q, fx, fy, fz, phi, energy, virial, nullptr};
+  return batch_eval(msm::kModeForces, Bt, ws, ws_bytes, stream, io, nullptr);
+}
+
+msm_status msm_batch_energy(const msm_batch* Bt, void* ws, size_t ws_bytes, msm_stream_t stream,
+                            const float* x, const float* y, const float* z, const float* q,
+                            double* energy) {
+  if (!energy) return fail(MSM_ERR_INVALID_ARG, "null energy output");
+  const msm::Io io{x, y, z, q, nullptr, nullptr, nullptr, nullptr, energy, nullptr, nullptr};
+  return batch_eval(msm::kModeEnergy, Bt, ws, ws_bytes, stream, io, nullptr);
+}
+
+msm_status msm_batch_backward(const msm_batch* Bt, void* ws, size_t ws_bytes, msm_stream_t stream,
+                              const float* x, const float* y, const float* z, const float* q,
+                              const double* grad_energy, float* dedx, float* dedy, float* dedz,
+                              float* dedq) {
+  if (!grad_energy) return fail(MSM_ERR_INVALID_ARG, "null grad_energy");
+  const msm::Io io{x, y, z, q, dedx, dedy, dedz, dedq, nullptr, nullptr, grad_energy};
+  return batch_eval(msm::kModeGradient, Bt, ws, ws_bytes, stream, io, nullptr);
+}
+
+msm_status msm_batch_graph_capture(const msm_batch* Bt, void* ws, size_t ws_bytes, const float* x,
+                                   const float* y, const float* z, const float* q, float* fx,
+                                   float* fy, float* fz, float* phi, double* energy, double* virial,
+                                   msm_graph** out) {
+  if (!out) return fail(MSM_ERR_INVALID_ARG, "null output pointer");
+  *out = nullptr;
+  const msm::Io io{x, y, z, q, fx, fy, fz, phi, energy, virial, nullptr};
+  return batch_eval(msm::kModeForces, Bt, ws, ws_bytes, nullptr, io, out);
+}
+
+msm_status msm_batch_status(const msm_batch* Bt, const void* ws, msm_stream_t stream,
+                            int32_t* flags_per_system) {
+  if (!Bt || !ws) return fail(MSM_ERR_INVALID_ARG, "null batch or workspace");
+  hipError_t e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+  int32_t all = 0;
+  for (int s = 0; s < Bt->n_sys; ++s) {
+    int32_t f = 0;
+    const msm_plan* P = Bt->plans[s];
+    const char* sub = static_cast<const char*>(ws) + Bt->sub_off[s];
+    e = hipMemcpy(&f, sub + P->lay.off[msm::kSecStatus], sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "read status");
+    if (flags_per_system) flags_per_system[s] = f;
+    all |= f;
+  }
+  if (all & msm::kFlagNonFinite) return fail(MSM_ERR_NONFINITE, "non-finite position or charge");
+  if (all & msm::kFlagOutOfBox) return fail(MSM_ERR_OUT_OF_BOX, "atom outside the box");
+  if (all & msm::kFlagCoincident) return fail(MSM_ERR_COINCIDENT, "coincident atoms");
+  return MSM_OK;
+}
+
+msm_status msm_batch_describe(const msm_batch* Bt, char* buf, size_t buf_bytes) {
+  if (!Bt || !buf || buf_bytes == 0) return fail(MSM_ERR_INVALID_ARG, "null batch or buffer");
+  const msm::LaunchGeom& L = Bt->lg;
+  std::string o = "{\"systems\": " + std::to_string(Bt->n_sys) +
+                  ", \"atoms\": " + std::to_string(Bt->total_atoms) +
+                  ", \"max_levels\": " + std::to_string(L.max_levels) +
+                  ", \"lattice_b\": " + std::to_string(L.lat_b) +
+                  ", \"lattice_lds\": " + std::to_string(L.lat_lds) +
+                  ", \"run_w\": " + std::to_string(Bt->plans[0]->g.run_w) +
+                  ", \"blocks\": {\"atoms\": " + std::to_string(L.atoms.blocks) +
+                  ", \"short\": " + std::to_string(L.shortr.blocks) +
+                  ", \"anterp\": " + std::to_string(L.anterp.blocks) +
+                  ", \"lattice\": " + std::to_string(L.lattice.blocks) +
+                  ", \"top\": " + std::to_string(L.top.blocks) + "}, \"levels\": [";
+  for (int s = 0; s < Bt->n_sys; ++s) o += (s ? ", " : "") + std::to_string(Bt->plans[s]->g.levels);
+  o += "], \"workspace_bytes\": " + std::to_string(Bt->total) + "}";
+  std::strncpy(buf, o.c_str(), buf_bytes - 1);
+  buf[buf_bytes - 1] = 0;
+  return o.size() < buf_bytes ? MSM_OK : fail(MSM_ERR_INVALID_ARG, "buffer too small");
+}
+
+// ---------------------------------------------------------------------------
+// Tuning knobs and the autotuner
+// ---------------------------------------------------------------------------
+
+msm_status msm_plan_tune(msm_plan* P, void* ws, size_t ws_bytes, msm_stream_t stream, int32_t lattice_b,
+                         int32_t run_w) {
+  if (!P) return fail(MSM_ERR_INVALID_ARG, "null plan");
+  if (lattice_b != 0 && lattice_b != 4 && lattice_b != 6 && lattice_b != 8)
+    return fail(MSM_ERR_INVALID_ARG, "lattice_b must be 0, 4, 6 or 8");
+  if (run_w < 0) return fail(MSM_ERR_INVALID_ARG, "run_w must be >= 0");
+  if (!ws || ws_bytes < P->lay.total || !P->ready.count(ws))
+    return fail(MSM_ERR_WORKSPACE, "workspace not initialised for this plan");
+  retune(P, lattice_b, run_w);
+  P->desc.d = dev_ptrs(P, ws);
+  // other workspaces now hold stale descriptors
+  P->ready.clear();
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(static_cast<char*>(ws) + P->lay.off[msm::kSecDesc], &P->desc,
+                                sizeof(msm::SysDesc), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "upload descriptor");
+  P->ready.insert(ws);
+  return MSM_OK;
+}
+
+msm_status msm_batch_tune(msm_batch* Bt, void* ws, size_t ws_bytes, msm_stream_t stream,
+                          int32_t lattice_b, int32_t run_w) {
+  msm_status st = check_batch(Bt, ws, ws_bytes);
+  if (st != MSM_OK) return st;
+  if (lattice_b != 0 && lattice_b != 4 && lattice_b != 6 && lattice_b != 8)
+    return fail(MSM_ERR_INVALID_ARG, "lattice_b must be 0, 4, 6 or 8");
+  if (run_w < 0) return fail(MSM_ERR_INVALID_ARG, "run_w must be >= 0");
+  for (msm_plan* P : Bt->plans) retune(P, lattice_b, run_w);
+  rebuild_maps(Bt);
+  Bt->ready.clear();
+  st = upload_tables(Bt, ws, reinterpret_cast<hipStream_t>(stream));
+  if (st != MSM_OK) return st;
+  Bt->ready.insert(ws);
+  return MSM_OK;
+}
+
+// Time each candidate (lattice_b in {4, 6, 8} x run_w in {1, 2, 3}) over
+// `trials` evaluations of the given inputs with HIP events on `stream`, apply
+// the fastest, and describe the search in `report` (JSON, nullable).
+static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm_stream_t stream,
+                           const float* x, const float* y, const float* z, const float* q,
+                           int32_t trials, char* report, size_t report_bytes) {
+  if (trials < 1) return fail(MSM_ERR_INVALID_ARG, "trials must be >= 1");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  if (he != hipSuccess) return hip_fail(he, "create timing events");
+  const bool tiled = batch ? static_cast<msm_batch*>(obj)->lg.lat_b > 0
+                           : static_cast<msm_plan*>(obj)->lat.b > 0;
+  std::vector<int> bs = tiled ? std::vector<int>{4, 6, 8} : std::vector<int>{0};
+  std::string rep = "{\"candidates\": [";
+  float best = 1e30f;
+  int best_b = 0, best_w = 0;
+  msm_status st = MSM_OK;
+  bool first = true;
+  for (int b : bs)
+    for (int w : {1, 2, 3}) {
+      st = batch ? msm_batch_tune(static_cast<msm_batch*>(obj), ws, ws_bytes, stream, b, w)
+                 : msm_plan_tune(static_cast<msm_plan*>(obj), ws, ws_bytes, stream, b, w);
+      if (st != MSM_OK) break;
+      // one warm-up evaluation, then `trials` timed ones
+      for (int t = -1; t < trials && st == MSM_OK; ++t) {
+        if (t == 0) (void)hipEventRecord(e0, s);
+        st = batch ? msm_batch_compute(static_cast<msm_batch*>(obj), ws, ws_bytes, stream, x, y, z, q,
+                                       nullptr, nullptr, nullptr, nullptr, nullptr, nullptr)
+                   : msm_compute(static_cast<msm_plan*>(obj), ws, ws_bytes, stream, x, y, z, q, nullptr,
+                                 nullptr, nullptr, nullptr, nullptr, nullptr);
+      }
+      if (st != MSM_OK) break;
+      (void)hipEventRecord(e1, s);
+      he = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+      if (he != hipSuccess) {
+        st = hip_fail(he, "time candidate");
+        break;
+      }
+      ms /= trials;
+      rep += std::string(first ? "" : ", ") + "{\"lattice_b\": " + std::to_string(b) +
+             ", \"run_w\": " + std::to_string(w) + ", \"ms\": " + std::to_string(ms) + "}";
+      first = false;
+      if (ms < best) {
+        best = ms;
+        best_b = b;
+        best_w = w;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != MSM_OK) return st;
+  st = batch ? msm_batch_tune(static_cast<msm_batch*>(obj), ws, ws_bytes, stream, best_b, best_w)
+             : msm_plan_tune(static_cast<msm_plan*>(obj), ws, ws_bytes, stream, best_b, best_w);
+  if (st != MSM_OK) return st;
+  rep += "], \"best\": {\"lattice_b\": " + std::to_string(best_b) + ", \"run_w\": " +
+         std::to_string(best_w) + ", \"ms\": " + std::to_string(best) + "}}";
+  if (report && report_bytes) {
+    std::strncpy(report, rep.c_str(), report_bytes - 1);
+    report[report_bytes - 1] = 0;
+  }
+  return MSM_OK;
+}
+
+msm_status msm_plan_autotune(msm_plan* P, void* ws, size_t ws_bytes, msm_stream_t stream,
+                             const float* x, const float* y, const float* z, const float* q,
+                             int32_t trials, char* report, size_t report_bytes) {
+  if (!P) return fail(MSM_ERR_INVALID_ARG, "null plan");
+  return autotune(false, P, ws, ws_bytes, stream, x, y, z, q, trials, report, report_bytes);
+}
+
+msm_status msm_batch_autotune(msm_batch* Bt, void* ws, size_t ws_bytes, msm_stream_t stream,
+                              const float* x, const float* y, const float* z, const float* q,
+                              int32_t trials, char* report, size_t report_bytes) {
+  msm_status st = check_batch(Bt, ws, ws_bytes);
+  if (st != MSM_OK) return st;
+  return autotune(true, Bt, ws, ws_bytes, stream, x, y, z, q, trials, report, report_bytes);
+}
+
+}  // extern "C"

@@ -103,6 +103,7 @@ enum Section : int {
   kSecWeightsC,       // float[n_wc]: W(nx, ny, |nz|) for nx = 0..xr per compact row
   kSecTop,            // double[top table]
   kSecPartials,       // double[10 * n_partials]: energy, then 9 virial components
+  kSecDesc,           // SysDesc: this workspace's descriptor (pointers into it)
   kSecCount
 };
 
@@ -139,6 +140,81 @@ enum Stage : int {
   kStageProlong, kStageInterp, kStageReduce, kStageCount
 };
 
+// Everything one system's kernels read, resident in device memory (one entry
+// per system of a batch; a plain plan has one).
+struct SysDesc {
+  Geom g;
+  DevPtrs d;
+  LatLaunch lat;
+  int atom_off;        // first atom of this system in the caller's arrays
+  int index;           // slot of this system's energy, virial (x9) and gradient scale
+  int n_partials;      // float64 partial slots (= interpolation blocks)
+  int n_rows;          // full stencil rows (untiled lattice kernel)
+};
+
+// Caller buffers of one evaluation (kernel arguments): base pointers; a
+// system's atoms start at atom_off and its scalars sit at index.
+struct Io {
+  const float* x;
+  const float* y;
+  const float* z;
+  const float* q;
+  float* fx;
+  float* fy;
+  float* fz;
+  float* phi;
+  double* energy;
+  double* virial;
+  const double* gscale;
+};
+
+// Kernel arguments shared by every stage: the descriptors, an optional
+// block -> (system, block of that system) table for batched launches, and
+// the caller's buffers.
+struct KArgs {
+  const SysDesc* sys;
+  const int2* map;
+  Io io;
+};
+
+__device__ inline const SysDesc& sys_of(const KArgs& a, int& blk) {
+  if (a.map) {
+    const int2 m = a.map[blockIdx.x];
+    blk = m.y;
+    return a.sys[m.x];
+  }
+  blk = blockIdx.x;
+  return a.sys[0];
+}
+
+// Host view of one launch sequence: block counts per stage (summed over the
+// systems of a batch) and the matching block tables (null for one system).
+struct StageGrid {
+  int blocks = 0;
+  const int2* map = nullptr;
+};
+
+struct LaunchGeom {
+  const SysDesc* sys = nullptr;      // device array of n_sys descriptors
+  int n_sys = 1;
+  int order = 4;                     // common to every system of a launch
+  int m = 2;
+  int lat_b = 0;                     // windowed lattice outputs per lane, 0 = untiled kernel
+  int lat_lds = 0;                   // dynamic LDS of the windowed kernel
+  int max_levels = 1;
+  StageGrid zero, atoms, one, shortr, anterp, lattice, top, energy;
+  StageGrid restrict_[kMaxLevels];   // level k -> k+1
+  StageGrid prolong[kMaxLevels];     // level k+1 -> k
+};
+
+// Per-stage block counts of one system.
+struct SysBlocks {
+  int zero, atoms, shortr, anterp, lattice, top, energy;
+  int restrict_[kMaxLevels];
+  int prolong[kMaxLevels];
+};
+SysBlocks system_blocks(const Geom& g, const LatLaunch& lat, int n_partials);
+
 // What one evaluation produces.
 enum Mode : int {
   kModeForces = 0,     // forces, potentials, energy, virial
@@ -146,20 +222,16 @@ enum Mode : int {
   kModeGradient = 2    // gscale * dE/dr into fx..fz, gscale * dE/dq into phi
 };
 
-// Launcher (msm_kernels.hip).  Enqueues one evaluation on `s` and returns the
-// first HIP error.
-// ev (nullable): kStageCount + 1 events recorded at the stage boundaries.
-// aux/fork/join (nullable): run the short-range pass on `aux`, concurrently
-// with the grid chain, joined back before it is needed.
-hipError_t launch_eval(int mode, const Geom& g, const DevPtrs& d, int n_rows, const LatLaunch& lat,
-                       int n_partials, hipStream_t s, const float* x, const float* y,
-                       const float* z, const float* q, float* fx, float* fy, float* fz,
-                       float* phi, double* energy, double* virial, const double* gscale,
-                       hipEvent_t* ev, hipStream_t aux, hipEvent_t fork, hipEvent_t join);
+// Enqueues one evaluation (of every system of L) on `s` and returns the first
+// HIP error.  ev (nullable): kStageCount + 1 events recorded at the stage
+// boundaries.  aux/fork/join (nullable): run the short-range pass on `aux`,
+// concurrently with the grid chain, joined back before it is needed.
+hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& io, hipEvent_t* ev,
+                       hipStream_t aux, hipEvent_t fork, hipEvent_t join);
 
-int interp_partials(const Geom& g);
+int interp_partials(const Geom& g);      // number of FP64 partial slots the forward pass uses
 
 // Workspace initialisation on the device (clears the cell counters).
-hipError_t launch_init(const Geom& g, const DevPtrs& d, hipStream_t s);      // number of FP64 partial slots the forward pass uses
+hipError_t launch_init(const LaunchGeom& L, hipStream_t s);
 
 }  // namespace msm

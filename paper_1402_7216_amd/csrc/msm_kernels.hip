@@ -114,9 +114,11 @@ __device__ __forceinline__ float phi_any(float u) {
 // --------------------------------------------------------------------------
 // Counts are zero on entry: the workspace is initialised that way and k_scan
 // clears them (with the scatter cursors and the status word) after reading.
-__global__ void k_zero_counts(int* __restrict__ counts, int n) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) counts[i] = 0;
+__global__ void k_zero_counts(KArgs A) {
+  int blk;
+  const SysDesc& S = sys_of(A, blk);
+  const int i = blk * blockDim.x + threadIdx.x;
+  if (i <= S.g.n_cells) S.d.counts[i] = 0;
 }
 
 __device__ __forceinline__ int cell_index(const Geom& g, float x, float y, float z) {
@@ -131,21 +133,30 @@ __device__ __forceinline__ int cell_index(const Geom& g, float x, float y, float
   return (c[2] * g.nc[1] + c[1]) * g.nc[0] + c[0];
 }
 
-__global__ void k_bin_count(Geom g, const float* __restrict__ x, const float* __restrict__ y,
-                            const float* __restrict__ z, int* __restrict__ counts,
-                            int* __restrict__ cell_of) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_bin_count(KArgs A) {
+  int blk;
+  const SysDesc& S = sys_of(A, blk);
+  const Geom& g = S.g;
+  const int i = blk * blockDim.x + threadIdx.x;
   if (i >= g.n_atoms) return;
-  int c = cell_index(g, x[i], y[i], z[i]);
-  cell_of[i] = c;
-  atomicAdd(&counts[c], 1);
+  const float* x = A.io.x + S.atom_off;
+  const float* y = A.io.y + S.atom_off;
+  const float* z = A.io.z + S.atom_off;
+  const int c = cell_index(g, x[i], y[i], z[i]);
+  S.d.cell_of[i] = c;
+  atomicAdd(&S.d.counts[c], 1);
 }
 
 // Exclusive scan of counts[0..n) into start[0..n] by one block of 1024
 // threads; then clears counts, cursors and the status word for this call.
-__global__ void __launch_bounds__(1024) k_scan(int* __restrict__ counts, int* __restrict__ start,
-                                               int* __restrict__ cursor, int* __restrict__ status,
-                                               int n) {
+__global__ void __launch_bounds__(1024) k_scan(KArgs A) {
+  int blk;
+  const SysDesc& S = sys_of(A, blk);
+  int* __restrict__ counts = S.d.counts;
+  int* __restrict__ start = S.d.cell_start;
+  int* __restrict__ cursor = S.d.cursor;
+  int* __restrict__ status = S.d.status;
+  const int n = S.g.n_cells;
   __shared__ int part[1024];
   int t = threadIdx.x;
   int chunk = (n + 1023) / 1024;
@@ -174,13 +185,20 @@ __global__ void __launch_bounds__(1024) k_scan(int* __restrict__ counts, int* __
 // Scatter into cell segments in arrival order (atomic cursors); the atom's
 // index and raw coordinates travel together so the next pass reads each
 // segment contiguously.
-__global__ void k_bin_scatter(Geom g, const float* __restrict__ x, const float* __restrict__ y,
-                              const float* __restrict__ z, const float* __restrict__ q,
-                              const int* __restrict__ cell_of, const int* __restrict__ start,
-                              int* __restrict__ cursor, int* __restrict__ tmp,
-                              float4* __restrict__ tmp4) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.n_atoms) return;
+__global__ void k_bin_scatter(KArgs A) {
+  int blk;
+  const SysDesc& S = sys_of(A, blk);
+  const int i = blk * blockDim.x + threadIdx.x;
+  if (i >= S.g.n_atoms) return;
+  const float* x = A.io.x + S.atom_off;
+  const float* y = A.io.y + S.atom_off;
+  const float* z = A.io.z + S.atom_off;
+  const float* q = A.io.q + S.atom_off;
+  const int* __restrict__ cell_of = S.d.cell_of;
+  const int* __restrict__ start = S.d.cell_start;
+  int* __restrict__ cursor = S.d.cursor;
+  int* __restrict__ tmp = S.d.tmp;
+  float4* __restrict__ tmp4 = S.d.fshort;   // coordinate copies until k_bin_place
   const float4 p = make_float4(x[i], y[i], z[i], q[i]);
   const int c = cell_of[i];
   const int slot = start[c] + atomicAdd(&cursor[c], 1);
@@ -193,12 +211,19 @@ __global__ void k_bin_scatter(Geom g, const float* __restrict__ x, const float* 
 // Also validates the input (non-finite, outside the box, coincident atoms) and
 // writes sanitised, box-clamped coordinates so every later kernel stays inside
 // the grid even for bad input.
-__global__ void k_bin_place(Geom g, const int* __restrict__ cell_of, const int* __restrict__ start,
-                            const int* __restrict__ tmp, const float4* __restrict__ tmp4,
-                            float4* __restrict__ sorted, int* __restrict__ perm,
-                            int* __restrict__ status) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_bin_place(KArgs A) {
+  int blk;
+  const SysDesc& S = sys_of(A, blk);
+  const Geom& g = S.g;
+  const int s = blk * blockDim.x + threadIdx.x;
   if (s >= g.n_atoms) return;
+  const int* __restrict__ cell_of = S.d.cell_of;
+  const int* __restrict__ start = S.d.cell_start;
+  const int* __restrict__ tmp = S.d.tmp;
+  const float4* __restrict__ tmp4 = S.d.fshort;
+  float4* __restrict__ sorted = S.d.sorted;
+  int* __restrict__ perm = S.d.perm;
+  int* __restrict__ status = S.d.status;
   const int i = tmp[s];
   const float4 p = tmp4[s];
   const int c = cell_of[i];
@@ -246,15 +271,19 @@ __global__ void k_bin_place(Geom g, const int* __restrict__ cell_of, const int* 
 // order through LDS.
 // --------------------------------------------------------------------------
 template <int M, bool FORCES>
-__global__ void __launch_bounds__(kBlock) k_short(Geom g, const float4* __restrict__ sorted,
-                                                  const int* __restrict__ start,
-                                                  float4* __restrict__ fshort) {
+__global__ void __launch_bounds__(kBlock) k_short(KArgs A) {
+  int blk;
+  const SysDesc& S = sys_of(A, blk);
+  const Geom& g = S.g;
+  const float4* __restrict__ sorted = S.d.sorted;
+  const int* __restrict__ start = S.d.cell_start;
+  float4* __restrict__ fshort = S.d.fshort;
   __shared__ float4 red[kBlock];
   __shared__ float4 jbuf[kBlock / kWave][kWave];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int run = blockIdx.x % g.runs_x;
-  const int row = blockIdx.x / g.runs_x;
+  const int run = blk % g.runs_x;
+  const int row = blk / g.runs_x;
   const int cy = row % g.nc[1], cz = row / g.nc[1];
   const int cx0 = run * g.run_w;
   const int cx1 = min(cx0 + g.run_w, g.nc[0]) - 1;
@@ -263,6 +292,12 @@ __global__ void __launch_bounds__(kBlock) k_short(Geom g, const float4* __restri
   const int R = g.reach, side = 2 * R + 1;
   const int jx0 = max(cx0 - R, 0), jx1 = min(cx1 + R, g.nc[0] - 1);
   const float a2 = g.a2, inv_a2 = g.inv_a2;
+  float gc[M + 1], dc[M + 1];
+#pragma unroll
+  for (int k = 0; k <= M; ++k) {
+    gc[k] = g.gcoef[k];
+    dc[k] = g.dcoef[k];
+  }
   float4* jb_w = jbuf[wave];
 
   for (int ic = ib; ic < ie; ic += kWave) {
@@ -292,11 +327,11 @@ __global__ void __launch_bounds__(kBlock) k_short(Geom g, const float4* __restri
             ri = fmaf(0.5f * ri, fmaf(-r2 * ri, ri, 1.f), ri);
             const float ri2 = ri * ri;
             const float s = r2 * inv_a2;
-            float gm = g.gcoef[M], dg = g.dcoef[M];
+            float gm = gc[M], dg = dc[M];
 #pragma unroll
-            for (int k = M - 1; k >= 0; --k) gm = fmaf(gm, s, g.gcoef[k]);
+            for (int k = M - 1; k >= 0; --k) gm = fmaf(gm, s, gc[k]);
 #pragma unroll
-            for (int k = M - 1; k >= 1; --k) dg = fmaf(dg, s, g.dcoef[k]);
+            for (int k = M - 1; k >= 1; --k) dg = fmaf(dg, s, dc[k]);
             const float gs = ri - gm;                    // g*(r)
             ap = fmaf(pj.w, gs, ap);
             if (FORCES) {
@@ -380,15 +415,19 @@ __device__ __forceinline__ void anterp_atom(const Geom& g, const int* n0, float4
 }
 
 template <int ORDER>
-__global__ void __launch_bounds__(kBlock) k_anterp(Geom g, const float4* __restrict__ sorted,
-                                                   const int* __restrict__ start,
-                                                   float* __restrict__ qgrid) {
+__global__ void __launch_bounds__(kBlock) k_anterp(KArgs A) {
+  int blk;
+  const SysDesc& S = sys_of(A, blk);
+  const Geom& g = S.g;
+  const float4* __restrict__ sorted = S.d.sorted;
+  const int* __restrict__ start = S.d.cell_start;
+  float* __restrict__ qgrid = S.d.qgrid;
   constexpr int H = ORDER / 2;
   __shared__ unsigned long long acc[kAX * kAY * kAZ];
   __shared__ int row_beg[64], row_pre[65];
   const Level L = g.lv[0];
   const int ntx = (L.n[0] + kAX - 1) / kAX, nty = (L.n[1] + kAY - 1) / kAY;
-  const int bx = blockIdx.x % ntx, by = (blockIdx.x / ntx) % nty, bz = blockIdx.x / (ntx * nty);
+  const int bx = blk % ntx, by = (blk / ntx) % nty, bz = blk / (ntx * nty);
   const int n0[3] = {L.lo[0] + bx * kAX, L.lo[1] + by * kAY, L.lo[2] + bz * kAZ};
   const int tdim[3] = {kAX, kAY, kAZ};
   for (int i = threadIdx.x; i < kAX * kAY * kAZ; i += blockDim.x) acc[i] = 0ull;
@@ -486,14 +525,18 @@ struct Dyadic {
 constexpr int kRX = 8, kRY = 8, kRZ = 4;
 
 template <int ORDER>
-__global__ void __launch_bounds__(kBlock) k_restrict(Geom g, int k, float* __restrict__ grid) {
+__global__ void __launch_bounds__(kBlock) k_restrict(KArgs A, int k) {
+  int blk;
+  const SysDesc& S = sys_of(A, blk);
+  const Geom& g = S.g;
+  float* __restrict__ grid = S.d.qgrid;
   using D = Dyadic<ORDER>;
   constexpr int R = D::R;
   constexpr int FX = 2 * kRX - 1 + 2 * R, FY = 2 * kRY - 1 + 2 * R, FZ = 2 * kRZ - 1 + 2 * R;
   __shared__ float fine[FX * FY * FZ];
   const Level F = g.lv[k], C = g.lv[k + 1];
   const int ntx = (C.n[0] + kRX - 1) / kRX, nty = (C.n[1] + kRY - 1) / kRY;
-  const int bx = blockIdx.x % ntx, by = (blockIdx.x / ntx) % nty, bz = blockIdx.x / (ntx * nty);
+  const int bx = blk % ntx, by = (blk / ntx) % nty, bz = blk / (ntx * nty);
   const int c0x = bx * kRX, c0y = by * kRY, c0z = bz * kRZ;          // level-local coarse origin
   // absolute fine index of local fine (0,0,0): 2 (C.lo + c0) - R
   const int f0x = 2 * (C.lo[0] + c0x) - R, f0y = 2 * (C.lo[1] + c0y) - R, f0z = 2 * (C.lo[2] + c0z) - R;
@@ -544,11 +587,17 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Geom g, int k, float* __res
 //   u^{k,cut}_mu = sum_{|n| < 2a/h} g^k(2^k h |n|) q^k_{mu+n} = 2^-k sum W(n) q^k_{mu+n}
 // with W(n) = g^0(h|n|) from the stencil table (rows of taps along z).
 // --------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_lattice(Geom g, const StencilRow* __restrict__ rows,
-                                                    int n_rows, const float* __restrict__ wts,
-                                                    const float* __restrict__ qgrid,
-                                                    float* __restrict__ ucut, int n_lattice_nodes) {
-  int gid = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(kBlock) k_lattice(KArgs A) {
+  int blk;
+  const SysDesc& S = sys_of(A, blk);
+  const Geom& g = S.g;
+  const StencilRow* __restrict__ rows = S.d.rows;
+  const int n_rows = S.n_rows;
+  const float* __restrict__ wts = S.d.weights;
+  const float* __restrict__ qgrid = S.d.qgrid;
+  float* __restrict__ ucut = S.d.ucut;
+  const int n_lattice_nodes = g.lv[g.levels - 1].off;   // every node below the top level
+  int gid = blk * blockDim.x + threadIdx.x;
   if (gid >= n_lattice_nodes) return;
   int k = 0;
   while (k + 1 < g.levels - 1 && gid >= g.lv[k + 1].off) ++k;
@@ -630,16 +679,20 @@ __device__ __forceinline__ void row_win_dispatch(int xr, float* acc, const float
 }
 
 template <int B>
-__global__ void __launch_bounds__(kLatThreads) k_lattice_win(Geom g, LatLaunch P,
-                                                             const int4* __restrict__ rows_g,
-                                                             const float* __restrict__ wc_g,
-                                                             const float* __restrict__ qgrid,
-                                                             float* __restrict__ ucut) {
+__global__ void __launch_bounds__(kLatThreads) k_lattice_win(KArgs A) {
+  int blk;
+  const SysDesc& S = sys_of(A, blk);
+  const Geom& g = S.g;
+  const LatLaunch& P = S.lat;
+  const int4* __restrict__ rows_g = S.d.rows_c;
+  const float* __restrict__ wc_g = S.d.weights_c;
+  const float* __restrict__ qgrid = S.d.qgrid;
+  float* __restrict__ ucut = S.d.ucut;
   extern __shared__ float4 lds4[];
   int4* rows = reinterpret_cast<int4*>(lds4);
   float* wc = reinterpret_cast<float*>(lds4 + P.n_rows);
   float* win = wc + P.n_wc;
-  int bid = blockIdx.x, li = 0;
+  int bid = blk, li = 0;
   while (li + 1 < P.n && bid >= P.t[li + 1].block0) ++li;
   const LatTile T = P.t[li];
   const Level Lv = g.lv[T.level];
@@ -745,11 +798,16 @@ __global__ void __launch_bounds__(kLatThreads) k_lattice_win(Geom g, LatLaunch P
 // --------------------------------------------------------------------------
 // One wave per output node: lanes stride over the input nodes, then a fixed
 // butterfly sums the 64 lane partials.
-__global__ void __launch_bounds__(kBlock) k_top(Geom g, const double* __restrict__ T,
-                                                const float* __restrict__ qgrid,
-                                                float* __restrict__ ucut, float* __restrict__ u) {
+__global__ void __launch_bounds__(kBlock) k_top(KArgs A) {
+  int blk;
+  const SysDesc& S = sys_of(A, blk);
+  const Geom& g = S.g;
+  const double* __restrict__ T = S.d.top;
+  const float* __restrict__ qgrid = S.d.qgrid;
+  float* __restrict__ ucut = S.d.ucut;
+  float* __restrict__ u = S.d.u;
   const Level L = g.lv[g.levels - 1];
-  const int node = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  const int node = __builtin_amdgcn_readfirstlane((blk * blockDim.x + threadIdx.x) / kWave);
   const int lane = threadIdx.x & (kWave - 1);
   if (node >= L.count) return;
   const int mx = node % L.n[0], my = (node / L.n[0]) % L.n[1], mz = node / (L.n[0] * L.n[1]);
@@ -779,15 +837,19 @@ __global__ void __launch_bounds__(kBlock) k_top(Geom g, const double* __restrict
 constexpr int kPX = 8, kPY = 8, kPZ = 4;
 
 template <int ORDER>
-__global__ void __launch_bounds__(kBlock) k_prolong(Geom g, int k, const float* __restrict__ ucut,
-                                                    float* __restrict__ u) {
+__global__ void __launch_bounds__(kBlock) k_prolong(KArgs A, int k) {
+  int blk;
+  const SysDesc& S = sys_of(A, blk);
+  const Geom& g = S.g;
+  const float* __restrict__ ucut = S.d.ucut;
+  float* __restrict__ u = S.d.u;
   using D = Dyadic<ORDER>;
   constexpr int R = D::R;
   constexpr int VX = (kPX - 1 + 2 * R) / 2 + 2, VY = (kPY - 1 + 2 * R) / 2 + 2, VZ = (kPZ - 1 + 2 * R) / 2 + 2;
   __shared__ float cs[VX * VY * VZ];
   const Level F = g.lv[k], C = g.lv[k + 1];
   const int ntx = (F.n[0] + kPX - 1) / kPX, nty = (F.n[1] + kPY - 1) / kPY;
-  const int bx = blockIdx.x % ntx, by = (blockIdx.x / ntx) % nty, bz = blockIdx.x / (ntx * nty);
+  const int bx = blk % ntx, by = (blk / ntx) % nty, bz = blk / (ntx * nty);
   // absolute fine origin of the tile; coarse origin = ceil((m0 - R) / 2)
   const int m0[3] = {F.lo[0] + bx * kPX, F.lo[1] + by * kPY, F.lo[2] + bz * kPZ};
   int v0[3];
@@ -862,18 +924,25 @@ __global__ void __launch_bounds__(kBlock) k_prolong(Geom g, int k, const float* 
 // MODE 1: gradients of the energy scaled by *gscale: fx..fz receive
 //         gscale dE/dr = -gscale F, phi receives gscale dE/dq = gscale phi.
 template <int ORDER, int MODE>
-__global__ void __launch_bounds__(kBlock) k_interp(Geom g, const float4* __restrict__ sorted,
-                                                   const int* __restrict__ perm,
-                                                   const float4* __restrict__ fshort,
-                                                   const float* __restrict__ u,
-                                                   float* __restrict__ fx, float* __restrict__ fy,
-                                                   float* __restrict__ fz, float* __restrict__ phi,
-                                                   double* __restrict__ partials, int n_partials,
-                                                   const double* __restrict__ gscale) {
+__global__ void __launch_bounds__(kBlock) k_interp(KArgs A) {
+  int blk;
+  const SysDesc& S = sys_of(A, blk);
+  const Geom& g = S.g;
+  const float4* __restrict__ sorted = S.d.sorted;
+  const int* __restrict__ perm = S.d.perm;
+  const float4* __restrict__ fshort = S.d.fshort;
+  const float* __restrict__ u = S.d.u;
+  float* __restrict__ fx = A.io.fx ? A.io.fx + S.atom_off : nullptr;
+  float* __restrict__ fy = A.io.fy ? A.io.fy + S.atom_off : nullptr;
+  float* __restrict__ fz = A.io.fz ? A.io.fz + S.atom_off : nullptr;
+  float* __restrict__ phi = A.io.phi ? A.io.phi + S.atom_off : nullptr;
+  double* __restrict__ partials = S.d.partials;
+  const int n_partials = S.n_partials;
+  const double* __restrict__ gscale = A.io.gscale ? A.io.gscale + S.index : nullptr;
   constexpr int H = ORDER / 2;
   __shared__ double red[10][kBlock / kWave];
   const Level L = g.lv[0];
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  int s = blk * blockDim.x + threadIdx.x;
   double e = 0.0, vir[9];
 #pragma unroll
   for (int t = 0; t < 9; ++t) vir[t] = 0.0;
@@ -892,7 +961,7 @@ __global__ void __launch_bounds__(kBlock) k_interp(Geom g, const float4* __restr
     }
     const float* u0 = u + L.off;
     float pl = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
-#pragma unroll
+#pragma unroll 1
     for (int sz = 0; sz < ORDER; ++sz) {
       float py_ = 0.f, gxy = 0.f, gyy = 0.f;
 #pragma unroll
@@ -969,7 +1038,7 @@ __global__ void __launch_bounds__(kBlock) k_interp(Geom g, const float4* __restr
   if (threadIdx.x < 10) {
     double v = 0.0;
     for (int w = 0; w < kBlock / kWave; ++w) v += red[threadIdx.x][w];
-    partials[(size_t)threadIdx.x * n_partials + blockIdx.x] = v;
+    partials[(size_t)threadIdx.x * n_partials + blk] = v;
   }
 }
 
@@ -977,19 +1046,23 @@ __global__ void __launch_bounds__(kBlock) k_interp(Geom g, const float4* __restr
 //   E = 1/2 sum_i q_i phi_i^s + 1/2 sum_k <q^k, u^{k,cut}> - gamma(0)/(2a) sum_i q_i^2,
 // since 1/2 q^0.u^0 = 1/2 sum_k <q^k, u^{k,cut}> when prolongation is the
 // transpose of restriction.  One float64 partial per block.
-__global__ void __launch_bounds__(kBlock) k_energy_terms(Geom g, const float4* __restrict__ sorted,
-                                                         const float4* __restrict__ fshort,
-                                                         const float* __restrict__ qgrid,
-                                                         const float* __restrict__ ucut,
-                                                         double* __restrict__ partials) {
+__global__ void __launch_bounds__(kBlock) k_energy_terms(KArgs A) {
+  int blk;
+  const SysDesc& S = sys_of(A, blk);
+  const Geom& g = S.g;
+  const float4* __restrict__ sorted = S.d.sorted;
+  const float4* __restrict__ fshort = S.d.fshort;
+  const float* __restrict__ qgrid = S.d.qgrid;
+  const float* __restrict__ ucut = S.d.ucut;
+  double* __restrict__ partials = S.d.partials;
   __shared__ double red[kBlock / kWave];
-  const int stride = gridDim.x * blockDim.x;
+  const int stride = S.n_partials * blockDim.x;
   double e = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g.n_atoms; i += stride) {
+  for (int i = blk * blockDim.x + threadIdx.x; i < g.n_atoms; i += stride) {
     const double q = (double)sorted[i].w;
     e += 0.5 * q * ((double)fshort[i].w - q * (double)g.self);
   }
-  for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < g.total_nodes; m += stride)
+  for (int m = blk * blockDim.x + threadIdx.x; m < g.total_nodes; m += stride)
     e += 0.5 * (double)qgrid[m] * (double)ucut[m];
   e *= g.ke;
 #pragma unroll
@@ -1000,15 +1073,19 @@ __global__ void __launch_bounds__(kBlock) k_energy_terms(Geom g, const float4* _
   if (threadIdx.x == 0) {
     double v = 0.0;
     for (int w = 0; w < kBlock / kWave; ++w) v += red[w];
-    partials[blockIdx.x] = v;
+    partials[blk] = v;
   }
 }
 
 // Sum the per-block partials in a fixed order (one block): each thread adds
 // its strided share, then a butterfly per wave and the 4 waves in order.
-__global__ void __launch_bounds__(kBlock) k_reduce(const double* __restrict__ partials, int n_partials,
-                                                   double* __restrict__ energy,
-                                                   double* __restrict__ virial) {
+__global__ void __launch_bounds__(kBlock) k_reduce(KArgs A, int with_virial) {
+  int blk;
+  const SysDesc& S = sys_of(A, blk);
+  const double* __restrict__ partials = S.d.partials;
+  const int n_partials = S.g.n_atoms > 0 ? S.n_partials : 0;
+  double* __restrict__ energy = A.io.energy ? A.io.energy + S.index : nullptr;
+  double* __restrict__ virial = (with_virial && A.io.virial) ? A.io.virial + 9 * (size_t)S.index : nullptr;
   __shared__ double red[10][kBlock / kWave];
   double acc[10];
 #pragma unroll
@@ -1047,48 +1124,69 @@ inline int blocks_for(int n, int b = kBlock) { return (n + b - 1) / b; }
 
 int interp_partials(const Geom& g) { return std::max(1, blocks_for(g.n_atoms)); }
 
-hipError_t launch_init(const Geom& g, const DevPtrs& d, hipStream_t s) {
-  k_zero_counts<<<blocks_for(g.n_cells + 1), kBlock, 0, s>>>(d.counts, g.n_cells + 1);
+SysBlocks system_blocks(const Geom& g, const LatLaunch& lat, int n_partials) {
+  SysBlocks b{};
+  b.zero = blocks_for(g.n_cells + 1);
+  b.atoms = g.n_atoms > 0 ? blocks_for(g.n_atoms) : 0;
+  b.shortr = g.n_atoms > 0 ? g.runs_x * g.nc[1] * g.nc[2] : 0;
+  const Level& L0 = g.lv[0];
+  b.anterp = ((L0.n[0] + kAX - 1) / kAX) * ((L0.n[1] + kAY - 1) / kAY) * ((L0.n[2] + kAZ - 1) / kAZ);
+  for (int k = 0; k + 1 < g.levels; ++k) {
+    const Level& C = g.lv[k + 1];
+    b.restrict_[k] = ((C.n[0] + kRX - 1) / kRX) * ((C.n[1] + kRY - 1) / kRY) * ((C.n[2] + kRZ - 1) / kRZ);
+    const Level& F = g.lv[k];
+    b.prolong[k] = ((F.n[0] + kPX - 1) / kPX) * ((F.n[1] + kPY - 1) / kPY) * ((F.n[2] + kPZ - 1) / kPZ);
+  }
+  if (g.levels > 1) {
+    if (lat.b > 0)
+      b.lattice = lat.t[lat.n - 1].block0 + lat.t[lat.n - 1].ntx * lat.t[lat.n - 1].nty * lat.t[lat.n - 1].ntz;
+    else
+      b.lattice = blocks_for(g.lv[g.levels - 1].off);
+  }
+  b.top = blocks_for(g.lv[g.levels - 1].count * kWave);
+  b.energy = n_partials;
+  return b;
+}
+
+hipError_t launch_init(const LaunchGeom& L, hipStream_t s) {
+  if (L.zero.blocks > 0) k_zero_counts<<<L.zero.blocks, kBlock, 0, s>>>(KArgs{L.sys, L.zero.map, Io{}});
   return hipGetLastError();
 }
 
-hipError_t launch_eval(int mode, const Geom& g, const DevPtrs& d, int n_rows, const LatLaunch& lat,
-                       int n_partials, hipStream_t s, const float* x, const float* y,
-                       const float* z, const float* q, float* fx, float* fy, float* fz,
-                       float* phi, double* energy, double* virial, const double* gscale,
-                       hipEvent_t* ev, hipStream_t aux, hipEvent_t fork, hipEvent_t join) {
-  const int n = g.n_atoms;
+hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& io, hipEvent_t* ev,
+                       hipStream_t aux, hipEvent_t fork, hipEvent_t join) {
   const bool forces = (mode != kModeEnergy);
+  auto args = [&](const StageGrid& sg) { return KArgs{L.sys, sg.map, io}; };
   auto mark = [&](int stage) {
     if (ev) (void)hipEventRecord(ev[stage], s);
   };
   mark(kStageBin);
-  const bool par = (n > 0 && aux != nullptr && ev == nullptr);
-  if (n > 0) {
-    k_bin_count<<<blocks_for(n), kBlock, 0, s>>>(g, x, y, z, d.counts, d.cell_of);
-    k_scan<<<1, 1024, 0, s>>>(d.counts, d.cell_start, d.cursor, d.status, g.n_cells);
-    // the scatter's coordinate copies live in the short-range output buffer
-    // until k_bin_place has consumed them
-    k_bin_scatter<<<blocks_for(n), kBlock, 0, s>>>(g, x, y, z, q, d.cell_of, d.cell_start, d.cursor,
-                                                   d.tmp, d.fshort);
-    k_bin_place<<<blocks_for(n), kBlock, 0, s>>>(g, d.cell_of, d.cell_start, d.tmp, d.fshort,
-                                                 d.sorted, d.perm, d.status);
-    mark(kStageShort);
+  const bool have_atoms = L.atoms.blocks > 0;
+  const bool par = (have_atoms && aux != nullptr && ev == nullptr);
+  if (have_atoms) k_bin_count<<<L.atoms.blocks, kBlock, 0, s>>>(args(L.atoms));
+  k_scan<<<L.one.blocks, 1024, 0, s>>>(args(L.one));
+  if (have_atoms) {
+    k_bin_scatter<<<L.atoms.blocks, kBlock, 0, s>>>(args(L.atoms));
+    k_bin_place<<<L.atoms.blocks, kBlock, 0, s>>>(args(L.atoms));
+  }
+  mark(kStageShort);
+  if (have_atoms && L.shortr.blocks > 0) {
     hipStream_t ss = s;
     if (par) {
       (void)hipEventRecord(fork, s);
       (void)hipStreamWaitEvent(aux, fork, 0);
       ss = aux;
     }
-    const int items = g.runs_x * g.nc[1] * g.nc[2];
-#define MSM_SHORT(MM)                                                                          \
-  do {                                                                                         \
-    if (forces)                                                                                \
-      k_short<MM, true><<<items, kBlock, 0, ss>>>(g, d.sorted, d.cell_start, d.fshort);        \
-    else                                                                                       \
-      k_short<MM, false><<<items, kBlock, 0, ss>>>(g, d.sorted, d.cell_start, d.fshort);       \
+    const KArgs A = args(L.shortr);
+    const int nb = L.shortr.blocks;
+#define MSM_SHORT(MM)                                               \
+  do {                                                              \
+    if (forces)                                                     \
+      k_short<MM, true><<<nb, kBlock, 0, ss>>>(A);                  \
+    else                                                            \
+      k_short<MM, false><<<nb, kBlock, 0, ss>>>(A);                 \
   } while (0)
-    switch (g.m) {
+    switch (L.m) {
       case 1: MSM_SHORT(1); break;
       case 2: MSM_SHORT(2); break;
       case 3: MSM_SHORT(3); break;
@@ -1099,98 +1197,80 @@ hipError_t launch_eval(int mode, const Geom& g, const DevPtrs& d, int n_rows, co
     }
 #undef MSM_SHORT
     if (par) (void)hipEventRecord(join, aux);
-  } else {
-    k_scan<<<1, 1024, 0, s>>>(d.counts, d.cell_start, d.cursor, d.status, g.n_cells);
-    mark(kStageShort);
   }
   mark(kStageAnterp);
-  const Level& L0 = g.lv[0];
-  const int ant_blocks = ((L0.n[0] + kAX - 1) / kAX) * ((L0.n[1] + kAY - 1) / kAY) *
-                         ((L0.n[2] + kAZ - 1) / kAZ);
-  if (g.order == 4)
-    k_anterp<4><<<ant_blocks, kBlock, 0, s>>>(g, d.sorted, d.cell_start, d.qgrid);
+  if (L.order == 4)
+    k_anterp<4><<<L.anterp.blocks, kBlock, 0, s>>>(args(L.anterp));
   else
-    k_anterp<6><<<ant_blocks, kBlock, 0, s>>>(g, d.sorted, d.cell_start, d.qgrid);
+    k_anterp<6><<<L.anterp.blocks, kBlock, 0, s>>>(args(L.anterp));
   mark(kStageRestrict);
-  for (int k = 0; k + 1 < g.levels; ++k) {
-    const Level& C = g.lv[k + 1];
-    const int nb = ((C.n[0] + kRX - 1) / kRX) * ((C.n[1] + kRY - 1) / kRY) * ((C.n[2] + kRZ - 1) / kRZ);
-    if (g.order == 4)
-      k_restrict<4><<<nb, kBlock, 0, s>>>(g, k, d.qgrid);
+  for (int k = 0; k + 1 < L.max_levels; ++k) {
+    const StageGrid& sg = L.restrict_[k];
+    if (sg.blocks == 0) continue;
+    if (L.order == 4)
+      k_restrict<4><<<sg.blocks, kBlock, 0, s>>>(args(sg), k);
     else
-      k_restrict<6><<<nb, kBlock, 0, s>>>(g, k, d.qgrid);
+      k_restrict<6><<<sg.blocks, kBlock, 0, s>>>(args(sg), k);
   }
   mark(kStageLattice);
-  if (g.levels > 1) {
-    if (lat.b > 0) {
-      const int nblk = lat.t[lat.n - 1].block0 + lat.t[lat.n - 1].ntx * lat.t[lat.n - 1].nty *
-                                                     lat.t[lat.n - 1].ntz;
-      if (lat.b == 4) {
-        (void)hipFuncSetAttribute((const void*)k_lattice_win<4>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, lat.lds_bytes);
-        k_lattice_win<4><<<nblk, kLatThreads, lat.lds_bytes, s>>>(g, lat, d.rows_c, d.weights_c,
-                                                                 d.qgrid, d.ucut);
-      } else if (lat.b == 6) {
-        (void)hipFuncSetAttribute((const void*)k_lattice_win<6>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, lat.lds_bytes);
-        k_lattice_win<6><<<nblk, kLatThreads, lat.lds_bytes, s>>>(g, lat, d.rows_c, d.weights_c,
-                                                                 d.qgrid, d.ucut);
-      } else {
-        (void)hipFuncSetAttribute((const void*)k_lattice_win<8>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, lat.lds_bytes);
-        k_lattice_win<8><<<nblk, kLatThreads, lat.lds_bytes, s>>>(g, lat, d.rows_c, d.weights_c,
-                                                                 d.qgrid, d.ucut);
-      }
+  if (L.lattice.blocks > 0) {
+    const KArgs A = args(L.lattice);
+    const int nb = L.lattice.blocks;
+    if (L.lat_b == 4) {
+      (void)hipFuncSetAttribute((const void*)k_lattice_win<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                L.lat_lds);
+      k_lattice_win<4><<<nb, kLatThreads, L.lat_lds, s>>>(A);
+    } else if (L.lat_b == 6) {
+      (void)hipFuncSetAttribute((const void*)k_lattice_win<6>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                L.lat_lds);
+      k_lattice_win<6><<<nb, kLatThreads, L.lat_lds, s>>>(A);
+    } else if (L.lat_b == 8) {
+      (void)hipFuncSetAttribute((const void*)k_lattice_win<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                L.lat_lds);
+      k_lattice_win<8><<<nb, kLatThreads, L.lat_lds, s>>>(A);
     } else {
-      int n_lat = g.lv[g.levels - 1].off;   // every node below the top level
-      k_lattice<<<blocks_for(n_lat), kBlock, 0, s>>>(g, d.rows, n_rows, d.weights, d.qgrid, d.ucut,
-                                                     n_lat);
+      k_lattice<<<nb, kBlock, 0, s>>>(A);
     }
   }
   mark(kStageTop);
-  k_top<<<blocks_for(g.lv[g.levels - 1].count * kWave), kBlock, 0, s>>>(g, d.top, d.qgrid, d.ucut, d.u);
+  k_top<<<L.top.blocks, kBlock, 0, s>>>(args(L.top));
   mark(kStageProlong);
   if (mode == kModeEnergy) {
     mark(kStageInterp);
     if (par) (void)hipStreamWaitEvent(s, join, 0);
     mark(kStageReduce);
-    k_energy_terms<<<n_partials, kBlock, 0, s>>>(g, d.sorted, d.fshort, d.qgrid, d.ucut, d.partials);
-    k_reduce<<<1, kBlock, 0, s>>>(d.partials, n_partials, energy, nullptr);
+    k_energy_terms<<<L.energy.blocks, kBlock, 0, s>>>(args(L.energy));
+    k_reduce<<<L.one.blocks, kBlock, 0, s>>>(args(L.one), 0);
     mark(kStageCount);
     return hipGetLastError();
   }
-  for (int k = g.levels - 2; k >= 0; --k) {
-    const Level& F = g.lv[k];
-    const int nb = ((F.n[0] + kPX - 1) / kPX) * ((F.n[1] + kPY - 1) / kPY) * ((F.n[2] + kPZ - 1) / kPZ);
-    if (g.order == 4)
-      k_prolong<4><<<nb, kBlock, 0, s>>>(g, k, d.ucut, d.u);
+  for (int k = L.max_levels - 2; k >= 0; --k) {
+    const StageGrid& sg = L.prolong[k];
+    if (sg.blocks == 0) continue;
+    if (L.order == 4)
+      k_prolong<4><<<sg.blocks, kBlock, 0, s>>>(args(sg), k);
     else
-      k_prolong<6><<<nb, kBlock, 0, s>>>(g, k, d.ucut, d.u);
+      k_prolong<6><<<sg.blocks, kBlock, 0, s>>>(args(sg), k);
   }
   mark(kStageInterp);
-  if (n > 0) {
+  if (have_atoms) {
     if (par) (void)hipStreamWaitEvent(s, join, 0);
+    const KArgs A = args(L.atoms);
+    const int nb = L.atoms.blocks;
     if (mode == kModeGradient) {
-      if (g.order == 4)
-        k_interp<4, 1><<<blocks_for(n), kBlock, 0, s>>>(g, d.sorted, d.perm, d.fshort, d.u, fx, fy, fz,
-                                                        phi, d.partials, n_partials, gscale);
+      if (L.order == 4)
+        k_interp<4, 1><<<nb, kBlock, 0, s>>>(A);
       else
-        k_interp<6, 1><<<blocks_for(n), kBlock, 0, s>>>(g, d.sorted, d.perm, d.fshort, d.u, fx, fy, fz,
-                                                        phi, d.partials, n_partials, gscale);
+        k_interp<6, 1><<<nb, kBlock, 0, s>>>(A);
     } else {
-      if (g.order == 4)
-        k_interp<4, 0><<<blocks_for(n), kBlock, 0, s>>>(g, d.sorted, d.perm, d.fshort, d.u, fx, fy, fz,
-                                                        phi, d.partials, n_partials, nullptr);
+      if (L.order == 4)
+        k_interp<4, 0><<<nb, kBlock, 0, s>>>(A);
       else
-        k_interp<6, 0><<<blocks_for(n), kBlock, 0, s>>>(g, d.sorted, d.perm, d.fshort, d.u, fx, fy, fz,
-                                                        phi, d.partials, n_partials, nullptr);
+        k_interp<6, 0><<<nb, kBlock, 0, s>>>(A);
     }
   }
   mark(kStageReduce);
-  if (mode == kModeForces && (energy || virial)) {
-    // with no atoms there are no partials and k_reduce writes zeros
-    k_reduce<<<1, kBlock, 0, s>>>(d.partials, n > 0 ? n_partials : 0, energy, virial);
-  }
+  if (mode == kModeForces && (io.energy || io.virial)) k_reduce<<<L.one.blocks, kBlock, 0, s>>>(args(L.one), 1);
   mark(kStageCount);
   return hipGetLastError();
 }

@@ -1,0 +1,91 @@
+// Host-side state of libmsm shared by the single-system API (msm_api.hip) and
+// the batch API (msm_batch.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <set>
+#include <string>
+#include <vector>
+
+#include "msm_internal.hpp"
+
+using msm::Geom;
+using msm::Layout;
+
+// Auxiliary stream and fork/join events for the concurrent short-range pass.
+struct AuxStreams {
+  hipStream_t stream = nullptr;
+  hipEvent_t fork = nullptr;
+  hipEvent_t join = nullptr;
+  int device = -1;
+};
+
+struct msm_plan {
+  msm_params p;
+  Geom g;
+  std::vector<msm::StencilRow> rows;         // full stencil rows (untiled lattice kernel)
+  std::vector<int4> rows_c;                  // compact rows of the windowed kernel
+  std::vector<float> weights_c;              // compact weights of the windowed kernel
+  std::vector<float> weights;                // full stencil weights
+  std::vector<double> top;                   // FP64 top-level kernel table
+  int n_partials = 1;
+  msm::LatLaunch lat;
+  int lat_tables = 0;                        // LDS bytes of the compact stencil tables
+  Layout lay;
+  msm::SysDesc desc;                         // host copy; device pointers filled per workspace
+  msm::LaunchGeom lg;                        // stage grids of one evaluation (descriptor set per call)
+  std::set<const void*> ready;               // workspaces initialised for this plan
+  // optional stage timing (diagnostics); mutable state of an otherwise fixed plan
+  bool profile = false;
+  hipEvent_t ev[msm::kStageCount + 1] = {};
+  AuxStreams aux;
+};
+
+struct msm_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+msm_status fail(msm_status s, const std::string& msg);
+msm_status hip_fail(hipError_t e, const char* what);
+hipError_t ensure_aux(AuxStreams& a);
+void destroy_aux(AuxStreams& a);
+
+// Device pointers of a workspace's sections.
+msm::DevPtrs dev_ptrs(const msm_plan* P, void* ws);
+// Recompute the host descriptor and stage grids after a tuning change.
+void refresh_launch(msm_plan* P);
+// Apply tuning knobs (0 keeps the current value): lattice outputs per lane
+// (4, 6 or 8) and short-range cells per work item.  Host-side only; the
+// caller re-uploads descriptors.
+void retune(msm_plan* P, int lat_b, int run_w);
+// Capture the work `launch` enqueues on a private stream into an instantiated graph.
+template <class F>
+msm_status capture_graph(F launch, msm_graph** out) {
+  *out = nullptr;
+  msm_graph* G = new (std::nothrow) msm_graph();
+  if (!G) return fail(MSM_ERR_INVALID_ARG, "out of host memory");
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete G;
+    return hip_fail(e, "create capture stream");
+  }
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t le = launch(cs);
+    e = hipStreamEndCapture(cs, &G->graph);
+    if (le != hipSuccess) e = le;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) {
+    if (G->exec) (void)hipGraphExecDestroy(G->exec);
+    if (G->graph) (void)hipGraphDestroy(G->graph);
+    delete G;
+    return hip_fail(e, "capture evaluation graph");
+  }
+  *out = G;
+  return MSM_OK;
+}

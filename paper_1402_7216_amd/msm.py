@@ -9,6 +9,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -25,7 +26,12 @@ EXPORTS = ("msm_plan_create", "msm_plan_destroy", "msm_plan_info", "msm_plan_des
            "msm_workspace_init", "msm_compute", "msm_energy", "msm_backward", "msm_status_query",
            "msm_workspace_section",
            "msm_profile_enable", "msm_profile_read", "msm_graph_capture", "msm_graph_launch",
-           "msm_graph_destroy", "msm_status_string", "msm_last_error")
+           "msm_graph_destroy", "msm_plan_tune", "msm_plan_autotune",
+           "msm_batch_create", "msm_batch_destroy", "msm_batch_workspace_bytes",
+           "msm_batch_atom_offsets", "msm_batch_workspace_init", "msm_batch_compute",
+           "msm_batch_energy", "msm_batch_backward", "msm_batch_graph_capture", "msm_batch_status",
+           "msm_batch_describe", "msm_batch_tune", "msm_batch_autotune",
+           "msm_status_string", "msm_last_error")
 
 STAGES = ("binning", "short_range", "anterpolation", "restriction", "lattice_cutoff", "top_level",
           "prolongation", "interpolation", "reduction")
@@ -72,6 +78,21 @@ def lib():
         L.msm_graph_capture.argtypes = [vp, vp, sz] + [vp] * 10 + [ctypes.POINTER(vp)]
         L.msm_graph_launch.argtypes = [vp, vp]
         L.msm_graph_destroy.argtypes = [vp]
+        L.msm_plan_tune.argtypes = [vp, vp, sz, vp, i32, i32]
+        L.msm_plan_autotune.argtypes = [vp, vp, sz, vp] + [vp] * 4 + [i32, ctypes.c_char_p, sz]
+        L.msm_batch_create.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(i32), i32, ctypes.POINTER(vp)]
+        L.msm_batch_destroy.argtypes = [vp]
+        L.msm_batch_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+        L.msm_batch_atom_offsets.argtypes = [vp, ctypes.POINTER(i32)]
+        L.msm_batch_workspace_init.argtypes = [vp, vp, sz, vp]
+        L.msm_batch_compute.argtypes = [vp, vp, sz, vp] + [vp] * 10
+        L.msm_batch_energy.argtypes = [vp, vp, sz, vp] + [vp] * 5
+        L.msm_batch_backward.argtypes = [vp, vp, sz, vp] + [vp] * 9
+        L.msm_batch_graph_capture.argtypes = [vp, vp, sz] + [vp] * 10 + [ctypes.POINTER(vp)]
+        L.msm_batch_status.argtypes = [vp, vp, vp, ctypes.POINTER(i32)]
+        L.msm_batch_describe.argtypes = [vp, ctypes.c_char_p, sz]
+        L.msm_batch_tune.argtypes = [vp, vp, sz, vp, i32, i32]
+        L.msm_batch_autotune.argtypes = [vp, vp, sz, vp] + [vp] * 4 + [i32, ctypes.c_char_p, sz]
         L.msm_status_string.argtypes = [i32]
         L.msm_status_string.restype = ctypes.c_char_p
         L.msm_last_error.argtypes = []
@@ -190,6 +211,19 @@ class Plan:
                                   _ptr(z), _ptr(q), _ptr(g), _ptr(dx), _ptr(dy), _ptr(dz), _ptr(dq)))
         return dpos, dq
 
+    def tune(self, lattice_b=0, run_w=0):
+        _check(lib().msm_plan_tune(self._h, _ptr(self.ws), self.ws.numel(), _stream(), int(lattice_b),
+                                   int(run_w)))
+
+    def autotune(self, x, y, z, q, trials=5):
+        """Time the tuning candidates on these inputs, keep the fastest, return the search."""
+        import json
+        self._check_inputs(x, y, z, q)
+        buf = ctypes.create_string_buffer(1 << 14)
+        _check(lib().msm_plan_autotune(self._h, _ptr(self.ws), self.ws.numel(), _stream(), _ptr(x),
+                                       _ptr(y), _ptr(z), _ptr(q), int(trials), buf, len(buf)))
+        return json.loads(buf.value.decode())
+
     def status(self):
         """Synchronise and return (status code, raw device flags) of the last evaluation."""
         flags = ctypes.c_int32()
@@ -275,6 +309,167 @@ class MSMEnergy(torch.autograd.Function):
 def energy(plan, pos, q):
     """Differentiable MSM energy (see MSMEnergy)."""
     return MSMEnergy.apply(pos, q, plan)
+
+
+class Batch:
+    """n_sys independent systems evaluated together (one launch per stage).
+
+    systems: list of parameter dicts (cutoff, spacing, order, split_m, levels,
+    box_lo, box_len[, coulomb_k]) and n_atoms: list of atom counts.  Inputs and
+    per-atom outputs are the systems' arrays concatenated in order."""
+
+    def __init__(self, systems, n_atoms, device="cuda"):
+        self.n_sys = len(systems)
+        arr = (Params * self.n_sys)()
+        for i, prm in enumerate(systems):
+            arr[i] = make_params(**prm)
+        na = (ctypes.c_int32 * self.n_sys)(*[int(v) for v in n_atoms])
+        h = ctypes.c_void_p()
+        _check(lib().msm_batch_create(arr, na, self.n_sys, ctypes.byref(h)))
+        self._h = h
+        offs = (ctypes.c_int32 * (self.n_sys + 1))()
+        _check(lib().msm_batch_atom_offsets(self._h, offs))
+        self.offsets = list(offs)
+        self.n = self.offsets[-1]
+        nb = ctypes.c_size_t()
+        _check(lib().msm_batch_workspace_bytes(self._h, ctypes.byref(nb)))
+        self.ws = torch.empty(int(nb.value), dtype=torch.uint8, device=device)
+        _check(lib().msm_batch_workspace_init(self._h, _ptr(self.ws), self.ws.numel(), _stream()))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.msm_batch_destroy(h)
+            self._h = None
+
+    def _check_inputs(self, x, y, z, q):
+        dev = self.ws.device
+        for t in (x, y, z, q):
+            if t.dtype != torch.float32 or t.device != dev or not t.is_contiguous() or t.numel() != self.n:
+                raise ValueError("x, y, z, q must be contiguous float32 device tensors of the batch's length")
+
+    def describe(self):
+        import json
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(lib().msm_batch_describe(self._h, buf, len(buf)))
+        return json.loads(buf.value.decode())
+
+    def outputs(self, virial=False):
+        dev = self.ws.device
+        o = {"energy": torch.empty(self.n_sys, dtype=torch.float64, device=dev),
+             "f": torch.empty((3, self.n), dtype=torch.float32, device=dev),
+             "phi": torch.empty(self.n, dtype=torch.float32, device=dev)}
+        if virial:
+            o["virial"] = torch.empty((self.n_sys, 9), dtype=torch.float64, device=dev)
+        return o
+
+    def compute(self, x, y, z, q, out=None, virial=False):
+        self._check_inputs(x, y, z, q)
+        o = out if out is not None else self.outputs(virial)
+        f = o["f"]
+        _check(lib().msm_batch_compute(self._h, _ptr(self.ws), self.ws.numel(), _stream(), _ptr(x), _ptr(y),
+                                       _ptr(z), _ptr(q), _ptr(f[0]), _ptr(f[1]), _ptr(f[2]), _ptr(o["phi"]),
+                                       _ptr(o["energy"]), _ptr(o.get("virial"))))
+        return o
+
+    def energy(self, x, y, z, q):
+        self._check_inputs(x, y, z, q)
+        e = torch.empty(self.n_sys, dtype=torch.float64, device=self.ws.device)
+        _check(lib().msm_batch_energy(self._h, _ptr(self.ws), self.ws.numel(), _stream(), _ptr(x), _ptr(y),
+                                      _ptr(z), _ptr(q), _ptr(e)))
+        return e
+
+    def backward(self, x, y, z, q, grad_energy, dpos=None, dq=None):
+        self._check_inputs(x, y, z, q)
+        g = grad_energy.reshape(self.n_sys).to(device=self.ws.device, dtype=torch.float64).contiguous()
+        dx, dy, dz = (dpos[0], dpos[1], dpos[2]) if dpos is not None else (None, None, None)
+        _check(lib().msm_batch_backward(self._h, _ptr(self.ws), self.ws.numel(), _stream(), _ptr(x), _ptr(y),
+                                        _ptr(z), _ptr(q), _ptr(g), _ptr(dx), _ptr(dy), _ptr(dz), _ptr(dq)))
+        return dpos, dq
+
+    def graph(self, x, y, z, q, out):
+        return _BatchGraph(self, x, y, z, q, out)
+
+    def status(self):
+        flags = (ctypes.c_int32 * self.n_sys)()
+        code = lib().msm_batch_status(self._h, _ptr(self.ws), _stream(), flags)
+        return code, list(flags)
+
+    def check(self):
+        code, _ = self.status()
+        _check(code)
+
+    def tune(self, lattice_b=0, run_w=0):
+        _check(lib().msm_batch_tune(self._h, _ptr(self.ws), self.ws.numel(), _stream(), int(lattice_b),
+                                    int(run_w)))
+
+    def autotune(self, x, y, z, q, trials=3):
+        import json
+        self._check_inputs(x, y, z, q)
+        buf = ctypes.create_string_buffer(1 << 14)
+        _check(lib().msm_batch_autotune(self._h, _ptr(self.ws), self.ws.numel(), _stream(), _ptr(x), _ptr(y),
+                                        _ptr(z), _ptr(q), int(trials), buf, len(buf)))
+        return json.loads(buf.value.decode())
+
+
+class _BatchGraph:
+    def __init__(self, batch, x, y, z, q, out):
+        self.keep = (batch, x, y, z, q, out)
+        f = out["f"]
+        h = ctypes.c_void_p()
+        _check(lib().msm_batch_graph_capture(batch._h, _ptr(batch.ws), batch.ws.numel(), _ptr(x), _ptr(y),
+                                             _ptr(z), _ptr(q), _ptr(f[0]), _ptr(f[1]), _ptr(f[2]),
+                                             _ptr(out["phi"]), _ptr(out["energy"]), _ptr(out.get("virial")),
+                                             ctypes.byref(h)))
+        self._h = h
+
+    def launch(self):
+        _check(lib().msm_graph_launch(self._h, _stream()))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.msm_graph_destroy(h)
+            self._h = None
+
+
+class MSMBatchEnergy(torch.autograd.Function):
+    """Per-system energies [n_sys] of a batch, with a hand-written backward
+    (incoming gradient [n_sys] read on the device)."""
+
+    @staticmethod
+    def forward(ctx, pos, q, batch):
+        pos = pos.contiguous()
+        q = q.contiguous()
+        e = batch.energy(pos[0], pos[1], pos[2], q)
+        ctx.batch = batch
+        ctx.save_for_backward(pos, q)
+        return e
+
+    @staticmethod
+    def backward(ctx, grad):
+        pos, q = ctx.saved_tensors
+        need_pos, need_q = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        dpos = torch.empty_like(pos) if need_pos else None
+        dq = torch.empty_like(q) if need_q else None
+        if need_pos or need_q:
+            ctx.batch.backward(pos[0], pos[1], pos[2], q, grad.detach(), dpos, dq)
+        return dpos, dq, None
+
+
+def batch_energy(batch, pos, q):
+    """Differentiable per-system energies of a batch (see MSMBatchEnergy)."""
+    return MSMBatchEnergy.apply(pos, q, batch)
+
+
+def batch_for(systems, device="cuda") -> Batch:
+    """Batch for a list of inputs.System."""
+    return Batch([{**s.params(), "split_m": s.split_m} for s in systems], [s.n for s in systems], device)
+
+
+def batch_to_device(systems, device="cuda"):
+    cat = lambda name: torch.from_numpy(np.concatenate([getattr(s, name) for s in systems])).to(device)
+    return cat("x"), cat("y"), cat("z"), cat("q")
 
 
 def plan_for(system, device="cuda") -> Plan:

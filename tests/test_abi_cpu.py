@@ -2,6 +2,7 @@
 entry point, and its host-side planning agrees with the oracle's grid layout.
 No compute call is made (no GPU here)."""
 import ctypes
+import json
 import os
 import re
 
@@ -117,3 +118,57 @@ def test_named_workload_generators_are_deterministic():
     sizes = inputs.batch_sizes()
     assert len(sizes) == 64 and min(sizes) >= 2000 and max(sizes) <= 60000
     assert all(s % 3 == 0 for s in sizes)
+
+
+def _batch(M, systems, n_atoms):
+    arr = (M.Params * len(systems))()
+    for i, prm in enumerate(systems):
+        arr[i] = M.make_params(**prm)
+    na = (ctypes.c_int32 * len(systems))(*n_atoms)
+    h = ctypes.c_void_p()
+    code = M.lib().msm_batch_create(arr, na, len(systems), ctypes.byref(h))
+    return code, h
+
+
+def test_batch_plan_describes_replicas_without_device(M):
+    """Creating a batch is host work: per-system plans, one stage table per
+    launch covering every system, atom offsets and one workspace size."""
+    reps = inputs.water_replicas(64)
+    code, h = _batch(M, [{**s.params()} for s in reps], [s.n for s in reps])
+    assert code == 0, M.lib().msm_last_error()
+    try:
+        offs = (ctypes.c_int32 * 65)()
+        assert M.lib().msm_batch_atom_offsets(h, offs) == 0
+        assert list(offs) == [0] + list(np.cumsum([s.n for s in reps]))
+        buf = ctypes.create_string_buffer(1 << 16)
+        assert M.lib().msm_batch_describe(h, buf, len(buf)) == 0
+        d = json.loads(buf.value.decode())
+        assert d["systems"] == 64 and d["atoms"] == offs[64]
+        # each system's level count is its own automatic choice
+        for s, lv in zip(reps, d["levels"]):
+            c1, p = _plan(M, s.n, **s.params())
+            nl = ctypes.c_int32()
+            lo = (ctypes.c_int32 * 48)()
+            nn = (ctypes.c_int32 * 48)()
+            assert M.lib().msm_plan_info(p, ctypes.byref(nl), lo, nn) == 0
+            M.lib().msm_plan_destroy(p)
+            assert nl.value == lv
+        nb = ctypes.c_size_t()
+        assert M.lib().msm_batch_workspace_bytes(h, ctypes.byref(nb)) == 0
+        assert nb.value >= d["workspace_bytes"] > 0
+        # uninitialised workspaces are refused before any device work
+        assert M.lib().msm_batch_compute(h, ctypes.c_void_p(256), nb.value, None, *([None] * 10)) == -4
+        assert M.lib().msm_batch_tune(h, ctypes.c_void_p(256), nb.value, None, 4, 1) == -4
+    finally:
+        M.lib().msm_batch_destroy(h)
+
+
+def test_batch_rejects_mixed_order_and_bad_sizes(M):
+    p4 = dict(CASES[0])
+    p6 = {**p4, "order": 6}
+    code, h = _batch(M, [p4, p6], [10, 10])
+    assert code == -6 and not h.value
+    code, h = _batch(M, [p4, p4], [10, -1])
+    assert code == -1 and not h.value
+    h = ctypes.c_void_p()
+    assert M.lib().msm_batch_create(None, None, 0, ctypes.byref(h)) == -1

@@ -1,0 +1,209 @@
+"""GPU batched evaluation: many independent systems of uneven size per launch.
+
+The 64-replica workload (rigid 3-site water boxes of 2,000 to 60,000 atoms,
+a = 10 A, h = 2 A, cubic basis, 2 to 4 levels chosen per box) is checked
+against the FP64 oracle system by system, against the single-system path with
+the same tuning bitwise, under hipGraph replay, through the differentiable
+batch energy, and after the autotuner has picked its tiles.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1402_7216_amd import inputs
+from _helpers import ENERGY_RTOL, FORCE_RTOL, PHI_RTOL, rel_err, rel_rms
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def M():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1402_7216_amd import msm
+    msm.lib()
+    return msm
+
+
+@pytest.fixture(scope="module")
+def replicas():
+    return inputs.water_replicas(64)
+
+
+@pytest.fixture(scope="module")
+def batch64(M, replicas):
+    b = M.batch_for(replicas)
+    x, y, z, q = M.batch_to_device(replicas)
+    out = b.compute(x, y, z, q, virial=True)
+    torch.cuda.synchronize()
+    code, flags = b.status()
+    assert code == 0 and not any(flags), flags
+    return b, (x, y, z, q), {k: v.clone() for k, v in out.items()}
+
+
+def _slice(out, off, s):
+    a, e = off[s], off[s + 1]
+    return (float(out["energy"][s].item()), out["f"][:, a:e].double().cpu().numpy(),
+            out["phi"][a:e].double().cpu().numpy())
+
+
+def test_batch_layout(M, batch64, replicas):
+    b, _, _ = batch64
+    d = b.describe()
+    print(f"case batch64 layout {d}", flush=True)
+    assert d["systems"] == 64 and d["atoms"] == sum(s.n for s in replicas)
+    assert b.offsets == list(np.concatenate([[0], np.cumsum([s.n for s in replicas])]))
+    assert len(d["levels"]) == 64 and set(d["levels"]) <= {2, 3, 4}
+
+
+def test_every_replica_matches_oracle(M, batch64, replicas):
+    b, _, out = batch64
+    worst = dict(e=0.0, f=0.0, phi=0.0)
+    for s, sys_ in enumerate(replicas):
+        e, f, phi = _slice(out, b.offsets, s)
+        r = oracle.system_msm(sys_)
+        de, df, dp = rel_err(e, r["energy"]), rel_rms(f, r["f"]), rel_rms(phi, r["phi"])
+        worst = dict(e=max(worst["e"], de), f=max(worst["f"], df), phi=max(worst["phi"], dp))
+        assert de <= ENERGY_RTOL, (s, sys_.n, de)
+        assert df <= FORCE_RTOL, (s, sys_.n, df)
+        assert dp <= PHI_RTOL, (s, sys_.n, dp)
+        # per-system virial: the float64 sum of (r - lo) F over the device forces
+        w = out["virial"][s].cpu().numpy().reshape(3, 3)
+        pos = sys_.pos64() - np.asarray(sys_.box_lo)[:, None]
+        scale = float(np.linalg.norm(pos, axis=0) @ np.linalg.norm(f, axis=0))
+        assert np.linalg.norm(w - pos @ f.T) / scale < 1e-12
+    print(f"  worst over 64 replicas: energy {worst['e']:.2e} forces {worst['f']:.2e} "
+          f"phi {worst['phi']:.2e}", flush=True)
+
+
+def test_batch_equals_single_system_path_bitwise(M, batch64, replicas):
+    """With the batch's tiles (lattice template and short-range run width) the
+    single-system path performs the same arithmetic in the same order."""
+    b, _, out = batch64
+    d = b.describe()
+    for s in list(range(0, 64, 7)) + [63]:
+        sys_ = replicas[s]
+        plan = M.plan_for(sys_)
+        plan.tune(d["lattice_b"], d["run_w"])
+        o = plan.compute(*M.to_device(sys_), virial=True)
+        torch.cuda.synchronize()
+        a, e = b.offsets[s], b.offsets[s + 1]
+        assert torch.equal(o["f"], out["f"][:, a:e]), s
+        assert torch.equal(o["phi"], out["phi"][a:e]), s
+        assert float(o["energy"].item()) == float(out["energy"][s].item()), s
+        assert torch.equal(o["virial"].reshape(9), out["virial"][s]), s
+
+
+def test_batch_graph_replay_matches_eager(M, batch64):
+    b, (x, y, z, q), ref = batch64
+    out = b.outputs(virial=True)
+    graph = b.graph(x, y, z, q, out)
+    other = M.plan_for(inputs.cloud_1k())
+    ox, oy, oz, oq = M.to_device(inputs.cloud_1k())
+    for rep in range(3):
+        for t in out.values():
+            t.fill_(float("nan"))
+        graph.launch()
+        torch.cuda.synchronize()
+        for k in ref:
+            assert torch.equal(out[k], ref[k]), (rep, k)
+        other.compute(ox, oy, oz, oq)     # unrelated eager work between replays
+        torch.cuda.synchronize()
+    code, flags = b.status()
+    assert code == 0
+
+
+def test_batch_energy_only_and_autograd(M, batch64):
+    b, (x, y, z, q), ref = batch64
+    e = b.energy(x, y, z, q)
+    torch.cuda.synchronize()
+    assert rel_rms(e.cpu().numpy(), ref["energy"].cpu().numpy()) <= 2 * ENERGY_RTOL
+    # d(sum_s w_s E_s)/dr = -w_s F, d/dq = w_s phi, with per-system weights w_s
+    pos = torch.stack([x, y, z]).requires_grad_(True)
+    qq = q.clone().requires_grad_(True)
+    w = torch.linspace(-1.5, 2.0, b.n_sys, dtype=torch.float64, device="cuda")
+    energies = M.batch_energy(b, pos, qq)
+    assert energies.shape == (b.n_sys,) and energies.dtype == torch.float64
+    (energies * w).sum().backward()
+    torch.cuda.synchronize()
+    wa = torch.repeat_interleave(w, torch.tensor(np.diff(b.offsets), device="cuda")).cpu().numpy()
+    f = ref["f"].double().cpu().numpy()
+    phi = ref["phi"].double().cpu().numpy()
+    gp = pos.grad.double().cpu().numpy()
+    gq = qq.grad.double().cpu().numpy()
+    print(f"  batch autograd: dE/dr rel_rms {rel_rms(gp, -wa * f):.2e} dE/dq rel_rms "
+          f"{rel_rms(gq, wa * phi):.2e}", flush=True)
+    assert rel_rms(gp, -wa * f) <= FORCE_RTOL
+    assert rel_rms(gq, wa * phi) <= PHI_RTOL
+
+
+def test_batch_with_empty_tiny_and_flagged_systems(M):
+    """Systems of a batch are independent: an empty and a 2-atom system beside
+    a water box, and a data error in one system flags only that system."""
+    box = dict(cutoff=8.0, spacing=2.0, order=4, levels=3)
+    water = inputs.water_box(3000, seed=41, **box)
+    L = water.box_len
+    rng = np.random.default_rng(9)
+    tiny = inputs.System(*(rng.uniform(0, 1, (3, 2)) * np.asarray(L)[:, None]).astype(np.float32),
+                         np.array([0.7, -0.4], np.float32), box_lo=water.box_lo, box_len=L,
+                         **box, name="tiny")
+    empty = inputs.System(*[np.zeros(0, np.float32)] * 4, box_lo=water.box_lo, box_len=L, **box,
+                          name="empty")
+    systems = [water, empty, tiny, water]
+    b = M.batch_for(systems)
+    x, y, z, q = M.batch_to_device(systems)
+    out = b.compute(x, y, z, q)
+    code, flags = b.status()
+    assert code == 0 and flags == [0, 0, 0, 0]
+    assert float(out["energy"][1].item()) == 0.0
+    r = oracle.system_msm(water)
+    for s in (0, 3):
+        e, f, phi = _slice(out, b.offsets, s)
+        assert rel_err(e, r["energy"]) <= ENERGY_RTOL and rel_rms(f, r["f"]) <= FORCE_RTOL
+    rt = oracle.system_msm(tiny)
+    e, f, _ = _slice(out, b.offsets, 2)
+    scale = 0.7 ** 2 * 2.0 / box["cutoff"]       # self-interaction scale of the larger charge
+    assert abs(e - rt["energy"]) <= 1e-6 * max(abs(rt["energy"]), scale)
+    # an atom outside the box in the last system only
+    xb = x.clone()
+    xb[b.offsets[3] + 5] = float(L[0]) + 1.0
+    b.compute(xb, y, z, q)
+    code, flags = b.status()
+    assert code == -2 and flags[0] == 0 and flags[1] == 0 and flags[2] == 0 and flags[3] != 0
+    b.compute(x, y, z, q)
+    assert b.status()[0] == 0
+
+
+def test_autotune_keeps_results_within_bars(M):
+    systems = inputs.water_replicas(64)[:8]
+    b = M.batch_for(systems)
+    x, y, z, q = M.batch_to_device(systems)
+    rep = b.autotune(x, y, z, q, trials=2)
+    print(f"case batch autotune: best {rep['best']} of {len(rep['candidates'])}", flush=True)
+    assert len(rep["candidates"]) in (3, 9)
+    best = rep["best"]
+    assert best["ms"] == min(c["ms"] for c in rep["candidates"])
+    d = b.describe()
+    assert d["lattice_b"] == best["lattice_b"] and d["run_w"] == best["run_w"]
+    out = b.compute(x, y, z, q)
+    torch.cuda.synchronize()
+    assert b.status()[0] == 0
+    for s in (0, 7):
+        r = oracle.system_msm(systems[s])
+        e, f, phi = _slice(out, b.offsets, s)
+        assert rel_err(e, r["energy"]) <= ENERGY_RTOL
+        assert rel_rms(f, r["f"]) <= FORCE_RTOL
+    # single-system autotune
+    s0 = inputs.water_24k()
+    plan = M.plan_for(s0)
+    xs = M.to_device(s0)
+    rep = plan.autotune(*xs, trials=2)
+    print(f"case plan autotune water24k: best {rep['best']}", flush=True)
+    o = plan.compute(*xs)
+    torch.cuda.synchronize()
+    plan.check()
+    r = oracle.system_msm(s0)
+    assert rel_err(float(o["energy"].item()), r["energy"]) <= ENERGY_RTOL
+    assert rel_rms(o["f"].double().cpu().numpy(), r["f"]) <= FORCE_RTOL
