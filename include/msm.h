@@ -175,14 +175,18 @@ msm_status msm_profile_read(const msm_plan* plan, float* ms, int32_t* n_stages);
 
 /* ------------------------------------------------------------------------ */
 /* Tuning.  msm_plan_tune sets the lattice-cutoff outputs per lane (4, 6 or 8;
- * 0 keeps the current value) and the short-range cells per work item (>= 1;
- * 0 keeps it), and re-uploads the plan's descriptor to ws (other workspaces
- * of the plan must be initialised again).  msm_plan_autotune times each
- * candidate (4, 6, 8) x (1, 2, 3) over `trials` evaluations of the given
- * device inputs on `stream` with HIP events, applies the fastest and writes
- * a JSON report (nullable) of the search. */
+ * 0 keeps the current value), the short-range cells per work item (>= 1; 0
+ * keeps it) and the number of blocks the short-range work items are strided
+ * over (> 0; -1 = one block per work item; 0 keeps it; fewer blocks leave
+ * compute units to the concurrent grid chain), and re-uploads the plan's
+ * descriptor to ws (other workspaces of the plan must be initialised again).
+ * Results depend on the tuning only through float32 summation order.
+ * msm_plan_autotune times candidates over `trials` evaluations of the given
+ * device inputs on `stream` with HIP events: (4, 6, 8) x (1, 2, 3) cells
+ * first, then short-range block counts for the best pair; it applies the
+ * fastest and writes a JSON report (nullable) of the search. */
 msm_status msm_plan_tune(msm_plan* plan, void* ws, size_t ws_bytes, msm_stream_t stream,
-                         int32_t lattice_b, int32_t run_w);
+                         int32_t lattice_b, int32_t run_w, int32_t short_blocks);
 msm_status msm_plan_autotune(msm_plan* plan, void* ws, size_t ws_bytes, msm_stream_t stream,
                              const float* x, const float* y, const float* z, const float* q,
                              int32_t trials, char* report, size_t report_bytes);
@@ -225,8 +229,10 @@ msm_status msm_batch_graph_capture(const msm_batch* batch, void* ws, size_t ws_b
 msm_status msm_batch_status(const msm_batch* batch, const void* ws, msm_stream_t stream,
                             int32_t* flags_per_system);
 msm_status msm_batch_describe(const msm_batch* batch, char* buf, size_t buf_bytes);
+/* Tuning of every system of the batch (same knobs as msm_plan_tune; the
+ * short-range block count applies per system). */
 msm_status msm_batch_tune(msm_batch* batch, void* ws, size_t ws_bytes, msm_stream_t stream,
-                          int32_t lattice_b, int32_t run_w);
+                          int32_t lattice_b, int32_t run_w, int32_t short_blocks);
 msm_status msm_batch_autotune(msm_batch* batch, void* ws, size_t ws_bytes, msm_stream_t stream,
                               const float* x, const float* y, const float* z, const float* q,
                               int32_t trials, char* report, size_t report_bytes);

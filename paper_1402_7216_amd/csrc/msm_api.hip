@@ -33,11 +33,13 @@ hipError_t ensure_aux(AuxStreams& A) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
-  if (A.stream && A.device == dev) return hipSuccess;
+  if (A.cc.shortr.stream && A.device == dev) return hipSuccess;
   destroy_aux(A);
-  e = hipStreamCreateWithFlags(&A.stream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&A.fork, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&A.join, hipEventDisableTiming);
+  for (msm::SideStream* ss : {&A.cc.shortr, &A.cc.lattice0}) {
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&ss->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ss->fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ss->join, hipEventDisableTiming);
+  }
   if (e != hipSuccess) {
     destroy_aux(A);
     return e;
@@ -47,9 +49,11 @@ hipError_t ensure_aux(AuxStreams& A) {
 }
 
 void destroy_aux(AuxStreams& A) {
-  if (A.stream) (void)hipStreamDestroy(A.stream);
-  if (A.fork) (void)hipEventDestroy(A.fork);
-  if (A.join) (void)hipEventDestroy(A.join);
+  for (msm::SideStream* ss : {&A.cc.shortr, &A.cc.lattice0}) {
+    if (ss->stream) (void)hipStreamDestroy(ss->stream);
+    if (ss->fork) (void)hipEventDestroy(ss->fork);
+    if (ss->join) (void)hipEventDestroy(ss->join);
+  }
   A = AuxStreams{};
 }
 
@@ -102,9 +106,9 @@ int bank_conflicts(int xl, int ty, int tz, int B, int px, int pp) {
   return worst;
 }
 
-// Row and plane pitches (floats) of a window tile with the fewest bank
-// conflicts whose window still fits in max_floats.
-void pad_window(msm::LatTile& t, int B, int H, int max_floats) {
+// Row and plane pitches (floats) of a window tile of `planes` z planes with
+// the fewest bank conflicts whose window still fits in max_floats.
+void pad_window(msm::LatTile& t, int B, int H, int planes, int max_floats) {
   const int WX = t.xl * B + 2 * H, PY = t.ty + 2 * H;
   int best = 1 << 30;
   t.px = WX;
@@ -112,9 +116,9 @@ void pad_window(msm::LatTile& t, int B, int H, int max_floats) {
   for (int px = WX; px < WX + 32; ++px)
     for (int extra = 0; extra < 32; ++extra) {
       const int pp = PY * px + extra;
-      if ((t.tz + 2 * H) * pp > max_floats) continue;
+      if (planes * pp > max_floats) continue;
       const int c = bank_conflicts(t.xl, t.ty, t.tz, B, px, pp);
-      const int score = c * 4096 + (pp * (t.tz + 2 * H) - WX * PY * (t.tz + 2 * H)) / 64;
+      const int score = c * 4096 + (pp * planes - WX * PY * planes) / 64;
       if (score < best) {
         best = score;
         t.px = px;
@@ -123,19 +127,54 @@ void pad_window(msm::LatTile& t, int B, int H, int max_floats) {
     }
 }
 
-// Tile shapes of the windowed lattice-cutoff kernel.  For each candidate B
-// (outputs per lane along x) and each sub-top level, pick (xl, ty, tz) lanes
-// minimising a cost in wave instructions: FMA slots including ragged-tile
-// waste (about half a FMA per tap with mirror-row pairing), plus the window
-// load; then penalise launches with fewer blocks than compute units.
-void choose_lattice_tiles(const Geom& g, int taps, int H_, int tables_bytes, msm::LatLaunch& lat,
-                          int force_b = 0) {
+// Split the compact rows (sorted by nz) into G contiguous nz ranges of nearly
+// equal work; grp[g] = first row of group g, grp[G] = number of rows.  Returns
+// the largest nz span (nz_hi - nz_lo) of a group.
+int split_rows(const std::vector<int4>& rows, int B, int G, short* grp) {
+  const int n = (int)rows.size();
+  std::vector<double> cost(n);
+  double total = 0.0;
+  for (int r = 0; r < n; ++r) {
+    const int xr = rows[r].z;
+    cost[r] = (2.0 * xr + 1.0) * B + (rows[r].y ? B + 2.0 * xr : 0.0) + 8.0;
+    total += cost[r];
+  }
+  int g = 0, span = 0, first = 0;
+  double acc = 0.0;
+  grp[0] = 0;
+  for (int r = 0; r < n; ++r) {
+    acc += cost[r];
+    const bool nz_ends = (r + 1 == n) || rows[r + 1].x != rows[r].x;
+    if (nz_ends && g + 1 < G && acc >= total * (g + 1) / G) {
+      grp[++g] = (short)(r + 1);
+      span = std::max(span, rows[r].x - rows[first].x);
+      first = r + 1;
+    }
+  }
+  span = std::max(span, rows[n - 1].x - rows[first].x);
+  while (g + 1 < G) grp[++g] = (short)n;        // fewer nz values than groups: empty groups
+  grp[G] = (short)n;
+  return span;
+}
+
+// Tile shapes and row groups of the windowed lattice-cutoff kernel.  For each
+// candidate B (outputs per lane along x) and each sub-top level, pick
+// (xl, ty, tz) lanes minimising a per-tile cost in wave instructions (FMA
+// slots including ragged-tile waste, about half a FMA per tap with mirror-row
+// pairing, plus the window load).  Then split the rows of each tile into
+// groups so that the blocks of a launch (level 0 alone; levels 1 .. l-2
+// together) cover the 256 compute units with short blocks: the launch is
+// estimated as ceil(blocks / 256) times its longest block.
+void choose_lattice_tiles(const Geom& g, const std::vector<int4>& rows, int taps, int H_,
+                          int tables_bytes, msm::LatLaunch& lat, int force_b = 0) {
   const int n_rows = lat.n_rows, n_wc = lat.n_wc;
   std::memset(&lat, 0, sizeof(lat));
   lat.H = H_;
   lat.n_rows = n_rows;
   lat.n_wc = n_wc;
   if (g.levels < 2 || H_ > msm::kLatMaxHalo) return;
+  const int max_floats = (msm::kLatMaxLds - tables_bytes) / 4;
+  const int gmax = std::min(msm::kLatMaxGroups, 2 * H_ + 1);
   double best = 1e300;
   msm::LatLaunch cand;
   const int Bs[3] = {4, 6, 8};
@@ -145,48 +184,91 @@ void choose_lattice_tiles(const Geom& g, int taps, int H_, int tables_bytes, msm
     cand = lat;
     cand.b = B;
     cand.n = g.levels - 1;
-    double cost = 0.0;
-    long long blocks = 0;
-    int lds_max = 0;
+    int span[msm::kLatMaxGroups + 1] = {};
+    for (int G = 1; G <= gmax; ++G) span[G] = split_rows(rows, B, G, cand.grp[G]);
+    // per level: best tile by per-tile cost (all groups)
+    double tile_cost[msm::kMaxLevels] = {};
+    long long tiles[msm::kMaxLevels] = {};
     bool ok = true;
     for (int k = 0; k < g.levels - 1; ++k) {
       const msm::Level& L = g.lv[k];
       double lbest = 1e300;
       msm::LatTile tb{};
-      int tb_lds = 0;
       for (int tz = 1; tz <= 16; ++tz)
         for (int ty = 1; ty <= 16; ++ty)
           for (int xl = 1; xl <= 16; ++xl) {
             if (xl * ty * tz > 64 || xl * ty * tz < 32) continue;
             const int WX = xl * B + 2 * H_, PY = ty + 2 * H_, WZ = tz + 2 * H_;
-            const int px = WX;                         // unpadded; padding must fit the budget later
-            const int lds = std::max(tables_bytes + WZ * PY * px * 4, msm::kLatWavesReduce * 64 * B * 8);
-            if (lds > msm::kLatMaxLds) continue;
-            const long long tiles = (long long)((L.n[0] + xl * B - 1) / (xl * B)) *
-                                    ((L.n[1] + ty - 1) / ty) * ((L.n[2] + tz - 1) / tz);
-            const double c = (double)tiles * (0.55 * B * taps + (double)WZ * PY * WX / 16.0);
+            if (WZ * PY * WX > max_floats) continue;
+            const long long nt = (long long)((L.n[0] + xl * B - 1) / (xl * B)) *
+                                 ((L.n[1] + ty - 1) / ty) * ((L.n[2] + tz - 1) / tz);
+            const double c = (double)nt * (0.55 * B * taps + (double)WZ * PY * WX / 16.0);
             if (c < lbest) {
               lbest = c;
               tb = msm::LatTile{k, xl, ty, tz, (L.n[0] + xl * B - 1) / (xl * B), (L.n[1] + ty - 1) / ty,
-                                (L.n[2] + tz - 1) / tz, 0, px};
-              tb_lds = lds;
+                                (L.n[2] + tz - 1) / tz, 0, WX, WX * PY, 1, 0};
             }
           }
       if (lbest >= 1e300) {
         ok = false;
         break;
       }
-      pad_window(tb, B, H_, (msm::kLatMaxLds - tables_bytes) / 4);
-      tb_lds = std::max(tables_bytes + (tb.tz + 2 * H_) * tb.pp * 4, msm::kLatWavesReduce * 64 * B * 8);
-      tb.block0 = (int)blocks;
-      blocks += (long long)tb.ntx * tb.nty * tb.ntz;
-      cost += lbest;
-      lds_max = std::max(lds_max, tb_lds);
       cand.t[k] = tb;
+      tiles[k] = (long long)tb.ntx * tb.nty * tb.ntz;
+      tile_cost[k] = lbest / (double)tiles[k];
     }
     if (!ok) continue;
-    const double est = cost * std::max(1.0, 256.0 / (double)std::max<long long>(blocks, 1));
+    // cost of one block of level k with G groups
+    auto block_cost = [&](int k, int G) {
+      const msm::LatTile& t = cand.t[k];
+      const int WX = t.xl * B + 2 * H_, PY = t.ty + 2 * H_;
+      const double stage = (double)(t.tz + span[G]) * PY * WX / 16.0;
+      return 0.55 * B * taps / G + stage + 300.0;
+    };
+    // groups per level for one launch over levels [k0, k1): a common target
+    // block cost tau sets G_k = ceil(cost_k(1) / tau)
+    auto choose_groups = [&](int k0, int k1) {
+      double est_best = 1e300;
+      int gbest[msm::kMaxLevels] = {};
+      for (int kk = k0; kk < k1; ++kk)
+        for (int G = 1; G <= gmax; ++G) {
+          const double tau = block_cost(kk, G);
+          int gk[msm::kMaxLevels] = {};
+          long long blocks = 0;
+          double longest = 0.0;
+          for (int k = k0; k < k1; ++k) {
+            int Gk = 1;
+            while (Gk < gmax && block_cost(k, Gk) > tau) ++Gk;
+            gk[k] = Gk;
+            blocks += tiles[k] * Gk;
+            longest = std::max(longest, block_cost(k, Gk));
+          }
+          const double est = (double)((blocks + 255) / 256) * longest;
+          if (est < est_best) {
+            est_best = est;
+            std::copy(gk, gk + msm::kMaxLevels, gbest);
+          }
+        }
+      for (int k = k0; k < k1; ++k) cand.t[k].groups = gbest[k];
+      return est_best;
+    };
+    const double est = choose_groups(0, 1) + (g.levels > 2 ? choose_groups(1, g.levels - 1) : 0.0);
+    // padding, LDS, block and partial offsets
+    long long blocks = 0;
+    int lds_max = 0, part = 0;
+    for (int k = 0; k < g.levels - 1; ++k) {
+      msm::LatTile& t = cand.t[k];
+      const int planes = t.tz + span[t.groups];
+      pad_window(t, B, H_, planes, max_floats);
+      const int lds = std::max(tables_bytes + planes * t.pp * 4, msm::kLatWavesReduce * 64 * B * 8);
+      lds_max = std::max(lds_max, lds);
+      t.block0 = (int)blocks;
+      blocks += tiles[k] * t.groups;
+      t.part0 = part;
+      if (t.groups > 1) part += t.groups * g.lv[k].count;
+    }
     cand.lds_bytes = lds_max;
+    cand.n_part = part;
     if (est < best) {
       best = est;
       lat = cand;
@@ -221,6 +303,7 @@ void refresh_launch(msm_plan* P) {
   lg.one.blocks = 1;
   lg.shortr.blocks = sb.shortr;
   lg.anterp.blocks = sb.anterp;
+  lg.lattice0.blocks = sb.lattice0;
   lg.lattice.blocks = sb.lattice;
   lg.top.blocks = sb.top;
   lg.energy.blocks = sb.energy;
@@ -230,14 +313,21 @@ void refresh_launch(msm_plan* P) {
   }
 }
 
-void retune(msm_plan* P, int lat_b, int run_w) {
+void set_short_blocks(Geom& g, int cap) {
+  const int items = g.runs_x * g.nc[1] * g.nc[2];
+  g.short_blocks = cap > 0 ? std::min(cap, items) : items;
+}
+
+void retune(msm_plan* P, int lat_b, int run_w, int short_blocks) {
   if (lat_b && P->lat.b && lat_b != P->lat.b)
-    choose_lattice_tiles(P->g, (int)P->weights.size(), P->lat.H, P->lat_tables, P->lat, lat_b);
+    choose_lattice_tiles(P->g, P->rows_c, (int)P->weights.size(), P->lat.H, P->lat_tables, P->lat, lat_b);
+  Geom& g = P->g;
   if (run_w > 0) {
-    Geom& g = P->g;
     g.run_w = std::max(1, std::min(run_w, g.nc[0]));
     g.runs_x = (g.nc[0] + g.run_w - 1) / g.run_w;
   }
+  if (short_blocks != 0) P->short_cap = short_blocks < 0 ? 0 : short_blocks;
+  set_short_blocks(g, P->short_cap);
   refresh_launch(P);
 }
 
@@ -263,6 +353,7 @@ msm::DevPtrs dev_ptrs(const msm_plan* P, void* ws) {
   d.weights_c = reinterpret_cast<const float*>(b + o[msm::kSecWeightsC]);
   d.top = reinterpret_cast<const double*>(b + o[msm::kSecTop]);
   d.partials = reinterpret_cast<double*>(b + o[msm::kSecPartials]);
+  d.lat_part = reinterpret_cast<double*>(b + o[msm::kSecLatPart]);
   return d;
 }
 
@@ -409,6 +500,7 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
   int w = (int)std::lround(48.0 / std::max(per_cell, 1e-3));
   g.run_w = std::max(1, std::min(w, g.nc[0]));
   g.runs_x = (g.nc[0] + g.run_w - 1) / g.run_w;
+  set_short_blocks(g, P->short_cap);
 
   // lattice-cutoff stencil: W(n) = g^0(h |n|) for h |n| < 2a, rows along z
   if (L > 1) {
@@ -470,7 +562,12 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
       P->lat.n_wc = (int)P->weights_c.size();
       const int tables = P->lat.n_rows * 16 + P->lat.n_wc * 4;
       P->lat_tables = tables;
-      choose_lattice_tiles(g, (int)P->weights.size(), H, tables, P->lat);
+      // the partials section holds the largest need of any tuning
+      for (int b : {4, 6, 8}) {
+        choose_lattice_tiles(g, P->rows_c, (int)P->weights.size(), H, tables, P->lat, b);
+        P->lat_part_max = std::max(P->lat_part_max, P->lat.n_part);
+      }
+      choose_lattice_tiles(g, P->rows_c, (int)P->weights.size(), H, tables, P->lat);
     } else {
       P->lat.b = 0;
       P->lat.H = H;
@@ -512,6 +609,7 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
   lay.bytes[msm::kSecWeightsC] = std::max<size_t>(P->weights_c.size(), 1) * sizeof(float);
   lay.bytes[msm::kSecTop] = P->top.size() * sizeof(double);
   lay.bytes[msm::kSecPartials] = 10 * (size_t)P->n_partials * sizeof(double);
+  lay.bytes[msm::kSecLatPart] = std::max<size_t>(P->lat_part_max, 1) * sizeof(double);
   lay.bytes[msm::kSecDesc] = sizeof(msm::SysDesc);
   size_t o = 0;
   for (int s = 0; s < msm::kSecCount; ++s) {
@@ -577,7 +675,7 @@ msm_status msm_plan_describe(const msm_plan* P, char* buf, size_t buf_bytes) {
   o += "\"levels\": " + std::to_string(g.levels);
   o += ", \"cells\": [" + std::to_string(g.nc[0]) + ", " + std::to_string(g.nc[1]) + ", " +
        std::to_string(g.nc[2]) + "], \"reach\": " + std::to_string(g.reach) +
-       ", \"run_w\": " + std::to_string(g.run_w);
+       ", \"run_w\": " + std::to_string(g.run_w) + ", \"short_blocks\": " + std::to_string(g.short_blocks);
   o += ", \"taps\": " + std::to_string(P->weights.size()) + ", \"halo\": " + std::to_string(P->lat.H);
   o += ", \"lattice_b\": " + std::to_string(P->lat.b) + ", \"lattice_lds\": " +
        std::to_string(P->lat.lds_bytes) + ", \"lattice_tiles\": [";
@@ -586,7 +684,8 @@ msm_status msm_plan_describe(const msm_plan* P, char* buf, size_t buf_bytes) {
     if (k) o += ", ";
     o += "[" + std::to_string(t.xl) + ", " + std::to_string(t.ty) + ", " + std::to_string(t.tz) + ", " +
          std::to_string(t.ntx * t.nty * t.ntz) + ", " +
-         std::to_string(bank_conflicts(t.xl, t.ty, t.tz, P->lat.b, t.px, t.pp)) + "]";
+         std::to_string(bank_conflicts(t.xl, t.ty, t.tz, P->lat.b, t.px, t.pp)) + ", " +
+         std::to_string(t.groups) + "]";
   }
   o += "], \"workspace_bytes\": " + std::to_string(P->lay.total) + "}";
   std::strncpy(buf, o.c_str(), buf_bytes - 1);
@@ -680,7 +779,7 @@ msm_status msm_compute(const msm_plan* P, void* ws, size_t ws_bytes, msm_stream_
   if (e != hipSuccess) return hip_fail(e, "create auxiliary stream");
   const msm::Io io{x, y, z, q, fx, fy, fz, phi, energy, virial, nullptr};
   e = msm::launch_eval(msm::kModeForces, launch_geom(P, ws), reinterpret_cast<hipStream_t>(stream), io,
-                       P->profile ? M->ev : nullptr, M->aux.stream, M->aux.fork, M->aux.join);
+                       P->profile ? M->ev : nullptr, &M->aux.cc);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return MSM_OK;
 }
@@ -696,7 +795,7 @@ static msm_status eval_mode(int mode, const msm_plan* P, void* ws, size_t ws_byt
   if (e != hipSuccess) return hip_fail(e, "create auxiliary stream");
   const msm::Io io{x, y, z, q, fx, fy, fz, phi, energy, nullptr, gscale};
   e = msm::launch_eval(mode, launch_geom(P, ws), reinterpret_cast<hipStream_t>(stream), io, nullptr,
-                       M->aux.stream, M->aux.fork, M->aux.join);
+                       &M->aux.cc);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return MSM_OK;
 }
@@ -741,8 +840,7 @@ msm_status msm_graph_capture(const msm_plan* P, void* ws, size_t ws_bytes, const
   const msm::LaunchGeom L = launch_geom(P, ws);
   return capture_graph(
       [&](hipStream_t cs) {
-        return msm::launch_eval(msm::kModeForces, L, cs, io, nullptr, M->aux.stream, M->aux.fork,
-                                M->aux.join);
+        return msm::launch_eval(msm::kModeForces, L, cs, io, nullptr, &M->aux.cc);
       },
       out);
 }

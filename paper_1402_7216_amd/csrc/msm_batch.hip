@@ -18,7 +18,7 @@ namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-constexpr int kNumStages = 8 + 2 * msm::kMaxLevels;
+constexpr int kNumStages = 9 + 2 * msm::kMaxLevels;
 
 }  // namespace
 
@@ -45,7 +45,7 @@ namespace {
 
 // Stage order inside the map arrays.
 enum : int {
-  kMZero = 0, kMAtoms, kMOne, kMShort, kMAnterp, kMLattice, kMTop, kMEnergy, kMRestrict0,
+  kMZero = 0, kMAtoms, kMOne, kMShort, kMAnterp, kMLattice0, kMLattice, kMTop, kMEnergy, kMRestrict0,
   kMProlong0 = kMRestrict0 + msm::kMaxLevels
 };
 
@@ -56,6 +56,7 @@ msm::StageGrid* stage_of(msm::LaunchGeom& L, int st) {
     case kMOne: return &L.one;
     case kMShort: return &L.shortr;
     case kMAnterp: return &L.anterp;
+    case kMLattice0: return &L.lattice0;
     case kMLattice: return &L.lattice;
     case kMTop: return &L.top;
     case kMEnergy: return &L.energy;
@@ -72,6 +73,7 @@ int blocks_of(const msm::SysBlocks& b, int st) {
     case kMOne: return 1;
     case kMShort: return b.shortr;
     case kMAnterp: return b.anterp;
+    case kMLattice0: return b.lattice0;
     case kMLattice: return b.lattice;
     case kMTop: return b.top;
     case kMEnergy: return b.energy;
@@ -201,7 +203,7 @@ msm_status msm_batch_create(const msm_params* params, const int32_t* n_atoms, in
   for (int s = 1; s < n_sys; ++s)
     if (n_atoms[s] > n_atoms[big]) big = s;
   const int b0 = Bt->plans[big]->lat.b;
-  for (msm_plan* P : Bt->plans) retune(P, b0, 0);
+  for (msm_plan* P : Bt->plans) retune(P, b0, 0, 0);
 
   // stage-table reserves: the most blocks any tuning can ask for
   // (lattice template 4, one cell per short-range work item)
@@ -209,16 +211,17 @@ msm_status msm_batch_create(const msm_params* params, const int32_t* n_atoms, in
   for (msm_plan* P : Bt->plans) {
     const Geom keep_g = P->g;
     const msm::LatLaunch keep_l = P->lat;
+    const int keep_cap = P->short_cap;
     size_t most[kNumStages] = {};
     for (int b : {4, 6, 8})
       for (int w : {1, keep_g.run_w}) {
-        if (P->lat.b) retune(P, b, w);
-        else retune(P, 0, w);
+        retune(P, P->lat.b ? b : 0, w, -1);        // one short-range block per work item: the most
         const msm::SysBlocks sb = msm::system_blocks(P->g, P->lat, P->n_partials);
         for (int st = 0; st < kNumStages; ++st) most[st] = std::max(most[st], (size_t)blocks_of(sb, st));
       }
     P->g = keep_g;
     P->lat = keep_l;
+    P->short_cap = keep_cap;
     refresh_launch(P);
     for (int st = 0; st < kNumStages; ++st) cap[st] += most[st];
   }
@@ -285,11 +288,10 @@ static msm_status batch_eval(int mode, const msm_batch* Bt, void* ws, size_t ws_
   if (graph)
     return capture_graph(
         [&](hipStream_t cs) {
-          return msm::launch_eval(mode, L, cs, io, nullptr, M->aux.stream, M->aux.fork, M->aux.join);
+          return msm::launch_eval(mode, L, cs, io, nullptr, &M->aux.cc);
         },
         graph);
-  e = msm::launch_eval(mode, L, reinterpret_cast<hipStream_t>(stream), io, nullptr, M->aux.stream,
-                       M->aux.fork, M->aux.join);
+  e = msm::launch_eval(mode, L, reinterpret_cast<hipStream_t>(stream), io, nullptr, &M->aux.cc);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return MSM_OK;
 }
@@ -358,13 +360,15 @@ msm_status msm_batch_describe(const msm_batch* Bt, char* buf, size_t buf_bytes) 
                   ", \"max_levels\": " + std::to_string(L.max_levels) +
                   ", \"lattice_b\": " + std::to_string(L.lat_b) +
                   ", \"lattice_lds\": " + std::to_string(L.lat_lds) +
-                  ", \"run_w\": " + std::to_string(Bt->plans[0]->g.run_w) +
+                  ", \"run_w\": " + std::to_string(Bt->plans[0]->g.run_w) +   // first system's
                   ", \"blocks\": {\"atoms\": " + std::to_string(L.atoms.blocks) +
                   ", \"short\": " + std::to_string(L.shortr.blocks) +
                   ", \"anterp\": " + std::to_string(L.anterp.blocks) +
-                  ", \"lattice\": " + std::to_string(L.lattice.blocks) +
+                  ", \"lattice\": " + std::to_string(L.lattice0.blocks + L.lattice.blocks) +
                   ", \"top\": " + std::to_string(L.top.blocks) + "}, \"levels\": [";
   for (int s = 0; s < Bt->n_sys; ++s) o += (s ? ", " : "") + std::to_string(Bt->plans[s]->g.levels);
+  o += "], \"run_ws\": [";
+  for (int s = 0; s < Bt->n_sys; ++s) o += (s ? ", " : "") + std::to_string(Bt->plans[s]->g.run_w);
   o += "], \"workspace_bytes\": " + std::to_string(Bt->total) + "}";
   std::strncpy(buf, o.c_str(), buf_bytes - 1);
   buf[buf_bytes - 1] = 0;
@@ -376,14 +380,15 @@ msm_status msm_batch_describe(const msm_batch* Bt, char* buf, size_t buf_bytes) 
 // ---------------------------------------------------------------------------
 
 msm_status msm_plan_tune(msm_plan* P, void* ws, size_t ws_bytes, msm_stream_t stream, int32_t lattice_b,
-                         int32_t run_w) {
+                         int32_t run_w, int32_t short_blocks) {
   if (!P) return fail(MSM_ERR_INVALID_ARG, "null plan");
   if (lattice_b != 0 && lattice_b != 4 && lattice_b != 6 && lattice_b != 8)
     return fail(MSM_ERR_INVALID_ARG, "lattice_b must be 0, 4, 6 or 8");
   if (run_w < 0) return fail(MSM_ERR_INVALID_ARG, "run_w must be >= 0");
+  if (short_blocks < -1) return fail(MSM_ERR_INVALID_ARG, "short_blocks must be >= -1");
   if (!ws || ws_bytes < P->lay.total || !P->ready.count(ws))
     return fail(MSM_ERR_WORKSPACE, "workspace not initialised for this plan");
-  retune(P, lattice_b, run_w);
+  retune(P, lattice_b, run_w, short_blocks);
   P->desc.d = dev_ptrs(P, ws);
   // other workspaces now hold stale descriptors
   P->ready.clear();
@@ -397,13 +402,14 @@ msm_status msm_plan_tune(msm_plan* P, void* ws, size_t ws_bytes, msm_stream_t st
 }
 
 msm_status msm_batch_tune(msm_batch* Bt, void* ws, size_t ws_bytes, msm_stream_t stream,
-                          int32_t lattice_b, int32_t run_w) {
+                          int32_t lattice_b, int32_t run_w, int32_t short_blocks) {
   msm_status st = check_batch(Bt, ws, ws_bytes);
   if (st != MSM_OK) return st;
   if (lattice_b != 0 && lattice_b != 4 && lattice_b != 6 && lattice_b != 8)
     return fail(MSM_ERR_INVALID_ARG, "lattice_b must be 0, 4, 6 or 8");
   if (run_w < 0) return fail(MSM_ERR_INVALID_ARG, "run_w must be >= 0");
-  for (msm_plan* P : Bt->plans) retune(P, lattice_b, run_w);
+  if (short_blocks < -1) return fail(MSM_ERR_INVALID_ARG, "short_blocks must be >= -1");
+  for (msm_plan* P : Bt->plans) retune(P, lattice_b, run_w, short_blocks);
   rebuild_maps(Bt);
   Bt->ready.clear();
   st = upload_tables(Bt, ws, reinterpret_cast<hipStream_t>(stream));
@@ -412,9 +418,10 @@ msm_status msm_batch_tune(msm_batch* Bt, void* ws, size_t ws_bytes, msm_stream_t
   return MSM_OK;
 }
 
-// Time each candidate (lattice_b in {4, 6, 8} x run_w in {1, 2, 3}) over
-// `trials` evaluations of the given inputs with HIP events on `stream`, apply
-// the fastest, and describe the search in `report` (JSON, nullable).
+// Time candidates over `trials` evaluations of the given inputs with HIP
+// events on `stream`: lattice_b in {4, 6, 8} x run_w in {1, 2, 3} with the
+// current short-range block count, then short-range block counts for the best
+// pair.  Apply the fastest and describe the search in `report` (JSON, nullable).
 static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm_stream_t stream,
                            const float* x, const float* y, const float* z, const float* q,
                            int32_t trials, char* report, size_t report_bytes) {
@@ -424,54 +431,68 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
   hipError_t he = hipEventCreate(&e0);
   if (he == hipSuccess) he = hipEventCreate(&e1);
   if (he != hipSuccess) return hip_fail(he, "create timing events");
-  const bool tiled = batch ? static_cast<msm_batch*>(obj)->lg.lat_b > 0
-                           : static_cast<msm_plan*>(obj)->lat.b > 0;
-  std::vector<int> bs = tiled ? std::vector<int>{4, 6, 8} : std::vector<int>{0};
+  msm_batch* Bt = batch ? static_cast<msm_batch*>(obj) : nullptr;
+  msm_plan* P = batch ? nullptr : static_cast<msm_plan*>(obj);
+  const bool tiled = batch ? Bt->lg.lat_b > 0 : P->lat.b > 0;
+  auto tune = [&](int b, int w, int c) {
+    return batch ? msm_batch_tune(Bt, ws, ws_bytes, stream, b, w, c)
+                 : msm_plan_tune(P, ws, ws_bytes, stream, b, w, c);
+  };
+  auto eval = [&]() {
+    return batch ? msm_batch_compute(Bt, ws, ws_bytes, stream, x, y, z, q, nullptr, nullptr, nullptr, nullptr,
+                                     nullptr, nullptr)
+                 : msm_compute(P, ws, ws_bytes, stream, x, y, z, q, nullptr, nullptr, nullptr, nullptr,
+                               nullptr, nullptr);
+  };
   std::string rep = "{\"candidates\": [";
   float best = 1e30f;
-  int best_b = 0, best_w = 0;
-  msm_status st = MSM_OK;
+  int best_b = 0, best_w = 0, best_c = 0;
   bool first = true;
+  auto time_one = [&](int b, int w, int c, float& ms) {
+    msm_status st = tune(b, w, c);
+    // one warm-up evaluation, then `trials` timed ones
+    for (int t = -1; t < trials && st == MSM_OK; ++t) {
+      if (t == 0) (void)hipEventRecord(e0, s);
+      st = eval();
+    }
+    if (st != MSM_OK) return st;
+    (void)hipEventRecord(e1, s);
+    hipError_t r = hipEventSynchronize(e1);
+    if (r == hipSuccess) r = hipEventElapsedTime(&ms, e0, e1);
+    if (r != hipSuccess) return hip_fail(r, "time candidate");
+    ms /= trials;
+    rep += std::string(first ? "" : ", ") + "{\"lattice_b\": " + std::to_string(b) + ", \"run_w\": " +
+           std::to_string(w) + ", \"short_blocks\": " + std::to_string(c) + ", \"ms\": " +
+           std::to_string(ms) + "}";
+    first = false;
+    if (ms < best) {
+      best = ms;
+      best_b = b;
+      best_w = w;
+      best_c = c;
+    }
+    return MSM_OK;
+  };
+  msm_status st = MSM_OK;
+  const std::vector<int> bs = tiled ? std::vector<int>{4, 6, 8} : std::vector<int>{0};
   for (int b : bs)
     for (int w : {1, 2, 3}) {
-      st = batch ? msm_batch_tune(static_cast<msm_batch*>(obj), ws, ws_bytes, stream, b, w)
-                 : msm_plan_tune(static_cast<msm_plan*>(obj), ws, ws_bytes, stream, b, w);
-      if (st != MSM_OK) break;
-      // one warm-up evaluation, then `trials` timed ones
-      for (int t = -1; t < trials && st == MSM_OK; ++t) {
-        if (t == 0) (void)hipEventRecord(e0, s);
-        st = batch ? msm_batch_compute(static_cast<msm_batch*>(obj), ws, ws_bytes, stream, x, y, z, q,
-                                       nullptr, nullptr, nullptr, nullptr, nullptr, nullptr)
-                   : msm_compute(static_cast<msm_plan*>(obj), ws, ws_bytes, stream, x, y, z, q, nullptr,
-                                 nullptr, nullptr, nullptr, nullptr, nullptr);
-      }
-      if (st != MSM_OK) break;
-      (void)hipEventRecord(e1, s);
-      he = hipEventSynchronize(e1);
       float ms = 0.f;
-      if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-      if (he != hipSuccess) {
-        st = hip_fail(he, "time candidate");
-        break;
-      }
-      ms /= trials;
-      rep += std::string(first ? "" : ", ") + "{\"lattice_b\": " + std::to_string(b) +
-             ", \"run_w\": " + std::to_string(w) + ", \"ms\": " + std::to_string(ms) + "}";
-      first = false;
-      if (ms < best) {
-        best = ms;
-        best_b = b;
-        best_w = w;
-      }
+      if (st == MSM_OK) st = time_one(b, w, -1, ms);
     }
+  const int bb = best_b, bw = best_w;
+  for (int c : {384, 256, 192, 128}) {
+    float ms = 0.f;
+    if (st == MSM_OK) st = time_one(bb, bw, c, ms);
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != MSM_OK) return st;
-  st = batch ? msm_batch_tune(static_cast<msm_batch*>(obj), ws, ws_bytes, stream, best_b, best_w)
-             : msm_plan_tune(static_cast<msm_plan*>(obj), ws, ws_bytes, stream, best_b, best_w);
+  st = tune(best_b, best_w, best_c);
   if (st != MSM_OK) return st;
   rep += "], \"best\": {\"lattice_b\": " + std::to_string(best_b) + ", \"run_w\": " +
-         std::to_string(best_w) + ", \"ms\": " + std::to_string(best) + "}}";
+         std::to_string(best_w) + ", \"short_blocks\": " + std::to_string(best_c) + ", \"ms\": " +
+         std::to_string(best) + "}}";
   if (report && report_bytes) {
     std::strncpy(report, rep.c_str(), report_bytes - 1);
     report[report_bytes - 1] = 0;

@@ -43,6 +43,7 @@ struct Geom {
   float inv_cs[3];                 // 1 / cell edge
   int run_w;                       // cells per short-range work item along x
   int runs_x;                      // work items per cell row
+  int short_blocks;                // blocks of the short-range launch (work items strided over them)
   // short-range constants
   float a2;                        // cutoff^2
   float inv_a2;                    // 1 / a^2
@@ -59,7 +60,10 @@ struct StencilRow {
   int nx, ny, zr, woff;
 };
 
-// Windowed lattice-cutoff launch: one tile shape per sub-top level.
+// Windowed lattice-cutoff launch: one tile shape per sub-top level.  A tile's
+// stencil rows may be split into `groups` contiguous ranges of nz, one block
+// each; each such block then writes float64 partial sums per node, which the
+// consumers of u^{k,cut} add in group order.
 struct LatTile {
   int level;
   int xl, ty, tz;          // lanes along x (B outputs each), y, z
@@ -67,11 +71,14 @@ struct LatTile {
   int block0;              // first block of this level
   int px;                  // padded LDS row pitch of the window (floats)
   int pp;                  // padded LDS plane pitch of the window (floats)
+  int groups;              // row groups per tile (1: the block writes u^{k,cut} itself)
+  int part0;               // first float64 partial of this level (groups * nodes of the level)
 };
 
 constexpr int kLatMaxHalo = 16;          // windowed kernel handles stencil half-widths up to this
 constexpr int kLatMaxLds = 150 * 1024;   // LDS budget of one windowed block (bytes)
 constexpr int kLatWavesReduce = 16;      // waves per windowed block (their totals meet in LDS)
+constexpr int kLatMaxGroups = 8;         // row groups per tile
 
 struct LatLaunch {
   int b;                   // outputs per lane along x (template), 0 = use the untiled kernel
@@ -80,6 +87,9 @@ struct LatLaunch {
   int lds_bytes;           // dynamic LDS per block
   int n_rows;              // compact rows (nz in [-H, H], ny >= 0)
   int n_wc;                // compact weights (floats, each row padded to a multiple of 4)
+  int n_part;              // float64 partials of every grouped level
+  // first compact row of group g when a tile has G groups: grp[G][g], g <= G
+  short grp[kLatMaxGroups + 1][kLatMaxGroups + 1];
   LatTile t[kMaxLevels];
 };
 
@@ -103,6 +113,7 @@ enum Section : int {
   kSecWeightsC,       // float[n_wc]: W(nx, ny, |nz|) for nx = 0..xr per compact row
   kSecTop,            // double[top table]
   kSecPartials,       // double[10 * n_partials]: energy, then 9 virial components
+  kSecLatPart,        // double[]: row-group partials of the lattice cutoff
   kSecDesc,           // SysDesc: this workspace's descriptor (pointers into it)
   kSecCount
 };
@@ -132,6 +143,7 @@ struct DevPtrs {
   const float* weights;
   const double* top;
   double* partials;
+  double* lat_part;
 };
 
 // Stages of one evaluation, in launch order (for optional event timing).
@@ -202,14 +214,16 @@ struct LaunchGeom {
   int lat_b = 0;                     // windowed lattice outputs per lane, 0 = untiled kernel
   int lat_lds = 0;                   // dynamic LDS of the windowed kernel
   int max_levels = 1;
-  StageGrid zero, atoms, one, shortr, anterp, lattice, top, energy;
+  StageGrid zero, atoms, one, shortr, anterp, top, energy;
+  StageGrid lattice0;                // lattice cutoff of level 0
+  StageGrid lattice;                 // lattice cutoff of levels 1 .. l-2
   StageGrid restrict_[kMaxLevels];   // level k -> k+1
   StageGrid prolong[kMaxLevels];     // level k+1 -> k
 };
 
 // Per-stage block counts of one system.
 struct SysBlocks {
-  int zero, atoms, shortr, anterp, lattice, top, energy;
+  int zero, atoms, shortr, anterp, lattice0, lattice, top, energy;
   int restrict_[kMaxLevels];
   int prolong[kMaxLevels];
 };
@@ -222,12 +236,29 @@ enum Mode : int {
   kModeGradient = 2    // gscale * dE/dr into fx..fz, gscale * dE/dq into phi
 };
 
+// A side stream with the events that fork work onto it and join it back.
+struct SideStream {
+  hipStream_t stream = nullptr;
+  hipEvent_t fork = nullptr;
+  hipEvent_t join = nullptr;
+};
+
+// Side streams of one evaluation: the short-range pass, and the level-0
+// lattice cutoff (which needs only the anterpolated charges, so it overlaps
+// the restriction chain, the coarse lattice levels, the top level and the
+// coarse prolongations).
+struct Concurrency {
+  SideStream shortr;
+  SideStream lattice0;
+};
+
 // Enqueues one evaluation (of every system of L) on `s` and returns the first
 // HIP error.  ev (nullable): kStageCount + 1 events recorded at the stage
-// boundaries.  aux/fork/join (nullable): run the short-range pass on `aux`,
-// concurrently with the grid chain, joined back before it is needed.
+// boundaries (the evaluation then runs in order on `s`).  cc (nullable): side
+// streams for the concurrent branches, each joined back before its result is
+// needed.
 hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& io, hipEvent_t* ev,
-                       hipStream_t aux, hipEvent_t fork, hipEvent_t join);
+                       const Concurrency* cc);
 
 int interp_partials(const Geom& g);      // number of FP64 partial slots the forward pass uses
 

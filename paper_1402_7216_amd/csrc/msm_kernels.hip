@@ -1,10 +1,11 @@
 // gfx950 kernels of the multilevel summation method (thesis Sec. 2.3).
 //
-// Forward chain on one stream:
-//   zero -> bin_count -> scan -> bin_scatter -> bin_place        link cells (Sec. 2.1)
-//   short_range                                                   u^short, F^short
-//   anterpolate -> restrict (k = 0..l-2)                          q^0 .. q^{l-1}
-//   lattice (all k <= l-2 in one launch) + top (FP64)             u^{k,cut}
+// One evaluation:
+//   bin_count -> scan -> bin_scatter -> bin_place                 link cells (Sec. 2.1)
+//   short_range                        (side stream)              u^short, F^short
+//   anterpolate                                                   q^0
+//   lattice, level 0                   (side stream)              u^{0,cut}
+//   restrict (k = 0..l-2) -> lattice, levels 1..l-2 -> top (FP64) q^k, u^{k,cut}
 //   prolong (k = l-2..0)                                          u^k
 //   interpolate_assemble -> reduce                                phi, F, E, virial
 //
@@ -18,6 +19,17 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWave = 64;
+
+// Quotient and remainder of 0 <= i < 2^20 by 0 < d <= 2^10 with a float
+// reciprocal (inv_d = 1/d rounded): (i + 1/2)/d lies at least 1/(2d) away from
+// an integer, far more than the rounding error of (i + 1/2) * inv_d, so the
+// truncation is exact.  Replaces the long integer-division sequence for
+// runtime divisors in index arithmetic.
+__device__ __forceinline__ int fdiv(int i, int d, float inv_d, int& rem) {
+  const int q = (int)(((float)i + 0.5f) * inv_d);
+  rem = i - q * d;
+  return q;
+}
 
 // --------------------------------------------------------------------------
 // Grid coordinates.  t = (x - lo)/h; f = floor(t) clamped to [0, floor(len/h)];
@@ -265,32 +277,31 @@ __global__ void k_bin_place(KArgs A) {
 //   phi_i^s = sum_j q_j g*(r_ij),  F_i^s = -q_i sum_j q_j g*'(r_ij) (r_i - r_j)/r_ij
 //   g*(r) = 1/r - gamma(r/a)/a,  g*'(r)/r = -1/r^3 - gamma'(r/a)/(a^2 r)
 // One work item = a run of run_w cells along x in one cell row; its atoms are
-// contiguous in sorted order.  Lanes hold i atoms; j atoms are read with
-// wave-uniform loads (scalar cache).  The (2 reach + 1)^2 neighbour rows are
-// split over the 4 waves of the block and the partial sums added in a fixed
-// order through LDS.
+// contiguous in sorted order.  Lanes hold i atoms (64 at a time).  For each
+// neighbour row (the (2 reach + 1)^2 cell rows around the run) the j atoms
+// form one contiguous range, cut into chunks of 64; the block's 16 waves take
+// the (row, chunk) units in turn, stage the chunk through their own LDS slice
+// (one coalesced load) and read it back as wave-wide broadcasts.  The waves'
+// partial sums meet in LDS and are added in wave order.
 // --------------------------------------------------------------------------
+constexpr int kShortThreads = 512;
+constexpr int kShortWaves = kShortThreads / kWave;
+constexpr int kShortMaxRows = 25;                // (2 reach + 1)^2 with reach <= 2
+
 template <int M, bool FORCES>
-__global__ void __launch_bounds__(kBlock) k_short(KArgs A) {
+__global__ void __launch_bounds__(kShortThreads) k_short(KArgs A) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
   const Geom& g = S.g;
   const float4* __restrict__ sorted = S.d.sorted;
   const int* __restrict__ start = S.d.cell_start;
   float4* __restrict__ fshort = S.d.fshort;
-  __shared__ float4 red[kBlock];
-  __shared__ float4 jbuf[kBlock / kWave][kWave];
+  __shared__ float4 red[kShortWaves][kWave];
+  __shared__ float4 jbuf[kShortWaves][kWave];
+  __shared__ int row_j0[kShortMaxRows], row_j1[kShortMaxRows], unit0[kShortMaxRows + 1];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int run = blk % g.runs_x;
-  const int row = blk / g.runs_x;
-  const int cy = row % g.nc[1], cz = row / g.nc[1];
-  const int cx0 = run * g.run_w;
-  const int cx1 = min(cx0 + g.run_w, g.nc[0]) - 1;
-  const int rowbase = (cz * g.nc[1] + cy) * g.nc[0];
-  const int ib = start[rowbase + cx0], ie = start[rowbase + cx1 + 1];
-  const int R = g.reach, side = 2 * R + 1;
-  const int jx0 = max(cx0 - R, 0), jx1 = min(cx1 + R, g.nc[0] - 1);
+  const int n_items = g.runs_x * g.nc[1] * g.nc[2];
   const float a2 = g.a2, inv_a2 = g.inv_a2;
   float gc[M + 1], dc[M + 1];
 #pragma unroll
@@ -299,65 +310,101 @@ __global__ void __launch_bounds__(kBlock) k_short(KArgs A) {
     dc[k] = g.dcoef[k];
   }
   float4* jb_w = jbuf[wave];
+  // the launch has g.short_blocks blocks; work items are strided over them
+  for (int item = blk; item < n_items; item += g.short_blocks) {
+  __syncthreads();                                       // tables of the previous item are done
+  const int run = item % g.runs_x;
+  const int row = item / g.runs_x;
+  const int cy = row % g.nc[1], cz = row / g.nc[1];
+  const int cx0 = run * g.run_w;
+  const int cx1 = min(cx0 + g.run_w, g.nc[0]) - 1;
+  const int rowbase = (cz * g.nc[1] + cy) * g.nc[0];
+  const int ib = start[rowbase + cx0], ie = start[rowbase + cx1 + 1];
+  const int R = g.reach, side = 2 * R + 1, nrows = side * side;
+  const int jx0 = max(cx0 - R, 0), jx1 = min(cx1 + R, g.nc[0] - 1);
+  // neighbour rows: j range and the first (row, chunk) unit of each row
+  if (threadIdx.x < nrows) {
+    const int jy = cy + threadIdx.x % side - R, jz = cz + threadIdx.x / side - R;
+    int j0 = 0, j1 = 0;
+    if (jy >= 0 && jz >= 0 && jy < g.nc[1] && jz < g.nc[2]) {
+      const int jrow = (jz * g.nc[1] + jy) * g.nc[0];
+      j0 = start[jrow + jx0];
+      j1 = start[jrow + jx1 + 1];
+    }
+    row_j0[threadIdx.x] = j0;
+    row_j1[threadIdx.x] = j1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int u = 0;
+    for (int r = 0; r < nrows; ++r) {
+      unit0[r] = u;
+      u += (row_j1[r] - row_j0[r] + kWave - 1) / kWave;
+    }
+    unit0[nrows] = u;
+  }
+  __syncthreads();
+  const int n_units = unit0[nrows];
 
   for (int ic = ib; ic < ie; ic += kWave) {
     const int i = ic + lane;
     const float4 pi = (i < ie) ? sorted[i] : make_float4(3.0e30f, 3.0e30f, 3.0e30f, 0.f);
     float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;
-    for (int rr = wave; rr < side * side; rr += kBlock / kWave) {
-      const int jy = cy + rr % side - R, jz = cz + rr / side - R;
-      if (jy < 0 || jz < 0 || jy >= g.nc[1] || jz >= g.nc[2]) continue;
-      const int jrow = (jz * g.nc[1] + jy) * g.nc[0];
-      const int j0 = start[jrow + jx0], j1 = start[jrow + jx1 + 1];
-      for (int jc = j0; jc < j1; jc += kWave) {
-        // stage up to 64 j atoms in this wave's LDS slice (coalesced), then
-        // read them back as wave-wide broadcasts
-        const int nj = min(kWave, j1 - jc);
-        jb_w[lane] = (lane < nj) ? sorted[jc + lane] : make_float4(-3.0e30f, -3.0e30f, -3.0e30f, 0.f);
-        const int nj4 = (nj + 3) & ~3;
+    int r = 0;
+    for (int u = wave; u < n_units; u += kShortWaves) {
+      while (unit0[r + 1] <= u) ++r;                 // wave-uniform walk over the rows
+      const int jc = row_j0[r] + (u - unit0[r]) * kWave;
+      const int nj = min(kWave, row_j1[r] - jc);
+      // stage up to 64 j atoms in this wave's LDS slice (coalesced), then
+      // read them back as wave-wide broadcasts
+      jb_w[lane] = (lane < nj) ? sorted[jc + lane] : make_float4(-3.0e30f, -3.0e30f, -3.0e30f, 0.f);
+      const int nj4 = (nj + 3) & ~3;
 #pragma unroll 4
-        for (int t = 0; t < nj4; ++t) {
-          const float4 pj = jb_w[t];
-          const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-          const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-          if (r2 < a2 && r2 > 0.f) {
-            // hardware reciprocal square root plus one Newton step (the raw
-            // instruction's error is biased, which would bias the energy)
-            float ri = __builtin_amdgcn_rsqf(r2);
-            ri = fmaf(0.5f * ri, fmaf(-r2 * ri, ri, 1.f), ri);
-            const float ri2 = ri * ri;
-            const float s = r2 * inv_a2;
-            float gm = gc[M], dg = dc[M];
+      for (int t = 0; t < nj4; ++t) {
+        const float4 pj = jb_w[t];
+        const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        if (r2 < a2 && r2 > 0.f) {
+          // hardware reciprocal square root plus one Newton step (the raw
+          // instruction's error is biased, which would bias the energy)
+          float ri = __builtin_amdgcn_rsqf(r2);
+          ri = fmaf(0.5f * ri, fmaf(-r2 * ri, ri, 1.f), ri);
+          const float ri2 = ri * ri;
+          const float s = r2 * inv_a2;
+          float gm = gc[M], dg = dc[M];
 #pragma unroll
-            for (int k = M - 1; k >= 0; --k) gm = fmaf(gm, s, gc[k]);
+          for (int k = M - 1; k >= 0; --k) gm = fmaf(gm, s, gc[k]);
 #pragma unroll
-            for (int k = M - 1; k >= 1; --k) dg = fmaf(dg, s, dc[k]);
-            const float gs = ri - gm;                    // g*(r)
-            ap = fmaf(pj.w, gs, ap);
-            if (FORCES) {
-              const float fr = fmaf(ri, ri2, dg);        // -g*'(r)/r
-              const float wq = pj.w * fr;
-              ax = fmaf(wq, dx, ax);
-              ay = fmaf(wq, dy, ay);
-              az = fmaf(wq, dz, az);
-            }
+          for (int k = M - 1; k >= 1; --k) dg = fmaf(dg, s, dc[k]);
+          const float gs = ri - gm;                    // g*(r)
+          ap = fmaf(pj.w, gs, ap);
+          if (FORCES) {
+            const float fr = fmaf(ri, ri2, dg);        // -g*'(r)/r
+            const float wq = pj.w * fr;
+            ax = fmaf(wq, dx, ax);
+            ay = fmaf(wq, dy, ay);
+            az = fmaf(wq, dz, az);
           }
         }
       }
     }
-    red[threadIdx.x] = make_float4(ax, ay, az, ap);
+    red[wave][lane] = make_float4(ax, ay, az, ap);
     __syncthreads();
     if (wave == 0 && i < ie) {
-      float4 s0 = red[lane], s1 = red[lane + 64], s2 = red[lane + 128], s3 = red[lane + 192];
-      float qi = pi.w;
-      float4 o;
-      o.x = qi * (((s0.x + s1.x) + s2.x) + s3.x);
-      o.y = qi * (((s0.y + s1.y) + s2.y) + s3.y);
-      o.z = qi * (((s0.z + s1.z) + s2.z) + s3.z);
-      o.w = ((s0.w + s1.w) + s2.w) + s3.w;
-      fshort[i] = o;
+      float4 t = red[0][lane];
+#pragma unroll
+      for (int w = 1; w < kShortWaves; ++w) {
+        const float4 v = red[w][lane];
+        t.x += v.x;
+        t.y += v.y;
+        t.z += v.z;
+        t.w += v.w;
+      }
+      const float qi = pi.w;
+      fshort[i] = make_float4(qi * t.x, qi * t.y, qi * t.z, t.w);
     }
     __syncthreads();
+  }
   }
 }
 
@@ -587,7 +634,8 @@ __global__ void __launch_bounds__(kBlock) k_restrict(KArgs A, int k) {
 //   u^{k,cut}_mu = sum_{|n| < 2a/h} g^k(2^k h |n|) q^k_{mu+n} = 2^-k sum W(n) q^k_{mu+n}
 // with W(n) = g^0(h|n|) from the stencil table (rows of taps along z).
 // --------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_lattice(KArgs A) {
+// part 0: the nodes of level 0; part 1: the nodes of levels 1 .. l-2.
+__global__ void __launch_bounds__(kBlock) k_lattice(KArgs A, int part) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
   const Geom& g = S.g;
@@ -596,9 +644,10 @@ __global__ void __launch_bounds__(kBlock) k_lattice(KArgs A) {
   const float* __restrict__ wts = S.d.weights;
   const float* __restrict__ qgrid = S.d.qgrid;
   float* __restrict__ ucut = S.d.ucut;
-  const int n_lattice_nodes = g.lv[g.levels - 1].off;   // every node below the top level
-  int gid = blk * blockDim.x + threadIdx.x;
-  if (gid >= n_lattice_nodes) return;
+  const int first = part ? g.lv[1].off : 0;
+  const int end = part ? g.lv[g.levels - 1].off : g.lv[1].off;   // the top level is not included
+  int gid = first + blk * blockDim.x + threadIdx.x;
+  if (gid >= end) return;
   int k = 0;
   while (k + 1 < g.levels - 1 && gid >= g.lv[k + 1].off) ++k;
   const Level L = g.lv[k];
@@ -678,12 +727,14 @@ __device__ __forceinline__ void row_win_dispatch(int xr, float* acc, const float
   }
 }
 
+// part 0: the tiles of level 0; part 1: the tiles of levels 1 .. l-2.
 template <int B>
-__global__ void __launch_bounds__(kLatThreads) k_lattice_win(KArgs A) {
+__global__ void __launch_bounds__(kLatThreads) k_lattice_win(KArgs A, int part) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
   const Geom& g = S.g;
   const LatLaunch& P = S.lat;
+  if (part) blk += P.t[1].block0;
   const int4* __restrict__ rows_g = S.d.rows_c;
   const float* __restrict__ wc_g = S.d.weights_c;
   const float* __restrict__ qgrid = S.d.qgrid;
@@ -697,37 +748,45 @@ __global__ void __launch_bounds__(kLatThreads) k_lattice_win(KArgs A) {
   const LatTile T = P.t[li];
   const Level Lv = g.lv[T.level];
   bid -= T.block0;
-  const int bx = bid % T.ntx, by = (bid / T.ntx) % T.nty, bz = bid / (T.ntx * T.nty);
+  // block = (tile, row group); the group's rows have nz in [nz_lo, nz_hi]
+  const int G = T.groups;
+  const int grp = bid % G;
+  const int tile = bid / G;
+  const int r_lo = P.grp[G][grp], r_hi = P.grp[G][grp + 1];
+  const int nz_lo = r_lo < r_hi ? rows_g[r_lo].x : 0, nz_hi = r_lo < r_hi ? rows_g[r_hi - 1].x : 0;
+  const int bx = tile % T.ntx, by = (tile / T.ntx) % T.nty, bz = tile / (T.ntx * T.nty);
   const int H = P.H;
   const int x0 = bx * T.xl * B, y0 = by * T.ty, z0 = bz * T.tz;
-  const int WX = T.xl * B + 2 * H, PY = T.ty + 2 * H, WZ = T.tz + 2 * H, PX = T.px, PP = T.pp;
+  // window: planes z0 + nz_lo .. z0 + tz - 1 + nz_hi, rows y0 - H .., columns x0 - H ..
+  const int WX = T.xl * B + 2 * H, PY = T.ty + 2 * H, WZ = T.tz + nz_hi - nz_lo, PX = T.px, PP = T.pp;
   const float* qk = qgrid + Lv.off;
   const int NX = Lv.n[0], NY = Lv.n[1], NZ = Lv.n[2];
 
   for (int i = threadIdx.x; i < P.n_rows; i += kLatThreads) rows[i] = rows_g[i];
   for (int i = threadIdx.x; i < P.n_wc; i += kLatThreads) wc[i] = wc_g[i];
-  const int nwin = WZ * PY * WX;
+  const int nwin = WZ * PY * WX;                       // < 2^16 (bounded by the LDS budget)
+  const float inv_wx = 1.f / (float)WX, inv_py = 1.f / (float)PY;
   for (int i0 = 0; i0 < nwin; i0 += 8 * kLatThreads) {      // 8 loads in flight per thread
     float v[8];
+    int dst[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int i = i0 + u * kLatThreads + threadIdx.x;
       v[u] = 0.f;
+      dst[u] = -1;
       if (i < nwin) {
-        const int xx = i % WX, yy = (i / WX) % PY, zz = i / (WX * PY);
-        const int gx = x0 - H + xx, gy = y0 - H + yy, gz = z0 - H + zz;
+        int xx, yy;
+        const int r = fdiv(i, WX, inv_wx, xx);
+        const int zz = fdiv(r, PY, inv_py, yy);
+        dst[u] = zz * PP + yy * PX + xx;
+        const int gx = x0 - H + xx, gy = y0 - H + yy, gz = z0 + nz_lo + zz;
         if (gx >= 0 && gx < NX && gy >= 0 && gy < NY && gz >= 0 && gz < NZ)
           v[u] = qk[((size_t)gz * NY + gy) * NX + gx];
       }
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int i = i0 + u * kLatThreads + threadIdx.x;
-      if (i < nwin) {
-        const int xx = i % WX, yy = (i / WX) % PY, zz = i / (WX * PY);
-        win[zz * PP + yy * PX + xx] = v[u];
-      }
-    }
+    for (int u = 0; u < 8; ++u)
+      if (dst[u] >= 0) win[dst[u]] = v[u];
   }
   __syncthreads();
 
@@ -735,7 +794,7 @@ __global__ void __launch_bounds__(kLatThreads) k_lattice_win(KArgs A) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int xi = lane % T.xl, yi = (lane / T.xl) % T.ty, zi = lane / (T.xl * T.ty);
   const bool active = zi < T.tz;
-  const float* base = win + (zi + H) * PP + (yi + H) * PX + xi * B + H;
+  const float* base = win + (zi - nz_lo) * PP + (yi + H) * PX + xi * B + H;
   double tot[B];
   float acc[B];
 #pragma unroll
@@ -744,10 +803,10 @@ __global__ void __launch_bounds__(kLatThreads) k_lattice_win(KArgs A) {
     acc[b] = 0.f;
   }
   int cnt = 0;
-  int4 row = (wave < P.n_rows) ? rows[wave] : make_int4(0, 0, 0, 0);
-  for (int r = wave; r < P.n_rows; r += kLatWaves) {
+  int4 row = (r_lo + wave < r_hi) ? rows[r_lo + wave] : make_int4(0, 0, 0, 0);
+  for (int r = r_lo + wave; r < r_hi; r += kLatWaves) {
     const int4 cur = row;
-    if (r + kLatWaves < P.n_rows) row = rows[r + kLatWaves];       // next descriptor in flight
+    if (r + kLatWaves < r_hi) row = rows[r + kLatWaves];           // next descriptor in flight
     const int nz = __builtin_amdgcn_readfirstlane(cur.x);
     const int ny = __builtin_amdgcn_readfirstlane(cur.y);
     const int xr = __builtin_amdgcn_readfirstlane(cur.z);
@@ -780,16 +839,40 @@ __global__ void __launch_bounds__(kLatThreads) k_lattice_win(KArgs A) {
   if (wave == 0 && active) {
     const int y = y0 + yi, z = z0 + zi;
     if (y < NY && z < NZ) {
-      float* out = ucut + Lv.off + ((size_t)z * NY + y) * NX;
+      const size_t row0 = ((size_t)z * NY + y) * NX;
+      float* out = ucut + Lv.off + row0;
+      double* part = S.d.lat_part + T.part0 + (size_t)grp * Lv.count + row0;
 #pragma unroll
       for (int b = 0; b < B; ++b) {
         double v = 0.0;
         for (int w = 0; w < kLatWaves; ++w) v += red[((size_t)w * kWave + lane) * B + b];
         const int x = x0 + xi * B + b;
-        if (x < NX) out[x] = (float)ldexp(v, -T.level);
+        if (x < NX) {
+          if (G == 1)
+            out[x] = (float)ldexp(v, -T.level);
+          else
+            part[x] = v;
+        }
       }
     }
   }
+}
+
+// u^{k,cut} at node `node` of level k (level-local index): the stored value,
+// or, where the level's lattice tiles were split into row groups, the sum of
+// the groups' float64 partials in group order (stored back into u^{k,cut} so
+// the grid is complete after its first consumer).
+__device__ __forceinline__ float ucut_at(const SysDesc& S, int k, int node) {
+  const Level& L = S.g.lv[k];
+  float* __restrict__ ucut = S.d.ucut;
+  if (S.lat.b == 0 || k >= S.lat.n || S.lat.t[k].groups == 1) return ucut[L.off + node];
+  const LatTile& T = S.lat.t[k];
+  const double* part = S.d.lat_part + T.part0 + node;
+  double v = 0.0;
+  for (int gi = 0; gi < T.groups; ++gi) v += part[(size_t)gi * L.count];
+  const float u = (float)ldexp(v, -k);
+  ucut[L.off + node] = u;
+  return u;
 }
 
 // --------------------------------------------------------------------------
@@ -812,9 +895,11 @@ __global__ void __launch_bounds__(kBlock) k_top(KArgs A) {
   if (node >= L.count) return;
   const int mx = node % L.n[0], my = (node / L.n[0]) % L.n[1], mz = node / (L.n[0] * L.n[1]);
   const float* qt = qgrid + L.off;
+  const float inv_n0 = 1.f / (float)L.n[0], inv_n1 = 1.f / (float)L.n[1];
   double acc = 0.0;
   for (int v = lane; v < L.count; v += kWave) {
-    const int vx = v % L.n[0], vy = (v / L.n[0]) % L.n[1], vz = v / (L.n[0] * L.n[1]);
+    int vx, vy;
+    const int vz = fdiv(fdiv(v, L.n[0], inv_n0, vx), L.n[1], inv_n1, vy);
     const double t = T[((size_t)abs(mz - vz) * L.n[1] + abs(my - vy)) * L.n[0] + abs(mx - vx)];
     acc = fma(t, (double)qt[v], acc);
   }
@@ -841,7 +926,6 @@ __global__ void __launch_bounds__(kBlock) k_prolong(KArgs A, int k) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
   const Geom& g = S.g;
-  const float* __restrict__ ucut = S.d.ucut;
   float* __restrict__ u = S.d.u;
   using D = Dyadic<ORDER>;
   constexpr int R = D::R;
@@ -862,8 +946,9 @@ __global__ void __launch_bounds__(kBlock) k_prolong(KArgs A, int k) {
   const int tx = threadIdx.x % kPX, ty = (threadIdx.x / kPX) % kPY, tz = threadIdx.x / (kPX * kPY);
   const int fx = bx * kPX + tx, fy = by * kPY + ty, fz = bz * kPZ + tz;      // level-local
   const bool inside = tz < kPZ && fx < F.n[0] && fy < F.n[1] && fz < F.n[2];
-  const size_t o = F.off + ((size_t)fz * F.n[1] + fy) * F.n[0] + fx;
-  const float own = inside ? ucut[o] : 0.f;                                  // in flight with the staging
+  const int node = (fz * F.n[1] + fy) * F.n[0] + fx;
+  const size_t o = F.off + (size_t)node;
+  const float own = inside ? ucut_at(S, k, node) : 0.f;                    // in flight with the staging
   constexpr int ncs = VX * VY * VZ;
   float v[(ncs + kBlock - 1) / kBlock];
 #pragma unroll
@@ -1053,7 +1138,6 @@ __global__ void __launch_bounds__(kBlock) k_energy_terms(KArgs A) {
   const float4* __restrict__ sorted = S.d.sorted;
   const float4* __restrict__ fshort = S.d.fshort;
   const float* __restrict__ qgrid = S.d.qgrid;
-  const float* __restrict__ ucut = S.d.ucut;
   double* __restrict__ partials = S.d.partials;
   __shared__ double red[kBlock / kWave];
   const int stride = S.n_partials * blockDim.x;
@@ -1062,8 +1146,11 @@ __global__ void __launch_bounds__(kBlock) k_energy_terms(KArgs A) {
     const double q = (double)sorted[i].w;
     e += 0.5 * q * ((double)fshort[i].w - q * (double)g.self);
   }
-  for (int m = blk * blockDim.x + threadIdx.x; m < g.total_nodes; m += stride)
-    e += 0.5 * (double)qgrid[m] * (double)ucut[m];
+  for (int k = 0; k < g.levels; ++k) {
+    const Level& L = g.lv[k];
+    for (int m = blk * blockDim.x + threadIdx.x; m < L.count; m += stride)
+      e += 0.5 * (double)qgrid[L.off + m] * (double)ucut_at(S, k, m);
+  }
   e *= g.ke;
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) e += __shfl_xor(e, off);
@@ -1128,7 +1215,7 @@ SysBlocks system_blocks(const Geom& g, const LatLaunch& lat, int n_partials) {
   SysBlocks b{};
   b.zero = blocks_for(g.n_cells + 1);
   b.atoms = g.n_atoms > 0 ? blocks_for(g.n_atoms) : 0;
-  b.shortr = g.n_atoms > 0 ? g.runs_x * g.nc[1] * g.nc[2] : 0;
+  b.shortr = g.n_atoms > 0 ? g.short_blocks : 0;
   const Level& L0 = g.lv[0];
   b.anterp = ((L0.n[0] + kAX - 1) / kAX) * ((L0.n[1] + kAY - 1) / kAY) * ((L0.n[2] + kAZ - 1) / kAZ);
   for (int k = 0; k + 1 < g.levels; ++k) {
@@ -1137,11 +1224,17 @@ SysBlocks system_blocks(const Geom& g, const LatLaunch& lat, int n_partials) {
     const Level& F = g.lv[k];
     b.prolong[k] = ((F.n[0] + kPX - 1) / kPX) * ((F.n[1] + kPY - 1) / kPY) * ((F.n[2] + kPZ - 1) / kPZ);
   }
+  // lattice cutoff in two launches: level 0, and levels 1 .. l-2
   if (g.levels > 1) {
-    if (lat.b > 0)
-      b.lattice = lat.t[lat.n - 1].block0 + lat.t[lat.n - 1].ntx * lat.t[lat.n - 1].nty * lat.t[lat.n - 1].ntz;
-    else
-      b.lattice = blocks_for(g.lv[g.levels - 1].off);
+    if (lat.b > 0) {
+      const LatTile& t = lat.t[lat.n - 1];
+      const int total = t.block0 + t.ntx * t.nty * t.ntz * t.groups;
+      b.lattice0 = lat.n > 1 ? lat.t[1].block0 : total;
+      b.lattice = total - b.lattice0;
+    } else {
+      b.lattice0 = blocks_for(g.lv[1].off);
+      b.lattice = blocks_for(g.lv[g.levels - 1].off - g.lv[1].off);
+    }
   }
   b.top = blocks_for(g.lv[g.levels - 1].count * kWave);
   b.energy = n_partials;
@@ -1154,37 +1247,46 @@ hipError_t launch_init(const LaunchGeom& L, hipStream_t s) {
 }
 
 hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& io, hipEvent_t* ev,
-                       hipStream_t aux, hipEvent_t fork, hipEvent_t join) {
+                       const Concurrency* cc) {
   const bool forces = (mode != kModeEnergy);
   auto args = [&](const StageGrid& sg) { return KArgs{L.sys, sg.map, io}; };
   auto mark = [&](int stage) {
     if (ev) (void)hipEventRecord(ev[stage], s);
   };
-  mark(kStageBin);
+  // fork: `side` waits for everything enqueued on s so far
+  auto fork = [&](const SideStream& side) {
+    (void)hipEventRecord(side.fork, s);
+    (void)hipStreamWaitEvent(side.stream, side.fork, 0);
+  };
+  auto join = [&](const SideStream& side) { (void)hipStreamWaitEvent(s, side.join, 0); };
+  const bool concurrent = (cc != nullptr && ev == nullptr);   // stage timing runs in order
   const bool have_atoms = L.atoms.blocks > 0;
-  const bool par = (have_atoms && aux != nullptr && ev == nullptr);
+
+  mark(kStageBin);
   if (have_atoms) k_bin_count<<<L.atoms.blocks, kBlock, 0, s>>>(args(L.atoms));
   k_scan<<<L.one.blocks, 1024, 0, s>>>(args(L.one));
   if (have_atoms) {
     k_bin_scatter<<<L.atoms.blocks, kBlock, 0, s>>>(args(L.atoms));
     k_bin_place<<<L.atoms.blocks, kBlock, 0, s>>>(args(L.atoms));
   }
+
+  // short-range pairs: on their own stream, joined before interpolation
   mark(kStageShort);
+  const bool short_side = concurrent && have_atoms && L.shortr.blocks > 0;
   if (have_atoms && L.shortr.blocks > 0) {
     hipStream_t ss = s;
-    if (par) {
-      (void)hipEventRecord(fork, s);
-      (void)hipStreamWaitEvent(aux, fork, 0);
-      ss = aux;
+    if (short_side) {
+      fork(cc->shortr);
+      ss = cc->shortr.stream;
     }
     const KArgs A = args(L.shortr);
     const int nb = L.shortr.blocks;
 #define MSM_SHORT(MM)                                               \
   do {                                                              \
     if (forces)                                                     \
-      k_short<MM, true><<<nb, kBlock, 0, ss>>>(A);                  \
+      k_short<MM, true><<<nb, kShortThreads, 0, ss>>>(A);           \
     else                                                            \
-      k_short<MM, false><<<nb, kBlock, 0, ss>>>(A);                 \
+      k_short<MM, false><<<nb, kShortThreads, 0, ss>>>(A);          \
   } while (0)
     switch (L.m) {
       case 1: MSM_SHORT(1); break;
@@ -1196,13 +1298,44 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
       default: MSM_SHORT(7); break;
     }
 #undef MSM_SHORT
-    if (par) (void)hipEventRecord(join, aux);
+    if (short_side) (void)hipEventRecord(cc->shortr.join, ss);
   }
+
   mark(kStageAnterp);
   if (L.order == 4)
     k_anterp<4><<<L.anterp.blocks, kBlock, 0, s>>>(args(L.anterp));
   else
     k_anterp<6><<<L.anterp.blocks, kBlock, 0, s>>>(args(L.anterp));
+
+  // lattice cutoff of one part (0: level 0, 1: levels 1 .. l-2) on stream `ls`
+  auto lattice = [&](const StageGrid& sg, int part, hipStream_t ls) {
+    if (sg.blocks == 0) return;
+    const KArgs A = args(sg);
+    const int nb = sg.blocks;
+    if (L.lat_b == 4) {
+      (void)hipFuncSetAttribute((const void*)k_lattice_win<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                L.lat_lds);
+      k_lattice_win<4><<<nb, kLatThreads, L.lat_lds, ls>>>(A, part);
+    } else if (L.lat_b == 6) {
+      (void)hipFuncSetAttribute((const void*)k_lattice_win<6>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                L.lat_lds);
+      k_lattice_win<6><<<nb, kLatThreads, L.lat_lds, ls>>>(A, part);
+    } else if (L.lat_b == 8) {
+      (void)hipFuncSetAttribute((const void*)k_lattice_win<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                L.lat_lds);
+      k_lattice_win<8><<<nb, kLatThreads, L.lat_lds, ls>>>(A, part);
+    } else {
+      k_lattice<<<nb, kBlock, 0, ls>>>(A, part);
+    }
+  };
+  // level 0 needs only the anterpolated charges: it overlaps the coarse chain
+  const bool lat0_side = concurrent && L.lattice0.blocks > 0;
+  if (lat0_side) {
+    fork(cc->lattice0);
+    lattice(L.lattice0, 0, cc->lattice0.stream);
+    (void)hipEventRecord(cc->lattice0.join, cc->lattice0.stream);
+  }
+
   mark(kStageRestrict);
   for (int k = 0; k + 1 < L.max_levels; ++k) {
     const StageGrid& sg = L.restrict_[k];
@@ -1213,38 +1346,26 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
       k_restrict<6><<<sg.blocks, kBlock, 0, s>>>(args(sg), k);
   }
   mark(kStageLattice);
-  if (L.lattice.blocks > 0) {
-    const KArgs A = args(L.lattice);
-    const int nb = L.lattice.blocks;
-    if (L.lat_b == 4) {
-      (void)hipFuncSetAttribute((const void*)k_lattice_win<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                L.lat_lds);
-      k_lattice_win<4><<<nb, kLatThreads, L.lat_lds, s>>>(A);
-    } else if (L.lat_b == 6) {
-      (void)hipFuncSetAttribute((const void*)k_lattice_win<6>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                L.lat_lds);
-      k_lattice_win<6><<<nb, kLatThreads, L.lat_lds, s>>>(A);
-    } else if (L.lat_b == 8) {
-      (void)hipFuncSetAttribute((const void*)k_lattice_win<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                L.lat_lds);
-      k_lattice_win<8><<<nb, kLatThreads, L.lat_lds, s>>>(A);
-    } else {
-      k_lattice<<<nb, kBlock, 0, s>>>(A);
-    }
-  }
+  if (!lat0_side) lattice(L.lattice0, 0, s);
+  lattice(L.lattice, 1, s);
   mark(kStageTop);
   k_top<<<L.top.blocks, kBlock, 0, s>>>(args(L.top));
-  mark(kStageProlong);
+
   if (mode == kModeEnergy) {
+    mark(kStageProlong);
     mark(kStageInterp);
-    if (par) (void)hipStreamWaitEvent(s, join, 0);
+    if (lat0_side) join(cc->lattice0);
+    if (short_side) join(cc->shortr);
     mark(kStageReduce);
     k_energy_terms<<<L.energy.blocks, kBlock, 0, s>>>(args(L.energy));
     k_reduce<<<L.one.blocks, kBlock, 0, s>>>(args(L.one), 0);
     mark(kStageCount);
     return hipGetLastError();
   }
+
+  mark(kStageProlong);
   for (int k = L.max_levels - 2; k >= 0; --k) {
+    if (k == 0 && lat0_side) join(cc->lattice0);     // u^0 adds the level-0 cutoff potential
     const StageGrid& sg = L.prolong[k];
     if (sg.blocks == 0) continue;
     if (L.order == 4)
@@ -1253,8 +1374,8 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
       k_prolong<6><<<sg.blocks, kBlock, 0, s>>>(args(sg), k);
   }
   mark(kStageInterp);
+  if (short_side) join(cc->shortr);
   if (have_atoms) {
-    if (par) (void)hipStreamWaitEvent(s, join, 0);
     const KArgs A = args(L.atoms);
     const int nb = L.atoms.blocks;
     if (mode == kModeGradient) {

@@ -13,11 +13,9 @@
 using msm::Geom;
 using msm::Layout;
 
-// Auxiliary stream and fork/join events for the concurrent short-range pass.
+// Side streams and fork/join events of the concurrent branches of an evaluation.
 struct AuxStreams {
-  hipStream_t stream = nullptr;
-  hipEvent_t fork = nullptr;
-  hipEvent_t join = nullptr;
+  msm::Concurrency cc;
   int device = -1;
 };
 
@@ -32,6 +30,8 @@ struct msm_plan {
   int n_partials = 1;
   msm::LatLaunch lat;
   int lat_tables = 0;                        // LDS bytes of the compact stencil tables
+  int lat_part_max = 0;                      // lattice row-group partials of the largest tuning
+  int short_cap = 0;                         // short-range blocks (0: one per work item)
   Layout lay;
   msm::SysDesc desc;                         // host copy; device pointers filled per workspace
   msm::LaunchGeom lg;                        // stage grids of one evaluation (descriptor set per call)
@@ -57,9 +57,9 @@ msm::DevPtrs dev_ptrs(const msm_plan* P, void* ws);
 // Recompute the host descriptor and stage grids after a tuning change.
 void refresh_launch(msm_plan* P);
 // Apply tuning knobs (0 keeps the current value): lattice outputs per lane
-// (4, 6 or 8) and short-range cells per work item.  Host-side only; the
-// caller re-uploads descriptors.
-void retune(msm_plan* P, int lat_b, int run_w);
+// (4, 6 or 8), short-range cells per work item, and short-range blocks
+// (-1: one per work item).  Host-side only; the caller re-uploads descriptors.
+void retune(msm_plan* P, int lat_b, int run_w, int short_blocks);
 // Capture the work `launch` enqueues on a private stream into an instantiated graph.
 template <class F>
 msm_status capture_graph(F launch, msm_graph** out) {

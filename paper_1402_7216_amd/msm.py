@@ -78,7 +78,7 @@ def lib():
         L.msm_graph_capture.argtypes = [vp, vp, sz] + [vp] * 10 + [ctypes.POINTER(vp)]
         L.msm_graph_launch.argtypes = [vp, vp]
         L.msm_graph_destroy.argtypes = [vp]
-        L.msm_plan_tune.argtypes = [vp, vp, sz, vp, i32, i32]
+        L.msm_plan_tune.argtypes = [vp, vp, sz, vp, i32, i32, i32]
         L.msm_plan_autotune.argtypes = [vp, vp, sz, vp] + [vp] * 4 + [i32, ctypes.c_char_p, sz]
         L.msm_batch_create.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(i32), i32, ctypes.POINTER(vp)]
         L.msm_batch_destroy.argtypes = [vp]
@@ -91,7 +91,7 @@ def lib():
         L.msm_batch_graph_capture.argtypes = [vp, vp, sz] + [vp] * 10 + [ctypes.POINTER(vp)]
         L.msm_batch_status.argtypes = [vp, vp, vp, ctypes.POINTER(i32)]
         L.msm_batch_describe.argtypes = [vp, ctypes.c_char_p, sz]
-        L.msm_batch_tune.argtypes = [vp, vp, sz, vp, i32, i32]
+        L.msm_batch_tune.argtypes = [vp, vp, sz, vp, i32, i32, i32]
         L.msm_batch_autotune.argtypes = [vp, vp, sz, vp] + [vp] * 4 + [i32, ctypes.c_char_p, sz]
         L.msm_status_string.argtypes = [i32]
         L.msm_status_string.restype = ctypes.c_char_p
@@ -211,9 +211,9 @@ class Plan:
                                   _ptr(z), _ptr(q), _ptr(g), _ptr(dx), _ptr(dy), _ptr(dz), _ptr(dq)))
         return dpos, dq
 
-    def tune(self, lattice_b=0, run_w=0):
+    def tune(self, lattice_b=0, run_w=0, short_blocks=0):
         _check(lib().msm_plan_tune(self._h, _ptr(self.ws), self.ws.numel(), _stream(), int(lattice_b),
-                                   int(run_w)))
+                                   int(run_w), int(short_blocks)))
 
     def autotune(self, x, y, z, q, trials=5):
         """Time the tuning candidates on these inputs, keep the fastest, return the search."""
@@ -399,9 +399,9 @@ class Batch:
         code, _ = self.status()
         _check(code)
 
-    def tune(self, lattice_b=0, run_w=0):
+    def tune(self, lattice_b=0, run_w=0, short_blocks=0):
         _check(lib().msm_batch_tune(self._h, _ptr(self.ws), self.ws.numel(), _stream(), int(lattice_b),
-                                    int(run_w)))
+                                    int(run_w), int(short_blocks)))
 
     def autotune(self, x, y, z, q, trials=3):
         import json

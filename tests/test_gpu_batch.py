@@ -79,14 +79,15 @@ def test_every_replica_matches_oracle(M, batch64, replicas):
 
 
 def test_batch_equals_single_system_path_bitwise(M, batch64, replicas):
-    """With the batch's tiles (lattice template and short-range run width) the
-    single-system path performs the same arithmetic in the same order."""
+    """With the batch's tiles (lattice template and the system's short-range
+    run width) the single-system path performs the same arithmetic in the same
+    order."""
     b, _, out = batch64
     d = b.describe()
     for s in list(range(0, 64, 7)) + [63]:
         sys_ = replicas[s]
         plan = M.plan_for(sys_)
-        plan.tune(d["lattice_b"], d["run_w"])
+        plan.tune(d["lattice_b"], d["run_ws"][s])
         o = plan.compute(*M.to_device(sys_), virial=True)
         torch.cuda.synchronize()
         a, e = b.offsets[s], b.offsets[s + 1]
@@ -182,7 +183,7 @@ def test_autotune_keeps_results_within_bars(M):
     x, y, z, q = M.batch_to_device(systems)
     rep = b.autotune(x, y, z, q, trials=2)
     print(f"case batch autotune: best {rep['best']} of {len(rep['candidates'])}", flush=True)
-    assert len(rep["candidates"]) in (3, 9)
+    assert len(rep["candidates"]) in (7, 13)
     best = rep["best"]
     assert best["ms"] == min(c["ms"] for c in rep["candidates"])
     d = b.describe()
