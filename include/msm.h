@@ -174,19 +174,30 @@ msm_status msm_profile_enable(msm_plan* plan, int32_t enable);
 msm_status msm_profile_read(const msm_plan* plan, float* ms, int32_t* n_stages);
 
 /* ------------------------------------------------------------------------ */
-/* Tuning.  msm_plan_tune sets the lattice-cutoff outputs per lane (4, 6 or 8;
- * 0 keeps the current value), the short-range cells per work item (>= 1; 0
- * keeps it) and the number of blocks the short-range work items are strided
- * over (> 0; -1 = one block per work item; 0 keeps it; fewer blocks leave
- * compute units to the concurrent grid chain), and re-uploads the plan's
- * descriptor to ws (other workspaces of the plan must be initialised again).
- * Results depend on the tuning only through float32 summation order.
- * msm_plan_autotune times candidates over `trials` evaluations of the given
- * device inputs on `stream` with HIP events: (4, 6, 8) x (1, 2, 3) cells
- * first, then short-range block counts for the best pair; it applies the
- * fastest and writes a JSON report (nullable) of the search. */
+/* Tuning knobs.  Results depend on them only through float32 summation
+ * order.  In msm_plan_tune / msm_batch_tune a zero field keeps the current
+ * value. */
+typedef struct msm_tuning {
+  int32_t lattice_b;     /* lattice-cutoff outputs per lane along x: 4, 6 or 8 */
+  int32_t item_chunks;   /* short-range 64-atom chunks of a cell row per work item (>= 1) */
+  int32_t short_blocks;  /* blocks the short-range work items are strided over
+                            (> 0), or -1 for one block per work item */
+  int32_t streams;       /* 1: every stage in order on the caller's stream;
+                            2: the short-range pass on a side stream;
+                            3: also the level-0 lattice cutoff on a side stream */
+  int32_t reserved[4];   /* must be zero */
+} msm_tuning;
+
+/* Apply tuning knobs to a plan and re-upload its descriptor to ws (other
+ * workspaces of the plan must be initialised again).  msm_plan_autotune times
+ * candidates over `trials` evaluations of the given device inputs on `stream`
+ * with HIP events: lattice_b (4, 6, 8) x item_chunks (1, 2, 3) first, then the
+ * stream layout and short-range block counts for the best pair; it applies
+ * the fastest and writes a JSON report (nullable) of the search.  *current
+ * (msm_plan_tuning, nullable) receives the tuning in effect. */
 msm_status msm_plan_tune(msm_plan* plan, void* ws, size_t ws_bytes, msm_stream_t stream,
-                         int32_t lattice_b, int32_t run_w, int32_t short_blocks);
+                         const msm_tuning* tuning);
+msm_status msm_plan_tuning(const msm_plan* plan, msm_tuning* current);
 msm_status msm_plan_autotune(msm_plan* plan, void* ws, size_t ws_bytes, msm_stream_t stream,
                              const float* x, const float* y, const float* z, const float* q,
                              int32_t trials, char* report, size_t report_bytes);
@@ -232,7 +243,7 @@ msm_status msm_batch_describe(const msm_batch* batch, char* buf, size_t buf_byte
 /* Tuning of every system of the batch (same knobs as msm_plan_tune; the
  * short-range block count applies per system). */
 msm_status msm_batch_tune(msm_batch* batch, void* ws, size_t ws_bytes, msm_stream_t stream,
-                          int32_t lattice_b, int32_t run_w, int32_t short_blocks);
+                          const msm_tuning* tuning);
 msm_status msm_batch_autotune(msm_batch* batch, void* ws, size_t ws_bytes, msm_stream_t stream,
                               const float* x, const float* y, const float* z, const float* q,
                               int32_t trials, char* report, size_t report_bytes);

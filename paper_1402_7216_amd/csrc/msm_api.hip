@@ -298,8 +298,11 @@ void refresh_launch(msm_plan* P) {
   lg.lat_b = P->lat.b;
   lg.lat_lds = P->lat.lds_bytes;
   lg.max_levels = g.levels;
+  lg.streams = P->streams;
   lg.zero.blocks = sb.zero;
   lg.atoms.blocks = sb.atoms;
+  lg.bin.blocks = sb.bin;
+  lg.bin4 = g.bin_blocks == 0;
   lg.one.blocks = 1;
   lg.shortr.blocks = sb.shortr;
   lg.anterp.blocks = sb.anterp;
@@ -313,22 +316,44 @@ void refresh_launch(msm_plan* P) {
   }
 }
 
+// Short-range work items: each cell row's atoms are cut into 64-atom chunks;
+// a row has row_items work items, item k taking chunks k, k + row_items, ...
+// (sized for the row's expected atom count, so each item gets about
+// item_chunks chunks; longer rows are still covered).
+void set_row_items(Geom& g, int item_chunks) {
+  g.item_chunks = std::max(1, item_chunks);
+  const double per_row = (double)g.n_atoms / ((double)g.nc[1] * g.nc[2]);
+  const int chunks = std::max(1, (int)std::ceil(per_row / 64.0));
+  g.row_items = std::max(1, (chunks + g.item_chunks - 1) / g.item_chunks);
+}
+
 void set_short_blocks(Geom& g, int cap) {
-  const int items = g.runs_x * g.nc[1] * g.nc[2];
+  const int items = g.row_items * g.nc[1] * g.nc[2];
   g.short_blocks = cap > 0 ? std::min(cap, items) : items;
 }
 
-void retune(msm_plan* P, int lat_b, int run_w, int short_blocks) {
-  if (lat_b && P->lat.b && lat_b != P->lat.b)
-    choose_lattice_tiles(P->g, P->rows_c, (int)P->weights.size(), P->lat.H, P->lat_tables, P->lat, lat_b);
+void retune(msm_plan* P, const msm_tuning& t) {
+  if (t.lattice_b && P->lat.b && t.lattice_b != P->lat.b)
+    choose_lattice_tiles(P->g, P->rows_c, (int)P->weights.size(), P->lat.H, P->lat_tables, P->lat,
+                         t.lattice_b);
   Geom& g = P->g;
-  if (run_w > 0) {
-    g.run_w = std::max(1, std::min(run_w, g.nc[0]));
-    g.runs_x = (g.nc[0] + g.run_w - 1) / g.run_w;
-  }
-  if (short_blocks != 0) P->short_cap = short_blocks < 0 ? 0 : short_blocks;
+  if (t.item_chunks > 0) set_row_items(g, t.item_chunks);
+  if (t.short_blocks != 0) P->short_cap = t.short_blocks < 0 ? 0 : t.short_blocks;
+  if (t.streams != 0) P->streams = t.streams;
   set_short_blocks(g, P->short_cap);
   refresh_launch(P);
+}
+
+msm_status check_tuning(const msm_tuning* t) {
+  if (!t) return fail(MSM_ERR_INVALID_ARG, "null tuning");
+  if (t->lattice_b != 0 && t->lattice_b != 4 && t->lattice_b != 6 && t->lattice_b != 8)
+    return fail(MSM_ERR_INVALID_ARG, "lattice_b must be 0, 4, 6 or 8");
+  if (t->item_chunks < 0) return fail(MSM_ERR_INVALID_ARG, "item_chunks must be >= 0");
+  if (t->short_blocks < -1) return fail(MSM_ERR_INVALID_ARG, "short_blocks must be >= -1");
+  if (t->streams < 0 || t->streams > 3) return fail(MSM_ERR_INVALID_ARG, "streams must be 0 .. 3");
+  for (int32_t r : t->reserved)
+    if (r != 0) return fail(MSM_ERR_INVALID_ARG, "reserved tuning fields must be zero");
+  return MSM_OK;
 }
 
 msm::DevPtrs dev_ptrs(const msm_plan* P, void* ws) {
@@ -347,6 +372,7 @@ msm::DevPtrs dev_ptrs(const msm_plan* P, void* ws) {
   d.cursor = reinterpret_cast<int*>(b + o[msm::kSecCursor]);
   d.cell_of = reinterpret_cast<int*>(b + o[msm::kSecCellOf]);
   d.tmp = reinterpret_cast<int*>(b + o[msm::kSecTmp]);
+  d.bin_hist = reinterpret_cast<int*>(b + o[msm::kSecBinHist]);
   d.rows = reinterpret_cast<const msm::StencilRow*>(b + o[msm::kSecRows]);
   d.weights = reinterpret_cast<const float*>(b + o[msm::kSecWeights]);
   d.rows_c = reinterpret_cast<const int4*>(b + o[msm::kSecRowsC]);
@@ -496,10 +522,13 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
     nct = set_cells(1, std::max(amargin, std::cbrt(vol / (double)cap)));
   }
   g.n_cells = (int)nct;
-  double per_cell = (double)n_atoms / (double)g.n_cells;
-  int w = (int)std::lround(48.0 / std::max(per_cell, 1e-3));
-  g.run_w = std::max(1, std::min(w, g.nc[0]));
-  g.runs_x = (g.nc[0] + g.run_w - 1) / g.run_w;
+  // two-kernel binning when the cell counts of every block fit (LDS, histogram size)
+  {
+    const long long nb = (n_atoms + msm::kBinChunk - 1) / msm::kBinChunk;
+    g.bin_blocks = (n_atoms > 0 && g.n_cells <= msm::kBinMaxCells && nb * g.n_cells <= msm::kBinMaxHist)
+                       ? (int)nb : 0;
+  }
+  set_row_items(g, 1);
   set_short_blocks(g, P->short_cap);
 
   // lattice-cutoff stencil: W(n) = g^0(h |n|) for h |n| < 2a, rows along z
@@ -603,6 +632,7 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
   lay.bytes[msm::kSecCursor] = (size_t)g.n_cells * sizeof(int);
   lay.bytes[msm::kSecCellOf] = n * sizeof(int);
   lay.bytes[msm::kSecTmp] = n * sizeof(int);
+  lay.bytes[msm::kSecBinHist] = std::max<size_t>((size_t)g.bin_blocks * g.n_cells, 1) * sizeof(int);
   lay.bytes[msm::kSecRows] = std::max<size_t>(P->rows.size(), 1) * sizeof(msm::StencilRow);
   lay.bytes[msm::kSecWeights] = std::max<size_t>(P->weights.size(), 1) * sizeof(float);
   lay.bytes[msm::kSecRowsC] = std::max<size_t>(P->rows_c.size(), 1) * sizeof(int4);
@@ -675,7 +705,9 @@ msm_status msm_plan_describe(const msm_plan* P, char* buf, size_t buf_bytes) {
   o += "\"levels\": " + std::to_string(g.levels);
   o += ", \"cells\": [" + std::to_string(g.nc[0]) + ", " + std::to_string(g.nc[1]) + ", " +
        std::to_string(g.nc[2]) + "], \"reach\": " + std::to_string(g.reach) +
-       ", \"run_w\": " + std::to_string(g.run_w) + ", \"short_blocks\": " + std::to_string(g.short_blocks);
+       ", \"bin_blocks\": " + std::to_string(g.bin_blocks) +
+       ", \"item_chunks\": " + std::to_string(g.item_chunks) + ", \"short_blocks\": " + std::to_string(g.short_blocks) +
+       ", \"streams\": " + std::to_string(P->streams);
   o += ", \"taps\": " + std::to_string(P->weights.size()) + ", \"halo\": " + std::to_string(P->lat.H);
   o += ", \"lattice_b\": " + std::to_string(P->lat.b) + ", \"lattice_lds\": " +
        std::to_string(P->lat.lds_bytes) + ", \"lattice_tiles\": [";

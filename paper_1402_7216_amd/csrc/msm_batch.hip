@@ -18,7 +18,7 @@ namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-constexpr int kNumStages = 9 + 2 * msm::kMaxLevels;
+constexpr int kNumStages = 10 + 2 * msm::kMaxLevels;
 
 }  // namespace
 
@@ -45,7 +45,7 @@ namespace {
 
 // Stage order inside the map arrays.
 enum : int {
-  kMZero = 0, kMAtoms, kMOne, kMShort, kMAnterp, kMLattice0, kMLattice, kMTop, kMEnergy, kMRestrict0,
+  kMZero = 0, kMAtoms, kMBin, kMOne, kMShort, kMAnterp, kMLattice0, kMLattice, kMTop, kMEnergy, kMRestrict0,
   kMProlong0 = kMRestrict0 + msm::kMaxLevels
 };
 
@@ -53,6 +53,7 @@ msm::StageGrid* stage_of(msm::LaunchGeom& L, int st) {
   switch (st) {
     case kMZero: return &L.zero;
     case kMAtoms: return &L.atoms;
+    case kMBin: return &L.bin;
     case kMOne: return &L.one;
     case kMShort: return &L.shortr;
     case kMAnterp: return &L.anterp;
@@ -70,6 +71,7 @@ int blocks_of(const msm::SysBlocks& b, int st) {
   switch (st) {
     case kMZero: return b.zero;
     case kMAtoms: return b.atoms;
+    case kMBin: return b.bin;
     case kMOne: return 1;
     case kMShort: return b.shortr;
     case kMAnterp: return b.anterp;
@@ -90,10 +92,13 @@ void rebuild_maps(msm_batch* Bt) {
   L.n_sys = Bt->n_sys;
   L.order = Bt->plans[0]->g.order;
   L.m = Bt->plans[0]->g.m;
+  L.streams = Bt->plans[0]->streams;
   L.lat_b = 0;
+  L.bin4 = false;
   for (int st = 0; st < kNumStages; ++st) Bt->map[st].clear();
   for (int s = 0; s < Bt->n_sys; ++s) {
     const msm_plan* P = Bt->plans[s];
+    if (P->g.bin_blocks == 0) L.bin4 = true;
     L.max_levels = std::max(L.max_levels, P->g.levels);
     L.lat_b = std::max(L.lat_b, P->lat.b);
     L.lat_lds = std::max(L.lat_lds, P->lat.lds_bytes);
@@ -203,7 +208,7 @@ msm_status msm_batch_create(const msm_params* params, const int32_t* n_atoms, in
   for (int s = 1; s < n_sys; ++s)
     if (n_atoms[s] > n_atoms[big]) big = s;
   const int b0 = Bt->plans[big]->lat.b;
-  for (msm_plan* P : Bt->plans) retune(P, b0, 0, 0);
+  for (msm_plan* P : Bt->plans) retune(P, msm_tuning{b0, 0, 0, 0, {}});
 
   // stage-table reserves: the most blocks any tuning can ask for
   // (lattice template 4, one cell per short-range work item)
@@ -214,8 +219,8 @@ msm_status msm_batch_create(const msm_params* params, const int32_t* n_atoms, in
     const int keep_cap = P->short_cap;
     size_t most[kNumStages] = {};
     for (int b : {4, 6, 8})
-      for (int w : {1, keep_g.run_w}) {
-        retune(P, P->lat.b ? b : 0, w, -1);        // one short-range block per work item: the most
+      for (int w : {1, keep_g.item_chunks}) {
+        retune(P, msm_tuning{P->lat.b ? b : 0, w, -1, 0, {}});   // one short-range block per item: the most
         const msm::SysBlocks sb = msm::system_blocks(P->g, P->lat, P->n_partials);
         for (int st = 0; st < kNumStages; ++st) most[st] = std::max(most[st], (size_t)blocks_of(sb, st));
       }
@@ -360,15 +365,15 @@ msm_status msm_batch_describe(const msm_batch* Bt, char* buf, size_t buf_bytes) 
                   ", \"max_levels\": " + std::to_string(L.max_levels) +
                   ", \"lattice_b\": " + std::to_string(L.lat_b) +
                   ", \"lattice_lds\": " + std::to_string(L.lat_lds) +
-                  ", \"run_w\": " + std::to_string(Bt->plans[0]->g.run_w) +   // first system's
+                  ", \"item_chunks\": " + std::to_string(Bt->plans[0]->g.item_chunks) +   // first system's
                   ", \"blocks\": {\"atoms\": " + std::to_string(L.atoms.blocks) +
                   ", \"short\": " + std::to_string(L.shortr.blocks) +
                   ", \"anterp\": " + std::to_string(L.anterp.blocks) +
                   ", \"lattice\": " + std::to_string(L.lattice0.blocks + L.lattice.blocks) +
                   ", \"top\": " + std::to_string(L.top.blocks) + "}, \"levels\": [";
   for (int s = 0; s < Bt->n_sys; ++s) o += (s ? ", " : "") + std::to_string(Bt->plans[s]->g.levels);
-  o += "], \"run_ws\": [";
-  for (int s = 0; s < Bt->n_sys; ++s) o += (s ? ", " : "") + std::to_string(Bt->plans[s]->g.run_w);
+  o += "], \"item_chunks_all\": [";
+  for (int s = 0; s < Bt->n_sys; ++s) o += (s ? ", " : "") + std::to_string(Bt->plans[s]->g.item_chunks);
   o += "], \"workspace_bytes\": " + std::to_string(Bt->total) + "}";
   std::strncpy(buf, o.c_str(), buf_bytes - 1);
   buf[buf_bytes - 1] = 0;
@@ -379,16 +384,20 @@ msm_status msm_batch_describe(const msm_batch* Bt, char* buf, size_t buf_bytes) 
 // Tuning knobs and the autotuner
 // ---------------------------------------------------------------------------
 
-msm_status msm_plan_tune(msm_plan* P, void* ws, size_t ws_bytes, msm_stream_t stream, int32_t lattice_b,
-                         int32_t run_w, int32_t short_blocks) {
+msm_status msm_plan_tuning(const msm_plan* P, msm_tuning* t) {
+  if (!P || !t) return fail(MSM_ERR_INVALID_ARG, "null plan or tuning");
+  *t = msm_tuning{P->lat.b, P->g.item_chunks, P->short_cap > 0 ? P->short_cap : -1, P->streams, {}};
+  return MSM_OK;
+}
+
+msm_status msm_plan_tune(msm_plan* P, void* ws, size_t ws_bytes, msm_stream_t stream,
+                         const msm_tuning* t) {
   if (!P) return fail(MSM_ERR_INVALID_ARG, "null plan");
-  if (lattice_b != 0 && lattice_b != 4 && lattice_b != 6 && lattice_b != 8)
-    return fail(MSM_ERR_INVALID_ARG, "lattice_b must be 0, 4, 6 or 8");
-  if (run_w < 0) return fail(MSM_ERR_INVALID_ARG, "run_w must be >= 0");
-  if (short_blocks < -1) return fail(MSM_ERR_INVALID_ARG, "short_blocks must be >= -1");
+  msm_status cs = check_tuning(t);
+  if (cs != MSM_OK) return cs;
   if (!ws || ws_bytes < P->lay.total || !P->ready.count(ws))
     return fail(MSM_ERR_WORKSPACE, "workspace not initialised for this plan");
-  retune(P, lattice_b, run_w, short_blocks);
+  retune(P, *t);
   P->desc.d = dev_ptrs(P, ws);
   // other workspaces now hold stale descriptors
   P->ready.clear();
@@ -402,14 +411,12 @@ msm_status msm_plan_tune(msm_plan* P, void* ws, size_t ws_bytes, msm_stream_t st
 }
 
 msm_status msm_batch_tune(msm_batch* Bt, void* ws, size_t ws_bytes, msm_stream_t stream,
-                          int32_t lattice_b, int32_t run_w, int32_t short_blocks) {
+                          const msm_tuning* t) {
   msm_status st = check_batch(Bt, ws, ws_bytes);
   if (st != MSM_OK) return st;
-  if (lattice_b != 0 && lattice_b != 4 && lattice_b != 6 && lattice_b != 8)
-    return fail(MSM_ERR_INVALID_ARG, "lattice_b must be 0, 4, 6 or 8");
-  if (run_w < 0) return fail(MSM_ERR_INVALID_ARG, "run_w must be >= 0");
-  if (short_blocks < -1) return fail(MSM_ERR_INVALID_ARG, "short_blocks must be >= -1");
-  for (msm_plan* P : Bt->plans) retune(P, lattice_b, run_w, short_blocks);
+  st = check_tuning(t);
+  if (st != MSM_OK) return st;
+  for (msm_plan* P : Bt->plans) retune(P, *t);
   rebuild_maps(Bt);
   Bt->ready.clear();
   st = upload_tables(Bt, ws, reinterpret_cast<hipStream_t>(stream));
@@ -419,7 +426,7 @@ msm_status msm_batch_tune(msm_batch* Bt, void* ws, size_t ws_bytes, msm_stream_t
 }
 
 // Time candidates over `trials` evaluations of the given inputs with HIP
-// events on `stream`: lattice_b in {4, 6, 8} x run_w in {1, 2, 3} with the
+// events on `stream`: lattice_b in {4, 6, 8} x item_chunks in {1, 2, 3} with the
 // current short-range block count, then short-range block counts for the best
 // pair.  Apply the fastest and describe the search in `report` (JSON, nullable).
 static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm_stream_t stream,
@@ -434,9 +441,9 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
   msm_batch* Bt = batch ? static_cast<msm_batch*>(obj) : nullptr;
   msm_plan* P = batch ? nullptr : static_cast<msm_plan*>(obj);
   const bool tiled = batch ? Bt->lg.lat_b > 0 : P->lat.b > 0;
-  auto tune = [&](int b, int w, int c) {
-    return batch ? msm_batch_tune(Bt, ws, ws_bytes, stream, b, w, c)
-                 : msm_plan_tune(P, ws, ws_bytes, stream, b, w, c);
+  auto tune = [&](int b, int w, int c, int n) {
+    const msm_tuning t{b, w, c, n, {}};
+    return batch ? msm_batch_tune(Bt, ws, ws_bytes, stream, &t) : msm_plan_tune(P, ws, ws_bytes, stream, &t);
   };
   auto eval = [&]() {
     return batch ? msm_batch_compute(Bt, ws, ws_bytes, stream, x, y, z, q, nullptr, nullptr, nullptr, nullptr,
@@ -446,10 +453,10 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
   };
   std::string rep = "{\"candidates\": [";
   float best = 1e30f;
-  int best_b = 0, best_w = 0, best_c = 0;
+  int best_b = 0, best_w = 0, best_c = 0, best_n = 0;
   bool first = true;
-  auto time_one = [&](int b, int w, int c, float& ms) {
-    msm_status st = tune(b, w, c);
+  auto time_one = [&](int b, int w, int c, int n, float& ms) {
+    msm_status st = tune(b, w, c, n);
     // one warm-up evaluation, then `trials` timed ones
     for (int t = -1; t < trials && st == MSM_OK; ++t) {
       if (t == 0) (void)hipEventRecord(e0, s);
@@ -461,15 +468,16 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
     if (r == hipSuccess) r = hipEventElapsedTime(&ms, e0, e1);
     if (r != hipSuccess) return hip_fail(r, "time candidate");
     ms /= trials;
-    rep += std::string(first ? "" : ", ") + "{\"lattice_b\": " + std::to_string(b) + ", \"run_w\": " +
-           std::to_string(w) + ", \"short_blocks\": " + std::to_string(c) + ", \"ms\": " +
-           std::to_string(ms) + "}";
+    rep += std::string(first ? "" : ", ") + "{\"lattice_b\": " + std::to_string(b) + ", \"item_chunks\": " +
+           std::to_string(w) + ", \"short_blocks\": " + std::to_string(c) + ", \"streams\": " +
+           std::to_string(n) + ", \"ms\": " + std::to_string(ms) + "}";
     first = false;
     if (ms < best) {
       best = ms;
       best_b = b;
       best_w = w;
       best_c = c;
+      best_n = n;
     }
     return MSM_OK;
   };
@@ -478,21 +486,28 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
   for (int b : bs)
     for (int w : {1, 2, 3}) {
       float ms = 0.f;
-      if (st == MSM_OK) st = time_one(b, w, -1, ms);
+      if (st == MSM_OK) st = time_one(b, w, -1, 3, ms);
     }
   const int bb = best_b, bw = best_w;
-  for (int c : {384, 256, 192, 128}) {
-    float ms = 0.f;
-    if (st == MSM_OK) st = time_one(bb, bw, c, ms);
-  }
+  for (int n : {1, 2})
+    if (st == MSM_OK) {
+      float ms = 0.f;
+      st = time_one(bb, bw, -1, n, ms);
+    }
+  const int bn = best_n;
+  for (int c : {384, 256, 128})
+    if (st == MSM_OK) {
+      float ms = 0.f;
+      st = time_one(bb, bw, c, bn, ms);
+    }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != MSM_OK) return st;
-  st = tune(best_b, best_w, best_c);
+  st = tune(best_b, best_w, best_c, best_n);
   if (st != MSM_OK) return st;
-  rep += "], \"best\": {\"lattice_b\": " + std::to_string(best_b) + ", \"run_w\": " +
-         std::to_string(best_w) + ", \"short_blocks\": " + std::to_string(best_c) + ", \"ms\": " +
-         std::to_string(best) + "}}";
+  rep += "], \"best\": {\"lattice_b\": " + std::to_string(best_b) + ", \"item_chunks\": " +
+         std::to_string(best_w) + ", \"short_blocks\": " + std::to_string(best_c) + ", \"streams\": " +
+         std::to_string(best_n) + ", \"ms\": " + std::to_string(best) + "}}";
   if (report && report_bytes) {
     std::strncpy(report, rep.c_str(), report_bytes - 1);
     report[report_bytes - 1] = 0;

@@ -15,6 +15,9 @@ constexpr int kMaxLevels = 12;
 constexpr int kMaxOrder = 6;
 constexpr int kMaxTopNodes = 1 << 17;     // all-pairs FP64 top level stays below ~1e10 pair terms
 constexpr int kRankCap = 2048;            // cells longer than this keep scatter order (see bin_place)
+constexpr int kBinChunk = 4096;           // atoms per block of the two-kernel binning
+constexpr int kBinMaxCells = 8192;        // cells the two-kernel binning keeps in LDS
+constexpr int kBinMaxHist = 1 << 20;      // block histogram entries of the two-kernel binning
 
 enum DeviceFlag : int { kFlagOutOfBox = 1, kFlagNonFinite = 2, kFlagCoincident = 4 };
 
@@ -39,10 +42,11 @@ struct Geom {
   // link cells
   int nc[3];
   int n_cells;
+  int bin_blocks;                  // blocks of the two-kernel binning (0: four-kernel binning)
   int reach;                       // neighbour cells per side
   float inv_cs[3];                 // 1 / cell edge
-  int run_w;                       // cells per short-range work item along x
-  int runs_x;                      // work items per cell row
+  int item_chunks;                 // short-range 64-atom chunks of a cell row per work item
+  int row_items;                   // short-range work items per cell row (chunks interleaved)
   int short_blocks;                // blocks of the short-range launch (work items strided over them)
   // short-range constants
   float a2;                        // cutoff^2
@@ -107,6 +111,7 @@ enum Section : int {
   kSecCursor,         // int[n_cells]
   kSecCellOf,         // int[n]
   kSecTmp,            // int[n]
+  kSecBinHist,        // int[bin_blocks * n_cells]: per-block cell counts (two-kernel binning)
   kSecRows,           // StencilRow[n_rows]
   kSecWeights,        // float[n_weights]
   kSecRowsC,          // int4[n_rows]: compact rows (nz, ny >= 0, xr, weight offset)
@@ -137,6 +142,7 @@ struct DevPtrs {
   int* cursor;
   int* cell_of;
   int* tmp;
+  int* bin_hist;
   const StencilRow* rows;
   const int4* rows_c;
   const float* weights_c;
@@ -214,7 +220,10 @@ struct LaunchGeom {
   int lat_b = 0;                     // windowed lattice outputs per lane, 0 = untiled kernel
   int lat_lds = 0;                   // dynamic LDS of the windowed kernel
   int max_levels = 1;
+  int streams = 3;                   // 1: in order; 2: short range on a side stream; 3: also level-0 lattice
   StageGrid zero, atoms, one, shortr, anterp, top, energy;
+  StageGrid bin;                     // two-kernel binning (systems with bin_blocks > 0)
+  bool bin4 = true;                  // some system uses the four-kernel binning
   StageGrid lattice0;                // lattice cutoff of level 0
   StageGrid lattice;                 // lattice cutoff of levels 1 .. l-2
   StageGrid restrict_[kMaxLevels];   // level k -> k+1
@@ -223,7 +232,7 @@ struct LaunchGeom {
 
 // Per-stage block counts of one system.
 struct SysBlocks {
-  int zero, atoms, shortr, anterp, lattice0, lattice, top, energy;
+  int zero, atoms, bin, shortr, anterp, lattice0, lattice, top, energy;
   int restrict_[kMaxLevels];
   int prolong[kMaxLevels];
 };

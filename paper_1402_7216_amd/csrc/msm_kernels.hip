@@ -150,7 +150,7 @@ __global__ void k_bin_count(KArgs A) {
   const SysDesc& S = sys_of(A, blk);
   const Geom& g = S.g;
   const int i = blk * blockDim.x + threadIdx.x;
-  if (i >= g.n_atoms) return;
+  if (i >= g.n_atoms || g.bin_blocks) return;
   const float* x = A.io.x + S.atom_off;
   const float* y = A.io.y + S.atom_off;
   const float* z = A.io.z + S.atom_off;
@@ -169,6 +169,7 @@ __global__ void __launch_bounds__(1024) k_scan(KArgs A) {
   int* __restrict__ cursor = S.d.cursor;
   int* __restrict__ status = S.d.status;
   const int n = S.g.n_cells;
+  if (S.g.bin_blocks) return;                       // binned by the two-kernel path
   __shared__ int part[1024];
   int t = threadIdx.x;
   int chunk = (n + 1023) / 1024;
@@ -201,7 +202,7 @@ __global__ void k_bin_scatter(KArgs A) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
   const int i = blk * blockDim.x + threadIdx.x;
-  if (i >= S.g.n_atoms) return;
+  if (i >= S.g.n_atoms || S.g.bin_blocks) return;
   const float* x = A.io.x + S.atom_off;
   const float* y = A.io.y + S.atom_off;
   const float* z = A.io.z + S.atom_off;
@@ -228,7 +229,7 @@ __global__ void k_bin_place(KArgs A) {
   const SysDesc& S = sys_of(A, blk);
   const Geom& g = S.g;
   const int s = blk * blockDim.x + threadIdx.x;
-  if (s >= g.n_atoms) return;
+  if (s >= g.n_atoms || g.bin_blocks) return;
   const int* __restrict__ cell_of = S.d.cell_of;
   const int* __restrict__ start = S.d.cell_start;
   const int* __restrict__ tmp = S.d.tmp;
@@ -273,20 +274,181 @@ __global__ void k_bin_place(KArgs A) {
 }
 
 // --------------------------------------------------------------------------
+// Link cells in two kernels (systems whose cell counts fit in LDS).  Block b
+// owns atoms [b kBinChunk, (b+1) kBinChunk).  k_bin_hist writes each block's
+// cell counts; k_bin_sort gives every atom the slot
+//   start[c] + (atoms of cell c in earlier blocks) + (atoms of cell c in this
+//   block with a smaller input index),
+// the same stable order as the four-kernel path, validates the input and
+// writes the sorted, box-clamped atoms.  Coincident atoms are flagged by the
+// short-range pass on this path.
+// --------------------------------------------------------------------------
+constexpr int kBinThreads = 1024;
+constexpr int kBinPerThread = kBinChunk / kBinThreads;
+
+__global__ void __launch_bounds__(kBinThreads) k_bin_hist(KArgs A) {
+  int blk;
+  const SysDesc& S = sys_of(A, blk);
+  const Geom& g = S.g;
+  extern __shared__ int hist[];
+  const int nc = g.n_cells;
+  for (int c = threadIdx.x; c < nc; c += kBinThreads) hist[c] = 0;
+  if (blk == 0 && threadIdx.x < 64) S.d.status[threadIdx.x] = 0;
+  __syncthreads();
+  const float* x = A.io.x + S.atom_off;
+  const float* y = A.io.y + S.atom_off;
+  const float* z = A.io.z + S.atom_off;
+  const int i0 = blk * kBinChunk;
+#pragma unroll
+  for (int u = 0; u < kBinPerThread; ++u) {
+    const int i = i0 + u * kBinThreads + threadIdx.x;
+    if (i < g.n_atoms) {
+      const int c = cell_index(g, x[i], y[i], z[i]);
+      S.d.cell_of[i] = c;
+      atomicAdd(&hist[c], 1);
+    }
+  }
+  __syncthreads();
+  int* out = S.d.bin_hist + (size_t)blk * nc;
+  for (int c = threadIdx.x; c < nc; c += kBinThreads) out[c] = hist[c];
+}
+
+__global__ void __launch_bounds__(kBinThreads) k_bin_sort(KArgs A) {
+  int blk;
+  const SysDesc& S = sys_of(A, blk);
+  const Geom& g = S.g;
+  extern __shared__ int lds[];
+  const int nc = g.n_cells, nb = g.bin_blocks;
+  int* base = lds;                 // [nc] first global slot of this block's atoms of cell c
+  int* cur = base + nc;            // [nc] atoms of cell c in earlier blocks, then a cursor
+  int* loc = cur + nc;             // [nc] first local slot of this block's atoms of cell c
+  int* lidx = loc + nc;            // [kBinChunk] this block's atom indices grouped by cell
+  int2* part = reinterpret_cast<int2*>(lidx + kBinChunk);   // [kBinThreads]
+  const int t = threadIdx.x;
+  // this thread's atoms (loads in flight during the scans)
+  const float* x = A.io.x + S.atom_off;
+  const float* y = A.io.y + S.atom_off;
+  const float* z = A.io.z + S.atom_off;
+  const float* q = A.io.q + S.atom_off;
+  const int i0 = blk * kBinChunk;
+  int cc[kBinPerThread];
+  float4 p[kBinPerThread];
+#pragma unroll
+  for (int u = 0; u < kBinPerThread; ++u) {
+    const int i = i0 + u * kBinThreads + t;
+    cc[u] = -1;
+    p[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (i < g.n_atoms) {
+      cc[u] = S.d.cell_of[i];
+      p[u] = make_float4(x[i], y[i], z[i], q[i]);
+    }
+  }
+  // per cell: atoms over all blocks, in earlier blocks, in this block
+  const int* __restrict__ bh = S.d.bin_hist;
+  for (int c = t; c < nc; c += kBinThreads) {
+    int tot = 0, pre = 0;
+    for (int b0 = 0; b0 < nb; b0 += 8) {              // 8 loads in flight
+      int v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = (b0 + u < nb) ? bh[(size_t)(b0 + u) * nc + c] : 0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        tot += v[u];
+        pre += (b0 + u < blk) ? v[u] : 0;
+      }
+    }
+    base[c] = tot;
+    cur[c] = pre;
+    loc[c] = bh[(size_t)blk * nc + c];
+  }
+  __syncthreads();
+  // exclusive scans of the totals and of this block's counts: thread t owns
+  // cells [t k, t k + k)
+  const int k = (nc + kBinThreads - 1) / kBinThreads;
+  const int c0 = min(t * k, nc), c1 = min(c0 + k, nc);
+  int2 sum = make_int2(0, 0);
+  for (int c = c0; c < c1; ++c) {
+    sum.x += base[c];
+    sum.y += loc[c];
+  }
+  part[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < kBinThreads; off <<= 1) {
+    const int2 v = (t >= off) ? part[t - off] : make_int2(0, 0);
+    __syncthreads();
+    part[t].x += v.x;
+    part[t].y += v.y;
+    __syncthreads();
+  }
+  int run = part[t].x - sum.x, lrun = part[t].y - sum.y;
+  for (int c = c0; c < c1; ++c) {
+    const int v = base[c], w = loc[c];
+    if (blk == 0) S.d.cell_start[c] = run;
+    base[c] = run + cur[c];
+    loc[c] = lrun;
+    cur[c] = 0;
+    run += v;
+    lrun += w;
+  }
+  if (blk == 0 && t == kBinThreads - 1) S.d.cell_start[nc] = part[t].x;
+  __syncthreads();
+  // group this block's atoms by cell in LDS (arrival order), then rank each
+  // by input index within its cell
+#pragma unroll
+  for (int u = 0; u < kBinPerThread; ++u)
+    if (cc[u] >= 0) lidx[loc[cc[u]] + atomicAdd(&cur[cc[u]], 1)] = i0 + u * kBinThreads + t;
+  __syncthreads();
+  int flags = 0;
+#pragma unroll
+  for (int u = 0; u < kBinPerThread; ++u) {
+    if (cc[u] < 0) continue;
+    const int i = i0 + u * kBinThreads + t;
+    const int c = cc[u], l0 = loc[c], n = cur[c];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) rank += (lidx[l0 + j] < i);
+    const float4 pi = p[u];
+    if (!(isfinite(pi.x) && isfinite(pi.y) && isfinite(pi.z) && isfinite(pi.w))) {
+      flags |= kFlagNonFinite;
+    } else {
+      const double pd[3] = {(double)pi.x, (double)pi.y, (double)pi.z};
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        if (pd[d] < g.lo[d] || pd[d] > g.hi[d]) flags |= kFlagOutOfBox;
+    }
+    float4 o;
+    o.x = fminf(fmaxf(pi.x, g.lo_f[0]), (float)g.hi[0]);
+    o.y = fminf(fmaxf(pi.y, g.lo_f[1]), (float)g.hi[1]);
+    o.z = fminf(fmaxf(pi.z, g.lo_f[2]), (float)g.hi[2]);
+    o.w = isfinite(pi.w) ? pi.w : 0.f;
+    S.d.sorted[base[c] + rank] = o;
+    S.d.perm[base[c] + rank] = i;
+  }
+  if (flags) atomicOr(S.d.status, flags);
+}
+
+// --------------------------------------------------------------------------
 // Short-range part (itemised algorithm, first sentence; eq. msmgrid g*):
 //   phi_i^s = sum_j q_j g*(r_ij),  F_i^s = -q_i sum_j q_j g*'(r_ij) (r_i - r_j)/r_ij
 //   g*(r) = 1/r - gamma(r/a)/a,  g*'(r)/r = -1/r^3 - gamma'(r/a)/(a^2 r)
-// One work item = a run of run_w cells along x in one cell row; its atoms are
-// contiguous in sorted order.  Lanes hold i atoms (64 at a time).  For each
-// neighbour row (the (2 reach + 1)^2 cell rows around the run) the j atoms
-// form one contiguous range, cut into chunks of 64; the block's 16 waves take
-// the (row, chunk) units in turn, stage the chunk through their own LDS slice
-// (one coalesced load) and read it back as wave-wide broadcasts.  The waves'
-// partial sums meet in LDS and are added in wave order.
+// Work items: the atoms of a cell row are contiguous in sorted order (cells
+// along x, then input order) and are cut into 64-atom chunks, one atom per
+// lane.  A chunk's atoms lie in x cells [cxa, cxb]; its neighbours lie in the
+// (2 reach + 1)^2 cell rows around it, x cells [cxa - reach, cxb + reach],
+// each row one contiguous j range, cut into chunks of 64.  The block's waves
+// take these (row, j chunk) units in turn, stage each j chunk through their
+// own LDS slice (one coalesced load) and read it back as wave-wide
+// broadcasts, four at a time.  The waves' partial sums meet in LDS and are
+// added in wave order.
 // --------------------------------------------------------------------------
 constexpr int kShortThreads = 512;
 constexpr int kShortWaves = kShortThreads / kWave;
 constexpr int kShortMaxRows = 25;                // (2 reach + 1)^2 with reach <= 2
+
+__device__ __forceinline__ int cell_x(const Geom& g, float x) {
+  float t = (x - g.lo_f[0]) * g.inv_cs[0];
+  t = fminf(fmaxf(t, 0.f), (float)(g.nc[0] - 1));
+  return min((int)t, g.nc[0] - 1);
+}
 
 template <int M, bool FORCES>
 __global__ void __launch_bounds__(kShortThreads) k_short(KArgs A) {
@@ -301,7 +463,8 @@ __global__ void __launch_bounds__(kShortThreads) k_short(KArgs A) {
   __shared__ int row_j0[kShortMaxRows], row_j1[kShortMaxRows], unit0[kShortMaxRows + 1];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int n_items = g.runs_x * g.nc[1] * g.nc[2];
+  const int n_rows_c = g.nc[1] * g.nc[2];
+  const int n_items = g.row_items * n_rows_c;
   const float a2 = g.a2, inv_a2 = g.inv_a2;
   float gc[M + 1], dc[M + 1];
 #pragma unroll
@@ -310,101 +473,111 @@ __global__ void __launch_bounds__(kShortThreads) k_short(KArgs A) {
     dc[k] = g.dcoef[k];
   }
   float4* jb_w = jbuf[wave];
+  const int R = g.reach, side = 2 * R + 1, nrows = side * side;
   // the launch has g.short_blocks blocks; work items are strided over them
   for (int item = blk; item < n_items; item += g.short_blocks) {
-  __syncthreads();                                       // tables of the previous item are done
-  const int run = item % g.runs_x;
-  const int row = item / g.runs_x;
-  const int cy = row % g.nc[1], cz = row / g.nc[1];
-  const int cx0 = run * g.run_w;
-  const int cx1 = min(cx0 + g.run_w, g.nc[0]) - 1;
-  const int rowbase = (cz * g.nc[1] + cy) * g.nc[0];
-  const int ib = start[rowbase + cx0], ie = start[rowbase + cx1 + 1];
-  const int R = g.reach, side = 2 * R + 1, nrows = side * side;
-  const int jx0 = max(cx0 - R, 0), jx1 = min(cx1 + R, g.nc[0] - 1);
-  // neighbour rows: j range and the first (row, chunk) unit of each row
-  if (threadIdx.x < nrows) {
-    const int jy = cy + threadIdx.x % side - R, jz = cz + threadIdx.x / side - R;
-    int j0 = 0, j1 = 0;
-    if (jy >= 0 && jz >= 0 && jy < g.nc[1] && jz < g.nc[2]) {
-      const int jrow = (jz * g.nc[1] + jy) * g.nc[0];
-      j0 = start[jrow + jx0];
-      j1 = start[jrow + jx1 + 1];
-    }
-    row_j0[threadIdx.x] = j0;
-    row_j1[threadIdx.x] = j1;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int u = 0;
-    for (int r = 0; r < nrows; ++r) {
-      unit0[r] = u;
-      u += (row_j1[r] - row_j0[r] + kWave - 1) / kWave;
-    }
-    unit0[nrows] = u;
-  }
-  __syncthreads();
-  const int n_units = unit0[nrows];
-
-  for (int ic = ib; ic < ie; ic += kWave) {
-    const int i = ic + lane;
-    const float4 pi = (i < ie) ? sorted[i] : make_float4(3.0e30f, 3.0e30f, 3.0e30f, 0.f);
-    float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;
-    int r = 0;
-    for (int u = wave; u < n_units; u += kShortWaves) {
-      while (unit0[r + 1] <= u) ++r;                 // wave-uniform walk over the rows
-      const int jc = row_j0[r] + (u - unit0[r]) * kWave;
-      const int nj = min(kWave, row_j1[r] - jc);
-      // stage up to 64 j atoms in this wave's LDS slice (coalesced), then
-      // read them back as wave-wide broadcasts
-      jb_w[lane] = (lane < nj) ? sorted[jc + lane] : make_float4(-3.0e30f, -3.0e30f, -3.0e30f, 0.f);
-      const int nj4 = (nj + 3) & ~3;
-#pragma unroll 4
-      for (int t = 0; t < nj4; ++t) {
-        const float4 pj = jb_w[t];
-        const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        if (r2 < a2 && r2 > 0.f) {
-          // hardware reciprocal square root plus one Newton step (the raw
-          // instruction's error is biased, which would bias the energy)
-          float ri = __builtin_amdgcn_rsqf(r2);
-          ri = fmaf(0.5f * ri, fmaf(-r2 * ri, ri, 1.f), ri);
-          const float ri2 = ri * ri;
-          const float s = r2 * inv_a2;
-          float gm = gc[M], dg = dc[M];
+    const int row = item / g.row_items, kk = item - row * g.row_items;
+    const int cy = row % g.nc[1], cz = row / g.nc[1];
+    const int rowbase = (cz * g.nc[1] + cy) * g.nc[0];
+    const int rb = start[rowbase], re = start[rowbase + g.nc[0]];
+    for (int ic = rb + kk * kWave; ic < re; ic += g.row_items * kWave) {
+      const int ie = min(ic + kWave, re);
+      __syncthreads();                               // tables of the previous chunk are done
+      // neighbour rows: j range and the first (row, chunk) unit of each row
+      if (threadIdx.x < nrows) {
+        const int cxa = cell_x(g, sorted[ic].x), cxb = cell_x(g, sorted[ie - 1].x);
+        const int jx0 = max(cxa - R, 0), jx1 = min(cxb + R, g.nc[0] - 1);
+        const int jy = cy + threadIdx.x % side - R, jz = cz + threadIdx.x / side - R;
+        int j0 = 0, j1 = 0;
+        if (jy >= 0 && jz >= 0 && jy < g.nc[1] && jz < g.nc[2]) {
+          const int jrow = (jz * g.nc[1] + jy) * g.nc[0];
+          j0 = start[jrow + jx0];
+          j1 = start[jrow + jx1 + 1];
+        }
+        row_j0[threadIdx.x] = j0;
+        row_j1[threadIdx.x] = j1;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int u = 0;
+        for (int r = 0; r < nrows; ++r) {
+          unit0[r] = u;
+          u += (row_j1[r] - row_j0[r] + kWave - 1) / kWave;
+        }
+        unit0[nrows] = u;
+      }
+      __syncthreads();
+      const int n_units = unit0[nrows];
+      const int i = ic + lane;
+      const float4 pi = (i < ie) ? sorted[i] : make_float4(3.0e30f, 3.0e30f, 3.0e30f, 0.f);
+      float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;
+      bool coincident = false;
+      int r = 0;
+      for (int u = wave; u < n_units; u += kShortWaves) {
+        while (unit0[r + 1] <= u) ++r;               // wave-uniform walk over the rows
+        const int jc = row_j0[r] + (u - unit0[r]) * kWave;
+        const int nj = min(kWave, row_j1[r] - jc);
+        // stage up to 64 j atoms in this wave's LDS slice (coalesced), then
+        // read them back as wave-wide broadcasts
+        jb_w[lane] = (lane < nj) ? sorted[jc + lane] : make_float4(-3.0e30f, -3.0e30f, -3.0e30f, 0.f);
+        if (r == nrows / 2) {
+          // the centre row holds the atom's own cell: any j other than the
+          // atom itself at distance zero is a coincident pair
+          int zeros = 0;
+          for (int t = 0; t < nj; ++t) {
+            const float4 pj = jb_w[t];
+            zeros += (pi.x == pj.x && pi.y == pj.y && pi.z == pj.z);
+          }
+          coincident |= zeros > ((i >= jc && i < jc + nj) ? 1 : 0);
+        }
+        for (int t0 = 0; t0 < nj; t0 += 4) {
+          float4 pj[4];
 #pragma unroll
-          for (int k = M - 1; k >= 0; --k) gm = fmaf(gm, s, gc[k]);
+          for (int v = 0; v < 4; ++v) pj[v] = jb_w[t0 + v];      // padded past nj
 #pragma unroll
-          for (int k = M - 1; k >= 1; --k) dg = fmaf(dg, s, dc[k]);
-          const float gs = ri - gm;                    // g*(r)
-          ap = fmaf(pj.w, gs, ap);
-          if (FORCES) {
-            const float fr = fmaf(ri, ri2, dg);        // -g*'(r)/r
-            const float wq = pj.w * fr;
-            ax = fmaf(wq, dx, ax);
-            ay = fmaf(wq, dy, ay);
-            az = fmaf(wq, dz, az);
+          for (int v = 0; v < 4; ++v) {
+            const float dx = pi.x - pj[v].x, dy = pi.y - pj[v].y, dz = pi.z - pj[v].z;
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            if (r2 < a2 && r2 > 0.f) {
+              // hardware reciprocal square root plus one Newton step (the raw
+              // instruction's error is biased, which would bias the energy)
+              float ri = __builtin_amdgcn_rsqf(r2);
+              ri = fmaf(0.5f * ri, fmaf(-r2 * ri, ri, 1.f), ri);
+              const float s = r2 * inv_a2;
+              float gm = gc[M], dg = dc[M];
+#pragma unroll
+              for (int k = M - 1; k >= 0; --k) gm = fmaf(gm, s, gc[k]);
+#pragma unroll
+              for (int k = M - 1; k >= 1; --k) dg = fmaf(dg, s, dc[k]);
+              const float qj = pj[v].w;
+              ap = fmaf(qj, ri - gm, ap);                     // q_j g*(r)
+              if (FORCES) {
+                const float wq = qj * fmaf(ri, ri * ri, dg);  // q_j (-g*'(r)/r)
+                ax = fmaf(wq, dx, ax);
+                ay = fmaf(wq, dy, ay);
+                az = fmaf(wq, dz, az);
+              }
+            }
           }
         }
       }
-    }
-    red[wave][lane] = make_float4(ax, ay, az, ap);
-    __syncthreads();
-    if (wave == 0 && i < ie) {
-      float4 t = red[0][lane];
+      if (coincident && i < ie) atomicOr(S.d.status, kFlagCoincident);
+      red[wave][lane] = make_float4(ax, ay, az, ap);
+      __syncthreads();
+      if (wave == 0 && i < ie) {
+        float4 t = red[0][lane];
 #pragma unroll
-      for (int w = 1; w < kShortWaves; ++w) {
-        const float4 v = red[w][lane];
-        t.x += v.x;
-        t.y += v.y;
-        t.z += v.z;
-        t.w += v.w;
+        for (int w = 1; w < kShortWaves; ++w) {
+          const float4 v = red[w][lane];
+          t.x += v.x;
+          t.y += v.y;
+          t.z += v.z;
+          t.w += v.w;
+        }
+        const float qi = pi.w;
+        fshort[i] = make_float4(qi * t.x, qi * t.y, qi * t.z, t.w);
       }
-      const float qi = pi.w;
-      fshort[i] = make_float4(qi * t.x, qi * t.y, qi * t.z, t.w);
     }
-    __syncthreads();
-  }
   }
 }
 
@@ -461,8 +634,10 @@ __device__ __forceinline__ void anterp_atom(const Geom& g, const int* n0, float4
   }
 }
 
+constexpr int kAThreads = 1024;
+
 template <int ORDER>
-__global__ void __launch_bounds__(kBlock) k_anterp(KArgs A) {
+__global__ void __launch_bounds__(kAThreads) k_anterp(KArgs A) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
   const Geom& g = S.g;
@@ -477,7 +652,7 @@ __global__ void __launch_bounds__(kBlock) k_anterp(KArgs A) {
   const int bx = blk % ntx, by = (blk / ntx) % nty, bz = blk / (ntx * nty);
   const int n0[3] = {L.lo[0] + bx * kAX, L.lo[1] + by * kAY, L.lo[2] + bz * kAZ};
   const int tdim[3] = {kAX, kAY, kAZ};
-  for (int i = threadIdx.x; i < kAX * kAY * kAZ; i += blockDim.x) acc[i] = 0ull;
+  for (int i = threadIdx.x; i < kAX * kAY * kAZ; i += kAThreads) acc[i] = 0ull;
   // atoms touching the tile have floor index f in [n0 - H, n0 + T - 1 + H - 1]:
   // box-relative positions in [(n0 - H) h, (n0 + T - 1 + H) h)
   int c0[3], c1[3];
@@ -517,7 +692,7 @@ __global__ void __launch_bounds__(kBlock) k_anterp(KArgs A) {
     }
     while (t < ncand) {
       const float4 p = nxt;
-      const int tn = t + blockDim.x;
+      const int tn = t + kAThreads;
       if (tn < ncand) {
         while (row_pre[row + 1] <= tn) ++row;
         nxt = sorted[row_beg[row] + (tn - row_pre[row])];
@@ -527,7 +702,7 @@ __global__ void __launch_bounds__(kBlock) k_anterp(KArgs A) {
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kAX * kAY * kAZ; i += blockDim.x) {
+  for (int i = threadIdx.x; i < kAX * kAY * kAZ; i += kAThreads) {
     const int lx = i % kAX, ly = (i / kAX) % kAY, lz = i / (kAX * kAY);
     const int gx = bx * kAX + lx, gy = by * kAY + ly, gz = bz * kAZ + lz;
     if (gx < L.n[0] && gy < L.n[1] && gz < L.n[2])
@@ -568,11 +743,14 @@ struct Dyadic {
   static constexpr float wodd(int i) { return (float)phi_half(ORDER, R - 2 * i); }
 };
 
-// One block = 8 x 8 x 4 coarse nodes; the fine nodes they read are staged in LDS.
+// One block = 8 x 8 x 4 coarse nodes; the fine nodes they read are staged in
+// LDS by all kRThreads threads (one round of loads), then one thread per
+// coarse node sums its taps.
 constexpr int kRX = 8, kRY = 8, kRZ = 4;
+constexpr int kRThreads = 1024;
 
 template <int ORDER>
-__global__ void __launch_bounds__(kBlock) k_restrict(KArgs A, int k) {
+__global__ void __launch_bounds__(kRThreads) k_restrict(KArgs A, int k) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
   const Geom& g = S.g;
@@ -589,11 +767,11 @@ __global__ void __launch_bounds__(kBlock) k_restrict(KArgs A, int k) {
   const int f0x = 2 * (C.lo[0] + c0x) - R, f0y = 2 * (C.lo[1] + c0y) - R, f0z = 2 * (C.lo[2] + c0z) - R;
   const float* fin = grid + F.off;
   constexpr int nfine = FX * FY * FZ;
-  for (int i0 = 0; i0 < nfine; i0 += 8 * kBlock) {       // 8 loads in flight per thread
+  for (int i0 = 0; i0 < nfine; i0 += 8 * kRThreads) {    // 8 loads in flight per thread
     float v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int i = i0 + u * kBlock + threadIdx.x;
+      const int i = i0 + u * kRThreads + threadIdx.x;
       v[u] = 0.f;
       if (i < nfine) {
         const int lx = i % FX, ly = (i / FX) % FY, lz = i / (FX * FY);
@@ -604,11 +782,12 @@ __global__ void __launch_bounds__(kBlock) k_restrict(KArgs A, int k) {
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int i = i0 + u * kBlock + threadIdx.x;
+      const int i = i0 + u * kRThreads + threadIdx.x;
       if (i < nfine) fine[i] = v[u];
     }
   }
   __syncthreads();
+  if (threadIdx.x >= kRX * kRY * kRZ) return;
   const int tx = threadIdx.x % kRX, ty = (threadIdx.x / kRX) % kRY, tz = threadIdx.x / (kRX * kRY);
   const int mx = c0x + tx, my = c0y + ty, mz = c0z + tz;
   if (tz >= kRZ || mx >= C.n[0] || my >= C.n[1] || mz >= C.n[2]) return;
@@ -868,8 +1047,13 @@ __device__ __forceinline__ float ucut_at(const SysDesc& S, int k, int node) {
   if (S.lat.b == 0 || k >= S.lat.n || S.lat.t[k].groups == 1) return ucut[L.off + node];
   const LatTile& T = S.lat.t[k];
   const double* part = S.d.lat_part + T.part0 + node;
+  double pv[kLatMaxGroups];
+#pragma unroll
+  for (int gi = 0; gi < kLatMaxGroups; ++gi) pv[gi] = (gi < T.groups) ? part[(size_t)gi * L.count] : 0.0;
   double v = 0.0;
-  for (int gi = 0; gi < T.groups; ++gi) v += part[(size_t)gi * L.count];
+#pragma unroll
+  for (int gi = 0; gi < kLatMaxGroups; ++gi)
+    if (gi < T.groups) v += pv[gi];
   const float u = (float)ldexp(v, -k);
   ucut[L.off + node] = u;
   return u;
@@ -897,11 +1081,23 @@ __global__ void __launch_bounds__(kBlock) k_top(KArgs A) {
   const float* qt = qgrid + L.off;
   const float inv_n0 = 1.f / (float)L.n[0], inv_n1 = 1.f / (float)L.n[1];
   double acc = 0.0;
-  for (int v = lane; v < L.count; v += kWave) {
-    int vx, vy;
-    const int vz = fdiv(fdiv(v, L.n[0], inv_n0, vx), L.n[1], inv_n1, vy);
-    const double t = T[((size_t)abs(mz - vz) * L.n[1] + abs(my - vy)) * L.n[0] + abs(mx - vx)];
-    acc = fma(t, (double)qt[v], acc);
+  for (int v0 = lane; v0 < L.count; v0 += 4 * kWave) {     // 4 table and charge loads in flight
+    double t[4];
+    float qv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int v = v0 + u * kWave;
+      t[u] = 0.0;
+      qv[u] = 0.f;
+      if (v < L.count) {
+        int vx, vy;
+        const int vz = fdiv(fdiv(v, L.n[0], inv_n0, vx), L.n[1], inv_n1, vy);
+        t[u] = T[((size_t)abs(mz - vz) * L.n[1] + abs(my - vy)) * L.n[0] + abs(mx - vx)];
+        qv[u] = qt[v];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = fma(t[u], (double)qv[u], acc);
   }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
@@ -1215,6 +1411,7 @@ SysBlocks system_blocks(const Geom& g, const LatLaunch& lat, int n_partials) {
   SysBlocks b{};
   b.zero = blocks_for(g.n_cells + 1);
   b.atoms = g.n_atoms > 0 ? blocks_for(g.n_atoms) : 0;
+  b.bin = g.bin_blocks;
   b.shortr = g.n_atoms > 0 ? g.short_blocks : 0;
   const Level& L0 = g.lv[0];
   b.anterp = ((L0.n[0] + kAX - 1) / kAX) * ((L0.n[1] + kAY - 1) / kAY) * ((L0.n[2] + kAZ - 1) / kAZ);
@@ -1263,16 +1460,26 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
   const bool have_atoms = L.atoms.blocks > 0;
 
   mark(kStageBin);
-  if (have_atoms) k_bin_count<<<L.atoms.blocks, kBlock, 0, s>>>(args(L.atoms));
-  k_scan<<<L.one.blocks, 1024, 0, s>>>(args(L.one));
-  if (have_atoms) {
-    k_bin_scatter<<<L.atoms.blocks, kBlock, 0, s>>>(args(L.atoms));
-    k_bin_place<<<L.atoms.blocks, kBlock, 0, s>>>(args(L.atoms));
+  if (L.bin4) {
+    if (have_atoms) k_bin_count<<<L.atoms.blocks, kBlock, 0, s>>>(args(L.atoms));
+    k_scan<<<L.one.blocks, 1024, 0, s>>>(args(L.one));
+    if (have_atoms) {
+      k_bin_scatter<<<L.atoms.blocks, kBlock, 0, s>>>(args(L.atoms));
+      k_bin_place<<<L.atoms.blocks, kBlock, 0, s>>>(args(L.atoms));
+    }
+  }
+  if (L.bin.blocks > 0) {
+    const int hist_lds = kBinMaxCells * (int)sizeof(int);
+    const int sort_lds = (3 * kBinMaxCells + kBinChunk + 2 * kBinThreads) * (int)sizeof(int);
+    (void)hipFuncSetAttribute((const void*)k_bin_hist, hipFuncAttributeMaxDynamicSharedMemorySize, hist_lds);
+    (void)hipFuncSetAttribute((const void*)k_bin_sort, hipFuncAttributeMaxDynamicSharedMemorySize, sort_lds);
+    k_bin_hist<<<L.bin.blocks, kBinThreads, hist_lds, s>>>(args(L.bin));
+    k_bin_sort<<<L.bin.blocks, kBinThreads, sort_lds, s>>>(args(L.bin));
   }
 
   // short-range pairs: on their own stream, joined before interpolation
   mark(kStageShort);
-  const bool short_side = concurrent && have_atoms && L.shortr.blocks > 0;
+  const bool short_side = concurrent && L.streams >= 2 && have_atoms && L.shortr.blocks > 0;
   if (have_atoms && L.shortr.blocks > 0) {
     hipStream_t ss = s;
     if (short_side) {
@@ -1303,9 +1510,9 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
 
   mark(kStageAnterp);
   if (L.order == 4)
-    k_anterp<4><<<L.anterp.blocks, kBlock, 0, s>>>(args(L.anterp));
+    k_anterp<4><<<L.anterp.blocks, kAThreads, 0, s>>>(args(L.anterp));
   else
-    k_anterp<6><<<L.anterp.blocks, kBlock, 0, s>>>(args(L.anterp));
+    k_anterp<6><<<L.anterp.blocks, kAThreads, 0, s>>>(args(L.anterp));
 
   // lattice cutoff of one part (0: level 0, 1: levels 1 .. l-2) on stream `ls`
   auto lattice = [&](const StageGrid& sg, int part, hipStream_t ls) {
@@ -1329,7 +1536,7 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
     }
   };
   // level 0 needs only the anterpolated charges: it overlaps the coarse chain
-  const bool lat0_side = concurrent && L.lattice0.blocks > 0;
+  const bool lat0_side = concurrent && L.streams >= 3 && L.lattice0.blocks > 0;
   if (lat0_side) {
     fork(cc->lattice0);
     lattice(L.lattice0, 0, cc->lattice0.stream);
@@ -1341,9 +1548,9 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
     const StageGrid& sg = L.restrict_[k];
     if (sg.blocks == 0) continue;
     if (L.order == 4)
-      k_restrict<4><<<sg.blocks, kBlock, 0, s>>>(args(sg), k);
+      k_restrict<4><<<sg.blocks, kRThreads, 0, s>>>(args(sg), k);
     else
-      k_restrict<6><<<sg.blocks, kBlock, 0, s>>>(args(sg), k);
+      k_restrict<6><<<sg.blocks, kRThreads, 0, s>>>(args(sg), k);
   }
   mark(kStageLattice);
   if (!lat0_side) lattice(L.lattice0, 0, s);

@@ -32,6 +32,7 @@ struct msm_plan {
   int lat_tables = 0;                        // LDS bytes of the compact stencil tables
   int lat_part_max = 0;                      // lattice row-group partials of the largest tuning
   int short_cap = 0;                         // short-range blocks (0: one per work item)
+  int streams = 3;                           // stream layout of an evaluation (msm_tuning.streams)
   Layout lay;
   msm::SysDesc desc;                         // host copy; device pointers filled per workspace
   msm::LaunchGeom lg;                        // stage grids of one evaluation (descriptor set per call)
@@ -56,10 +57,11 @@ void destroy_aux(AuxStreams& a);
 msm::DevPtrs dev_ptrs(const msm_plan* P, void* ws);
 // Recompute the host descriptor and stage grids after a tuning change.
 void refresh_launch(msm_plan* P);
-// Apply tuning knobs (0 keeps the current value): lattice outputs per lane
-// (4, 6 or 8), short-range cells per work item, and short-range blocks
-// (-1: one per work item).  Host-side only; the caller re-uploads descriptors.
-void retune(msm_plan* P, int lat_b, int run_w, int short_blocks);
+// Apply tuning knobs (zero fields keep the current value).  Host-side only;
+// the caller re-uploads descriptors.
+void retune(msm_plan* P, const msm_tuning& t);
+// Reject knob values outside their documented ranges.
+msm_status check_tuning(const msm_tuning* t);
 // Capture the work `launch` enqueues on a private stream into an instantiated graph.
 template <class F>
 msm_status capture_graph(F launch, msm_graph** out) {

@@ -26,7 +26,7 @@ EXPORTS = ("msm_plan_create", "msm_plan_destroy", "msm_plan_info", "msm_plan_des
            "msm_workspace_init", "msm_compute", "msm_energy", "msm_backward", "msm_status_query",
            "msm_workspace_section",
            "msm_profile_enable", "msm_profile_read", "msm_graph_capture", "msm_graph_launch",
-           "msm_graph_destroy", "msm_plan_tune", "msm_plan_autotune",
+           "msm_graph_destroy", "msm_plan_tune", "msm_plan_tuning", "msm_plan_autotune",
            "msm_batch_create", "msm_batch_destroy", "msm_batch_workspace_bytes",
            "msm_batch_atom_offsets", "msm_batch_workspace_init", "msm_batch_compute",
            "msm_batch_energy", "msm_batch_backward", "msm_batch_graph_capture", "msm_batch_status",
@@ -35,6 +35,17 @@ EXPORTS = ("msm_plan_create", "msm_plan_destroy", "msm_plan_info", "msm_plan_des
 
 STAGES = ("binning", "short_range", "anterpolation", "restriction", "lattice_cutoff", "top_level",
           "prolongation", "interpolation", "reduction")
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("lattice_b", ctypes.c_int32), ("item_chunks", ctypes.c_int32), ("short_blocks", ctypes.c_int32),
+                ("streams", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+def make_tuning(lattice_b=0, item_chunks=0, short_blocks=0, streams=0) -> Tuning:
+    t = Tuning()
+    t.lattice_b, t.item_chunks, t.short_blocks, t.streams = int(lattice_b), int(item_chunks), int(short_blocks), int(streams)
+    return t
 
 
 class MSMError(RuntimeError):
@@ -78,7 +89,8 @@ def lib():
         L.msm_graph_capture.argtypes = [vp, vp, sz] + [vp] * 10 + [ctypes.POINTER(vp)]
         L.msm_graph_launch.argtypes = [vp, vp]
         L.msm_graph_destroy.argtypes = [vp]
-        L.msm_plan_tune.argtypes = [vp, vp, sz, vp, i32, i32, i32]
+        L.msm_plan_tune.argtypes = [vp, vp, sz, vp, ctypes.POINTER(Tuning)]
+        L.msm_plan_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
         L.msm_plan_autotune.argtypes = [vp, vp, sz, vp] + [vp] * 4 + [i32, ctypes.c_char_p, sz]
         L.msm_batch_create.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(i32), i32, ctypes.POINTER(vp)]
         L.msm_batch_destroy.argtypes = [vp]
@@ -91,7 +103,7 @@ def lib():
         L.msm_batch_graph_capture.argtypes = [vp, vp, sz] + [vp] * 10 + [ctypes.POINTER(vp)]
         L.msm_batch_status.argtypes = [vp, vp, vp, ctypes.POINTER(i32)]
         L.msm_batch_describe.argtypes = [vp, ctypes.c_char_p, sz]
-        L.msm_batch_tune.argtypes = [vp, vp, sz, vp, i32, i32, i32]
+        L.msm_batch_tune.argtypes = [vp, vp, sz, vp, ctypes.POINTER(Tuning)]
         L.msm_batch_autotune.argtypes = [vp, vp, sz, vp] + [vp] * 4 + [i32, ctypes.c_char_p, sz]
         L.msm_status_string.argtypes = [i32]
         L.msm_status_string.restype = ctypes.c_char_p
@@ -211,9 +223,15 @@ class Plan:
                                   _ptr(z), _ptr(q), _ptr(g), _ptr(dx), _ptr(dy), _ptr(dz), _ptr(dq)))
         return dpos, dq
 
-    def tune(self, lattice_b=0, run_w=0, short_blocks=0):
-        _check(lib().msm_plan_tune(self._h, _ptr(self.ws), self.ws.numel(), _stream(), int(lattice_b),
-                                   int(run_w), int(short_blocks)))
+    def tune(self, lattice_b=0, item_chunks=0, short_blocks=0, streams=0):
+        """Set tuning knobs (zero keeps a knob's value); see msm_tuning."""
+        t = make_tuning(lattice_b, item_chunks, short_blocks, streams)
+        _check(lib().msm_plan_tune(self._h, _ptr(self.ws), self.ws.numel(), _stream(), ctypes.byref(t)))
+
+    def tuning(self) -> dict:
+        t = Tuning()
+        _check(lib().msm_plan_tuning(self._h, ctypes.byref(t)))
+        return {"lattice_b": t.lattice_b, "item_chunks": t.item_chunks, "short_blocks": t.short_blocks, "streams": t.streams}
 
     def autotune(self, x, y, z, q, trials=5):
         """Time the tuning candidates on these inputs, keep the fastest, return the search."""
@@ -399,9 +417,9 @@ class Batch:
         code, _ = self.status()
         _check(code)
 
-    def tune(self, lattice_b=0, run_w=0, short_blocks=0):
-        _check(lib().msm_batch_tune(self._h, _ptr(self.ws), self.ws.numel(), _stream(), int(lattice_b),
-                                    int(run_w), int(short_blocks)))
+    def tune(self, lattice_b=0, item_chunks=0, short_blocks=0, streams=0):
+        t = make_tuning(lattice_b, item_chunks, short_blocks, streams)
+        _check(lib().msm_batch_tune(self._h, _ptr(self.ws), self.ws.numel(), _stream(), ctypes.byref(t)))
 
     def autotune(self, x, y, z, q, trials=3):
         import json

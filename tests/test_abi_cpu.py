@@ -158,7 +158,8 @@ def test_batch_plan_describes_replicas_without_device(M):
         assert nb.value >= d["workspace_bytes"] > 0
         # uninitialised workspaces are refused before any device work
         assert M.lib().msm_batch_compute(h, ctypes.c_void_p(256), nb.value, None, *([None] * 10)) == -4
-        assert M.lib().msm_batch_tune(h, ctypes.c_void_p(256), nb.value, None, 4, 1, 0) == -4
+        t = M.make_tuning(4, 1)
+        assert M.lib().msm_batch_tune(h, ctypes.c_void_p(256), nb.value, None, ctypes.byref(t)) == -4
     finally:
         M.lib().msm_batch_destroy(h)
 

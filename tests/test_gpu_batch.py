@@ -87,7 +87,7 @@ def test_batch_equals_single_system_path_bitwise(M, batch64, replicas):
     for s in list(range(0, 64, 7)) + [63]:
         sys_ = replicas[s]
         plan = M.plan_for(sys_)
-        plan.tune(d["lattice_b"], d["run_ws"][s])
+        plan.tune(d["lattice_b"], d["item_chunks_all"][s])
         o = plan.compute(*M.to_device(sys_), virial=True)
         torch.cuda.synchronize()
         a, e = b.offsets[s], b.offsets[s + 1]
@@ -183,11 +183,11 @@ def test_autotune_keeps_results_within_bars(M):
     x, y, z, q = M.batch_to_device(systems)
     rep = b.autotune(x, y, z, q, trials=2)
     print(f"case batch autotune: best {rep['best']} of {len(rep['candidates'])}", flush=True)
-    assert len(rep["candidates"]) in (7, 13)
+    assert len(rep["candidates"]) in (8, 14)
     best = rep["best"]
     assert best["ms"] == min(c["ms"] for c in rep["candidates"])
     d = b.describe()
-    assert d["lattice_b"] == best["lattice_b"] and d["run_w"] == best["run_w"]
+    assert d["lattice_b"] == best["lattice_b"] and d["item_chunks"] == best["item_chunks"]
     out = b.compute(x, y, z, q)
     torch.cuda.synchronize()
     assert b.status()[0] == 0
