@@ -371,16 +371,32 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_sort(KArgs A) {
     sum.x += base[c];
     sum.y += loc[c];
   }
-  part[t] = sum;
-  __syncthreads();
-  for (int off = 1; off < kBinThreads; off <<= 1) {
-    const int2 v = (t >= off) ? part[t - off] : make_int2(0, 0);
-    __syncthreads();
-    part[t].x += v.x;
-    part[t].y += v.y;
-    __syncthreads();
+  // inclusive scan of the thread sums: within each wave by shuffles, then
+  // over the wave totals
+  const int lane = t & (kWave - 1), wv = t / kWave;
+  int2 inc = sum;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int vx = __shfl_up(inc.x, off), vy = __shfl_up(inc.y, off);
+    if (lane >= off) {
+      inc.x += vx;
+      inc.y += vy;
+    }
   }
-  int run = part[t].x - sum.x, lrun = part[t].y - sum.y;
+  if (lane == kWave - 1) part[wv] = inc;
+  __syncthreads();
+  if (t == 0) {
+    int2 acc = make_int2(0, 0);
+    for (int w = 0; w < kBinThreads / kWave; ++w) {
+      const int2 v = part[w];
+      part[w] = acc;                                  // exclusive prefix of the wave totals
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+    part[kBinThreads / kWave] = acc;
+  }
+  __syncthreads();
+  int run = part[wv].x + inc.x - sum.x, lrun = part[wv].y + inc.y - sum.y;
   for (int c = c0; c < c1; ++c) {
     const int v = base[c], w = loc[c];
     if (blk == 0) S.d.cell_start[c] = run;
@@ -390,7 +406,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_sort(KArgs A) {
     run += v;
     lrun += w;
   }
-  if (blk == 0 && t == kBinThreads - 1) S.d.cell_start[nc] = part[t].x;
+  if (blk == 0 && t == kBinThreads - 1) S.d.cell_start[nc] = part[kBinThreads / kWave].x;
   __syncthreads();
   // group this block's atoms by cell in LDS (arrival order), then rank each
   // by input index within its cell
@@ -809,6 +825,65 @@ __global__ void __launch_bounds__(kRThreads) k_restrict(KArgs A, int k) {
 }
 
 // --------------------------------------------------------------------------
+// Top level (itemised algorithm), float64: u^{l-1}_mu = sum over every node nu
+// of g^{l-1}(2^{l-1} h |mu - nu|) q^{l-1}_nu, from a table T[|dx|][|dy|][|dz|].
+// One wave per output node: lanes stride over the input nodes, then a fixed
+// butterfly sums the 64 lane partials.  Runs as extra blocks of the coarse
+// lattice-cutoff launch (same inputs ready) or, with the untiled lattice
+// kernel, as its own launch.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void top_node(const SysDesc& S, int node, int lane) {
+  const Geom& g = S.g;
+  const double* __restrict__ T = S.d.top;
+  const Level L = g.lv[g.levels - 1];
+  if (node >= L.count) return;
+  const float inv_n0 = 1.f / (float)L.n[0], inv_n1 = 1.f / (float)L.n[1];
+  int mx, my;
+  const int mz = fdiv(fdiv(node, L.n[0], inv_n0, mx), L.n[1], inv_n1, my);
+  const float* qt = S.d.qgrid + L.off;
+  double acc = 0.0;
+  for (int v0 = lane; v0 < L.count; v0 += 4 * kWave) {     // 4 table and charge loads in flight
+    double t[4];
+    float qv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int v = v0 + u * kWave;
+      t[u] = 0.0;
+      qv[u] = 0.f;
+      if (v < L.count) {
+        int vx, vy;
+        const int vz = fdiv(fdiv(v, L.n[0], inv_n0, vx), L.n[1], inv_n1, vy);
+        t[u] = T[((size_t)abs(mz - vz) * L.n[1] + abs(my - vy)) * L.n[0] + abs(mx - vx)];
+        qv[u] = qt[v];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = fma(t[u], (double)qv[u], acc);
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) {
+    S.d.ucut[L.off + node] = (float)acc;
+    S.d.u[L.off + node] = (float)acc;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_top(KArgs A) {
+  int blk;
+  const SysDesc& S = sys_of(A, blk);
+  const int node = __builtin_amdgcn_readfirstlane((blk * (int)blockDim.x + (int)threadIdx.x) / kWave);
+  top_node(S, node, threadIdx.x & (kWave - 1));
+}
+
+// Blocks of the coarse lattice-cutoff launch (part 1) of a system: its coarse
+// tiles, then kLatWaves top-level nodes per block.
+__device__ __forceinline__ int lattice_coarse_blocks(const LatLaunch& P) {
+  if (P.n < 2) return 0;
+  const LatTile& t = P.t[P.n - 1];
+  return t.block0 + t.ntx * t.nty * t.ntz * t.groups - P.t[1].block0;
+}
+
+// --------------------------------------------------------------------------
 // Lattice cutoff (itemised algorithm) for every level k <= l-2 in one launch:
 //   u^{k,cut}_mu = sum_{|n| < 2a/h} g^k(2^k h |n|) q^k_{mu+n} = 2^-k sum W(n) q^k_{mu+n}
 // with W(n) = g^0(h|n|) from the stencil table (rows of taps along z).
@@ -913,7 +988,14 @@ __global__ void __launch_bounds__(kLatThreads) k_lattice_win(KArgs A, int part) 
   const SysDesc& S = sys_of(A, blk);
   const Geom& g = S.g;
   const LatLaunch& P = S.lat;
-  if (part) blk += P.t[1].block0;
+  if (part) {
+    const int nl = lattice_coarse_blocks(P);
+    if (blk >= nl) {                                    // a top-level block (no barriers)
+      top_node(S, (blk - nl) * kLatWaves + (int)(threadIdx.x / kWave), threadIdx.x & (kWave - 1));
+      return;
+    }
+    if (P.n > 1) blk += P.t[1].block0;
+  }
   const int4* __restrict__ rows_g = S.d.rows_c;
   const float* __restrict__ wc_g = S.d.weights_c;
   const float* __restrict__ qgrid = S.d.qgrid;
@@ -1057,54 +1139,6 @@ __device__ __forceinline__ float ucut_at(const SysDesc& S, int k, int node) {
   const float u = (float)ldexp(v, -k);
   ucut[L.off + node] = u;
   return u;
-}
-
-// --------------------------------------------------------------------------
-// Top level (itemised algorithm), float64: u^{l-1}_mu = sum over every node nu
-// of g^{l-1}(2^{l-1} h |mu - nu|) q^{l-1}_nu, from a table T[|dx|][|dy|][|dz|].
-// --------------------------------------------------------------------------
-// One wave per output node: lanes stride over the input nodes, then a fixed
-// butterfly sums the 64 lane partials.
-__global__ void __launch_bounds__(kBlock) k_top(KArgs A) {
-  int blk;
-  const SysDesc& S = sys_of(A, blk);
-  const Geom& g = S.g;
-  const double* __restrict__ T = S.d.top;
-  const float* __restrict__ qgrid = S.d.qgrid;
-  float* __restrict__ ucut = S.d.ucut;
-  float* __restrict__ u = S.d.u;
-  const Level L = g.lv[g.levels - 1];
-  const int node = __builtin_amdgcn_readfirstlane((blk * blockDim.x + threadIdx.x) / kWave);
-  const int lane = threadIdx.x & (kWave - 1);
-  if (node >= L.count) return;
-  const int mx = node % L.n[0], my = (node / L.n[0]) % L.n[1], mz = node / (L.n[0] * L.n[1]);
-  const float* qt = qgrid + L.off;
-  const float inv_n0 = 1.f / (float)L.n[0], inv_n1 = 1.f / (float)L.n[1];
-  double acc = 0.0;
-  for (int v0 = lane; v0 < L.count; v0 += 4 * kWave) {     // 4 table and charge loads in flight
-    double t[4];
-    float qv[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int v = v0 + u * kWave;
-      t[u] = 0.0;
-      qv[u] = 0.f;
-      if (v < L.count) {
-        int vx, vy;
-        const int vz = fdiv(fdiv(v, L.n[0], inv_n0, vx), L.n[1], inv_n1, vy);
-        t[u] = T[((size_t)abs(mz - vz) * L.n[1] + abs(my - vy)) * L.n[0] + abs(mx - vx)];
-        qv[u] = qt[v];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) acc = fma(t[u], (double)qv[u], acc);
-  }
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
-  if (lane == 0) {
-    ucut[L.off + node] = (float)acc;
-    u[L.off + node] = (float)acc;
-  }
 }
 
 // --------------------------------------------------------------------------
@@ -1433,7 +1467,13 @@ SysBlocks system_blocks(const Geom& g, const LatLaunch& lat, int n_partials) {
       b.lattice = blocks_for(g.lv[g.levels - 1].off - g.lv[1].off);
     }
   }
-  b.top = blocks_for(g.lv[g.levels - 1].count * kWave);
+  const int top_nodes = g.lv[g.levels - 1].count;
+  if (g.levels > 1 && lat.b > 0) {
+    b.lattice += (top_nodes + kLatWaves - 1) / kLatWaves;   // top level rides in the coarse launch
+    b.top = 0;
+  } else {
+    b.top = blocks_for(top_nodes * kWave);
+  }
   b.energy = n_partials;
   return b;
 }
@@ -1556,7 +1596,7 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
   if (!lat0_side) lattice(L.lattice0, 0, s);
   lattice(L.lattice, 1, s);
   mark(kStageTop);
-  k_top<<<L.top.blocks, kBlock, 0, s>>>(args(L.top));
+  if (L.top.blocks > 0) k_top<<<L.top.blocks, kBlock, 0, s>>>(args(L.top));
 
   if (mode == kModeEnergy) {
     mark(kStageProlong);
