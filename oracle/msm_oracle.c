@@ -30,6 +30,12 @@
  *     non-zero weight;
  *   - the self term q_i gamma(0)/a is removed from each potential;
  *   - no bonded exclusions: all pairs interact.
+ *
+ * Parity unpinned against the thesis (it prints nothing these readings could
+ * be compared with; the test suite pins them only by mathematics and
+ * invariants): the quintic basis and its pairing with m = 3, the automatic
+ * level count (fewest levels whose top grid interior is at most 8 nodes per
+ * side), free-space boundaries and the absence of exclusions.
  */
 #include <math.h>
 #include <stdint.h>

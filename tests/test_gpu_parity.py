@@ -307,3 +307,33 @@ def test_graph_replay_matches_eager(M):
         # move the atoms a little (inside the box) and replay on the new positions
         d = torch.from_numpy(rng.uniform(-0.01, 0.01, s.n).astype(np.float32)).cuda()
         x.copy_(torch.clamp(x + d, 0.0, float(s.box_len[0])))
+
+
+def test_tunings_keep_bars_and_stream_layouts_are_bitwise_equal(M):
+    """Every tuning (lattice outputs per lane, chunks per short-range item,
+    short-range block count) stays within the bars; the stream layout only
+    changes concurrency, so its results are bitwise identical."""
+    s = inputs.water_box(9000, seed=33, cutoff=10.0, spacing=2.0, order=4, levels=3)
+    r = oracle.system_msm(s)
+    plan = M.plan_for(s)
+    x, y, z, q = M.to_device(s)
+    for b in (4, 6, 8):
+        for w in (1, 3):
+            for sb in (-1, 64):
+                outs = []
+                for n in (1, 2, 3):
+                    plan.tune(b, w, sb, n)
+                    assert plan.tuning()["streams"] == n
+                    o = plan.compute(x, y, z, q, virial=True)
+                    torch.cuda.synchronize()
+                    plan.check()
+                    outs.append({k: v.clone() for k, v in o.items()})
+                for o in outs[1:]:
+                    for k in o:
+                        assert torch.equal(o[k], outs[0][k]), (b, w, sb, k)
+                f = outs[0]["f"].double().cpu().numpy()
+                e = float(outs[0]["energy"].item())
+                print(f"  tuning b={b} w={w} blocks={sb}: e_rel {rel_err(e, r['energy']):.2e} "
+                      f"f_rms {rel_rms(f, r['f']):.2e}", flush=True)
+                assert rel_err(e, r["energy"]) <= ENERGY_RTOL
+                assert rel_rms(f, r["f"]) <= FORCE_RTOL
