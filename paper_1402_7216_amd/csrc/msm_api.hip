@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <utility>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -316,6 +317,47 @@ void refresh_launch(msm_plan* P) {
   }
 }
 
+// Neighbour cell rows (offsets oy, oz in [-reach, reach], row index
+// (oz + reach) (2 reach + 1) + oy + reach) dealt to the 8 waves of a
+// short-range block, largest expected x window first, each to the wave with
+// the least work so far.  A row's expected window is the mean over atom
+// positions (y, z) in a cell of 2 sqrt(a^2 - d^2), d the distance to the row.
+void assign_short_rows(Geom& g) {
+  const int R = g.reach, side = 2 * R + 1, nrows = side * side;
+  const double a = g.a_win, cy = g.cs[1], cz = g.cs[2];
+  std::vector<std::pair<double, int>> cost;
+  for (int r = 0; r < nrows; ++r) {
+    const int oy = r % side - R, oz = r / side - R;
+    double sum = 0.0;
+    const int K = 16;
+    for (int iy = 0; iy < K; ++iy)
+      for (int iz = 0; iz < K; ++iz) {
+        const double y = (iy + 0.5) / K * cy, z = (iz + 0.5) / K * cz;
+        auto gap = [](double v, int o, double c) {
+          if (o > 0) return o * c - v;
+          if (o < 0) return v - (o + 1) * c;
+          return 0.0;
+        };
+        const double dy = gap(y, oy, cy), dz = gap(z, oz, cz), d2 = dy * dy + dz * dz;
+        if (d2 < a * a) sum += 2.0 * std::sqrt(a * a - d2);
+      }
+    cost.push_back({sum / (K * K) + 1.0, r});
+  }
+  std::sort(cost.begin(), cost.end(), [](const auto& x, const auto& y) {
+    return x.first > y.first || (x.first == y.first && x.second < y.second);
+  });
+  double load[8] = {};
+  int count[8] = {};
+  std::memset(g.short_rows, -1, sizeof(g.short_rows));
+  for (const auto& c : cost) {
+    int w = 0;
+    for (int v = 1; v < 8; ++v)
+      if (count[v] < 8 && (count[w] >= 8 || load[v] < load[w])) w = v;
+    g.short_rows[w][count[w]++] = (signed char)c.second;
+    load[w] += c.first;
+  }
+}
+
 // Short-range work items: each cell row's atoms are cut into 64-atom chunks;
 // a row has row_items work items, item k taking chunks k, k + row_items, ...
 // (sized for the row's expected atom count, so each item gets about
@@ -502,14 +544,17 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
 
   // link cells: edge >= a / reach (with a margin for float rounding of cell ids)
   const double amargin = a * (1.0 + 1e-4);
+  // (x cells kXSub times finer: the short-range pass cuts each atom's window
+  // along x to its own reach)
   auto set_cells = [&](int reach, double edge_min) {
     g.reach = reach;
     long long tot = 1;
     for (int d = 0; d < 3; ++d) {
-      int nc = (int)std::floor(p.box_len[d] / edge_min);
-      nc = std::max(1, std::min(nc, 1 << 10));
+      int nc = (int)std::floor(p.box_len[d] / (d == 0 ? edge_min / msm::kXSub : edge_min));
+      nc = std::max(1, std::min(nc, d == 0 ? 4096 : 1024));
       g.nc[d] = nc;
       g.inv_cs[d] = (float)(nc / p.box_len[d]);
+      g.cs[d] = (float)(p.box_len[d] / nc);
       tot *= nc;
     }
     return tot;
@@ -522,6 +567,8 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
     nct = set_cells(1, std::max(amargin, std::cbrt(vol / (double)cap)));
   }
   g.n_cells = (int)nct;
+  g.a_win = (float)(a * (1.0 + 1e-4));
+  assign_short_rows(g);
   // two-kernel binning when the cell counts of every block fit (LDS, histogram size)
   {
     const long long nb = (n_atoms + msm::kBinChunk - 1) / msm::kBinChunk;
@@ -632,7 +679,8 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
   lay.bytes[msm::kSecCursor] = (size_t)g.n_cells * sizeof(int);
   lay.bytes[msm::kSecCellOf] = n * sizeof(int);
   lay.bytes[msm::kSecTmp] = n * sizeof(int);
-  lay.bytes[msm::kSecBinHist] = std::max<size_t>((size_t)g.bin_blocks * g.n_cells, 1) * sizeof(int);
+  lay.bytes[msm::kSecBinHist] =
+      std::max<size_t>((size_t)g.bin_blocks * ((g.n_cells + 3) & ~3), 1) * sizeof(int);
   lay.bytes[msm::kSecRows] = std::max<size_t>(P->rows.size(), 1) * sizeof(msm::StencilRow);
   lay.bytes[msm::kSecWeights] = std::max<size_t>(P->weights.size(), 1) * sizeof(float);
   lay.bytes[msm::kSecRowsC] = std::max<size_t>(P->rows_c.size(), 1) * sizeof(int4);

@@ -15,7 +15,8 @@ constexpr int kMaxLevels = 12;
 constexpr int kMaxOrder = 6;
 constexpr int kMaxTopNodes = 1 << 17;     // all-pairs FP64 top level stays below ~1e10 pair terms
 constexpr int kRankCap = 2048;            // cells longer than this keep scatter order (see bin_place)
-constexpr int kBinChunk = 4096;           // atoms per block of the two-kernel binning
+constexpr int kBinChunk = 2048;           // atoms per block of the two-kernel binning
+constexpr int kXSub = 4;                  // link cells are this many times finer along x
 constexpr int kBinMaxCells = 8192;        // cells the two-kernel binning keeps in LDS
 constexpr int kBinMaxHist = 1 << 20;      // block histogram entries of the two-kernel binning
 
@@ -43,8 +44,11 @@ struct Geom {
   int nc[3];
   int n_cells;
   int bin_blocks;                  // blocks of the two-kernel binning (0: four-kernel binning)
-  int reach;                       // neighbour cells per side
+  int reach;                       // neighbour cell rows per side in y and z
   float inv_cs[3];                 // 1 / cell edge
+  float cs[3];                     // cell edge (x cells are kXSub times finer than y, z)
+  float a_win;                     // cutoff with a margin, for the short-range x windows
+  signed char short_rows[8][8];    // neighbour rows of each short-range wave (-1 ends a list)
   int item_chunks;                 // short-range 64-atom chunks of a cell row per work item
   int row_items;                   // short-range work items per cell row (chunks interleaved)
   int short_blocks;                // blocks of the short-range launch (work items strided over them)

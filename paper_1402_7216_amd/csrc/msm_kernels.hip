@@ -309,8 +309,9 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_hist(KArgs A) {
     }
   }
   __syncthreads();
-  int* out = S.d.bin_hist + (size_t)blk * nc;
-  for (int c = threadIdx.x; c < nc; c += kBinThreads) out[c] = hist[c];
+  const int nc4 = (nc + 3) & ~3;                     // rows padded for 16-byte loads
+  int* out = S.d.bin_hist + (size_t)blk * nc4;
+  for (int c = threadIdx.x; c < nc4; c += kBinThreads) out[c] = c < nc ? hist[c] : 0;
 }
 
 __global__ void __launch_bounds__(kBinThreads) k_bin_sort(KArgs A) {
@@ -343,33 +344,58 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_sort(KArgs A) {
       p[u] = make_float4(x[i], y[i], z[i], q[i]);
     }
   }
-  // per cell: atoms over all blocks, in earlier blocks, in this block
-  const int* __restrict__ bh = S.d.bin_hist;
-  for (int c = t; c < nc; c += kBinThreads) {
-    int tot = 0, pre = 0;
-    for (int b0 = 0; b0 < nb; b0 += 8) {              // 8 loads in flight
-      int v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = (b0 + u < nb) ? bh[(size_t)(b0 + u) * nc + c] : 0;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        tot += v[u];
-        pre += (b0 + u < blk) ? v[u] : 0;
-      }
-    }
-    base[c] = tot;
-    cur[c] = pre;
-    loc[c] = bh[(size_t)blk * nc + c];
-  }
-  __syncthreads();
-  // exclusive scans of the totals and of this block's counts: thread t owns
-  // cells [t k, t k + k)
-  const int k = (nc + kBinThreads - 1) / kBinThreads;
+  // per cell: atoms over all blocks, in earlier blocks, in this block.
+  // Thread t owns cells [t k, t k + k), k = 4 or 8 (rows of the block
+  // histogram are padded to a multiple of 4, read 4 cells per load); the
+  // loads of all its cells are in flight together, blocks taken 8 at a time.
+  const int4* __restrict__ bh4 = reinterpret_cast<const int4*>(S.d.bin_hist);
+  constexpr int kMaxK = kBinMaxCells / kBinThreads;
+  const int nc4 = (nc + 3) & ~3, row4 = nc4 / 4;
+  const int k = ((nc4 + kBinThreads - 1) / kBinThreads + 3) & ~3;
   const int c0 = min(t * k, nc), c1 = min(c0 + k, nc);
+  const bool has = c0 < c1;
+  int tot[kMaxK], pre[kMaxK], own[kMaxK];
+#pragma unroll
+  for (int u4 = 0; u4 < kMaxK / 4; ++u4) {
+    const int4 v = (has && 4 * u4 < k && c0 + 4 * u4 < nc4) ? bh4[(size_t)blk * row4 + c0 / 4 + u4]
+                                                             : make_int4(0, 0, 0, 0);
+    own[4 * u4] = v.x;
+    own[4 * u4 + 1] = v.y;
+    own[4 * u4 + 2] = v.z;
+    own[4 * u4 + 3] = v.w;
+  }
+#pragma unroll
+  for (int u = 0; u < kMaxK; ++u) tot[u] = pre[u] = 0;
+  for (int b0 = 0; b0 < nb; b0 += 8) {
+    int4 v[8][kMaxK / 4];
+#pragma unroll
+    for (int w = 0; w < 8; ++w)
+#pragma unroll
+      for (int u4 = 0; u4 < kMaxK / 4; ++u4)
+        v[w][u4] = (has && b0 + w < nb && 4 * u4 < k && c0 + 4 * u4 < nc4)
+                       ? bh4[(size_t)(b0 + w) * row4 + c0 / 4 + u4]
+                       : make_int4(0, 0, 0, 0);
+#pragma unroll
+    for (int w = 0; w < 8; ++w)
+#pragma unroll
+      for (int u4 = 0; u4 < kMaxK / 4; ++u4) {
+        const int e[4] = {v[w][u4].x, v[w][u4].y, v[w][u4].z, v[w][u4].w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          tot[4 * u4 + c] += e[c];
+          pre[4 * u4 + c] += (b0 + w < blk) ? e[c] : 0;
+        }
+      }
+  }
+#pragma unroll
+  for (int u = 0; u < kMaxK; ++u)
+    if (c0 + u >= c1) tot[u] = pre[u] = own[u] = 0;   // padding cells
+  // exclusive scans of the totals and of this block's counts
   int2 sum = make_int2(0, 0);
-  for (int c = c0; c < c1; ++c) {
-    sum.x += base[c];
-    sum.y += loc[c];
+#pragma unroll
+  for (int u = 0; u < kMaxK; ++u) {
+    sum.x += tot[u];
+    sum.y += own[u];
   }
   // inclusive scan of the thread sums: within each wave by shuffles, then
   // over the wave totals
@@ -385,28 +411,37 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_sort(KArgs A) {
   }
   if (lane == kWave - 1) part[wv] = inc;
   __syncthreads();
-  if (t == 0) {
-    int2 acc = make_int2(0, 0);
-    for (int w = 0; w < kBinThreads / kWave; ++w) {
-      const int2 v = part[w];
-      part[w] = acc;                                  // exclusive prefix of the wave totals
-      acc.x += v.x;
-      acc.y += v.y;
+  constexpr int kWaves = kBinThreads / kWave;
+  if (t < kWave) {                                    // scan of the wave totals by wave 0
+    int2 v = (t < kWaves) ? part[t] : make_int2(0, 0);
+    const int2 own_total = v;
+#pragma unroll
+    for (int off = 1; off < kWaves; off <<= 1) {
+      const int vx = __shfl_up(v.x, off), vy = __shfl_up(v.y, off);
+      if (t >= off) {
+        v.x += vx;
+        v.y += vy;
+      }
     }
-    part[kBinThreads / kWave] = acc;
+    if (t < kWaves) part[kWaves + 1 + t] = make_int2(v.x - own_total.x, v.y - own_total.y);
+    if (t == kWaves - 1) part[kWaves] = v;            // grand totals
   }
   __syncthreads();
-  int run = part[wv].x + inc.x - sum.x, lrun = part[wv].y + inc.y - sum.y;
-  for (int c = c0; c < c1; ++c) {
-    const int v = base[c], w = loc[c];
-    if (blk == 0) S.d.cell_start[c] = run;
-    base[c] = run + cur[c];
-    loc[c] = lrun;
-    cur[c] = 0;
-    run += v;
-    lrun += w;
+  const int2 wpre = part[kWaves + 1 + wv];
+  int run = wpre.x + inc.x - sum.x, lrun = wpre.y + inc.y - sum.y;
+#pragma unroll
+  for (int u = 0; u < kMaxK; ++u) {
+    const int c = c0 + u;
+    if (c < c1) {
+      if (blk == 0) S.d.cell_start[c] = run;
+      base[c] = run + pre[u];
+      loc[c] = lrun;
+      cur[c] = 0;
+      run += tot[u];
+      lrun += own[u];
+    }
   }
-  if (blk == 0 && t == kBinThreads - 1) S.d.cell_start[nc] = part[kBinThreads / kWave].x;
+  if (blk == 0 && t == kBinThreads - 1) S.d.cell_start[nc] = part[kWaves].x;
   __syncthreads();
   // group this block's atoms by cell in LDS (arrival order), then rank each
   // by input index within its cell
@@ -446,24 +481,39 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_sort(KArgs A) {
 // Short-range part (itemised algorithm, first sentence; eq. msmgrid g*):
 //   phi_i^s = sum_j q_j g*(r_ij),  F_i^s = -q_i sum_j q_j g*'(r_ij) (r_i - r_j)/r_ij
 //   g*(r) = 1/r - gamma(r/a)/a,  g*'(r)/r = -1/r^3 - gamma'(r/a)/(a^2 r)
-// Work items: the atoms of a cell row are contiguous in sorted order (cells
-// along x, then input order) and are cut into 64-atom chunks, one atom per
-// lane.  A chunk's atoms lie in x cells [cxa, cxb]; its neighbours lie in the
-// (2 reach + 1)^2 cell rows around it, x cells [cxa - reach, cxb + reach],
-// each row one contiguous j range, cut into chunks of 64.  The block's waves
-// take these (row, j chunk) units in turn, stage each j chunk through their
-// own LDS slice (one coalesced load) and read it back as wave-wide
-// broadcasts, four at a time.  The waves' partial sums meet in LDS and are
-// added in wave order.
+// Work items: the atoms of a cell row are contiguous in sorted order (x
+// cells, then input order) and are cut into 64-atom chunks, one atom per lane.
+// The neighbour atoms of a chunk lie in the (2 reach + 1)^2 cell rows around
+// it (y, z offsets up to reach).  For each such row every lane cuts its own
+// window: with d the distance of the atom to the row in (y, z), only x cells
+// within sqrt(a^2 - d^2) of the atom can hold partners, a contiguous range of
+// sorted atoms.  A wave stages the union of its lanes' windows in LDS (one
+// coalesced load per 256 atoms) and each lane walks its own range (gathered
+// LDS reads).  The rows are dealt to the block's 8 waves by expected window
+// length (fixed per plan); the waves' partial sums meet in LDS and are added
+// in wave order.
 // --------------------------------------------------------------------------
 constexpr int kShortThreads = 512;
 constexpr int kShortWaves = kShortThreads / kWave;
-constexpr int kShortMaxRows = 25;                // (2 reach + 1)^2 with reach <= 2
+constexpr int kShortSeg = 256;                   // j atoms a wave stages at a time
+constexpr int kShortRowsPerWave = 8;
 
 __device__ __forceinline__ int cell_x(const Geom& g, float x) {
   float t = (x - g.lo_f[0]) * g.inv_cs[0];
-  t = fminf(fmaxf(t, 0.f), (float)(g.nc[0] - 1));
+  t = fminf(fmaxf(t, 0.f), (float)(g.nc[0] - 1));   // NaN -> 0
   return min((int)t, g.nc[0] - 1);
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off));
+  return v;
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off));
+  return v;
 }
 
 template <int M, bool FORCES>
@@ -475,21 +525,19 @@ __global__ void __launch_bounds__(kShortThreads) k_short(KArgs A) {
   const int* __restrict__ start = S.d.cell_start;
   float4* __restrict__ fshort = S.d.fshort;
   __shared__ float4 red[kShortWaves][kWave];
-  __shared__ float4 jbuf[kShortWaves][kWave];
-  __shared__ int row_j0[kShortMaxRows], row_j1[kShortMaxRows], unit0[kShortMaxRows + 1];
+  __shared__ float4 jbuf[kShortWaves][kShortSeg];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int n_rows_c = g.nc[1] * g.nc[2];
-  const int n_items = g.row_items * n_rows_c;
-  const float a2 = g.a2, inv_a2 = g.inv_a2;
+  const int n_items = g.row_items * g.nc[1] * g.nc[2];
+  const float a2 = g.a2, inv_a2 = g.inv_a2, aw = g.a_win;
   float gc[M + 1], dc[M + 1];
 #pragma unroll
   for (int k = 0; k <= M; ++k) {
     gc[k] = g.gcoef[k];
     dc[k] = g.dcoef[k];
   }
-  float4* jb_w = jbuf[wave];
-  const int R = g.reach, side = 2 * R + 1, nrows = side * side;
+  float4* jb = jbuf[wave];
+  const int R = g.reach, side = 2 * R + 1, centre = (side * side) / 2;
   // the launch has g.short_blocks blocks; work items are strided over them
   for (int item = blk; item < n_items; item += g.short_blocks) {
     const int row = item / g.row_items, kk = item - row * g.row_items;
@@ -498,89 +546,89 @@ __global__ void __launch_bounds__(kShortThreads) k_short(KArgs A) {
     const int rb = start[rowbase], re = start[rowbase + g.nc[0]];
     for (int ic = rb + kk * kWave; ic < re; ic += g.row_items * kWave) {
       const int ie = min(ic + kWave, re);
-      __syncthreads();                               // tables of the previous chunk are done
-      // neighbour rows: j range and the first (row, chunk) unit of each row
-      if (threadIdx.x < nrows) {
-        const int cxa = cell_x(g, sorted[ic].x), cxb = cell_x(g, sorted[ie - 1].x);
-        const int jx0 = max(cxa - R, 0), jx1 = min(cxb + R, g.nc[0] - 1);
-        const int jy = cy + threadIdx.x % side - R, jz = cz + threadIdx.x / side - R;
-        int j0 = 0, j1 = 0;
-        if (jy >= 0 && jz >= 0 && jy < g.nc[1] && jz < g.nc[2]) {
-          const int jrow = (jz * g.nc[1] + jy) * g.nc[0];
-          j0 = start[jrow + jx0];
-          j1 = start[jrow + jx1 + 1];
-        }
-        row_j0[threadIdx.x] = j0;
-        row_j1[threadIdx.x] = j1;
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        int u = 0;
-        for (int r = 0; r < nrows; ++r) {
-          unit0[r] = u;
-          u += (row_j1[r] - row_j0[r] + kWave - 1) / kWave;
-        }
-        unit0[nrows] = u;
-      }
-      __syncthreads();
-      const int n_units = unit0[nrows];
       const int i = ic + lane;
-      const float4 pi = (i < ie) ? sorted[i] : make_float4(3.0e30f, 3.0e30f, 3.0e30f, 0.f);
+      const bool live = i < ie;
+      const float4 pi = live ? sorted[i] : make_float4(0.f, 0.f, 0.f, 0.f);
       float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;
       bool coincident = false;
-      int r = 0;
-      for (int u = wave; u < n_units; u += kShortWaves) {
-        while (unit0[r + 1] <= u) ++r;               // wave-uniform walk over the rows
-        const int jc = row_j0[r] + (u - unit0[r]) * kWave;
-        const int nj = min(kWave, row_j1[r] - jc);
-        // stage up to 64 j atoms in this wave's LDS slice (coalesced), then
-        // read them back as wave-wide broadcasts
-        jb_w[lane] = (lane < nj) ? sorted[jc + lane] : make_float4(-3.0e30f, -3.0e30f, -3.0e30f, 0.f);
-        if (r == nrows / 2) {
-          // the centre row holds the atom's own cell: any j other than the
-          // atom itself at distance zero is a coincident pair
-          int zeros = 0;
-          for (int t = 0; t < nj; ++t) {
-            const float4 pj = jb_w[t];
-            zeros += (pi.x == pj.x && pi.y == pj.y && pi.z == pj.z);
-          }
-          coincident |= zeros > ((i >= jc && i < jc + nj) ? 1 : 0);
+      for (int q = 0; q < kShortRowsPerWave; ++q) {
+        const int r = g.short_rows[wave][q];
+        if (r < 0) break;
+        const int oy = r % side - R, oz = r / side - R;
+        const int jy = cy + oy, jz = cz + oz;
+        if (jy < 0 || jz < 0 || jy >= g.nc[1] || jz >= g.nc[2]) continue;
+        // this lane's window in the row
+        const float ylo = g.lo_f[1] + (float)jy * g.cs[1], zlo = g.lo_f[2] + (float)jz * g.cs[2];
+        const float dyw = fmaxf(fmaxf(ylo - pi.y, pi.y - (ylo + g.cs[1])), 0.f);
+        const float dzw = fmaxf(fmaxf(zlo - pi.z, pi.z - (zlo + g.cs[2])), 0.f);
+        const float d2 = fmaf(dyw, dyw, dzw * dzw);
+        const int jrow = (jz * g.nc[1] + jy) * g.nc[0];
+        int lo = 0x7fffffff, hi = -1;
+        if (live && d2 < aw * aw) {
+          const float e = sqrtf(aw * aw - d2) + 1e-4f * aw;
+          lo = start[jrow + cell_x(g, pi.x - e)];
+          hi = start[jrow + cell_x(g, pi.x + e) + 1];
         }
-        for (int t0 = 0; t0 < nj; t0 += 4) {
-          float4 pj[4];
+        const int u0 = wave_min(lo), u1 = wave_max(hi);
+        for (int s0 = u0; s0 < u1; s0 += kShortSeg) {
+          // stage the union of the windows, 256 atoms at a time
 #pragma unroll
-          for (int v = 0; v < 4; ++v) pj[v] = jb_w[t0 + v];      // padded past nj
+          for (int v = 0; v < kShortSeg / kWave; ++v) {
+            const int j = s0 + v * kWave + lane;
+            jb[v * kWave + lane] = (j < u1) ? sorted[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+          }
+          // this lane's part of the staged segment: [a0, a0 + n) (n = 0 keeps a0 = 0)
+          const int lo_s = max(lo, s0) - s0, hi_s = min(hi, s0 + kShortSeg) - s0;
+          const int n = (hi > lo && hi_s > lo_s) ? hi_s - lo_s : 0;
+          const int a0 = n > 0 ? lo_s : 0;
+          const int b0 = a0 + n;
+          const int nmax = wave_max(n);
+          if (r == centre) {
+            // the centre row holds the atom's own cell: any other atom at
+            // distance zero is a coincident pair
+            int zeros = 0;
+            for (int t = 0; t < n; ++t) {
+              const float4 pj = jb[a0 + t];
+              zeros += (pi.x == pj.x && pi.y == pj.y && pi.z == pj.z);
+            }
+            coincident |= zeros > ((i >= s0 + a0 && i < s0 + b0) ? 1 : 0);
+          }
+          for (int t0 = 0; t0 < nmax; t0 += 4) {
+            float4 pj[4];
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const float dx = pi.x - pj[v].x, dy = pi.y - pj[v].y, dz = pi.z - pj[v].z;
-            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            if (r2 < a2 && r2 > 0.f) {
-              // hardware reciprocal square root plus one Newton step (the raw
-              // instruction's error is biased, which would bias the energy)
-              float ri = __builtin_amdgcn_rsqf(r2);
-              ri = fmaf(0.5f * ri, fmaf(-r2 * ri, ri, 1.f), ri);
-              const float s = r2 * inv_a2;
-              float gm = gc[M], dg = dc[M];
+            for (int v = 0; v < 4; ++v) pj[v] = jb[min(a0 + t0 + v, kShortSeg - 1)];
 #pragma unroll
-              for (int k = M - 1; k >= 0; --k) gm = fmaf(gm, s, gc[k]);
+            for (int v = 0; v < 4; ++v) {
+              const float dx = pi.x - pj[v].x, dy = pi.y - pj[v].y, dz = pi.z - pj[v].z;
+              const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+              if (t0 + v < n && r2 < a2 && r2 > 0.f) {
+                // hardware reciprocal square root plus one Newton step (the raw
+                // instruction's error is biased, which would bias the energy)
+                float ri = __builtin_amdgcn_rsqf(r2);
+                ri = fmaf(0.5f * ri, fmaf(-r2 * ri, ri, 1.f), ri);
+                const float sr = r2 * inv_a2;
+                float gm = gc[M], dg = dc[M];
 #pragma unroll
-              for (int k = M - 1; k >= 1; --k) dg = fmaf(dg, s, dc[k]);
-              const float qj = pj[v].w;
-              ap = fmaf(qj, ri - gm, ap);                     // q_j g*(r)
-              if (FORCES) {
-                const float wq = qj * fmaf(ri, ri * ri, dg);  // q_j (-g*'(r)/r)
-                ax = fmaf(wq, dx, ax);
-                ay = fmaf(wq, dy, ay);
-                az = fmaf(wq, dz, az);
+                for (int k = M - 1; k >= 0; --k) gm = fmaf(gm, sr, gc[k]);
+#pragma unroll
+                for (int k = M - 1; k >= 1; --k) dg = fmaf(dg, sr, dc[k]);
+                const float qj = pj[v].w;
+                ap = fmaf(qj, ri - gm, ap);                     // q_j g*(r)
+                if (FORCES) {
+                  const float wq = qj * fmaf(ri, ri * ri, dg);  // q_j (-g*'(r)/r)
+                  ax = fmaf(wq, dx, ax);
+                  ay = fmaf(wq, dy, ay);
+                  az = fmaf(wq, dz, az);
+                }
               }
             }
           }
         }
       }
-      if (coincident && i < ie) atomicOr(S.d.status, kFlagCoincident);
+      if (coincident) atomicOr(S.d.status, kFlagCoincident);
       red[wave][lane] = make_float4(ax, ay, az, ap);
       __syncthreads();
-      if (wave == 0 && i < ie) {
+      if (wave == 0 && live) {
         float4 t = red[0][lane];
 #pragma unroll
         for (int w = 1; w < kShortWaves; ++w) {
@@ -593,6 +641,7 @@ __global__ void __launch_bounds__(kShortThreads) k_short(KArgs A) {
         const float qi = pi.w;
         fshort[i] = make_float4(qi * t.x, qi * t.y, qi * t.z, t.w);
       }
+      __syncthreads();
     }
   }
 }
