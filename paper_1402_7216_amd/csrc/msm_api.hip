@@ -537,6 +537,8 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
   for (int k = 0; k <= g.m; ++k) {
     g.gcoef[k] = (float)(c[k] / a);
     g.dcoef[k] = (float)(2.0 * k * c[k] / (a * a * a));
+    g.gr[k] = (float)(c[k] / std::pow(a, 2.0 * k + 1.0));
+    g.dr[k] = (float)(2.0 * k * c[k] / std::pow(a, 2.0 * k + 1.0));
   }
   g.self = (float)(c[0] / a);
   g.a2 = (float)(a * a);

@@ -426,9 +426,10 @@ msm_status msm_batch_tune(msm_batch* Bt, void* ws, size_t ws_bytes, msm_stream_t
 }
 
 // Time candidates over `trials` evaluations of the given inputs with HIP
-// events on `stream`: lattice_b in {4, 6, 8} x item_chunks in {1, 2, 3} with the
-// current short-range block count, then short-range block counts for the best
-// pair.  Apply the fastest and describe the search in `report` (JSON, nullable).
+// events on `stream`: lattice_b in {4, 6, 8} x item_chunks in {1, 2, 3} with
+// every stream on and one short-range block per work item, then the stream
+// layouts x short-range block counts for the best pair.  Apply the fastest and
+// describe the search in `report` (JSON, nullable).
 static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm_stream_t stream,
                            const float* x, const float* y, const float* z, const float* q,
                            int32_t trials, char* report, size_t report_bytes) {
@@ -488,18 +489,23 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
       float ms = 0.f;
       if (st == MSM_OK) st = time_one(b, w, -1, 3, ms);
     }
+  // stream layouts x short-range block counts for the best (B, chunks); the
+  // counts are fractions of the compute units, so the short-range pass leaves
+  // room for the grid chain running beside it
   const int bb = best_b, bw = best_w;
-  for (int n : {1, 2})
-    if (st == MSM_OK) {
-      float ms = 0.f;
-      st = time_one(bb, bw, -1, n, ms);
-    }
-  const int bn = best_n;
-  for (int c : {384, 256, 128})
-    if (st == MSM_OK) {
-      float ms = 0.f;
-      st = time_one(bb, bw, c, bn, ms);
-    }
+  int n_cu = 256;
+  {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      n_cu = prop.multiProcessorCount;
+  }
+  for (int n : {1, 2, 3})
+    for (int c : {-1, 3 * n_cu / 2, n_cu, 3 * n_cu / 4, n_cu / 2})
+      if (st == MSM_OK && !(n == 3 && c == -1)) {
+        float ms = 0.f;
+        st = time_one(bb, bw, c, n, ms);
+      }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != MSM_OK) return st;

@@ -57,6 +57,8 @@ struct Geom {
   float inv_a2;                    // 1 / a^2
   float gcoef[8];                  // c_k / a         (gamma(rho)/a = sum gcoef[k] s^k, s = rho^2)
   float dcoef[8];                  // 2 k c_k / a^3   (gamma'(rho)/(a^2 r) = sum_{k>=1} dcoef[k] s^{k-1})
+  float gr[8];                     // c_k / a^(2k+1)       (gamma(r/a)/a as a polynomial in r^2)
+  float dr[8];                     // 2 k c_k / a^(2k+1)   (gamma'(r/a)/(a^2 r) = sum_{k>=1} dr[k] r^2(k-1))
   int m;                           // smoothing degree
   float self;                      // gamma(0) / a
   double ke;                       // energy prefactor

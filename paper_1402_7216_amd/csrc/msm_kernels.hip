@@ -529,12 +529,12 @@ __global__ void __launch_bounds__(kShortThreads) k_short(KArgs A) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int n_items = g.row_items * g.nc[1] * g.nc[2];
-  const float a2 = g.a2, inv_a2 = g.inv_a2, aw = g.a_win;
+  const float a2 = g.a2, aw = g.a_win;
   float gc[M + 1], dc[M + 1];
 #pragma unroll
   for (int k = 0; k <= M; ++k) {
-    gc[k] = g.gcoef[k];
-    dc[k] = g.dcoef[k];
+    gc[k] = g.gr[k];
+    dc[k] = g.dr[k];
   }
   float4* jb = jbuf[wave];
   const int R = g.reach, side = 2 * R + 1, centre = (side * side) / 2;
@@ -601,17 +601,18 @@ __global__ void __launch_bounds__(kShortThreads) k_short(KArgs A) {
             for (int v = 0; v < 4; ++v) {
               const float dx = pi.x - pj[v].x, dy = pi.y - pj[v].y, dz = pi.z - pj[v].z;
               const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-              if (t0 + v < n && r2 < a2 && r2 > 0.f) {
+              // one predicate (non-short-circuit), so a single branch per pair
+              if ((t0 + v < n) & (r2 < a2) & (r2 > 0.f)) {
                 // hardware reciprocal square root plus one Newton step (the raw
                 // instruction's error is biased, which would bias the energy)
                 float ri = __builtin_amdgcn_rsqf(r2);
                 ri = fmaf(0.5f * ri, fmaf(-r2 * ri, ri, 1.f), ri);
-                const float sr = r2 * inv_a2;
+                // gamma(r/a)/a and gamma'(r/a)/(a^2 r) as polynomials in r^2
                 float gm = gc[M], dg = dc[M];
 #pragma unroll
-                for (int k = M - 1; k >= 0; --k) gm = fmaf(gm, sr, gc[k]);
+                for (int k = M - 1; k >= 0; --k) gm = fmaf(gm, r2, gc[k]);
 #pragma unroll
-                for (int k = M - 1; k >= 1; --k) dg = fmaf(dg, sr, dc[k]);
+                for (int k = M - 1; k >= 1; --k) dg = fmaf(dg, r2, dc[k]);
                 const float qj = pj[v].w;
                 ap = fmaf(qj, ri - gm, ap);                     // q_j g*(r)
                 if (FORCES) {
