@@ -185,15 +185,18 @@ typedef struct msm_tuning {
   int32_t streams;       /* 1: every stage in order on the caller's stream;
                             2: the short-range pass on a side stream;
                             3: also the level-0 lattice cutoff on a side stream */
-  int32_t reserved[4];   /* must be zero */
+  int32_t short_after;   /* with a side stream, the short-range pass starts after
+                            1: binning, 2: anterpolation, 3: the coarse lattice
+                            cutoff (it then overlaps the prolongations) */
+  int32_t reserved[3];   /* must be zero */
 } msm_tuning;
 
 /* Apply tuning knobs to a plan and re-upload its descriptor to ws (other
  * workspaces of the plan must be initialised again).  msm_plan_autotune times
  * candidates over `trials` evaluations of the given device inputs on `stream`
  * with HIP events: lattice_b (4, 6, 8) x item_chunks (1, 2, 3) first, then the
- * stream layout and short-range block counts for the best pair; it applies
- * the fastest and writes a JSON report (nullable) of the search.  *current
+ * stream layout x short-range block counts, then the short-range start; it
+ * applies the fastest and writes a JSON report (nullable) of the search.  *current
  * (msm_plan_tuning, nullable) receives the tuning in effect. */
 msm_status msm_plan_tune(msm_plan* plan, void* ws, size_t ws_bytes, msm_stream_t stream,
                          const msm_tuning* tuning);

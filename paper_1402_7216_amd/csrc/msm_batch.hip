@@ -93,6 +93,7 @@ void rebuild_maps(msm_batch* Bt) {
   L.order = Bt->plans[0]->g.order;
   L.m = Bt->plans[0]->g.m;
   L.streams = Bt->plans[0]->streams;
+  L.short_after = Bt->plans[0]->short_after;
   L.lat_b = 0;
   L.bin4 = false;
   for (int st = 0; st < kNumStages; ++st) Bt->map[st].clear();
@@ -208,7 +209,7 @@ msm_status msm_batch_create(const msm_params* params, const int32_t* n_atoms, in
   for (int s = 1; s < n_sys; ++s)
     if (n_atoms[s] > n_atoms[big]) big = s;
   const int b0 = Bt->plans[big]->lat.b;
-  for (msm_plan* P : Bt->plans) retune(P, msm_tuning{b0, 0, 0, 0, {}});
+  for (msm_plan* P : Bt->plans) retune(P, msm_tuning{b0, 0, 0, 0, 0, {}});
 
   // stage-table reserves: the most blocks any tuning can ask for
   // (lattice template 4, one cell per short-range work item)
@@ -220,7 +221,7 @@ msm_status msm_batch_create(const msm_params* params, const int32_t* n_atoms, in
     size_t most[kNumStages] = {};
     for (int b : {4, 6, 8})
       for (int w : {1, keep_g.item_chunks}) {
-        retune(P, msm_tuning{P->lat.b ? b : 0, w, -1, 0, {}});   // one short-range block per item: the most
+        retune(P, msm_tuning{P->lat.b ? b : 0, w, -1, 0, 0, {}});   // one short-range block per item: the most
         const msm::SysBlocks sb = msm::system_blocks(P->g, P->lat, P->n_partials);
         for (int st = 0; st < kNumStages; ++st) most[st] = std::max(most[st], (size_t)blocks_of(sb, st));
       }
@@ -386,7 +387,8 @@ msm_status msm_batch_describe(const msm_batch* Bt, char* buf, size_t buf_bytes) 
 
 msm_status msm_plan_tuning(const msm_plan* P, msm_tuning* t) {
   if (!P || !t) return fail(MSM_ERR_INVALID_ARG, "null plan or tuning");
-  *t = msm_tuning{P->lat.b, P->g.item_chunks, P->short_cap > 0 ? P->short_cap : -1, P->streams, {}};
+  *t = msm_tuning{P->lat.b, P->g.item_chunks, P->short_cap > 0 ? P->short_cap : -1, P->streams,
+                  P->short_after, {}};
   return MSM_OK;
 }
 
@@ -442,8 +444,8 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
   msm_batch* Bt = batch ? static_cast<msm_batch*>(obj) : nullptr;
   msm_plan* P = batch ? nullptr : static_cast<msm_plan*>(obj);
   const bool tiled = batch ? Bt->lg.lat_b > 0 : P->lat.b > 0;
-  auto tune = [&](int b, int w, int c, int n) {
-    const msm_tuning t{b, w, c, n, {}};
+  auto tune = [&](int b, int w, int c, int n, int sa) {
+    const msm_tuning t{b, w, c, n, sa, {}};
     return batch ? msm_batch_tune(Bt, ws, ws_bytes, stream, &t) : msm_plan_tune(P, ws, ws_bytes, stream, &t);
   };
   auto eval = [&]() {
@@ -454,10 +456,10 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
   };
   std::string rep = "{\"candidates\": [";
   float best = 1e30f;
-  int best_b = 0, best_w = 0, best_c = 0, best_n = 0;
+  int best_b = 0, best_w = 0, best_c = 0, best_n = 0, best_sa = 1;
   bool first = true;
-  auto time_one = [&](int b, int w, int c, int n, float& ms) {
-    msm_status st = tune(b, w, c, n);
+  auto time_one = [&](int b, int w, int c, int n, int sa, float& ms) {
+    msm_status st = tune(b, w, c, n, sa);
     // one warm-up evaluation, then `trials` timed ones
     for (int t = -1; t < trials && st == MSM_OK; ++t) {
       if (t == 0) (void)hipEventRecord(e0, s);
@@ -471,7 +473,8 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
     ms /= trials;
     rep += std::string(first ? "" : ", ") + "{\"lattice_b\": " + std::to_string(b) + ", \"item_chunks\": " +
            std::to_string(w) + ", \"short_blocks\": " + std::to_string(c) + ", \"streams\": " +
-           std::to_string(n) + ", \"ms\": " + std::to_string(ms) + "}";
+           std::to_string(n) + ", \"short_after\": " + std::to_string(sa) + ", \"ms\": " + std::to_string(ms) +
+           "}";
     first = false;
     if (ms < best) {
       best = ms;
@@ -479,6 +482,7 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
       best_w = w;
       best_c = c;
       best_n = n;
+      best_sa = sa;
     }
     return MSM_OK;
   };
@@ -487,7 +491,7 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
   for (int b : bs)
     for (int w : {1, 2, 3}) {
       float ms = 0.f;
-      if (st == MSM_OK) st = time_one(b, w, -1, 3, ms);
+      if (st == MSM_OK) st = time_one(b, w, -1, 3, 1, ms);
     }
   // stream layouts x short-range block counts for the best (B, chunks); the
   // counts are fractions of the compute units, so the short-range pass leaves
@@ -504,16 +508,25 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
     for (int c : {-1, 3 * n_cu / 2, n_cu, 3 * n_cu / 4, n_cu / 2})
       if (st == MSM_OK && !(n == 3 && c == -1)) {
         float ms = 0.f;
-        st = time_one(bb, bw, c, n, ms);
+        st = time_one(bb, bw, c, n, 1, ms);
+      }
+  // where the side-stream short range starts, for the best layout so far
+  const int bc = best_c, bn = best_n;
+  if (bn >= 2)
+    for (int sa : {2, 3})
+      if (st == MSM_OK) {
+        float ms = 0.f;
+        st = time_one(bb, bw, bc, bn, sa, ms);
       }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != MSM_OK) return st;
-  st = tune(best_b, best_w, best_c, best_n);
+  st = tune(best_b, best_w, best_c, best_n, best_sa);
   if (st != MSM_OK) return st;
   rep += "], \"best\": {\"lattice_b\": " + std::to_string(best_b) + ", \"item_chunks\": " +
          std::to_string(best_w) + ", \"short_blocks\": " + std::to_string(best_c) + ", \"streams\": " +
-         std::to_string(best_n) + ", \"ms\": " + std::to_string(best) + "}}";
+         std::to_string(best_n) + ", \"short_after\": " + std::to_string(best_sa) + ", \"ms\": " +
+         std::to_string(best) + "}}";
   if (report && report_bytes) {
     std::strncpy(report, rep.c_str(), report_bytes - 1);
     report[report_bytes - 1] = 0;

@@ -20,6 +20,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWave = 64;
 
+
 // Quotient and remainder of 0 <= i < 2^20 by 0 < d <= 2^10 with a float
 // reciprocal (inv_d = 1/d rounded): (i + 1/2)/d lies at least 1/(2d) away from
 // an integer, far more than the rounding error of (i + 1/2) * inv_d, so the
@@ -1567,10 +1568,12 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
     k_bin_sort<<<L.bin.blocks, kBinThreads, sort_lds, s>>>(args(L.bin));
   }
 
-  // short-range pairs: on their own stream, joined before interpolation
+  // short-range pairs: on their own stream (forked after binning,
+  // anterpolation or the coarse lattice cutoff), joined before interpolation
   mark(kStageShort);
   const bool short_side = concurrent && L.streams >= 2 && have_atoms && L.shortr.blocks > 0;
-  if (have_atoms && L.shortr.blocks > 0) {
+  auto launch_short = [&]() {
+    if (!(have_atoms && L.shortr.blocks > 0)) return;
     hipStream_t ss = s;
     if (short_side) {
       fork(cc->shortr);
@@ -1596,13 +1599,16 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
     }
 #undef MSM_SHORT
     if (short_side) (void)hipEventRecord(cc->shortr.join, ss);
-  }
+  };
+  const int short_at = short_side ? L.short_after : 1;
+  if (short_at == 1) launch_short();
 
   mark(kStageAnterp);
   if (L.order == 4)
     k_anterp<4><<<L.anterp.blocks, kAThreads, 0, s>>>(args(L.anterp));
   else
     k_anterp<6><<<L.anterp.blocks, kAThreads, 0, s>>>(args(L.anterp));
+  if (short_at == 2) launch_short();
 
   // lattice cutoff of one part (0: level 0, 1: levels 1 .. l-2) on stream `ls`
   auto lattice = [&](const StageGrid& sg, int part, hipStream_t ls) {
@@ -1645,6 +1651,7 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
   mark(kStageLattice);
   if (!lat0_side) lattice(L.lattice0, 0, s);
   lattice(L.lattice, 1, s);
+  if (short_at == 3) launch_short();
   mark(kStageTop);
   if (L.top.blocks > 0) k_top<<<L.top.blocks, kBlock, 0, s>>>(args(L.top));
 

@@ -33,6 +33,7 @@ struct msm_plan {
   int lat_part_max = 0;                      // lattice row-group partials of the largest tuning
   int short_cap = 0;                         // short-range blocks (0: one per work item)
   int streams = 3;                           // stream layout of an evaluation (msm_tuning.streams)
+  int short_after = 1;                       // start of the side-stream short range (msm_tuning.short_after)
   Layout lay;
   msm::SysDesc desc;                         // host copy; device pointers filled per workspace
   msm::LaunchGeom lg;                        // stage grids of one evaluation (descriptor set per call)

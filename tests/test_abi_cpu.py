@@ -176,7 +176,7 @@ def test_batch_rejects_mixed_order_and_bad_sizes(M):
 
 
 @pytest.mark.parametrize("field,value", [("lattice_b", 5), ("item_chunks", -2), ("short_blocks", -2),
-                                         ("streams", 4), ("reserved", 1)])
+                                         ("streams", 4), ("short_after", 4), ("reserved", 1)])
 def test_tuning_values_are_checked_before_any_device_work(M, field, value):
     code, h = _plan(M, 10, **CASES[0])
     assert code == 0
@@ -190,5 +190,6 @@ def test_tuning_values_are_checked_before_any_device_work(M, field, value):
         cur = M.Tuning()
         assert M.lib().msm_plan_tuning(h, ctypes.byref(cur)) == 0
         assert cur.lattice_b in (0, 4, 6, 8) and cur.item_chunks >= 1 and cur.streams == 3
+        assert cur.short_after == 1
     finally:
         M.lib().msm_plan_destroy(h)
