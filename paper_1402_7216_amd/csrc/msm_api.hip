@@ -310,6 +310,7 @@ void refresh_launch(msm_plan* P) {
   lg.anterp.blocks = sb.anterp;
   lg.lattice0.blocks = sb.lattice0;
   lg.lattice.blocks = sb.lattice;
+  lg.lattice_all.blocks = sb.lattice_all;
   lg.top.blocks = sb.top;
   lg.energy.blocks = sb.energy;
   for (int k = 0; k + 1 < g.levels; ++k) {

@@ -18,7 +18,7 @@ namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-constexpr int kNumStages = 10 + 2 * msm::kMaxLevels;
+constexpr int kNumStages = 11 + 2 * msm::kMaxLevels;
 
 }  // namespace
 
@@ -45,7 +45,8 @@ namespace {
 
 // Stage order inside the map arrays.
 enum : int {
-  kMZero = 0, kMAtoms, kMBin, kMOne, kMShort, kMAnterp, kMLattice0, kMLattice, kMTop, kMEnergy, kMRestrict0,
+  kMZero = 0, kMAtoms, kMBin, kMOne, kMShort, kMAnterp, kMLattice0, kMLattice, kMLatticeAll, kMTop, kMEnergy,
+  kMRestrict0,
   kMProlong0 = kMRestrict0 + msm::kMaxLevels
 };
 
@@ -59,6 +60,7 @@ msm::StageGrid* stage_of(msm::LaunchGeom& L, int st) {
     case kMAnterp: return &L.anterp;
     case kMLattice0: return &L.lattice0;
     case kMLattice: return &L.lattice;
+    case kMLatticeAll: return &L.lattice_all;
     case kMTop: return &L.top;
     case kMEnergy: return &L.energy;
     default:
@@ -77,6 +79,7 @@ int blocks_of(const msm::SysBlocks& b, int st) {
     case kMAnterp: return b.anterp;
     case kMLattice0: return b.lattice0;
     case kMLattice: return b.lattice;
+    case kMLatticeAll: return b.lattice_all;
     case kMTop: return b.top;
     case kMEnergy: return b.energy;
     default:
@@ -370,7 +373,7 @@ msm_status msm_batch_describe(const msm_batch* Bt, char* buf, size_t buf_bytes) 
                   ", \"blocks\": {\"atoms\": " + std::to_string(L.atoms.blocks) +
                   ", \"short\": " + std::to_string(L.shortr.blocks) +
                   ", \"anterp\": " + std::to_string(L.anterp.blocks) +
-                  ", \"lattice\": " + std::to_string(L.lattice0.blocks + L.lattice.blocks) +
+                  ", \"lattice\": " + std::to_string(L.lattice_all.blocks) +
                   ", \"top\": " + std::to_string(L.top.blocks) + "}, \"levels\": [";
   for (int s = 0; s < Bt->n_sys; ++s) o += (s ? ", " : "") + std::to_string(Bt->plans[s]->g.levels);
   o += "], \"item_chunks_all\": [";

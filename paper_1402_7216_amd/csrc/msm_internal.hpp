@@ -233,14 +233,15 @@ struct LaunchGeom {
   StageGrid bin;                     // two-kernel binning (systems with bin_blocks > 0)
   bool bin4 = true;                  // some system uses the four-kernel binning
   StageGrid lattice0;                // lattice cutoff of level 0
-  StageGrid lattice;                 // lattice cutoff of levels 1 .. l-2
+  StageGrid lattice;                 // lattice cutoff of levels 1 .. l-2 (with the top level)
+  StageGrid lattice_all;             // every level in one launch (no level-0 side stream)
   StageGrid restrict_[kMaxLevels];   // level k -> k+1
   StageGrid prolong[kMaxLevels];     // level k+1 -> k
 };
 
 // Per-stage block counts of one system.
 struct SysBlocks {
-  int zero, atoms, bin, shortr, anterp, lattice0, lattice, top, energy;
+  int zero, atoms, bin, shortr, anterp, lattice0, lattice, lattice_all, top, energy;
   int restrict_[kMaxLevels];
   int prolong[kMaxLevels];
 };

@@ -926,12 +926,16 @@ __global__ void __launch_bounds__(kBlock) k_top(KArgs A) {
   top_node(S, node, threadIdx.x & (kWave - 1));
 }
 
-// Blocks of the coarse lattice-cutoff launch (part 1) of a system: its coarse
-// tiles, then kLatWaves top-level nodes per block.
-__device__ __forceinline__ int lattice_coarse_blocks(const LatLaunch& P) {
-  if (P.n < 2) return 0;
+// Blocks of a lattice-cutoff launch of a system.  part 0: the level-0 tiles;
+// part 1: the coarse tiles (levels 1 .. l-2) then kLatWaves top-level nodes
+// per block; part 2: every tile then the top level (one launch when level 0
+// has no stream of its own).  first = first tile block of the part.
+__device__ __forceinline__ int lattice_tile_blocks(const LatLaunch& P, int part, int& first) {
   const LatTile& t = P.t[P.n - 1];
-  return t.block0 + t.ntx * t.nty * t.ntz * t.groups - P.t[1].block0;
+  const int total = t.block0 + t.ntx * t.nty * t.ntz * t.groups;
+  const int b1 = P.n > 1 ? P.t[1].block0 : total;
+  first = (part == 1) ? b1 : 0;
+  return (part == 0) ? b1 : (part == 1 ? total - b1 : total);
 }
 
 // --------------------------------------------------------------------------
@@ -939,7 +943,8 @@ __device__ __forceinline__ int lattice_coarse_blocks(const LatLaunch& P) {
 //   u^{k,cut}_mu = sum_{|n| < 2a/h} g^k(2^k h |n|) q^k_{mu+n} = 2^-k sum W(n) q^k_{mu+n}
 // with W(n) = g^0(h|n|) from the stencil table (rows of taps along z).
 // --------------------------------------------------------------------------
-// part 0: the nodes of level 0; part 1: the nodes of levels 1 .. l-2.
+// part 0: the nodes of level 0; part 1: the nodes of levels 1 .. l-2;
+// part 2: both.
 __global__ void __launch_bounds__(kBlock) k_lattice(KArgs A, int part) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
@@ -949,8 +954,8 @@ __global__ void __launch_bounds__(kBlock) k_lattice(KArgs A, int part) {
   const float* __restrict__ wts = S.d.weights;
   const float* __restrict__ qgrid = S.d.qgrid;
   float* __restrict__ ucut = S.d.ucut;
-  const int first = part ? g.lv[1].off : 0;
-  const int end = part ? g.lv[g.levels - 1].off : g.lv[1].off;   // the top level is not included
+  const int first = (part == 1) ? g.lv[1].off : 0;
+  const int end = (part == 0) ? g.lv[1].off : g.lv[g.levels - 1].off;   // the top level is not included
   int gid = first + blk * blockDim.x + threadIdx.x;
   if (gid >= end) return;
   int k = 0;
@@ -1032,20 +1037,22 @@ __device__ __forceinline__ void row_win_dispatch(int xr, float* acc, const float
   }
 }
 
-// part 0: the tiles of level 0; part 1: the tiles of levels 1 .. l-2.
+// part 0: the tiles of level 0; part 1: the tiles of levels 1 .. l-2 and the
+// top level; part 2: every tile and the top level.
 template <int B>
 __global__ void __launch_bounds__(kLatThreads) k_lattice_win(KArgs A, int part) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
   const Geom& g = S.g;
   const LatLaunch& P = S.lat;
-  if (part) {
-    const int nl = lattice_coarse_blocks(P);
+  {
+    int first;
+    const int nl = lattice_tile_blocks(P, part, first);
     if (blk >= nl) {                                    // a top-level block (no barriers)
       top_node(S, (blk - nl) * kLatWaves + (int)(threadIdx.x / kWave), threadIdx.x & (kWave - 1));
       return;
     }
-    if (P.n > 1) blk += P.t[1].block0;
+    blk += first;
   }
   const int4* __restrict__ rows_g = S.d.rows_c;
   const float* __restrict__ wc_g = S.d.weights_c;
@@ -1519,8 +1526,11 @@ SysBlocks system_blocks(const Geom& g, const LatLaunch& lat, int n_partials) {
     }
   }
   const int top_nodes = g.lv[g.levels - 1].count;
+  b.lattice_all = b.lattice0 + b.lattice;
   if (g.levels > 1 && lat.b > 0) {
-    b.lattice += (top_nodes + kLatWaves - 1) / kLatWaves;   // top level rides in the coarse launch
+    const int tb = (top_nodes + kLatWaves - 1) / kLatWaves;  // top level rides in the coarse launch
+    b.lattice += tb;
+    b.lattice_all += tb;
     b.top = 0;
   } else {
     b.top = blocks_for(top_nodes * kWave);
@@ -1610,7 +1620,8 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
     k_anterp<6><<<L.anterp.blocks, kAThreads, 0, s>>>(args(L.anterp));
   if (short_at == 2) launch_short();
 
-  // lattice cutoff of one part (0: level 0, 1: levels 1 .. l-2) on stream `ls`
+  // lattice cutoff of one part (0: level 0, 1: levels 1 .. l-2 and the top,
+  // 2: all of them) on stream `ls`
   auto lattice = [&](const StageGrid& sg, int part, hipStream_t ls) {
     if (sg.blocks == 0) return;
     const KArgs A = args(sg);
@@ -1649,8 +1660,10 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
       k_restrict<6><<<sg.blocks, kRThreads, 0, s>>>(args(sg), k);
   }
   mark(kStageLattice);
-  if (!lat0_side) lattice(L.lattice0, 0, s);
-  lattice(L.lattice, 1, s);
+  if (lat0_side)
+    lattice(L.lattice, 1, s);
+  else
+    lattice(L.lattice_all, 2, s);                      // every level (and the top) in one launch
   if (short_at == 3) launch_short();
   mark(kStageTop);
   if (L.top.blocks > 0) k_top<<<L.top.blocks, kBlock, 0, s>>>(args(L.top));
