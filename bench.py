@@ -120,6 +120,9 @@ def main():
     ap.add_argument("--launch", default="best", choices=("best", "hipGraph", "eager"),
                     help="launch mode to time (best: time both, report the faster)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the plan's default tuning")
+    ap.add_argument("--tuning", default=None,
+                    help="JSON tuning to apply instead of autotuning, e.g. the config.tuning of an "
+                         "earlier run (for profiler passes over the timed configuration)")
     ap.add_argument("--cpu-repeats", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-replica batched leg")
@@ -144,9 +147,10 @@ def main():
     plan.check()
     levels, glo, gn = plan.info()
     nodes = [int(np.prod(v)) for v in gn]
-    tuning = None
-    if not args.no_autotune:
-        tuning = plan.autotune(x, y, z, q, trials=20)["best"]
+    if args.tuning:
+        plan.tune(**json.loads(args.tuning))
+    elif not args.no_autotune:
+        plan.autotune(x, y, z, q, trials=20)
 
     graph = msm.Graph(plan, x, y, z, q, out)
 

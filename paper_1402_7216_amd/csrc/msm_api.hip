@@ -315,8 +315,8 @@ void refresh_launch(msm_plan* P) {
   lg.energy.blocks = sb.energy;
   for (int k = 0; k + 1 < g.levels; ++k) {
     lg.restrict_[k].blocks = sb.restrict_[k];
-    lg.prolong[k].blocks = sb.prolong[k];
   }
+  lg.prolong.blocks = sb.prolong;
 }
 
 // Neighbour cell rows (offsets oy, oz in [-reach, reach], row index

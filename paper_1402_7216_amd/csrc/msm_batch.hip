@@ -18,7 +18,7 @@ namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-constexpr int kNumStages = 11 + 2 * msm::kMaxLevels;
+constexpr int kNumStages = 12 + msm::kMaxLevels;
 
 }  // namespace
 
@@ -46,8 +46,8 @@ namespace {
 // Stage order inside the map arrays.
 enum : int {
   kMZero = 0, kMAtoms, kMBin, kMOne, kMShort, kMAnterp, kMLattice0, kMLattice, kMLatticeAll, kMTop, kMEnergy,
-  kMRestrict0,
-  kMProlong0 = kMRestrict0 + msm::kMaxLevels
+  kMProlong,
+  kMRestrict0
 };
 
 msm::StageGrid* stage_of(msm::LaunchGeom& L, int st) {
@@ -63,9 +63,8 @@ msm::StageGrid* stage_of(msm::LaunchGeom& L, int st) {
     case kMLatticeAll: return &L.lattice_all;
     case kMTop: return &L.top;
     case kMEnergy: return &L.energy;
-    default:
-      if (st < kMProlong0) return &L.restrict_[st - kMRestrict0];
-      return &L.prolong[st - kMProlong0];
+    case kMProlong: return &L.prolong;
+    default: return &L.restrict_[st - kMRestrict0];
   }
 }
 
@@ -82,9 +81,8 @@ int blocks_of(const msm::SysBlocks& b, int st) {
     case kMLatticeAll: return b.lattice_all;
     case kMTop: return b.top;
     case kMEnergy: return b.energy;
-    default:
-      if (st < kMProlong0) return b.restrict_[st - kMRestrict0];
-      return b.prolong[st - kMProlong0];
+    case kMProlong: return b.prolong;
+    default: return b.restrict_[st - kMRestrict0];
   }
 }
 

@@ -236,14 +236,14 @@ struct LaunchGeom {
   StageGrid lattice;                 // lattice cutoff of levels 1 .. l-2 (with the top level)
   StageGrid lattice_all;             // every level in one launch (no level-0 side stream)
   StageGrid restrict_[kMaxLevels];   // level k -> k+1
-  StageGrid prolong[kMaxLevels];     // level k+1 -> k
+  StageGrid prolong;                 // every level k+1 -> k, one launch
 };
 
 // Per-stage block counts of one system.
 struct SysBlocks {
   int zero, atoms, bin, shortr, anterp, lattice0, lattice, lattice_all, top, energy;
   int restrict_[kMaxLevels];
-  int prolong[kMaxLevels];
+  int prolong;                       // tiles of every level below the top
 };
 SysBlocks system_blocks(const Geom& g, const LatLaunch& lat, int n_partials);
 

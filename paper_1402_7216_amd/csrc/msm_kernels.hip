@@ -6,7 +6,7 @@
 //   anterpolate                                                   q^0
 //   lattice, level 0                   (side stream)              u^{0,cut}
 //   restrict (k = 0..l-2) -> lattice, levels 1..l-2 -> top (FP64) q^k, u^{k,cut}
-//   prolong (k = l-2..0)                                          u^k
+//   prolong (every level, one launch)                             u^k
 //   interpolate_assemble -> reduce                                phi, F, E, virial
 //
 // Every per-atom and per-node value is a gather in a fixed order, so results
@@ -1179,112 +1179,198 @@ __global__ void __launch_bounds__(kLatThreads) k_lattice_win(KArgs A, int part) 
 
 // u^{k,cut} at node `node` of level k (level-local index): the stored value,
 // or, where the level's lattice tiles were split into row groups, the sum of
-// the groups' float64 partials in group order (stored back into u^{k,cut} so
-// the grid is complete after its first consumer).
-__device__ __forceinline__ float ucut_at(const SysDesc& S, int k, int node) {
+// the groups' float64 partials in group order (with `store`, written back into
+// u^{k,cut} so the grid is complete after the prolongation).  The partials are
+// loaded together (indices clamped to the last group, extra loads unused).
+__device__ __forceinline__ float ucut_value(const SysDesc& S, int k, int node, bool store) {
   const Level& L = S.g.lv[k];
+  const int off = L.off;
   float* __restrict__ ucut = S.d.ucut;
-  if (S.lat.b == 0 || k >= S.lat.n || S.lat.t[k].groups == 1) return ucut[L.off + node];
-  const LatTile& T = S.lat.t[k];
-  const double* part = S.d.lat_part + T.part0 + node;
+  const int groups = (S.lat.b == 0 || k >= S.lat.n) ? 1 : S.lat.t[k].groups;
+  if (groups == 1) return ucut[off + node];
+  const size_t cnt = (size_t)L.count;
+  const double* __restrict__ part = S.d.lat_part + S.lat.t[k].part0 + node;
   double pv[kLatMaxGroups];
 #pragma unroll
-  for (int gi = 0; gi < kLatMaxGroups; ++gi) pv[gi] = (gi < T.groups) ? part[(size_t)gi * L.count] : 0.0;
+  for (int gi = 0; gi < kLatMaxGroups; ++gi) pv[gi] = part[(size_t)min(gi, groups - 1) * cnt];
   double v = 0.0;
 #pragma unroll
   for (int gi = 0; gi < kLatMaxGroups; ++gi)
-    if (gi < T.groups) v += pv[gi];
+    if (gi < groups) v += pv[gi];
   const float u = (float)ldexp(v, -k);
-  ucut[L.off + node] = u;
+  if (store) ucut[off + node] = u;
   return u;
 }
 
 // --------------------------------------------------------------------------
 // Prolongation (itemised algorithm):
 //   u^k_mu = u^{k,cut}_mu + sum_nu Phi(mu/2 - nu)^3 u^{k+1}_nu, |mu - 2 nu| <= order - 1.
-// pw[j + order - 1] = Phi(j/2).
-// --------------------------------------------------------------------------
-// One block = 8 x 8 x 4 fine nodes; the coarse nodes they read are staged in LDS.
 // Per dimension, an even fine index m reads only nu = m/2 (weight Phi(0) = 1);
 // an odd one reads the ORDER coarse nodes nu = (m - R)/2 + i.
+//
+// Every level in one launch.  The blocks own 8 x 8 x 4 node tiles of every
+// level below the top (level 0 first).  A block of level k rebuilds in LDS the
+// coarser potentials its tile reads: the top grid over a box of nodes, then
+// levels l-2 .. k+1 each over the box the next finer box reads, and finally
+// writes u^k (and the completed u^{k,cut}) of its tile.  A box (o, e) of
+// level j reads the level-(j+1) box (ceil((o - R)/2), (e - 1 + 2R)/2 + 2),
+// which never exceeds 2R + 3 nodes per side.  Every rebuilt value is computed
+// by the same operations as at its owner, so the results equal those of a
+// level-by-level pass while the blocks need no other block's output.
+// --------------------------------------------------------------------------
 constexpr int kPX = 8, kPY = 8, kPZ = 4;
 
+__host__ __device__ inline int prolong_tiles(const Level& F) {
+  return ((F.n[0] + kPX - 1) / kPX) * ((F.n[1] + kPY - 1) / kPY) * ((F.n[2] + kPZ - 1) / kPZ);
+}
+
+__device__ __forceinline__ int ceil_half(int v) { return v >= 0 ? (v + 1) / 2 : -((-v) / 2); }
+
+// sum_nu Phi(m/2 - nu)^3 u^{k+1}_nu for the absolute fine index m, from the
+// coarse box (co, ce) held in cs (x fastest).  Every dimension takes ORDER
+// taps: an odd m its ORDER weights from nu = (m - R)/2, an even m the weight
+// 1 at nu = m/2 among zeros from nu = (m - R + 1)/2 (zero taps leave the sums
+// unchanged; all of them lie inside the box).  Straight-line code, the same
+// for every lane.
 template <int ORDER>
-__global__ void __launch_bounds__(kBlock) k_prolong(KArgs A, int k) {
+__device__ __forceinline__ float prolong_sum(const float* cs, const int* co, const int* ce, const int* m) {
+  using D = Dyadic<ORDER>;
+  constexpr int R = D::R;
+  constexpr int E0 = (R - 1) / 2;                      // tap of nu = m/2 for even m
+  int b0[3];
+  float w[3][ORDER];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const bool odd = (m[d] & 1) != 0;
+    b0[d] = (odd ? (m[d] - R) / 2 : (m[d] - R + 1) / 2) - co[d];   // exact halves of even numbers
+#pragma unroll
+    for (int i = 0; i < ORDER; ++i) w[d][i] = odd ? D::wodd(i) : (i == E0 ? 1.f : 0.f);
+  }
+  const float* base = cs + (b0[2] * ce[1] + b0[1]) * ce[0] + b0[0];
+  float acc = 0.f;
+#pragma unroll
+  for (int c = 0; c < ORDER; ++c) {
+#pragma unroll
+    for (int b = 0; b < ORDER; ++b) {
+      const float* rowp = base + (c * ce[1] + b) * ce[0];
+      float racc = 0.f;
+#pragma unroll
+      for (int a = 0; a < ORDER; ++a) racc = fmaf(w[0][a], rowp[a], racc);
+      acc = fmaf(w[2][c] * w[1][b], racc, acc);
+    }
+  }
+  return acc;
+}
+
+// LDS of one block: a box of up to (2R + 3)^3 nodes for each level above the
+// block's own (dynamic shared memory, sized for the launch's deepest system).
+__host__ __device__ constexpr int prolong_box(int order) { return (2 * order + 1) * (2 * order + 1) * (2 * order + 1); }
+
+// Box of one level in LDS: origin (absolute), extents, the level's grid.
+struct PBox {
+  int o[3], e[3], lo[3], n[3], off;
+  float inv_e0, inv_e01;
+};
+
+template <int ORDER>
+__global__ void __launch_bounds__(kBlock) k_prolong(KArgs A) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
   const Geom& g = S.g;
   float* __restrict__ u = S.d.u;
-  using D = Dyadic<ORDER>;
-  constexpr int R = D::R;
-  constexpr int VX = (kPX - 1 + 2 * R) / 2 + 2, VY = (kPY - 1 + 2 * R) / 2 + 2, VZ = (kPZ - 1 + 2 * R) / 2 + 2;
-  __shared__ float cs[VX * VY * VZ];
-  const Level F = g.lv[k], C = g.lv[k + 1];
+  constexpr int R = Dyadic<ORDER>::R;
+  constexpr int BOX = prolong_box(ORDER);              // (2R + 3)^3
+  extern __shared__ float pbox[];                      // box of level j at pbox + (j - k - 1) * BOX
+  __shared__ PBox pb[kMaxLevels];
+  const int top = g.levels - 1;
+  // level and tile of this block
+  int k = 0, t = blk;
+  while (k + 1 < top && t >= prolong_tiles(g.lv[k])) {
+    t -= prolong_tiles(g.lv[k]);
+    ++k;
+  }
+  const Level F = g.lv[k];
   const int ntx = (F.n[0] + kPX - 1) / kPX, nty = (F.n[1] + kPY - 1) / kPY;
-  const int bx = blk % ntx, by = (blk / ntx) % nty, bz = blk / (ntx * nty);
-  // absolute fine origin of the tile; coarse origin = ceil((m0 - R) / 2)
-  const int m0[3] = {F.lo[0] + bx * kPX, F.lo[1] + by * kPY, F.lo[2] + bz * kPZ};
-  int v0[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const int lo = m0[d] - R;
-    v0[d] = (lo >= 0) ? (lo + 1) / 2 : -((-lo) / 2);
-  }
-  const float* uc = u + C.off;
+  const int bx = t % ntx, by = (t / ntx) % nty, bz = t / (ntx * nty);
+  const int to[3] = {F.lo[0] + bx * kPX, F.lo[1] + by * kPY, F.lo[2] + bz * kPZ};   // absolute
   const int tx = threadIdx.x % kPX, ty = (threadIdx.x / kPX) % kPY, tz = threadIdx.x / (kPX * kPY);
-  const int fx = bx * kPX + tx, fy = by * kPY + ty, fz = bz * kPZ + tz;      // level-local
-  const bool inside = tz < kPZ && fx < F.n[0] && fy < F.n[1] && fz < F.n[2];
+  const int fx = bx * kPX + tx, fy = by * kPY + ty, fz = bz * kPZ + tz;          // level-local
+  const bool inside = fx < F.n[0] && fy < F.n[1] && fz < F.n[2];
   const int node = (fz * F.n[1] + fy) * F.n[0] + fx;
-  const size_t o = F.off + (size_t)node;
-  const float own = inside ? ucut_at(S, k, node) : 0.f;                    // in flight with the staging
-  constexpr int ncs = VX * VY * VZ;
-  float v[(ncs + kBlock - 1) / kBlock];
+  const float own = inside ? ucut_value(S, k, node, true) : 0.f;
+  if (threadIdx.x == 0) {
+    int o[3] = {to[0], to[1], to[2]}, e[3] = {kPX, kPY, kPZ};
+    for (int j = k + 1; j <= top; ++j) {
+      PBox& b = pb[j - k - 1];
+      const Level J = g.lv[j];
 #pragma unroll
-  for (int t = 0; t < (ncs + kBlock - 1) / kBlock; ++t) {
-    const int i = threadIdx.x + t * kBlock;
-    v[t] = 0.f;
-    if (i < ncs) {
-      const int lx = i % VX, ly = (i / VX) % VY, lz = i / (VX * VY);
-      const int cx = v0[0] + lx - C.lo[0], cy = v0[1] + ly - C.lo[1], cz = v0[2] + lz - C.lo[2];
-      if (cx >= 0 && cx < C.n[0] && cy >= 0 && cy < C.n[1] && cz >= 0 && cz < C.n[2])
-        v[t] = uc[((size_t)cz * C.n[1] + cy) * C.n[0] + cx];
+      for (int d = 0; d < 3; ++d) {
+        o[d] = ceil_half(o[d] - R);
+        e[d] = (e[d] - 1 + 2 * R) / 2 + 2;
+        b.o[d] = o[d];
+        b.e[d] = e[d];
+        b.lo[d] = J.lo[d];
+        b.n[d] = J.n[d];
+      }
+      b.off = J.off;
+      b.inv_e0 = 1.f / (float)e[0];
+      b.inv_e01 = 1.f / (float)(e[0] * e[1]);
     }
-  }
-#pragma unroll
-  for (int t = 0; t < (ncs + kBlock - 1) / kBlock; ++t) {
-    const int i = threadIdx.x + t * kBlock;
-    if (i < ncs) cs[i] = v[t];
   }
   __syncthreads();
-  if (!inside) return;
-  const int m[3] = {m0[0] + tx, m0[1] + ty, m0[2] + tz};
-  // per dimension: first local coarse index, and odd/even
-  int b0[3];
-  bool odd[3];
+  // one round of loads fills every box: u^{l-1} for the top box, u^{j,cut}
+  // for the others, zero outside the grids
+  const int total = (top - k) * BOX;
+  for (int i0 = 0; i0 < total; i0 += 4 * kBlock) {
+    float v[4];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    odd[d] = (m[d] & 1) != 0;
-    const int first = odd[d] ? (m[d] - R) / 2 : (m[d] >= 0 ? m[d] / 2 : -((-m[d]) / 2));
-    b0[d] = first - v0[d];
-  }
-  float wx[ORDER], wy[ORDER], wz[ORDER];
+    for (int w = 0; w < 4; ++w) {
+      const int i = i0 + w * kBlock + threadIdx.x;
+      v[w] = 0.f;
+      if (i < total) {
+        const int jj = i / BOX, li = i - jj * BOX;     // box jj holds level k + 1 + jj
+        const PBox& b = pb[jj];
+        if (li < b.e[0] * b.e[1] * b.e[2]) {
+          int lx, ly;
+          const int lz = fdiv(li, b.e[0] * b.e[1], b.inv_e01, ly);
+          ly = fdiv(ly, b.e[0], b.inv_e0, lx);
+          const int vx = b.o[0] + lx - b.lo[0], vy = b.o[1] + ly - b.lo[1], vz = b.o[2] + lz - b.lo[2];
+          if (vx >= 0 && vx < b.n[0] && vy >= 0 && vy < b.n[1] && vz >= 0 && vz < b.n[2]) {
+            const int jn = (vz * b.n[1] + vy) * b.n[0] + vx;
+            const int j = k + 1 + jj;
+            v[w] = (j == top) ? u[b.off + jn] : ucut_value(S, j, jn, false);
+          }
+        }
+      }
+    }
 #pragma unroll
-  for (int i = 0; i < ORDER; ++i) {
-    wx[i] = odd[0] ? D::wodd(i) : (i == 0 ? 1.f : 0.f);
-    wy[i] = odd[1] ? D::wodd(i) : (i == 0 ? 1.f : 0.f);
-    wz[i] = odd[2] ? D::wodd(i) : (i == 0 ? 1.f : 0.f);
-  }
-  const int nx_ = odd[0] ? ORDER : 1, ny_ = odd[1] ? ORDER : 1, nz_ = odd[2] ? ORDER : 1;
-  float acc = 0.f;
-  for (int c = 0; c < nz_; ++c) {
-    for (int b = 0; b < ny_; ++b) {
-      const float* rowp = cs + ((b0[2] + c) * VY + (b0[1] + b)) * VX + b0[0];
-      float racc = 0.f;
-      for (int a = 0; a < nx_; ++a) racc = fmaf(wx[a], rowp[a], racc);
-      acc = fmaf(wz[c] * wy[b], racc, acc);
+    for (int w = 0; w < 4; ++w) {
+      const int i = i0 + w * kBlock + threadIdx.x;
+      if (i < total) pbox[i] = v[w];
     }
   }
-  u[o] = own + acc;
+  __syncthreads();
+  // levels top-1 .. k+1 in place: u^j = u^{j,cut} + prolongation of u^{j+1}
+  for (int j = top - 1; j > k; --j) {
+    const PBox& b = pb[j - k - 1];
+    const PBox& c = pb[j - k];
+    float* __restrict__ fine = pbox + (j - k - 1) * BOX;
+    const float* coarse = fine + BOX;
+    const int nb = b.e[0] * b.e[1] * b.e[2];
+    for (int i = threadIdx.x; i < nb; i += kBlock) {
+      int lx, ly;
+      const int lz = fdiv(i, b.e[0] * b.e[1], b.inv_e01, ly);
+      ly = fdiv(ly, b.e[0], b.inv_e0, lx);
+      const int m[3] = {b.o[0] + lx, b.o[1] + ly, b.o[2] + lz};
+      const int vx = m[0] - b.lo[0], vy = m[1] - b.lo[1], vz = m[2] - b.lo[2];
+      if (vx >= 0 && vx < b.n[0] && vy >= 0 && vy < b.n[1] && vz >= 0 && vz < b.n[2])
+        fine[i] = fine[i] + prolong_sum<ORDER>(coarse, c.o, c.e, m);
+    }
+    __syncthreads();
+  }
+  if (!inside) return;
+  const int m[3] = {to[0] + tx, to[1] + ty, to[2] + tz};
+  u[F.off + (size_t)node] = own + prolong_sum<ORDER>(pbox, pb[0].o, pb[0].e, m);
 }
 
 // --------------------------------------------------------------------------
@@ -1437,7 +1523,7 @@ __global__ void __launch_bounds__(kBlock) k_energy_terms(KArgs A) {
   for (int k = 0; k < g.levels; ++k) {
     const Level& L = g.lv[k];
     for (int m = blk * blockDim.x + threadIdx.x; m < L.count; m += stride)
-      e += 0.5 * (double)qgrid[L.off + m] * (double)ucut_at(S, k, m);
+      e += 0.5 * (double)qgrid[L.off + m] * (double)ucut_value(S, k, m, true);
   }
   e *= g.ke;
 #pragma unroll
@@ -1510,8 +1596,7 @@ SysBlocks system_blocks(const Geom& g, const LatLaunch& lat, int n_partials) {
   for (int k = 0; k + 1 < g.levels; ++k) {
     const Level& C = g.lv[k + 1];
     b.restrict_[k] = ((C.n[0] + kRX - 1) / kRX) * ((C.n[1] + kRY - 1) / kRY) * ((C.n[2] + kRZ - 1) / kRZ);
-    const Level& F = g.lv[k];
-    b.prolong[k] = ((F.n[0] + kPX - 1) / kPX) * ((F.n[1] + kPY - 1) / kPY) * ((F.n[2] + kPZ - 1) / kPZ);
+    b.prolong += prolong_tiles(g.lv[k]);
   }
   // lattice cutoff in two launches: level 0, and levels 1 .. l-2
   if (g.levels > 1) {
@@ -1681,14 +1766,16 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
   }
 
   mark(kStageProlong);
-  for (int k = L.max_levels - 2; k >= 0; --k) {
-    if (k == 0 && lat0_side) join(cc->lattice0);     // u^0 adds the level-0 cutoff potential
-    const StageGrid& sg = L.prolong[k];
-    if (sg.blocks == 0) continue;
-    if (L.order == 4)
-      k_prolong<4><<<sg.blocks, kBlock, 0, s>>>(args(sg), k);
-    else
-      k_prolong<6><<<sg.blocks, kBlock, 0, s>>>(args(sg), k);
+  if (lat0_side) join(cc->lattice0);                 // u^0 adds the level-0 cutoff potential
+  if (L.prolong.blocks > 0) {
+    const int lds = (L.max_levels - 1) * prolong_box(L.order) * (int)sizeof(float);
+    if (L.order == 4) {
+      (void)hipFuncSetAttribute((const void*)k_prolong<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+      k_prolong<4><<<L.prolong.blocks, kBlock, lds, s>>>(args(L.prolong));
+    } else {
+      (void)hipFuncSetAttribute((const void*)k_prolong<6>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+      k_prolong<6><<<L.prolong.blocks, kBlock, lds, s>>>(args(L.prolong));
+    }
   }
   mark(kStageInterp);
   if (short_side) join(cc->shortr);
