@@ -1181,7 +1181,7 @@ __global__ void __launch_bounds__(kLatThreads) k_lattice_win(KArgs A, int part) 
 // or, where the level's lattice tiles were split into row groups, the sum of
 // the groups' float64 partials in group order (with `store`, written back into
 // u^{k,cut} so the grid is complete after the prolongation).  The partials are
-// loaded together (indices clamped to the last group, extra loads unused).
+// loaded together.
 __device__ __forceinline__ float ucut_value(const SysDesc& S, int k, int node, bool store) {
   const Level& L = S.g.lv[k];
   const int off = L.off;
@@ -1192,7 +1192,7 @@ __device__ __forceinline__ float ucut_value(const SysDesc& S, int k, int node, b
   const double* __restrict__ part = S.d.lat_part + S.lat.t[k].part0 + node;
   double pv[kLatMaxGroups];
 #pragma unroll
-  for (int gi = 0; gi < kLatMaxGroups; ++gi) pv[gi] = part[(size_t)min(gi, groups - 1) * cnt];
+  for (int gi = 0; gi < kLatMaxGroups; ++gi) pv[gi] = (gi < groups) ? part[(size_t)gi * cnt] : 0.0;
   double v = 0.0;
 #pragma unroll
   for (int gi = 0; gi < kLatMaxGroups; ++gi)
@@ -1226,62 +1226,108 @@ __host__ __device__ inline int prolong_tiles(const Level& F) {
 
 __device__ __forceinline__ int ceil_half(int v) { return v >= 0 ? (v + 1) / 2 : -((-v) / 2); }
 
-// sum_nu Phi(m/2 - nu)^3 u^{k+1}_nu for the absolute fine index m, from the
-// coarse box (co, ce) held in cs (x fastest).  Every dimension takes ORDER
-// taps: an odd m its ORDER weights from nu = (m - R)/2, an even m the weight
-// 1 at nu = m/2 among zeros from nu = (m - R + 1)/2 (zero taps leave the sums
-// unchanged; all of them lie inside the box).  Straight-line code, the same
-// for every lane.
+// Prolongation weights along one dimension for the absolute fine index m:
+// first coarse node (local to a box starting at c0) and ORDER taps.  An odd m
+// takes its ORDER weights from nu = (m - R)/2; an even m the weight 1 at
+// nu = m/2 among zeros from nu = (m - R + 1)/2 (zero taps leave the sums
+// unchanged, and all of them lie inside the box).
 template <int ORDER>
-__device__ __forceinline__ float prolong_sum(const float* cs, const int* co, const int* ce, const int* m) {
+__device__ __forceinline__ int prolong_taps(int m, int c0, float* w) {
   using D = Dyadic<ORDER>;
   constexpr int R = D::R;
   constexpr int E0 = (R - 1) / 2;                      // tap of nu = m/2 for even m
-  int b0[3];
-  float w[3][ORDER];
+  const bool odd = (m & 1) != 0;
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const bool odd = (m[d] & 1) != 0;
-    b0[d] = (odd ? (m[d] - R) / 2 : (m[d] - R + 1) / 2) - co[d];   // exact halves of even numbers
+  for (int i = 0; i < ORDER; ++i) w[i] = odd ? D::wodd(i) : (i == E0 ? 1.f : 0.f);
+  return (odd ? (m - R) / 2 : (m - R + 1) / 2) - c0;   // exact halves of even numbers
+}
+
+// The prolongation of a coarse box (co, ce) in cs onto the fine box (fo, fe)
+// in two passes.  x pass: for every coarse (z, y) row and fine x, the row sum
+//   xs[zc][yc][xf] = sum_a wx_a cs[zc][yc][bx + a]          (a ascending)
+// into xs (ce[2] x ce[1] x fe[0], x fastest); then, per fine node,
+//   sum_{c, b} (wz_c wy_b) xs[bz + c][by + b][xf]            (c, then b ascending)
+// in prolong_yz.  The order of operations is that of the direct triple sum.
+template <int ORDER>
+__device__ __forceinline__ void prolong_x(const float* cs, const int* co, const int* ce, const int* fo,
+                                          const int* fe, float* xs) {
+  const int n = ce[2] * ce[1] * fe[0];
+  const float inv_x = 1.f / (float)fe[0];
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    int xf;
+    const int row = fdiv(i, fe[0], inv_x, xf);         // zc * ce[1] + yc
+    float w[ORDER];
+    const int bx = prolong_taps<ORDER>(fo[0] + xf, co[0], w);
+    const float* rowp = cs + row * ce[0] + bx;
+    float r[ORDER];
 #pragma unroll
-    for (int i = 0; i < ORDER; ++i) w[d][i] = odd ? D::wodd(i) : (i == E0 ? 1.f : 0.f);
+    for (int a = 0; a < ORDER; ++a) r[a] = rowp[a];
+    float racc = 0.f;
+#pragma unroll
+    for (int a = 0; a < ORDER; ++a) racc = fmaf(w[a], r[a], racc);
+    xs[i] = racc;
   }
-  const float* base = cs + (b0[2] * ce[1] + b0[1]) * ce[0] + b0[0];
+}
+
+template <int ORDER>
+__device__ __forceinline__ float prolong_yz(const float* xs, const int* co, const int* ce, const int* fe,
+                                            const int* m, int xf) {
+  float wy[ORDER], wz[ORDER];
+  const int by = prolong_taps<ORDER>(m[1], co[1], wy);
+  const int bz = prolong_taps<ORDER>(m[2], co[2], wz);
+  const float* base = xs + (bz * ce[1] + by) * fe[0] + xf;
+  float r[ORDER][ORDER];                               // every read in flight before the sums
+#pragma unroll
+  for (int c = 0; c < ORDER; ++c)
+#pragma unroll
+    for (int b = 0; b < ORDER; ++b) r[c][b] = base[(c * ce[1] + b) * fe[0]];
   float acc = 0.f;
 #pragma unroll
-  for (int c = 0; c < ORDER; ++c) {
+  for (int c = 0; c < ORDER; ++c)
 #pragma unroll
-    for (int b = 0; b < ORDER; ++b) {
-      const float* rowp = base + (c * ce[1] + b) * ce[0];
-      float racc = 0.f;
-#pragma unroll
-      for (int a = 0; a < ORDER; ++a) racc = fmaf(w[0][a], rowp[a], racc);
-      acc = fmaf(w[2][c] * w[1][b], racc, acc);
-    }
-  }
+    for (int b = 0; b < ORDER; ++b) acc = fmaf(wz[c] * wy[b], r[c][b], acc);
   return acc;
 }
 
-// LDS of one block: a box of up to (2R + 3)^3 nodes for each level above the
-// block's own (dynamic shared memory, sized for the launch's deepest system).
-__host__ __device__ constexpr int prolong_box(int order) { return (2 * order + 1) * (2 * order + 1) * (2 * order + 1); }
+// Box of level j read (through levels k+1 .. j-1) by the tile (to, (kPX, kPY, kPZ))
+// of level k: origin (absolute) and extents.  Uniform arithmetic.
+template <int R>
+__device__ __forceinline__ void box_of(int k, int j, const int* to, int* o, int* e) {
+  o[0] = to[0];
+  o[1] = to[1];
+  o[2] = to[2];
+  e[0] = kPX;
+  e[1] = kPY;
+  e[2] = kPZ;
+  for (int i = k; i < j; ++i) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      o[d] = ceil_half(o[d] - R);
+      e[d] = (e[d] - 1 + 2 * R) / 2 + 2;
+    }
+  }
+}
 
-// Box of one level in LDS: origin (absolute), extents, the level's grid.
-struct PBox {
-  int o[3], e[3], lo[3], n[3], off;
-  float inv_e0, inv_e01;
-};
+// LDS of one block: a box of up to (2R + 3)^3 nodes, padded to a whole number
+// of block-wide rounds, for each level above the block's own, and one more for
+// the x-pass sums (dynamic shared memory, sized for the launch's deepest system).
+__host__ __device__ constexpr int prolong_box(int order) {
+  return ((2 * order + 1) * (2 * order + 1) * (2 * order + 1) + kBlock - 1) / kBlock * kBlock;
+}
 
+// Few waves per SIMD (one launch of a few hundred blocks): registers are spent
+// on loads in flight instead of occupancy.
 template <int ORDER>
-__global__ void __launch_bounds__(kBlock) k_prolong(KArgs A) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 2))) k_prolong(KArgs A) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
   const Geom& g = S.g;
   float* __restrict__ u = S.d.u;
   constexpr int R = Dyadic<ORDER>::R;
-  constexpr int BOX = prolong_box(ORDER);              // (2R + 3)^3
+  constexpr int BOX = prolong_box(ORDER);              // (2R + 3)^3 rounded up to kBlock
+  constexpr int SL = BOX / kBlock;                     // nodes per thread and box
+  constexpr int LV = SL >= 9 ? 1 : 9 / SL;             // boxes per round of loads
   extern __shared__ float pbox[];                      // box of level j at pbox + (j - k - 1) * BOX
-  __shared__ PBox pb[kMaxLevels];
   const int top = g.levels - 1;
   // level and tile of this block
   int k = 0, t = blk;
@@ -1289,6 +1335,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong(KArgs A) {
     t -= prolong_tiles(g.lv[k]);
     ++k;
   }
+  float* __restrict__ xs = pbox + (top - k) * BOX;     // x-pass sums of the box being built
   const Level F = g.lv[k];
   const int ntx = (F.n[0] + kPX - 1) / kPX, nty = (F.n[1] + kPY - 1) / kPY;
   const int bx = t % ntx, by = (t / ntx) % nty, bz = t / (ntx * nty);
@@ -1297,80 +1344,107 @@ __global__ void __launch_bounds__(kBlock) k_prolong(KArgs A) {
   const int fx = bx * kPX + tx, fy = by * kPY + ty, fz = bz * kPZ + tz;          // level-local
   const bool inside = fx < F.n[0] && fy < F.n[1] && fz < F.n[2];
   const int node = (fz * F.n[1] + fy) * F.n[0] + fx;
-  const float own = inside ? ucut_value(S, k, node, true) : 0.f;
-  if (threadIdx.x == 0) {
-    int o[3] = {to[0], to[1], to[2]}, e[3] = {kPX, kPY, kPZ};
-    for (int j = k + 1; j <= top; ++j) {
-      PBox& b = pb[j - k - 1];
+  const float own = inside ? ucut_value(S, k, node, false) : 0.f;   // stored with u^k at the end
+  // Fill the boxes, LV of them per round of loads: u^{l-1} for the top box,
+  // u^{j,cut} for the others (the sum of the partials in group order where
+  // grouped), zero outside the grids.  Every load of a round is issued before
+  // the first sum; the per-level choices are uniform branches.
+  const int nlev = top - k;
+  for (int j0 = 0; j0 < nlev; j0 += LV) {
+    float fv[LV][SL];
+    double pv[LV][SL][kLatMaxGroups];
+    bool ok[LV][SL];
+    int ng[LV];
+#pragma unroll
+    for (int lv = 0; lv < LV; ++lv) {
+      ng[lv] = 0;
+      if (j0 + lv >= nlev) continue;
+      const int j = k + 1 + j0 + lv;
+      int o[3], e[3];
+      box_of<R>(k, j, to, o, e);
       const Level J = g.lv[j];
+      const int groups = (j == top || S.lat.b == 0 || j >= S.lat.n) ? 1 : S.lat.t[j].groups;
+      ng[lv] = groups;
+      const float inv_e0 = 1.f / (float)e[0], inv_e01 = 1.f / (float)(e[0] * e[1]);
+      int jn[SL];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        o[d] = ceil_half(o[d] - R);
-        e[d] = (e[d] - 1 + 2 * R) / 2 + 2;
-        b.o[d] = o[d];
-        b.e[d] = e[d];
-        b.lo[d] = J.lo[d];
-        b.n[d] = J.n[d];
+      for (int sl = 0; sl < SL; ++sl) {
+        const int li = sl * kBlock + threadIdx.x;
+        int lx, ly;
+        const int lz = fdiv(li, e[0] * e[1], inv_e01, ly);
+        ly = fdiv(ly, e[0], inv_e0, lx);
+        const int vx = o[0] + lx - J.lo[0], vy = o[1] + ly - J.lo[1], vz = o[2] + lz - J.lo[2];
+        ok[lv][sl] = lz < e[2] && vx >= 0 && vx < J.n[0] && vy >= 0 && vy < J.n[1] && vz >= 0 && vz < J.n[2];
+        jn[sl] = J.off + (ok[lv][sl] ? (vz * J.n[1] + vy) * J.n[0] + vx : 0);
       }
-      b.off = J.off;
-      b.inv_e0 = 1.f / (float)e[0];
-      b.inv_e01 = 1.f / (float)(e[0] * e[1]);
-    }
-  }
-  __syncthreads();
-  // one round of loads fills every box: u^{l-1} for the top box, u^{j,cut}
-  // for the others, zero outside the grids
-  const int total = (top - k) * BOX;
-  for (int i0 = 0; i0 < total; i0 += 4 * kBlock) {
-    float v[4];
+      if (groups == 1) {
+        const float* __restrict__ src = (j == top) ? u : S.d.ucut;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      const int i = i0 + w * kBlock + threadIdx.x;
-      v[w] = 0.f;
-      if (i < total) {
-        const int jj = i / BOX, li = i - jj * BOX;     // box jj holds level k + 1 + jj
-        const PBox& b = pb[jj];
-        if (li < b.e[0] * b.e[1] * b.e[2]) {
-          int lx, ly;
-          const int lz = fdiv(li, b.e[0] * b.e[1], b.inv_e01, ly);
-          ly = fdiv(ly, b.e[0], b.inv_e0, lx);
-          const int vx = b.o[0] + lx - b.lo[0], vy = b.o[1] + ly - b.lo[1], vz = b.o[2] + lz - b.lo[2];
-          if (vx >= 0 && vx < b.n[0] && vy >= 0 && vy < b.n[1] && vz >= 0 && vz < b.n[2]) {
-            const int jn = (vz * b.n[1] + vy) * b.n[0] + vx;
-            const int j = k + 1 + jj;
-            v[w] = (j == top) ? u[b.off + jn] : ucut_value(S, j, jn, false);
-          }
+        for (int sl = 0; sl < SL; ++sl) fv[lv][sl] = src[jn[sl]];
+      } else {
+        const double* __restrict__ part = S.d.lat_part + S.lat.t[j].part0 - J.off;
+        const size_t cnt = (size_t)J.count;
+#pragma unroll
+        for (int gi = 0; gi < kLatMaxGroups; ++gi)
+          if (gi < groups)
+#pragma unroll
+            for (int sl = 0; sl < SL; ++sl) pv[lv][sl][gi] = part[gi * cnt + jn[sl]];
+      }
+    }
+#pragma unroll
+    for (int lv = 0; lv < LV; ++lv) {
+      if (j0 + lv >= nlev) continue;
+      const int j = k + 1 + j0 + lv;
+#pragma unroll
+      for (int sl = 0; sl < SL; ++sl) {
+        float v;
+        if (ng[lv] == 1) {
+          v = fv[lv][sl];
+        } else {
+          double d = 0.0;
+#pragma unroll
+          for (int gi = 0; gi < kLatMaxGroups; ++gi)
+            if (gi < ng[lv]) d += pv[lv][sl][gi];
+          v = (float)ldexp(d, -j);
         }
+        pbox[(j0 + lv) * BOX + sl * kBlock + threadIdx.x] = ok[lv][sl] ? v : 0.f;
       }
-    }
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      const int i = i0 + w * kBlock + threadIdx.x;
-      if (i < total) pbox[i] = v[w];
     }
   }
   __syncthreads();
   // levels top-1 .. k+1 in place: u^j = u^{j,cut} + prolongation of u^{j+1}
   for (int j = top - 1; j > k; --j) {
-    const PBox& b = pb[j - k - 1];
-    const PBox& c = pb[j - k];
+    const Level J = g.lv[j];
+    int jo[3], je[3], co[3], ce[3];
+    box_of<R>(k, j, to, jo, je);
+    box_of<R>(k, j + 1, to, co, ce);
     float* __restrict__ fine = pbox + (j - k - 1) * BOX;
-    const float* coarse = fine + BOX;
-    const int nb = b.e[0] * b.e[1] * b.e[2];
+    prolong_x<ORDER>(fine + BOX, co, ce, jo, je, xs);
+    __syncthreads();
+    const int nb = je[0] * je[1] * je[2];
+    const float inv_e0 = 1.f / (float)je[0], inv_e01 = 1.f / (float)(je[0] * je[1]);
     for (int i = threadIdx.x; i < nb; i += kBlock) {
       int lx, ly;
-      const int lz = fdiv(i, b.e[0] * b.e[1], b.inv_e01, ly);
-      ly = fdiv(ly, b.e[0], b.inv_e0, lx);
-      const int m[3] = {b.o[0] + lx, b.o[1] + ly, b.o[2] + lz};
-      const int vx = m[0] - b.lo[0], vy = m[1] - b.lo[1], vz = m[2] - b.lo[2];
-      if (vx >= 0 && vx < b.n[0] && vy >= 0 && vy < b.n[1] && vz >= 0 && vz < b.n[2])
-        fine[i] = fine[i] + prolong_sum<ORDER>(coarse, c.o, c.e, m);
+      const int lz = fdiv(i, je[0] * je[1], inv_e01, ly);
+      ly = fdiv(ly, je[0], inv_e0, lx);
+      const int m[3] = {jo[0] + lx, jo[1] + ly, jo[2] + lz};
+      const int vx = m[0] - J.lo[0], vy = m[1] - J.lo[1], vz = m[2] - J.lo[2];
+      if (vx >= 0 && vx < J.n[0] && vy >= 0 && vy < J.n[1] && vz >= 0 && vz < J.n[2])
+        fine[i] = fine[i] + prolong_yz<ORDER>(xs, co, ce, je, m, lx);
     }
     __syncthreads();
   }
-  if (!inside) return;
-  const int m[3] = {to[0] + tx, to[1] + ty, to[2] + tz};
-  u[F.off + (size_t)node] = own + prolong_sum<ORDER>(pbox, pb[0].o, pb[0].e, m);
+  {
+    int co[3], ce[3];
+    const int te[3] = {kPX, kPY, kPZ};
+    box_of<R>(k, k + 1, to, co, ce);
+    prolong_x<ORDER>(pbox, co, ce, to, te, xs);
+    __syncthreads();
+    if (!inside) return;
+    const int m[3] = {to[0] + tx, to[1] + ty, to[2] + tz};
+    u[F.off + (size_t)node] = own + prolong_yz<ORDER>(xs, co, ce, te, m, tx);
+  }
+  if (!(S.lat.b == 0 || k >= S.lat.n) && S.lat.t[k].groups > 1) S.d.ucut[F.off + (size_t)node] = own;
 }
 
 // --------------------------------------------------------------------------
@@ -1768,7 +1842,7 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
   mark(kStageProlong);
   if (lat0_side) join(cc->lattice0);                 // u^0 adds the level-0 cutoff potential
   if (L.prolong.blocks > 0) {
-    const int lds = (L.max_levels - 1) * prolong_box(L.order) * (int)sizeof(float);
+    const int lds = L.max_levels * prolong_box(L.order) * (int)sizeof(float);   // boxes + x-pass sums
     if (L.order == 4) {
       (void)hipFuncSetAttribute((const void*)k_prolong<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
       k_prolong<4><<<L.prolong.blocks, kBlock, lds, s>>>(args(L.prolong));
