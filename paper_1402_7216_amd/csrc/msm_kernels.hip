@@ -526,18 +526,27 @@ __global__ void __launch_bounds__(kShortThreads) k_short(KArgs A) {
   const int* __restrict__ start = S.d.cell_start;
   float4* __restrict__ fshort = S.d.fshort;
   __shared__ float4 red[kShortWaves][kWave];
-  __shared__ float4 jbuf[kShortWaves][kShortSeg];
+  // staged j atoms of each wave, then 4 far-away uncharged entries: a lane
+  // reads 4 entries from min(window start + t0, kShortSeg), and every entry past
+  // its window fails the cutoff test (same-row atoms beyond the window lie
+  // farther than a)
+  __shared__ float4 jbuf[kShortWaves][kShortSeg + 4];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int n_items = g.row_items * g.nc[1] * g.nc[2];
   const float a2 = g.a2, aw = g.a_win;
+  const unsigned a2m1 = __float_as_uint(a2) - 1u;
+  // the polynomial coefficients live in vector registers (an FMA may take
+  // only one scalar operand, so scalar copies would cost a move per use)
   float gc[M + 1], dc[M + 1];
 #pragma unroll
   for (int k = 0; k <= M; ++k) {
-    gc[k] = g.gr[k];
-    dc[k] = g.dr[k];
+    asm volatile("v_mov_b32 %0, %1" : "=v"(gc[k]) : "s"(g.gr[k]));
+    asm volatile("v_mov_b32 %0, %1" : "=v"(dc[k]) : "s"(g.dr[k]));
   }
   float4* jb = jbuf[wave];
+  const float4 far = make_float4(3e30f, 3e30f, 3e30f, 0.f);
+  if (lane < 4) jb[kShortSeg + lane] = far;
   const int R = g.reach, side = 2 * R + 1, centre = (side * side) / 2;
   // the launch has g.short_blocks blocks; work items are strided over them
   for (int item = blk; item < n_items; item += g.short_blocks) {
@@ -576,7 +585,7 @@ __global__ void __launch_bounds__(kShortThreads) k_short(KArgs A) {
 #pragma unroll
           for (int v = 0; v < kShortSeg / kWave; ++v) {
             const int j = s0 + v * kWave + lane;
-            jb[v * kWave + lane] = (j < u1) ? sorted[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+            jb[v * kWave + lane] = (j < u1) ? sorted[j] : far;
           }
           // this lane's part of the staged segment: [a0, a0 + n) (n = 0 keeps a0 = 0)
           const int lo_s = max(lo, s0) - s0, hi_s = min(hi, s0 + kShortSeg) - s0;
@@ -595,15 +604,17 @@ __global__ void __launch_bounds__(kShortThreads) k_short(KArgs A) {
             coincident |= zeros > ((i >= s0 + a0 && i < s0 + b0) ? 1 : 0);
           }
           for (int t0 = 0; t0 < nmax; t0 += 4) {
+            const float4* jp = jb + min(a0 + t0, kShortSeg);
             float4 pj[4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) pj[v] = jb[min(a0 + t0 + v, kShortSeg - 1)];
+            for (int v = 0; v < 4; ++v) pj[v] = jp[v];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               const float dx = pi.x - pj[v].x, dy = pi.y - pj[v].y, dz = pi.z - pj[v].z;
               const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
               // one predicate (non-short-circuit), so a single branch per pair
-              if ((t0 + v < n) & (r2 < a2) & (r2 > 0.f)) {
+              // 0 < r2 < a2 as one unsigned compare of the bit patterns (r2 >= +0)
+              if (__float_as_uint(r2) - 1u < a2m1) {
                 // hardware reciprocal square root plus one Newton step (the raw
                 // instruction's error is biased, which would bias the energy)
                 float ri = __builtin_amdgcn_rsqf(r2);
