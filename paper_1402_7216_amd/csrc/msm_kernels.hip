@@ -1010,17 +1010,26 @@ constexpr int kLatWaves = kLatThreads / kWave;
 template <int B, int XR, bool PAIR>
 __device__ __forceinline__ void row_win(float* acc, const float* a, const float* b,
                                         const float* wrow) {
-  float w[XR + 1];
-#pragma unroll
-  for (int t = 0; t <= XR; ++t) w[t] = wrow[t];
+  // taps in groups of 4: each group reads the 4 window values (and weights) it
+  // adds to the window, and the scheduler keeps the groups apart, so a lane
+  // holds about B + 8 values instead of the whole row (8 waves per SIMD fit)
+  constexpr int NT = 2 * XR + 1;
   float v[B + 2 * XR];
 #pragma unroll
-  for (int j = 0; j < B + 2 * XR; ++j) v[j] = PAIR ? a[j] + b[j] : a[j];
+  for (int j = 0; j < B - 1; ++j) v[j] = PAIR ? a[j] + b[j] : a[j];
 #pragma unroll
-  for (int t = 0; t < 2 * XR + 1; ++t) {
-    const float wt = w[t < XR ? XR - t : t - XR];
+  for (int t0 = 0; t0 < NT; t0 += 4) {
+    float w[4];
 #pragma unroll
-    for (int bb = 0; bb < B; ++bb) acc[bb] = fmaf(wt, v[bb + t], acc[bb]);
+    for (int t = t0; t < t0 + 4 && t < NT; ++t) {
+      v[t + B - 1] = PAIR ? a[t + B - 1] + b[t + B - 1] : a[t + B - 1];
+      w[t - t0] = wrow[t < XR ? XR - t : t - XR];
+    }
+#pragma unroll
+    for (int t = t0; t < t0 + 4 && t < NT; ++t)
+#pragma unroll
+      for (int bb = 0; bb < B; ++bb) acc[bb] = fmaf(w[t - t0], v[bb + t], acc[bb]);
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -1051,7 +1060,7 @@ __device__ __forceinline__ void row_win_dispatch(int xr, float* acc, const float
 // part 0: the tiles of level 0; part 1: the tiles of levels 1 .. l-2 and the
 // top level; part 2: every tile and the top level.
 template <int B>
-__global__ void __launch_bounds__(kLatThreads) k_lattice_win(KArgs A, int part) {
+__global__ void __launch_bounds__(kLatThreads, B <= 6 ? 8 : 4) k_lattice_win(KArgs A, int part) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
   const Geom& g = S.g;
