@@ -188,7 +188,12 @@ typedef struct msm_tuning {
   int32_t short_after;   /* with a side stream, the short-range pass starts after
                             1: binning, 2: anterpolation, 3: the coarse lattice
                             cutoff (it then overlaps the prolongations) */
-  int32_t reserved[3];   /* must be zero */
+  int32_t short_split;   /* with a side stream: per mille (1 .. 1000) of the
+                            short-range work items that start at short_after; the
+                            others start after the lattice cutoff (so they
+                            overlap the prolongation rather than the lattice
+                            cutoff); 1000: all of them */
+  int32_t reserved[2];   /* must be zero */
 } msm_tuning;
 
 /* Apply tuning knobs to a plan and re-upload its descriptor to ws (other

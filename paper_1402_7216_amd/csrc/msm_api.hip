@@ -301,6 +301,7 @@ void refresh_launch(msm_plan* P) {
   lg.max_levels = g.levels;
   lg.streams = P->streams;
   lg.short_after = P->short_after;
+  lg.short_split = P->short_split;
   lg.zero.blocks = sb.zero;
   lg.atoms.blocks = sb.atoms;
   lg.bin.blocks = sb.bin;
@@ -385,6 +386,7 @@ void retune(msm_plan* P, const msm_tuning& t) {
   if (t.short_blocks != 0) P->short_cap = t.short_blocks < 0 ? 0 : t.short_blocks;
   if (t.streams != 0) P->streams = t.streams;
   if (t.short_after != 0) P->short_after = t.short_after;
+  if (t.short_split != 0) P->short_split = t.short_split;
   set_short_blocks(g, P->short_cap);
   refresh_launch(P);
 }
@@ -397,6 +399,8 @@ msm_status check_tuning(const msm_tuning* t) {
   if (t->short_blocks < -1) return fail(MSM_ERR_INVALID_ARG, "short_blocks must be >= -1");
   if (t->streams < 0 || t->streams > 3) return fail(MSM_ERR_INVALID_ARG, "streams must be 0 .. 3");
   if (t->short_after < 0 || t->short_after > 3) return fail(MSM_ERR_INVALID_ARG, "short_after must be 0 .. 3");
+  if (t->short_split < 0 || t->short_split > 1000)
+    return fail(MSM_ERR_INVALID_ARG, "short_split must be 0 .. 1000");
   for (int32_t r : t->reserved)
     if (r != 0) return fail(MSM_ERR_INVALID_ARG, "reserved tuning fields must be zero");
   return MSM_OK;
@@ -761,7 +765,8 @@ msm_status msm_plan_describe(const msm_plan* P, char* buf, size_t buf_bytes) {
        std::to_string(g.nc[2]) + "], \"reach\": " + std::to_string(g.reach) +
        ", \"bin_blocks\": " + std::to_string(g.bin_blocks) +
        ", \"item_chunks\": " + std::to_string(g.item_chunks) + ", \"short_blocks\": " + std::to_string(g.short_blocks) +
-       ", \"streams\": " + std::to_string(P->streams) + ", \"short_after\": " + std::to_string(P->short_after);
+       ", \"streams\": " + std::to_string(P->streams) + ", \"short_after\": " + std::to_string(P->short_after) +
+       ", \"short_split\": " + std::to_string(P->short_split);
   o += ", \"taps\": " + std::to_string(P->weights.size()) + ", \"halo\": " + std::to_string(P->lat.H);
   o += ", \"lattice_b\": " + std::to_string(P->lat.b) + ", \"lattice_lds\": " +
        std::to_string(P->lat.lds_bytes) + ", \"lattice_tiles\": [";

@@ -95,6 +95,7 @@ void rebuild_maps(msm_batch* Bt) {
   L.m = Bt->plans[0]->g.m;
   L.streams = Bt->plans[0]->streams;
   L.short_after = Bt->plans[0]->short_after;
+  L.short_split = Bt->plans[0]->short_split;
   L.lat_b = 0;
   L.bin4 = false;
   for (int st = 0; st < kNumStages; ++st) Bt->map[st].clear();
@@ -389,7 +390,7 @@ msm_status msm_batch_describe(const msm_batch* Bt, char* buf, size_t buf_bytes) 
 msm_status msm_plan_tuning(const msm_plan* P, msm_tuning* t) {
   if (!P || !t) return fail(MSM_ERR_INVALID_ARG, "null plan or tuning");
   *t = msm_tuning{P->lat.b, P->g.item_chunks, P->short_cap > 0 ? P->short_cap : -1, P->streams,
-                  P->short_after, {}};
+                  P->short_after, P->short_split, {}};
   return MSM_OK;
 }
 
@@ -431,8 +432,9 @@ msm_status msm_batch_tune(msm_batch* Bt, void* ws, size_t ws_bytes, msm_stream_t
 // Time candidates over `trials` evaluations of the given inputs with HIP
 // events on `stream`: lattice_b in {4, 6, 8} x item_chunks in {1, 2, 3} with
 // every stream on and one short-range block per work item, then the stream
-// layouts x short-range block counts for the best pair.  Apply the fastest and
-// describe the search in `report` (JSON, nullable).
+// layouts x short-range block counts for the best pair, then where the side
+// short range starts and how much of it waits for the lattice cutoff.  Apply
+// the fastest and describe the search in `report` (JSON, nullable).
 static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm_stream_t stream,
                            const float* x, const float* y, const float* z, const float* q,
                            int32_t trials, char* report, size_t report_bytes) {
@@ -445,8 +447,8 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
   msm_batch* Bt = batch ? static_cast<msm_batch*>(obj) : nullptr;
   msm_plan* P = batch ? nullptr : static_cast<msm_plan*>(obj);
   const bool tiled = batch ? Bt->lg.lat_b > 0 : P->lat.b > 0;
-  auto tune = [&](int b, int w, int c, int n, int sa) {
-    const msm_tuning t{b, w, c, n, sa, {}};
+  auto tune = [&](int b, int w, int c, int n, int sa, int sp) {
+    const msm_tuning t{b, w, c, n, sa, sp, {}};
     return batch ? msm_batch_tune(Bt, ws, ws_bytes, stream, &t) : msm_plan_tune(P, ws, ws_bytes, stream, &t);
   };
   auto eval = [&]() {
@@ -457,10 +459,10 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
   };
   std::string rep = "{\"candidates\": [";
   float best = 1e30f;
-  int best_b = 0, best_w = 0, best_c = 0, best_n = 0, best_sa = 1;
+  int best_b = 0, best_w = 0, best_c = 0, best_n = 0, best_sa = 1, best_sp = 1000;
   bool first = true;
-  auto time_one = [&](int b, int w, int c, int n, int sa, float& ms) {
-    msm_status st = tune(b, w, c, n, sa);
+  auto time_one = [&](int b, int w, int c, int n, int sa, int sp, float& ms) {
+    msm_status st = tune(b, w, c, n, sa, sp);
     // one warm-up evaluation, then `trials` timed ones
     for (int t = -1; t < trials && st == MSM_OK; ++t) {
       if (t == 0) (void)hipEventRecord(e0, s);
@@ -474,8 +476,8 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
     ms /= trials;
     rep += std::string(first ? "" : ", ") + "{\"lattice_b\": " + std::to_string(b) + ", \"item_chunks\": " +
            std::to_string(w) + ", \"short_blocks\": " + std::to_string(c) + ", \"streams\": " +
-           std::to_string(n) + ", \"short_after\": " + std::to_string(sa) + ", \"ms\": " + std::to_string(ms) +
-           "}";
+           std::to_string(n) + ", \"short_after\": " + std::to_string(sa) + ", \"short_split\": " +
+           std::to_string(sp) + ", \"ms\": " + std::to_string(ms) + "}";
     first = false;
     if (ms < best) {
       best = ms;
@@ -484,6 +486,7 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
       best_c = c;
       best_n = n;
       best_sa = sa;
+      best_sp = sp;
     }
     return MSM_OK;
   };
@@ -492,7 +495,7 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
   for (int b : bs)
     for (int w : {1, 2, 3}) {
       float ms = 0.f;
-      if (st == MSM_OK) st = time_one(b, w, -1, 3, 1, ms);
+      if (st == MSM_OK) st = time_one(b, w, -1, 3, 1, 1000, ms);
     }
   // stream layouts x short-range block counts for the best (B, chunks); the
   // counts are fractions of the compute units, so the short-range pass leaves
@@ -509,7 +512,7 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
     for (int c : {-1, 3 * n_cu / 2, n_cu, 3 * n_cu / 4, n_cu / 2})
       if (st == MSM_OK && !(n == 3 && c == -1)) {
         float ms = 0.f;
-        st = time_one(bb, bw, c, n, 1, ms);
+        st = time_one(bb, bw, c, n, 1, 1000, ms);
       }
   // where the side-stream short range starts, for the best layout so far
   const int bc = best_c, bn = best_n;
@@ -517,17 +520,25 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
     for (int sa : {2, 3})
       if (st == MSM_OK) {
         float ms = 0.f;
-        st = time_one(bb, bw, bc, bn, sa, ms);
+        st = time_one(bb, bw, bc, bn, sa, 1000, ms);
+      }
+  // part of the short range after the lattice cutoff, for the best start
+  const int bsa = best_sa;
+  if (bn >= 2 && bsa < 3)
+    for (int sp : {300, 500, 700})
+      if (st == MSM_OK) {
+        float ms = 0.f;
+        st = time_one(bb, bw, bc, bn, bsa, sp, ms);
       }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != MSM_OK) return st;
-  st = tune(best_b, best_w, best_c, best_n, best_sa);
+  st = tune(best_b, best_w, best_c, best_n, best_sa, best_sp);
   if (st != MSM_OK) return st;
   rep += "], \"best\": {\"lattice_b\": " + std::to_string(best_b) + ", \"item_chunks\": " +
          std::to_string(best_w) + ", \"short_blocks\": " + std::to_string(best_c) + ", \"streams\": " +
-         std::to_string(best_n) + ", \"short_after\": " + std::to_string(best_sa) + ", \"ms\": " +
-         std::to_string(best) + "}}";
+         std::to_string(best_n) + ", \"short_after\": " + std::to_string(best_sa) + ", \"short_split\": " +
+         std::to_string(best_sp) + ", \"ms\": " + std::to_string(best) + "}}";
   if (report && report_bytes) {
     std::strncpy(report, rep.c_str(), report_bytes - 1);
     report[report_bytes - 1] = 0;

@@ -229,6 +229,8 @@ struct LaunchGeom {
   int streams = 3;                   // 1: in order; 2: short range on a side stream; 3: also level-0 lattice
   int short_after = 1;               // side-stream short range starts after 1: binning, 2: anterpolation,
                                      // 3: the coarse lattice cutoff
+  int short_split = 1000;            // per mille of its work items started there (the rest after the
+                                     // lattice cutoff)
   StageGrid zero, atoms, one, shortr, anterp, top, energy;
   StageGrid bin;                     // two-kernel binning (systems with bin_blocks > 0)
   bool bin4 = true;                  // some system uses the four-kernel binning

@@ -517,8 +517,9 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
+// A launch takes the work items [n lo_pm / 1000, n hi_pm / 1000) of each system.
 template <int M, bool FORCES>
-__global__ void __launch_bounds__(kShortThreads) k_short(KArgs A) {
+__global__ void __launch_bounds__(kShortThreads) k_short(KArgs A, int lo_pm, int hi_pm) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
   const Geom& g = S.g;
@@ -549,7 +550,9 @@ __global__ void __launch_bounds__(kShortThreads) k_short(KArgs A) {
   if (lane < 4) jb[kShortSeg + lane] = far;
   const int R = g.reach, side = 2 * R + 1, centre = (side * side) / 2;
   // the launch has g.short_blocks blocks; work items are strided over them
-  for (int item = blk; item < n_items; item += g.short_blocks) {
+  const int item_lo = (int)((long long)n_items * lo_pm / 1000);
+  const int item_hi = (int)((long long)n_items * hi_pm / 1000);
+  for (int item = item_lo + blk; item < item_hi; item += g.short_blocks) {
     const int row = item / g.row_items, kk = item - row * g.row_items;
     const int cy = row % g.nc[1], cz = row / g.nc[1];
     const int rowbase = (cz * g.nc[1] + cy) * g.nc[0];
@@ -1761,8 +1764,11 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
   // anterpolation or the coarse lattice cutoff), joined before interpolation
   mark(kStageShort);
   const bool short_side = concurrent && L.streams >= 2 && have_atoms && L.shortr.blocks > 0;
-  auto launch_short = [&]() {
-    if (!(have_atoms && L.shortr.blocks > 0)) return;
+  // with a side stream, the work items [0, split) start at short_after and the
+  // rest after the lattice cutoff
+  const int split = (short_side && L.short_split > 0 && L.short_split < 1000) ? L.short_split : 1000;
+  auto launch_short = [&](int lo_pm, int hi_pm) {
+    if (!(have_atoms && L.shortr.blocks > 0) || lo_pm >= hi_pm) return;
     hipStream_t ss = s;
     if (short_side) {
       fork(cc->shortr);
@@ -1770,12 +1776,12 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
     }
     const KArgs A = args(L.shortr);
     const int nb = L.shortr.blocks;
-#define MSM_SHORT(MM)                                               \
-  do {                                                              \
-    if (forces)                                                     \
-      k_short<MM, true><<<nb, kShortThreads, 0, ss>>>(A);           \
-    else                                                            \
-      k_short<MM, false><<<nb, kShortThreads, 0, ss>>>(A);          \
+#define MSM_SHORT(MM)                                                       \
+  do {                                                                      \
+    if (forces)                                                             \
+      k_short<MM, true><<<nb, kShortThreads, 0, ss>>>(A, lo_pm, hi_pm);     \
+    else                                                                    \
+      k_short<MM, false><<<nb, kShortThreads, 0, ss>>>(A, lo_pm, hi_pm);    \
   } while (0)
     switch (L.m) {
       case 1: MSM_SHORT(1); break;
@@ -1790,14 +1796,14 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
     if (short_side) (void)hipEventRecord(cc->shortr.join, ss);
   };
   const int short_at = short_side ? L.short_after : 1;
-  if (short_at == 1) launch_short();
+  if (short_at == 1) launch_short(0, split);
 
   mark(kStageAnterp);
   if (L.order == 4)
     k_anterp<4><<<L.anterp.blocks, kAThreads, 0, s>>>(args(L.anterp));
   else
     k_anterp<6><<<L.anterp.blocks, kAThreads, 0, s>>>(args(L.anterp));
-  if (short_at == 2) launch_short();
+  if (short_at == 2) launch_short(0, split);
 
   // lattice cutoff of one part (0: level 0, 1: levels 1 .. l-2 and the top,
   // 2: all of them) on stream `ls`
@@ -1843,7 +1849,8 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
     lattice(L.lattice, 1, s);
   else
     lattice(L.lattice_all, 2, s);                      // every level (and the top) in one launch
-  if (short_at == 3) launch_short();
+  if (short_at == 3) launch_short(0, split);
+  launch_short(split, 1000);
   mark(kStageTop);
   if (L.top.blocks > 0) k_top<<<L.top.blocks, kBlock, 0, s>>>(args(L.top));
 

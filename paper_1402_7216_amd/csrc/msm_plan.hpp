@@ -34,6 +34,7 @@ struct msm_plan {
   int short_cap = 0;                         // short-range blocks (0: one per work item)
   int streams = 3;                           // stream layout of an evaluation (msm_tuning.streams)
   int short_after = 1;                       // start of the side-stream short range (msm_tuning.short_after)
+  int short_split = 1000;                    // per mille of it started there (msm_tuning.short_split)
   Layout lay;
   msm::SysDesc desc;                         // host copy; device pointers filled per workspace
   msm::LaunchGeom lg;                        // stage grids of one evaluation (descriptor set per call)

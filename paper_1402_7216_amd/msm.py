@@ -39,13 +39,14 @@ STAGES = ("binning", "short_range", "anterpolation", "restriction", "lattice_cut
 
 class Tuning(ctypes.Structure):
     _fields_ = [("lattice_b", ctypes.c_int32), ("item_chunks", ctypes.c_int32), ("short_blocks", ctypes.c_int32),
-                ("streams", ctypes.c_int32), ("short_after", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("streams", ctypes.c_int32), ("short_after", ctypes.c_int32), ("short_split", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
-def make_tuning(lattice_b=0, item_chunks=0, short_blocks=0, streams=0, short_after=0) -> Tuning:
+def make_tuning(lattice_b=0, item_chunks=0, short_blocks=0, streams=0, short_after=0, short_split=0) -> Tuning:
     t = Tuning()
     t.lattice_b, t.item_chunks, t.short_blocks = int(lattice_b), int(item_chunks), int(short_blocks)
-    t.streams, t.short_after = int(streams), int(short_after)
+    t.streams, t.short_after, t.short_split = int(streams), int(short_after), int(short_split)
     return t
 
 
@@ -224,16 +225,16 @@ class Plan:
                                   _ptr(z), _ptr(q), _ptr(g), _ptr(dx), _ptr(dy), _ptr(dz), _ptr(dq)))
         return dpos, dq
 
-    def tune(self, lattice_b=0, item_chunks=0, short_blocks=0, streams=0, short_after=0):
+    def tune(self, lattice_b=0, item_chunks=0, short_blocks=0, streams=0, short_after=0, short_split=0):
         """Set tuning knobs (zero keeps a knob's value); see msm_tuning."""
-        t = make_tuning(lattice_b, item_chunks, short_blocks, streams, short_after)
+        t = make_tuning(lattice_b, item_chunks, short_blocks, streams, short_after, short_split)
         _check(lib().msm_plan_tune(self._h, _ptr(self.ws), self.ws.numel(), _stream(), ctypes.byref(t)))
 
     def tuning(self) -> dict:
         t = Tuning()
         _check(lib().msm_plan_tuning(self._h, ctypes.byref(t)))
         return {"lattice_b": t.lattice_b, "item_chunks": t.item_chunks, "short_blocks": t.short_blocks,
-                "streams": t.streams, "short_after": t.short_after}
+                "streams": t.streams, "short_after": t.short_after, "short_split": t.short_split}
 
     def autotune(self, x, y, z, q, trials=5):
         """Time the tuning candidates on these inputs, keep the fastest, return the search."""
@@ -419,8 +420,8 @@ class Batch:
         code, _ = self.status()
         _check(code)
 
-    def tune(self, lattice_b=0, item_chunks=0, short_blocks=0, streams=0, short_after=0):
-        t = make_tuning(lattice_b, item_chunks, short_blocks, streams, short_after)
+    def tune(self, lattice_b=0, item_chunks=0, short_blocks=0, streams=0, short_after=0, short_split=0):
+        t = make_tuning(lattice_b, item_chunks, short_blocks, streams, short_after, short_split)
         _check(lib().msm_batch_tune(self._h, _ptr(self.ws), self.ws.numel(), _stream(), ctypes.byref(t)))
 
     def autotune(self, x, y, z, q, trials=3):

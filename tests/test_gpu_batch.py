@@ -183,7 +183,7 @@ def test_autotune_keeps_results_within_bars(M):
     x, y, z, q = M.batch_to_device(systems)
     rep = b.autotune(x, y, z, q, trials=2)
     print(f"case batch autotune: best {rep['best']} of {len(rep['candidates'])}", flush=True)
-    assert len(rep["candidates"]) in (17, 19, 23, 25)
+    assert len(rep["candidates"]) in (17, 19, 22, 23, 25, 28)
     best = rep["best"]
     assert best["ms"] == min(c["ms"] for c in rep["candidates"])
     d = b.describe()

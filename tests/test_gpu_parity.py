@@ -311,9 +311,9 @@ def test_graph_replay_matches_eager(M):
 
 def test_tunings_keep_bars_and_stream_layouts_are_bitwise_equal(M):
     """Every tuning (lattice outputs per lane, chunks per short-range item,
-    short-range block count) stays within the bars; the stream layout and the
-    short-range start only change concurrency, so their results are bitwise
-    identical."""
+    short-range block count) stays within the bars; the stream layout, the
+    short-range start and its split around the lattice cutoff only change
+    concurrency, so their results are bitwise identical."""
     s = inputs.water_box(9000, seed=33, cutoff=10.0, spacing=2.0, order=4, levels=3)
     r = oracle.system_msm(s)
     plan = M.plan_for(s)
@@ -322,9 +322,11 @@ def test_tunings_keep_bars_and_stream_layouts_are_bitwise_equal(M):
         for w in (1, 3):
             for sb in (-1, 64):
                 outs = []
-                for n, sa in ((1, 1), (2, 1), (3, 1), (2, 3), (3, 2), (3, 3)):
-                    plan.tune(b, w, sb, n, sa)
-                    assert plan.tuning()["streams"] == n and plan.tuning()["short_after"] == sa
+                for n, sa, sp in ((1, 1, 1000), (2, 1, 1000), (3, 1, 1000), (2, 3, 1000), (3, 2, 1000),
+                                  (3, 3, 1000), (2, 1, 400), (3, 2, 700), (2, 1, 1)):
+                    plan.tune(b, w, sb, n, sa, sp)
+                    t = plan.tuning()
+                    assert t["streams"] == n and t["short_after"] == sa and t["short_split"] == sp
                     o = plan.compute(x, y, z, q, virial=True)
                     torch.cuda.synchronize()
                     plan.check()
