@@ -675,6 +675,7 @@ constexpr double kInvFix = 1.0 / 68719476736.0;
 
 constexpr int kAX = 8, kAY = 8, kAZ = 4;          // anterpolation tile (level-0 nodes)
 
+
 template <int ORDER>
 __device__ __forceinline__ void anterp_atom(const Geom& g, const int* n0, float4 p,
                                             unsigned long long* acc) {
@@ -760,15 +761,29 @@ __global__ void __launch_bounds__(kAThreads) k_anterp(KArgs A) {
     }
     if (threadIdx.x == 0) row_pre[0] = 0;
     __syncthreads();
-    if (threadIdx.x == 0)
-      for (int q = 0; q < nr; ++q) row_pre[q + 1] += row_pre[q];
+    if (threadIdx.x < kWave) {                         // inclusive scan of the row lengths by wave 0
+      int v = (int)threadIdx.x < nr ? row_pre[threadIdx.x + 1] : 0;
+#pragma unroll
+      for (int off = 1; off < kWave; off <<= 1) {
+        const int u = __shfl_up(v, off);
+        if ((int)threadIdx.x >= off) v += u;
+      }
+      if ((int)threadIdx.x < nr) row_pre[threadIdx.x + 1] = v;
+    }
     __syncthreads();
     const int ncand = row_pre[nr];
     int row = 0;
     int t = threadIdx.x;
     float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
     if (t < ncand) {
-      while (row_pre[row + 1] <= t) ++row;
+      // last row with row_pre[row] <= t (binary search over the nr + 1 prefixes)
+      int lo = 0, hi = nr - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (row_pre[mid] <= t) lo = mid;
+        else hi = mid - 1;
+      }
+      row = lo;
       nxt = sorted[row_beg[row] + (t - row_pre[row])];
     }
     while (t < ncand) {
