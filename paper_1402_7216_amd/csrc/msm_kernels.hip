@@ -840,8 +840,8 @@ struct Dyadic {
 };
 
 // One block = 8 x 8 x 4 coarse nodes; the fine nodes they read are staged in
-// LDS by all kRThreads threads (one round of loads), then one thread per
-// coarse node sums its taps.
+// LDS by all kRThreads threads (one round of loads), all threads form the
+// x-direction row sums, then one thread per coarse node combines its rows.
 constexpr int kRX = 8, kRY = 8, kRZ = 4;
 constexpr int kRThreads = 1024;
 
@@ -855,6 +855,7 @@ __global__ void __launch_bounds__(kRThreads) k_restrict(KArgs A, int k) {
   constexpr int R = D::R;
   constexpr int FX = 2 * kRX - 1 + 2 * R, FY = 2 * kRY - 1 + 2 * R, FZ = 2 * kRZ - 1 + 2 * R;
   __shared__ float fine[FX * FY * FZ];
+  __shared__ float xs[FZ * FY * kRX];                  // x-pass row sums
   const Level F = g.lv[k], C = g.lv[k + 1];
   const int ntx = (C.n[0] + kRX - 1) / kRX, nty = (C.n[1] + kRY - 1) / kRY;
   const int bx = blk % ntx, by = (blk / ntx) % nty, bz = blk / (ntx * nty);
@@ -883,24 +884,38 @@ __global__ void __launch_bounds__(kRThreads) k_restrict(KArgs A, int k) {
     }
   }
   __syncthreads();
+  // x pass over every staged (z, y) fine row, by all threads:
+  //   xs[lz][ly][tx] = sum_c w_c fine[lz][ly][2 tx + R + j_c]      (c ascending)
+  constexpr int nxs = FZ * FY * kRX;
+  for (int i = threadIdx.x; i < nxs; i += kRThreads) {
+    const int tx = i % kRX, row = i / kRX;             // row = lz * FY + ly
+    const float* rowp = fine + row * FX + 2 * tx + R;
+    float r[D::NT];
+#pragma unroll
+    for (int c = 0; c < D::NT; ++c) r[c] = rowp[D::j(c)];
+    float racc = 0.f;
+#pragma unroll
+    for (int c = 0; c < D::NT; ++c) racc = fmaf(D::w(c), r[c], racc);
+    xs[i] = racc;
+  }
+  __syncthreads();
   if (threadIdx.x >= kRX * kRY * kRZ) return;
   const int tx = threadIdx.x % kRX, ty = (threadIdx.x / kRX) % kRY, tz = threadIdx.x / (kRX * kRY);
   const int mx = c0x + tx, my = c0y + ty, mz = c0z + tz;
   if (tz >= kRZ || mx >= C.n[0] || my >= C.n[1] || mz >= C.n[2]) return;
+  // then sum_{a, b} (w_b w_a) xs[2 tz + R + j_a][2 ty + R + j_b][tx] (a, then b
+  // ascending): the operations of the direct triple sum, in its order
+  float r[D::NT][D::NT];
+#pragma unroll
+  for (int a = 0; a < D::NT; ++a)
+#pragma unroll
+    for (int b = 0; b < D::NT; ++b)
+      r[a][b] = xs[((2 * tz + D::j(a) + R) * FY + (2 * ty + D::j(b) + R)) * kRX + tx];
   float acc = 0.f;
 #pragma unroll
-  for (int a = 0; a < D::NT; ++a) {
-    const int lz = 2 * tz + D::j(a) + R;
+  for (int a = 0; a < D::NT; ++a)
 #pragma unroll
-    for (int b = 0; b < D::NT; ++b) {
-      const int ly = 2 * ty + D::j(b) + R;
-      const float* rowp = fine + (lz * FY + ly) * FX + 2 * tx + R;
-      float racc = 0.f;
-#pragma unroll
-      for (int c = 0; c < D::NT; ++c) racc = fmaf(D::w(c), rowp[D::j(c)], racc);
-      acc = fmaf(D::w(b) * D::w(a), racc, acc);
-    }
-  }
+    for (int b = 0; b < D::NT; ++b) acc = fmaf(D::w(b) * D::w(a), r[a][b], acc);
   grid[C.off + ((size_t)mz * C.n[1] + my) * C.n[0] + mx] = acc;
 }
 
