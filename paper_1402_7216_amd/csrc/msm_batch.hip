@@ -479,7 +479,8 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
            std::to_string(n) + ", \"short_after\": " + std::to_string(sa) + ", \"short_split\": " +
            std::to_string(sp) + ", \"ms\": " + std::to_string(ms) + "}";
     first = false;
-    if (ms < best) {
+    // a later (more elaborate) candidate must win by more than 1% (timing noise)
+    if (ms < best * 0.99f) {
       best = ms;
       best_b = b;
       best_w = w;

@@ -542,12 +542,14 @@ __global__ void __launch_bounds__(kShortThreads) k_short(KArgs A, int lo_pm, int
   float gc[M + 1], dc[M + 1];
 #pragma unroll
   for (int k = 0; k <= M; ++k) {
-    asm volatile("v_mov_b32 %0, %1" : "=v"(gc[k]) : "s"(g.gr[k]));
-    asm volatile("v_mov_b32 %0, %1" : "=v"(dc[k]) : "s"(g.dr[k]));
+    float gv, dv;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(gv) : "s"(g.gr[k]));
+    asm volatile("v_mov_b32 %0, %1" : "=v"(dv) : "s"(g.dr[k]));
+    gc[k] = gv;
+    dc[k] = dv;
   }
   float4* jb = jbuf[wave];
-  const float4 far = make_float4(3e30f, 3e30f, 3e30f, 0.f);
-  if (lane < 4) jb[kShortSeg + lane] = far;
+  if (lane < 4) jb[kShortSeg + lane] = make_float4(3e30f, 3e30f, 3e30f, 0.f);
   const int R = g.reach, side = 2 * R + 1, centre = (side * side) / 2;
   // the launch has g.short_blocks blocks; work items are strided over them
   const int item_lo = (int)((long long)n_items * lo_pm / 1000);
@@ -588,7 +590,7 @@ __global__ void __launch_bounds__(kShortThreads) k_short(KArgs A, int lo_pm, int
 #pragma unroll
           for (int v = 0; v < kShortSeg / kWave; ++v) {
             const int j = s0 + v * kWave + lane;
-            jb[v * kWave + lane] = (j < u1) ? sorted[j] : far;
+            jb[v * kWave + lane] = (j < u1) ? sorted[j] : make_float4(3e30f, 3e30f, 3e30f, 0.f);
           }
           // this lane's part of the staged segment: [a0, a0 + n) (n = 0 keeps a0 = 0)
           const int lo_s = max(lo, s0) - s0, hi_s = min(hi, s0 + kShortSeg) - s0;

@@ -185,7 +185,9 @@ def test_autotune_keeps_results_within_bars(M):
     print(f"case batch autotune: best {rep['best']} of {len(rep['candidates'])}", flush=True)
     assert len(rep["candidates"]) in (17, 19, 22, 23, 25, 28)
     best = rep["best"]
-    assert best["ms"] == min(c["ms"] for c in rep["candidates"])
+    # the best is within 1% of the fastest (later candidates must win by more)
+    assert best["ms"] <= 1.0101 * min(c["ms"] for c in rep["candidates"])
+    assert any(c["ms"] == best["ms"] for c in rep["candidates"])
     d = b.describe()
     assert d["lattice_b"] == best["lattice_b"] and d["item_chunks"] == best["item_chunks"]
     out = b.compute(x, y, z, q)
