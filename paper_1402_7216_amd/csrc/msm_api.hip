@@ -349,13 +349,13 @@ void assign_short_rows(Geom& g) {
   std::sort(cost.begin(), cost.end(), [](const auto& x, const auto& y) {
     return x.first > y.first || (x.first == y.first && x.second < y.second);
   });
-  double load[8] = {};
-  int count[8] = {};
+  double load[msm::kShortWaves] = {};
+  int count[msm::kShortWaves] = {};
   std::memset(g.short_rows, -1, sizeof(g.short_rows));
   for (const auto& c : cost) {
     int w = 0;
-    for (int v = 1; v < 8; ++v)
-      if (count[v] < 8 && (count[w] >= 8 || load[v] < load[w])) w = v;
+    for (int v = 1; v < msm::kShortWaves; ++v)
+      if (count[v] < msm::kShortRowsPerWave && (count[w] >= msm::kShortRowsPerWave || load[v] < load[w])) w = v;
     g.short_rows[w][count[w]++] = (signed char)c.second;
     load[w] += c.first;
   }

@@ -12,6 +12,8 @@
 namespace msm {
 
 constexpr int kMaxLevels = 12;
+constexpr int kShortWaves = 16;          // waves of a short-range block (they split the neighbour rows)
+constexpr int kShortRowsPerWave = 8;     // neighbour rows one wave can take
 constexpr int kMaxOrder = 6;
 constexpr int kMaxTopNodes = 1 << 17;     // all-pairs FP64 top level stays below ~1e10 pair terms
 constexpr int kRankCap = 2048;            // cells longer than this keep scatter order (see bin_place)
@@ -48,7 +50,8 @@ struct Geom {
   float inv_cs[3];                 // 1 / cell edge
   float cs[3];                     // cell edge (x cells are kXSub times finer than y, z)
   float a_win;                     // cutoff with a margin, for the short-range x windows
-  signed char short_rows[8][8];    // neighbour rows of each short-range wave (-1 ends a list)
+  signed char short_rows[kShortWaves][kShortRowsPerWave];   // neighbour rows of each short-range
+                                                           // wave (-1 ends a list)
   int item_chunks;                 // short-range 64-atom chunks of a cell row per work item
   int row_items;                   // short-range work items per cell row (chunks interleaved)
   int short_blocks;                // blocks of the short-range launch (work items strided over them)

@@ -494,10 +494,8 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_sort(KArgs A) {
 // length (fixed per plan); the waves' partial sums meet in LDS and are added
 // in wave order.
 // --------------------------------------------------------------------------
-constexpr int kShortThreads = 512;
-constexpr int kShortWaves = kShortThreads / kWave;
+constexpr int kShortThreads = kShortWaves * kWave;
 constexpr int kShortSeg = 256;                   // j atoms a wave stages at a time
-constexpr int kShortRowsPerWave = 8;
 
 __device__ __forceinline__ int cell_x(const Geom& g, float x) {
   float t = (x - g.lo_f[0]) * g.inv_cs[0];
@@ -519,14 +517,14 @@ __device__ __forceinline__ int wave_max(int v) {
 
 // A launch takes the work items [n lo_pm / 1000, n hi_pm / 1000) of each system.
 template <int M, bool FORCES>
-__global__ void __launch_bounds__(kShortThreads) k_short(KArgs A, int lo_pm, int hi_pm) {
+// Two blocks per CU: 8 waves per SIMD, so at most 64 registers per lane.
+__global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, int hi_pm) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
   const Geom& g = S.g;
   const float4* __restrict__ sorted = S.d.sorted;
   const int* __restrict__ start = S.d.cell_start;
   float4* __restrict__ fshort = S.d.fshort;
-  __shared__ float4 red[kShortWaves][kWave];
   // staged j atoms of each wave, then 4 far-away uncharged entries: a lane
   // reads 4 entries from min(window start + t0, kShortSeg), and every entry past
   // its window fails the cutoff test (same-row atoms beyond the window lie
@@ -644,13 +642,16 @@ __global__ void __launch_bounds__(kShortThreads) k_short(KArgs A, int lo_pm, int
         }
       }
       if (coincident) atomicOr(S.d.status, kFlagCoincident);
-      red[wave][lane] = make_float4(ax, ay, az, ap);
+      // the waves' partial sums meet in the staging buffers (all waves are done with them)
+      float4* red = &jbuf[0][0];                       // kShortWaves x kWave entries
+      __syncthreads();
+      red[wave * kWave + lane] = make_float4(ax, ay, az, ap);
       __syncthreads();
       if (wave == 0 && live) {
-        float4 t = red[0][lane];
+        float4 t = red[lane];
 #pragma unroll
         for (int w = 1; w < kShortWaves; ++w) {
-          const float4 v = red[w][lane];
+          const float4 v = red[w * kWave + lane];
           t.x += v.x;
           t.y += v.y;
           t.z += v.z;
