@@ -21,6 +21,19 @@ constexpr int kBlock = 256;
 constexpr int kWave = 64;
 
 
+// A copy of the block's system descriptor in LDS (one round of 16-byte loads
+// by the block, then a barrier).  Kernels that walk the level and tile tables
+// with data-dependent indices read them from here: a chain of dependent scalar
+// loads from the descriptor in global memory costs hundreds of cycles a link.
+static_assert(sizeof(SysDesc) % 16 == 0, "descriptor copied in 16-byte words");
+__device__ __forceinline__ const SysDesc& stage_desc(const SysDesc& src, SysDesc* dst) {
+  const int4* __restrict__ s4 = reinterpret_cast<const int4*>(&src);
+  int4* d4 = reinterpret_cast<int4*>(dst);
+  for (int i = threadIdx.x; i < (int)(sizeof(SysDesc) / 16); i += blockDim.x) d4[i] = s4[i];
+  __syncthreads();
+  return *dst;
+}
+
 // Quotient and remainder of 0 <= i < 2^20 by 0 < d <= 2^10 with a float
 // reciprocal (inv_d = 1/d rounded): (i + 1/2)/d lies at least 1/(2d) away from
 // an integer, far more than the rounding error of (i + 1/2) * inv_d, so the
@@ -1264,7 +1277,7 @@ __device__ __forceinline__ float ucut_value(const SysDesc& S, int k, int node, b
 // Per dimension, an even fine index m reads only nu = m/2 (weight Phi(0) = 1);
 // an odd one reads the ORDER coarse nodes nu = (m - R)/2 + i.
 //
-// Every level in one launch.  The blocks own 8 x 8 x 4 node tiles of every
+// Every level in one launch.  The blocks own 8 x 8 x 8 node tiles of every
 // level below the top (level 0 first).  A block of level k rebuilds in LDS the
 // coarser potentials its tile reads: the top grid over a box of nodes, then
 // levels l-2 .. k+1 each over the box the next finer box reads, and finally
@@ -1274,7 +1287,8 @@ __device__ __forceinline__ float ucut_value(const SysDesc& S, int k, int node, b
 // by the same operations as at its owner, so the results equal those of a
 // level-by-level pass while the blocks need no other block's output.
 // --------------------------------------------------------------------------
-constexpr int kPX = 8, kPY = 8, kPZ = 4;
+constexpr int kPX = 8, kPY = 8, kPZ = 8;
+constexpr int kPThreads = kPX * kPY * kPZ;          // one thread per node of a tile
 
 __host__ __device__ inline int prolong_tiles(const Level& F) {
   return ((F.n[0] + kPX - 1) / kPX) * ((F.n[1] + kPY - 1) / kPY) * ((F.n[2] + kPZ - 1) / kPZ);
@@ -1309,7 +1323,7 @@ __device__ __forceinline__ void prolong_x(const float* cs, const int* co, const 
                                           const int* fe, float* xs) {
   const int n = ce[2] * ce[1] * fe[0];
   const float inv_x = 1.f / (float)fe[0];
-  for (int i = threadIdx.x; i < n; i += kBlock) {
+  for (int i = threadIdx.x; i < n; i += kPThreads) {
     int xf;
     const int row = fdiv(i, fe[0], inv_x, xf);         // zc * ce[1] + yc
     float w[ORDER];
@@ -1368,20 +1382,21 @@ __device__ __forceinline__ void box_of(int k, int j, const int* to, int* o, int*
 // of block-wide rounds, for each level above the block's own, and one more for
 // the x-pass sums (dynamic shared memory, sized for the launch's deepest system).
 __host__ __device__ constexpr int prolong_box(int order) {
-  return ((2 * order + 1) * (2 * order + 1) * (2 * order + 1) + kBlock - 1) / kBlock * kBlock;
+  return ((2 * order + 1) * (2 * order + 1) * (2 * order + 1) + kPThreads - 1) / kPThreads * kPThreads;
 }
 
 // Few waves per SIMD (one launch of a few hundred blocks): registers are spent
 // on loads in flight instead of occupancy.
 template <int ORDER>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 2))) k_prolong(KArgs A) {
+__global__ void __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(1, 2))) k_prolong(KArgs A) {
   int blk;
-  const SysDesc& S = sys_of(A, blk);
+  __shared__ __align__(16) SysDesc sdesc;
+  const SysDesc& S = stage_desc(sys_of(A, blk), &sdesc);
   const Geom& g = S.g;
   float* __restrict__ u = S.d.u;
   constexpr int R = Dyadic<ORDER>::R;
-  constexpr int BOX = prolong_box(ORDER);              // (2R + 3)^3 rounded up to kBlock
-  constexpr int SL = BOX / kBlock;                     // nodes per thread and box
+  constexpr int BOX = prolong_box(ORDER);              // (2R + 3)^3 rounded up to kPThreads
+  constexpr int SL = BOX / kPThreads;                     // nodes per thread and box
   constexpr int LV = SL >= 9 ? 1 : 9 / SL;             // boxes per round of loads
   extern __shared__ float pbox[];                      // box of level j at pbox + (j - k - 1) * BOX
   const int top = g.levels - 1;
@@ -1425,7 +1440,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 
       int jn[SL];
 #pragma unroll
       for (int sl = 0; sl < SL; ++sl) {
-        const int li = sl * kBlock + threadIdx.x;
+        const int li = sl * kPThreads + threadIdx.x;
         int lx, ly;
         const int lz = fdiv(li, e[0] * e[1], inv_e01, ly);
         ly = fdiv(ly, e[0], inv_e0, lx);
@@ -1463,7 +1478,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 
             if (gi < ng[lv]) d += pv[lv][sl][gi];
           v = (float)ldexp(d, -j);
         }
-        pbox[(j0 + lv) * BOX + sl * kBlock + threadIdx.x] = ok[lv][sl] ? v : 0.f;
+        pbox[(j0 + lv) * BOX + sl * kPThreads + threadIdx.x] = ok[lv][sl] ? v : 0.f;
       }
     }
   }
@@ -1479,7 +1494,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 
     __syncthreads();
     const int nb = je[0] * je[1] * je[2];
     const float inv_e0 = 1.f / (float)je[0], inv_e01 = 1.f / (float)(je[0] * je[1]);
-    for (int i = threadIdx.x; i < nb; i += kBlock) {
+    for (int i = threadIdx.x; i < nb; i += kPThreads) {
       int lx, ly;
       const int lz = fdiv(i, je[0] * je[1], inv_e01, ly);
       ly = fdiv(ly, je[0], inv_e0, lx);
@@ -1905,10 +1920,10 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
     const int lds = L.max_levels * prolong_box(L.order) * (int)sizeof(float);   // boxes + x-pass sums
     if (L.order == 4) {
       (void)hipFuncSetAttribute((const void*)k_prolong<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-      k_prolong<4><<<L.prolong.blocks, kBlock, lds, s>>>(args(L.prolong));
+      k_prolong<4><<<L.prolong.blocks, kPThreads, lds, s>>>(args(L.prolong));
     } else {
       (void)hipFuncSetAttribute((const void*)k_prolong<6>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-      k_prolong<6><<<L.prolong.blocks, kBlock, lds, s>>>(args(L.prolong));
+      k_prolong<6><<<L.prolong.blocks, kPThreads, lds, s>>>(args(L.prolong));
     }
   }
   mark(kStageInterp);
