@@ -36,10 +36,13 @@ hipError_t ensure_aux(AuxStreams& A) {
   if (e != hipSuccess) return e;
   if (A.cc.shortr.stream && A.device == dev) return hipSuccess;
   destroy_aux(A);
+  // the events only order work between streams of this device: no timing and
+  // no system-scope fence (kernels end with a device-scope release already)
+  const unsigned ev_flags = hipEventDisableTiming | hipEventDisableSystemFence;
   for (msm::SideStream* ss : {&A.cc.shortr, &A.cc.lattice0}) {
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&ss->stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&ss->fork, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&ss->join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ss->fork, ev_flags);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ss->join, ev_flags);
   }
   if (e != hipSuccess) {
     destroy_aux(A);
