@@ -150,7 +150,7 @@ def main():
     if args.tuning:
         plan.tune(**json.loads(args.tuning))
     elif not args.no_autotune:
-        plan.autotune(x, y, z, q, trials=20)
+        plan.autotune(x, y, z, q, trials=40)
 
     graph = msm.Graph(plan, x, y, z, q, out)
 

@@ -199,11 +199,11 @@ typedef struct msm_tuning {
 /* Apply tuning knobs to a plan and re-upload its descriptor to ws (other
  * workspaces of the plan must be initialised again).  msm_plan_autotune times
  * candidates over `trials` evaluations of the given device inputs on `stream`
- * with HIP events: lattice_b (4, 6, 8) x item_chunks (1, 2, 3) first, then the
- * stream layout x short-range block counts, then the short-range start and
- * split; it applies the fastest (a later candidate replaces the best so far
- * only when faster by more than 1%) and writes a JSON report (nullable) of the
- * search.  *current
+ * with HIP events: lattice_b (4, 6, 8) x item_chunks (1, 2, 3) x streams
+ * (2, 3) first, then the stream layout x short-range block counts, then the
+ * short-range start, the chunks per item again and the split; it applies the
+ * fastest (a later candidate replaces the best so far only when faster by more
+ * than 1%) and writes a JSON report (nullable) of the search.  *current
  * (msm_plan_tuning, nullable) receives the tuning in effect. */
 msm_status msm_plan_tune(msm_plan* plan, void* ws, size_t ws_bytes, msm_stream_t stream,
                          const msm_tuning* tuning);

@@ -430,10 +430,11 @@ msm_status msm_batch_tune(msm_batch* Bt, void* ws, size_t ws_bytes, msm_stream_t
 }
 
 // Time candidates over `trials` evaluations of the given inputs with HIP
-// events on `stream`: lattice_b in {4, 6, 8} x item_chunks in {1, 2, 3} with
-// every stream on and one short-range block per work item, then the stream
-// layouts x short-range block counts for the best pair, then where the side
-// short range starts and how much of it waits for the lattice cutoff.  Apply
+// events on `stream`: lattice_b in {4, 6, 8} x item_chunks in {1, 2, 3} x the
+// two side-stream layouts with one short-range block per work item, then the
+// stream layouts x short-range block counts for the best pair, then where the
+// side short range starts, the chunks again, and how much of the short range
+// waits for the lattice cutoff.  Apply
 // the fastest and describe the search in `report` (JSON, nullable).
 static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm_stream_t stream,
                            const float* x, const float* y, const float* z, const float* q,
@@ -493,11 +494,14 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
   };
   msm_status st = MSM_OK;
   const std::vector<int> bs = tiled ? std::vector<int>{4, 6, 8} : std::vector<int>{0};
-  for (int b : bs)
-    for (int w : {1, 2, 3}) {
-      float ms = 0.f;
-      if (st == MSM_OK) st = time_one(b, w, -1, 3, 1, 1000, ms);
-    }
+  // B x chunks under both side-stream layouts (the best chunk count depends
+  // on the layout)
+  for (int n : {3, 2})
+    for (int b : bs)
+      for (int w : {1, 2, 3}) {
+        float ms = 0.f;
+        if (st == MSM_OK) st = time_one(b, w, -1, n, 1, 1000, ms);
+      }
   // stream layouts x short-range block counts for the best (B, chunks); the
   // counts are fractions of the compute units, so the short-range pass leaves
   // room for the grid chain running beside it
@@ -523,13 +527,20 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
         float ms = 0.f;
         st = time_one(bb, bw, bc, bn, sa, 1000, ms);
       }
+  // chunks per short-range item again, for the best layout and start (the
+  // first pass chose them with every stream on)
+  const int bsa = best_sa, bc2 = best_c, bn2 = best_n;
+  for (int w : {1, 2, 3})
+    if (st == MSM_OK && w != bw) {
+      float ms = 0.f;
+      st = time_one(bb, w, bc2, bn2, bsa, 1000, ms);
+    }
   // part of the short range after the lattice cutoff, for the best start
-  const int bsa = best_sa;
-  if (bn >= 2 && bsa < 3)
+  if (bn2 >= 2 && bsa < 3)
     for (int sp : {300, 500, 700})
       if (st == MSM_OK) {
         float ms = 0.f;
-        st = time_one(bb, bw, bc, bn, bsa, sp, ms);
+        st = time_one(bb, best_w, bc2, bn2, bsa, sp, ms);
       }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -183,7 +183,7 @@ def test_autotune_keeps_results_within_bars(M):
     x, y, z, q = M.batch_to_device(systems)
     rep = b.autotune(x, y, z, q, trials=2)
     print(f"case batch autotune: best {rep['best']} of {len(rep['candidates'])}", flush=True)
-    assert len(rep["candidates"]) in (17, 19, 22, 23, 25, 28)
+    assert 20 <= len(rep["candidates"]) <= 40
     best = rep["best"]
     # the best is within 1% of the fastest (later candidates must win by more)
     assert best["ms"] <= 1.0101 * min(c["ms"] for c in rep["candidates"])
