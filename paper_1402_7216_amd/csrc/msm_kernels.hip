@@ -1224,25 +1224,23 @@ __global__ void __launch_bounds__(kLatThreads, B <= 6 ? 8 : 4) k_lattice_win(KAr
 #pragma unroll
   for (int b = 0; b < B; ++b) red[((size_t)wave * kWave + lane) * B + b] = tot[b];
   __syncthreads();
-  if (wave == 0 && active) {
-    const int y = y0 + yi, z = z0 + zi;
-    if (y < NY && z < NZ) {
-      const size_t row0 = ((size_t)z * NY + y) * NX;
-      float* out = ucut + Lv.off + row0;
-      double* part = S.d.lat_part + T.part0 + (size_t)grp * Lv.count + row0;
+  // every thread sums one output over the waves (in wave order)
+  for (int o = threadIdx.x; o < kWave * B; o += kLatThreads) {
+    const int l = o / B, b = o - l * B;
+    const int lxi = l % T.xl, lyi = (l / T.xl) % T.ty, lzi = l / (T.xl * T.ty);
+    const int x = x0 + lxi * B + b, y = y0 + lyi, z = z0 + lzi;
+    if (lzi >= T.tz || x >= NX || y >= NY || z >= NZ) continue;
+    double r[kLatWaves];
 #pragma unroll
-      for (int b = 0; b < B; ++b) {
-        double v = 0.0;
-        for (int w = 0; w < kLatWaves; ++w) v += red[((size_t)w * kWave + lane) * B + b];
-        const int x = x0 + xi * B + b;
-        if (x < NX) {
-          if (G == 1)
-            out[x] = (float)ldexp(v, -T.level);
-          else
-            part[x] = v;
-        }
-      }
-    }
+    for (int w = 0; w < kLatWaves; ++w) r[w] = red[((size_t)w * kWave + l) * B + b];
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < kLatWaves; ++w) v += r[w];
+    const size_t node = ((size_t)z * NY + y) * NX + x;
+    if (G == 1)
+      ucut[Lv.off + node] = (float)ldexp(v, -T.level);
+    else
+      S.d.lat_part[T.part0 + (size_t)grp * Lv.count + node] = v;
   }
 }
 
