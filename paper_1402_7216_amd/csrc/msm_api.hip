@@ -308,7 +308,9 @@ void refresh_launch(msm_plan* P) {
   lg.zero.blocks = sb.zero;
   lg.atoms.blocks = sb.atoms;
   lg.bin.blocks = sb.bin;
-  lg.bin4 = g.bin_blocks == 0;
+  lg.binrow.blocks = sb.binrow;
+  lg.binrow_lds = msm::bin_rows_lds(g);
+  lg.bin4 = g.bin_blocks == 0 && g.bin_row_blocks == 0;
   lg.one.blocks = 1;
   lg.shortr.blocks = sb.shortr;
   lg.anterp.blocks = sb.anterp;
@@ -409,30 +411,41 @@ msm_status check_tuning(const msm_tuning* t) {
   return MSM_OK;
 }
 
+hipError_t read_flags(const msm_plan* P, const char* ws, int32_t* flags) {
+  int32_t w[msm::kStatusWords];
+  const int nw = 64 + P->g.bin_row_blocks;
+  hipError_t e = hipMemcpy(w, ws + P->lay.off[msm::kSecStatus], nw * sizeof(int32_t), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return e;
+  int32_t f = w[0];
+  for (int b = 64; b < nw; ++b) f |= w[b];
+  *flags = f;
+  return hipSuccess;
+}
+
 msm::DevPtrs dev_ptrs(const msm_plan* P, void* ws) {
   char* b = static_cast<char*>(ws);
   const size_t* o = P->lay.off;
   msm::DevPtrs d;
-  d.qgrid = reinterpret_cast<float*>(b + o[msm::kSecQGrid]);
-  d.ucut = reinterpret_cast<float*>(b + o[msm::kSecUCut]);
-  d.u = reinterpret_cast<float*>(b + o[msm::kSecU]);
-  d.sorted = reinterpret_cast<float4*>(b + o[msm::kSecSorted]);
-  d.perm = reinterpret_cast<int*>(b + o[msm::kSecPerm]);
-  d.fshort = reinterpret_cast<float4*>(b + o[msm::kSecShort]);
-  d.status = reinterpret_cast<int*>(b + o[msm::kSecStatus]);
-  d.counts = reinterpret_cast<int*>(b + o[msm::kSecCounts]);
-  d.cell_start = reinterpret_cast<int*>(b + o[msm::kSecCellStart]);
-  d.cursor = reinterpret_cast<int*>(b + o[msm::kSecCursor]);
-  d.cell_of = reinterpret_cast<int*>(b + o[msm::kSecCellOf]);
-  d.tmp = reinterpret_cast<int*>(b + o[msm::kSecTmp]);
-  d.bin_hist = reinterpret_cast<int*>(b + o[msm::kSecBinHist]);
-  d.rows = reinterpret_cast<const msm::StencilRow*>(b + o[msm::kSecRows]);
-  d.weights = reinterpret_cast<const float*>(b + o[msm::kSecWeights]);
-  d.rows_c = reinterpret_cast<const int4*>(b + o[msm::kSecRowsC]);
-  d.weights_c = reinterpret_cast<const float*>(b + o[msm::kSecWeightsC]);
-  d.top = reinterpret_cast<const double*>(b + o[msm::kSecTop]);
-  d.partials = reinterpret_cast<double*>(b + o[msm::kSecPartials]);
-  d.lat_part = reinterpret_cast<double*>(b + o[msm::kSecLatPart]);
+  d.qgrid = (decltype(d.qgrid))(b + o[msm::kSecQGrid]);
+  d.ucut = (decltype(d.ucut))(b + o[msm::kSecUCut]);
+  d.u = (decltype(d.u))(b + o[msm::kSecU]);
+  d.sorted = (decltype(d.sorted))(b + o[msm::kSecSorted]);
+  d.perm = (decltype(d.perm))(b + o[msm::kSecPerm]);
+  d.fshort = (decltype(d.fshort))(b + o[msm::kSecShort]);
+  d.status = (decltype(d.status))(b + o[msm::kSecStatus]);
+  d.counts = (decltype(d.counts))(b + o[msm::kSecCounts]);
+  d.cell_start = (decltype(d.cell_start))(b + o[msm::kSecCellStart]);
+  d.cursor = (decltype(d.cursor))(b + o[msm::kSecCursor]);
+  d.cell_of = (decltype(d.cell_of))(b + o[msm::kSecCellOf]);
+  d.tmp = (decltype(d.tmp))(b + o[msm::kSecTmp]);
+  d.bin_hist = (decltype(d.bin_hist))(b + o[msm::kSecBinHist]);
+  d.rows = (decltype(d.rows))(b + o[msm::kSecRows]);
+  d.weights = (decltype(d.weights))(b + o[msm::kSecWeights]);
+  d.rows_c = (decltype(d.rows_c))(b + o[msm::kSecRowsC]);
+  d.weights_c = (decltype(d.weights_c))(b + o[msm::kSecWeightsC]);
+  d.top = (decltype(d.top))(b + o[msm::kSecTop]);
+  d.partials = (decltype(d.partials))(b + o[msm::kSecPartials]);
+  d.lat_part = (decltype(d.lat_part))(b + o[msm::kSecLatPart]);
   return d;
 }
 
@@ -582,10 +595,17 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
   g.n_cells = (int)nct;
   g.a_win = (float)(a * (1.0 + 1e-4));
   assign_short_rows(g);
-  // two-kernel binning when the cell counts of every block fit (LDS, histogram size)
+  // one-kernel binning for small systems whose blocks own few enough cells;
+  // else two-kernel binning when the cell counts of every block fit (LDS,
+  // histogram size); else four kernels
   {
+    const int rows = g.nc[1] * g.nc[2];
+    const int nbr = std::min(rows, msm::kBinRowMaxBlocks);
+    const long long own = (long long)((rows + nbr - 1) / nbr) * g.nc[0];
+    g.bin_row_blocks = (n_atoms > 0 && n_atoms <= msm::kBinRowAtoms && own <= msm::kBinRowCells) ? nbr : 0;
     const long long nb = (n_atoms + msm::kBinChunk - 1) / msm::kBinChunk;
-    g.bin_blocks = (n_atoms > 0 && g.n_cells <= msm::kBinMaxCells && nb * g.n_cells <= msm::kBinMaxHist)
+    g.bin_blocks = (g.bin_row_blocks == 0 && n_atoms > 0 && g.n_cells <= msm::kBinMaxCells &&
+                    nb * g.n_cells <= msm::kBinMaxHist)
                        ? (int)nb : 0;
   }
   set_row_items(g, 1);
@@ -686,7 +706,7 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
   lay.bytes[msm::kSecSorted] = n * sizeof(float4);
   lay.bytes[msm::kSecPerm] = n * sizeof(int);
   lay.bytes[msm::kSecShort] = n * sizeof(float4);
-  lay.bytes[msm::kSecStatus] = 64 * sizeof(int);
+  lay.bytes[msm::kSecStatus] = msm::kStatusWords * sizeof(int);
   lay.bytes[msm::kSecCounts] = ((size_t)g.n_cells + 1) * sizeof(int);
   lay.bytes[msm::kSecCellStart] = ((size_t)g.n_cells + 1) * sizeof(int);
   lay.bytes[msm::kSecCursor] = (size_t)g.n_cells * sizeof(int);
@@ -767,6 +787,7 @@ msm_status msm_plan_describe(const msm_plan* P, char* buf, size_t buf_bytes) {
   o += ", \"cells\": [" + std::to_string(g.nc[0]) + ", " + std::to_string(g.nc[1]) + ", " +
        std::to_string(g.nc[2]) + "], \"reach\": " + std::to_string(g.reach) +
        ", \"bin_blocks\": " + std::to_string(g.bin_blocks) +
+       ", \"bin_row_blocks\": " + std::to_string(g.bin_row_blocks) +
        ", \"item_chunks\": " + std::to_string(g.item_chunks) + ", \"short_blocks\": " + std::to_string(g.short_blocks) +
        ", \"streams\": " + std::to_string(P->streams) + ", \"short_after\": " + std::to_string(P->short_after) +
        ", \"short_split\": " + std::to_string(P->short_split);
@@ -953,8 +974,7 @@ msm_status msm_status_query(const msm_plan* P, const void* ws, msm_stream_t stre
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "stream synchronize");
   int32_t flags = 0;
-  e = hipMemcpy(&flags, static_cast<const char*>(ws) + P->lay.off[msm::kSecStatus], sizeof(int32_t),
-                hipMemcpyDeviceToHost);
+  e = read_flags(P, static_cast<const char*>(ws), &flags);
   if (e != hipSuccess) return hip_fail(e, "read status");
   if (device_flags) *device_flags = flags;
   if (flags & msm::kFlagNonFinite) return fail(MSM_ERR_NONFINITE, "non-finite position or charge");

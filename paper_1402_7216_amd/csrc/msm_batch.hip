@@ -18,7 +18,7 @@ namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-constexpr int kNumStages = 12 + msm::kMaxLevels;
+constexpr int kNumStages = 13 + msm::kMaxLevels;
 
 }  // namespace
 
@@ -46,7 +46,7 @@ namespace {
 // Stage order inside the map arrays.
 enum : int {
   kMZero = 0, kMAtoms, kMBin, kMOne, kMShort, kMAnterp, kMLattice0, kMLattice, kMLatticeAll, kMTop, kMEnergy,
-  kMProlong,
+  kMProlong, kMBinRow,
   kMRestrict0
 };
 
@@ -64,6 +64,7 @@ msm::StageGrid* stage_of(msm::LaunchGeom& L, int st) {
     case kMTop: return &L.top;
     case kMEnergy: return &L.energy;
     case kMProlong: return &L.prolong;
+    case kMBinRow: return &L.binrow;
     default: return &L.restrict_[st - kMRestrict0];
   }
 }
@@ -82,6 +83,7 @@ int blocks_of(const msm::SysBlocks& b, int st) {
     case kMTop: return b.top;
     case kMEnergy: return b.energy;
     case kMProlong: return b.prolong;
+    case kMBinRow: return b.binrow;
     default: return b.restrict_[st - kMRestrict0];
   }
 }
@@ -101,7 +103,8 @@ void rebuild_maps(msm_batch* Bt) {
   for (int st = 0; st < kNumStages; ++st) Bt->map[st].clear();
   for (int s = 0; s < Bt->n_sys; ++s) {
     const msm_plan* P = Bt->plans[s];
-    if (P->g.bin_blocks == 0) L.bin4 = true;
+    if (P->g.bin_blocks == 0 && P->g.bin_row_blocks == 0) L.bin4 = true;
+    L.binrow_lds = std::max(L.binrow_lds, msm::bin_rows_lds(P->g));
     L.max_levels = std::max(L.max_levels, P->g.levels);
     L.lat_b = std::max(L.lat_b, P->lat.b);
     L.lat_lds = std::max(L.lat_lds, P->lat.lds_bytes);
@@ -349,7 +352,7 @@ msm_status msm_batch_status(const msm_batch* Bt, const void* ws, msm_stream_t st
     int32_t f = 0;
     const msm_plan* P = Bt->plans[s];
     const char* sub = static_cast<const char*>(ws) + Bt->sub_off[s];
-    e = hipMemcpy(&f, sub + P->lay.off[msm::kSecStatus], sizeof(int32_t), hipMemcpyDeviceToHost);
+    e = read_flags(P, sub, &f);
     if (e != hipSuccess) return hip_fail(e, "read status");
     if (flags_per_system) flags_per_system[s] = f;
     all |= f;

@@ -21,6 +21,10 @@ constexpr int kBinChunk = 2048;           // atoms per block of the two-kernel b
 constexpr int kXSub = 4;                  // link cells are this many times finer along x
 constexpr int kBinMaxCells = 8192;        // cells the two-kernel binning keeps in LDS
 constexpr int kBinMaxHist = 1 << 20;      // block histogram entries of the two-kernel binning
+constexpr int kBinRowAtoms = 32768;       // atoms per system at most for the one-kernel binning
+constexpr int kBinRowCells = 512;         // cells one block of the one-kernel binning owns at most
+constexpr int kBinRowMaxBlocks = 256;     // blocks of the one-kernel binning per system at most
+constexpr int kStatusWords = 64 + kBinRowMaxBlocks;   // [0]: flags; [64 + b]: flags of binning block b
 
 enum DeviceFlag : int { kFlagOutOfBox = 1, kFlagNonFinite = 2, kFlagCoincident = 4 };
 
@@ -45,7 +49,8 @@ struct Geom {
   // link cells
   int nc[3];
   int n_cells;
-  int bin_blocks;                  // blocks of the two-kernel binning (0: four-kernel binning)
+  int bin_blocks;                  // blocks of the two-kernel binning (0: another binning)
+  int bin_row_blocks;              // blocks of the one-kernel binning (0: another binning)
   int reach;                       // neighbour cell rows per side in y and z
   float inv_cs[3];                 // 1 / cell edge
   float cs[3];                     // cell edge (x cells are kXSub times finer than y, z)
@@ -114,7 +119,7 @@ enum Section : int {
   kSecSorted = 3,     // float4[n]
   kSecPerm = 4,       // int[n]
   kSecShort = 5,      // float4[n]
-  kSecStatus,         // int[64]
+  kSecStatus,         // int[kStatusWords]
   kSecCounts,         // int[n_cells + 1]
   kSecCellStart,      // int[n_cells + 1]
   kSecCursor,         // int[n_cells]
@@ -138,27 +143,37 @@ struct Layout {
   size_t total;
 };
 
+// Device code sees the workspace pointers in the global address space, so
+// every access through them is a global (not a flat) memory operation: flat
+// operations also count as LDS operations, and a kernel waiting for an LDS
+// result would wait for every flat load in flight.  The layout is the same.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define MSM_GLOBAL __attribute__((address_space(1)))
+#else
+#define MSM_GLOBAL
+#endif
+
 struct DevPtrs {
-  float* qgrid;
-  float* ucut;
-  float* u;
-  float4* sorted;
-  int* perm;
-  float4* fshort;
-  int* status;
-  int* counts;
-  int* cell_start;
-  int* cursor;
-  int* cell_of;
-  int* tmp;
-  int* bin_hist;
-  const StencilRow* rows;
-  const int4* rows_c;
-  const float* weights_c;
-  const float* weights;
-  const double* top;
-  double* partials;
-  double* lat_part;
+  MSM_GLOBAL float* qgrid;
+  MSM_GLOBAL float* ucut;
+  MSM_GLOBAL float* u;
+  MSM_GLOBAL float4* sorted;
+  MSM_GLOBAL int* perm;
+  MSM_GLOBAL float4* fshort;
+  MSM_GLOBAL int* status;
+  MSM_GLOBAL int* counts;
+  MSM_GLOBAL int* cell_start;
+  MSM_GLOBAL int* cursor;
+  MSM_GLOBAL int* cell_of;
+  MSM_GLOBAL int* tmp;
+  MSM_GLOBAL int* bin_hist;
+  MSM_GLOBAL const StencilRow* rows;
+  MSM_GLOBAL const int4* rows_c;
+  MSM_GLOBAL const float* weights_c;
+  MSM_GLOBAL const float* weights;
+  MSM_GLOBAL const double* top;
+  MSM_GLOBAL double* partials;
+  MSM_GLOBAL double* lat_part;
 };
 
 // Stages of one evaluation, in launch order (for optional event timing).
@@ -236,6 +251,8 @@ struct LaunchGeom {
                                      // lattice cutoff)
   StageGrid zero, atoms, one, shortr, anterp, top, energy;
   StageGrid bin;                     // two-kernel binning (systems with bin_blocks > 0)
+  StageGrid binrow;                  // one-kernel binning (systems with bin_row_blocks > 0)
+  int binrow_lds = 0;                // dynamic LDS of the one-kernel binning (largest system)
   bool bin4 = true;                  // some system uses the four-kernel binning
   StageGrid lattice0;                // lattice cutoff of level 0
   StageGrid lattice;                 // lattice cutoff of levels 1 .. l-2 (with the top level)
@@ -246,11 +263,21 @@ struct LaunchGeom {
 
 // Per-stage block counts of one system.
 struct SysBlocks {
-  int zero, atoms, bin, shortr, anterp, lattice0, lattice, lattice_all, top, energy;
+  int zero, atoms, bin, binrow, shortr, anterp, lattice0, lattice, lattice_all, top, energy;
   int restrict_[kMaxLevels];
   int prolong;                       // tiles of every level below the top
 };
 SysBlocks system_blocks(const Geom& g, const LatLaunch& lat, int n_partials);
+
+// Dynamic LDS of the one-kernel binning for one system: per-wave counts of the
+// cells a block owns, scan scratch, and a 16-bit list entry per atom.
+inline int bin_rows_lds(const Geom& g) {
+  if (g.bin_row_blocks == 0) return 0;
+  const int rows = g.nc[1] * g.nc[2];
+  const int own = (rows + g.bin_row_blocks - 1) / g.bin_row_blocks * g.nc[0];
+  const int chunks = (g.n_atoms + 63) / 64;
+  return 16 * own * 4 + 2 * 16 * 4 + chunks * 64 * 2;
+}
 
 // What one evaluation produces.
 enum Mode : int {

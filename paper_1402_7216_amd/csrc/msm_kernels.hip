@@ -147,16 +147,14 @@ __global__ void k_zero_counts(KArgs A) {
   if (i <= S.g.n_cells) S.d.counts[i] = 0;
 }
 
+__device__ __forceinline__ int cell_coord(const Geom& g, float p, int d) {
+  float t = (p - g.lo_f[d]) * g.inv_cs[d];
+  t = fminf(fmaxf(t, 0.f), (float)(g.nc[d] - 1));   // NaN -> 0
+  return min((int)t, g.nc[d] - 1);
+}
+
 __device__ __forceinline__ int cell_index(const Geom& g, float x, float y, float z) {
-  int c[3];
-  float p[3] = {x, y, z};
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    float t = (p[d] - g.lo_f[d]) * g.inv_cs[d];
-    t = fminf(fmaxf(t, 0.f), (float)(g.nc[d] - 1));   // NaN -> 0
-    c[d] = min((int)t, g.nc[d] - 1);
-  }
-  return (c[2] * g.nc[1] + c[1]) * g.nc[0] + c[0];
+  return (cell_coord(g, z, 2) * g.nc[1] + cell_coord(g, y, 1)) * g.nc[0] + cell_coord(g, x, 0);
 }
 
 __global__ void k_bin_count(KArgs A) {
@@ -164,7 +162,7 @@ __global__ void k_bin_count(KArgs A) {
   const SysDesc& S = sys_of(A, blk);
   const Geom& g = S.g;
   const int i = blk * blockDim.x + threadIdx.x;
-  if (i >= g.n_atoms || g.bin_blocks) return;
+  if (i >= g.n_atoms || g.bin_blocks || g.bin_row_blocks) return;
   const float* x = A.io.x + S.atom_off;
   const float* y = A.io.y + S.atom_off;
   const float* z = A.io.z + S.atom_off;
@@ -183,7 +181,7 @@ __global__ void __launch_bounds__(1024) k_scan(KArgs A) {
   int* __restrict__ cursor = S.d.cursor;
   int* __restrict__ status = S.d.status;
   const int n = S.g.n_cells;
-  if (S.g.bin_blocks) return;                       // binned by the two-kernel path
+  if (S.g.bin_blocks || S.g.bin_row_blocks) return;  // binned by another path
   __shared__ int part[1024];
   int t = threadIdx.x;
   int chunk = (n + 1023) / 1024;
@@ -216,7 +214,7 @@ __global__ void k_bin_scatter(KArgs A) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
   const int i = blk * blockDim.x + threadIdx.x;
-  if (i >= S.g.n_atoms || S.g.bin_blocks) return;
+  if (i >= S.g.n_atoms || S.g.bin_blocks || S.g.bin_row_blocks) return;
   const float* x = A.io.x + S.atom_off;
   const float* y = A.io.y + S.atom_off;
   const float* z = A.io.z + S.atom_off;
@@ -243,7 +241,7 @@ __global__ void k_bin_place(KArgs A) {
   const SysDesc& S = sys_of(A, blk);
   const Geom& g = S.g;
   const int s = blk * blockDim.x + threadIdx.x;
-  if (s >= g.n_atoms || g.bin_blocks) return;
+  if (s >= g.n_atoms || g.bin_blocks || g.bin_row_blocks) return;
   const int* __restrict__ cell_of = S.d.cell_of;
   const int* __restrict__ start = S.d.cell_start;
   const int* __restrict__ tmp = S.d.tmp;
@@ -489,6 +487,212 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_sort(KArgs A) {
     S.d.perm[base[c] + rank] = i;
   }
   if (flags) atomicOr(S.d.status, flags);
+}
+
+// --------------------------------------------------------------------------
+// Link cells in one kernel (systems of at most kBinRowAtoms atoms).  Cells are
+// numbered (cz ny + cy) nx + cx, so the cell row r = cz ny + cy holds the
+// cells [r nx, (r + 1) nx).  Block b of B owns the rows [b R / B, (b + 1) R / B)
+// of the R rows.  Every block walks all atoms of its system, each of its 16
+// waves over a contiguous range of 64-atom chunks: it counts the atoms of
+// earlier rows, counts per wave the atoms of each cell it owns, and lists in
+// LDS (in input order) the wave's atoms that fall in its rows.  A prefix over
+// the cells and the waves gives each (wave, cell) its first slot, and each
+// wave places its listed atoms.  The order is the one of the other binning
+// paths (cell, then input index), reached without any pass across blocks.
+// Validation flags of a block's atoms go to its own status word.
+// --------------------------------------------------------------------------
+constexpr int kBRWaves = 16;
+constexpr int kBRThreads = kBRWaves * kWave;
+constexpr int kBRUnroll = 8;   // chunks of a wave whose loads are in flight together
+
+__global__ void __launch_bounds__(kBRThreads) k_bin_rows(KArgs A) {
+  int blk;
+  const SysDesc& S = sys_of(A, blk);
+  const Geom& g = S.g;
+  extern __shared__ int lds[];
+  // every descriptor field the kernel uses, read before its first store (the
+  // compiler cannot keep later reads of the descriptor in scalar registers)
+  const int n = g.n_atoms, nb = g.bin_row_blocks, nx = g.nc[0], ny = g.nc[1], nz = g.nc[2];
+  const float lo0 = g.lo_f[0], lo1 = g.lo_f[1], lo2 = g.lo_f[2];
+  const float iv0 = g.inv_cs[0], iv1 = g.inv_cs[1], iv2 = g.inv_cs[2];
+  const double blo0 = g.lo[0], blo1 = g.lo[1], blo2 = g.lo[2];
+  const double bhi0 = g.hi[0], bhi1 = g.hi[1], bhi2 = g.hi[2];
+  int* const status = S.d.status;
+  int* const cell_start = S.d.cell_start;
+  float4* const sorted = S.d.sorted;
+  int* const perm = S.d.perm;
+  const float* x = A.io.x + S.atom_off;
+  const float* y = A.io.y + S.atom_off;
+  const float* z = A.io.z + S.atom_off;
+  const float* q = A.io.q + S.atom_off;
+  const int rows = ny * nz;
+  // (B <= kBinRowMaxBlocks and R <= B kBinRowCells: the products fit in 32 bits)
+  const int r0 = (int)((unsigned)(blk * rows) / (unsigned)nb);
+  const int r1 = (int)((unsigned)((blk + 1) * rows) / (unsigned)nb);
+  const int own = (r1 - r0) * nx;                  // cells of the block: local index (r - r0) nx + cx
+  int* cnt = lds;                                  // [kBRWaves][own] counts, then first slots
+  int* red = cnt + kBRWaves * own;                 // [2 kBRWaves]
+  unsigned short* list = reinterpret_cast<unsigned short*>(red + 2 * kBRWaves);   // [chunks * 64]
+  const int t = threadIdx.x, lane = t & (kWave - 1);
+  const int w = __builtin_amdgcn_readfirstlane(t / kWave);   // wave-uniform, in a scalar register
+  for (int c = t; c < kBRWaves * own; c += kBRThreads) cnt[c] = 0;
+  if (blk == 0 && t < 64) status[t] = 0;
+  __syncthreads();
+  const int nch = (n + kWave - 1) / kWave;
+  const int cb = w * nch / kBRWaves, ce = (w + 1) * nch / kBRWaves;
+  int* wc = cnt + w * own;
+  unsigned short* wl = list + cb * kWave;
+  // cell coordinates as cell_index computes them, with the geometry in
+  // registers (one median-of-three clamps to [0, mx], a NaN lands on 0 as
+  // there; the final min of cell_index never changes a clamped value)
+  const float mx0 = (float)(nx - 1), mx1 = (float)(ny - 1), mx2 = (float)(nz - 1);
+  auto coord = [](float p, float lo, float iv, float mx) {
+    return (int)__builtin_amdgcn_fmed3f((p - lo) * iv, 0.f, mx);
+  };
+  auto local_cell = [&](float px, float py, float pz) {
+    return (coord(pz, lo2, iv2, mx2) * ny + coord(py, lo1, iv1, mx1) - r0) * nx + coord(px, lo0, iv0, mx0);
+  };
+  const unsigned span = (unsigned)(r1 - r0);
+  int below = 0, len = 0;                          // wave-uniform
+  // one chunk: count the atoms of earlier rows, list the block's own
+  auto chunk = [&](int i, bool live, float py, float pz) {
+    const int r = coord(pz, lo2, iv2, mx2) * ny + coord(py, lo1, iv1, mx1);
+    below += __popcll(__ballot(live && r < r0));
+    const bool mine = live && (unsigned)(r - r0) < span;
+    const unsigned long long m = __ballot(mine);
+    if (m) {
+      if (mine) {
+        const int before = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
+        wl[len + before] = (unsigned short)i;
+      }
+      len += __popcll(m);
+    }
+  };
+  int c = cb;
+  // whole batches inside the atom range: loads at fixed offsets, all in flight
+  for (; c + kBRUnroll <= ce && (c + kBRUnroll) * kWave <= n; c += kBRUnroll) {
+    const int i0 = c * kWave + lane;
+    float py[kBRUnroll], pz[kBRUnroll];
+#pragma unroll
+    for (int u = 0; u < kBRUnroll; ++u) {
+      py[u] = y[i0 + u * kWave];
+      pz[u] = z[i0 + u * kWave];
+    }
+#pragma unroll
+    for (int u = 0; u < kBRUnroll; ++u) chunk(i0 + u * kWave, true, py[u], pz[u]);
+  }
+  for (; c < ce; ++c) {
+    const int i = c * kWave + lane;
+    const bool live = i < n;
+    const int il = live ? i : n - 1;
+    chunk(i, live, y[il], z[il]);
+  }
+  // per-wave counts of the listed atoms' cells; the first 64 listed atoms
+  // stay in registers for the placement
+  float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f);
+  int lc0 = -1;
+  for (int e0 = 0; e0 < len; e0 += kWave) {
+    const bool act = e0 + lane < len;
+    const int i = act ? (int)wl[e0 + lane] : 0;
+    const float4 pi = make_float4(x[i], y[i], z[i], q[i]);
+    const int lc = act ? local_cell(pi.x, pi.y, pi.z) : -1;
+    if (act) atomicAdd(&wc[lc], 1);
+    if (e0 == 0) {
+      p0 = pi;
+      lc0 = lc;
+    }
+  }
+  // first slot of every (wave, cell): atoms of earlier rows, of earlier cells
+  // of the block, and of the same cell in earlier waves
+  if (lane == 0) red[w] = below;
+  __syncthreads();
+  int v16[kBRWaves];
+#pragma unroll
+  for (int v = 0; v < kBRWaves; ++v) v16[v] = red[v];
+  int base = 0;
+#pragma unroll
+  for (int v = 0; v < kBRWaves; ++v) base += v16[v];
+  int tot = 0;
+  if (t < own) {
+#pragma unroll
+    for (int v = 0; v < kBRWaves; ++v) v16[v] = cnt[v * own + t];
+#pragma unroll
+    for (int v = 0; v < kBRWaves; ++v) {
+      const int e = v16[v];
+      v16[v] = tot;
+      tot += e;
+    }
+  }
+  int inc = tot;                                   // inclusive scan over the cells (own <= threads)
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int v = __shfl_up(inc, off);
+    if (lane >= off) inc += v;
+  }
+  if (lane == kWave - 1) red[kBRWaves + w] = inc;
+  __syncthreads();
+  int pre = 0;
+#pragma unroll
+  for (int v = 0; v < kBRWaves; ++v) {
+    const int e = red[kBRWaves + v];
+    pre += v < w ? e : 0;
+  }
+  const int start = base + pre + inc - tot;
+  if (t < own) {
+#pragma unroll
+    for (int v = 0; v < kBRWaves; ++v) cnt[v * own + t] = v16[v] + start;
+    cell_start[r0 * nx + t] = start;
+  }
+  if (blk == nb - 1 && t == 0) cell_start[rows * nx] = n;
+  __syncthreads();
+  // place the listed atoms: slot = first slot of (wave, cell) + atoms of the
+  // same cell listed earlier by the wave
+  int flags = 0;
+  for (int e0 = 0; e0 < len; e0 += kWave) {
+    const bool act = e0 + lane < len;
+    const int i = act ? (int)wl[e0 + lane] : 0;
+    float4 pi = p0;
+    int lc = lc0;
+    if (e0 > 0) {
+      pi = make_float4(x[i], y[i], z[i], q[i]);
+      lc = act ? local_cell(pi.x, pi.y, pi.z) : -1;
+    }
+    int rank = 0;
+    for (unsigned long long b = __ballot(act); b; b &= b - 1) {
+      const int j = __builtin_ctzll(b);
+      const int lj = __builtin_amdgcn_readlane(lc, j);
+      rank += (j < lane && lj == lc) ? 1 : 0;
+    }
+    if (act) {
+      const int slot = wc[lc] + rank;
+      atomicAdd(&wc[lc], 1);
+      if (!(isfinite(pi.x) && isfinite(pi.y) && isfinite(pi.z) && isfinite(pi.w))) {
+        flags |= kFlagNonFinite;
+      } else {
+        const double px = pi.x, py = pi.y, pz = pi.z;
+        if (px < blo0 || px > bhi0 || py < blo1 || py > bhi1 || pz < blo2 || pz > bhi2) flags |= kFlagOutOfBox;
+      }
+      float4 o;
+      o.x = fminf(fmaxf(pi.x, lo0), (float)bhi0);
+      o.y = fminf(fmaxf(pi.y, lo1), (float)bhi1);
+      o.z = fminf(fmaxf(pi.z, lo2), (float)bhi2);
+      o.w = isfinite(pi.w) ? pi.w : 0.f;
+      sorted[slot] = o;
+      perm[slot] = i;
+    }
+  }
+  // the block's flags: wave ORs by ballot, then over the waves
+  const int wf = (__ballot(flags & kFlagOutOfBox) ? kFlagOutOfBox : 0) |
+                 (__ballot(flags & kFlagNonFinite) ? kFlagNonFinite : 0);
+  if (lane == 0) red[w] = wf;
+  __syncthreads();
+  if (t == 0) {
+    int f = 0;
+#pragma unroll
+    for (int v = 0; v < kBRWaves; ++v) f |= red[v];
+    status[64 + blk] = f;
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -1733,6 +1937,7 @@ SysBlocks system_blocks(const Geom& g, const LatLaunch& lat, int n_partials) {
   b.zero = blocks_for(g.n_cells + 1);
   b.atoms = g.n_atoms > 0 ? blocks_for(g.n_atoms) : 0;
   b.bin = g.bin_blocks;
+  b.binrow = g.bin_row_blocks;
   b.shortr = g.n_atoms > 0 ? g.short_blocks : 0;
   const Level& L0 = g.lv[0];
   b.anterp = ((L0.n[0] + kAX - 1) / kAX) * ((L0.n[1] + kAY - 1) / kAY) * ((L0.n[2] + kAZ - 1) / kAZ);
@@ -1804,6 +2009,10 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
     (void)hipFuncSetAttribute((const void*)k_bin_sort, hipFuncAttributeMaxDynamicSharedMemorySize, sort_lds);
     k_bin_hist<<<L.bin.blocks, kBinThreads, hist_lds, s>>>(args(L.bin));
     k_bin_sort<<<L.bin.blocks, kBinThreads, sort_lds, s>>>(args(L.bin));
+  }
+  if (L.binrow.blocks > 0) {
+    (void)hipFuncSetAttribute((const void*)k_bin_rows, hipFuncAttributeMaxDynamicSharedMemorySize, L.binrow_lds);
+    k_bin_rows<<<L.binrow.blocks, kBRThreads, L.binrow_lds, s>>>(args(L.binrow));
   }
 
   // short-range pairs: on their own stream (forked after binning,

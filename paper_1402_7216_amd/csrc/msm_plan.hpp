@@ -57,6 +57,9 @@ void destroy_aux(AuxStreams& a);
 
 // Device pointers of a workspace's sections.
 msm::DevPtrs dev_ptrs(const msm_plan* P, void* ws);
+// Device flags of the last evaluation of plan P in workspace ws: status word 0
+// ORed with the words of the one-kernel binning's blocks (synchronous copy).
+hipError_t read_flags(const msm_plan* P, const char* ws, int32_t* flags);
 // Recompute the host descriptor and stage grids after a tuning change.
 void refresh_launch(msm_plan* P);
 // Apply tuning knobs (zero fields keep the current value).  Host-side only;

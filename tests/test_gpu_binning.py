@@ -1,0 +1,82 @@
+"""Link-cell binning on the GPU against its definition.
+
+Cells are numbered (cz ny + cy) nx + cx with c_d = floor((p_d - lo_d) / edge_d)
+in float32 arithmetic, clamped to the grid; the sorted order is by cell, ties
+in input order (a stable sort).  Every later kernel relies on that order (a
+cell row's atoms are contiguous; sums run in that order), so each of the three
+binning paths (one kernel for small systems, two kernels, four kernels) is
+checked against a host stable sort on systems that take that path, including
+a clustered system whose few occupied rows hold thousands of atoms each.
+"""
+import numpy as np
+import pytest
+
+from paper_1402_7216_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def M():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1402_7216_amd import msm
+    msm.lib()
+    return msm
+
+
+def host_cells(s, nc):
+    """Cell of every atom, computed as the device computes it (float32)."""
+    cells = []
+    for d, p in enumerate((s.x, s.y, s.z)):
+        lo = np.float32(s.box_lo[d])
+        inv = np.float32(nc[d] / s.box_len[d])
+        t = (p.astype(np.float32) - lo) * inv
+        t = np.minimum(np.maximum(t, np.float32(0.0)), np.float32(nc[d] - 1))
+        cells.append(np.minimum(t.astype(np.int64), nc[d] - 1))
+    return (cells[2] * nc[1] + cells[1]) * nc[0] + cells[0]
+
+
+def clustered(n, seed=11):
+    """n charges packed into a 6 A cube inside a 60 A box: a few cell rows
+    hold every atom."""
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(20.0, 26.0, size=(3, n))
+    q = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    return inputs._as_f32_system(pos, q, (0.0, 0.0, 0.0), (60.0, 60.0, 60.0), cutoff=12.0,
+                                 spacing=2.0, order=4, levels=0, name=f"clustered{n}")
+
+
+CASES = {
+    "water24k": (lambda: inputs.water_24k(), "one"),
+    "clustered20k": (lambda: clustered(20000), "one"),
+    "uniform1000": (lambda: inputs.uniform_charges(n=1000), "one"),
+    "uniform65": (lambda: inputs.uniform_charges(n=65, seed=3), "one"),
+    "uniform1": (lambda: inputs.uniform_charges(n=1, seed=4), "one"),
+    "water40k": (lambda: inputs.water_box(40000, seed=9), "two"),
+    "water100k": (lambda: inputs.water_100k(), "four"),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_binning_is_stable_cell_sort(M, name):
+    make, path = CASES[name]
+    s = make()
+    print(f"case {name} n={s.n}", flush=True)
+    plan = M.plan_for(s)
+    d = plan.describe()
+    taken = "one" if d["bin_row_blocks"] > 0 else ("two" if d["bin_blocks"] > 0 else "four")
+    assert taken == path, d
+    x, y, z, q = M.to_device(s)
+    plan.compute(x, y, z, q)
+    torch.cuda.synchronize()
+    code, flags = plan.status()
+    assert code == 0, flags
+    perm = plan.section(M.SECTION_PERM, torch.int32).cpu().numpy()[:s.n]
+    srt = plan.section(M.SECTION_SORTED).cpu().numpy()[:4 * s.n].reshape(s.n, 4)
+    order = np.argsort(host_cells(s, d["cells"]), kind="stable")
+    assert np.array_equal(perm, order)
+    for k, v in enumerate((s.x, s.y, s.z, s.q)):
+        assert np.array_equal(srt[:, k], v[order])
