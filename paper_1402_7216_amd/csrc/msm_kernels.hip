@@ -536,11 +536,24 @@ __global__ void __launch_bounds__(kBRThreads) k_bin_rows(KArgs A) {
   unsigned short* list = reinterpret_cast<unsigned short*>(red + 2 * kBRWaves);   // [chunks * 64]
   const int t = threadIdx.x, lane = t & (kWave - 1);
   const int w = __builtin_amdgcn_readfirstlane(t / kWave);   // wave-uniform, in a scalar register
+  const int nch = (n + kWave - 1) / kWave;
+  const int cb = w * nch / kBRWaves, ce = (w + 1) * nch / kBRWaves;
+  // whole batches of kBRUnroll chunks inside the atom range
+  auto full = [&](int c0) { return c0 + kBRUnroll <= ce && (c0 + kBRUnroll) * kWave <= n; };
+  // the first batch's loads are issued before the LDS is cleared and the
+  // block meets at the barrier
+  float fy[kBRUnroll], fz[kBRUnroll];
+  const bool first = full(cb);
+  if (first) {
+#pragma unroll
+    for (int u = 0; u < kBRUnroll; ++u) {
+      fy[u] = y[(cb + u) * kWave + lane];
+      fz[u] = z[(cb + u) * kWave + lane];
+    }
+  }
   for (int c = t; c < kBRWaves * own; c += kBRThreads) cnt[c] = 0;
   if (blk == 0 && t < 64) status[t] = 0;
   __syncthreads();
-  const int nch = (n + kWave - 1) / kWave;
-  const int cb = w * nch / kBRWaves, ce = (w + 1) * nch / kBRWaves;
   int* wc = cnt + w * own;
   unsigned short* wl = list + cb * kWave;
   // cell coordinates as cell_index computes them, with the geometry in
@@ -570,8 +583,13 @@ __global__ void __launch_bounds__(kBRThreads) k_bin_rows(KArgs A) {
     }
   };
   int c = cb;
-  // whole batches inside the atom range: loads at fixed offsets, all in flight
-  for (; c + kBRUnroll <= ce && (c + kBRUnroll) * kWave <= n; c += kBRUnroll) {
+  if (first) {
+#pragma unroll
+    for (int u = 0; u < kBRUnroll; ++u) chunk((c + u) * kWave + lane, true, fy[u], fz[u]);
+    c += kBRUnroll;
+  }
+  // the other whole batches: loads at fixed offsets, all in flight
+  for (; full(c); c += kBRUnroll) {
     const int i0 = c * kWave + lane;
     float py[kBRUnroll], pz[kBRUnroll];
 #pragma unroll
