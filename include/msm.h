@@ -26,7 +26,7 @@
  *   - Atom arrays are structure-of-arrays, float32, length n_atoms, in the
  *     caller's atom order; outputs are written in the same order.
  *   - Data errors (non-finite input, atom outside the box, coincident atoms)
- *     are detected on the device and recorded in a status word inside the
+ *     are detected on the device and recorded in status words inside the
  *     workspace; msm_status_query reports them.  With such an error the
  *     outputs are undefined (but every kernel stays in bounds).
  */
