@@ -72,7 +72,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+            raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_1402_7216_amd.build first")
         L = ctypes.CDLL(LIB_PATH)
         vp, sz, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32
         L.msm_plan_create.argtypes = [ctypes.POINTER(Params), i32, ctypes.POINTER(vp)]
