@@ -49,12 +49,25 @@ def clustered(n, seed=11):
                                  spacing=2.0, order=4, levels=0, name=f"clustered{n}")
 
 
+def slab(n, seed=13):
+    """n charges in a flat 20 x 120 x 120 A box with a = 8 A: 841 cell rows,
+    so blocks of the one-kernel binning own several rows each."""
+    rng = np.random.default_rng(seed)
+    size = np.array([20.0, 120.0, 120.0])
+    pos = rng.uniform(0.0, 1.0, size=(3, n)) * size[:, None]
+    q = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    return inputs._as_f32_system(pos, q, (0.0, 0.0, 0.0), tuple(size), cutoff=8.0, spacing=2.0,
+                                 order=4, levels=0, name=f"slab{n}")
+
+
 CASES = {
     "water24k": (lambda: inputs.water_24k(), "one"),
     "clustered20k": (lambda: clustered(20000), "one"),
     "uniform1000": (lambda: inputs.uniform_charges(n=1000), "one"),
     "uniform65": (lambda: inputs.uniform_charges(n=65, seed=3), "one"),
     "uniform1": (lambda: inputs.uniform_charges(n=1, seed=4), "one"),
+    "slab32768": (lambda: slab(32768), "one"),
+    "slab32769": (lambda: slab(32769, seed=14), "four"),
     "water40k": (lambda: inputs.water_box(40000, seed=9), "two"),
     "water100k": (lambda: inputs.water_100k(), "four"),
 }
