@@ -1785,7 +1785,9 @@ __global__ void __launch_bounds__(kBlock) k_interp(KArgs A) {
     }
     const float* u0 = u + L.off;
     float pl = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
-#pragma unroll 1
+    // cubic: all 64 node values are loaded in one round (registers are not
+    // scarce in this small launch); quintic: one z plane at a time
+#pragma unroll ORDER == 4 ? ORDER : 1
     for (int sz = 0; sz < ORDER; ++sz) {
       float py_ = 0.f, gxy = 0.f, gyy = 0.f;
 #pragma unroll
