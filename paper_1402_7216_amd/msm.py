@@ -131,6 +131,21 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _force_rows(f, n):
+    """Pointers to the three rows of a contiguous [3, n] float32 force buffer."""
+    if f is None:
+        return None, None, None
+    f0 = f.data_ptr()
+    return ctypes.c_void_p(f0), ctypes.c_void_p(f0 + 4 * n), ctypes.c_void_p(f0 + 8 * n)
+
+
+def _require_out(t, numel, dtype, device, name):
+    """An output buffer the kernels write through a raw pointer: contiguous,
+    of the right dtype, device and size."""
+    if t.dtype != dtype or t.device != device or not t.is_contiguous() or t.numel() != numel:
+        raise ValueError(f"out[{name!r}] must be a contiguous {dtype} tensor on {device} with {numel} elements")
+
+
 def make_params(cutoff, spacing, order=4, split_m=0, levels=0, box_lo=(0.0, 0.0, 0.0),
                 box_len=(1.0, 1.0, 1.0), coulomb_k=1.0) -> Params:
     p = Params()
@@ -195,11 +210,18 @@ class Plan:
         if virial and "virial" not in o:
             o["virial"] = torch.empty(9, dtype=torch.float64, device=dev)
         f = o.get("f") if forces else None
-        fx, fy, fz = (f[0], f[1], f[2]) if f is not None else (None, None, None)
+        ph = o.get("phi") if potentials else None
+        vr = o.get("virial") if virial else None
+        _require_out(o["energy"], 1, torch.float64, dev, "energy")
+        if f is not None:
+            _require_out(f, 3 * self.n, torch.float32, dev, "f")
+        if ph is not None:
+            _require_out(ph, self.n, torch.float32, dev, "phi")
+        if vr is not None:
+            _require_out(vr, 9, torch.float64, dev, "virial")
+        fx, fy, fz = _force_rows(f, self.n)
         _check(lib().msm_compute(self._h, _ptr(self.ws), self.ws.numel(), _stream(), _ptr(x), _ptr(y),
-                                 _ptr(z), _ptr(q), _ptr(fx), _ptr(fy), _ptr(fz),
-                                 _ptr(o.get("phi") if potentials else None), _ptr(o["energy"]),
-                                 _ptr(o.get("virial") if virial else None)))
+                                 _ptr(z), _ptr(q), fx, fy, fz, _ptr(ph), _ptr(o["energy"]), _ptr(vr)))
         return o
 
     def _check_inputs(self, x, y, z, q):
@@ -220,9 +242,13 @@ class Plan:
         """grad_energy * dE/dr into dpos [3, N] and grad_energy * dE/dq into dq [N] (float32)."""
         self._check_inputs(x, y, z, q)
         g = grad_energy.reshape(1).to(device=self.ws.device, dtype=torch.float64).contiguous()
-        dx, dy, dz = (dpos[0], dpos[1], dpos[2]) if dpos is not None else (None, None, None)
+        if dpos is not None:
+            _require_out(dpos, 3 * self.n, torch.float32, self.ws.device, "dpos")
+        if dq is not None:
+            _require_out(dq, self.n, torch.float32, self.ws.device, "dq")
+        dx, dy, dz = _force_rows(dpos, self.n)
         _check(lib().msm_backward(self._h, _ptr(self.ws), self.ws.numel(), _stream(), _ptr(x), _ptr(y),
-                                  _ptr(z), _ptr(q), _ptr(g), _ptr(dx), _ptr(dy), _ptr(dz), _ptr(dq)))
+                                  _ptr(z), _ptr(q), _ptr(g), dx, dy, dz, _ptr(dq)))
         return dpos, dq
 
     def tune(self, lattice_b=0, item_chunks=0, short_blocks=0, streams=0, short_after=0, short_split=0):
@@ -277,11 +303,17 @@ class Graph:
 
     def __init__(self, plan, x, y, z, q, out):
         self.plan, self.keep = plan, (x, y, z, q, out)
+        plan._check_inputs(x, y, z, q)
+        dev = plan.ws.device
         f = out.get("f")
-        fx, fy, fz = (f[0], f[1], f[2]) if f is not None else (None, None, None)
+        for name, numel, dtype in (("energy", 1, torch.float64), ("f", 3 * plan.n, torch.float32),
+                                   ("phi", plan.n, torch.float32), ("virial", 9, torch.float64)):
+            if out.get(name) is not None:
+                _require_out(out[name], numel, dtype, dev, name)
+        fx, fy, fz = _force_rows(f, plan.n)
         h = ctypes.c_void_p()
         _check(lib().msm_graph_capture(plan._h, _ptr(plan.ws), plan.ws.numel(), _ptr(x), _ptr(y),
-                                       _ptr(z), _ptr(q), _ptr(fx), _ptr(fy), _ptr(fz),
+                                       _ptr(z), _ptr(q), fx, fy, fz,
                                        _ptr(out.get("phi")), _ptr(out.get("energy")),
                                        _ptr(out.get("virial")), ctypes.byref(h)))
         self._h = h
@@ -384,12 +416,20 @@ class Batch:
             o["virial"] = torch.empty((self.n_sys, 9), dtype=torch.float64, device=dev)
         return o
 
+    def _check_outputs(self, o):
+        dev = self.ws.device
+        for name, numel, dtype in (("energy", self.n_sys, torch.float64), ("f", 3 * self.n, torch.float32),
+                                   ("phi", self.n, torch.float32), ("virial", 9 * self.n_sys, torch.float64)):
+            if name in ("energy", "f", "phi") or o.get(name) is not None:
+                _require_out(o[name], numel, dtype, dev, name)
+
     def compute(self, x, y, z, q, out=None, virial=False):
         self._check_inputs(x, y, z, q)
         o = out if out is not None else self.outputs(virial)
-        f = o["f"]
+        self._check_outputs(o)
+        fx, fy, fz = _force_rows(o["f"], self.n)
         _check(lib().msm_batch_compute(self._h, _ptr(self.ws), self.ws.numel(), _stream(), _ptr(x), _ptr(y),
-                                       _ptr(z), _ptr(q), _ptr(f[0]), _ptr(f[1]), _ptr(f[2]), _ptr(o["phi"]),
+                                       _ptr(z), _ptr(q), fx, fy, fz, _ptr(o["phi"]),
                                        _ptr(o["energy"]), _ptr(o.get("virial"))))
         return o
 
@@ -403,9 +443,13 @@ class Batch:
     def backward(self, x, y, z, q, grad_energy, dpos=None, dq=None):
         self._check_inputs(x, y, z, q)
         g = grad_energy.reshape(self.n_sys).to(device=self.ws.device, dtype=torch.float64).contiguous()
-        dx, dy, dz = (dpos[0], dpos[1], dpos[2]) if dpos is not None else (None, None, None)
+        if dpos is not None:
+            _require_out(dpos, 3 * self.n, torch.float32, self.ws.device, "dpos")
+        if dq is not None:
+            _require_out(dq, self.n, torch.float32, self.ws.device, "dq")
+        dx, dy, dz = _force_rows(dpos, self.n)
         _check(lib().msm_batch_backward(self._h, _ptr(self.ws), self.ws.numel(), _stream(), _ptr(x), _ptr(y),
-                                        _ptr(z), _ptr(q), _ptr(g), _ptr(dx), _ptr(dy), _ptr(dz), _ptr(dq)))
+                                        _ptr(z), _ptr(q), _ptr(g), dx, dy, dz, _ptr(dq)))
         return dpos, dq
 
     def graph(self, x, y, z, q, out):
@@ -436,10 +480,12 @@ class Batch:
 class _BatchGraph:
     def __init__(self, batch, x, y, z, q, out):
         self.keep = (batch, x, y, z, q, out)
-        f = out["f"]
+        batch._check_inputs(x, y, z, q)
+        batch._check_outputs(out)
+        fx, fy, fz = _force_rows(out["f"], batch.n)
         h = ctypes.c_void_p()
         _check(lib().msm_batch_graph_capture(batch._h, _ptr(batch.ws), batch.ws.numel(), _ptr(x), _ptr(y),
-                                             _ptr(z), _ptr(q), _ptr(f[0]), _ptr(f[1]), _ptr(f[2]),
+                                             _ptr(z), _ptr(q), fx, fy, fz,
                                              _ptr(out["phi"]), _ptr(out["energy"]), _ptr(out.get("virial")),
                                              ctypes.byref(h)))
         self._h = h

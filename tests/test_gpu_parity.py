@@ -340,3 +340,27 @@ def test_tunings_keep_bars_and_stream_layouts_are_bitwise_equal(M):
                       f"f_rms {rel_rms(f, r['f']):.2e}", flush=True)
                 assert rel_err(e, r["energy"]) <= ENERGY_RTOL
                 assert rel_rms(f, r["f"]) <= FORCE_RTOL
+
+
+def test_output_buffers_are_validated(M):
+    """The kernels write outputs through raw pointers, so the binding rejects
+    buffers of the wrong dtype, size or layout instead of writing past them."""
+    s = inputs.cloud_1k()
+    plan = M.plan_for(s)
+    x, y, z, q = M.to_device(s)
+    good = plan.compute(x, y, z, q)
+    torch.cuda.synchronize()
+    bad = [dict(good, f=torch.empty((s.n, 3), dtype=torch.float32, device="cuda").t()),
+           dict(good, f=torch.empty((3, s.n - 1), dtype=torch.float32, device="cuda")),
+           dict(good, energy=torch.empty(1, dtype=torch.float32, device="cuda")),
+           dict(good, phi=torch.empty(2 * s.n, dtype=torch.float32, device="cuda")[::2])]
+    for out in bad:
+        with pytest.raises(ValueError):
+            plan.compute(x, y, z, q, out=out)
+    with pytest.raises(ValueError):
+        plan.backward(x, y, z, q, torch.ones(1, dtype=torch.float64, device="cuda"),
+                      dpos=torch.empty((s.n, 3), dtype=torch.float32, device="cuda").t())
+    # the accepted buffers still give the same result
+    again = plan.compute(x, y, z, q, out={k: torch.empty_like(v) for k, v in good.items()})
+    torch.cuda.synchronize()
+    assert torch.equal(again["f"], good["f"]) and torch.equal(again["energy"], good["energy"])
