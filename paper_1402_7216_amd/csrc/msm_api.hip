@@ -604,9 +604,9 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
     const long long own = (long long)((rows + nbr - 1) / nbr) * g.nc[0];
     g.bin_row_blocks = (n_atoms > 0 && n_atoms <= msm::kBinRowAtoms && own <= msm::kBinRowCells) ? nbr : 0;
     const long long nb = (n_atoms + msm::kBinChunk - 1) / msm::kBinChunk;
-    g.bin_blocks = (g.bin_row_blocks == 0 && n_atoms > 0 && g.n_cells <= msm::kBinMaxCells &&
-                    nb * g.n_cells <= msm::kBinMaxHist)
-                       ? (int)nb : 0;
+    P->bin2_blocks = (n_atoms > 0 && g.n_cells <= msm::kBinMaxCells && nb * g.n_cells <= msm::kBinMaxHist)
+                         ? (int)nb : 0;
+    g.bin_blocks = g.bin_row_blocks == 0 ? P->bin2_blocks : 0;
   }
   set_row_items(g, 1);
   set_short_blocks(g, P->short_cap);
@@ -712,8 +712,10 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
   lay.bytes[msm::kSecCursor] = (size_t)g.n_cells * sizeof(int);
   lay.bytes[msm::kSecCellOf] = n * sizeof(int);
   lay.bytes[msm::kSecTmp] = n * sizeof(int);
+  // sized for the two-kernel binning wherever it is possible (a batch may
+  // switch a system to it)
   lay.bytes[msm::kSecBinHist] =
-      std::max<size_t>((size_t)g.bin_blocks * ((g.n_cells + 3) & ~3), 1) * sizeof(int);
+      std::max<size_t>((size_t)P->bin2_blocks * ((g.n_cells + 3) & ~3), 1) * sizeof(int);
   lay.bytes[msm::kSecRows] = std::max<size_t>(P->rows.size(), 1) * sizeof(msm::StencilRow);
   lay.bytes[msm::kSecWeights] = std::max<size_t>(P->weights.size(), 1) * sizeof(float);
   lay.bytes[msm::kSecRowsC] = std::max<size_t>(P->rows_c.size(), 1) * sizeof(int4);

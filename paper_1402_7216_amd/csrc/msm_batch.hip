@@ -196,6 +196,16 @@ msm_status msm_batch_create(const msm_params* params, const int32_t* n_atoms, in
     }
   }
   Bt->total_atoms = off;
+  // with several systems the two-kernel binning wins on throughput: the
+  // one-kernel binning walks all of a system's atoms in every block, which
+  // pays for a single system's latency but not when many systems fill the GPU
+  if (n_sys > 1)
+    for (msm_plan* P : Bt->plans)
+      if (P->g.bin_row_blocks > 0 && P->bin2_blocks > 0) {
+        P->g.bin_row_blocks = 0;
+        P->g.bin_blocks = P->bin2_blocks;
+        refresh_launch(P);
+      }
   const msm_plan* P0 = Bt->plans[0];
   bool tiled = P0->lat.b > 0 || P0->g.levels == 1;
   for (const msm_plan* P : Bt->plans) {

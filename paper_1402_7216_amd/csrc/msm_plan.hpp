@@ -28,6 +28,7 @@ struct msm_plan {
   std::vector<float> weights;                // full stencil weights
   std::vector<double> top;                   // FP64 top-level kernel table
   int n_partials = 1;
+  int bin2_blocks = 0;                       // blocks of the two-kernel binning where it is possible
   msm::LatLaunch lat;
   int lat_tables = 0;                        // LDS bytes of the compact stencil tables
   int lat_part_max = 0;                      // lattice row-group partials of the largest tuning
