@@ -1077,10 +1077,12 @@ struct Dyadic {
   static constexpr float wodd(int i) { return (float)phi_half(ORDER, R - 2 * i); }
 };
 
-// One block = 8 x 8 x 4 coarse nodes; the fine nodes they read are staged in
+// One block = 4 x 4 x 4 coarse nodes (small tiles: more blocks, each a short
+// round of loads; 8 x 8 x 4 took 16.4 us for the three launches on water24k
+// against 13.6 us); the fine nodes they read are staged in
 // LDS by all kRThreads threads (one round of loads), all threads form the
 // x-direction row sums, then one thread per coarse node combines its rows.
-constexpr int kRX = 8, kRY = 8, kRZ = 4;
+constexpr int kRX = 4, kRY = 4, kRZ = 4;
 constexpr int kRThreads = 1024;
 
 template <int ORDER>
