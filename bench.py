@@ -3,16 +3,25 @@
 
 One step = one full evaluation (binning, short-range pairs, anterpolation,
 restriction, lattice cutoff, top level, prolongation, interpolation,
-reductions) of a 24,000-atom rigid 3-site water box (62.1 A cube, a = 12 A,
-h = 2 A, cubic basis, 4 levels) whose float32 inputs are already resident in
-HBM.  The metric is atom-evaluations per second (N / time per evaluation).
-The plan is autotuned on the inputs first (untimed); the evaluation is timed
-both replayed as a HIP graph and launched eagerly, and the faster is reported.
+reductions) whose float32 inputs are already resident in HBM.  The headline
+workload is the largest single-GPU system: 999,999 atoms of rigid 3-site
+water (215.4 A cube, a = 12 A, h = 2.5 A, quintic basis, 5 levels).  The
+metric is atom-evaluations per second (N / time per evaluation).  The plan is
+autotuned on the inputs first (untimed); the evaluation is timed both replayed
+as a HIP graph and launched eagerly, and the faster is reported.  Each timed
+step is bracketed by HIP events, so the line carries the median step beside
+the mean of the K-step window.
 
 Prints one JSON line.  Besides the timed steps it reports
   * roofline: the dominant kernel's algorithmic FLOP rate against the FP32
-    vector peak, timed with HIP events on the library's stream,
-  * cpu_baseline: the FP64 CPU oracle on the same inputs on the host cores.
+    vector peak, timed with HIP events on the library's stream;
+  * parity: the timed configuration's forces, potentials and energy against
+    the FP64 CPU oracle on the same inputs;
+  * cpu_baseline: that oracle run, timed on the host cores (plus one-thread
+    times of the 1,000-atom cloud and the 24,000-atom water box);
+  * extras: the 24,000-atom box, the 100,000-atom box through the
+    differentiable path (energy, then backward), and the 64-replica batch
+    (forward, and forward + backward) against 64 sequential evaluations.
 """
 from __future__ import annotations
 
@@ -27,8 +36,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 (256 CUs x 2.4 GHz x 256 FLOP/clk)
-WORKLOADS = ("water24k", "water100k", "water1m", "cloud1k")
+PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 (256 CUs x 2.4 GHz x 256 FLOP/clk, packed)
+WORKLOADS = ("water1m", "water24k", "water100k", "cloud1k")
 
 
 def make_system(name):
@@ -37,14 +46,22 @@ def make_system(name):
             "water1m": inputs.water_1m, "cloud1k": inputs.cloud_1k}[name]()
 
 
-def traffic_for(kernel_key):
+def describe_workload(s):
+    if s.name == "water1m":
+        return "water1m: 999,999-atom rigid 3-site water box, 0.1 atoms/A^3"
+    if s.name.startswith("water"):
+        return f"{s.name}: {s.n}-atom rigid 3-site water box, 0.1 atoms/A^3"
+    return s.name
+
+
+def traffic_for(kernel_key, workload):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
-        rec = json.load(f).get(kernel_key)
+        rec = json.load(f).get(workload, {}).get(kernel_key)
     if not rec:
         return None
     src = os.path.join(ROOT, "paper_1402_7216_amd", "csrc", "msm_kernels.hip")
@@ -54,24 +71,145 @@ def traffic_for(kernel_key):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(system, repeats):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def event_timed(torch, step, steps, warmup):
+    """W untimed steps, then K steps bracketed by synchronisation, each step
+    between two HIP events on the current stream.  Returns (mean s, median s)."""
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record()
+    for k in range(steps):
+        step()
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / max(steps, 1)
+    per = [ev[k].elapsed_time(ev[k + 1]) * 1e-3 for k in range(steps)]
+    return max(wall, sum(per) / max(steps, 1)), statistics.median(per)
+
+
+def parity(out, ref):
+    import numpy as np
+    f = out["f"].double().cpu().numpy()
+    phi = out["phi"].double().cpu().numpy()
+    e = float(out["energy"].item())
+    fr = float(np.linalg.norm(f - ref["f"]) / np.linalg.norm(ref["f"]))
+    pr = float(np.linalg.norm(phi - ref["phi"]) / np.linalg.norm(ref["phi"]))
+    er = abs(e - ref["energy"]) / abs(ref["energy"])
+    return {"force_rel_rms": fr, "phi_rel_rms": pr, "energy_rel": er,
+            "within_bars": bool(fr <= 1e-5 and pr <= 1e-5 and er <= 1e-7)}
+
+
+def cpu_leg(system, out):
+    """The FP64 oracle on the timed inputs: its time on every host core (the
+    CPU baseline) and the parity of the GPU outputs against it; then the
+    one-thread oracle on the 1,000-atom cloud and the 24,000-atom box."""
     import oracle
+    from paper_1402_7216_amd import inputs
     cores = len(os.sched_getaffinity(0))
-    times = []
-    for _ in range(repeats):
-        t0 = time.perf_counter()
-        oracle.system_msm(system, threads=cores)
-        times.append(time.perf_counter() - t0)
-    t = statistics.median(times)
-    return {"value": system.n / t, "unit": "atom-evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"full {system.n}-atom evaluation (energy, forces, potentials) in FP64, "
-                      f"median of {repeats} runs, {t:.3f} s each"}
+    t0 = time.perf_counter()
+    ref = oracle.system_msm(system, threads=cores)
+    t = time.perf_counter() - t0
+    one = {}
+    for name, make in (("cloud1k", inputs.cloud_1k), ("water24k", inputs.water_24k)):
+        s = make()
+        t1 = time.perf_counter()
+        oracle.system_msm(s, threads=1)
+        dt = time.perf_counter() - t1
+        one[name] = {"s": round(dt, 4), "atom_evals_per_s": s.n / dt}
+    base = {"value": system.n / t, "unit": "atom-evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"one full {system.n}-atom evaluation (energy, forces, potentials) in FP64 "
+                      f"on {cores} threads, {t:.2f} s",
+            "cpu_model": cpu_model(), "one_thread": one}
+    return base, parity(out, ref)
 
 
-def batched_leg(msm, steps, warmup, autotune):
+def coarse_leg(msm, torch, s, t_msm, steps, warmup, x, y, z, q):
+    """The cheap pair methods the thesis proposes as coarse propagators G
+    (plain cutoff, shifted-force smoothed cutoff, Wolf summation, rc = a,
+    Wolf alpha = 0.2 / A) on the same inputs, each autotuned over its cell
+    knobs; Q_F/G = t(MSM) / t(G), the ratio the thesis estimates as about 60
+    from operation counts."""
+    res = {}
+    for kind in ("cutoff", "shifted_force", "wolf"):
+        plan = msm.pair_plan_for(s, kind, alpha=0.2)
+        out = plan.compute(x, y, z, q)
+        torch.cuda.synchronize()
+        plan.check()
+        plan.autotune(x, y, z, q, trials=10)
+        mean, med = event_timed(torch, lambda: plan.compute(x, y, z, q, out=out), steps, warmup)
+        plan.check()
+        res[kind] = {"ms": round(mean * 1e3, 5), "ms_median": round(med * 1e3, 5),
+                     "atom_evals_per_s": s.n / mean, "q_f_over_g": round(t_msm / mean, 3),
+                     "tuning": plan.tuning()}
+    return res
+
+
+def water24k_leg(msm, torch, steps, warmup):
+    s = make_system("water24k")
+    plan = msm.plan_for(s)
+    x, y, z, q = msm.to_device(s)
+    out = plan.compute(x, y, z, q)
+    torch.cuda.synchronize()
+    plan.check()
+    plan.autotune(x, y, z, q, trials=20)
+    graph = msm.Graph(plan, x, y, z, q, out)
+    modes = {"hipGraph replay": graph.launch, "eager": lambda: plan.compute(x, y, z, q, out=out)}
+    res = {k: event_timed(torch, fn, steps, warmup) for k, fn in modes.items()}
+    launch = min(res, key=lambda k: res[k][0])
+    plan.check()
+    mean, med = res[launch]
+    return {"workload": describe_workload(s), "atoms": s.n, "launch": launch,
+            "ms_per_step": round(mean * 1e3, 5), "ms_median": round(med * 1e3, 5),
+            "atom_evals_per_s": s.n / mean, "tuning": plan.tuning(),
+            "coarse_propagators": coarse_leg(msm, torch, s, mean, steps, warmup, x, y, z, q)}
+
+
+def water100k_grad_leg(msm, torch, steps, warmup):
+    """Differentiable path on the 100,000-atom box: energy-only forward, then
+    the adjoint backward (dE/dr and dE/dq), as autograd would call them."""
+    s = make_system("water100k")
+    plan = msm.plan_for(s)
+    x, y, z, q = msm.to_device(s)
+    plan.compute(x, y, z, q)
+    torch.cuda.synchronize()
+    plan.check()
+    plan.autotune(x, y, z, q, trials=10)
+    e = torch.empty(1, dtype=torch.float64, device="cuda")
+    g = torch.ones(1, dtype=torch.float64, device="cuda")
+    dpos = torch.empty((3, s.n), dtype=torch.float32, device="cuda")
+    dq = torch.empty(s.n, dtype=torch.float32, device="cuda")
+
+    def fwd_bwd():
+        plan.energy(x, y, z, q, out=e)
+        plan.backward(x, y, z, q, g, dpos, dq)
+
+    mean, med = event_timed(torch, fwd_bwd, steps, warmup)
+    fmean, fmed = event_timed(torch, lambda: plan.compute(x, y, z, q), steps, warmup)
+    plan.check()
+    return {"workload": describe_workload(s), "atoms": s.n,
+            "ms_forward_backward": round(mean * 1e3, 5), "ms_forward_backward_median": round(med * 1e3, 5),
+            "atom_evals_per_s_forward_backward": s.n / mean,
+            "ms_forces_eval": round(fmean * 1e3, 5)}
+
+
+def batched_leg(msm, torch, workmodel, steps, warmup, autotune):
     """64 uneven water replicas (2,000-60,000 atoms, a = 10 A, h = 2 A): one
-    batched graph replay against 64 single-system evaluations in sequence."""
-    import torch
+    batched graph replay against 64 single-system evaluations in sequence,
+    forward (energy, forces, potentials) and forward + backward (energy, then
+    dE/dr and dE/dq)."""
     from paper_1402_7216_amd import inputs
     reps = inputs.water_replicas(64)
     b = msm.batch_for(reps)
@@ -85,47 +223,77 @@ def batched_leg(msm, steps, warmup, autotune):
     ins = [msm.to_device(s) for s in reps]
     outs = [p.compute(*i) for p, i in zip(plans, ins)]
     graphs = [msm.Graph(p, *i, o) for p, i, o in zip(plans, ins, outs)]
+    t_batch, t_batch_med = event_timed(torch, graph.launch, steps, warmup)
+    t_seq_graph, _ = event_timed(torch, lambda: [g.launch() for g in graphs], steps, warmup)
+    t_seq_eager, _ = event_timed(torch, lambda: [p.compute(*i, out=o) for p, i, o in zip(plans, ins, outs)],
+                                 steps, warmup)
+    # forward + backward
+    e = torch.empty(b.n_sys, dtype=torch.float64, device="cuda")
+    gs = torch.ones(b.n_sys, dtype=torch.float64, device="cuda")
+    dpos = torch.empty((3, b.n), dtype=torch.float32, device="cuda")
+    dq = torch.empty(b.n, dtype=torch.float32, device="cuda")
 
-    def timed(fn):
-        for _ in range(warmup):
-            fn()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / steps
+    def batch_fb():
+        e.copy_(b.energy(x, y, z, q))
+        b.backward(x, y, z, q, gs, dpos, dq)
 
-    t_batch = timed(graph.launch)
-    t_seq_graph = timed(lambda: [g.launch() for g in graphs])
-    t_seq_eager = timed(lambda: [p.compute(*i, out=o) for p, i, o in zip(plans, ins, outs)])
+    g1 = torch.ones(1, dtype=torch.float64, device="cuda")
+    grads = [(torch.empty((3, p.n), dtype=torch.float32, device="cuda"),
+              torch.empty(p.n, dtype=torch.float32, device="cuda")) for p in plans]
+
+    def seq_fb():
+        for p, i, (gp, gq) in zip(plans, ins, grads):
+            p.energy(*i)
+            p.backward(*i, g1, gp, gq)
+
+    t_fb, t_fb_med = event_timed(torch, batch_fb, steps, warmup)
+    t_seq_fb, _ = event_timed(torch, seq_fb, steps, warmup)
     b.check()
+    # whole-batch algorithmic work and its rate against the FP32 vector peak
+    flop = 0.0
+    for s, p in zip(reps, plans):
+        _, _, gn = p.info()
+        nodes = [int(v[0]) * int(v[1]) * int(v[2]) for v in gn]
+        pairs = workmodel.count_pairs_within(s.pos64(), s.cutoff)
+        flop += workmodel.evaluation_work(s.n, pairs, nodes, s.cutoff, s.spacing, s.order,
+                                          s.split_m or s.order // 2)["total"]
+    ach = flop / t_batch / 1e12
     n = b.n
     return {"workload": "64 rigid-water replicas, 2k-60k atoms each (a = 10 A, h = 2 A, cubic)",
             "atoms": n, "ms_batched_graph": round(t_batch * 1e3, 4),
+            "ms_batched_graph_median": round(t_batch_med * 1e3, 4),
             "ms_64_sequential_graphs": round(t_seq_graph * 1e3, 4),
             "ms_64_sequential_eager": round(t_seq_eager * 1e3, 4),
             "atom_evals_per_s": n / t_batch,
             "speedup_vs_sequential_eager": round(t_seq_eager / t_batch, 3),
             "speedup_vs_sequential_graphs": round(t_seq_graph / t_batch, 3),
+            "ms_batched_forward_backward": round(t_fb * 1e3, 4),
+            "ms_batched_forward_backward_median": round(t_fb_med * 1e3, 4),
+            "ms_64_sequential_forward_backward": round(t_seq_fb * 1e3, 4),
+            "atom_evals_per_s_forward_backward": n / t_fb,
+            "speedup_forward_backward_vs_sequential": round(t_seq_fb / t_fb, 3),
+            "roofline": {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4),
+                         "scope": "whole batched evaluation", "algorithmic_flop": flop},
             "tuning": best}
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="water24k", choices=WORKLOADS)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="water1m", choices=WORKLOADS)
     ap.add_argument("--launch", default="best", choices=("best", "hipGraph", "eager"),
                     help="launch mode to time (best: time both, report the faster)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the plan's default tuning")
     ap.add_argument("--tuning", default=None,
                     help="JSON tuning to apply instead of autotuning, e.g. the config.tuning of an "
                          "earlier run (for profiler passes over the timed configuration)")
-    ap.add_argument("--cpu-repeats", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batch", action="store_true", help="skip the 64-replica batched leg")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle (CPU baseline and parity)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the 24k, 100k-gradient and 64-replica legs")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -150,33 +318,26 @@ def main():
     if args.tuning:
         plan.tune(**json.loads(args.tuning))
     elif not args.no_autotune:
-        plan.autotune(x, y, z, q, trials=40)
+        plan.autotune(x, y, z, q, trials=40 if s.n < 200000 else 10)
 
     graph = msm.Graph(plan, x, y, z, q, out)
-
-    def timed(step, steps, warmup):
-        for _ in range(warmup):
-            step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            step()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / max(steps, 1)
-
     # both launch modes time the same evaluation; the faster one is reported
     modes = {"hipGraph replay": graph.launch, "eager": lambda: plan.compute(x, y, z, q, out=out)}
     if args.launch != "best":
         modes = {k: v for k, v in modes.items() if k.startswith(args.launch)}
-    mode_sec = {k: timed(fn, args.steps, args.warmup) for k, fn in modes.items()}
-    launch = min(mode_sec, key=mode_sec.get)
-    sec = mode_sec[launch]
+    mode_sec = {k: event_timed(torch, fn, args.steps, args.warmup) for k, fn in modes.items()}
+    launch = min(mode_sec, key=lambda k: mode_sec[k][0])
+    sec, sec_med = mode_sec[launch]
     plan.check()
+    # the outputs of the timed configuration (for the parity check)
+    out = plan.compute(x, y, z, q, out=out)
+    torch.cuda.synchronize()
+    timed_out = {k: v.clone() for k, v in out.items()}
 
-    # per-stage kernel durations, HIP events on the library's stream (eager launches)
+    # per-stage kernel durations, HIP events on the library's stream (stages in order)
     plan.profile(True)
     stage_sum = {}
-    n_prof = max(10, min(args.steps, 200))
+    n_prof = max(10, min(args.steps, 100))
     for _ in range(n_prof):
         plan.compute(x, y, z, q, out=out)
         for k, v in plan.stage_ms().items():
@@ -193,7 +354,7 @@ def main():
     achieved = kernel_flops[dom] / dom_s / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": traffic_for(dom), "kernel": dom,
+                "traffic": traffic_for(dom, s.name), "kernel": dom,
                 "kernel_ms": round(stage_ms[dom], 5), "kernel_flop": kernel_flops[dom]}
 
     rec = {
@@ -204,26 +365,32 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": sec * 1e3,
+        "ms_per_step_median": sec_med * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{s.name}: rigid 3-site water, 0.1 atoms/A^3" if s.name.startswith("water")
-                   else s.name, "n_atoms": s.n, "cutoff": s.cutoff, "spacing": s.spacing,
-                   "order": s.order, "levels": levels, "grid_sides": [int(v[0]) for v in gn],
-                   "launch": launch, "tuning": plan.tuning()},
-        "ms_per_launch_mode": {k: round(v * 1e3, 5) for k, v in mode_sec.items()},
+        "config": {"workload": describe_workload(s), "n_atoms": s.n, "cutoff": s.cutoff,
+                   "spacing": s.spacing, "order": s.order, "levels": levels,
+                   "grid_sides": [int(v[0]) for v in gn], "launch": launch, "tuning": plan.tuning()},
+        "ms_per_launch_mode": {k: round(v[0] * 1e3, 5) for k, v in mode_sec.items()},
         "roofline": roofline,
         "stages_ms": {k: round(v, 5) for k, v in stage_ms.items()},
         "algorithmic_tflops_per_step": round(work["total"] / sec / 1e12, 3),
         "algorithmic_flop_per_eval": work["total"],
         "unique_pairs": n_pairs,
     }
-    if not args.no_batch:
-        rec["batched"] = batched_leg(msm, max(5, min(args.steps // 10, 50)), 5, not args.no_autotune)
+    if not args.no_extras:
+        rec["coarse_propagators"] = coarse_leg(msm, torch, s, sec, args.steps, args.warmup, x, y, z, q)
+        rec["extras"] = {
+            "water24k": water24k_leg(msm, torch, max(args.steps, 50), args.warmup),
+            "water100k_forward_backward": water100k_grad_leg(msm, torch, max(args.steps, 50), args.warmup),
+            "batched": batched_leg(msm, torch, workmodel, max(20, min(args.steps, 50)), 5,
+                                   not args.no_autotune),
+        }
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(s, args.cpu_repeats)
+        rec["cpu_baseline"], rec["parity"] = cpu_leg(s, timed_out)
     print(json.dumps(rec), flush=True)
 
 

@@ -71,6 +71,10 @@ typedef struct {
 typedef struct msm_plan msm_plan;   /* host object; immutable after creation */
 
 /* Create a plan for systems of exactly n_atoms atoms (n_atoms >= 0).
+ * Thesis Sec. 2.3: the l grids of spacing 2^k h (nodal basis display), the
+ * cutoff 2^k a carried by level k (eq. msmgrid), the interpolation degree p
+ * and smoothing degree m of eq. (flop); Sec. 2.1 "Potentials" for the link
+ * cells of the short-range sum.
  * Validates the parameters, derives the grid hierarchy (level k node mu sits
  * at box_lo + 2^k h mu; each level spans every node with a non-zero weight)
  * and the cell decomposition.  *out receives the plan (host memory owned by
@@ -79,6 +83,34 @@ typedef struct msm_plan msm_plan;   /* host object; immutable after creation */
  * this build's limits). */
 msm_status msm_plan_create(const msm_params* params, int32_t n_atoms, msm_plan** out);
 msm_status msm_plan_destroy(msm_plan* plan);
+
+/* Cheap pair methods on their own: the coarse propagators the thesis proposes
+ * beside MSM (Sec. 3.2 "Proposed Solutions": "Cutoff Method", "Wolf Summation
+ * Method"; the smoothed cutoff method of Sec. 2.2).  The pair energy
+ * q_i q_j e(r) is summed over the unordered pairs closer than rc:
+ *   MSM_PAIR_CUTOFF          e(r) = 1/r
+ *   MSM_PAIR_SHIFTED_FORCE   e(r) = 1/r - 1/rc + (r - rc)/rc^2 (smoothed cutoff:
+ *                            energy and force vanish continuously at rc)
+ *   MSM_PAIR_WOLF            e(r) = erfc(alpha r)/r - erfc(alpha rc)/rc, plus the
+ *                            self energy -(erfc(alpha rc)/(2 rc) + alpha/sqrt(pi)) q_i^2
+ * msm_pair_plan_create returns a plan for n_atoms atoms that works with
+ * msm_workspace_bytes, msm_workspace_init, msm_compute (same outputs: forces
+ * -dE/dr_i, potentials dE/dq_i, energy, virial), msm_graph_capture,
+ * msm_status_query, msm_plan_describe, msm_plan_tune / msm_plan_autotune (the
+ * cell knobs) and msm_plan_destroy; msm_energy and
+ * msm_backward return MSM_ERR_UNSUPPORTED for it, and batches do not take it.
+ * Pair arithmetic is float32 (erfcf, expf for Wolf), reductions float64. */
+typedef enum { MSM_PAIR_CUTOFF = 1, MSM_PAIR_SHIFTED_FORCE = 2, MSM_PAIR_WOLF = 3 } msm_pair_kind;
+typedef struct {
+  int32_t kind;           /* msm_pair_kind */
+  int32_t reserved;       /* must be 0 */
+  double cutoff;          /* rc > 0, Angstrom */
+  double alpha;           /* Wolf damping (1/Angstrom), >= 0; ignored by the other kinds */
+  double box_lo[3];       /* box lower corner */
+  double box_len[3];      /* box edge lengths > 0; atoms must lie in [lo, lo + len] */
+  double coulomb_k;       /* prefactor 1/(4 pi eps0); 0 -> 1 */
+} msm_pair_params;
+msm_status msm_pair_plan_create(const msm_pair_params* params, int32_t n_atoms, msm_plan** out);
 
 /* Grid hierarchy of a plan: *levels, and per level k the lowest node index
  * grid_lo[3k+d] and node count grid_n[3k+d] along dimension d (host arrays of
@@ -100,7 +132,11 @@ msm_status msm_workspace_bytes(const msm_plan* plan, size_t* bytes);
  * `stream`.  ws: device, at least msm_workspace_bytes bytes. */
 msm_status msm_workspace_init(const msm_plan* plan, void* ws, size_t ws_bytes, msm_stream_t stream);
 
-/* Full evaluation (energy, forces, potentials).
+/* Full evaluation (energy, forces, potentials): the itemised MSM algorithm of
+ * Sec. 2.3 (short-range part, anterpolation, restriction and lattice cutoff
+ * per level, top level, prolongation, interpolation), the potential display
+ * U_i ~ (u_i^short + u_i^long) / (4 pi eps0), and F_i = -dU/dr_i of Sec. 2.1
+ * "Simulation loop".
  * x, y, z, q : device float32 [n_atoms]  positions (A) and charges (e)
  * fx, fy, fz : device float32 [n_atoms]  forces F_i = -dE/dr_i (nullable: all three or none)
  * phi        : device float32 [n_atoms]  potentials phi_i = dE/dq_i (nullable)
@@ -114,8 +150,9 @@ msm_status msm_compute(const msm_plan* plan, void* ws, size_t ws_bytes, msm_stre
                        float* fx, float* fy, float* fz, float* phi, double* energy,
                        double* virial);
 
-/* Energy only: E as msm_compute would return it, evaluated through the grid
- * form 1/2 sum_k <q^k, u^{k,cut}> of the long-range part (no prolongation,
+/* Energy only (Sec. 2.3 potential display, E = 1/2 sum_i q_i U_i): E as
+ * msm_compute would return it, evaluated through the grid form
+ * 1/2 sum_k <q^k, u^{k,cut}> of the long-range part (no prolongation,
  * interpolation or short-range forces).  energy: device float64 [1].
  * Nothing but the workspace is written; grid potentials are not kept for a
  * later backward pass (msm_backward recomputes them). */
@@ -123,7 +160,8 @@ msm_status msm_energy(const msm_plan* plan, void* ws, size_t ws_bytes, msm_strea
                       const float* x, const float* y, const float* z, const float* q,
                       double* energy);
 
-/* Backward pass of the energy: with g = *grad_energy (device float64 scalar,
+/* Backward pass of the energy (F_i = -dU/dr_i, Sec. 2.1 "Simulation loop";
+ * the chain of Sec. 2.3 run as its adjoint): with g = *grad_energy (device float64 scalar,
  * read on the device, so no host synchronisation),
  *   dedx, dedy, dedz (device float32 [n], nullable all three) = g dE/dr_i = -g F_i
  *   dedq            (device float32 [n], nullable)            = g dE/dq_i =  g phi_i.
@@ -148,7 +186,11 @@ msm_status msm_status_query(const msm_plan* plan, const void* ws, msm_stream_t s
  * nothing is executed.  msm_graph_launch replays it on `stream`: each replay
  * is a complete evaluation of the current contents of x, y, z, q.  The plan,
  * workspace and buffers must outlive the graph; replays on one workspace
- * must not overlap.  Free with msm_graph_destroy. */
+ * must not overlap.  A graph holds the launch grids, kernel variants and LDS
+ * sizes of the tuning in effect when it was captured: after msm_plan_tune,
+ * msm_plan_autotune, msm_batch_tune or msm_batch_autotune on its plan or
+ * batch, msm_graph_launch refuses it (MSM_ERR_INVALID_ARG, nothing runs);
+ * capture it again.  Free with msm_graph_destroy. */
 typedef struct msm_graph msm_graph;
 msm_status msm_graph_capture(const msm_plan* plan, void* ws, size_t ws_bytes, const float* x,
                              const float* y, const float* z, const float* q, float* fx, float* fy,
@@ -193,7 +235,10 @@ typedef struct msm_tuning {
                             others start after the lattice cutoff (so they
                             overlap the prolongation rather than the lattice
                             cutoff); 1000: all of them */
-  int32_t reserved[2];   /* must be zero */
+  int32_t cell_reach;    /* link cells of edge a / cell_reach along y and z
+                            (2, 3 or 4; x cells are 4 times finer): finer cells
+                            cut the short-range candidates beyond the cutoff */
+  int32_t reserved;      /* must be zero */
 } msm_tuning;
 
 /* Apply tuning knobs to a plan and re-upload its descriptor to ws (other

@@ -46,6 +46,7 @@
 #endif
 
 #define OR_MAX_LEVELS 12
+#define OR_PI 3.14159265358979323846
 #define OR_MAX_M 8
 
 enum {
@@ -730,5 +731,141 @@ int oracle_direct(int n, const double* x, const double* y, const double* z, cons
   if (phi) memcpy(phi, ph, sizeof(double) * (size_t)n);
   if (energy) *energy = e.s + e.c;
   free(ph);
+  return bad ? OR_ECOINCIDENT : OR_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Cheap pair methods the thesis proposes as coarse propagators G (Sec. 3.2  */
+/* "Proposed Solutions": "Cutoff Method", "Wolf Summation Method"; the       */
+/* smoothed cutoff is named in Sec. 2.2).  Each sums a pair energy           */
+/* q_i q_j e(r) over the unordered pairs closer than rc, plus a self term    */
+/* s q_i^2 per atom:                                                         */
+/*   kind 1, plain cutoff:  e(r) = 1/r                                       */
+/*   kind 2, smoothed cutoff (shifted force; reading of the thesis, which    */
+/*           names the method only): e(r) = 1/r - 1/rc + (r - rc)/rc^2,     */
+/*           so e and e' vanish at rc                                        */
+/*   kind 3, Wolf summation: e(r) = erfc(alpha r)/r - erfc(alpha rc)/rc,     */
+/*           s = -(erfc(alpha rc)/(2 rc) + alpha/sqrt(pi))                   */
+/* Outputs (times ke): E = sum_{i<j} q_i q_j e(r_ij) + s sum_i q_i^2,        */
+/*   phi_i = dE/dq_i = sum_{j != i} q_j e(r_ij) + 2 s q_i,                   */
+/*   F_i = -dE/dr_i = -q_i sum_{j != i} q_j e'(r_ij) (r_i - r_j)/r_ij,       */
+/*   W_ab = sum_i (r_i - lo)_a F_i,b.                                        */
+/* Pairs are found through cells of edge >= rc (each atom scans the 27       */
+/* cells around its own), or over all pairs when all_pairs is set.           */
+/* ------------------------------------------------------------------------- */
+static double pair_e(int kind, double rc, double alpha, double r) {
+  if (kind == 1) return 1.0 / r;
+  if (kind == 2) return 1.0 / r - 1.0 / rc + (r - rc) / (rc * rc);
+  return erfc(alpha * r) / r - erfc(alpha * rc) / rc;
+}
+
+static double pair_de(int kind, double rc, double alpha, double r) {   /* d e / d r */
+  if (kind == 1) return -1.0 / (r * r);
+  if (kind == 2) return -1.0 / (r * r) + 1.0 / (rc * rc);
+  return -erfc(alpha * r) / (r * r) - 2.0 * alpha / sqrt(OR_PI) * exp(-alpha * alpha * r * r) / r;
+}
+
+double oracle_pair_e(int kind, double rc, double alpha, double r) { return pair_e(kind, rc, alpha, r); }
+
+int oracle_pair(int kind, double rc, double alpha, const double* lo, const double* len, double ke,
+                int n, const double* x, const double* y, const double* z, const double* q,
+                double* fx, double* fy, double* fz, double* phi, double* energy, double* virial,
+                int all_pairs, int nthreads) {
+  if (kind < 1 || kind > 3 || !(rc > 0.0) || !(alpha >= 0.0) || n < 0) return OR_EINVAL;
+  if (ke == 0.0) ke = 1.0;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+  for (int d = 0; d < 3; ++d)
+    if (!(len[d] > 0.0)) return OR_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    if (!isfinite(x[i]) || !isfinite(y[i]) || !isfinite(z[i]) || !isfinite(q[i])) return OR_ENONFINITE;
+    const double p3[3] = {x[i], y[i], z[i]};
+    for (int d = 0; d < 3; ++d)
+      if (p3[d] < lo[d] || p3[d] > lo[d] + len[d]) return OR_EOUTBOX;
+  }
+  const double self = (kind == 3) ? -(erfc(alpha * rc) / (2.0 * rc) + alpha / sqrt(OR_PI)) : 0.0;
+  int nc[3];
+  double cs[3];
+  for (int d = 0; d < 3; ++d) {
+    nc[d] = (int)floor(len[d] / rc);
+    if (nc[d] < 1) nc[d] = 1;
+    cs[d] = len[d] / nc[d];
+  }
+  size_t ncell = (size_t)nc[0] * nc[1] * nc[2];
+  int* cell = (int*)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+  int* start = (int*)calloc(ncell + 1, sizeof(int));
+  int* list = (int*)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+  const double* r[3] = {x, y, z};
+  for (int i = 0; i < n; ++i) {
+    int c3[3];
+    for (int d = 0; d < 3; ++d) {
+      int c = (int)floor((r[d][i] - lo[d]) / cs[d]);
+      c3[d] = c < 0 ? 0 : (c >= nc[d] ? nc[d] - 1 : c);
+    }
+    cell[i] = (c3[2] * nc[1] + c3[1]) * nc[0] + c3[0];
+    start[cell[i] + 1]++;
+  }
+  for (size_t c = 0; c < ncell; ++c) start[c + 1] += start[c];
+  {
+    int* fill = (int*)malloc(sizeof(int) * (ncell > 0 ? ncell : 1));
+    for (size_t c = 0; c < ncell; ++c) fill[c] = start[c];
+    for (int i = 0; i < n; ++i) list[fill[cell[i]]++] = i;
+    free(fill);
+  }
+  double* ph = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  double* f3 = (double*)calloc(3 * (size_t)(n > 0 ? n : 1), sizeof(double));
+  const double rc2 = rc * rc;
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(| : bad)
+  for (int i = 0; i < n; ++i) {
+    double p = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
+    int ci = cell[i], cx = ci % nc[0], cy = (ci / nc[0]) % nc[1], cz = ci / (nc[0] * nc[1]);
+    for (int oz = -1; oz <= 1; ++oz)
+      for (int oy = -1; oy <= 1; ++oy)
+        for (int ox = -1; ox <= 1; ++ox) {
+          if (all_pairs && (ox || oy || oz)) continue;
+          int jx = cx + ox, jy = cy + oy, jz = cz + oz;
+          if (jx < 0 || jy < 0 || jz < 0 || jx >= nc[0] || jy >= nc[1] || jz >= nc[2]) continue;
+          int cj = (jz * nc[1] + jy) * nc[0] + jx;
+          const int t0 = all_pairs ? 0 : start[cj], t1 = all_pairs ? n : start[cj + 1];
+          for (int t = t0; t < t1; ++t) {
+            int j = all_pairs ? t : list[t];
+            if (j == i) continue;
+            double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 >= rc2) continue;
+            if (r2 == 0.0) { bad = 1; continue; }
+            double rr = sqrt(r2);
+            p += q[j] * pair_e(kind, rc, alpha, rr);
+            double w = -q[i] * q[j] * pair_de(kind, rc, alpha, rr) / rr;
+            ax += w * dx; ay += w * dy; az += w * dz;
+          }
+        }
+    ph[i] = ke * (p + 2.0 * self * q[i]);
+    f3[3 * (size_t)i] = ke * ax;
+    f3[3 * (size_t)i + 1] = ke * ay;
+    f3[3 * (size_t)i + 2] = ke * az;
+  }
+  nsum_t e = {0.0, 0.0};
+  nsum_t w[9];
+  memset(w, 0, sizeof(w));
+  for (int i = 0; i < n; ++i) {
+    const double* fi = f3 + 3 * (size_t)i;
+    const double r3[3] = {x[i] - lo[0], y[i] - lo[1], z[i] - lo[2]};
+    nsum_add(&e, 0.5 * q[i] * ph[i]);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) nsum_add(&w[3 * a + b], r3[a] * fi[b]);
+    if (fx) fx[i] = fi[0];
+    if (fy) fy[i] = fi[1];
+    if (fz) fz[i] = fi[2];
+  }
+  if (phi) memcpy(phi, ph, sizeof(double) * (size_t)n);
+  if (energy) *energy = e.s + e.c;
+  if (virial)
+    for (int t = 0; t < 9; ++t) virial[t] = w[t].s + w[t].c;
+  free(cell); free(start); free(list); free(ph); free(f3);
   return bad ? OR_ECOINCIDENT : OR_OK;
 }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <utility>
 #include <cmath>
 #include <cstring>
@@ -299,6 +300,7 @@ void refresh_launch(msm_plan* P) {
   lg.n_sys = 1;
   lg.order = g.order;
   lg.m = g.m;
+  lg.pair = g.pair;
   lg.lat_b = P->lat.b;
   lg.lat_lds = P->lat.lds_bytes;
   lg.max_levels = g.levels;
@@ -312,6 +314,9 @@ void refresh_launch(msm_plan* P) {
   lg.binrow_lds = msm::bin_rows_lds(g);
   lg.bin4 = g.bin_blocks == 0 && g.bin_row_blocks == 0;
   lg.one.blocks = 1;
+  lg.scan.blocks = sb.scan;
+  lg.agather.blocks = sb.agather;
+  lg.anterp_lds = msm::anterp_lds(g);
   lg.shortr.blocks = sb.shortr;
   lg.anterp.blocks = sb.anterp;
   lg.lattice0.blocks = sb.lattice0;
@@ -382,7 +387,59 @@ void set_short_blocks(Geom& g, int cap) {
   g.short_blocks = cap > 0 ? std::min(cap, items) : items;
 }
 
+// Link cells of edge >= a / reach along y and z (kXSub times finer along x;
+// coarser if the cell count would exceed 8 n + 4096), the short-range row
+// assignment and work items, and the binning path the cells allow: one kernel
+// for small systems whose blocks own few enough cells (unless the plan prefers
+// the two-kernel path, as in batches), else two kernels when the cell counts of
+// every block fit (LDS, histogram size), else four.
+void set_cell_geometry(msm_plan* P, int reach) {
+  Geom& g = P->g;
+  const msm_params& p = P->p;
+  const int n_atoms = g.n_atoms;
+  const double amargin = p.cutoff * (1.0 + 1e-4);
+  auto set_cells = [&](int r, double edge_min) {
+    g.reach = r;
+    long long tot = 1;
+    for (int d = 0; d < 3; ++d) {
+      int nc = (int)std::floor(p.box_len[d] / (d == 0 ? edge_min / msm::kXSub : edge_min));
+      nc = std::max(1, std::min(nc, d == 0 ? 4096 : 1024));
+      g.nc[d] = nc;
+      g.inv_cs[d] = (float)(nc / p.box_len[d]);
+      g.cs[d] = (float)(p.box_len[d] / nc);
+      tot *= nc;
+    }
+    return tot;
+  };
+  const long long cap = 8LL * std::max(n_atoms, 1) + 4096;
+  long long nct = set_cells(reach, amargin / reach);
+  for (int r = reach - 1; r >= 1 && nct > cap; --r) nct = set_cells(r, amargin / r);
+  if (nct > cap) {
+    const double vol = p.box_len[0] * p.box_len[1] * p.box_len[2];
+    nct = set_cells(1, std::max(amargin, std::cbrt(vol / (double)cap)));
+  }
+  g.n_cells = (int)nct;
+  assign_short_rows(g);
+  const int rows = g.nc[1] * g.nc[2];
+  const int nbr = std::min(rows, msm::kBinRowMaxBlocks);
+  const long long own = (long long)((rows + nbr - 1) / nbr) * g.nc[0];
+  const long long nb = (n_atoms + msm::kBinChunk - 1) / msm::kBinChunk;
+  P->bin2_blocks = (n_atoms > 0 && g.n_cells <= msm::kBinMaxCells && nb * g.n_cells <= msm::kBinMaxHist)
+                       ? (int)nb : 0;
+  const bool one = n_atoms > 0 && n_atoms <= msm::kBinRowAtoms && own <= msm::kBinRowCells;
+  g.bin_row_blocks = (one && !(P->prefer_bin2 && P->bin2_blocks > 0)) ? nbr : 0;
+  g.bin_blocks = g.bin_row_blocks == 0 ? P->bin2_blocks : 0;
+  set_row_items(g, g.item_chunks);
+  set_short_blocks(g, P->short_cap);
+}
+
+// Cell reach of a new plan: finer rows (higher reach) cut the short-range
+// candidates that fail the cutoff test but add rows to every work item, which
+// only pays when many work items keep the GPU busy.
+int default_reach(int n_atoms) { return n_atoms >= 200000 ? 4 : 2; }
+
 void retune(msm_plan* P, const msm_tuning& t) {
+  if (t.cell_reach != 0 && t.cell_reach != P->g.reach) set_cell_geometry(P, t.cell_reach);
   if (t.lattice_b && P->lat.b && t.lattice_b != P->lat.b)
     choose_lattice_tiles(P->g, P->rows_c, (int)P->weights.size(), P->lat.H, P->lat_tables, P->lat,
                          t.lattice_b);
@@ -406,8 +463,9 @@ msm_status check_tuning(const msm_tuning* t) {
   if (t->short_after < 0 || t->short_after > 3) return fail(MSM_ERR_INVALID_ARG, "short_after must be 0 .. 3");
   if (t->short_split < 0 || t->short_split > 1000)
     return fail(MSM_ERR_INVALID_ARG, "short_split must be 0 .. 1000");
-  for (int32_t r : t->reserved)
-    if (r != 0) return fail(MSM_ERR_INVALID_ARG, "reserved tuning fields must be zero");
+  if (t->cell_reach != 0 && (t->cell_reach < 2 || t->cell_reach > 4))
+    return fail(MSM_ERR_INVALID_ARG, "cell_reach must be 0, 2, 3 or 4");
+  if (t->reserved != 0) return fail(MSM_ERR_INVALID_ARG, "reserved tuning field must be zero");
   return MSM_OK;
 }
 
@@ -439,6 +497,8 @@ msm::DevPtrs dev_ptrs(const msm_plan* P, void* ws) {
   d.cell_of = (decltype(d.cell_of))(b + o[msm::kSecCellOf]);
   d.tmp = (decltype(d.tmp))(b + o[msm::kSecTmp]);
   d.bin_hist = (decltype(d.bin_hist))(b + o[msm::kSecBinHist]);
+  d.scan = (decltype(d.scan))(b + o[msm::kSecScan]);
+  d.ant_part = (decltype(d.ant_part))(b + o[msm::kSecAntPart]);
   d.rows = (decltype(d.rows))(b + o[msm::kSecRows]);
   d.weights = (decltype(d.weights))(b + o[msm::kSecWeights]);
   d.rows_c = (decltype(d.rows_c))(b + o[msm::kSecRowsC]);
@@ -487,6 +547,8 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
 
   msm_plan* P = new (std::nothrow) msm_plan();
   if (!P) return fail(MSM_ERR_INVALID_ARG, "out of host memory");
+  static std::atomic<uint64_t> next_uid{1};
+  P->uid = next_uid.fetch_add(1);
   P->p = p;
   Geom& g = P->g;
   std::memset(&g, 0, sizeof(g));
@@ -555,6 +617,31 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
     return fail(MSM_ERR_UNSUPPORTED, "top level too large for the all-pairs sum; use more levels");
   }
 
+  // anterpolation tiles: start from 16 x 16 x 8 level-0 nodes and halve the
+  // largest side (down to 4) until there are at least 512 tiles, so a launch
+  // covers the 256 compute units twice
+  {
+    int t[3] = {16, 16, 8};
+    auto tiles = [&]() {
+      long long n = 1;
+      for (int d = 0; d < 3; ++d) n *= (g.fmax[d] + t[d]) / t[d];
+      return n;
+    };
+    while (tiles() < 512) {
+      int d = 0;
+      for (int e = 1; e < 3; ++e)
+        if (t[e] > t[d]) d = e;
+      if (t[d] <= 4) break;
+      t[d] /= 2;
+    }
+    g.at_ext = 1;
+    for (int d = 0; d < 3; ++d) {
+      g.at[d] = t[d];
+      g.atn[d] = (g.fmax[d] + t[d]) / t[d];          // tiles covering floor indices 0 .. fmax
+      g.at_ext *= t[d] + p.order - 1;
+    }
+  }
+
   // smoothing constants
   double c[9];
   taylor_coeffs(g.m, c);
@@ -568,48 +655,16 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
   g.a2 = (float)(a * a);
   g.inv_a2 = (float)(1.0 / (a * a));
 
-  // link cells: edge >= a / reach (with a margin for float rounding of cell ids)
-  const double amargin = a * (1.0 + 1e-4);
-  // (x cells kXSub times finer: the short-range pass cuts each atom's window
-  // along x to its own reach)
-  auto set_cells = [&](int reach, double edge_min) {
-    g.reach = reach;
-    long long tot = 1;
-    for (int d = 0; d < 3; ++d) {
-      int nc = (int)std::floor(p.box_len[d] / (d == 0 ? edge_min / msm::kXSub : edge_min));
-      nc = std::max(1, std::min(nc, d == 0 ? 4096 : 1024));
-      g.nc[d] = nc;
-      g.inv_cs[d] = (float)(nc / p.box_len[d]);
-      g.cs[d] = (float)(p.box_len[d] / nc);
-      tot *= nc;
-    }
-    return tot;
-  };
-  long long cap = 8LL * std::max(n_atoms, 1) + 4096;
-  long long nct = set_cells(2, amargin / 2.0);
-  if (nct > cap) nct = set_cells(1, amargin);
-  if (nct > cap) {
-    double vol = p.box_len[0] * p.box_len[1] * p.box_len[2];
-    nct = set_cells(1, std::max(amargin, std::cbrt(vol / (double)cap)));
-  }
-  g.n_cells = (int)nct;
+  // link cells: the finest reach any tuning may ask for sizes the cell
+  // sections; the plan starts at the default reach
   g.a_win = (float)(a * (1.0 + 1e-4));
-  assign_short_rows(g);
-  // one-kernel binning for small systems whose blocks own few enough cells;
-  // else two-kernel binning when the cell counts of every block fit (LDS,
-  // histogram size); else four kernels
-  {
-    const int rows = g.nc[1] * g.nc[2];
-    const int nbr = std::min(rows, msm::kBinRowMaxBlocks);
-    const long long own = (long long)((rows + nbr - 1) / nbr) * g.nc[0];
-    g.bin_row_blocks = (n_atoms > 0 && n_atoms <= msm::kBinRowAtoms && own <= msm::kBinRowCells) ? nbr : 0;
-    const long long nb = (n_atoms + msm::kBinChunk - 1) / msm::kBinChunk;
-    P->bin2_blocks = (n_atoms > 0 && g.n_cells <= msm::kBinMaxCells && nb * g.n_cells <= msm::kBinMaxHist)
-                         ? (int)nb : 0;
-    g.bin_blocks = g.bin_row_blocks == 0 ? P->bin2_blocks : 0;
+  g.item_chunks = 1;
+  for (int r : {2, 3, 4}) {
+    set_cell_geometry(P, r);
+    P->max_cells = std::max(P->max_cells, g.n_cells);
+    P->max_bin_hist = std::max(P->max_bin_hist, (long long)P->bin2_blocks * ((g.n_cells + 3) & ~3));
   }
-  set_row_items(g, 1);
-  set_short_blocks(g, P->short_cap);
+  set_cell_geometry(P, default_reach(n_atoms));
 
   // lattice-cutoff stencil: W(n) = g^0(h |n|) for h |n| < 2a, rows along z
   if (L > 1) {
@@ -707,15 +762,16 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
   lay.bytes[msm::kSecPerm] = n * sizeof(int);
   lay.bytes[msm::kSecShort] = n * sizeof(float4);
   lay.bytes[msm::kSecStatus] = msm::kStatusWords * sizeof(int);
-  lay.bytes[msm::kSecCounts] = ((size_t)g.n_cells + 1) * sizeof(int);
-  lay.bytes[msm::kSecCellStart] = ((size_t)g.n_cells + 1) * sizeof(int);
-  lay.bytes[msm::kSecCursor] = (size_t)g.n_cells * sizeof(int);
+  lay.bytes[msm::kSecCounts] = ((size_t)P->max_cells + 1) * sizeof(int);
+  lay.bytes[msm::kSecCellStart] = ((size_t)P->max_cells + 1) * sizeof(int);
+  lay.bytes[msm::kSecCursor] = (size_t)P->max_cells * sizeof(int);
   lay.bytes[msm::kSecCellOf] = n * sizeof(int);
   lay.bytes[msm::kSecTmp] = n * sizeof(int);
   // sized for the two-kernel binning wherever it is possible (a batch may
   // switch a system to it)
-  lay.bytes[msm::kSecBinHist] =
-      std::max<size_t>((size_t)P->bin2_blocks * ((g.n_cells + 3) & ~3), 1) * sizeof(int);
+  lay.bytes[msm::kSecBinHist] = std::max<size_t>((size_t)P->max_bin_hist, 1) * sizeof(int);
+  lay.bytes[msm::kSecScan] = ((size_t)P->max_cells / msm::kScanTile + 1) * sizeof(int);
+  lay.bytes[msm::kSecAntPart] = (size_t)g.atn[0] * g.atn[1] * g.atn[2] * g.at_ext * sizeof(long long);
   lay.bytes[msm::kSecRows] = std::max<size_t>(P->rows.size(), 1) * sizeof(msm::StencilRow);
   lay.bytes[msm::kSecWeights] = std::max<size_t>(P->weights.size(), 1) * sizeof(float);
   lay.bytes[msm::kSecRowsC] = std::max<size_t>(P->rows_c.size(), 1) * sizeof(int4);
@@ -731,6 +787,55 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
   }
   lay.total = o;
 
+  refresh_launch(P);
+  *out = P;
+  return MSM_OK;
+}
+
+msm_status msm_pair_plan_create(const msm_pair_params* pp, int32_t n_atoms, msm_plan** out) {
+  if (!pp || !out) return fail(MSM_ERR_INVALID_ARG, "null params or output pointer");
+  *out = nullptr;
+  if (pp->kind < MSM_PAIR_CUTOFF || pp->kind > MSM_PAIR_WOLF)
+    return fail(MSM_ERR_INVALID_ARG, "kind must be MSM_PAIR_CUTOFF, MSM_PAIR_SHIFTED_FORCE or MSM_PAIR_WOLF");
+  if (pp->reserved != 0) return fail(MSM_ERR_INVALID_ARG, "reserved field must be 0");
+  if (!finite_pos(pp->cutoff)) return fail(MSM_ERR_INVALID_ARG, "cutoff must be finite and > 0");
+  if (!std::isfinite(pp->alpha) || pp->alpha < 0.0) return fail(MSM_ERR_INVALID_ARG, "alpha must be finite and >= 0");
+  // the cells, binning and short-range pass of an MSM plan with cutoff rc; its
+  // (unused) grid is one coarse level
+  msm_params p{};
+  p.cutoff = pp->cutoff;
+  double maxlen = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    p.box_lo[d] = pp->box_lo[d];
+    p.box_len[d] = pp->box_len[d];
+    if (std::isfinite(pp->box_len[d])) maxlen = std::max(maxlen, pp->box_len[d]);
+  }
+  p.spacing = std::max(pp->cutoff, maxlen / 8.0);
+  p.order = 4;
+  p.levels = 1;
+  p.coulomb_k = pp->coulomb_k;
+  msm_plan* P = nullptr;
+  msm_status st = msm_plan_create(&p, n_atoms, &P);
+  if (st != MSM_OK) return st;
+  Geom& g = P->g;
+  const double rc = pp->cutoff, al = pp->alpha;
+  g.pair = pp->kind;
+  g.pk[0] = g.pk[1] = g.pk[2] = g.pk[3] = 0.f;
+  g.self = 0.f;
+  if (pp->kind == MSM_PAIR_SHIFTED_FORCE) {
+    g.pk[0] = (float)(1.0 / rc);
+    g.pk[1] = (float)(1.0 / (rc * rc));
+  } else if (pp->kind == MSM_PAIR_WOLF) {
+    const double two_over_sqrt_pi = 1.1283791670955126;
+    g.pk[0] = (float)al;
+    g.pk[1] = (float)(std::erfc(al * rc) / rc);
+    g.pk[2] = (float)(al * two_over_sqrt_pi);
+    g.pk[3] = (float)(al * al);
+    // phi_i gains 2 s q_i with s = -(erfc(alpha rc)/(2 rc) + alpha/sqrt(pi)); the
+    // assembly subtracts q_i self
+    g.self = (float)(std::erfc(al * rc) / rc + al * two_over_sqrt_pi);
+  }
+  P->pp = *pp;
   refresh_launch(P);
   *out = P;
   return MSM_OK;
@@ -785,7 +890,7 @@ msm_status msm_plan_describe(const msm_plan* P, char* buf, size_t buf_bytes) {
   if (!P || !buf || buf_bytes == 0) return fail(MSM_ERR_INVALID_ARG, "null plan or buffer");
   const Geom& g = P->g;
   std::string o = "{";
-  o += "\"levels\": " + std::to_string(g.levels);
+  o += "\"pair\": " + std::to_string(g.pair) + ", \"levels\": " + std::to_string(g.levels);
   o += ", \"cells\": [" + std::to_string(g.nc[0]) + ", " + std::to_string(g.nc[1]) + ", " +
        std::to_string(g.nc[2]) + "], \"reach\": " + std::to_string(g.reach) +
        ", \"bin_blocks\": " + std::to_string(g.bin_blocks) +
@@ -825,10 +930,12 @@ msm_status msm_workspace_section(const msm_plan* P, int32_t section, size_t* off
 }
 
 
-msm_status msm_workspace_init(const msm_plan* P, void* ws, size_t ws_bytes, msm_stream_t stream) {
-  if (!P) return fail(MSM_ERR_INVALID_ARG, "null plan");
-  if (!ws || ws_bytes < P->lay.total) return fail(MSM_ERR_WORKSPACE, "workspace missing or too small");
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+}  // extern "C"
+
+// Upload the plan's tables and descriptor into the workspace at ws (device)
+// and clear its cell counters, on stream s; waits for the copies (they read
+// pageable host memory of the plan).
+msm_status init_workspace(const msm_plan* P, void* ws, hipStream_t s) {
   char* base = static_cast<char*>(ws);
   hipError_t e;
   if (!P->rows.empty()) {
@@ -862,7 +969,17 @@ msm_status msm_workspace_init(const msm_plan* P, void* ws, size_t ws_bytes, msm_
   // pageable-memory copies are staged before returning; the plan may be destroyed afterwards
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "workspace init");
-  M->ready.insert(ws);
+  return MSM_OK;
+}
+
+extern "C" {
+
+msm_status msm_workspace_init(const msm_plan* P, void* ws, size_t ws_bytes, msm_stream_t stream) {
+  if (!P) return fail(MSM_ERR_INVALID_ARG, "null plan");
+  if (!ws || ws_bytes < P->lay.total) return fail(MSM_ERR_WORKSPACE, "workspace missing or too small");
+  const msm_status st = init_workspace(P, ws, reinterpret_cast<hipStream_t>(stream));
+  if (st != MSM_OK) return st;
+  const_cast<msm_plan*>(P)->ready.insert(ws);
   return MSM_OK;
 }
 
@@ -921,6 +1038,7 @@ msm_status msm_energy(const msm_plan* P, void* ws, size_t ws_bytes, msm_stream_t
                       const float* x, const float* y, const float* z, const float* q,
                       double* energy) {
   if (!energy) return fail(MSM_ERR_INVALID_ARG, "null energy output");
+  if (P && P->g.pair) return fail(MSM_ERR_UNSUPPORTED, "msm_energy is for multilevel-summation plans");
   return eval_mode(msm::kModeEnergy, P, ws, ws_bytes, stream, x, y, z, q, nullptr, nullptr, nullptr,
                    nullptr, energy, nullptr);
 }
@@ -930,6 +1048,7 @@ msm_status msm_backward(const msm_plan* P, void* ws, size_t ws_bytes, msm_stream
                         const double* grad_energy, float* dedx, float* dedy, float* dedz,
                         float* dedq) {
   if (!grad_energy) return fail(MSM_ERR_INVALID_ARG, "null grad_energy");
+  if (P && P->g.pair) return fail(MSM_ERR_UNSUPPORTED, "msm_backward is for multilevel-summation plans");
   return eval_mode(msm::kModeGradient, P, ws, ws_bytes, stream, x, y, z, q, dedx, dedy, dedz, dedq,
                    nullptr, grad_energy);
 }
@@ -959,11 +1078,13 @@ msm_status msm_graph_capture(const msm_plan* P, void* ws, size_t ws_bytes, const
       [&](hipStream_t cs) {
         return msm::launch_eval(msm::kModeForces, L, cs, io, nullptr, &M->aux.cc);
       },
-      out);
+      &M->tune_gen, out);
 }
 
 msm_status msm_graph_launch(const msm_graph* G, msm_stream_t stream) {
   if (!G || !G->exec) return fail(MSM_ERR_INVALID_ARG, "null graph");
+  if (G->owner_gen && *G->owner_gen != G->gen)
+    return fail(MSM_ERR_INVALID_ARG, "the plan or batch was re-tuned after this graph was captured");
   hipError_t e = hipGraphLaunch(G->exec, reinterpret_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "graph launch");
   return MSM_OK;

@@ -18,7 +18,7 @@ namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-constexpr int kNumStages = 13 + msm::kMaxLevels;
+constexpr int kNumStages = 15 + msm::kMaxLevels;
 
 }  // namespace
 
@@ -38,6 +38,7 @@ struct msm_batch {
   std::vector<int2> map[kNumStages];
   msm::LaunchGeom lg;                      // pointers set per workspace
   std::set<const void*> ready;
+  uint64_t tune_gen = 0;                   // bumped by every tuning change (graphs record it)
   AuxStreams aux;
 };
 
@@ -46,7 +47,7 @@ namespace {
 // Stage order inside the map arrays.
 enum : int {
   kMZero = 0, kMAtoms, kMBin, kMOne, kMShort, kMAnterp, kMLattice0, kMLattice, kMLatticeAll, kMTop, kMEnergy,
-  kMProlong, kMBinRow,
+  kMProlong, kMBinRow, kMScan, kMAGather,
   kMRestrict0
 };
 
@@ -65,6 +66,8 @@ msm::StageGrid* stage_of(msm::LaunchGeom& L, int st) {
     case kMEnergy: return &L.energy;
     case kMProlong: return &L.prolong;
     case kMBinRow: return &L.binrow;
+    case kMScan: return &L.scan;
+    case kMAGather: return &L.agather;
     default: return &L.restrict_[st - kMRestrict0];
   }
 }
@@ -84,6 +87,8 @@ int blocks_of(const msm::SysBlocks& b, int st) {
     case kMEnergy: return b.energy;
     case kMProlong: return b.prolong;
     case kMBinRow: return b.binrow;
+    case kMScan: return b.scan;
+    case kMAGather: return b.agather;
     default: return b.restrict_[st - kMRestrict0];
   }
 }
@@ -105,6 +110,7 @@ void rebuild_maps(msm_batch* Bt) {
     const msm_plan* P = Bt->plans[s];
     if (P->g.bin_blocks == 0 && P->g.bin_row_blocks == 0) L.bin4 = true;
     L.binrow_lds = std::max(L.binrow_lds, msm::bin_rows_lds(P->g));
+    L.anterp_lds = std::max(L.anterp_lds, msm::anterp_lds(P->g));
     L.max_levels = std::max(L.max_levels, P->g.levels);
     L.lat_b = std::max(L.lat_b, P->lat.b);
     L.lat_lds = std::max(L.lat_lds, P->lat.lds_bytes);
@@ -200,15 +206,18 @@ msm_status msm_batch_create(const msm_params* params, const int32_t* n_atoms, in
   // one-kernel binning walks all of a system's atoms in every block, which
   // pays for a single system's latency but not when many systems fill the GPU
   if (n_sys > 1)
-    for (msm_plan* P : Bt->plans)
-      if (P->g.bin_row_blocks > 0 && P->bin2_blocks > 0) {
-        P->g.bin_row_blocks = 0;
-        P->g.bin_blocks = P->bin2_blocks;
-        refresh_launch(P);
-      }
+    for (msm_plan* P : Bt->plans) {
+      P->prefer_bin2 = true;
+      set_cell_geometry(P, P->g.reach);
+      refresh_launch(P);
+    }
   const msm_plan* P0 = Bt->plans[0];
   bool tiled = P0->lat.b > 0 || P0->g.levels == 1;
   for (const msm_plan* P : Bt->plans) {
+    if (P->g.pair) {
+      msm_batch_destroy(Bt);
+      return fail(MSM_ERR_UNSUPPORTED, "batches hold multilevel-summation systems only");
+    }
     if (P->g.order != P0->g.order || P->g.m != P0->g.m) {
       msm_batch_destroy(Bt);
       return fail(MSM_ERR_UNSUPPORTED, "systems of a batch must share order and split_m");
@@ -224,7 +233,7 @@ msm_status msm_batch_create(const msm_params* params, const int32_t* n_atoms, in
   for (int s = 1; s < n_sys; ++s)
     if (n_atoms[s] > n_atoms[big]) big = s;
   const int b0 = Bt->plans[big]->lat.b;
-  for (msm_plan* P : Bt->plans) retune(P, msm_tuning{b0, 0, 0, 0, 0, {}});
+  for (msm_plan* P : Bt->plans) retune(P, msm_tuning{b0, 0, 0, 0, 0, 0, 0, 0});
 
   // stage-table reserves: the most blocks any tuning can ask for
   // (lattice template 4, one cell per short-range work item)
@@ -232,17 +241,20 @@ msm_status msm_batch_create(const msm_params* params, const int32_t* n_atoms, in
   for (msm_plan* P : Bt->plans) {
     const Geom keep_g = P->g;
     const msm::LatLaunch keep_l = P->lat;
-    const int keep_cap = P->short_cap;
+    const int keep_cap = P->short_cap, keep_bin2 = P->bin2_blocks;
     size_t most[kNumStages] = {};
-    for (int b : {4, 6, 8})
-      for (int w : {1, keep_g.item_chunks}) {
-        retune(P, msm_tuning{P->lat.b ? b : 0, w, -1, 0, 0, {}});   // one short-range block per item: the most
-        const msm::SysBlocks sb = msm::system_blocks(P->g, P->lat, P->n_partials);
-        for (int st = 0; st < kNumStages; ++st) most[st] = std::max(most[st], (size_t)blocks_of(sb, st));
-      }
+    for (int r : {2, 3, 4})
+      for (int b : {4, 6, 8})
+        for (int w : {1, keep_g.item_chunks}) {
+          // one short-range block per item: the most
+          retune(P, msm_tuning{P->lat.b ? b : 0, w, -1, 0, 0, 0, r, 0});
+          const msm::SysBlocks sb = msm::system_blocks(P->g, P->lat, P->n_partials);
+          for (int st = 0; st < kNumStages; ++st) most[st] = std::max(most[st], (size_t)blocks_of(sb, st));
+        }
     P->g = keep_g;
     P->lat = keep_l;
     P->short_cap = keep_cap;
+    P->bin2_blocks = keep_bin2;
     refresh_launch(P);
     for (int st = 0; st < kNumStages; ++st) cap[st] += most[st];
   }
@@ -311,7 +323,7 @@ static msm_status batch_eval(int mode, const msm_batch* Bt, void* ws, size_t ws_
         [&](hipStream_t cs) {
           return msm::launch_eval(mode, L, cs, io, nullptr, &M->aux.cc);
         },
-        graph);
+        &M->tune_gen, graph);
   e = msm::launch_eval(mode, L, reinterpret_cast<hipStream_t>(stream), io, nullptr, &M->aux.cc);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return MSM_OK;
@@ -403,7 +415,7 @@ msm_status msm_batch_describe(const msm_batch* Bt, char* buf, size_t buf_bytes) 
 msm_status msm_plan_tuning(const msm_plan* P, msm_tuning* t) {
   if (!P || !t) return fail(MSM_ERR_INVALID_ARG, "null plan or tuning");
   *t = msm_tuning{P->lat.b, P->g.item_chunks, P->short_cap > 0 ? P->short_cap : -1, P->streams,
-                  P->short_after, P->short_split, {}};
+                  P->short_after, P->short_split, P->g.reach, 0};
   return MSM_OK;
 }
 
@@ -415,6 +427,7 @@ msm_status msm_plan_tune(msm_plan* P, void* ws, size_t ws_bytes, msm_stream_t st
   if (!ws || ws_bytes < P->lay.total || !P->ready.count(ws))
     return fail(MSM_ERR_WORKSPACE, "workspace not initialised for this plan");
   retune(P, *t);
+  ++P->tune_gen;
   P->desc.d = dev_ptrs(P, ws);
   // other workspaces now hold stale descriptors
   P->ready.clear();
@@ -434,6 +447,7 @@ msm_status msm_batch_tune(msm_batch* Bt, void* ws, size_t ws_bytes, msm_stream_t
   st = check_tuning(t);
   if (st != MSM_OK) return st;
   for (msm_plan* P : Bt->plans) retune(P, *t);
+  ++Bt->tune_gen;
   rebuild_maps(Bt);
   Bt->ready.clear();
   st = upload_tables(Bt, ws, reinterpret_cast<hipStream_t>(stream));
@@ -444,11 +458,12 @@ msm_status msm_batch_tune(msm_batch* Bt, void* ws, size_t ws_bytes, msm_stream_t
 
 // Time candidates over `trials` evaluations of the given inputs with HIP
 // events on `stream`: lattice_b in {4, 6, 8} x item_chunks in {1, 2, 3} x the
-// two side-stream layouts with one short-range block per work item, then the
-// stream layouts x short-range block counts for the best pair, then where the
-// side short range starts, the chunks again, and how much of the short range
-// waits for the lattice cutoff.  Apply
-// the fastest and describe the search in `report` (JSON, nullable).
+// two side-stream layouts with one short-range block per work item (at the
+// current cell reach), then the cell reach (2, 3, 4), the stream layouts x
+// short-range block counts for the best so far, where the side short range
+// starts, the chunks again, and how much of the short range waits for the
+// lattice cutoff.  Apply the fastest and describe the search in `report`
+// (JSON, nullable).
 static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm_stream_t stream,
                            const float* x, const float* y, const float* z, const float* q,
                            int32_t trials, char* report, size_t report_bytes) {
@@ -461,8 +476,7 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
   msm_batch* Bt = batch ? static_cast<msm_batch*>(obj) : nullptr;
   msm_plan* P = batch ? nullptr : static_cast<msm_plan*>(obj);
   const bool tiled = batch ? Bt->lg.lat_b > 0 : P->lat.b > 0;
-  auto tune = [&](int b, int w, int c, int n, int sa, int sp) {
-    const msm_tuning t{b, w, c, n, sa, sp, {}};
+  auto tune = [&](const msm_tuning& t) {
     return batch ? msm_batch_tune(Bt, ws, ws_bytes, stream, &t) : msm_plan_tune(P, ws, ws_bytes, stream, &t);
   };
   auto eval = [&]() {
@@ -471,37 +485,43 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
                  : msm_compute(P, ws, ws_bytes, stream, x, y, z, q, nullptr, nullptr, nullptr, nullptr,
                                nullptr, nullptr);
   };
+  auto describe = [](const msm_tuning& t) {
+    return "\"lattice_b\": " + std::to_string(t.lattice_b) + ", \"item_chunks\": " + std::to_string(t.item_chunks) +
+           ", \"short_blocks\": " + std::to_string(t.short_blocks) + ", \"streams\": " +
+           std::to_string(t.streams) + ", \"short_after\": " + std::to_string(t.short_after) +
+           ", \"short_split\": " + std::to_string(t.short_split) + ", \"cell_reach\": " +
+           std::to_string(t.cell_reach);
+  };
+  msm_tuning cur{};
+  if (batch) {
+    (void)msm_plan_tuning(Bt->plans[0], &cur);
+  } else {
+    (void)msm_plan_tuning(P, &cur);
+  }
   std::string rep = "{\"candidates\": [";
   float best = 1e30f;
-  int best_b = 0, best_w = 0, best_c = 0, best_n = 0, best_sa = 1, best_sp = 1000;
+  msm_tuning bt{0, 0, 0, 0, 1, 1000, cur.cell_reach, 0};
   bool first = true;
-  auto time_one = [&](int b, int w, int c, int n, int sa, int sp, float& ms) {
-    msm_status st = tune(b, w, c, n, sa, sp);
+  auto time_one = [&](const msm_tuning& t) {
+    msm_status st = tune(t);
     // one warm-up evaluation, then `trials` timed ones
-    for (int t = -1; t < trials && st == MSM_OK; ++t) {
-      if (t == 0) (void)hipEventRecord(e0, s);
+    for (int k = -1; k < trials && st == MSM_OK; ++k) {
+      if (k == 0) (void)hipEventRecord(e0, s);
       st = eval();
     }
     if (st != MSM_OK) return st;
     (void)hipEventRecord(e1, s);
+    float ms = 0.f;
     hipError_t r = hipEventSynchronize(e1);
     if (r == hipSuccess) r = hipEventElapsedTime(&ms, e0, e1);
     if (r != hipSuccess) return hip_fail(r, "time candidate");
     ms /= trials;
-    rep += std::string(first ? "" : ", ") + "{\"lattice_b\": " + std::to_string(b) + ", \"item_chunks\": " +
-           std::to_string(w) + ", \"short_blocks\": " + std::to_string(c) + ", \"streams\": " +
-           std::to_string(n) + ", \"short_after\": " + std::to_string(sa) + ", \"short_split\": " +
-           std::to_string(sp) + ", \"ms\": " + std::to_string(ms) + "}";
+    rep += std::string(first ? "" : ", ") + "{" + describe(t) + ", \"ms\": " + std::to_string(ms) + "}";
     first = false;
     // a later (more elaborate) candidate must win by more than 1% (timing noise)
     if (ms < best * 0.99f) {
       best = ms;
-      best_b = b;
-      best_w = w;
-      best_c = c;
-      best_n = n;
-      best_sa = sa;
-      best_sp = sp;
+      bt = t;
     }
     return MSM_OK;
   };
@@ -511,14 +531,18 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
   // on the layout)
   for (int n : {3, 2})
     for (int b : bs)
-      for (int w : {1, 2, 3}) {
-        float ms = 0.f;
-        if (st == MSM_OK) st = time_one(b, w, -1, n, 1, 1000, ms);
-      }
-  // stream layouts x short-range block counts for the best (B, chunks); the
-  // counts are fractions of the compute units, so the short-range pass leaves
-  // room for the grid chain running beside it
-  const int bb = best_b, bw = best_w;
+      for (int w : {1, 2, 3})
+        if (st == MSM_OK) st = time_one(msm_tuning{b, w, -1, n, 1, 1000, cur.cell_reach, 0});
+  // cell reach for the best (B, chunks, layout)
+  for (int r : {2, 3, 4})
+    if (st == MSM_OK && r != bt.cell_reach) {
+      msm_tuning t = bt;
+      t.cell_reach = r;
+      st = time_one(t);
+    }
+  // stream layouts x short-range block counts for the best so far; the counts
+  // are fractions of the compute units, so the short-range pass leaves room
+  // for the grid chain running beside it
   int n_cu = 256;
   {
     int dev = 0;
@@ -526,44 +550,54 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
       n_cu = prop.multiProcessorCount;
   }
-  for (int n : {1, 2, 3})
-    for (int c : {-1, 3 * n_cu / 2, n_cu, 3 * n_cu / 4, n_cu / 2})
-      if (st == MSM_OK && !(n == 3 && c == -1)) {
-        float ms = 0.f;
-        st = time_one(bb, bw, c, n, 1, 1000, ms);
-      }
+  {
+    const msm_tuning base = bt;
+    for (int n : {1, 2, 3})
+      for (int c : {-1, 3 * n_cu / 2, n_cu, 3 * n_cu / 4, n_cu / 2})
+        if (st == MSM_OK && !(n == 3 && c == -1) && !(n == base.streams && c == base.short_blocks)) {
+          msm_tuning t = base;
+          t.streams = n;
+          t.short_blocks = c;
+          st = time_one(t);
+        }
+  }
   // where the side-stream short range starts, for the best layout so far
-  const int bc = best_c, bn = best_n;
-  if (bn >= 2)
+  if (bt.streams >= 2) {
+    const msm_tuning base = bt;
     for (int sa : {2, 3})
       if (st == MSM_OK) {
-        float ms = 0.f;
-        st = time_one(bb, bw, bc, bn, sa, 1000, ms);
+        msm_tuning t = base;
+        t.short_after = sa;
+        st = time_one(t);
       }
+  }
   // chunks per short-range item again, for the best layout and start (the
   // first pass chose them with every stream on)
-  const int bsa = best_sa, bc2 = best_c, bn2 = best_n;
-  for (int w : {1, 2, 3})
-    if (st == MSM_OK && w != bw) {
-      float ms = 0.f;
-      st = time_one(bb, w, bc2, bn2, bsa, 1000, ms);
-    }
+  {
+    const msm_tuning base = bt;
+    for (int w : {1, 2, 3})
+      if (st == MSM_OK && w != base.item_chunks) {
+        msm_tuning t = base;
+        t.item_chunks = w;
+        st = time_one(t);
+      }
+  }
   // part of the short range after the lattice cutoff, for the best start
-  if (bn2 >= 2 && bsa < 3)
+  if (bt.streams >= 2 && bt.short_after < 3) {
+    const msm_tuning base = bt;
     for (int sp : {300, 500, 700})
       if (st == MSM_OK) {
-        float ms = 0.f;
-        st = time_one(bb, best_w, bc2, bn2, bsa, sp, ms);
+        msm_tuning t = base;
+        t.short_split = sp;
+        st = time_one(t);
       }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != MSM_OK) return st;
-  st = tune(best_b, best_w, best_c, best_n, best_sa, best_sp);
+  st = tune(bt);
   if (st != MSM_OK) return st;
-  rep += "], \"best\": {\"lattice_b\": " + std::to_string(best_b) + ", \"item_chunks\": " +
-         std::to_string(best_w) + ", \"short_blocks\": " + std::to_string(best_c) + ", \"streams\": " +
-         std::to_string(best_n) + ", \"short_after\": " + std::to_string(best_sa) + ", \"short_split\": " +
-         std::to_string(best_sp) + ", \"ms\": " + std::to_string(best) + "}}";
+  rep += "], \"best\": {" + describe(bt) + ", \"ms\": " + std::to_string(best) + "}}";
   if (report && report_bytes) {
     std::strncpy(report, rep.c_str(), report_bytes - 1);
     report[report_bytes - 1] = 0;

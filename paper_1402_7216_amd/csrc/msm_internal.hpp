@@ -25,8 +25,13 @@ constexpr int kBinRowAtoms = 32768;       // atoms per system at most for the on
 constexpr int kBinRowCells = 512;         // cells one block of the one-kernel binning owns at most
 constexpr int kBinRowMaxBlocks = 256;     // blocks of the one-kernel binning per system at most
 constexpr int kStatusWords = 64 + kBinRowMaxBlocks;   // [0]: flags; [64 + b]: flags of binning block b
+constexpr int kScanTile = 4096;           // cells per block of the four-kernel binning's scan
 
 enum DeviceFlag : int { kFlagOutOfBox = 1, kFlagNonFinite = 2, kFlagCoincident = 4 };
+
+// Pair function of the short-range pass: the MSM short-range kernel g*, or one
+// of the cheap pair methods evaluated on their own (values of msm_pair_kind).
+enum PairKind : int { kPairMsm = 0, kPairCutoff = 1, kPairShiftedForce = 2, kPairWolf = 3 };
 
 struct Level {
   int lo[3];     // lowest node index per dimension
@@ -67,6 +72,11 @@ struct Geom {
   float dcoef[8];                  // 2 k c_k / a^3   (gamma'(rho)/(a^2 r) = sum_{k>=1} dcoef[k] s^{k-1})
   float gr[8];                     // c_k / a^(2k+1)       (gamma(r/a)/a as a polynomial in r^2)
   float dr[8];                     // 2 k c_k / a^(2k+1)   (gamma'(r/a)/(a^2 r) = sum_{k>=1} dr[k] r^2(k-1))
+  int at[3];                       // anterpolation node tile (level-0 nodes per dimension)
+  int atn[3];                      // anterpolation tiles per dimension (they own floor indices 0..fmax)
+  int at_ext;                      // nodes of a tile's private region (at[d] + order - 1 per dimension)
+  int pair;                        // 0: MSM; else the cheap pair method evaluated alone (kPair*)
+  float pk[4];                     // constants of the pair method (see k_short)
   int m;                           // smoothing degree
   float self;                      // gamma(0) / a
   double ke;                       // energy prefactor
@@ -126,6 +136,8 @@ enum Section : int {
   kSecCellOf,         // int[n]
   kSecTmp,            // int[n]
   kSecBinHist,        // int[bin_blocks * n_cells]: per-block cell counts (two-kernel binning)
+  kSecScan,           // int[scan tiles]: cell counts per tile of the four-kernel binning's scan
+  kSecAntPart,        // int64[anterpolation tiles * at_ext]: fixed-point private regions of the tiles
   kSecRows,           // StencilRow[n_rows]
   kSecWeights,        // float[n_weights]
   kSecRowsC,          // int4[n_rows]: compact rows (nz, ny >= 0, xr, weight offset)
@@ -167,6 +179,8 @@ struct DevPtrs {
   MSM_GLOBAL int* cell_of;
   MSM_GLOBAL int* tmp;
   MSM_GLOBAL int* bin_hist;
+  MSM_GLOBAL int* scan;
+  MSM_GLOBAL long long* ant_part;
   MSM_GLOBAL const StencilRow* rows;
   MSM_GLOBAL const int4* rows_c;
   MSM_GLOBAL const float* weights_c;
@@ -184,7 +198,7 @@ enum Stage : int {
 
 // Everything one system's kernels read, resident in device memory (one entry
 // per system of a batch; a plain plan has one).
-struct SysDesc {
+struct alignas(16) SysDesc {
   Geom g;
   DevPtrs d;
   LatLaunch lat;
@@ -241,6 +255,7 @@ struct LaunchGeom {
   int n_sys = 1;
   int order = 4;                     // common to every system of a launch
   int m = 2;
+  int pair = kPairMsm;               // pair method (common to every system of a launch)
   int lat_b = 0;                     // windowed lattice outputs per lane, 0 = untiled kernel
   int lat_lds = 0;                   // dynamic LDS of the windowed kernel
   int max_levels = 1;
@@ -250,6 +265,9 @@ struct LaunchGeom {
   int short_split = 1000;            // per mille of its work items started there (the rest after the
                                      // lattice cutoff)
   StageGrid zero, atoms, one, shortr, anterp, top, energy;
+  StageGrid scan;                    // tiles of the four-kernel binning's cell-count scan
+  StageGrid agather;                 // level-0 nodes (gather of the anterpolation partials)
+  int anterp_lds = 0;                // dynamic LDS of the anterpolation (largest system)
   StageGrid bin;                     // two-kernel binning (systems with bin_blocks > 0)
   StageGrid binrow;                  // one-kernel binning (systems with bin_row_blocks > 0)
   int binrow_lds = 0;                // dynamic LDS of the one-kernel binning (largest system)
@@ -263,7 +281,8 @@ struct LaunchGeom {
 
 // Per-stage block counts of one system.
 struct SysBlocks {
-  int zero, atoms, bin, binrow, shortr, anterp, lattice0, lattice, lattice_all, top, energy;
+  int zero, atoms, bin, binrow, shortr, anterp, lattice0, lattice, lattice_all, top, energy, scan;
+  int agather;
   int restrict_[kMaxLevels];
   int prolong;                       // tiles of every level below the top
 };
@@ -278,6 +297,10 @@ inline int bin_rows_lds(const Geom& g) {
   const int chunks = (g.n_atoms + 63) / 64;
   return 16 * own * 4 + 2 * 16 * 4 + chunks * 64 * 2;
 }
+
+// Dynamic LDS of the anterpolation of one system: its tile's private region
+// as 64-bit fixed-point accumulators.
+inline int anterp_lds(const Geom& g) { return g.at_ext * 8; }
 
 // What one evaluation produces.
 enum Mode : int {

@@ -171,40 +171,87 @@ __global__ void k_bin_count(KArgs A) {
   atomicAdd(&S.d.counts[c], 1);
 }
 
-// Exclusive scan of counts[0..n) into start[0..n] by one block of 1024
-// threads; then clears counts, cursors and the status word for this call.
-__global__ void __launch_bounds__(1024) k_scan(KArgs A) {
+// Exclusive scan of counts[0..n) into start[0..n] in two launches over tiles
+// of kScanTile cells (1024 threads, 4 cells each): k_scan_tiles writes each
+// tile's total; k_scan_apply adds the totals of the earlier tiles (a fixed-
+// order block sum), scans its tile, writes start[], and clears the counts and
+// cursors (and, block 0, the status words) for this call.
+constexpr int kScanThreads = kScanTile / 4;
+
+// Block-wide sum of one int per thread (wave butterflies, then the waves in order).
+__device__ __forceinline__ int block_sum_1024(int v, int* red) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  int t = 0;
+#pragma unroll
+  for (int w = 0; w < kScanThreads / kWave; ++w) t += red[w];
+  return t;
+}
+
+__device__ __forceinline__ int4 load_counts4(const int* counts, int c, int n) {
+  if (c + 3 < n) return *reinterpret_cast<const int4*>(counts + c);
+  int4 v = make_int4(0, 0, 0, 0);
+  if (c < n) v.x = counts[c];
+  if (c + 1 < n) v.y = counts[c + 1];
+  if (c + 2 < n) v.z = counts[c + 2];
+  return v;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(KArgs A) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
+  if (S.g.bin_blocks || S.g.bin_row_blocks) return;  // binned by another path
+  __shared__ int red[kScanThreads / kWave];
+  const int n = S.g.n_cells;
+  const int4 v = load_counts4(S.d.counts, blk * kScanTile + 4 * (int)threadIdx.x, n);
+  const int t = block_sum_1024(v.x + v.y + v.z + v.w, red);
+  if (threadIdx.x == 0) S.d.scan[blk] = t;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_apply(KArgs A) {
+  int blk;
+  const SysDesc& S = sys_of(A, blk);
+  if (S.g.bin_blocks || S.g.bin_row_blocks) return;
+  __shared__ int red[kScanThreads / kWave];
+  __shared__ int wsum[kScanThreads / kWave];
   int* __restrict__ counts = S.d.counts;
   int* __restrict__ start = S.d.cell_start;
   int* __restrict__ cursor = S.d.cursor;
-  int* __restrict__ status = S.d.status;
   const int n = S.g.n_cells;
-  if (S.g.bin_blocks || S.g.bin_row_blocks) return;  // binned by another path
-  __shared__ int part[1024];
-  int t = threadIdx.x;
-  int chunk = (n + 1023) / 1024;
-  int b = t * chunk, e = min(b + chunk, n);
-  int s = 0;
-  for (int i = b; i < e; ++i) s += counts[i];
-  part[t] = s;
+  const int t = threadIdx.x;
+  const int c = blk * kScanTile + 4 * t;
+  const int4 v = load_counts4(counts, c, n);
+  int before = 0;
+  for (int b = t; b < blk; b += kScanThreads) before += S.d.scan[b];
+  const int offset = block_sum_1024(before, red);
+  // exclusive scan of the thread sums: within the wave, then over the waves
+  const int own = v.x + v.y + v.z + v.w;
+  const int lane = t & (kWave - 1), wv = t / kWave;
+  int inc = own;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int u = __shfl_up(inc, off);
+    if (lane >= off) inc += u;
+  }
+  if (lane == kWave - 1) wsum[wv] = inc;
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    int v = (t >= off) ? part[t - off] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  int run = part[t] - s;
-  for (int i = b; i < e; ++i) {
-    start[i] = run;
-    run += counts[i];
-    counts[i] = 0;
-    cursor[i] = 0;
-  }
-  if (t == 1023) start[n] = part[1023];
-  if (t < 64) status[t] = 0;
+  int run = offset + inc - own;
+  for (int w = 0; w < wv; ++w) run += wsum[w];
+  const int e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (c + u < n) {
+      start[c + u] = run;
+      run += e[u];
+      counts[c + u] = 0;
+      cursor[c + u] = 0;
+    }
+  if (c < n && c + 4 >= n) start[n] = run;           // the thread holding the last cell
+  if (blk == 0 && t < 64) S.d.status[t] = 0;
 }
 
 // Scatter into cell segments in arrival order (atomic cursors); the atom's
@@ -751,7 +798,14 @@ __device__ __forceinline__ int wave_max(int v) {
 }
 
 // A launch takes the work items [n lo_pm / 1000, n hi_pm / 1000) of each system.
-template <int M, bool FORCES>
+// KIND selects the pair function: the MSM short-range kernel g* (gamma of
+// degree M), or a cheap pair method on its own with e(r) and -e'(r)/r
+//   plain cutoff     e = 1/r                                -e'/r = 1/r^3
+//   shifted force    e = 1/r + r pk1 - 2 pk0                -e'/r = (1/r^2 - pk1)/r
+//                    (pk0 = 1/rc, pk1 = 1/rc^2)
+//   Wolf             e = erfc(pk0 r)/r - pk1                -e'/r = (erfc(pk0 r)/r + pk2 exp(-pk3 r^2))/r^2
+//                    (pk0 = alpha, pk1 = erfc(alpha rc)/rc, pk2 = 2 alpha/sqrt(pi), pk3 = alpha^2)
+template <int M, bool FORCES, int KIND>
 // Two blocks per CU: 8 waves per SIMD, so at most 64 registers per lane.
 __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, int hi_pm) {
   int blk;
@@ -780,6 +834,13 @@ __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, 
     asm volatile("v_mov_b32 %0, %1" : "=v"(dv) : "s"(g.dr[k]));
     gc[k] = gv;
     dc[k] = dv;
+  }
+  float pk[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    float v;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(g.pk[k]));
+    pk[k] = v;
   }
   float4* jb = jbuf[wave];
   if (lane < 4) jb[kShortSeg + lane] = make_float4(3e30f, 3e30f, 3e30f, 0.f);
@@ -857,19 +918,41 @@ __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, 
                 // instruction's error is biased, which would bias the energy)
                 float ri = __builtin_amdgcn_rsqf(r2);
                 ri = fmaf(0.5f * ri, fmaf(-r2 * ri, ri, 1.f), ri);
-                // gamma(r/a)/a and gamma'(r/a)/(a^2 r) as polynomials in r^2
-                float gm = gc[M], dg = dc[M];
-#pragma unroll
-                for (int k = M - 1; k >= 0; --k) gm = fmaf(gm, r2, gc[k]);
-#pragma unroll
-                for (int k = M - 1; k >= 1; --k) dg = fmaf(dg, r2, dc[k]);
                 const float qj = pj[v].w;
-                ap = fmaf(qj, ri - gm, ap);                     // q_j g*(r)
-                if (FORCES) {
-                  const float wq = qj * fmaf(ri, ri * ri, dg);  // q_j (-g*'(r)/r)
-                  ax = fmaf(wq, dx, ax);
-                  ay = fmaf(wq, dy, ay);
-                  az = fmaf(wq, dz, az);
+                if (KIND == kPairMsm) {
+                  // gamma(r/a)/a and gamma'(r/a)/(a^2 r) as polynomials in r^2
+                  float gm = gc[M], dg = dc[M];
+#pragma unroll
+                  for (int k = M - 1; k >= 0; --k) gm = fmaf(gm, r2, gc[k]);
+#pragma unroll
+                  for (int k = M - 1; k >= 1; --k) dg = fmaf(dg, r2, dc[k]);
+                  ap = fmaf(qj, ri - gm, ap);                     // q_j g*(r)
+                  if (FORCES) {
+                    const float wq = qj * fmaf(ri, ri * ri, dg);  // q_j (-g*'(r)/r)
+                    ax = fmaf(wq, dx, ax);
+                    ay = fmaf(wq, dy, ay);
+                    az = fmaf(wq, dz, az);
+                  }
+                } else {
+                  float e, fr;                                     // e(r), -e'(r)/r
+                  if (KIND == kPairCutoff) {
+                    e = ri;
+                    fr = ri * ri * ri;
+                  } else if (KIND == kPairShiftedForce) {
+                    e = ri + fmaf(r2 * ri, pk[1], -2.f * pk[0]);
+                    fr = ri * fmaf(ri, ri, -pk[1]);
+                  } else {
+                    const float er = erfcf(pk[0] * (r2 * ri));
+                    e = fmaf(er, ri, -pk[1]);
+                    fr = ri * ri * fmaf(er, ri, pk[2] * expf(-pk[3] * r2));
+                  }
+                  ap = fmaf(qj, e, ap);
+                  if (FORCES) {
+                    const float wq = qj * fr;
+                    ax = fmaf(wq, dx, ax);
+                    ay = fmaf(wq, dy, ay);
+                    az = fmaf(wq, dz, az);
+                  }
                 }
               }
             }
@@ -902,59 +985,35 @@ __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, 
 
 // --------------------------------------------------------------------------
 // Anterpolation (itemised algorithm): q^0_mu = sum_j phi^0_mu(r_j) q_j.
-// One block owns an 8x8x8 tile of level-0 nodes.  Its threads walk the atoms
-// of the cells whose atoms can touch the tile; each atom computes its basis
-// weights once and adds q_j phi^0_mu(r_j) for the tile's nodes it touches into
-// LDS as 2^-36 fixed-point integers.  Integer addition is associative, so the
-// result does not depend on the order of the atomics.
+// An atom whose level-0 floor index is f touches the ORDER nodes f .. f +
+// ORDER - 1 (level-local indices) per dimension.  Block b owns a node tile
+// [n0, n0 + T) per dimension and processes exactly the atoms whose f lies in
+// it, so every atom is visited once; their contributions land in a private LDS
+// region of T + ORDER - 1 nodes per dimension as 2^-36 fixed-point integers
+// (integer sums do not depend on the order of the atomics, so the result is
+// bitwise reproducible).  The block writes its region as int64 partials and
+// k_anterp_gather adds, for every node, the partials of the (at most two per
+// dimension) tiles whose regions hold it, in tile order.
 // --------------------------------------------------------------------------
 constexpr double kFix = 68719476736.0;            // 2^36
 constexpr double kInvFix = 1.0 / 68719476736.0;
+constexpr int kAThreads = 256;
 
-constexpr int kAX = 8, kAY = 8, kAZ = 4;          // anterpolation tile (level-0 nodes)
-
-
-template <int ORDER>
-__device__ __forceinline__ void anterp_atom(const Geom& g, const int* n0, float4 p,
-                                            unsigned long long* acc) {
-  constexpr int H = ORDER / 2;
-  const float pp[3] = {p.x, p.y, p.z};
-  const int tdim[3] = {kAX, kAY, kAZ};
-  int base[3];
-  float w[3][ORDER], dw[3][ORDER];
-  bool touch = true;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    int f;
-    float off;
-    grid_coord(pp[d], g.lo_f[d], g.h, g.inv_h, g.fmax[d], f, off);
-    base[d] = f - (H - 1) - n0[d];            // tile-local index of the atom's first node
-    touch = touch && (base[d] + ORDER > 0) && (base[d] < tdim[d]);
-    basis<ORDER>(off, w[d], dw[d]);
+// round(v 2^36) as a 64-bit integer from float arithmetic: v 16 = hi + frac
+// with hi = floor(v 16) and frac in [0, 1) (both exact); frac 2^32 is exact
+// and rounded to the nearest integer (a carry when it rounds up to 2^32).
+// Valid for |v| < 2^27.
+__device__ __forceinline__ unsigned long long fixed36(float v) {
+  const float a = v * 16.f;
+  const float hi = floorf(a);
+  float lo = rintf((a - hi) * 4294967296.f);
+  int h = (int)hi;
+  if (lo >= 4294967296.f) {
+    lo = 0.f;
+    h += 1;
   }
-  if (!touch) return;
-#pragma unroll
-  for (int sz = 0; sz < ORDER; ++sz) {
-    const int lz = base[2] + sz;
-    if (lz < 0 || lz >= kAZ) continue;
-    const float qz = p.w * w[2][sz];
-#pragma unroll
-    for (int sy = 0; sy < ORDER; ++sy) {
-      const int ly = base[1] + sy;
-      if (ly < 0 || ly >= kAY) continue;
-      const float qyz = qz * w[1][sy];
-#pragma unroll
-      for (int sx = 0; sx < ORDER; ++sx) {
-        const int lx = base[0] + sx;
-        if (lx < 0 || lx >= kAX) continue;
-        const long long v = __double2ll_rn((double)(qyz * w[0][sx]) * kFix);
-        atomicAdd(&acc[(lz * kAY + ly) * kAX + lx], (unsigned long long)v);
-      }
-    }
-  }
+  return ((unsigned long long)(unsigned)h << 32) + (unsigned long long)(unsigned)lo;
 }
-
-constexpr int kAThreads = 1024;
 
 template <int ORDER>
 __global__ void __launch_bounds__(kAThreads) k_anterp(KArgs A) {
@@ -963,29 +1022,28 @@ __global__ void __launch_bounds__(kAThreads) k_anterp(KArgs A) {
   const Geom& g = S.g;
   const float4* __restrict__ sorted = S.d.sorted;
   const int* __restrict__ start = S.d.cell_start;
-  float* __restrict__ qgrid = S.d.qgrid;
-  constexpr int H = ORDER / 2;
-  __shared__ unsigned long long acc[kAX * kAY * kAZ];
+  extern __shared__ unsigned long long acc[];
   __shared__ int row_beg[64], row_pre[65];
-  const Level L = g.lv[0];
-  const int ntx = (L.n[0] + kAX - 1) / kAX, nty = (L.n[1] + kAY - 1) / kAY;
-  const int bx = blk % ntx, by = (blk / ntx) % nty, bz = blk / (ntx * nty);
-  const int n0[3] = {L.lo[0] + bx * kAX, L.lo[1] + by * kAY, L.lo[2] + bz * kAZ};
-  const int tdim[3] = {kAX, kAY, kAZ};
-  for (int i = threadIdx.x; i < kAX * kAY * kAZ; i += kAThreads) acc[i] = 0ull;
-  // atoms touching the tile have floor index f in [n0 - H, n0 + T - 1 + H - 1]:
-  // box-relative positions in [(n0 - H) h, (n0 + T - 1 + H) h)
+  const int T[3] = {g.at[0], g.at[1], g.at[2]};
+  const int ex = T[0] + ORDER - 1, ey = T[1] + ORDER - 1;
+  const int ext = g.at_ext;
+  const int bx = blk % g.atn[0], by = (blk / g.atn[0]) % g.atn[1], bz = blk / (g.atn[0] * g.atn[1]);
+  const int n0[3] = {bx * T[0], by * T[1], bz * T[2]};
+  for (int i = threadIdx.x; i < ext; i += kAThreads) acc[i] = 0ull;
+  // the tile's atoms lie at box-relative positions [n0 h, (n0 + T) h) (the
+  // last tile also takes atoms on the upper box face); candidate cells cover
+  // that range with a margin for the rounding of cell and floor indices
   int c0[3], c1[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const float xl = ((float)(n0[d] - H) - 0.01f) * g.h, xh = ((float)(n0[d] + tdim[d] - 1 + H) + 0.01f) * g.h;
+    const float xl = ((float)n0[d] - 0.01f) * g.h, xh = ((float)(n0[d] + T[d]) + 0.01f) * g.h;
     c0[d] = min(g.nc[d] - 1, max(0, (int)floorf(fmaxf(xl, 0.f) * g.inv_cs[d])));
     c1[d] = max(c0[d], min(g.nc[d] - 1, (int)floorf(fmaxf(xh, 0.f) * g.inv_cs[d])));
+    if (n0[d] + T[d] > g.fmax[d]) c1[d] = g.nc[d] - 1;
   }
   // candidate atoms: the contiguous sorted ranges of the cell rows in
   // [c0, c1], taken 64 rows at a time; prefix sums over a chunk's rows let
-  // every thread walk one flat index space (the next atom is loaded while the
-  // current one is processed)
+  // every thread walk one flat index space
   const int nry = c1[1] - c0[1] + 1, nrows = nry * (c1[2] - c0[2] + 1);
   for (int rc0 = 0; rc0 < nrows; rc0 += 64) {
     const int nr = min(64, nrows - rc0);
@@ -1011,38 +1069,72 @@ __global__ void __launch_bounds__(kAThreads) k_anterp(KArgs A) {
     __syncthreads();
     const int ncand = row_pre[nr];
     int row = 0;
-    int t = threadIdx.x;
-    float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (t < ncand) {
-      // last row with row_pre[row] <= t (binary search over the nr + 1 prefixes)
-      int lo = 0, hi = nr - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (row_pre[mid] <= t) lo = mid;
-        else hi = mid - 1;
+    for (int t = threadIdx.x; t < ncand; t += kAThreads) {
+      while (row_pre[row + 1] <= t) ++row;
+      const float4 p = sorted[row_beg[row] + (t - row_pre[row])];
+      const float pp[3] = {p.x, p.y, p.z};
+      int f[3];
+      float w[3][ORDER], dw[3][ORDER];
+      bool own = true;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        float r;
+        grid_coord(pp[d], g.lo_f[d], g.h, g.inv_h, g.fmax[d], f[d], r);
+        f[d] -= n0[d];
+        own = own && f[d] >= 0 && f[d] < T[d];
+        basis<ORDER>(r, w[d], dw[d]);
       }
-      row = lo;
-      nxt = sorted[row_beg[row] + (t - row_pre[row])];
-    }
-    while (t < ncand) {
-      const float4 p = nxt;
-      const int tn = t + kAThreads;
-      if (tn < ncand) {
-        while (row_pre[row + 1] <= tn) ++row;
-        nxt = sorted[row_beg[row] + (tn - row_pre[row])];
+      if (!own) continue;
+#pragma unroll
+      for (int sz = 0; sz < ORDER; ++sz) {
+        const float qz = p.w * w[2][sz];
+#pragma unroll
+        for (int sy = 0; sy < ORDER; ++sy) {
+          const float qyz = qz * w[1][sy];
+          unsigned long long* rowp = acc + ((f[2] + sz) * ey + (f[1] + sy)) * ex + f[0];
+#pragma unroll
+          for (int sx = 0; sx < ORDER; ++sx) atomicAdd(rowp + sx, fixed36(qyz * w[0][sx]));
+        }
       }
-      anterp_atom<ORDER>(g, n0, p, acc);
-      t = tn;
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kAX * kAY * kAZ; i += kAThreads) {
-    const int lx = i % kAX, ly = (i / kAX) % kAY, lz = i / (kAX * kAY);
-    const int gx = bx * kAX + lx, gy = by * kAY + ly, gz = bz * kAZ + lz;
-    if (gx < L.n[0] && gy < L.n[1] && gz < L.n[2])
-      qgrid[L.off + ((size_t)gz * L.n[1] + gy) * L.n[0] + gx] =
-          (float)((double)(long long)acc[i] * kInvFix);
+  long long* __restrict__ out = S.d.ant_part + (size_t)blk * ext;
+  for (int i = threadIdx.x; i < ext; i += kAThreads) out[i] = (long long)acc[i];
+}
+
+// q^0 of every level-0 node: the sum, in tile order, of the partials of the
+// tiles whose private regions hold the node.
+template <int ORDER>
+__global__ void __launch_bounds__(kBlock) k_anterp_gather(KArgs A) {
+  int blk;
+  const SysDesc& S = sys_of(A, blk);
+  const Geom& g = S.g;
+  const Level L = g.lv[0];
+  const int node = blk * kBlock + threadIdx.x;
+  if (node >= L.count) return;
+  const float inv_n0 = 1.f / (float)L.n[0], inv_n1 = 1.f / (float)L.n[1];
+  int m[3];
+  m[2] = fdiv(fdiv(node, L.n[0], inv_n0, m[0]), L.n[1], inv_n1, m[1]);
+  int t0[3], t1[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    // tiles t with t T <= m < (t + 1) T + ORDER - 1, clipped to the tiles that exist
+    t1[d] = min(m[d] / g.at[d], g.atn[d] - 1);
+    t0[d] = max(0, (m[d] - (ORDER - 1)) / g.at[d]);
+    if (m[d] < ORDER - 1) t0[d] = 0;
   }
+  const int ex = g.at[0] + ORDER - 1, ey = g.at[1] + ORDER - 1;
+  const long long* __restrict__ part = S.d.ant_part;
+  long long sum = 0;
+  for (int tz = t0[2]; tz <= t1[2]; ++tz)
+    for (int ty = t0[1]; ty <= t1[1]; ++ty)
+      for (int tx = t0[0]; tx <= t1[0]; ++tx) {
+        const int tile = (tz * g.atn[1] + ty) * g.atn[0] + tx;
+        const int lx = m[0] - tx * g.at[0], ly = m[1] - ty * g.at[1], lz = m[2] - tz * g.at[2];
+        sum += part[(size_t)tile * g.at_ext + (lz * ey + ly) * ex + lx];
+      }
+  S.d.qgrid[L.off + node] = (float)((double)sum * kInvFix);
 }
 
 // --------------------------------------------------------------------------
@@ -1740,6 +1832,35 @@ __global__ void __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(
   if (!(S.lat.b == 0 || k >= S.lat.n) && S.lat.t[k].groups > 1) S.d.ucut[F.off + (size_t)node] = own;
 }
 
+// Fixed-order block reduction of one energy and 9 virial values per thread
+// (butterfly within the wave, then the waves in order) into the block's slot
+// of the float64 partials (component t at t * n_partials + blk).
+__device__ __forceinline__ void block_partials(double e, const double* vir, double* partials, int n_partials,
+                                               int blk) {
+  __shared__ double red[10][kBlock / kWave];
+  double vals[10];
+  vals[0] = e;
+#pragma unroll
+  for (int t = 0; t < 9; ++t) vals[t + 1] = vir[t];
+#pragma unroll
+  for (int t = 0; t < 10; ++t) {
+    double v = vals[t];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    vals[t] = v;
+  }
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  if (lane == 0)
+#pragma unroll
+    for (int t = 0; t < 10; ++t) red[t][wave] = vals[t];
+  __syncthreads();
+  if (threadIdx.x < 10) {
+    double v = 0.0;
+    for (int w = 0; w < kBlock / kWave; ++w) v += red[threadIdx.x][w];
+    partials[(size_t)threadIdx.x * n_partials + blk] = v;
+  }
+}
+
 // --------------------------------------------------------------------------
 // Interpolation (itemised algorithm) and assembly (potential display, force as
 // minus gradient):  phi_i^L = sum_mu phi^0_mu(r_i) u^0_mu,  grad phi_i^L,
@@ -1766,7 +1887,6 @@ __global__ void __launch_bounds__(kBlock) k_interp(KArgs A) {
   const int n_partials = S.n_partials;
   const double* __restrict__ gscale = A.io.gscale ? A.io.gscale + S.index : nullptr;
   constexpr int H = ORDER / 2;
-  __shared__ double red[10][kBlock / kWave];
   const Level L = g.lv[0];
   int s = blk * blockDim.x + threadIdx.x;
   double e = 0.0, vir[9];
@@ -1826,48 +1946,68 @@ __global__ void __launch_bounds__(kBlock) k_interp(KArgs A) {
         fz[i] = (float)(-gsc * g.ke * ((double)fs.z - qd * (double)gz));
       }
       if (phi) phi[i] = (float)(gsc * ph);
-      return;
+    } else {
+      float ofx = (float)(g.ke * ((double)fs.x - qd * (double)gx));
+      float ofy = (float)(g.ke * ((double)fs.y - qd * (double)gy));
+      float ofz = (float)(g.ke * ((double)fs.z - qd * (double)gz));
+      int i = perm[s];
+      if (fx) {
+        fx[i] = ofx;
+        fy[i] = ofy;
+        fz[i] = ofz;
+      }
+      if (phi) phi[i] = (float)ph;
+      e = 0.5 * qd * ph;
+      double rr[3] = {(double)p.x - g.lo[0], (double)p.y - g.lo[1], (double)p.z - g.lo[2]};
+      double ff[3] = {(double)ofx, (double)ofy, (double)ofz};
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) vir[3 * a + b] = rr[a] * ff[b];
     }
-    float ofx = (float)(g.ke * ((double)fs.x - qd * (double)gx));
-    float ofy = (float)(g.ke * ((double)fs.y - qd * (double)gy));
-    float ofz = (float)(g.ke * ((double)fs.z - qd * (double)gz));
-    int i = perm[s];
+  }
+  // gradient mode has no reductions: every thread of the block leaves here
+  if (MODE == 1) return;
+  block_partials(e, vir, partials, n_partials, blk);
+}
+
+// Assembly of a cheap pair method evaluated on its own (no grids):
+//   phi_i = ke (phi_i^pair - q_i self),  F_i = ke F_i^pair,
+// with self = -2 s (s the method's self-energy coefficient), plus per-block
+// float64 partials of E = 1/2 sum q_i phi_i and W = sum (r_i - lo) F_i.
+__global__ void __launch_bounds__(kBlock) k_pair_finish(KArgs A) {
+  int blk;
+  const SysDesc& S = sys_of(A, blk);
+  const Geom& g = S.g;
+  float* __restrict__ fx = A.io.fx ? A.io.fx + S.atom_off : nullptr;
+  float* __restrict__ fy = A.io.fy ? A.io.fy + S.atom_off : nullptr;
+  float* __restrict__ fz = A.io.fz ? A.io.fz + S.atom_off : nullptr;
+  float* __restrict__ phi = A.io.phi ? A.io.phi + S.atom_off : nullptr;
+  const int s = blk * blockDim.x + threadIdx.x;
+  double e = 0.0, vir[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) vir[t] = 0.0;
+  if (s < g.n_atoms) {
+    const float4 p = S.d.sorted[s];
+    const float4 fs = S.d.fshort[s];
+    const int i = S.d.perm[s];
+    const double qd = (double)p.w;
+    const double ph = g.ke * ((double)fs.w - qd * (double)g.self);
+    const float of[3] = {(float)(g.ke * (double)fs.x), (float)(g.ke * (double)fs.y), (float)(g.ke * (double)fs.z)};
     if (fx) {
-      fx[i] = ofx;
-      fy[i] = ofy;
-      fz[i] = ofz;
+      fx[i] = of[0];
+      fy[i] = of[1];
+      fz[i] = of[2];
     }
     if (phi) phi[i] = (float)ph;
     e = 0.5 * qd * ph;
-    double rr[3] = {(double)p.x - g.lo[0], (double)p.y - g.lo[1], (double)p.z - g.lo[2]};
-    double ff[3] = {(double)ofx, (double)ofy, (double)ofz};
+    const double rr[3] = {(double)p.x - g.lo[0], (double)p.y - g.lo[1], (double)p.z - g.lo[2]};
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int b = 0; b < 3; ++b) vir[3 * a + b] = rr[a] * ff[b];
+      for (int b = 0; b < 3; ++b) vir[3 * a + b] = rr[a] * (double)of[b];
   }
-  // fixed-order block reduction: butterfly within the wave, then waves in order
-  double vals[10];
-  vals[0] = e;
-#pragma unroll
-  for (int t = 0; t < 9; ++t) vals[t + 1] = vir[t];
-#pragma unroll
-  for (int t = 0; t < 10; ++t) {
-    double v = vals[t];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-    vals[t] = v;
-  }
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  if (lane == 0)
-#pragma unroll
-    for (int t = 0; t < 10; ++t) red[t][wave] = vals[t];
-  __syncthreads();
-  if (threadIdx.x < 10) {
-    double v = 0.0;
-    for (int w = 0; w < kBlock / kWave; ++w) v += red[threadIdx.x][w];
-    partials[(size_t)threadIdx.x * n_partials + blk] = v;
-  }
+  block_partials(e, vir, S.d.partials, S.n_partials, blk);
 }
 
 // Energy without prolongation or interpolation (grid form):
@@ -1957,12 +2097,14 @@ int interp_partials(const Geom& g) { return std::max(1, blocks_for(g.n_atoms)); 
 SysBlocks system_blocks(const Geom& g, const LatLaunch& lat, int n_partials) {
   SysBlocks b{};
   b.zero = blocks_for(g.n_cells + 1);
+  b.scan = (g.bin_blocks == 0 && g.bin_row_blocks == 0) ? (g.n_cells + kScanTile - 1) / kScanTile : 0;
   b.atoms = g.n_atoms > 0 ? blocks_for(g.n_atoms) : 0;
   b.bin = g.bin_blocks;
   b.binrow = g.bin_row_blocks;
   b.shortr = g.n_atoms > 0 ? g.short_blocks : 0;
   const Level& L0 = g.lv[0];
-  b.anterp = ((L0.n[0] + kAX - 1) / kAX) * ((L0.n[1] + kAY - 1) / kAY) * ((L0.n[2] + kAZ - 1) / kAZ);
+  b.anterp = g.atn[0] * g.atn[1] * g.atn[2];
+  b.agather = blocks_for(L0.count);
   for (int k = 0; k + 1 < g.levels; ++k) {
     const Level& C = g.lv[k + 1];
     b.restrict_[k] = ((C.n[0] + kRX - 1) / kRX) * ((C.n[1] + kRY - 1) / kRY) * ((C.n[2] + kRZ - 1) / kRZ);
@@ -2018,7 +2160,8 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
   mark(kStageBin);
   if (L.bin4) {
     if (have_atoms) k_bin_count<<<L.atoms.blocks, kBlock, 0, s>>>(args(L.atoms));
-    k_scan<<<L.one.blocks, 1024, 0, s>>>(args(L.one));
+    k_scan_tiles<<<L.scan.blocks, kScanThreads, 0, s>>>(args(L.scan));
+    k_scan_apply<<<L.scan.blocks, kScanThreads, 0, s>>>(args(L.scan));
     if (have_atoms) {
       k_bin_scatter<<<L.atoms.blocks, kBlock, 0, s>>>(args(L.atoms));
       k_bin_place<<<L.atoms.blocks, kBlock, 0, s>>>(args(L.atoms));
@@ -2040,7 +2183,8 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
   // short-range pairs: on their own stream (forked after binning,
   // anterpolation or the coarse lattice cutoff), joined before interpolation
   mark(kStageShort);
-  const bool short_side = concurrent && L.streams >= 2 && have_atoms && L.shortr.blocks > 0;
+  const bool short_side =
+      concurrent && L.streams >= 2 && have_atoms && L.shortr.blocks > 0 && L.pair == kPairMsm;
   // with a side stream, the work items [0, split) start at short_after and the
   // rest after the lattice cutoff
   const int split = (short_side && L.short_split > 0 && L.short_split < 1000) ? L.short_split : 1000;
@@ -2053,13 +2197,20 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
     }
     const KArgs A = args(L.shortr);
     const int nb = L.shortr.blocks;
-#define MSM_SHORT(MM)                                                       \
-  do {                                                                      \
-    if (forces)                                                             \
-      k_short<MM, true><<<nb, kShortThreads, 0, ss>>>(A, lo_pm, hi_pm);     \
-    else                                                                    \
-      k_short<MM, false><<<nb, kShortThreads, 0, ss>>>(A, lo_pm, hi_pm);    \
+#define MSM_SHORT(MM)                                                          \
+  do {                                                                         \
+    if (forces)                                                                \
+      k_short<MM, true, kPairMsm><<<nb, kShortThreads, 0, ss>>>(A, lo_pm, hi_pm);  \
+    else                                                                       \
+      k_short<MM, false, kPairMsm><<<nb, kShortThreads, 0, ss>>>(A, lo_pm, hi_pm); \
   } while (0)
+    if (L.pair == kPairCutoff)
+      k_short<1, true, kPairCutoff><<<nb, kShortThreads, 0, ss>>>(A, lo_pm, hi_pm);
+    else if (L.pair == kPairShiftedForce)
+      k_short<1, true, kPairShiftedForce><<<nb, kShortThreads, 0, ss>>>(A, lo_pm, hi_pm);
+    else if (L.pair == kPairWolf)
+      k_short<1, true, kPairWolf><<<nb, kShortThreads, 0, ss>>>(A, lo_pm, hi_pm);
+    else
     switch (L.m) {
       case 1: MSM_SHORT(1); break;
       case 2: MSM_SHORT(2); break;
@@ -2075,11 +2226,26 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
   const int short_at = short_side ? L.short_after : 1;
   if (short_at == 1) launch_short(0, split);
 
+  if (L.pair != kPairMsm) {
+    // a cheap pair method on its own: no grids
+    for (int st = kStageAnterp; st <= kStageInterp; ++st) mark(st);
+    if (have_atoms) k_pair_finish<<<L.atoms.blocks, kBlock, 0, s>>>(args(L.atoms));
+    mark(kStageReduce);
+    if (io.energy || io.virial) k_reduce<<<L.one.blocks, kBlock, 0, s>>>(args(L.one), 1);
+    mark(kStageCount);
+    return hipGetLastError();
+  }
+
   mark(kStageAnterp);
-  if (L.order == 4)
-    k_anterp<4><<<L.anterp.blocks, kAThreads, 0, s>>>(args(L.anterp));
-  else
-    k_anterp<6><<<L.anterp.blocks, kAThreads, 0, s>>>(args(L.anterp));
+  if (L.order == 4) {
+    (void)hipFuncSetAttribute((const void*)k_anterp<4>, hipFuncAttributeMaxDynamicSharedMemorySize, L.anterp_lds);
+    k_anterp<4><<<L.anterp.blocks, kAThreads, L.anterp_lds, s>>>(args(L.anterp));
+    k_anterp_gather<4><<<L.agather.blocks, kBlock, 0, s>>>(args(L.agather));
+  } else {
+    (void)hipFuncSetAttribute((const void*)k_anterp<6>, hipFuncAttributeMaxDynamicSharedMemorySize, L.anterp_lds);
+    k_anterp<6><<<L.anterp.blocks, kAThreads, L.anterp_lds, s>>>(args(L.anterp));
+    k_anterp_gather<6><<<L.agather.blocks, kBlock, 0, s>>>(args(L.agather));
+  }
   if (short_at == 2) launch_short(0, split);
 
   // lattice cutoff of one part (0: level 0, 1: levels 1 .. l-2 and the top,

@@ -21,6 +21,7 @@ struct AuxStreams {
 
 struct msm_plan {
   msm_params p;
+  msm_pair_params pp{};                      // parameters of a pair-method plan (g.pair != 0)
   Geom g;
   std::vector<msm::StencilRow> rows;         // full stencil rows (untiled lattice kernel)
   std::vector<int4> rows_c;                  // compact rows of the windowed kernel
@@ -29,6 +30,9 @@ struct msm_plan {
   std::vector<double> top;                   // FP64 top-level kernel table
   int n_partials = 1;
   int bin2_blocks = 0;                       // blocks of the two-kernel binning where it is possible
+  bool prefer_bin2 = false;                  // two-kernel binning over one kernel where both work (batches)
+  int max_cells = 0;                         // link cells of the finest cell reach (sizes the cell sections)
+  long long max_bin_hist = 0;                // two-kernel histogram entries of any cell reach
   msm::LatLaunch lat;
   int lat_tables = 0;                        // LDS bytes of the compact stencil tables
   int lat_part_max = 0;                      // lattice row-group partials of the largest tuning
@@ -36,6 +40,8 @@ struct msm_plan {
   int streams = 3;                           // stream layout of an evaluation (msm_tuning.streams)
   int short_after = 1;                       // start of the side-stream short range (msm_tuning.short_after)
   int short_split = 1000;                    // per mille of it started there (msm_tuning.short_split)
+  uint64_t tune_gen = 0;                     // bumped by every tuning change (graphs record it)
+  uint64_t uid = 0;                          // unique over the process (never reused)
   Layout lay;
   msm::SysDesc desc;                         // host copy; device pointers filled per workspace
   msm::LaunchGeom lg;                        // stage grids of one evaluation (descriptor set per call)
@@ -46,9 +52,15 @@ struct msm_plan {
   AuxStreams aux;
 };
 
+// A captured evaluation.  Its launch grids, kernel templates and LDS sizes are
+// those of the tuning in effect at capture; `owner_gen` points at the tuning
+// generation of the plan or batch it was captured from, and a replay after a
+// tuning change is refused.
 struct msm_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  const uint64_t* owner_gen = nullptr;
+  uint64_t gen = 0;
 };
 
 msm_status fail(msm_status s, const std::string& msg);
@@ -56,6 +68,9 @@ msm_status hip_fail(hipError_t e, const char* what);
 hipError_t ensure_aux(AuxStreams& a);
 void destroy_aux(AuxStreams& a);
 
+// Upload a plan's tables and descriptor into workspace ws and clear its cell
+// counters (stream s; synchronises).
+msm_status init_workspace(const msm_plan* P, void* ws, hipStream_t s);
 // Device pointers of a workspace's sections.
 msm::DevPtrs dev_ptrs(const msm_plan* P, void* ws);
 // Device flags of the last evaluation of plan P in workspace ws: status word 0
@@ -63,6 +78,10 @@ msm::DevPtrs dev_ptrs(const msm_plan* P, void* ws);
 hipError_t read_flags(const msm_plan* P, const char* ws, int32_t* flags);
 // Recompute the host descriptor and stage grids after a tuning change.
 void refresh_launch(msm_plan* P);
+// Link cells of reach 2, 3 or 4 (edge a / reach along y and z), with the
+// short-range rows, work items and binning path they imply.
+void set_cell_geometry(msm_plan* P, int reach);
+int default_reach(int n_atoms);
 // Apply tuning knobs (zero fields keep the current value).  Host-side only;
 // the caller re-uploads descriptors.
 void retune(msm_plan* P, const msm_tuning& t);
@@ -70,10 +89,12 @@ void retune(msm_plan* P, const msm_tuning& t);
 msm_status check_tuning(const msm_tuning* t);
 // Capture the work `launch` enqueues on a private stream into an instantiated graph.
 template <class F>
-msm_status capture_graph(F launch, msm_graph** out) {
+msm_status capture_graph(F launch, const uint64_t* owner_gen, msm_graph** out) {
   *out = nullptr;
   msm_graph* G = new (std::nothrow) msm_graph();
   if (!G) return fail(MSM_ERR_INVALID_ARG, "out of host memory");
+  G->owner_gen = owner_gen;
+  G->gen = *owner_gen;
   hipStream_t cs = nullptr;
   hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e != hipSuccess) {

@@ -21,9 +21,10 @@ ERR_WORKSPACE, ERR_HIP, ERR_UNSUPPORTED, ERR_COINCIDENT = -4, -5, -6, -7
 SECTION_QGRID, SECTION_UCUT, SECTION_U, SECTION_SORTED, SECTION_PERM, SECTION_SHORT = range(6)
 
 # every entry point include/msm.h declares
-EXPORTS = ("msm_plan_create", "msm_plan_destroy", "msm_plan_info", "msm_plan_describe",
+EXPORTS = ("msm_plan_create", "msm_pair_plan_create", "msm_plan_destroy", "msm_plan_info", "msm_plan_describe",
            "msm_workspace_bytes",
-           "msm_workspace_init", "msm_compute", "msm_energy", "msm_backward", "msm_status_query",
+           "msm_workspace_init", "msm_compute", "msm_energy", "msm_backward",
+           "msm_status_query",
            "msm_workspace_section",
            "msm_profile_enable", "msm_profile_read", "msm_graph_capture", "msm_graph_launch",
            "msm_graph_destroy", "msm_plan_tune", "msm_plan_tuning", "msm_plan_autotune",
@@ -40,13 +41,18 @@ STAGES = ("binning", "short_range", "anterpolation", "restriction", "lattice_cut
 class Tuning(ctypes.Structure):
     _fields_ = [("lattice_b", ctypes.c_int32), ("item_chunks", ctypes.c_int32), ("short_blocks", ctypes.c_int32),
                 ("streams", ctypes.c_int32), ("short_after", ctypes.c_int32), ("short_split", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("cell_reach", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
-def make_tuning(lattice_b=0, item_chunks=0, short_blocks=0, streams=0, short_after=0, short_split=0) -> Tuning:
+TUNING_KEYS = ("lattice_b", "item_chunks", "short_blocks", "streams", "short_after", "short_split", "cell_reach")
+
+
+def make_tuning(lattice_b=0, item_chunks=0, short_blocks=0, streams=0, short_after=0, short_split=0,
+                cell_reach=0) -> Tuning:
     t = Tuning()
     t.lattice_b, t.item_chunks, t.short_blocks = int(lattice_b), int(item_chunks), int(short_blocks)
     t.streams, t.short_after, t.short_split = int(streams), int(short_after), int(short_split)
+    t.cell_reach, t.reserved = int(cell_reach), 0
     return t
 
 
@@ -64,6 +70,14 @@ class Params(ctypes.Structure):
                 ("coulomb_k", ctypes.c_double)]
 
 
+class PairParams(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("cutoff", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("box_lo", ctypes.c_double * 3), ("box_len", ctypes.c_double * 3),
+                ("coulomb_k", ctypes.c_double)]
+
+
+PAIR_KINDS = {"cutoff": 1, "shifted_force": 2, "wolf": 3}
+
 _lib = None
 
 
@@ -76,6 +90,7 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         vp, sz, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32
         L.msm_plan_create.argtypes = [ctypes.POINTER(Params), i32, ctypes.POINTER(vp)]
+        L.msm_pair_plan_create.argtypes = [ctypes.POINTER(PairParams), i32, ctypes.POINTER(vp)]
         L.msm_plan_destroy.argtypes = [vp]
         L.msm_plan_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.msm_plan_describe.argtypes = [vp, ctypes.c_char_p, sz]
@@ -168,6 +183,9 @@ class Plan:
         h = ctypes.c_void_p()
         _check(lib().msm_plan_create(ctypes.byref(self.params), self.n, ctypes.byref(h)))
         self._h = h
+        self._init_workspace(device)
+
+    def _init_workspace(self, device):
         nb = ctypes.c_size_t()
         _check(lib().msm_workspace_bytes(self._h, ctypes.byref(nb)))
         self.ws = torch.empty(int(nb.value), dtype=torch.uint8, device=device)
@@ -251,16 +269,16 @@ class Plan:
                                   _ptr(z), _ptr(q), _ptr(g), dx, dy, dz, _ptr(dq)))
         return dpos, dq
 
-    def tune(self, lattice_b=0, item_chunks=0, short_blocks=0, streams=0, short_after=0, short_split=0):
+    def tune(self, lattice_b=0, item_chunks=0, short_blocks=0, streams=0, short_after=0, short_split=0,
+             cell_reach=0):
         """Set tuning knobs (zero keeps a knob's value); see msm_tuning."""
-        t = make_tuning(lattice_b, item_chunks, short_blocks, streams, short_after, short_split)
+        t = make_tuning(lattice_b, item_chunks, short_blocks, streams, short_after, short_split, cell_reach)
         _check(lib().msm_plan_tune(self._h, _ptr(self.ws), self.ws.numel(), _stream(), ctypes.byref(t)))
 
     def tuning(self) -> dict:
         t = Tuning()
         _check(lib().msm_plan_tuning(self._h, ctypes.byref(t)))
-        return {"lattice_b": t.lattice_b, "item_chunks": t.item_chunks, "short_blocks": t.short_blocks,
-                "streams": t.streams, "short_after": t.short_after, "short_split": t.short_split}
+        return {k: getattr(t, k) for k in TUNING_KEYS}
 
     def autotune(self, x, y, z, q, trials=5):
         """Time the tuning candidates on these inputs, keep the fastest, return the search."""
@@ -296,6 +314,34 @@ class Plan:
         off, nb = ctypes.c_size_t(), ctypes.c_size_t()
         _check(lib().msm_workspace_section(self._h, int(idx), ctypes.byref(off), ctypes.byref(nb)))
         return self.ws[off.value:off.value + nb.value].view(dtype)
+
+
+class PairPlan(Plan):
+    """A cheap pair method on its own (msm_pair_plan_create): kind "cutoff",
+    "shifted_force" or "wolf" with cutoff rc and (Wolf) damping alpha.  Same
+    compute / compute_static / graph / tune interface as Plan; energy() and
+    backward() are not available."""
+
+    def __init__(self, n_atoms, *, kind, cutoff, alpha=0.0, box_lo=(0.0, 0.0, 0.0), box_len=(1.0, 1.0, 1.0),
+                 coulomb_k=1.0, device="cuda"):
+        p = PairParams()
+        p.kind = PAIR_KINDS[kind] if isinstance(kind, str) else int(kind)
+        p.reserved, p.cutoff, p.alpha, p.coulomb_k = 0, float(cutoff), float(alpha), float(coulomb_k)
+        for d in range(3):
+            p.box_lo[d] = float(box_lo[d])
+            p.box_len[d] = float(box_len[d])
+        self.params = p
+        self.n = int(n_atoms)
+        h = ctypes.c_void_p()
+        _check(lib().msm_pair_plan_create(ctypes.byref(p), self.n, ctypes.byref(h)))
+        self._h = h
+        self._init_workspace(device)
+
+
+def pair_plan_for(system, kind, cutoff=None, alpha=0.0, device="cuda") -> PairPlan:
+    """A pair-method plan for an inputs.System (cutoff defaults to the system's a)."""
+    return PairPlan(system.n, kind=kind, cutoff=system.cutoff if cutoff is None else cutoff, alpha=alpha,
+                    box_lo=system.box_lo, box_len=system.box_len, device=device)
 
 
 class Graph:
@@ -395,6 +441,22 @@ class Batch:
             _lib.msm_batch_destroy(h)
             self._h = None
 
+    def compute_static(self, x, y, z, q, out):
+        """msm_compute_static: the evaluation of compute() with the library's
+        static device workspace instead of self.ws (nothing is allocated; out
+        holds preallocated "energy" [1], "f" [3, N], "phi" [N] and optionally
+        "virial" [9] tensors)."""
+        self._check_inputs(x, y, z, q)
+        dev = self.ws.device
+        for name, numel, dtype in (("energy", 1, torch.float64), ("f", 3 * self.n, torch.float32),
+                                   ("phi", self.n, torch.float32), ("virial", 9, torch.float64)):
+            if out.get(name) is not None:
+                _require_out(out[name], numel, dtype, dev, name)
+        fx, fy, fz = _force_rows(out.get("f"), self.n)
+        _check(lib().msm_compute_static(self._h, _stream(), _ptr(x), _ptr(y), _ptr(z), _ptr(q), fx, fy, fz,
+                                        _ptr(out.get("phi")), _ptr(out.get("energy")), _ptr(out.get("virial"))))
+        return out
+
     def _check_inputs(self, x, y, z, q):
         dev = self.ws.device
         for t in (x, y, z, q):
@@ -464,8 +526,9 @@ class Batch:
         code, _ = self.status()
         _check(code)
 
-    def tune(self, lattice_b=0, item_chunks=0, short_blocks=0, streams=0, short_after=0, short_split=0):
-        t = make_tuning(lattice_b, item_chunks, short_blocks, streams, short_after, short_split)
+    def tune(self, lattice_b=0, item_chunks=0, short_blocks=0, streams=0, short_after=0, short_split=0,
+             cell_reach=0):
+        t = make_tuning(lattice_b, item_chunks, short_blocks, streams, short_after, short_split, cell_reach)
         _check(lib().msm_batch_tune(self._h, _ptr(self.ws), self.ws.numel(), _stream(), ctypes.byref(t)))
 
     def autotune(self, x, y, z, q, trials=3):

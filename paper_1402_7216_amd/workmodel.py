@@ -61,46 +61,21 @@ def stencil_taps(a, h):
 
 
 def count_pairs_within(pos, a):
-    """Unique pairs closer than a (pos: [3, N] float64), via a coarse cell grid."""
+    """Unique pairs closer than a (pos: [3, N] float64).
+
+    A k-d tree counts, for every atom, the atoms within the largest float64
+    below a (itself included); the sum less N, halved, is the number of
+    unordered pairs with r < a."""
+    from scipy.spatial import cKDTree
+
     pos = np.asarray(pos, dtype=np.float64)
     n = pos.shape[1]
     if n < 2:
         return 0
-    lo = pos.min(axis=1)
-    cell = np.floor((pos - lo[:, None]) / a).astype(np.int64)
-    nc = cell.max(axis=1) + 1
-    key = (cell[2] * nc[1] + cell[1]) * nc[0] + cell[0]
-    order = np.argsort(key, kind="stable")
-    skey = key[order]
-    starts = np.searchsorted(skey, np.arange(nc.prod() + 1))
-    total = 0
-    a2 = a * a
-    for cz in range(nc[2]):
-        for cy in range(nc[1]):
-            for cx in range(nc[0]):
-                ci = (cz * nc[1] + cy) * nc[0] + cx
-                ii = order[starts[ci]:starts[ci + 1]]
-                if ii.size == 0:
-                    continue
-                for oz in (-1, 0, 1):
-                    for oy in (-1, 0, 1):
-                        for ox in (-1, 0, 1):
-                            jx, jy, jz = cx + ox, cy + oy, cz + oz
-                            if not (0 <= jx < nc[0] and 0 <= jy < nc[1] and 0 <= jz < nc[2]):
-                                continue
-                            cj = (jz * nc[1] + jy) * nc[0] + jx
-                            if cj < ci:
-                                continue
-                            jj = order[starts[cj]:starts[cj + 1]]
-                            if jj.size == 0:
-                                continue
-                            d = pos[:, ii][:, :, None] - pos[:, jj][:, None, :]
-                            d2 = (d * d).sum(axis=0)
-                            if cj == ci:
-                                total += int(np.count_nonzero(np.triu(d2 < a2, k=1)))
-                            else:
-                                total += int(np.count_nonzero(d2 < a2))
-    return total
+    pts = np.ascontiguousarray(pos.T)
+    tree = cKDTree(pts)
+    counts = tree.query_ball_point(pts, np.nextafter(float(a), 0.0), return_length=True, workers=-1)
+    return (int(np.sum(counts, dtype=np.int64)) - n) // 2
 
 
 def evaluation_work(n_atoms, n_pairs, grid_nodes, a, h, order, m):

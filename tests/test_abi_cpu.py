@@ -177,20 +177,18 @@ def test_batch_rejects_mixed_order_and_bad_sizes(M):
 
 @pytest.mark.parametrize("field,value", [("lattice_b", 5), ("item_chunks", -2), ("short_blocks", -2),
                                          ("streams", 4), ("short_after", 4), ("short_split", 1001),
-                                         ("short_split", -1), ("reserved", 1)])
+                                         ("short_split", -1), ("cell_reach", 1), ("cell_reach", 5),
+                                         ("reserved", 1)])
 def test_tuning_values_are_checked_before_any_device_work(M, field, value):
     code, h = _plan(M, 10, **CASES[0])
     assert code == 0
     try:
         t = M.make_tuning()
-        if field == "reserved":
-            t.reserved[1] = value
-        else:
-            setattr(t, field, value)
+        setattr(t, field, value)
         assert M.lib().msm_plan_tune(h, ctypes.c_void_p(256), 1 << 30, None, ctypes.byref(t)) == -1
         cur = M.Tuning()
         assert M.lib().msm_plan_tuning(h, ctypes.byref(cur)) == 0
         assert cur.lattice_b in (0, 4, 6, 8) and cur.item_chunks >= 1 and cur.streams == 3
-        assert cur.short_after == 1 and cur.short_split == 1000
+        assert cur.short_after == 1 and cur.short_split == 1000 and cur.cell_reach in (2, 3, 4)
     finally:
         M.lib().msm_plan_destroy(h)

@@ -90,8 +90,8 @@ def test_autograd_scales_with_incoming_gradient(M):
 
 
 def test_autograd_vs_oracle_central_differences(M):
-    """Central differences of the FP64 oracle energy (1e-4 A, 1e-6 e) on 8
-    atoms x 3 coordinates and 8 charges of a 6,000-atom water box, against the
+    """Central differences of the FP64 oracle energy (1e-4 A, 1e-6 e) on 32
+    atoms x 3 coordinates and 32 charges of a 6,000-atom water box, against the
     device autograd gradient."""
     s = inputs.water_box(6000, seed=32, cutoff=10.0, spacing=2.0, order=4, levels=3)
     print(f"case finite differences n={s.n}", flush=True)
@@ -103,7 +103,7 @@ def test_autograd_vs_oracle_central_differences(M):
     gpos = pos.grad.double().cpu().numpy()
     gq = q.grad.double().cpu().numpy()
     rng = np.random.default_rng(4)
-    atoms = rng.choice(s.n, size=8, replace=False)
+    atoms = rng.choice(s.n, size=32, replace=False)
     p64 = s.pos64()
     q64 = s.q.astype(np.float64)
     prm = s.params()

@@ -93,3 +93,46 @@ def test_binning_is_stable_cell_sort(M, name):
     assert np.array_equal(perm, order)
     for k, v in enumerate((s.x, s.y, s.z, s.q)):
         assert np.array_equal(srt[:, k], v[order])
+
+
+@pytest.mark.parametrize("name", ["water24k", "water40k", "slab32769", "water100k"])
+def test_coincident_atoms_are_flagged_on_every_binning_path(M, name):
+    """Two atoms of different molecules moved onto the same point are reported
+    as MSM_ERR_COINCIDENT whichever binning path the system takes (the one-
+    and two-kernel paths flag them in the short-range pass, the four-kernel
+    path while ranking atoms inside a cell); a clean call clears the flag."""
+    make, path = CASES[name]
+    s = make()
+    print(f"case coincident {name} n={s.n} path={path}", flush=True)
+    plan = M.plan_for(s)
+    x, y, z, q = M.to_device(s)
+    j, k = 10, s.n // 2 + 1
+    xb, yb, zb = x.clone(), y.clone(), z.clone()
+    xb[k], yb[k], zb[k] = x[j], y[j], z[j]
+    plan.compute(xb, yb, zb, q)
+    code, flags = plan.status()
+    assert code == M.ERR_COINCIDENT, (code, flags)
+    plan.compute(x, y, z, q)
+    assert plan.status()[0] == 0
+
+
+@pytest.mark.parametrize("name", ["water24k", "water40k", "water100k"])
+@pytest.mark.parametrize("reach", [3, 4])
+def test_finer_cells_keep_the_stable_cell_sort(M, name, reach):
+    """Link cells of edge a/3 and a/4 (the cell_reach tuning) still give the
+    stable cell sort, whichever binning path the finer cells select."""
+    make, _ = CASES[name]
+    s = make()
+    print(f"case {name} reach {reach} n={s.n}", flush=True)
+    plan = M.plan_for(s)
+    plan.tune(cell_reach=reach)
+    d = plan.describe()
+    assert d["reach"] == reach
+    x, y, z, q = M.to_device(s)
+    plan.compute(x, y, z, q)
+    torch.cuda.synchronize()
+    code, flags = plan.status()
+    assert code == 0, flags
+    perm = plan.section(M.SECTION_PERM, torch.int32).cpu().numpy()[:s.n]
+    order = np.argsort(host_cells(s, d["cells"]), kind="stable")
+    assert np.array_equal(perm, order)

@@ -101,13 +101,24 @@ SMALL = {
     "water3k_l1": lambda: inputs.water_box(3000, seed=23, cutoff=8.0, spacing=2.5, order=4, levels=1),
     "cloud_m3": lambda: inputs.uniform_charges(777, 17.3, seed=24, cutoff=6.5, spacing=1.9, order=4,
                                                levels=3, split_m=3),
+    # stencils the windowed lattice kernel does not take, so the untiled
+    # lattice kernel and the standalone top-level launch run: half-width 16
+    # (2a/h = 17) whose window does not fit in LDS, and half-width 17 (2a/h = 18)
+    "cloud500_wide": lambda: inputs.uniform_charges(500, 20.0, seed=29, cutoff=8.5, spacing=1.0, order=4,
+                                                    levels=3),
+    "cloud500_wide_quintic": lambda: inputs.uniform_charges(500, 20.0, seed=30, cutoff=9.0, spacing=1.0,
+                                                            order=6, levels=3),
 }
+UNTILED = ("cloud500_wide", "cloud500_wide_quintic")
 
 
 @pytest.mark.parametrize("name", list(SMALL))
 def test_small_systems_match_oracle(M, name):
     s = SMALL[name]()
     print(f"case {name} n={s.n}", flush=True)
+    if name in UNTILED:
+        d = M.plan_for(s).describe()
+        assert d["lattice_b"] == 0 and d["halo"] >= 16, d
     g = run_gpu(M, s)
     r = oracle.system_msm(s)
     check_full(g, r, name)
@@ -160,22 +171,14 @@ def test_water100k_matches_oracle(M):
     check_full(run_gpu(M, s), oracle.system_msm(s), "water100k")
 
 
-def test_water1m_sampled_atoms_match_oracle(M):
-    """One million atoms, quintic, 5 levels: every 997th atom against the
-    oracle's per-atom evaluation, plus global properties."""
+def test_water1m_matches_oracle(M):
+    """One million atoms, quintic basis, 5 levels: every force component, every
+    potential and the energy against a full oracle evaluation."""
     s = inputs.water_1m()
     print(f"case water1m n={s.n}", flush=True)
-    g = run_gpu(M, s, virial=False)
-    assert g["code"] == 0
-    idx = np.arange(0, s.n, 997)
-    r = oracle.system_msm(s, sample=idx)
-    ferr = rel_rms(g["f"][:, idx], r["f"][:, idx])
-    perr = rel_rms(g["phi"][idx], r["phi"][idx])
-    print(f"  sampled f_rms={ferr:.2e} phi_rms={perr:.2e}", flush=True)
-    assert ferr <= FORCE_RTOL and perr <= PHI_RTOL
-    # E = 1/2 sum q_i phi_i holds for the device outputs themselves
-    e_from_phi = 0.5 * float(np.dot(s.q.astype(np.float64), g["phi"]))
-    assert rel_err(g["energy"], e_from_phi) < 1e-6
+    g = run_gpu(M, s)
+    r = oracle.system_msm(s)
+    check_full(g, r, "water1m")
 
 
 def test_repeat_is_bitwise_identical(M):
@@ -309,6 +312,34 @@ def test_graph_replay_matches_eager(M):
         x.copy_(torch.clamp(x + d, 0.0, float(s.box_len[0])))
 
 
+def test_graph_is_refused_after_retuning(M):
+    """A graph keeps the launch grids, kernel variant and LDS size of the
+    tuning it was captured under: after a re-tune its replay is refused with
+    MSM_ERR_INVALID_ARG and nothing runs; a graph captured afterwards works."""
+    s = inputs.water_box(6000, seed=34, cutoff=10.0, spacing=2.0, order=4, levels=3)
+    plan = M.plan_for(s)
+    x, y, z, q = M.to_device(s)
+    ref = {k: v.clone() for k, v in plan.compute(x, y, z, q).items()}
+    out = {k: torch.empty_like(v) for k, v in ref.items()}
+    graph = M.Graph(plan, x, y, z, q, out)
+    t = plan.tuning()
+    plan.tune(lattice_b=4 if t["lattice_b"] != 4 else 6, short_blocks=64)
+    for v in out.values():
+        v.fill_(float("nan"))
+    with pytest.raises(M.MSMError) as err:
+        graph.launch()
+    assert err.value.code == M.ERR_INVALID_ARG
+    torch.cuda.synchronize()
+    assert all(bool(torch.isnan(v).all()) for v in out.values())
+    fresh = M.Graph(plan, x, y, z, q, out)
+    fresh.launch()
+    torch.cuda.synchronize()
+    again = plan.compute(x, y, z, q)
+    torch.cuda.synchronize()
+    for k in ref:
+        assert torch.equal(out[k], again[k]), k
+
+
 def test_tunings_keep_bars_and_stream_layouts_are_bitwise_equal(M):
     """Every tuning (lattice outputs per lane, chunks per short-range item,
     short-range block count) stays within the bars; the stream layout, the
@@ -340,6 +371,25 @@ def test_tunings_keep_bars_and_stream_layouts_are_bitwise_equal(M):
                       f"f_rms {rel_rms(f, r['f']):.2e}", flush=True)
                 assert rel_err(e, r["energy"]) <= ENERGY_RTOL
                 assert rel_rms(f, r["f"]) <= FORCE_RTOL
+
+
+@pytest.mark.parametrize("reach", [2, 3, 4])
+def test_cell_reach_keeps_bars(M, reach):
+    """Every link-cell reach (edge a/2, a/3, a/4) gives results within the bars
+    on a quintic water box and on the cubic 24k box."""
+    for s in (inputs.water_box(9000, seed=35, cutoff=12.0, spacing=2.5, order=6, levels=0), inputs.water_24k()):
+        print(f"case reach {reach} {s.name} n={s.n}", flush=True)
+        plan = M.plan_for(s)
+        plan.tune(cell_reach=reach)
+        assert plan.tuning()["cell_reach"] == reach
+        x, y, z, q = M.to_device(s)
+        o = plan.compute(x, y, z, q)
+        torch.cuda.synchronize()
+        plan.check()
+        r = oracle.system_msm(s)
+        g = dict(energy=float(o["energy"].item()), f=o["f"].double().cpu().numpy(),
+                 phi=o["phi"].double().cpu().numpy(), code=0, flags=0)
+        check_full(g, r, f"reach{reach}-{s.name}")
 
 
 def test_output_buffers_are_validated(M):

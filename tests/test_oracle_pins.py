@@ -469,3 +469,17 @@ def test_flop_model_reproduces_printed_numbers():
     assert round(512 / 7) == g["lattice_term_coeff"]
     assert full["restrict_prolong"] * 2 ** 3 == g["restrict_term_coeff"]
     assert workmodel.stencil_taps(12, 2) == 7123
+
+
+def test_pair_count_of_the_work_model_equals_brute_force():
+    """The work model's count of unique pairs closer than a (a k-d tree) equals
+    the all-pairs count on small systems, including a box with coincident
+    atoms and pairs at exactly the cutoff (which do not count)."""
+    rng = np.random.default_rng(3)
+    for n, side, a in ((300, 20.0, 5.0), (1000, 15.0, 7.5), (50, 3.0, 10.0)):
+        pos = rng.uniform(0.0, side, (3, n))
+        pos[:, 1] = pos[:, 0]
+        pos[:, 3] = pos[:, 2] + np.array([a, 0.0, 0.0])
+        d = np.sqrt(((pos[:, :, None] - pos[:, None, :]) ** 2).sum(axis=0))
+        brute = int(np.count_nonzero(np.triu(d < a, k=1)))
+        assert workmodel.count_pairs_within(pos, a) == brute
