@@ -95,8 +95,8 @@ msm_status msm_plan_destroy(msm_plan* plan);
  *                            self energy -(erfc(alpha rc)/(2 rc) + alpha/sqrt(pi)) q_i^2
  * msm_pair_plan_create returns a plan for n_atoms atoms that works with
  * msm_workspace_bytes, msm_workspace_init, msm_compute (same outputs: forces
- * -dE/dr_i, potentials dE/dq_i, energy, virial), msm_graph_capture,
- * msm_status_query, msm_plan_describe, msm_plan_tune / msm_plan_autotune (the
+ * -dE/dr_i, potentials dE/dq_i, energy, virial), msm_compute_static,
+ * msm_graph_capture, msm_status_query, msm_plan_describe, msm_plan_tune / msm_plan_autotune (the
  * cell knobs) and msm_plan_destroy; msm_energy and
  * msm_backward return MSM_ERR_UNSUPPORTED for it, and batches do not take it.
  * Pair arithmetic is float32 (erfcf, expf for Wolf), reductions float64. */
@@ -149,6 +149,24 @@ msm_status msm_compute(const msm_plan* plan, void* ws, size_t ws_bytes, msm_stre
                        const float* x, const float* y, const float* z, const float* q,
                        float* fx, float* fy, float* fz, float* phi, double* energy,
                        double* virial);
+
+/* msm_compute without a caller workspace and without any device allocation,
+ * for callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation).  Same arguments and
+ * results as msm_compute minus ws/ws_bytes; every stage runs in order on
+ * `stream`.  The workspace is a 64 MiB array in the library's device data,
+ * one copy per GPU, held until the process ends; plans whose workspace
+ * (msm_workspace_bytes) exceeds 64 MiB are rejected with MSM_ERR_UNSUPPORTED
+ * before anything runs.  The array keeps the last call's contents: the first
+ * call of a plan on a device (and the first after a re-tune, or after another
+ * plan's call) uploads the plan's tables into it and synchronises `stream`.
+ * All calls on one GPU share the array, so calls that overlap on one GPU (two
+ * streams, two threads) race and give undefined results.  Data errors (non-
+ * finite input, atoms outside the box, coincident atoms) are not reported on
+ * this path; the kernels stay in bounds and the outputs are then undefined. */
+msm_status msm_compute_static(const msm_plan* plan, msm_stream_t stream, const float* x,
+                              const float* y, const float* z, const float* q, float* fx,
+                              float* fy, float* fz, float* phi, double* energy, double* virial);
 
 /* Energy only (Sec. 2.3 potential display, E = 1/2 sum_i q_i U_i): E as
  * msm_compute would return it, evaluated through the grid form

@@ -23,7 +23,7 @@ SECTION_QGRID, SECTION_UCUT, SECTION_U, SECTION_SORTED, SECTION_PERM, SECTION_SH
 # every entry point include/msm.h declares
 EXPORTS = ("msm_plan_create", "msm_pair_plan_create", "msm_plan_destroy", "msm_plan_info", "msm_plan_describe",
            "msm_workspace_bytes",
-           "msm_workspace_init", "msm_compute", "msm_energy", "msm_backward",
+           "msm_workspace_init", "msm_compute", "msm_compute_static", "msm_energy", "msm_backward",
            "msm_status_query",
            "msm_workspace_section",
            "msm_profile_enable", "msm_profile_read", "msm_graph_capture", "msm_graph_launch",
@@ -97,6 +97,7 @@ def lib():
         L.msm_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
         L.msm_workspace_init.argtypes = [vp, vp, sz, vp]
         L.msm_compute.argtypes = [vp, vp, sz, vp] + [vp] * 10
+        L.msm_compute_static.argtypes = [vp, vp] + [vp] * 10
         L.msm_energy.argtypes = [vp, vp, sz, vp] + [vp] * 5
         L.msm_backward.argtypes = [vp, vp, sz, vp] + [vp] * 9
         L.msm_status_query.argtypes = [vp, vp, vp, ctypes.POINTER(i32)]
@@ -241,6 +242,22 @@ class Plan:
         _check(lib().msm_compute(self._h, _ptr(self.ws), self.ws.numel(), _stream(), _ptr(x), _ptr(y),
                                  _ptr(z), _ptr(q), fx, fy, fz, _ptr(ph), _ptr(o["energy"]), _ptr(vr)))
         return o
+
+    def compute_static(self, x, y, z, q, out):
+        """msm_compute_static: the evaluation of compute() with the library's
+        static device workspace instead of self.ws (nothing is allocated; out
+        holds preallocated "energy" [1], "f" [3, N], "phi" [N] and optionally
+        "virial" [9] tensors)."""
+        self._check_inputs(x, y, z, q)
+        dev = self.ws.device
+        for name, numel, dtype in (("energy", 1, torch.float64), ("f", 3 * self.n, torch.float32),
+                                   ("phi", self.n, torch.float32), ("virial", 9, torch.float64)):
+            if out.get(name) is not None:
+                _require_out(out[name], numel, dtype, dev, name)
+        fx, fy, fz = _force_rows(out.get("f"), self.n)
+        _check(lib().msm_compute_static(self._h, _stream(), _ptr(x), _ptr(y), _ptr(z), _ptr(q), fx, fy, fz,
+                                        _ptr(out.get("phi")), _ptr(out.get("energy")), _ptr(out.get("virial"))))
+        return out
 
     def _check_inputs(self, x, y, z, q):
         dev = self.ws.device
