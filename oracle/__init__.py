@@ -76,7 +76,7 @@ def lib():
         L.oracle_pair.restype = ctypes.c_int
         L.oracle_pair.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp, ctypes.c_double,
                                   ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, ctypes.c_int,
-                                  ctypes.c_int]
+                                  ctypes.c_int, ctypes.c_int]
         L.oracle_pair_e.restype = ctypes.c_double
         L.oracle_pair_e.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.oracle_gamma_coeffs.restype = None
@@ -189,9 +189,11 @@ PAIR_KINDS = {"cutoff": 1, "shifted_force": 2, "wolf": 3}
 
 
 def pair(x, y, z, q, *, kind, cutoff, alpha=0.0, box_lo=(0, 0, 0), box_len=(1, 1, 1), ke=1.0,
-         all_pairs=False, threads=0):
+         all_pairs=False, f32_cut=False, threads=0):
     """A cheap pair method (plain cutoff, shifted-force smoothed cutoff, Wolf
-    summation) in FP64: energy, forces f[3,N], potentials phi[N], virial[3,3]."""
+    summation) in FP64: energy, forces f[3,N], potentials phi[N], virial[3,3].
+    f32_cut: decide r < rc in float32 as a float32 kernel does (the pair
+    terms stay double)."""
     x, y, z, q = _f64(x), _f64(y), _f64(z), _f64(q)
     n = int(x.shape[0])
     lo, ln = _f64(box_lo), _f64(box_len)
@@ -200,7 +202,7 @@ def pair(x, y, z, q, *, kind, cutoff, alpha=0.0, box_lo=(0, 0, 0), box_len=(1, 1
     k = PAIR_KINDS[kind] if isinstance(kind, str) else int(kind)
     rc = lib().oracle_pair(k, float(cutoff), float(alpha), _dptr(lo), _dptr(ln), float(ke), n, _dptr(x),
                            _dptr(y), _dptr(z), _dptr(q), _dptr(fx), _dptr(fy), _dptr(fz), _dptr(phi),
-                           _dptr(e), _dptr(w), int(bool(all_pairs)), int(threads))
+                           _dptr(e), _dptr(w), int(bool(all_pairs)), int(bool(f32_cut)), int(threads))
     if rc:
         raise OracleError(rc)
     return dict(f=np.stack([fx, fy, fz]), phi=phi, energy=float(e[0]), virial=w.reshape(3, 3))

@@ -751,7 +751,12 @@ int oracle_direct(int n, const double* x, const double* y, const double* z, cons
 /*   F_i = -dE/dr_i = -q_i sum_{j != i} q_j e'(r_ij) (r_i - r_j)/r_ij,       */
 /*   W_ab = sum_i (r_i - lo)_a F_i,b.                                        */
 /* Pairs are found through cells of edge >= rc (each atom scans the 27       */
-/* cells around its own), or over all pairs when all_pairs is set.           */
+/* cells around its own), or over all pairs when all_pairs is set.  Whether  */
+/* a pair is inside the cutoff is a discrete decision; with f32_cut set it is */
+/* taken in float32 the way a float32 kernel takes it (differences of the    */
+/* float32 coordinates, r^2 = fma(dx, dx, fma(dy, dy, dz dz)) compared with  */
+/* float32(rc^2)), so both sides include the same pairs; the pair terms are  */
+/* still evaluated in double.                                                */
 /* ------------------------------------------------------------------------- */
 static double pair_e(int kind, double rc, double alpha, double r) {
   if (kind == 1) return 1.0 / r;
@@ -770,7 +775,7 @@ double oracle_pair_e(int kind, double rc, double alpha, double r) { return pair_
 int oracle_pair(int kind, double rc, double alpha, const double* lo, const double* len, double ke,
                 int n, const double* x, const double* y, const double* z, const double* q,
                 double* fx, double* fy, double* fz, double* phi, double* energy, double* virial,
-                int all_pairs, int nthreads) {
+                int all_pairs, int f32_cut, int nthreads) {
   if (kind < 1 || kind > 3 || !(rc > 0.0) || !(alpha >= 0.0) || n < 0) return OR_EINVAL;
   if (ke == 0.0) ke = 1.0;
 #ifdef _OPENMP
@@ -818,6 +823,7 @@ int oracle_pair(int kind, double rc, double alpha, const double* lo, const doubl
   double* ph = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
   double* f3 = (double*)calloc(3 * (size_t)(n > 0 ? n : 1), sizeof(double));
   const double rc2 = rc * rc;
+  const float rc2f = (float)(rc * rc);
   int bad = 0;
 #pragma omp parallel for schedule(dynamic, 64) reduction(| : bad)
   for (int i = 0; i < n; ++i) {
@@ -836,8 +842,15 @@ int oracle_pair(int kind, double rc, double alpha, const double* lo, const doubl
             if (j == i) continue;
             double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
             double r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 >= rc2) continue;
             if (r2 == 0.0) { bad = 1; continue; }
+            if (f32_cut) {
+              const float dxf = (float)x[i] - (float)x[j], dyf = (float)y[i] - (float)y[j];
+              const float dzf = (float)z[i] - (float)z[j];
+              const float r2f = fmaf(dxf, dxf, fmaf(dyf, dyf, dzf * dzf));
+              if (!(r2f > 0.0f && r2f < rc2f)) continue;
+            } else if (r2 >= rc2) {
+              continue;
+            }
             double rr = sqrt(r2);
             p += q[j] * pair_e(kind, rc, alpha, rr);
             double w = -q[i] * q[j] * pair_de(kind, rc, alpha, rr) / rr;

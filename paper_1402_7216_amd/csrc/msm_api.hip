@@ -434,9 +434,11 @@ void set_cell_geometry(msm_plan* P, int reach) {
 }
 
 // Cell reach of a new plan: finer rows (higher reach) cut the short-range
-// candidates that fail the cutoff test but add rows to every work item, which
-// only pays when many work items keep the GPU busy.
-int default_reach(int n_atoms) { return n_atoms >= 200000 ? 4 : 2; }
+// candidates that fail the cutoff test, but a 64-atom chunk of a thin row
+// spans a long stretch of x, so every work item stages more atoms (on the
+// 1M-atom water box reach 4 doubled the short-range time); the autotuner
+// tries the finer cells.
+int default_reach(int) { return 2; }
 
 void retune(msm_plan* P, const msm_tuning& t) {
   if (t.cell_reach != 0 && t.cell_reach != P->g.reach) set_cell_geometry(P, t.cell_reach);
@@ -646,12 +648,11 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
   double c[9];
   taylor_coeffs(g.m, c);
   for (int k = 0; k <= g.m; ++k) {
-    g.gcoef[k] = (float)(c[k] / a);
-    g.dcoef[k] = (float)(2.0 * k * c[k] / (a * a * a));
-    g.gr[k] = (float)(c[k] / std::pow(a, 2.0 * k + 1.0));
     g.dr[k] = (float)(2.0 * k * c[k] / std::pow(a, 2.0 * k + 1.0));
   }
   g.self = (float)(c[0] / a);
+  g.inv_a = (float)(1.0 / a);
+  g.inv_a2f = (float)(1.0 / (a * a));
   g.a2 = (float)(a * a);
   g.inv_a2 = (float)(1.0 / (a * a));
 
@@ -664,6 +665,7 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
     P->max_cells = std::max(P->max_cells, g.n_cells);
     P->max_bin_hist = std::max(P->max_bin_hist, (long long)P->bin2_blocks * ((g.n_cells + 3) & ~3));
   }
+  g.max_cells = P->max_cells;
   set_cell_geometry(P, default_reach(n_atoms));
 
   // lattice-cutoff stencil: W(n) = g^0(h |n|) for h |n| < 2a, rows along z

@@ -54,6 +54,7 @@ struct Geom {
   // link cells
   int nc[3];
   int n_cells;
+  int max_cells;                   // cells of the finest reach any tuning may select (sizes the cell arrays)
   int bin_blocks;                  // blocks of the two-kernel binning (0: another binning)
   int bin_row_blocks;              // blocks of the one-kernel binning (0: another binning)
   int reach;                       // neighbour cell rows per side in y and z
@@ -68,9 +69,8 @@ struct Geom {
   // short-range constants
   float a2;                        // cutoff^2
   float inv_a2;                    // 1 / a^2
-  float gcoef[8];                  // c_k / a         (gamma(rho)/a = sum gcoef[k] s^k, s = rho^2)
-  float dcoef[8];                  // 2 k c_k / a^3   (gamma'(rho)/(a^2 r) = sum_{k>=1} dcoef[k] s^{k-1})
-  float gr[8];                     // c_k / a^(2k+1)       (gamma(r/a)/a as a polynomial in r^2)
+  float inv_a;                     // 1 / a
+  float inv_a2f;                   // 1 / a^2 (float)
   float dr[8];                     // 2 k c_k / a^(2k+1)   (gamma'(r/a)/(a^2 r) = sum_{k>=1} dr[k] r^2(k-1))
   int at[3];                       // anterpolation node tile (level-0 nodes per dimension)
   int atn[3];                      // anterpolation tiles per dimension (they own floor indices 0..fmax)

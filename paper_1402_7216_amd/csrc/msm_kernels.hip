@@ -138,13 +138,14 @@ __device__ __forceinline__ float phi_any(float u) {
 // --------------------------------------------------------------------------
 // Link cells (Sec. 2.1): counting sort of atoms by cell, stable in input order.
 // --------------------------------------------------------------------------
-// Counts are zero on entry: the workspace is initialised that way and k_scan
-// clears them (with the scatter cursors and the status word) after reading.
+// Counts are zero on entry: the workspace is initialised that way (for the
+// cells of every reach a re-tune may select) and the scan clears them (with
+// the scatter cursors and the status word) after reading.
 __global__ void k_zero_counts(KArgs A) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
   const int i = blk * blockDim.x + threadIdx.x;
-  if (i <= S.g.n_cells) S.d.counts[i] = 0;
+  if (i <= S.g.max_cells) S.d.counts[i] = 0;
 }
 
 __device__ __forceinline__ int cell_coord(const Geom& g, float p, int d) {
@@ -274,6 +275,7 @@ __global__ void k_bin_scatter(KArgs A) {
   const float4 p = make_float4(x[i], y[i], z[i], q[i]);
   const int c = cell_of[i];
   const int slot = start[c] + atomicAdd(&cursor[c], 1);
+  if ((unsigned)slot >= (unsigned)S.g.n_atoms) return;   // only a corrupted workspace gets here
   tmp[slot] = i;
   tmp4[slot] = p;
 }
@@ -297,6 +299,7 @@ __global__ void k_bin_place(KArgs A) {
   int* __restrict__ perm = S.d.perm;
   int* __restrict__ status = S.d.status;
   const int i = tmp[s];
+  if ((unsigned)i >= (unsigned)g.n_atoms) return;       // only a corrupted workspace gets here
   const float4 p = tmp4[s];
   const int c = cell_of[i];
   const int b = start[c], e = start[c + 1];
@@ -310,7 +313,7 @@ __global__ void k_bin_place(KArgs A) {
       if (pd[d] < g.lo[d] || pd[d] > g.hi[d]) flags |= kFlagOutOfBox;
   }
   int dst = s;
-  if (e - b <= kRankCap) {
+  if (0 <= b && b <= e && e <= g.n_atoms && e - b <= kRankCap) {
     int rank = 0;
 #pragma unroll 4
     for (int t = b; t < e; ++t) {
@@ -798,6 +801,14 @@ __device__ __forceinline__ int wave_max(int v) {
 }
 
 // A launch takes the work items [n lo_pm / 1000, n hi_pm / 1000) of each system.
+// binom(-1/2, j): the coefficients of the Taylor polynomial of s^{-1/2} about
+// s = 1 in powers of (s - 1) (exact dyadic rationals).
+constexpr float binom_half(int j) {
+  double v = 1.0;
+  for (int i = 0; i < j; ++i) v *= (-0.5 - i) / (i + 1);
+  return (float)v;
+}
+
 // KIND selects the pair function: the MSM short-range kernel g* (gamma of
 // degree M), or a cheap pair method on its own with e(r) and -e'(r)/r
 //   plain cutoff     e = 1/r                                -e'/r = 1/r^3
@@ -824,17 +835,20 @@ __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, 
   const int n_items = g.row_items * g.nc[1] * g.nc[2];
   const float a2 = g.a2, aw = g.a_win;
   const unsigned a2m1 = __float_as_uint(a2) - 1u;
-  // the polynomial coefficients live in vector registers (an FMA may take
-  // only one scalar operand, so scalar copies would cost a move per use)
-  float gc[M + 1], dc[M + 1];
+  // Constants of the pair terms, copied into registers once: left to the
+  // compiler they are reloaded from the descriptor inside the pair loop (a
+  // global load and wait per pair).  The force polynomial's coefficients go to
+  // vector registers (its first FMA would otherwise read two scalars), 1/a and
+  // 1/a^2 to scalar registers.
+  float dc[M + 1];
 #pragma unroll
   for (int k = 0; k <= M; ++k) {
-    float gv, dv;
-    asm volatile("v_mov_b32 %0, %1" : "=v"(gv) : "s"(g.gr[k]));
-    asm volatile("v_mov_b32 %0, %1" : "=v"(dv) : "s"(g.dr[k]));
-    gc[k] = gv;
-    dc[k] = dv;
+    float v;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(g.dr[k]));
+    dc[k] = v;
   }
+  const float inv_a = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(g.inv_a)));
+  const float inv_a2 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(g.inv_a2f)));
   float pk[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -858,6 +872,7 @@ __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, 
       const int i = ic + lane;
       const bool live = i < ie;
       const float4 pi = live ? sorted[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+      // ap: sum q_j g*(r) (MSM) or sum q_j e(r) (pair methods)
       float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;
       bool coincident = false;
       for (int q = 0; q < kShortRowsPerWave; ++q) {
@@ -920,13 +935,21 @@ __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, 
                 ri = fmaf(0.5f * ri, fmaf(-r2 * ri, ri, 1.f), ri);
                 const float qj = pj[v].w;
                 if (KIND == kPairMsm) {
-                  // gamma(r/a)/a and gamma'(r/a)/(a^2 r) as polynomials in r^2
-                  float gm = gc[M], dg = dc[M];
+                  // g*(r) = 1/r - gamma(r/a)/a with gamma the Taylor polynomial of
+                  // s^{-1/2} in t = s - 1, s = (r/a)^2: exact coefficients and
+                  // every term of one sign, then one rounding for the difference.
+                  // (Horner in r^2 with the rounded coefficients c_k / a^{2k+1}
+                  // leaves a fixed bias in every pair that does not average out
+                  // over the pairs of rigid molecules.)
+                  const float t = fmaf(r2, inv_a2, -1.f);
+                  float gm = binom_half(M);
 #pragma unroll
-                  for (int k = M - 1; k >= 0; --k) gm = fmaf(gm, r2, gc[k]);
+                  for (int k = M - 1; k >= 0; --k) gm = fmaf(gm, t, binom_half(k));
+                  ap = fmaf(qj, fmaf(-gm, inv_a, ri), ap);
+                  // gamma'(r/a)/(a^2 r) as a polynomial in r^2
+                  float dg = dc[M];
 #pragma unroll
                   for (int k = M - 1; k >= 1; --k) dg = fmaf(dg, r2, dc[k]);
-                  ap = fmaf(qj, ri - gm, ap);                     // q_j g*(r)
                   if (FORCES) {
                     const float wq = qj * fmaf(ri, ri * ri, dg);  // q_j (-g*'(r)/r)
                     ax = fmaf(wq, dx, ax);
@@ -1074,17 +1097,18 @@ __global__ void __launch_bounds__(kAThreads) k_anterp(KArgs A) {
       const float4 p = sorted[row_beg[row] + (t - row_pre[row])];
       const float pp[3] = {p.x, p.y, p.z};
       int f[3];
-      float w[3][ORDER], dw[3][ORDER];
+      float r[3];
       bool own = true;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        float r;
-        grid_coord(pp[d], g.lo_f[d], g.h, g.inv_h, g.fmax[d], f[d], r);
+        grid_coord(pp[d], g.lo_f[d], g.h, g.inv_h, g.fmax[d], f[d], r[d]);
         f[d] -= n0[d];
         own = own && f[d] >= 0 && f[d] < T[d];
-        basis<ORDER>(r, w[d], dw[d]);
       }
       if (!own) continue;
+      float w[3][ORDER], dw[3][ORDER];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) basis<ORDER>(r[d], w[d], dw[d]);
 #pragma unroll
       for (int sz = 0; sz < ORDER; ++sz) {
         const float qz = p.w * w[2][sz];
@@ -2096,7 +2120,7 @@ int interp_partials(const Geom& g) { return std::max(1, blocks_for(g.n_atoms)); 
 
 SysBlocks system_blocks(const Geom& g, const LatLaunch& lat, int n_partials) {
   SysBlocks b{};
-  b.zero = blocks_for(g.n_cells + 1);
+  b.zero = blocks_for(g.max_cells + 1);
   b.scan = (g.bin_blocks == 0 && g.bin_row_blocks == 0) ? (g.n_cells + kScanTile - 1) / kScanTile : 0;
   b.atoms = g.n_atoms > 0 ? blocks_for(g.n_atoms) : 0;
   b.bin = g.bin_blocks;

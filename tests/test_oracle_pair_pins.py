@@ -133,3 +133,17 @@ def test_wolf_erfc_is_the_complementary_error_function():
     e = oracle.pair_e("wolf", 1e6, 1.0 / r, r)
     assert abs(e - 0.157299207050285 / r) < 1e-12
     assert math.isclose(oracle.pair_e("cutoff", 5.0, 0.0, 2.0), 0.5)
+
+
+@pytest.mark.parametrize("kind", ["shifted_force", "wolf"])
+def test_float32_cutoff_decision_only_moves_pairs_at_the_cutoff(kind):
+    """Taking the r < rc decision in float32 changes only pairs within rounding
+    of rc; where e(rc) = 0 (shifted force, Wolf) the energy is unchanged to
+    rounding, and for float32-exact inputs far from rc nothing changes."""
+    pos, q = _cloud(800, 25.0, 5)
+    pos = pos.astype(np.float32).astype(np.float64)
+    prm = dict(kind=kind, cutoff=6.0, alpha=0.2, box_len=(25.0,) * 3)
+    a = oracle.pair(*pos, q, **prm)
+    b = oracle.pair(*pos, q, f32_cut=True, **prm)
+    assert abs(a["energy"] - b["energy"]) <= 1e-9 * abs(a["energy"])
+    assert np.allclose(a["f"], b["f"], rtol=0, atol=1e-8 * np.abs(a["f"]).max())
