@@ -14,7 +14,8 @@ the mean of the K-step window.
 
 Prints one JSON line.  Besides the timed steps it reports
   * roofline: the dominant kernel's algorithmic FLOP rate against the FP32
-    vector peak, timed with HIP events on the library's stream;
+    vector peak, its launches timed with HIP events on the stream they run on
+    in the timed schedule (K more evaluations), and alone (stages in order);
   * parity: the timed configuration's forces, potentials and energy against
     the FP64 CPU oracle on the same inputs;
   * cpu_baseline: that oracle run, timed on the host cores (plus one-thread
@@ -294,6 +295,9 @@ def main():
                     help="skip the oracle (CPU baseline and parity)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 24k, 100k-gradient and 64-replica legs")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy a 256 MiB device buffer 5 times (the reference kernel that scales the "
+                         "FETCH_SIZE / WRITE_SIZE counters to bytes)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -307,6 +311,14 @@ def main():
     from paper_1402_7216_amd import msm, workmodel
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": src.numel() * 4}), flush=True)
+        return
     s = make_system(args.workload)
     plan = msm.plan_for(s)
     x, y, z, q = msm.to_device(s)
@@ -334,28 +346,37 @@ def main():
     torch.cuda.synchronize()
     timed_out = {k: v.clone() for k, v in out.items()}
 
-    # per-stage kernel durations, HIP events on the library's stream (stages in order)
-    plan.profile(True)
-    stage_sum = {}
-    n_prof = max(10, min(args.steps, 100))
-    for _ in range(n_prof):
-        plan.compute(x, y, z, q, out=out)
-        for k, v in plan.stage_ms().items():
-            stage_sum[k] = stage_sum.get(k, 0.0) + v
-    plan.profile(False)
-    stage_ms = {k: v / n_prof for k, v in stage_sum.items()}
+    # per-stage durations in the timed schedule: each stage's launches bracketed
+    # by HIP events on the stream they run on (side streams included), over K
+    # more evaluations identical to the timed ones
+    def stage_pass(live, n):
+        plan.profile(True, live=live)
+        acc = {}
+        for _ in range(n):
+            plan.compute(x, y, z, q, out=out)
+            for k, v in plan.stage_ms().items():
+                acc[k] = acc.get(k, 0.0) + v
+        plan.profile(False)
+        return {k: v / n for k, v in acc.items()}
+
+    stage_live = stage_pass(True, args.steps)
+    # and each stage alone (in order on one stream): where the time goes
+    stage_ms = stage_pass(False, 5)
 
     m = s.split_m or s.order // 2
     n_pairs = workmodel.count_pairs_within(s.pos64(), s.cutoff)
     work = workmodel.evaluation_work(s.n, n_pairs, nodes, s.cutoff, s.spacing, s.order, m)
     kernel_flops = {"short_range": work["short"], "lattice_cutoff": work["lattice"]}
-    dom = max(kernel_flops, key=lambda k: stage_ms.get(k, 0.0))
-    dom_s = stage_ms[dom] * 1e-3
+    dom = max(kernel_flops, key=lambda k: stage_live.get(k, 0.0))
+    dom_s = stage_live[dom] * 1e-3
     achieved = kernel_flops[dom] / dom_s / 1e12
+    alone = kernel_flops[dom] / (stage_ms[dom] * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                 "traffic": traffic_for(dom, s.name), "kernel": dom,
-                "kernel_ms": round(stage_ms[dom], 5), "kernel_flop": kernel_flops[dom]}
+                "kernel_ms": round(stage_live[dom], 5), "kernel_flop": kernel_flops[dom],
+                "kernel_ms_alone": round(stage_ms[dom], 5),
+                "frac_alone": round(alone / PEAK_FP32_TFLOPS, 4)}
 
     rec = {
         "metric": "MSM atom-evals/s (E+F)",
@@ -377,6 +398,7 @@ def main():
         "ms_per_launch_mode": {k: round(v[0] * 1e3, 5) for k, v in mode_sec.items()},
         "roofline": roofline,
         "stages_ms": {k: round(v, 5) for k, v in stage_ms.items()},
+        "stages_ms_live": {k: round(v, 5) for k, v in stage_live.items()},
         "algorithmic_tflops_per_step": round(work["total"] / sec / 1e12, 3),
         "algorithmic_flop_per_eval": work["total"],
         "unique_pairs": n_pairs,

@@ -224,12 +224,18 @@ msm_status msm_graph_destroy(msm_graph* graph);
  * results per sorted atom (float4 Fx,Fy,Fz,phi, without the prefactor). */
 msm_status msm_workspace_section(const msm_plan* plan, int32_t section, size_t* offset, size_t* bytes);
 
-/* Diagnostics: per-stage timing.  While enabled, msm_compute records HIP
- * events (created on the current device by this call) on its stream at the
- * boundaries of its 9 stages: binning, short range, anterpolation,
- * restriction, lattice cutoff, top level, prolongation, interpolation,
- * reduction.  msm_profile_read waits for the last evaluation and writes the
- * 9 stage durations in milliseconds to ms[0..8] (host). */
+/* Diagnostics: per-stage timing of msm_compute, for its 9 stages: binning,
+ * short range, anterpolation, restriction, lattice cutoff, top level,
+ * prolongation, interpolation, reduction.  enable: 0 off; 1 in order (every
+ * stage runs on the caller's stream, with a HIP event at each stage
+ * boundary, so a stage's time is its launches alone); 2 live (the tuned
+ * stream layout is kept and each stage's launches are bracketed by two
+ * events on the stream they run on, so a stage's time includes the slowdown
+ * from the stages that overlap it).  Events are created on the current
+ * device by the first enabling call.  msm_profile_read waits for the last
+ * evaluation timed since profiling was enabled and writes the 9 stage
+ * durations in milliseconds to ms[0..8] (host); it fails when no evaluation
+ * was timed. */
 msm_status msm_profile_enable(msm_plan* plan, int32_t enable);
 msm_status msm_profile_read(const msm_plan* plan, float* ms, int32_t* n_stages);
 

@@ -855,23 +855,39 @@ msm_status msm_plan_destroy(msm_plan* plan) {
 
 msm_status msm_profile_enable(msm_plan* P, int32_t enable) {
   if (!P) return fail(MSM_ERR_INVALID_ARG, "null plan");
+  if (enable < 0 || enable > 2) return fail(MSM_ERR_INVALID_ARG, "profile mode must be 0, 1 or 2");
   if (enable && !P->ev[0])
     for (auto& e : P->ev) {
       hipError_t r = hipEventCreate(&e);
       if (r != hipSuccess) return hip_fail(r, "create timing events");
     }
-  P->profile = enable != 0;
+  P->profile = enable;
+  P->profiled = false;
   return MSM_OK;
 }
 
 msm_status msm_profile_read(const msm_plan* P, float* ms, int32_t* n_stages) {
   if (!P || !ms || !n_stages) return fail(MSM_ERR_INVALID_ARG, "null argument");
   if (!P->profile) return fail(MSM_ERR_INVALID_ARG, "profiling is not enabled on this plan");
-  hipError_t r = hipEventSynchronize(P->ev[msm::kStageCount]);
-  if (r != hipSuccess) return hip_fail(r, "wait for timing events");
-  for (int i = 0; i < msm::kStageCount; ++i) {
-    r = hipEventElapsedTime(&ms[i], P->ev[i], P->ev[i + 1]);
-    if (r != hipSuccess) return hip_fail(r, "read timing events");
+  if (!P->profiled) return fail(MSM_ERR_INVALID_ARG, "no evaluation was timed since profiling was enabled");
+  hipError_t r;
+  if (P->profile == 1) {
+    r = hipEventSynchronize(P->ev[msm::kStageCount]);
+    if (r != hipSuccess) return hip_fail(r, "wait for timing events");
+    for (int i = 0; i < msm::kStageCount; ++i) {
+      r = hipEventElapsedTime(&ms[i], P->ev[i], P->ev[i + 1]);
+      if (r != hipSuccess) return hip_fail(r, "read timing events");
+    }
+  } else {
+    float slot[msm::kLiveSlots];
+    for (int i = 0; i < msm::kLiveSlots; ++i) {
+      r = hipEventSynchronize(P->ev[msm::kLiveSlots + i]);
+      if (r == hipSuccess) r = hipEventElapsedTime(&slot[i], P->ev[i], P->ev[msm::kLiveSlots + i]);
+      if (r != hipSuccess) return hip_fail(r, "read timing events");
+    }
+    for (int i = 0; i < msm::kStageCount; ++i) ms[i] = slot[i];
+    ms[msm::kStageShort] += slot[msm::kSlotShort2];
+    ms[msm::kStageLattice] += slot[msm::kSlotLattice0];
   }
   *n_stages = msm::kStageCount;
   return MSM_OK;
@@ -1015,7 +1031,8 @@ msm_status msm_compute(const msm_plan* P, void* ws, size_t ws_bytes, msm_stream_
   if (e != hipSuccess) return hip_fail(e, "create auxiliary stream");
   const msm::Io io{x, y, z, q, fx, fy, fz, phi, energy, virial, nullptr};
   e = msm::launch_eval(msm::kModeForces, launch_geom(P, ws), reinterpret_cast<hipStream_t>(stream), io,
-                       P->profile ? M->ev : nullptr, &M->aux.cc);
+                       P->profile ? M->ev : nullptr, &M->aux.cc, P->profile == 2);
+  if (P->profile) M->profiled = true;
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return MSM_OK;
 }

@@ -26,6 +26,7 @@ constexpr int kBinRowCells = 512;         // cells one block of the one-kernel b
 constexpr int kBinRowMaxBlocks = 256;     // blocks of the one-kernel binning per system at most
 constexpr int kStatusWords = 64 + kBinRowMaxBlocks;   // [0]: flags; [64 + b]: flags of binning block b
 constexpr int kScanTile = 4096;           // cells per block of the four-kernel binning's scan
+constexpr int kXcds = 8;                  // accelerator dies of the chip, each with its own L2
 
 enum DeviceFlag : int { kFlagOutOfBox = 1, kFlagNonFinite = 2, kFlagCoincident = 4 };
 
@@ -195,6 +196,10 @@ enum Stage : int {
   kStageBin = 0, kStageShort, kStageAnterp, kStageRestrict, kStageLattice, kStageTop,
   kStageProlong, kStageInterp, kStageReduce, kStageCount
 };
+// Live timing slots: the stages, the second short-range launch (when its work
+// is split) and the level-0 lattice cutoff on its side stream.
+enum LiveSlot : int { kSlotShort2 = kStageCount, kSlotLattice0, kLiveSlots };
+constexpr int kProfileEvents = 2 * kLiveSlots;   // enough for either timing mode
 
 // Everything one system's kernels read, resident in device memory (one entry
 // per system of a batch; a plain plan has one).
@@ -233,13 +238,24 @@ struct KArgs {
   Io io;
 };
 
+// The dispatcher hands workgroups to the kXcds dies in turn (workgroup b to
+// die b mod kXcds).  Numbering the logical blocks so that each die runs one
+// contiguous range of them keeps neighbouring tiles, which read the same atoms
+// and grid nodes, behind one L2 instead of fetching every input into all
+// eight.  A bijection of [0, n) for any n.
+__host__ __device__ inline int xcd_block(int b, int n) {
+  const int x = b % kXcds, i = b / kXcds, per = n / kXcds, rem = n % kXcds;
+  return x * per + (x < rem ? x : rem) + i;
+}
+
 __device__ inline const SysDesc& sys_of(const KArgs& a, int& blk) {
+  const int b = xcd_block((int)blockIdx.x, (int)gridDim.x);
   if (a.map) {
-    const int2 m = a.map[blockIdx.x];
+    const int2 m = a.map[b];
     blk = m.y;
     return a.sys[m.x];
   }
-  blk = blockIdx.x;
+  blk = b;
   return a.sys[0];
 }
 
@@ -326,12 +342,14 @@ struct Concurrency {
 };
 
 // Enqueues one evaluation (of every system of L) on `s` and returns the first
-// HIP error.  ev (nullable): kStageCount + 1 events recorded at the stage
-// boundaries (the evaluation then runs in order on `s`).  cc (nullable): side
-// streams for the concurrent branches, each joined back before its result is
-// needed.
+// HIP error.  cc (nullable): side streams for the concurrent branches, each
+// joined back before its result is needed.  ev (nullable): timing events.
+// With live false, kStageCount + 1 events recorded at the stage boundaries,
+// and the evaluation runs in order on `s`; with live true, the schedule is
+// kept and ev[slot] / ev[kLiveSlots + slot] bracket the launches of each
+// LiveSlot on the stream they run on.
 hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& io, hipEvent_t* ev,
-                       const Concurrency* cc);
+                       const Concurrency* cc, bool live = false);
 
 int interp_partials(const Geom& g);      // number of FP64 partial slots the forward pass uses
 

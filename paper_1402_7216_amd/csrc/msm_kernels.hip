@@ -2166,11 +2166,32 @@ hipError_t launch_init(const LaunchGeom& L, hipStream_t s) {
 }
 
 hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& io, hipEvent_t* ev,
-                       const Concurrency* cc) {
+                       const Concurrency* cc, bool live) {
   const bool forces = (mode != kModeEnergy);
   auto args = [&](const StageGrid& sg) { return KArgs{L.sys, sg.map, io}; };
+  // in-order timing: one event at every stage boundary on s
   auto mark = [&](int stage) {
-    if (ev) (void)hipEventRecord(ev[stage], s);
+    if (ev && !live) (void)hipEventRecord(ev[stage], s);
+  };
+  // live timing: a begin and an end event around each slot's launches, on the
+  // stream they run on; slots without work get an empty interval on s
+  bool recorded[kLiveSlots] = {};
+  auto beg = [&](int slot, hipStream_t st) {
+    if (ev && live) (void)hipEventRecord(ev[slot], st);
+  };
+  auto end = [&](int slot, hipStream_t st) {
+    if (ev && live) {
+      (void)hipEventRecord(ev[kLiveSlots + slot], st);
+      recorded[slot] = true;
+    }
+  };
+  auto finish = [&]() {
+    for (int slot = 0; slot < kLiveSlots; ++slot)
+      if (ev && live && !recorded[slot]) {
+        beg(slot, s);
+        end(slot, s);
+      }
+    return hipGetLastError();
   };
   // fork: `side` waits for everything enqueued on s so far
   auto fork = [&](const SideStream& side) {
@@ -2178,10 +2199,11 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
     (void)hipStreamWaitEvent(side.stream, side.fork, 0);
   };
   auto join = [&](const SideStream& side) { (void)hipStreamWaitEvent(s, side.join, 0); };
-  const bool concurrent = (cc != nullptr && ev == nullptr);   // stage timing runs in order
+  const bool concurrent = (cc != nullptr && (ev == nullptr || live));   // in-order timing runs in order
   const bool have_atoms = L.atoms.blocks > 0;
 
   mark(kStageBin);
+  beg(kStageBin, s);
   if (L.bin4) {
     if (have_atoms) k_bin_count<<<L.atoms.blocks, kBlock, 0, s>>>(args(L.atoms));
     k_scan_tiles<<<L.scan.blocks, kScanThreads, 0, s>>>(args(L.scan));
@@ -2203,6 +2225,7 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
     (void)hipFuncSetAttribute((const void*)k_bin_rows, hipFuncAttributeMaxDynamicSharedMemorySize, L.binrow_lds);
     k_bin_rows<<<L.binrow.blocks, kBRThreads, L.binrow_lds, s>>>(args(L.binrow));
   }
+  end(kStageBin, s);
 
   // short-range pairs: on their own stream (forked after binning,
   // anterpolation or the coarse lattice cutoff), joined before interpolation
@@ -2212,6 +2235,7 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
   // with a side stream, the work items [0, split) start at short_after and the
   // rest after the lattice cutoff
   const int split = (short_side && L.short_split > 0 && L.short_split < 1000) ? L.short_split : 1000;
+  int short_part = 0;
   auto launch_short = [&](int lo_pm, int hi_pm) {
     if (!(have_atoms && L.shortr.blocks > 0) || lo_pm >= hi_pm) return;
     hipStream_t ss = s;
@@ -2219,6 +2243,8 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
       fork(cc->shortr);
       ss = cc->shortr.stream;
     }
+    const int slot = short_part++ == 0 ? kStageShort : kSlotShort2;
+    beg(slot, ss);
     const KArgs A = args(L.shortr);
     const int nb = L.shortr.blocks;
 #define MSM_SHORT(MM)                                                          \
@@ -2245,6 +2271,7 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
       default: MSM_SHORT(7); break;
     }
 #undef MSM_SHORT
+    end(slot, ss);
     if (short_side) (void)hipEventRecord(cc->shortr.join, ss);
   };
   const int short_at = short_side ? L.short_after : 1;
@@ -2253,14 +2280,19 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
   if (L.pair != kPairMsm) {
     // a cheap pair method on its own: no grids
     for (int st = kStageAnterp; st <= kStageInterp; ++st) mark(st);
+    beg(kStageInterp, s);
     if (have_atoms) k_pair_finish<<<L.atoms.blocks, kBlock, 0, s>>>(args(L.atoms));
+    end(kStageInterp, s);
     mark(kStageReduce);
+    beg(kStageReduce, s);
     if (io.energy || io.virial) k_reduce<<<L.one.blocks, kBlock, 0, s>>>(args(L.one), 1);
+    end(kStageReduce, s);
     mark(kStageCount);
-    return hipGetLastError();
+    return finish();
   }
 
   mark(kStageAnterp);
+  beg(kStageAnterp, s);
   if (L.order == 4) {
     (void)hipFuncSetAttribute((const void*)k_anterp<4>, hipFuncAttributeMaxDynamicSharedMemorySize, L.anterp_lds);
     k_anterp<4><<<L.anterp.blocks, kAThreads, L.anterp_lds, s>>>(args(L.anterp));
@@ -2270,6 +2302,7 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
     k_anterp<6><<<L.anterp.blocks, kAThreads, L.anterp_lds, s>>>(args(L.anterp));
     k_anterp_gather<6><<<L.agather.blocks, kBlock, 0, s>>>(args(L.agather));
   }
+  end(kStageAnterp, s);
   if (short_at == 2) launch_short(0, split);
 
   // lattice cutoff of one part (0: level 0, 1: levels 1 .. l-2 and the top,
@@ -2298,11 +2331,14 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
   const bool lat0_side = concurrent && L.streams >= 3 && L.lattice0.blocks > 0;
   if (lat0_side) {
     fork(cc->lattice0);
+    beg(kSlotLattice0, cc->lattice0.stream);
     lattice(L.lattice0, 0, cc->lattice0.stream);
+    end(kSlotLattice0, cc->lattice0.stream);
     (void)hipEventRecord(cc->lattice0.join, cc->lattice0.stream);
   }
 
   mark(kStageRestrict);
+  beg(kStageRestrict, s);
   for (int k = 0; k + 1 < L.max_levels; ++k) {
     const StageGrid& sg = L.restrict_[k];
     if (sg.blocks == 0) continue;
@@ -2311,15 +2347,20 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
     else
       k_restrict<6><<<sg.blocks, kRThreads, 0, s>>>(args(sg), k);
   }
+  end(kStageRestrict, s);
   mark(kStageLattice);
+  beg(kStageLattice, s);
   if (lat0_side)
     lattice(L.lattice, 1, s);
   else
     lattice(L.lattice_all, 2, s);                      // every level (and the top) in one launch
+  end(kStageLattice, s);
   if (short_at == 3) launch_short(0, split);
   launch_short(split, 1000);
   mark(kStageTop);
+  beg(kStageTop, s);
   if (L.top.blocks > 0) k_top<<<L.top.blocks, kBlock, 0, s>>>(args(L.top));
+  end(kStageTop, s);
 
   if (mode == kModeEnergy) {
     mark(kStageProlong);
@@ -2327,14 +2368,17 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
     if (lat0_side) join(cc->lattice0);
     if (short_side) join(cc->shortr);
     mark(kStageReduce);
+    beg(kStageReduce, s);
     k_energy_terms<<<L.energy.blocks, kBlock, 0, s>>>(args(L.energy));
     k_reduce<<<L.one.blocks, kBlock, 0, s>>>(args(L.one), 0);
+    end(kStageReduce, s);
     mark(kStageCount);
-    return hipGetLastError();
+    return finish();
   }
 
   mark(kStageProlong);
   if (lat0_side) join(cc->lattice0);                 // u^0 adds the level-0 cutoff potential
+  beg(kStageProlong, s);
   if (L.prolong.blocks > 0) {
     const int lds = L.max_levels * prolong_box(L.order) * (int)sizeof(float);   // boxes + x-pass sums
     if (L.order == 4) {
@@ -2345,8 +2389,10 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
       k_prolong<6><<<L.prolong.blocks, kPThreads, lds, s>>>(args(L.prolong));
     }
   }
+  end(kStageProlong, s);
   mark(kStageInterp);
   if (short_side) join(cc->shortr);
+  beg(kStageInterp, s);
   if (have_atoms) {
     const KArgs A = args(L.atoms);
     const int nb = L.atoms.blocks;
@@ -2362,10 +2408,13 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
         k_interp<6, 0><<<nb, kBlock, 0, s>>>(A);
     }
   }
+  end(kStageInterp, s);
   mark(kStageReduce);
+  beg(kStageReduce, s);
   if (mode == kModeForces && (io.energy || io.virial)) k_reduce<<<L.one.blocks, kBlock, 0, s>>>(args(L.one), 1);
+  end(kStageReduce, s);
   mark(kStageCount);
-  return hipGetLastError();
+  return finish();
 }
 
 }  // namespace msm

@@ -47,8 +47,9 @@ struct msm_plan {
   msm::LaunchGeom lg;                        // stage grids of one evaluation (descriptor set per call)
   std::set<const void*> ready;               // workspaces initialised for this plan
   // optional stage timing (diagnostics); mutable state of an otherwise fixed plan
-  bool profile = false;
-  hipEvent_t ev[msm::kStageCount + 1] = {};
+  int profile = 0;                           // 0 off, 1 stages in order, 2 live schedule
+  bool profiled = false;                     // an evaluation was timed since profiling was enabled
+  hipEvent_t ev[msm::kProfileEvents] = {};
   AuxStreams aux;
 };
 

@@ -316,9 +316,11 @@ class Plan:
         code, _ = self.status()
         _check(code)
 
-    def profile(self, enable=True):
-        """Record per-stage HIP events inside every following compute()."""
-        _check(lib().msm_profile_enable(self._h, 1 if enable else 0))
+    def profile(self, enable=True, live=False):
+        """Record per-stage HIP events inside every following compute(): with
+        live=False every stage runs in order on the stream; with live=True the
+        tuned stream layout is kept and each stage is timed on its own stream."""
+        _check(lib().msm_profile_enable(self._h, (2 if live else 1) if enable else 0))
 
     def stage_ms(self):
         """Stage durations (ms) of the last compute(), keyed by stage name."""

@@ -192,3 +192,20 @@ def test_tuning_values_are_checked_before_any_device_work(M, field, value):
         assert cur.short_after == 1 and cur.short_split == 1000 and cur.cell_reach in (2, 3, 4)
     finally:
         M.lib().msm_plan_destroy(h)
+
+
+def test_profile_mode_and_read_are_checked_without_device(M):
+    """Timing modes are 0, 1 and 2; reading needs profiling on and a timed
+    evaluation.  Every refusal comes before any event is created."""
+    code, h = _plan(M, 10, **CASES[0])
+    assert code == 0
+    try:
+        ms = (ctypes.c_float * 16)()
+        n = ctypes.c_int32()
+        assert M.lib().msm_profile_enable(h, 3) == -1
+        assert M.lib().msm_profile_enable(h, -1) == -1
+        assert M.lib().msm_profile_read(h, ms, ctypes.byref(n)) == -1
+        assert M.lib().msm_profile_enable(h, 0) == 0
+        assert M.lib().msm_profile_read(h, ms, ctypes.byref(n)) == -1
+    finally:
+        M.lib().msm_plan_destroy(h)

@@ -193,6 +193,29 @@ def test_repeat_is_bitwise_identical(M):
     assert torch.equal(a["energy"], b["energy"])
 
 
+@pytest.mark.parametrize("streams", [1, 2, 3])
+def test_stage_timing_modes_keep_results_bitwise(M, streams):
+    """Both timing modes only add events: the results equal an untimed
+    evaluation bitwise, every stage time is finite and non-negative, and the
+    short range, the lattice cutoff and the interpolation take time."""
+    s = inputs.water_box(9000, seed=26, cutoff=10.0, spacing=2.0, order=4, levels=3)
+    plan = M.plan_for(s)
+    plan.tune(streams=streams, short_after=2, short_split=500)
+    x, y, z, q = M.to_device(s)
+    ref = {k: v.clone() for k, v in plan.compute(x, y, z, q).items()}
+    for live in (False, True, False):
+        plan.profile(True, live=live)
+        out = plan.compute(x, y, z, q)
+        ms = plan.stage_ms()
+        print(f"streams={streams} live={live} stage ms {ms}", flush=True)
+        assert torch.equal(out["f"], ref["f"]) and torch.equal(out["phi"], ref["phi"])
+        assert torch.equal(out["energy"], ref["energy"])
+        assert list(ms) == list(M.STAGES)
+        assert all(np.isfinite(v) and v >= 0.0 for v in ms.values())
+        assert ms["short_range"] > 0 and ms["lattice_cutoff"] > 0 and ms["interpolation"] > 0
+    plan.profile(False)
+
+
 def test_input_order_does_not_change_results_beyond_rounding(M):
     s = inputs.water_box(3000, seed=27, cutoff=9.0, spacing=2.0, order=4, levels=3)
     g0 = run_gpu(M, s)
