@@ -137,6 +137,20 @@ def cpu_leg(system, out):
     return base, parity(out, ref)
 
 
+TUNE_CACHE = None     # tuning cache consulted by autotune() (set in main)
+
+
+def autotune(obj, x, y, z, q, trials):
+    """Apply the cached tuning of a plan or batch when the cache holds its key;
+    otherwise run the search (the cache is never written here)."""
+    from paper_1402_7216_amd import msm
+    if TUNE_CACHE and msm.cache_lookup(TUNE_CACHE, obj.tuning_key()) is not None:
+        return obj.autotune(x, y, z, q, trials=trials, cache=TUNE_CACHE)
+    rep = obj.autotune(x, y, z, q, trials=trials)
+    rep["cache"] = "none"
+    return rep
+
+
 def coarse_leg(msm, torch, s, t_msm, steps, warmup, x, y, z, q):
     """The cheap pair methods the thesis proposes as coarse propagators G
     (plain cutoff, shifted-force smoothed cutoff, Wolf summation, rc = a,
@@ -149,7 +163,7 @@ def coarse_leg(msm, torch, s, t_msm, steps, warmup, x, y, z, q):
         out = plan.compute(x, y, z, q)
         torch.cuda.synchronize()
         plan.check()
-        plan.autotune(x, y, z, q, trials=10)
+        autotune(plan, x, y, z, q, 10)
         mean, med = event_timed(torch, lambda: plan.compute(x, y, z, q, out=out), steps, warmup)
         plan.check()
         res[kind] = {"ms": round(mean * 1e3, 5), "ms_median": round(med * 1e3, 5),
@@ -165,7 +179,7 @@ def water24k_leg(msm, torch, steps, warmup):
     out = plan.compute(x, y, z, q)
     torch.cuda.synchronize()
     plan.check()
-    plan.autotune(x, y, z, q, trials=20)
+    autotune(plan, x, y, z, q, 20)
     graph = msm.Graph(plan, x, y, z, q, out)
     modes = {"hipGraph replay": graph.launch, "eager": lambda: plan.compute(x, y, z, q, out=out)}
     res = {k: event_timed(torch, fn, steps, warmup) for k, fn in modes.items()}
@@ -187,7 +201,7 @@ def water100k_grad_leg(msm, torch, steps, warmup):
     plan.compute(x, y, z, q)
     torch.cuda.synchronize()
     plan.check()
-    plan.autotune(x, y, z, q, trials=10)
+    autotune(plan, x, y, z, q, 10)
     e = torch.empty(1, dtype=torch.float64, device="cuda")
     g = torch.ones(1, dtype=torch.float64, device="cuda")
     dpos = torch.empty((3, s.n), dtype=torch.float32, device="cuda")
@@ -206,7 +220,7 @@ def water100k_grad_leg(msm, torch, steps, warmup):
             "ms_forces_eval": round(fmean * 1e3, 5)}
 
 
-def batched_leg(msm, torch, workmodel, steps, warmup, autotune):
+def batched_leg(msm, torch, workmodel, steps, warmup, do_tune):
     """64 uneven water replicas (2,000-60,000 atoms, a = 10 A, h = 2 A): one
     batched graph replay against 64 single-system evaluations in sequence,
     forward (energy, forces, potentials) and forward + backward (energy, then
@@ -218,7 +232,7 @@ def batched_leg(msm, torch, workmodel, steps, warmup, autotune):
     out = b.compute(x, y, z, q)
     torch.cuda.synchronize()
     b.check()
-    best = b.autotune(x, y, z, q, trials=5)["best"] if autotune else None
+    best = autotune(b, x, y, z, q, 5)["best"] if do_tune else None
     graph = b.graph(x, y, z, q, out)
     plans = [msm.plan_for(s) for s in reps]
     ins = [msm.to_device(s) for s in reps]
@@ -288,6 +302,8 @@ def main():
     ap.add_argument("--launch", default="best", choices=("best", "hipGraph", "eager"),
                     help="launch mode to time (best: time both, report the faster)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the plan's default tuning")
+    ap.add_argument("--retune", action="store_true",
+                    help="run the autotuner's search even where the package's tuning cache has an entry")
     ap.add_argument("--tuning", default=None,
                     help="JSON tuning to apply instead of autotuning, e.g. the config.tuning of an "
                          "earlier run (for profiler passes over the timed configuration)")
@@ -309,6 +325,8 @@ def main():
     import torch
 
     from paper_1402_7216_amd import msm, workmodel
+    global TUNE_CACHE
+    TUNE_CACHE = None if args.retune or not os.path.exists(msm.TUNING_CACHE) else msm.TUNING_CACHE
 
     torch.cuda.set_device(0)
     if args.calibrate_copy:
@@ -327,10 +345,13 @@ def main():
     plan.check()
     levels, glo, gn = plan.info()
     nodes = [int(np.prod(v)) for v in gn]
+    tuning_source = "default"
     if args.tuning:
         plan.tune(**json.loads(args.tuning))
+        tuning_source = "--tuning"
     elif not args.no_autotune:
-        plan.autotune(x, y, z, q, trials=40 if s.n < 200000 else 10)
+        tune_rep = autotune(plan, x, y, z, q, 40 if s.n < 200000 else 10)
+        tuning_source = "cache " + plan.tuning_key() if tune_rep.get("cache") == "hit" else "search"
 
     graph = msm.Graph(plan, x, y, z, q, out)
     # both launch modes time the same evaluation; the faster one is reported
@@ -394,7 +415,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": describe_workload(s), "n_atoms": s.n, "cutoff": s.cutoff,
                    "spacing": s.spacing, "order": s.order, "levels": levels,
-                   "grid_sides": [int(v[0]) for v in gn], "launch": launch, "tuning": plan.tuning()},
+                   "grid_sides": [int(v[0]) for v in gn], "launch": launch, "tuning": plan.tuning(),
+                   "tuning_source": tuning_source},
         "ms_per_launch_mode": {k: round(v[0] * 1e3, 5) for k, v in mode_sec.items()},
         "roofline": roofline,
         "stages_ms": {k: round(v, 5) for k, v in stage_ms.items()},

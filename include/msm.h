@@ -281,6 +281,32 @@ msm_status msm_plan_autotune(msm_plan* plan, void* ws, size_t ws_bytes, msm_stre
                              const float* x, const float* y, const float* z, const float* q,
                              int32_t trials, char* report, size_t report_bytes);
 
+/* Tuning cache (host files, no device work).  A cache is a text file with one
+ * line per key: "<key> lattice_b item_chunks short_blocks streams short_after
+ * short_split cell_reach" ('#' starts a comment line).  A key names what the
+ * best tuning depends on: target (gfx950), interpolation order, smoothing
+ * degree, level-0 stencil taps and, rounded to half octaves, the level-0 node
+ * count and the atom count; a batch key adds the system count and uses the
+ * largest stencil and the totals.  msm_*_tuning_key writes the key (with its
+ * terminating zero) to key[key_bytes]; it fails when the buffer is too small.
+ * msm_tuning_cache_lookup: MSM_OK with *tuning filled when the entry exists,
+ * MSM_ERR_UNSUPPORTED when the file or the entry does not (*tuning
+ * untouched), MSM_ERR_INVALID_ARG for a malformed or out-of-range entry.
+ * msm_tuning_cache_store adds or replaces the key's entry; the file is
+ * written beside the old one and renamed over it, so concurrent readers see
+ * one or the other.  Keys contain no white space and no '#'.
+ * msm_plan_autotune_cached / msm_batch_autotune_cached: with a cache entry
+ * for the plan's key, apply it without timing anything; otherwise run the
+ * autotuner and store its result (cache null: autotune, store nothing).  The
+ * JSON report gives the key, "cache": "hit" | "miss" | "none", and the
+ * applied tuning or the search. */
+msm_status msm_plan_tuning_key(const msm_plan* plan, char* key, size_t key_bytes);
+msm_status msm_tuning_cache_lookup(const char* path, const char* key, msm_tuning* tuning);
+msm_status msm_tuning_cache_store(const char* path, const char* key, const msm_tuning* tuning);
+msm_status msm_plan_autotune_cached(msm_plan* plan, void* ws, size_t ws_bytes, msm_stream_t stream,
+                                    const float* x, const float* y, const float* z, const float* q,
+                                    int32_t trials, const char* cache, char* report, size_t report_bytes);
+
 /* ------------------------------------------------------------------------ */
 /* Batches: n_sys independent systems (replicas of uneven size) evaluated
  * together.  Every stage is one launch covering all systems, so a batch costs
@@ -326,6 +352,10 @@ msm_status msm_batch_tune(msm_batch* batch, void* ws, size_t ws_bytes, msm_strea
 msm_status msm_batch_autotune(msm_batch* batch, void* ws, size_t ws_bytes, msm_stream_t stream,
                               const float* x, const float* y, const float* z, const float* q,
                               int32_t trials, char* report, size_t report_bytes);
+msm_status msm_batch_tuning_key(const msm_batch* batch, char* key, size_t key_bytes);
+msm_status msm_batch_autotune_cached(msm_batch* batch, void* ws, size_t ws_bytes, msm_stream_t stream,
+                                     const float* x, const float* y, const float* z, const float* q,
+                                     int32_t trials, const char* cache, char* report, size_t report_bytes);
 
 const char* msm_status_string(msm_status status);
 const char* msm_last_error(void);

@@ -5,10 +5,16 @@
 // plans and batches.
 #include <hip/hip_runtime.h>
 
+#include <unistd.h>
+
 #include <algorithm>
+#include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <new>
 #include <set>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -603,6 +609,205 @@ static msm_status autotune(bool batch, void* obj, void* ws, size_t ws_bytes, msm
     report[report_bytes - 1] = 0;
   }
   return MSM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Tuning cache: one text line per key, "<key> lattice_b item_chunks
+// short_blocks streams short_after short_split cell_reach"; '#' starts a
+// comment line.  The key names what the best tuning depends on: the target,
+// the interpolation order, the smoothing degree, the level-0 stencil taps and,
+// rounded to half octaves, the level-0 node count and the atom count.
+// ---------------------------------------------------------------------------
+static int stencil_taps(double a, double h) {
+  if (!(h > 0.0) || !(a > 0.0) || 2.0 * a / h > 1024.0) return 0;
+  const double R = 2.0 * a / h;
+  const int r = (int)std::floor(R);
+  int n = 0;
+  for (int i = -r; i <= r; ++i)
+    for (int j = -r; j <= r; ++j)
+      for (int k = -r; k <= r; ++k)
+        if ((double)(i * i + j * j + k * k) < R * R) ++n;
+  return n;
+}
+
+static int half_octave(double v) { return v > 0 ? (int)std::lround(2.0 * std::log2(v)) : -1; }
+
+static msm_status write_key(const std::string& k, char* key, size_t key_bytes) {
+  if (!key || key_bytes <= k.size()) return fail(MSM_ERR_INVALID_ARG, "key buffer missing or too small");
+  std::memcpy(key, k.c_str(), k.size() + 1);
+  return MSM_OK;
+}
+
+static std::string plan_key(const msm_plan* P) {
+  char b[160];
+  if (P->g.pair != msm::kPairMsm) {   // a cheap pair method: no grids
+    std::snprintf(b, sizeof b, "gfx950/pair%d/a%ld/n%d", P->g.pair, std::lround(10.0 * P->p.cutoff),
+                  half_octave(P->g.n_atoms));
+    return b;
+  }
+  std::snprintf(b, sizeof b, "gfx950/o%d/m%d/S%d/g%d/n%d", P->g.order, P->g.m,
+                stencil_taps(P->p.cutoff, P->p.spacing), half_octave(P->g.lv[0].count),
+                half_octave(P->g.n_atoms));
+  return b;
+}
+
+static std::string batch_key(const msm_batch* Bt) {
+  int taps = 0;
+  double nodes = 0;
+  for (const msm_plan* P : Bt->plans) {
+    taps = std::max(taps, stencil_taps(P->p.cutoff, P->p.spacing));
+    nodes += P->g.lv[0].count;
+  }
+  const msm_plan* P0 = Bt->plans[0];
+  char b[160];
+  std::snprintf(b, sizeof b, "gfx950/batch%d/o%d/m%d/S%d/g%d/n%d", Bt->n_sys, P0->g.order, P0->g.m, taps,
+                half_octave(nodes), half_octave((double)Bt->total_atoms));
+  return b;
+}
+
+static bool valid_key(const char* key) {
+  if (!key || !*key) return false;
+  for (const char* c = key; *c; ++c)
+    if (*c == ' ' || *c == '\t' || *c == '\n' || *c == '\r' || *c == '#') return false;
+  return true;
+}
+
+static std::string tuning_fields(const msm_tuning& t) {
+  return std::to_string(t.lattice_b) + " " + std::to_string(t.item_chunks) + " " + std::to_string(t.short_blocks) +
+         " " + std::to_string(t.streams) + " " + std::to_string(t.short_after) + " " +
+         std::to_string(t.short_split) + " " + std::to_string(t.cell_reach);
+}
+
+static std::string describe_tuning(const msm_tuning& t) {
+  return "\"lattice_b\": " + std::to_string(t.lattice_b) + ", \"item_chunks\": " + std::to_string(t.item_chunks) +
+         ", \"short_blocks\": " + std::to_string(t.short_blocks) + ", \"streams\": " +
+         std::to_string(t.streams) + ", \"short_after\": " + std::to_string(t.short_after) +
+         ", \"short_split\": " + std::to_string(t.short_split) + ", \"cell_reach\": " +
+         std::to_string(t.cell_reach);
+}
+
+static void put_report(const std::string& rep, char* report, size_t report_bytes) {
+  if (report && report_bytes) {
+    std::strncpy(report, rep.c_str(), report_bytes - 1);
+    report[report_bytes - 1] = 0;
+  }
+}
+
+msm_status msm_plan_tuning_key(const msm_plan* P, char* key, size_t key_bytes) {
+  if (!P) return fail(MSM_ERR_INVALID_ARG, "null plan");
+  return write_key(plan_key(P), key, key_bytes);
+}
+
+msm_status msm_batch_tuning_key(const msm_batch* Bt, char* key, size_t key_bytes) {
+  if (!Bt) return fail(MSM_ERR_INVALID_ARG, "null batch");
+  return write_key(batch_key(Bt), key, key_bytes);
+}
+
+msm_status msm_tuning_cache_lookup(const char* path, const char* key, msm_tuning* tuning) {
+  if (!path || !tuning || !valid_key(key)) return fail(MSM_ERR_INVALID_ARG, "null path or tuning, or bad key");
+  std::ifstream f(path);
+  if (!f) return fail(MSM_ERR_UNSUPPORTED, std::string("no tuning cache at ") + path);
+  std::string line;
+  while (std::getline(f, line)) {
+    if (line.empty() || line[0] == '#') continue;
+    std::istringstream in(line);
+    std::string k;
+    in >> k;
+    if (k != key) continue;
+    msm_tuning t{};
+    in >> t.lattice_b >> t.item_chunks >> t.short_blocks >> t.streams >> t.short_after >> t.short_split >>
+        t.cell_reach;
+    std::string rest;
+    if (in.fail() || (in >> rest)) return fail(MSM_ERR_INVALID_ARG, "malformed tuning cache entry: " + line);
+    const msm_status st = check_tuning(&t);
+    if (st != MSM_OK) return st;
+    *tuning = t;
+    return MSM_OK;
+  }
+  return fail(MSM_ERR_UNSUPPORTED, std::string("no entry for ") + key + " in " + path);
+}
+
+msm_status msm_tuning_cache_store(const char* path, const char* key, const msm_tuning* tuning) {
+  if (!path || !valid_key(key)) return fail(MSM_ERR_INVALID_ARG, "null path or bad key");
+  msm_status st = check_tuning(tuning);
+  if (st != MSM_OK) return st;
+  std::vector<std::string> lines;
+  {
+    std::ifstream f(path);
+    std::string line;
+    while (f && std::getline(f, line)) {
+      std::istringstream in(line);
+      std::string k;
+      in >> k;
+      if (line.empty() || line[0] == '#' || k != key) lines.push_back(line);
+    }
+  }
+  lines.push_back(std::string(key) + " " + tuning_fields(*tuning));
+  // written beside the file and renamed over it: readers see the old or the new file
+  const std::string tmp = std::string(path) + ".tmp" + std::to_string((long)getpid());
+  {
+    std::ofstream o(tmp, std::ios::trunc);
+    if (!o) return fail(MSM_ERR_INVALID_ARG, "cannot write " + tmp);
+    for (const std::string& l : lines) o << l << "\n";
+    o.flush();
+    if (!o) return fail(MSM_ERR_INVALID_ARG, "cannot write " + tmp);
+  }
+  if (std::rename(tmp.c_str(), path) != 0) {
+    std::remove(tmp.c_str());
+    return fail(MSM_ERR_INVALID_ARG, std::string("cannot replace ") + path);
+  }
+  return MSM_OK;
+}
+
+// Autotune through the cache: a hit applies the stored tuning without timing
+// anything; a miss runs the search and stores its result.
+static msm_status autotune_cached(bool batch, void* obj, const std::string& key, void* ws, size_t ws_bytes,
+                                  msm_stream_t stream, const float* x, const float* y, const float* z,
+                                  const float* q, int32_t trials, const char* cache, char* report,
+                                  size_t report_bytes) {
+  msm_batch* Bt = batch ? static_cast<msm_batch*>(obj) : nullptr;
+  msm_plan* P = batch ? nullptr : static_cast<msm_plan*>(obj);
+  msm_tuning t{};
+  const std::string hdr = "{\"key\": \"" + key + "\", ";
+  if (cache && msm_tuning_cache_lookup(cache, key.c_str(), &t) == MSM_OK) {
+    const msm_status st =
+        batch ? msm_batch_tune(Bt, ws, ws_bytes, stream, &t) : msm_plan_tune(P, ws, ws_bytes, stream, &t);
+    if (st != MSM_OK) return st;
+    put_report(hdr + "\"cache\": \"hit\", \"best\": {" + describe_tuning(t) + "}}", report, report_bytes);
+    return MSM_OK;
+  }
+  std::vector<char> inner(std::max<size_t>(report_bytes, 1), 0);
+  msm_status st = autotune(batch, obj, ws, ws_bytes, stream, x, y, z, q, trials, inner.data(), inner.size());
+  if (st != MSM_OK) return st;
+  st = batch ? msm_plan_tuning(Bt->plans[0], &t) : msm_plan_tuning(P, &t);
+  if (st != MSM_OK) return st;
+  if (cache) {
+    st = msm_tuning_cache_store(cache, key.c_str(), &t);
+    if (st != MSM_OK) return st;
+  }
+  put_report(hdr + "\"cache\": \"" + (cache ? "miss" : "none") + "\", \"search\": " + std::string(inner.data()) +
+                 "}",
+             report, report_bytes);
+  return MSM_OK;
+}
+
+msm_status msm_plan_autotune_cached(msm_plan* P, void* ws, size_t ws_bytes, msm_stream_t stream, const float* x,
+                                    const float* y, const float* z, const float* q, int32_t trials,
+                                    const char* cache, char* report, size_t report_bytes) {
+  if (!P) return fail(MSM_ERR_INVALID_ARG, "null plan");
+  if (trials < 1) return fail(MSM_ERR_INVALID_ARG, "trials must be >= 1");
+  return autotune_cached(false, P, plan_key(P), ws, ws_bytes, stream, x, y, z, q, trials, cache, report,
+                         report_bytes);
+}
+
+msm_status msm_batch_autotune_cached(msm_batch* Bt, void* ws, size_t ws_bytes, msm_stream_t stream,
+                                     const float* x, const float* y, const float* z, const float* q,
+                                     int32_t trials, const char* cache, char* report, size_t report_bytes) {
+  msm_status st = check_batch(Bt, ws, ws_bytes);
+  if (st != MSM_OK) return st;
+  if (trials < 1) return fail(MSM_ERR_INVALID_ARG, "trials must be >= 1");
+  return autotune_cached(true, Bt, batch_key(Bt), ws, ws_bytes, stream, x, y, z, q, trials, cache, report,
+                         report_bytes);
 }
 
 msm_status msm_plan_autotune(msm_plan* P, void* ws, size_t ws_bytes, msm_stream_t stream,

@@ -28,11 +28,16 @@ EXPORTS = ("msm_plan_create", "msm_pair_plan_create", "msm_plan_destroy", "msm_p
            "msm_workspace_section",
            "msm_profile_enable", "msm_profile_read", "msm_graph_capture", "msm_graph_launch",
            "msm_graph_destroy", "msm_plan_tune", "msm_plan_tuning", "msm_plan_autotune",
+           "msm_plan_tuning_key", "msm_tuning_cache_lookup", "msm_tuning_cache_store",
+           "msm_plan_autotune_cached", "msm_batch_tuning_key", "msm_batch_autotune_cached",
            "msm_batch_create", "msm_batch_destroy", "msm_batch_workspace_bytes",
            "msm_batch_atom_offsets", "msm_batch_workspace_init", "msm_batch_compute",
            "msm_batch_energy", "msm_batch_backward", "msm_batch_graph_capture", "msm_batch_status",
            "msm_batch_describe", "msm_batch_tune", "msm_batch_autotune",
            "msm_status_string", "msm_last_error")
+
+# tunings measured on MI355X for the named workloads (see msm_tuning_cache_lookup)
+TUNING_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx950.txt")
 
 STAGES = ("binning", "short_range", "anterpolation", "restriction", "lattice_cutoff", "top_level",
           "prolongation", "interpolation", "reduction")
@@ -54,6 +59,22 @@ def make_tuning(lattice_b=0, item_chunks=0, short_blocks=0, streams=0, short_aft
     t.streams, t.short_after, t.short_split = int(streams), int(short_after), int(short_split)
     t.cell_reach, t.reserved = int(cell_reach), 0
     return t
+
+
+def cache_lookup(path, key):
+    """The tuning stored under key in a cache file (a dict), or None."""
+    t = Tuning()
+    code = lib().msm_tuning_cache_lookup(os.fsencode(path), key.encode(), ctypes.byref(t))
+    if code == -6:
+        return None
+    _check(code)
+    return {k: getattr(t, k) for k in TUNING_KEYS}
+
+
+def cache_store(path, key, **tuning):
+    """Add or replace key's entry in a cache file."""
+    t = make_tuning(**tuning)
+    _check(lib().msm_tuning_cache_store(os.fsencode(path), key.encode(), ctypes.byref(t)))
 
 
 class MSMError(RuntimeError):
@@ -110,6 +131,14 @@ def lib():
         L.msm_plan_tune.argtypes = [vp, vp, sz, vp, ctypes.POINTER(Tuning)]
         L.msm_plan_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
         L.msm_plan_autotune.argtypes = [vp, vp, sz, vp] + [vp] * 4 + [i32, ctypes.c_char_p, sz]
+        L.msm_plan_tuning_key.argtypes = [vp, ctypes.c_char_p, sz]
+        L.msm_batch_tuning_key.argtypes = [vp, ctypes.c_char_p, sz]
+        L.msm_tuning_cache_lookup.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(Tuning)]
+        L.msm_tuning_cache_store.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(Tuning)]
+        L.msm_plan_autotune_cached.argtypes = [vp, vp, sz, vp] + [vp] * 4 + [i32, ctypes.c_char_p,
+                                                                              ctypes.c_char_p, sz]
+        L.msm_batch_autotune_cached.argtypes = [vp, vp, sz, vp] + [vp] * 4 + [i32, ctypes.c_char_p,
+                                                                               ctypes.c_char_p, sz]
         L.msm_batch_create.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(i32), i32, ctypes.POINTER(vp)]
         L.msm_batch_destroy.argtypes = [vp]
         L.msm_batch_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
@@ -297,14 +326,26 @@ class Plan:
         _check(lib().msm_plan_tuning(self._h, ctypes.byref(t)))
         return {k: getattr(t, k) for k in TUNING_KEYS}
 
-    def autotune(self, x, y, z, q, trials=5):
-        """Time the tuning candidates on these inputs, keep the fastest, return the search."""
+    def autotune(self, x, y, z, q, trials=5, cache=None):
+        """Time the tuning candidates on these inputs, keep the fastest, return
+        the search.  With a cache file: apply its entry for this plan's key if
+        there is one (nothing timed), else search and store the result."""
         import json
         self._check_inputs(x, y, z, q)
         buf = ctypes.create_string_buffer(1 << 14)
-        _check(lib().msm_plan_autotune(self._h, _ptr(self.ws), self.ws.numel(), _stream(), _ptr(x),
-                                       _ptr(y), _ptr(z), _ptr(q), int(trials), buf, len(buf)))
+        if cache is None:
+            _check(lib().msm_plan_autotune(self._h, _ptr(self.ws), self.ws.numel(), _stream(), _ptr(x),
+                                           _ptr(y), _ptr(z), _ptr(q), int(trials), buf, len(buf)))
+        else:
+            _check(lib().msm_plan_autotune_cached(self._h, _ptr(self.ws), self.ws.numel(), _stream(), _ptr(x),
+                                                  _ptr(y), _ptr(z), _ptr(q), int(trials),
+                                                  os.fsencode(cache), buf, len(buf)))
         return json.loads(buf.value.decode())
+
+    def tuning_key(self) -> str:
+        buf = ctypes.create_string_buffer(256)
+        _check(lib().msm_plan_tuning_key(self._h, buf, len(buf)))
+        return buf.value.decode()
 
     def status(self):
         """Synchronise and return (status code, raw device flags) of the last evaluation."""
@@ -550,13 +591,23 @@ class Batch:
         t = make_tuning(lattice_b, item_chunks, short_blocks, streams, short_after, short_split, cell_reach)
         _check(lib().msm_batch_tune(self._h, _ptr(self.ws), self.ws.numel(), _stream(), ctypes.byref(t)))
 
-    def autotune(self, x, y, z, q, trials=3):
+    def autotune(self, x, y, z, q, trials=3, cache=None):
         import json
         self._check_inputs(x, y, z, q)
         buf = ctypes.create_string_buffer(1 << 14)
-        _check(lib().msm_batch_autotune(self._h, _ptr(self.ws), self.ws.numel(), _stream(), _ptr(x), _ptr(y),
-                                        _ptr(z), _ptr(q), int(trials), buf, len(buf)))
+        if cache is None:
+            _check(lib().msm_batch_autotune(self._h, _ptr(self.ws), self.ws.numel(), _stream(), _ptr(x),
+                                            _ptr(y), _ptr(z), _ptr(q), int(trials), buf, len(buf)))
+        else:
+            _check(lib().msm_batch_autotune_cached(self._h, _ptr(self.ws), self.ws.numel(), _stream(), _ptr(x),
+                                                   _ptr(y), _ptr(z), _ptr(q), int(trials),
+                                                   os.fsencode(cache), buf, len(buf)))
         return json.loads(buf.value.decode())
+
+    def tuning_key(self) -> str:
+        buf = ctypes.create_string_buffer(256)
+        _check(lib().msm_batch_tuning_key(self._h, buf, len(buf)))
+        return buf.value.decode()
 
 
 class _BatchGraph:

@@ -209,3 +209,88 @@ def test_profile_mode_and_read_are_checked_without_device(M):
         assert M.lib().msm_profile_read(h, ms, ctypes.byref(n)) == -1
     finally:
         M.lib().msm_plan_destroy(h)
+
+
+def _key(M, fn, h):
+    buf = ctypes.create_string_buffer(256)
+    assert fn(h, buf, len(buf)) == 0
+    small = ctypes.create_string_buffer(8)
+    assert fn(h, small, len(small)) == -1
+    return buf.value.decode()
+
+
+def _taps(a, h):
+    R = 2.0 * a / h
+    r = int(np.floor(R))
+    g = np.arange(-r, r + 1)
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    return int(((X * X + Y * Y + Z * Z) < R * R).sum())
+
+
+def test_tuning_keys_name_what_the_tuning_depends_on(M):
+    """Plan key: target, order, smoothing degree, level-0 stencil taps and the
+    half-octave level-0 node and atom counts; batch key adds the system count."""
+    prm = CASES[2]                                   # the 1M-atom water box geometry
+    code, h = _plan(M, 999999, **prm)
+    assert code == 0
+    try:
+        key = _key(M, M.lib().msm_plan_tuning_key, h)
+        L, lo, n = _info(M, h)
+        nodes0 = int(np.prod(n[0]))
+        assert key == (f"gfx950/o6/m3/S{_taps(12.0, 2.5)}/g{round(2 * np.log2(nodes0))}"
+                       f"/n{round(2 * np.log2(999999))}")
+        assert _taps(12.0, 2.5) == 3743
+    finally:
+        M.lib().msm_plan_destroy(h)
+    reps = inputs.water_replicas(64)
+    code, hb = _batch(M, [{**r.params()} for r in reps], [r.n for r in reps])
+    assert code == 0
+    try:
+        key = _key(M, M.lib().msm_batch_tuning_key, hb)
+        assert key.startswith(f"gfx950/batch64/o4/m2/S{_taps(10.0, 2.0)}/g")
+        assert key.endswith(f"/n{round(2 * np.log2(sum(r.n for r in reps)))}")
+    finally:
+        M.lib().msm_batch_destroy(hb)
+
+
+def test_tuning_cache_store_lookup_replace(M, tmp_path):
+    path = str(tmp_path / "cache.txt")
+    assert M.cache_lookup(path, "gfx950/o4/m2/S1/g1/n1") is None          # no file
+    M.cache_store(path, "gfx950/o4/m2/S1/g1/n1", lattice_b=6, item_chunks=2, short_blocks=-1, streams=3,
+                  short_after=2, short_split=500, cell_reach=3)
+    M.cache_store(path, "gfx950/o6/m3/S2/g2/n2", lattice_b=4, item_chunks=1, short_blocks=512, streams=2,
+                  short_after=1, short_split=1000, cell_reach=2)
+    assert M.cache_lookup(path, "gfx950/o4/m2/S1/g1/n1") == dict(
+        lattice_b=6, item_chunks=2, short_blocks=-1, streams=3, short_after=2, short_split=500, cell_reach=3)
+    assert M.cache_lookup(path, "gfx950/o4/m2/S9/g1/n1") is None           # no entry
+    # replacing keeps one line per key and the other entries
+    M.cache_store(path, "gfx950/o4/m2/S1/g1/n1", lattice_b=8, item_chunks=1, short_blocks=-1, streams=1,
+                  short_after=1, short_split=1000, cell_reach=2)
+    lines = [l for l in open(path).read().splitlines() if l and not l.startswith("#")]
+    assert len(lines) == 2 and lines[-1].split()[1] == "8"
+    assert M.cache_lookup(path, "gfx950/o6/m3/S2/g2/n2")["short_blocks"] == 512
+    assert not [p for p in os.listdir(tmp_path) if ".tmp" in p]
+    # bad keys and values are refused; malformed files are reported
+    t = M.make_tuning(4, 1, -1, 2, 1, 1000, 2)
+    assert M.lib().msm_tuning_cache_store(path.encode(), b"has space", ctypes.byref(t)) == -1
+    assert M.lib().msm_tuning_cache_store(path.encode(), b"a#b", ctypes.byref(t)) == -1
+    bad = M.make_tuning(5, 1, -1, 2, 1, 1000, 2)
+    assert M.lib().msm_tuning_cache_store(path.encode(), b"k", ctypes.byref(bad)) == -1
+    with open(path, "a") as f:
+        f.write("# comment line\nbroken 4 1\nrange 4 1 -1 9 1 1000 2\n")
+    assert M.cache_lookup(path, "gfx950/o6/m3/S2/g2/n2")["lattice_b"] == 4
+    with pytest.raises(M.MSMError):
+        M.cache_lookup(path, "broken")
+    with pytest.raises(M.MSMError):
+        M.cache_lookup(path, "range")
+
+
+def test_committed_tuning_cache_entries_are_valid(M):
+    path = M.TUNING_CACHE
+    if not os.path.exists(path):
+        pytest.skip("no committed tuning cache")
+    keys = [l.split()[0] for l in open(path).read().splitlines() if l and not l.startswith("#")]
+    assert keys and len(keys) == len(set(keys))
+    for k in keys:
+        assert k.startswith("gfx950/")
+        assert M.cache_lookup(path, k) is not None
