@@ -20,7 +20,14 @@ Prints one JSON line.  Besides the timed steps it reports
     the FP64 CPU oracle on the same inputs;
   * cpu_baseline: that oracle run, timed on the host cores (plus one-thread
     times of the 1,000-atom cloud and the 24,000-atom water box);
-  * extras: the 24,000-atom box, the 100,000-atom box through the
+  * coarse_propagators / cheap_msm_propagators: the cheap pair methods
+    (cutoff, shifted-force smoothed cutoff, Wolf) and MSM with a 4x coarser
+    finest grid or a 6 A cutoff on the same inputs, as parareal coarse
+    functions G: time, Q_F/G against the timed evaluation F, and their
+    force / energy distance from F;
+  * extras: a parareal window (batched MSM fine propagator, shifted-force
+    coarse propagator) on a 27,000-ion cluster against sequential steps,
+    the 24,000-atom box, the 100,000-atom box through the
     differentiable path (energy, then backward), and the 64-replica batch
     (forward, and forward + backward) against 64 sequential evaluations.
 """
@@ -151,12 +158,20 @@ def autotune(obj, x, y, z, q, trials):
     return rep
 
 
-def coarse_leg(msm, torch, s, t_msm, steps, warmup, x, y, z, q):
+def _vs_ref(torch, out, ref):
+    """Force relative RMS and energy relative difference of `out` against `ref`."""
+    df = (out["f"].double() - ref["f"].double()).pow(2).sum()
+    f = float(torch.sqrt(df / ref["f"].double().pow(2).sum()).item())
+    e, e0 = float(out["energy"].item()), float(ref["energy"].item())
+    return f, abs(e - e0) / abs(e0)
+
+
+def coarse_leg(msm, torch, s, t_msm, steps, warmup, x, y, z, q, ref):
     """The cheap pair methods the thesis proposes as coarse propagators G
     (plain cutoff, shifted-force smoothed cutoff, Wolf summation, rc = a,
     Wolf alpha = 0.2 / A) on the same inputs, each autotuned over its cell
     knobs; Q_F/G = t(MSM) / t(G), the ratio the thesis estimates as about 60
-    from operation counts."""
+    from operation counts, and each G's distance from the MSM result F."""
     res = {}
     for kind in ("cutoff", "shifted_force", "wolf"):
         plan = msm.pair_plan_for(s, kind, alpha=0.2)
@@ -166,10 +181,105 @@ def coarse_leg(msm, torch, s, t_msm, steps, warmup, x, y, z, q):
         autotune(plan, x, y, z, q, 10)
         mean, med = event_timed(torch, lambda: plan.compute(x, y, z, q, out=out), steps, warmup)
         plan.check()
+        out = plan.compute(x, y, z, q, out=out)
+        f_err, e_err = _vs_ref(torch, out, ref)
         res[kind] = {"ms": round(mean * 1e3, 5), "ms_median": round(med * 1e3, 5),
                      "atom_evals_per_s": s.n / mean, "q_f_over_g": round(t_msm / mean, 3),
+                     "force_rel_rms_vs_F": round(f_err, 6), "energy_rel_vs_F": round(e_err, 6),
                      "tuning": plan.tuning()}
     return res
+
+
+def cheap_msm_leg(msm, torch, workmodel, s, t_msm, work_f, steps, warmup, x, y, z, q, ref):
+    """MSM itself as the coarse propagator G, on the same inputs: the finest
+    grid four times coarser (h -> 4h), or the finest-grid cutoff halved
+    (a = 6 A, every level's cutoff halving with it).  Reports the measured
+    Q_F/G, the FLOP-model ratio of the two evaluations, and G's distance from
+    F."""
+    import dataclasses
+    res = {}
+    for name, kw in (("coarse_grid_4h", dict(spacing=4.0 * s.spacing)), ("short_cutoff_6A", dict(cutoff=6.0))):
+        v = dataclasses.replace(s, **kw)
+        plan = msm.plan_for(v)
+        out = plan.compute(x, y, z, q)
+        torch.cuda.synchronize()
+        plan.check()
+        autotune(plan, x, y, z, q, 10)
+        mean, med = event_timed(torch, lambda: plan.compute(x, y, z, q, out=out), steps, warmup)
+        plan.check()
+        out = plan.compute(x, y, z, q, out=out)
+        f_err, e_err = _vs_ref(torch, out, ref)
+        levels, _, gn = plan.info()
+        nodes = [int(v_[0]) * int(v_[1]) * int(v_[2]) for v_ in gn]
+        pairs = workmodel.count_pairs_within(v.pos64(), v.cutoff)
+        work = workmodel.evaluation_work(v.n, pairs, nodes, v.cutoff, v.spacing, v.order,
+                                         v.split_m or v.order // 2)
+        res[name] = {"cutoff": v.cutoff, "spacing": v.spacing, "levels": levels,
+                     "ms": round(mean * 1e3, 5), "ms_median": round(med * 1e3, 5),
+                     "q_f_over_g": round(t_msm / mean, 3),
+                     "q_f_over_g_flop_model": round(work_f / work["total"], 3),
+                     "force_rel_rms_vs_F": round(f_err, 6), "energy_rel_vs_F": round(e_err, 6),
+                     "tuning": plan.tuning()}
+    return res
+
+
+def parareal_leg(msm, torch, reps=3):
+    """One parareal window on a 27,000-ion rock-salt cluster (a = 12 A, h = 2
+    A, cubic): T = 8 slices of 5 velocity Verlet steps of 1 fs, fine
+    propagator MSM over all slices as one batched evaluation per force call,
+    coarse propagator the shifted-force cutoff; stops when no position changes
+    by more than 1e-4 A.  Against the same 40 steps run sequentially with the
+    single-system MSM plan."""
+    from paper_1402_7216_amd import inputs
+    T, steps, dt, tol = 8, 5, 1.0, 1e-4
+    ions = inputs.rock_salt(30, seed=31, cutoff=12.0, grid=2.0)
+    s = ions.system
+    x, y, z, q = msm.to_device(s)
+    pos0 = torch.stack([x, y, z]).contiguous()
+    vel0 = torch.from_numpy(ions.vel).cuda().contiguous()
+    im = torch.from_numpy(ions.inv_mass).cuda()
+    state0 = torch.cat([pos0, vel0]).contiguous()
+    plan = msm.plan_for(s)
+    autotune(plan, x, y, z, q, 10)
+    fine = msm.batch_for([s] * T)
+    xb = torch.cat([x] * T).contiguous()
+    yb, zb, qb = torch.cat([y] * T).contiguous(), torch.cat([z] * T).contiguous(), torch.cat([q] * T).contiguous()
+    autotune(fine, xb, yb, zb, qb, 5)
+    coarse = msm.pair_plan_for(s, "shifted_force")
+    autotune(coarse, x, y, z, q, 10)
+
+    def timed(fn):
+        ts, out = [], None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return statistics.median(ts), out
+
+    def sequential():
+        p, v = pos0.clone(), vel0.clone()
+        plan.vv_run(p, v, q, im, T * steps, dt, inputs.ACCEL_SCALE)
+        return p
+    t_seq, p_seq = timed(sequential)
+    t_pr, (states, it, res) = timed(lambda: msm.parareal(fine, coarse, q, im, state0, slices=T,
+                                                        steps_per_slice=steps, dt=dt,
+                                                        accel_scale=inputs.ACCEL_SCALE, tol=tol))
+    # one force evaluation: single system, the batch of T (per slice), the coarse function
+    t_f = event_timed(torch, lambda: plan.compute(x, y, z, q), 20, 3)[0]
+    t_fb = event_timed(torch, lambda: fine.compute(xb, yb, zb, qb), 20, 3)[0]
+    t_g = event_timed(torch, lambda: coarse.compute(x, y, z, q), 20, 3)[0]
+    err = float((states[:3, T] - p_seq).abs().max().item())
+    return {"workload": f"{s.n}-ion rock-salt cluster, a = 12 A, h = 2 A, cubic; T = {T} slices x {steps} "
+                        f"velocity Verlet steps of {dt} fs; G = shifted-force cutoff; tol {tol} A",
+            "iterations": it, "position_changes": [round(r, 8) for r in res],
+            "ms_parareal_window": round(t_pr * 1e3, 3), "ms_sequential_fine": round(t_seq * 1e3, 3),
+            "max_position_error_vs_sequential_A": err,
+            "ms_force_single": round(t_f * 1e3, 5),
+            "ms_force_batched_per_slice": round(t_fb * 1e3 / T, 5),
+            "ms_force_coarse": round(t_g * 1e3, 5),
+            "q_f_over_g": round(t_f / t_g, 3)}
 
 
 def water24k_leg(msm, torch, steps, warmup):
@@ -186,10 +296,11 @@ def water24k_leg(msm, torch, steps, warmup):
     launch = min(res, key=lambda k: res[k][0])
     plan.check()
     mean, med = res[launch]
+    ref = {k: v.clone() for k, v in plan.compute(x, y, z, q, out=out).items()}
     return {"workload": describe_workload(s), "atoms": s.n, "launch": launch,
             "ms_per_step": round(mean * 1e3, 5), "ms_median": round(med * 1e3, 5),
             "atom_evals_per_s": s.n / mean, "tuning": plan.tuning(),
-            "coarse_propagators": coarse_leg(msm, torch, s, mean, steps, warmup, x, y, z, q)}
+            "coarse_propagators": coarse_leg(msm, torch, s, mean, steps, warmup, x, y, z, q, ref)}
 
 
 def water100k_grad_leg(msm, torch, steps, warmup):
@@ -426,10 +537,14 @@ def main():
         "unique_pairs": n_pairs,
     }
     if not args.no_extras:
-        rec["coarse_propagators"] = coarse_leg(msm, torch, s, sec, args.steps, args.warmup, x, y, z, q)
+        rec["coarse_propagators"] = coarse_leg(msm, torch, s, sec, args.steps, args.warmup, x, y, z, q,
+                                               timed_out)
+        rec["cheap_msm_propagators"] = cheap_msm_leg(msm, torch, workmodel, s, sec, work["total"], args.steps,
+                                                     args.warmup, x, y, z, q, timed_out)
         rec["extras"] = {
             "water24k": water24k_leg(msm, torch, max(args.steps, 50), args.warmup),
             "water100k_forward_backward": water100k_grad_leg(msm, torch, max(args.steps, 50), args.warmup),
+            "parareal": parareal_leg(msm, torch),
             "batched": batched_leg(msm, torch, workmodel, max(20, min(args.steps, 50)), 5,
                                    not args.no_autotune),
         }

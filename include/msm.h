@@ -357,6 +357,66 @@ msm_status msm_batch_autotune_cached(msm_batch* batch, void* ws, size_t ws_bytes
                                      const float* x, const float* y, const float* z, const float* q,
                                      int32_t trials, const char* cache, char* report, size_t report_bytes);
 
+/* ------------------------------------------------------------------------ */
+/* Time stepping (Sec. 2.1 "Simulation loop": velocity Verlet; Sec. "Parareal
+ * Method", eq. (parareal)).
+ *
+ * msm_vv_run / msm_batch_vv_run: n_steps velocity Verlet steps of dt on the
+ * plan's (or batch's concatenated) atoms, forces from the plan or batch (any
+ * plan: MSM or a cheap pair method).  Per step: v += (dt/2) s F / m; r += dt v;
+ * F at the new r; v += (dt/2) s F / m, with s = accel_scale (the factor that
+ * turns force / mass in the caller's units into acceleration, e.g. 0.138935
+ * A/fs^2 per e^2/A^2/amu with coulomb_k = 1) and inv_mass = 1/m per atom.
+ * Forces are evaluated at the start positions first (n_steps + 1 evaluations
+ * in all).  x, y, z, vx, vy, vz (device) are updated in place; fx, fy, fz
+ * (device) receive the forces at the final positions.  All work is enqueued
+ * on `stream`; the data-error flags (msm_status_query / msm_batch_status)
+ * are those of the last evaluation.
+ *
+ * msm_parareal_run: one computational window of the parareal iteration.
+ * State lambda_t = (x, y, z, vx, vy, vz) of every atom at time points t = 0 ..
+ * T (T = slices), stored in `states` (device, float, [6][T + 1][n]: component
+ * c of time t at states + (c (T + 1) + t) n); the caller fills t = 0.  The
+ * fine propagator F and the coarse G each take steps_per_slice velocity
+ * Verlet steps of dt; F's forces come from `fine`, a batch of T systems with
+ * the coarse plan's atom count (normally T copies of the MSM plan's
+ * parameters), which advances all T slices together (one batched evaluation
+ * per force call), and G's from `coarse` (one system, e.g. a cutoff or Wolf
+ * pair plan).  Initial sweep: lambda_{t+1} = G(lambda_t).  Iteration k (0 ..
+ * max_iter - 1): f_t = F(lambda_t) for every t < T at once, then for t = k ..
+ * T - 1 in order lambda_{t+1} = f_t + (G(lambda_t) - g_t) with g_t the
+ * previous G(lambda_t) (slices before k are final).  A slice whose start
+ * state did not change gets f_t bit for bit, so after k iterations the first k
+ * slices equal k sequential fine propagations exactly.  The iteration stops
+ * after the first k whose largest position change max |lambda^{k+1} -
+ * lambda^k| is <= tol (A), or after max_iter (<= T) iterations.
+ * residuals (host, nullable, max_iter floats) receives those changes and
+ * *iterations (host) the iterations run.  ws (device, >=
+ * msm_parareal_workspace_bytes) is scratch.  q and inv_mass (device, n).
+ * Synchronises once per iteration (to read the change); data errors of the
+ * fine batch or the coarse plan are returned then. */
+typedef struct {
+  int32_t slices;           /* T >= 1 */
+  int32_t steps_per_slice;  /* >= 1 */
+  double dt;                /* time step */
+  double accel_scale;       /* > 0 */
+  int32_t max_iter;         /* 1 .. slices */
+  int32_t reserved;         /* must be zero */
+  double tol;               /* >= 0, A */
+} msm_parareal_params;
+msm_status msm_vv_run(const msm_plan* plan, void* ws, size_t ws_bytes, msm_stream_t stream, int32_t n_steps,
+                      double dt, double accel_scale, float* x, float* y, float* z, const float* q, float* vx,
+                      float* vy, float* vz, const float* inv_mass, float* fx, float* fy, float* fz);
+msm_status msm_batch_vv_run(const msm_batch* batch, void* ws, size_t ws_bytes, msm_stream_t stream,
+                            int32_t n_steps, double dt, double accel_scale, float* x, float* y, float* z,
+                            const float* q, float* vx, float* vy, float* vz, const float* inv_mass, float* fx,
+                            float* fy, float* fz);
+msm_status msm_parareal_workspace_bytes(int32_t n_atoms, int32_t slices, size_t* bytes);
+msm_status msm_parareal_run(const msm_parareal_params* params, const msm_batch* fine, void* fine_ws,
+                            size_t fine_ws_bytes, const msm_plan* coarse, void* coarse_ws, size_t coarse_ws_bytes,
+                            void* ws, size_t ws_bytes, msm_stream_t stream, const float* q, const float* inv_mass,
+                            float* states, int32_t* iterations, float* residuals);
+
 const char* msm_status_string(msm_status status);
 const char* msm_last_error(void);
 

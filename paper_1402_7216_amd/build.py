@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmsm.so")
-SOURCES = ["msm_api.hip", "msm_batch.hip", "msm_kernels.hip", "msm_static.hip"]
+SOURCES = ["msm_api.hip", "msm_batch.hip", "msm_kernels.hip", "msm_md.hip", "msm_static.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

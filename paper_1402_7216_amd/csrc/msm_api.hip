@@ -620,8 +620,9 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
   }
 
   // anterpolation tiles: start from 16 x 16 x 8 level-0 nodes and halve the
-  // largest side (down to 4) until there are at least 512 tiles, so a launch
-  // covers the 256 compute units twice
+  // largest side (down to 1) until there are at least 512 tiles, so a launch
+  // covers the 256 compute units twice (a coarse grid, e.g. h = 10 A, has few
+  // nodes but as many atoms: its tiles shrink to a few nodes each)
   {
     int t[3] = {16, 16, 8};
     auto tiles = [&]() {
@@ -633,7 +634,7 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
       int d = 0;
       for (int e = 1; e < 3; ++e)
         if (t[e] > t[d]) d = e;
-      if (t[d] <= 4) break;
+      if (t[d] <= 1) break;
       t[d] /= 2;
     }
     g.at_ext = 1;

@@ -171,6 +171,13 @@ msm_status check_batch(const msm_batch* Bt, const void* ws, size_t ws_bytes) {
 
 }  // namespace
 
+msm_status batch_shape(const msm_batch* B, int32_t* n_sys, int32_t* total_atoms) {
+  if (!B || !n_sys || !total_atoms) return fail(MSM_ERR_INVALID_ARG, "null batch or output");
+  *n_sys = B->n_sys;
+  *total_atoms = (int32_t)B->total_atoms;
+  return MSM_OK;
+}
+
 extern "C" {
 
 msm_status msm_batch_destroy(msm_batch* Bt) {

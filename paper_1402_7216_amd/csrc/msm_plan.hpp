@@ -83,6 +83,10 @@ void refresh_launch(msm_plan* P);
 // short-range rows, work items and binning path they imply.
 void set_cell_geometry(msm_plan* P, int reach);
 int default_reach(int n_atoms);
+
+// Number of systems and total atom count of a batch (the concatenated arrays'
+// length).
+msm_status batch_shape(const msm_batch* B, int32_t* n_sys, int32_t* total_atoms);
 // Apply tuning knobs (zero fields keep the current value).  Host-side only;
 // the caller re-uploads descriptors.
 void retune(msm_plan* P, const msm_tuning& t);

@@ -135,6 +135,49 @@ def water_box(n_atoms, seed, cutoff=12.0, spacing=2.0, order=4, levels=0, split_
                           split_m=split_m, name=name or f"water{n_atoms}")
 
 
+# Ions for time stepping.  The evaluated force is electrostatics alone (no
+# short-range repulsion), so the test dynamics is a nearly perfect rock-salt
+# lattice of +1 / -1 ions at a low temperature, where ions stay apart over
+# the short windows simulated.
+NA_MASS, CL_MASS = 22.98977, 35.453          # amu
+KB_KCAL = 0.0019872041                       # kcal/mol/K
+COULOMB_KCAL = 332.0637                      # kcal/mol A per e^2 (the e^2/A energy unit)
+ACCEL_PER_KCAL_A_AMU = 4.184e-4              # A/fs^2 per kcal/mol/A/amu
+VEL_PER_SQRT_KCAL_AMU = 2.0455e-2            # A/fs per sqrt(kcal/mol/amu)
+# acceleration in A/fs^2 of a force in e^2/A^2 on a mass in amu
+ACCEL_SCALE = COULOMB_KCAL * ACCEL_PER_KCAL_A_AMU
+
+
+@dataclasses.dataclass
+class Ions:
+    system: System           # positions, charges and MSM parameters
+    inv_mass: np.ndarray     # float32 [N], 1/amu
+    vel: np.ndarray          # float32 [3, N], A/fs
+
+
+def rock_salt(n_side, seed, spacing=2.82, jitter=0.05, margin=8.0, temperature=50.0, cutoff=8.0,
+              grid=2.0, order=4, levels=0) -> Ions:
+    """n_side^3 ions on a simple-cubic lattice of `spacing` A, charges +1 (Na
+    mass) and -1 (Cl mass) alternating (the rock-salt arrangement), each
+    displaced uniformly by up to `jitter` A per coordinate, in a box with
+    `margin` A of free space on every side; Maxwell-Boltzmann velocities at
+    `temperature` K (momentum not removed)."""
+    rng = np.random.default_rng(seed)
+    g = np.arange(n_side)
+    X, Y, Z = (v.ravel() for v in np.meshgrid(g, g, g, indexing="ij"))
+    q = np.where((X + Y + Z) % 2 == 0, 1.0, -1.0)
+    pos = np.stack([X, Y, Z]).astype(np.float64) * spacing + margin
+    pos += rng.uniform(-jitter, jitter, size=pos.shape)
+    side = (n_side - 1) * spacing + 2.0 * margin
+    mass = np.where(q > 0, NA_MASS, CL_MASS)
+    sigma = np.sqrt(KB_KCAL * temperature / mass) * VEL_PER_SQRT_KCAL_AMU
+    vel = rng.standard_normal(size=pos.shape) * sigma
+    s = _as_f32_system(pos, q, (0.0, 0.0, 0.0), (side, side, side), cutoff=cutoff, spacing=grid,
+                       order=order, levels=levels, name=f"rocksalt{n_side ** 3}")
+    return Ions(system=s, inv_mass=(1.0 / mass).astype(np.float32),
+                vel=np.ascontiguousarray(vel.astype(np.float32)))
+
+
 def batch_sizes(n_sys=64, lo=2000, hi=60000, seed=5):
     """Atom counts log-uniform in [lo, hi], rounded to whole molecules."""
     rng = np.random.default_rng(seed)

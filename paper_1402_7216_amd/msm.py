@@ -30,6 +30,7 @@ EXPORTS = ("msm_plan_create", "msm_pair_plan_create", "msm_plan_destroy", "msm_p
            "msm_graph_destroy", "msm_plan_tune", "msm_plan_tuning", "msm_plan_autotune",
            "msm_plan_tuning_key", "msm_tuning_cache_lookup", "msm_tuning_cache_store",
            "msm_plan_autotune_cached", "msm_batch_tuning_key", "msm_batch_autotune_cached",
+           "msm_vv_run", "msm_batch_vv_run", "msm_parareal_workspace_bytes", "msm_parareal_run",
            "msm_batch_create", "msm_batch_destroy", "msm_batch_workspace_bytes",
            "msm_batch_atom_offsets", "msm_batch_workspace_init", "msm_batch_compute",
            "msm_batch_energy", "msm_batch_backward", "msm_batch_graph_capture", "msm_batch_status",
@@ -99,6 +100,12 @@ class PairParams(ctypes.Structure):
 
 PAIR_KINDS = {"cutoff": 1, "shifted_force": 2, "wolf": 3}
 
+
+class PararealParams(ctypes.Structure):
+    _fields_ = [("slices", ctypes.c_int32), ("steps_per_slice", ctypes.c_int32), ("dt", ctypes.c_double),
+                ("accel_scale", ctypes.c_double), ("max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tol", ctypes.c_double)]
+
 _lib = None
 
 
@@ -131,6 +138,11 @@ def lib():
         L.msm_plan_tune.argtypes = [vp, vp, sz, vp, ctypes.POINTER(Tuning)]
         L.msm_plan_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
         L.msm_plan_autotune.argtypes = [vp, vp, sz, vp] + [vp] * 4 + [i32, ctypes.c_char_p, sz]
+        L.msm_vv_run.argtypes = [vp, vp, sz, vp, i32, ctypes.c_double, ctypes.c_double] + [vp] * 11
+        L.msm_batch_vv_run.argtypes = [vp, vp, sz, vp, i32, ctypes.c_double, ctypes.c_double] + [vp] * 11
+        L.msm_parareal_workspace_bytes.argtypes = [i32, i32, ctypes.POINTER(sz)]
+        L.msm_parareal_run.argtypes = [ctypes.POINTER(PararealParams), vp, vp, sz, vp, vp, sz, vp, sz, vp, vp, vp,
+                                       vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float)]
         L.msm_plan_tuning_key.argtypes = [vp, ctypes.c_char_p, sz]
         L.msm_batch_tuning_key.argtypes = [vp, ctypes.c_char_p, sz]
         L.msm_tuning_cache_lookup.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(Tuning)]
@@ -189,6 +201,25 @@ def _require_out(t, numel, dtype, device, name):
     of the right dtype, device and size."""
     if t.dtype != dtype or t.device != device or not t.is_contiguous() or t.numel() != numel:
         raise ValueError(f"out[{name!r}] must be a contiguous {dtype} tensor on {device} with {numel} elements")
+
+
+def _vv_run(self, pos, vel, q, inv_mass, n_steps, dt, accel_scale, f=None):
+    """n_steps velocity Verlet steps on these forces (msm_vv_run /
+    msm_batch_vv_run): pos and vel ([3, N] float32 device) are advanced in
+    place; returns the forces at the final positions ([3, N], into f when
+    given)."""
+    dev = self.ws.device
+    for name, t, numel in (("pos", pos, 3 * self.n), ("vel", vel, 3 * self.n), ("q", q, self.n),
+                           ("inv_mass", inv_mass, self.n)):
+        _require_out(t, numel, torch.float32, dev, name)
+    if f is None:
+        f = torch.empty((3, self.n), dtype=torch.float32, device=dev)
+    _require_out(f, 3 * self.n, torch.float32, dev, "f")
+    fn = lib().msm_batch_vv_run if isinstance(self, Batch) else lib().msm_vv_run
+    _check(fn(self._h, _ptr(self.ws), self.ws.numel(), _stream(), int(n_steps), float(dt), float(accel_scale),
+              *_force_rows(pos, self.n), _ptr(q), *_force_rows(vel, self.n), _ptr(inv_mass),
+              *_force_rows(f, self.n)))
+    return f
 
 
 def make_params(cutoff, spacing, order=4, split_m=0, levels=0, box_lo=(0.0, 0.0, 0.0),
@@ -271,6 +302,8 @@ class Plan:
         _check(lib().msm_compute(self._h, _ptr(self.ws), self.ws.numel(), _stream(), _ptr(x), _ptr(y),
                                  _ptr(z), _ptr(q), fx, fy, fz, _ptr(ph), _ptr(o["energy"]), _ptr(vr)))
         return o
+
+    vv_run = _vv_run
 
     def compute_static(self, x, y, z, q, out):
         """msm_compute_static: the evaluation of compute() with the library's
@@ -501,6 +534,8 @@ class Batch:
             _lib.msm_batch_destroy(h)
             self._h = None
 
+    vv_run = _vv_run
+
     def compute_static(self, x, y, z, q, out):
         """msm_compute_static: the evaluation of compute() with the library's
         static device workspace instead of self.ws (nothing is allocated; out
@@ -655,6 +690,33 @@ class MSMBatchEnergy(torch.autograd.Function):
         if need_pos or need_q:
             ctx.batch.backward(pos[0], pos[1], pos[2], q, grad.detach(), dpos, dq)
         return dpos, dq, None
+
+
+def parareal(fine, coarse, q, inv_mass, state0, *, slices, steps_per_slice, dt, accel_scale, max_iter=None,
+             tol=0.0):
+    """One parareal window (msm_parareal_run): fine is a Batch of `slices`
+    systems (the fine propagator's forces, all slices at once), coarse a Plan
+    or PairPlan of the same atom count (the coarse propagator's forces),
+    state0 the [6, N] start state (x, y, z, vx, vy, vz).  Returns the states
+    [6, slices + 1, N], the iterations run and the position change of each."""
+    n = coarse.n
+    dev = coarse.ws.device
+    _require_out(state0, 6 * n, torch.float32, dev, "state0")
+    for name, t in (("q", q), ("inv_mass", inv_mass)):
+        _require_out(t, n, torch.float32, dev, name)
+    mi = int(slices if max_iter is None else max_iter)
+    p = PararealParams(int(slices), int(steps_per_slice), float(dt), float(accel_scale), mi, 0, float(tol))
+    states = torch.empty((6, slices + 1, n), dtype=torch.float32, device=dev)
+    states[:, 0, :] = state0
+    nb = ctypes.c_size_t()
+    _check(lib().msm_parareal_workspace_bytes(n, int(slices), ctypes.byref(nb)))
+    ws = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
+    it = ctypes.c_int32()
+    res = (ctypes.c_float * max(mi, 1))()
+    _check(lib().msm_parareal_run(ctypes.byref(p), fine._h, _ptr(fine.ws), fine.ws.numel(), coarse._h,
+                                  _ptr(coarse.ws), coarse.ws.numel(), _ptr(ws), ws.numel(), _stream(), _ptr(q),
+                                  _ptr(inv_mass), _ptr(states), ctypes.byref(it), res))
+    return states, it.value, [float(res[k]) for k in range(it.value)]
 
 
 def batch_energy(batch, pos, q):

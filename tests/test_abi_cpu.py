@@ -294,3 +294,40 @@ def test_committed_tuning_cache_entries_are_valid(M):
     for k in keys:
         assert k.startswith("gfx950/")
         assert M.cache_lookup(path, k) is not None
+
+
+def test_time_stepping_arguments_are_checked_without_device(M):
+    """msm_vv_run / msm_parareal_run refuse bad arguments before any device
+    work: negative step counts, a fine batch whose system count or atom count
+    does not match, max_iter outside 1 .. slices, a missing workspace."""
+    ions = inputs.rock_salt(3, seed=1)
+    s = ions.system
+    code, h = _plan(M, s.n, **s.params())
+    assert code == 0
+    code, hb = _batch(M, [s.params()] * 3, [s.n] * 3)
+    assert code == 0
+    try:
+        nb = ctypes.c_size_t()
+        assert M.lib().msm_parareal_workspace_bytes(s.n, 0, ctypes.byref(nb)) == -1
+        assert M.lib().msm_parareal_workspace_bytes(s.n, 3, ctypes.byref(nb)) == 0 and nb.value > 0
+        arr = [ctypes.c_void_p(256)] * 11
+        assert M.lib().msm_vv_run(h, ctypes.c_void_p(256), 1 << 30, None, -1, 1.0, 1.0, *arr) == -1
+        assert M.lib().msm_vv_run(h, ctypes.c_void_p(256), 1 << 30, None, 1, 1.0, 0.0, *arr) == -1
+        it = ctypes.c_int32()
+
+        def run(slices, max_iter, steps=2, reserved=0, ws=ctypes.c_void_p(256), ws_bytes=1 << 30):
+            p = M.PararealParams(slices, steps, 1.0, 0.1, max_iter, reserved, 0.0)
+            return M.lib().msm_parareal_run(ctypes.byref(p), hb, ctypes.c_void_p(256), 1 << 30, h,
+                                            ctypes.c_void_p(256), 1 << 30, ws, ws_bytes, None,
+                                            ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_void_p(256),
+                                            ctypes.byref(it), None)
+        assert run(4, 1) == -1                  # the batch holds 3 systems
+        assert run(3, 4) == -1                  # max_iter > slices
+        assert run(3, 0) == -1
+        assert run(3, 1, steps=0) == -1
+        assert run(3, 1, reserved=1) == -1
+        assert run(3, 1, ws=None) == -4         # no scratch
+        assert run(3, 1, ws_bytes=16) == -4
+    finally:
+        M.lib().msm_batch_destroy(hb)
+        M.lib().msm_plan_destroy(h)

@@ -171,6 +171,19 @@ def test_water100k_matches_oracle(M):
     check_full(run_gpu(M, s), oracle.system_msm(s), "water100k")
 
 
+@pytest.mark.parametrize("variant", ["coarse_grid_4h", "short_cutoff_6A"])
+def test_cheap_msm_propagators_match_oracle(M, variant):
+    """MSM as a coarse propagator: the finest grid four times coarser (h = 8
+    A against 2 A) or the finest-grid cutoff halved to 6 A, on the 24,000-atom
+    box, against the oracle with the same parameters (same bars)."""
+    import dataclasses
+    s = inputs.water_24k()
+    kw = dict(spacing=4.0 * s.spacing, levels=0) if variant == "coarse_grid_4h" else dict(cutoff=6.0)
+    v = dataclasses.replace(s, **kw)
+    print(f"case {variant} a={v.cutoff} h={v.spacing} n={v.n}", flush=True)
+    check_full(run_gpu(M, v), oracle.system_msm(v), variant)
+
+
 def test_water1m_matches_oracle(M):
     """One million atoms, quintic basis, 5 levels: every force component, every
     potential and the energy against a full oracle evaluation."""
