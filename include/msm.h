@@ -358,6 +358,30 @@ msm_status msm_batch_autotune_cached(msm_batch* batch, void* ws, size_t ws_bytes
                                      int32_t trials, const char* cache, char* report, size_t report_bytes);
 
 /* ------------------------------------------------------------------------ */
+/* Bonded exclusions: pairs whose Coulomb interaction is left out of the sum
+ * (atoms with bonded interactions are excluded from eq. (coulomb), Sec.
+ * "Calculation of Long-Range Interactions").  Per-atom partner lists in CSR form over input indices:
+ * the partners of atom g are idx[start[g] .. start[g + 1]) (device int32;
+ * start has one entry per atom plus one; every pair listed from both sides;
+ * nnz = start[n]).  For a batch the indices are global (into the
+ * concatenated arrays) and a system's atoms may only list atoms of the same
+ * system.  The library keeps the pointers: the arrays must stay valid and
+ * unchanged while evaluations on ws use them; start = null removes the
+ * exclusions.  Like a tuning change, the call re-uploads the descriptor to ws
+ * (other workspaces must be initialised again) and refuses later replays of
+ * graphs captured before it.  Effect on an MSM plan: every excluded pair loses
+ * q_i q_j / r_ij from the energy, q_j / r_ij from phi_i and the matching
+ * Coulomb force, i.e. its short-range term and the exact smooth part the grids
+ * approximate (so an excluded pair keeps the grid's approximation error of that
+ * smooth part); on a pair-method plan it loses the method's own pair term when
+ * the short-range pass counted the pair.  Entries out of range are reported
+ * through the data-error status as MSM_ERR_INVALID_ARG. */
+msm_status msm_set_exclusions(msm_plan* plan, void* ws, size_t ws_bytes, msm_stream_t stream,
+                              const int32_t* start, const int32_t* idx, int64_t nnz);
+msm_status msm_batch_set_exclusions(msm_batch* batch, void* ws, size_t ws_bytes, msm_stream_t stream,
+                                    const int32_t* start, const int32_t* idx, int64_t nnz);
+
+/* ------------------------------------------------------------------------ */
 /* Time stepping (Sec. 2.1 "Simulation loop": velocity Verlet; Sec. "Parareal
  * Method", eq. (parareal)).
  *

@@ -79,6 +79,8 @@ def lib():
                                   ctypes.c_int, ctypes.c_int]
         L.oracle_pair_e.restype = ctypes.c_double
         L.oracle_pair_e.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.oracle_inside_f32.restype = None
+        L.oracle_inside_f32.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp, dp, ctypes.c_double, ip]
         L.oracle_gamma_coeffs.restype = None
         L.oracle_gamma_coeffs.argtypes = [ctypes.c_int, dp]
         _lib = L
@@ -129,14 +131,15 @@ def split_grids(flat, n):
 
 
 def msm(x, y, z, q, *, cutoff, spacing, order=4, split_m=0, levels=0, box_lo=(0, 0, 0),
-        box_len=(1, 1, 1), ke=1.0, grids=False, sample=None, short_mode=0, threads=0):
+        box_len=(1, 1, 1), ke=1.0, grids=False, sample=None, short_mode=0, threads=0, exclusions=None):
     """Run the FP64 oracle.
 
     Returns a dict with energy, forces f[3,N], potentials phi[N], virial[3,3],
     the short-range potential phis[N] and (grids=True) the per-level grids
     q (charges), ucut (lattice-cutoff / top-level sums) and u (prolongated).
     With ``sample`` (atom indices) only those atoms' outputs are computed;
-    energy and virial are then absent.
+    energy and virial are then absent.  ``exclusions`` = (start, idx): bonded
+    pairs left out (``exclusion_terms`` with kind "coulomb" taken off).
     """
     x, y, z, q = _f64(x), _f64(y), _f64(z), _f64(q)
     n = int(x.shape[0])
@@ -170,6 +173,74 @@ def msm(x, y, z, q, *, cutoff, spacing, order=4, split_m=0, levels=0, box_lo=(0,
         out["q"] = split_grids(qg, gn)
         out["ucut"] = split_grids(uc, gn)
         out["u"] = split_grids(ug, gn)
+    if exclusions is not None:
+        out = _minus_exclusions(out, x, y, z, q, exclusions, sample=sample, kind="coulomb", ke=ke,
+                                box_lo=box_lo)
+    return out
+
+
+def exclusion_terms(x, y, z, q, start, idx, *, kind="coulomb", cutoff=None, alpha=0.0, ke=1.0,
+                    f32_cut=False, box_lo=(0, 0, 0)):
+    """The contribution of the listed (excluded) pairs, in FP64, to be taken
+    off an evaluation: bonded pairs are left out of the Coulomb sum (Sec.
+    "Calculation of Long-Range Interactions", before eq. (coulomb)).
+
+    kind "coulomb": the whole Coulomb term q_i q_j / r of each pair (what a
+    multilevel-summation evaluation carries for it: the short-range part plus
+    the exact smooth part).  A pair-method kind: that method's pair term e(r)
+    for the pairs inside the cutoff (decided in float32 with f32_cut, as in
+    ``pair``).  Partner lists in CSR form over input indices (start [N + 1],
+    idx), every pair listed from both sides.  Returns energy, f [3, N], phi [N]
+    and virial [3, 3] of those pairs."""
+    x, y, z, q = _f64(x), _f64(y), _f64(z), _f64(q)
+    n = int(x.shape[0])
+    start = np.asarray(start, dtype=np.int64)
+    j = np.asarray(idx, dtype=np.int64)[:start[-1]]
+    i = np.repeat(np.arange(n), np.diff(start))
+    pos = np.stack([x, y, z])
+    d = pos[:, i] - pos[:, j]
+    r = np.sqrt(np.sum(d * d, axis=0))
+    if kind == "coulomb":
+        e, de = 1.0 / r, -1.0 / (r * r)
+    else:
+        k = PAIR_KINDS[kind] if isinstance(kind, str) else int(kind)
+        rc = float(cutoff)
+        if f32_cut:
+            a, b = np.ascontiguousarray(pos[:, i]), np.ascontiguousarray(pos[:, j])
+            flag = np.zeros(i.shape[0], dtype=np.int32)
+            lib().oracle_inside_f32(int(i.shape[0]), _dptr(a[0]), _dptr(a[1]), _dptr(a[2]), _dptr(b[0]),
+                                    _dptr(b[1]), _dptr(b[2]), float(rc),
+                                    flag.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+            inside = flag.astype(bool)
+        else:
+            inside = r < rc
+        if k == 1:
+            e, de = 1.0 / r, -1.0 / (r * r)
+        elif k == 2:
+            e, de = 1.0 / r - 1.0 / rc + (r - rc) / (rc * rc), -1.0 / (r * r) + 1.0 / (rc * rc)
+        else:
+            from scipy.special import erfc
+            e = erfc(alpha * r) / r - erfc(alpha * rc) / rc
+            de = -erfc(alpha * r) / (r * r) - 2.0 * alpha / np.sqrt(np.pi) * np.exp(-(alpha * r) ** 2) / r
+        e, de = np.where(inside, e, 0.0), np.where(inside, de, 0.0)
+    phi = ke * np.bincount(i, weights=q[j] * e, minlength=n)
+    w = -q[i] * q[j] * de / r                      # the force on i from j is w (r_i - r_j)
+    f = ke * np.stack([np.bincount(i, weights=w * d[c], minlength=n) for c in range(3)])
+    rel = pos - np.asarray(box_lo, dtype=np.float64)[:, None]
+    return dict(energy=0.5 * float(q @ phi), f=f, phi=phi, virial=rel @ f.T)
+
+
+def _minus_exclusions(out, x, y, z, q, exclusions, sample=None, **kw):
+    ex = exclusion_terms(x, y, z, q, *exclusions, **kw)
+    if sample is not None:
+        smp = np.asarray(sample)
+        out["f"] = out["f"] - ex["f"][:, smp]
+        out["phi"] = out["phi"] - ex["phi"][smp]
+        return out
+    out["f"] = out["f"] - ex["f"]
+    out["phi"] = out["phi"] - ex["phi"]
+    out["energy"] = out["energy"] - ex["energy"]
+    out["virial"] = out["virial"] - ex["virial"]
     return out
 
 
@@ -189,11 +260,11 @@ PAIR_KINDS = {"cutoff": 1, "shifted_force": 2, "wolf": 3}
 
 
 def pair(x, y, z, q, *, kind, cutoff, alpha=0.0, box_lo=(0, 0, 0), box_len=(1, 1, 1), ke=1.0,
-         all_pairs=False, f32_cut=False, threads=0):
+         all_pairs=False, f32_cut=False, threads=0, exclusions=None):
     """A cheap pair method (plain cutoff, shifted-force smoothed cutoff, Wolf
     summation) in FP64: energy, forces f[3,N], potentials phi[N], virial[3,3].
     f32_cut: decide r < rc in float32 as a float32 kernel does (the pair
-    terms stay double)."""
+    terms stay double).  exclusions = (start, idx): bonded pairs left out."""
     x, y, z, q = _f64(x), _f64(y), _f64(z), _f64(q)
     n = int(x.shape[0])
     lo, ln = _f64(box_lo), _f64(box_len)
@@ -205,7 +276,11 @@ def pair(x, y, z, q, *, kind, cutoff, alpha=0.0, box_lo=(0, 0, 0), box_len=(1, 1
                            _dptr(e), _dptr(w), int(bool(all_pairs)), int(bool(f32_cut)), int(threads))
     if rc:
         raise OracleError(rc)
-    return dict(f=np.stack([fx, fy, fz]), phi=phi, energy=float(e[0]), virial=w.reshape(3, 3))
+    out = dict(f=np.stack([fx, fy, fz]), phi=phi, energy=float(e[0]), virial=w.reshape(3, 3))
+    if exclusions is not None:
+        out = _minus_exclusions(out, x, y, z, q, exclusions, kind=kind, cutoff=cutoff, alpha=alpha, ke=ke,
+                                f32_cut=f32_cut, box_lo=box_lo)
+    return out
 
 
 def pair_e(kind, cutoff, alpha, r):

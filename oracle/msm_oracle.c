@@ -772,6 +772,19 @@ static double pair_de(int kind, double rc, double alpha, double r) {   /* d e / 
 
 double oracle_pair_e(int kind, double rc, double alpha, double r) { return pair_e(kind, rc, alpha, r); }
 
+/* For each of n pairs (a_k, b_k): whether 0 < r^2 < rc^2 holds when decided  */
+/* in float32 the way a float32 kernel decides it (see f32_cut above).       */
+void oracle_inside_f32(int n, const double* ax, const double* ay, const double* az, const double* bx,
+                       const double* by, const double* bz, double rc, int* inside) {
+  const float rc2f = (float)(rc * rc);
+  for (int k = 0; k < n; ++k) {
+    const float dxf = (float)ax[k] - (float)bx[k], dyf = (float)ay[k] - (float)by[k];
+    const float dzf = (float)az[k] - (float)bz[k];
+    const float r2f = fmaf(dxf, dxf, fmaf(dyf, dyf, dzf * dzf));
+    inside[k] = (r2f > 0.0f && r2f < rc2f) ? 1 : 0;
+  }
+}
+
 int oracle_pair(int kind, double rc, double alpha, const double* lo, const double* len, double ke,
                 int n, const double* x, const double* y, const double* z, const double* q,
                 double* fx, double* fy, double* fz, double* phi, double* energy, double* virial,

@@ -508,6 +508,9 @@ msm::DevPtrs dev_ptrs(const msm_plan* P, void* ws) {
   d.top = (decltype(d.top))(b + o[msm::kSecTop]);
   d.partials = (decltype(d.partials))(b + o[msm::kSecPartials]);
   d.lat_part = (decltype(d.lat_part))(b + o[msm::kSecLatPart]);
+  d.excl_start = (decltype(d.excl_start))(P->excl_start);
+  d.excl_idx = (decltype(d.excl_idx))(P->excl_idx);
+  d.excl_nnz = P->excl_nnz;
   return d;
 }
 
@@ -1123,6 +1126,7 @@ msm_status msm_status_query(const msm_plan* P, const void* ws, msm_stream_t stre
   if (flags & msm::kFlagNonFinite) return fail(MSM_ERR_NONFINITE, "non-finite position or charge");
   if (flags & msm::kFlagOutOfBox) return fail(MSM_ERR_OUT_OF_BOX, "atom outside the box");
   if (flags & msm::kFlagCoincident) return fail(MSM_ERR_COINCIDENT, "coincident atoms");
+  if (flags & msm::kFlagBadExclusion) return fail(MSM_ERR_INVALID_ARG, "exclusion list entry out of range");
   return MSM_OK;
 }
 

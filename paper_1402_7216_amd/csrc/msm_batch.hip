@@ -8,6 +8,7 @@
 #include <unistd.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -395,6 +396,7 @@ msm_status msm_batch_status(const msm_batch* Bt, const void* ws, msm_stream_t st
   if (all & msm::kFlagNonFinite) return fail(MSM_ERR_NONFINITE, "non-finite position or charge");
   if (all & msm::kFlagOutOfBox) return fail(MSM_ERR_OUT_OF_BOX, "atom outside the box");
   if (all & msm::kFlagCoincident) return fail(MSM_ERR_COINCIDENT, "coincident atoms");
+  if (all & msm::kFlagBadExclusion) return fail(MSM_ERR_INVALID_ARG, "exclusion list entry out of range");
   return MSM_OK;
 }
 
@@ -450,6 +452,54 @@ msm_status msm_plan_tune(msm_plan* P, void* ws, size_t ws_bytes, msm_stream_t st
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "upload descriptor");
   P->ready.insert(ws);
+  return MSM_OK;
+}
+
+static msm_status check_exclusions(const int32_t* start, const int32_t* idx, int64_t nnz) {
+  if (nnz < 0 || nnz > INT32_MAX) return fail(MSM_ERR_INVALID_ARG, "nnz must be in 0 .. 2^31 - 1");
+  if (start && nnz > 0 && !idx) return fail(MSM_ERR_INVALID_ARG, "null exclusion partner array");
+  return MSM_OK;
+}
+
+msm_status msm_set_exclusions(msm_plan* P, void* ws, size_t ws_bytes, msm_stream_t stream, const int32_t* start,
+                              const int32_t* idx, int64_t nnz) {
+  if (!P) return fail(MSM_ERR_INVALID_ARG, "null plan");
+  msm_status st = check_exclusions(start, idx, nnz);
+  if (st != MSM_OK) return st;
+  if (!ws || ws_bytes < P->lay.total || !P->ready.count(ws))
+    return fail(MSM_ERR_WORKSPACE, "workspace not initialised for this plan");
+  P->excl_start = start;
+  P->excl_idx = start ? idx : nullptr;
+  P->excl_nnz = start ? nnz : 0;
+  ++P->tune_gen;                                   // graphs and the static workspace see a new plan state
+  P->desc.d = dev_ptrs(P, ws);
+  P->ready.clear();
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(static_cast<char*>(ws) + P->lay.off[msm::kSecDesc], &P->desc,
+                                sizeof(msm::SysDesc), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "upload descriptor");
+  P->ready.insert(ws);
+  return MSM_OK;
+}
+
+msm_status msm_batch_set_exclusions(msm_batch* Bt, void* ws, size_t ws_bytes, msm_stream_t stream,
+                                    const int32_t* start, const int32_t* idx, int64_t nnz) {
+  msm_status st = check_batch(Bt, ws, ws_bytes);
+  if (st != MSM_OK) return st;
+  st = check_exclusions(start, idx, nnz);
+  if (st != MSM_OK) return st;
+  for (msm_plan* P : Bt->plans) {
+    P->excl_start = start;
+    P->excl_idx = start ? idx : nullptr;
+    P->excl_nnz = start ? nnz : 0;
+    ++P->tune_gen;
+  }
+  ++Bt->tune_gen;
+  Bt->ready.clear();
+  st = upload_tables(Bt, ws, reinterpret_cast<hipStream_t>(stream));
+  if (st != MSM_OK) return st;
+  Bt->ready.insert(ws);
   return MSM_OK;
 }
 

@@ -28,7 +28,7 @@ constexpr int kStatusWords = 64 + kBinRowMaxBlocks;   // [0]: flags; [64 + b]: f
 constexpr int kScanTile = 4096;           // cells per block of the four-kernel binning's scan
 constexpr int kXcds = 8;                  // accelerator dies of the chip, each with its own L2
 
-enum DeviceFlag : int { kFlagOutOfBox = 1, kFlagNonFinite = 2, kFlagCoincident = 4 };
+enum DeviceFlag : int { kFlagOutOfBox = 1, kFlagNonFinite = 2, kFlagCoincident = 4, kFlagBadExclusion = 8 };
 
 // Pair function of the short-range pass: the MSM short-range kernel g*, or one
 // of the cheap pair methods evaluated on their own (values of msm_pair_kind).
@@ -189,6 +189,11 @@ struct DevPtrs {
   MSM_GLOBAL const double* top;
   MSM_GLOBAL double* partials;
   MSM_GLOBAL double* lat_part;
+  // bonded exclusions (caller's arrays, null: none): partners of the atom with
+  // global input index g are excl_idx[excl_start[g] .. excl_start[g + 1])
+  MSM_GLOBAL const int* excl_start;
+  MSM_GLOBAL const int* excl_idx;
+  long long excl_nnz;
 };
 
 // Stages of one evaluation, in launch order (for optional event timing).

@@ -1894,6 +1894,97 @@ __device__ __forceinline__ void block_partials(double e, const double* vir, doub
 // MODE 0: forces and potentials, plus per-block energy/virial partials.
 // MODE 1: gradients of the energy scaled by *gscale: fx..fz receive
 //         gscale dE/dr = -gscale F, phi receives gscale dE/dq = gscale phi.
+// Bonded exclusions (pairs left out of the Coulomb sum).  For the atom with
+// local input index i: the sums over its listed partners j of q_j / r and of
+// q_j (r_i - r_j) / r^3, from the caller's float32 inputs.  A list entry out
+// of range (start not within [0, nnz], a partner outside this system) sets
+// kFlagBadExclusion and ends the atom's list.
+struct ExclSums {
+  float p = 0.f, x = 0.f, y = 0.f, z = 0.f;
+};
+
+__device__ __forceinline__ bool excl_range(const SysDesc& S, int i, int& b, int& e) {
+  const int gi = S.atom_off + i;
+  b = S.d.excl_start[gi];
+  e = S.d.excl_start[gi + 1];
+  if (b < 0 || e < b || (long long)e > S.d.excl_nnz) {
+    atomicOr(S.d.status, kFlagBadExclusion);
+    return false;
+  }
+  return true;
+}
+
+__device__ __forceinline__ bool excl_partner(const SysDesc& S, int k, int& j) {
+  j = S.d.excl_idx[k];
+  if ((unsigned)(j - S.atom_off) >= (unsigned)S.g.n_atoms) {
+    atomicOr(S.d.status, kFlagBadExclusion);
+    return false;
+  }
+  return true;
+}
+
+__device__ ExclSums coulomb_exclusions(const SysDesc& S, const Io& io, int i) {
+  ExclSums r;
+  int b, e;
+  if (!S.d.excl_start || !excl_range(S, i, b, e)) return r;
+  const int gi = S.atom_off + i;
+  const float xi = io.x[gi], yi = io.y[gi], zi = io.z[gi];
+  for (int k = b; k < e; ++k) {
+    int j;
+    if (!excl_partner(S, k, j)) break;
+    const float dx = xi - io.x[j], dy = yi - io.y[j], dz = zi - io.z[j];
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    if (!(r2 > 0.f)) continue;
+    const float ri = 1.f / sqrtf(r2);
+    const float qj = io.q[j];
+    r.p = fmaf(qj, ri, r.p);
+    const float w = qj * ri * ri * ri;
+    r.x = fmaf(w, dx, r.x);
+    r.y = fmaf(w, dy, r.y);
+    r.z = fmaf(w, dz, r.z);
+  }
+  return r;
+}
+
+// The same sums for a cheap pair method: q_j e(r) and q_j (-e'(r)/r) (r_i -
+// r_j) over the listed partners that the short-range pass counted (0 < r^2
+// < rc^2 decided in float32 as there), with its pair functions.
+__device__ ExclSums pair_exclusions(const SysDesc& S, const Io& io, int i) {
+  ExclSums r;
+  int b, e;
+  if (!S.d.excl_start || !excl_range(S, i, b, e)) return r;
+  const Geom& g = S.g;
+  const int gi = S.atom_off + i;
+  const float xi = io.x[gi], yi = io.y[gi], zi = io.z[gi];
+  for (int k = b; k < e; ++k) {
+    int j;
+    if (!excl_partner(S, k, j)) break;
+    const float dx = xi - io.x[j], dy = yi - io.y[j], dz = zi - io.z[j];
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    if (!(r2 > 0.f && r2 < g.a2)) continue;
+    const float ri = 1.f / sqrtf(r2);
+    float ev, fr;
+    if (g.pair == kPairCutoff) {
+      ev = ri;
+      fr = ri * ri * ri;
+    } else if (g.pair == kPairShiftedForce) {
+      ev = ri + fmaf(r2 * ri, g.pk[1], -2.f * g.pk[0]);
+      fr = ri * fmaf(ri, ri, -g.pk[1]);
+    } else {
+      const float er = erfcf(g.pk[0] * (r2 * ri));
+      ev = fmaf(er, ri, -g.pk[1]);
+      fr = ri * ri * fmaf(er, ri, g.pk[2] * expf(-g.pk[3] * r2));
+    }
+    const float qj = io.q[j];
+    r.p = fmaf(qj, ev, r.p);
+    const float w = qj * fr;
+    r.x = fmaf(w, dx, r.x);
+    r.y = fmaf(w, dy, r.y);
+    r.z = fmaf(w, dz, r.z);
+  }
+  return r;
+}
+
 template <int ORDER, int MODE>
 __global__ void __launch_bounds__(kBlock) k_interp(KArgs A) {
   int blk;
@@ -1959,6 +2050,13 @@ __global__ void __launch_bounds__(kBlock) k_interp(KArgs A) {
     gy *= g.inv_h;
     gz *= g.inv_h;
     float4 fs = fshort[s];
+    // excluded pairs lose their whole Coulomb term q_i q_j / r (the short-range
+    // part and the smooth part the grids carry)
+    const ExclSums ex = coulomb_exclusions(S, A.io, perm[s]);
+    gx += ex.x;
+    gy += ex.y;
+    gz += ex.z;
+    fs.w -= ex.p;
     double qd = (double)p.w;
     double ph = g.ke * ((double)fs.w + (double)pl - qd * (double)g.self);
     if (MODE == 1) {
@@ -2013,8 +2111,14 @@ __global__ void __launch_bounds__(kBlock) k_pair_finish(KArgs A) {
   for (int t = 0; t < 9; ++t) vir[t] = 0.0;
   if (s < g.n_atoms) {
     const float4 p = S.d.sorted[s];
-    const float4 fs = S.d.fshort[s];
+    float4 fs = S.d.fshort[s];
     const int i = S.d.perm[s];
+    // excluded pairs lose the method's own pair term
+    const ExclSums ex = pair_exclusions(S, A.io, i);
+    fs.x -= p.w * ex.x;
+    fs.y -= p.w * ex.y;
+    fs.z -= p.w * ex.z;
+    fs.w -= ex.p;
     const double qd = (double)p.w;
     const double ph = g.ke * ((double)fs.w - qd * (double)g.self);
     const float of[3] = {(float)(g.ke * (double)fs.x), (float)(g.ke * (double)fs.y), (float)(g.ke * (double)fs.z)};
@@ -2051,7 +2155,8 @@ __global__ void __launch_bounds__(kBlock) k_energy_terms(KArgs A) {
   double e = 0.0;
   for (int i = blk * blockDim.x + threadIdx.x; i < g.n_atoms; i += stride) {
     const double q = (double)sorted[i].w;
-    e += 0.5 * q * ((double)fshort[i].w - q * (double)g.self);
+    const double ex = S.d.excl_start ? (double)coulomb_exclusions(S, A.io, S.d.perm[i]).p : 0.0;
+    e += 0.5 * q * ((double)fshort[i].w - ex - q * (double)g.self);
   }
   for (int k = 0; k < g.levels; ++k) {
     const Level& L = g.lv[k];

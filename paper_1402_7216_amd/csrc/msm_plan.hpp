@@ -42,6 +42,9 @@ struct msm_plan {
   int short_split = 1000;                    // per mille of it started there (msm_tuning.short_split)
   uint64_t tune_gen = 0;                     // bumped by every tuning change (graphs record it)
   uint64_t uid = 0;                          // unique over the process (never reused)
+  const int32_t* excl_start = nullptr;       // bonded exclusions (device arrays of the caller)
+  const int32_t* excl_idx = nullptr;
+  int64_t excl_nnz = 0;
   Layout lay;
   msm::SysDesc desc;                         // host copy; device pointers filled per workspace
   msm::LaunchGeom lg;                        // stage grids of one evaluation (descriptor set per call)

@@ -178,6 +178,19 @@ def rock_salt(n_side, seed, spacing=2.82, jitter=0.05, margin=8.0, temperature=5
                 vel=np.ascontiguousarray(vel.astype(np.float32)))
 
 
+def water_exclusions(n_atoms, offset=0):
+    """Bonded exclusions of 3-site water molecules (O, H, H in that order):
+    each atom excludes the other two of its molecule.  CSR over the atom
+    indices offset .. offset + n_atoms - 1: start int32 [n_atoms + 1], idx
+    int32 (partners, global indices)."""
+    n_mol = n_atoms // 3
+    base = offset + 3 * np.repeat(np.arange(n_mol), 3)
+    local = np.tile(np.array([[1, 2], [0, 2], [0, 1]]), (n_mol, 1))
+    idx = (base[:, None] + local).reshape(-1).astype(np.int32)
+    start = (2 * np.arange(3 * n_mol + 1)).astype(np.int32)
+    return start, idx
+
+
 def batch_sizes(n_sys=64, lo=2000, hi=60000, seed=5):
     """Atom counts log-uniform in [lo, hi], rounded to whole molecules."""
     rng = np.random.default_rng(seed)

@@ -31,6 +31,7 @@ EXPORTS = ("msm_plan_create", "msm_pair_plan_create", "msm_plan_destroy", "msm_p
            "msm_plan_tuning_key", "msm_tuning_cache_lookup", "msm_tuning_cache_store",
            "msm_plan_autotune_cached", "msm_batch_tuning_key", "msm_batch_autotune_cached",
            "msm_vv_run", "msm_batch_vv_run", "msm_parareal_workspace_bytes", "msm_parareal_run",
+           "msm_set_exclusions", "msm_batch_set_exclusions",
            "msm_batch_create", "msm_batch_destroy", "msm_batch_workspace_bytes",
            "msm_batch_atom_offsets", "msm_batch_workspace_init", "msm_batch_compute",
            "msm_batch_energy", "msm_batch_backward", "msm_batch_graph_capture", "msm_batch_status",
@@ -138,6 +139,8 @@ def lib():
         L.msm_plan_tune.argtypes = [vp, vp, sz, vp, ctypes.POINTER(Tuning)]
         L.msm_plan_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
         L.msm_plan_autotune.argtypes = [vp, vp, sz, vp] + [vp] * 4 + [i32, ctypes.c_char_p, sz]
+        L.msm_set_exclusions.argtypes = [vp, vp, sz, vp, vp, vp, ctypes.c_int64]
+        L.msm_batch_set_exclusions.argtypes = [vp, vp, sz, vp, vp, vp, ctypes.c_int64]
         L.msm_vv_run.argtypes = [vp, vp, sz, vp, i32, ctypes.c_double, ctypes.c_double] + [vp] * 11
         L.msm_batch_vv_run.argtypes = [vp, vp, sz, vp, i32, ctypes.c_double, ctypes.c_double] + [vp] * 11
         L.msm_parareal_workspace_bytes.argtypes = [i32, i32, ctypes.POINTER(sz)]
@@ -222,6 +225,25 @@ def _vv_run(self, pos, vel, q, inv_mass, n_steps, dt, accel_scale, f=None):
     return f
 
 
+def _set_exclusions(self, start, idx):
+    """Bonded exclusions (msm_set_exclusions / msm_batch_set_exclusions): CSR
+    partner lists over input indices, start [N + 1] and idx [nnz] int32 (numpy
+    or device tensors; kept alive by this object); None removes them."""
+    if start is None:
+        self._excl = None
+        fn = lib().msm_batch_set_exclusions if isinstance(self, Batch) else lib().msm_set_exclusions
+        _check(fn(self._h, _ptr(self.ws), self.ws.numel(), _stream(), None, None, 0))
+        return
+    dev = self.ws.device
+    st = torch.as_tensor(start, dtype=torch.int32).to(dev).contiguous()
+    ix = torch.as_tensor(idx, dtype=torch.int32).to(dev).contiguous()
+    if st.numel() != self.n + 1:
+        raise ValueError("start must have n_atoms + 1 entries")
+    self._excl = (st, ix)
+    fn = lib().msm_batch_set_exclusions if isinstance(self, Batch) else lib().msm_set_exclusions
+    _check(fn(self._h, _ptr(self.ws), self.ws.numel(), _stream(), _ptr(st), _ptr(ix), int(ix.numel())))
+
+
 def make_params(cutoff, spacing, order=4, split_m=0, levels=0, box_lo=(0.0, 0.0, 0.0),
                 box_len=(1.0, 1.0, 1.0), coulomb_k=1.0) -> Params:
     p = Params()
@@ -304,6 +326,7 @@ class Plan:
         return o
 
     vv_run = _vv_run
+    set_exclusions = _set_exclusions
 
     def compute_static(self, x, y, z, q, out):
         """msm_compute_static: the evaluation of compute() with the library's
@@ -535,6 +558,7 @@ class Batch:
             self._h = None
 
     vv_run = _vv_run
+    set_exclusions = _set_exclusions
 
     def compute_static(self, x, y, z, q, out):
         """msm_compute_static: the evaluation of compute() with the library's
