@@ -317,6 +317,15 @@ void refresh_launch(msm_plan* P) {
   lg.scan.blocks = sb.scan;
   lg.agather.blocks = sb.agather;
   lg.anterp_lds = msm::anterp_lds(g);
+  // large grids: one prolongation launch per level instead of every block
+  // rebuilding the coarser levels it reads (a level-0 tile of 8^3 nodes would
+  // rebuild boxes of up to (2R + 3)^3 nodes on every coarser level)
+  int tiles0 = 0;
+  for (int k = 0; k + 1 < g.levels; ++k) {
+    lg.prolong_level[k] = msm::prolong_level_blocks(g, k);
+    if (k == 0) tiles0 = lg.prolong_level[k];
+  }
+  lg.prolong_split = g.levels > 1 && tiles0 >= msm::kProlongSplitTiles;
   lg.shortr.blocks = sb.shortr;
   lg.anterp.blocks = sb.anterp;
   lg.lattice0.blocks = sb.lattice0;
@@ -931,7 +940,8 @@ msm_status msm_plan_describe(const msm_plan* P, char* buf, size_t buf_bytes) {
          std::to_string(bank_conflicts(t.xl, t.ty, t.tz, P->lat.b, t.px, t.pp)) + ", " +
          std::to_string(t.groups) + "]";
   }
-  o += "], \"workspace_bytes\": " + std::to_string(P->lay.total) + "}";
+  o += "], \"prolong_per_level\": " + std::to_string(P->lg.prolong_split ? 1 : 0);
+  o += ", \"workspace_bytes\": " + std::to_string(P->lay.total) + "}";
   std::strncpy(buf, o.c_str(), buf_bytes - 1);
   buf[buf_bytes - 1] = 0;
   return o.size() < buf_bytes ? MSM_OK : fail(MSM_ERR_INVALID_ARG, "buffer too small");

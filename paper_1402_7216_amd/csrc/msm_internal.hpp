@@ -27,6 +27,7 @@ constexpr int kBinRowMaxBlocks = 256;     // blocks of the one-kernel binning pe
 constexpr int kStatusWords = 64 + kBinRowMaxBlocks;   // [0]: flags; [64 + b]: flags of binning block b
 constexpr int kScanTile = 4096;           // cells per block of the four-kernel binning's scan
 constexpr int kXcds = 8;                  // accelerator dies of the chip, each with its own L2
+constexpr int kProlongSplitTiles = 1000;  // level-0 prolongation tiles from which each level gets its own launch
 
 enum DeviceFlag : int { kFlagOutOfBox = 1, kFlagNonFinite = 2, kFlagCoincident = 4, kFlagBadExclusion = 8 };
 
@@ -289,6 +290,8 @@ struct LaunchGeom {
   StageGrid scan;                    // tiles of the four-kernel binning's cell-count scan
   StageGrid agather;                 // level-0 nodes (gather of the anterpolation partials)
   int anterp_lds = 0;                // dynamic LDS of the anterpolation (largest system)
+  bool prolong_split = false;        // one prolongation launch per level (one large system)
+  int prolong_level[kMaxLevels] = {};   // prolongation tiles of each level below the top
   StageGrid bin;                     // two-kernel binning (systems with bin_blocks > 0)
   StageGrid binrow;                  // one-kernel binning (systems with bin_row_blocks > 0)
   int binrow_lds = 0;                // dynamic LDS of the one-kernel binning (largest system)
@@ -308,6 +311,7 @@ struct SysBlocks {
   int prolong;                       // tiles of every level below the top
 };
 SysBlocks system_blocks(const Geom& g, const LatLaunch& lat, int n_partials);
+int prolong_level_blocks(const Geom& g, int k);   // prolongation tiles of level k
 
 // Dynamic LDS of the one-kernel binning for one system: per-wave counts of the
 // cells a block owns, scan scratch, and a 16-bit list entry per atom.

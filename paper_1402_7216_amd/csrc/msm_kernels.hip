@@ -1024,18 +1024,14 @@ constexpr int kAThreads = 256;
 
 // round(v 2^36) as a 64-bit integer from float arithmetic: v 16 = hi + frac
 // with hi = floor(v 16) and frac in [0, 1) (both exact); frac 2^32 is exact
-// and rounded to the nearest integer (a carry when it rounds up to 2^32).
+// and rounded to the nearest integer.  frac is at most 1 - 2^-24 (the largest
+// float below 1), so the rounding never reaches 2^32 and needs no carry.
 // Valid for |v| < 2^27.
 __device__ __forceinline__ unsigned long long fixed36(float v) {
   const float a = v * 16.f;
   const float hi = floorf(a);
-  float lo = rintf((a - hi) * 4294967296.f);
-  int h = (int)hi;
-  if (lo >= 4294967296.f) {
-    lo = 0.f;
-    h += 1;
-  }
-  return ((unsigned long long)(unsigned)h << 32) + (unsigned long long)(unsigned)lo;
+  const float lo = rintf((a - hi) * 4294967296.f);
+  return ((unsigned long long)(unsigned)(int)hi << 32) + (unsigned long long)(unsigned)lo;
 }
 
 template <int ORDER>
@@ -1725,8 +1721,15 @@ __host__ __device__ constexpr int prolong_box(int order) {
 
 // Few waves per SIMD (one launch of a few hundred blocks): registers are spent
 // on loads in flight instead of occupancy.
-template <int ORDER>
-__global__ void __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(1, 2))) k_prolong(KArgs A) {
+//
+// With ONE set the launch covers the tiles of level `level` only and reads the
+// finished u^{level+1} from global memory (written by the launch of the level
+// above), so nothing is rebuilt: for large grids, where a level-0 block would
+// otherwise rebuild several (2R + 3)^3 boxes for its 8^3 nodes, the per-level
+// launches do each level's work once.  Results are the same either way.
+template <int ORDER, bool ONE>
+__global__ void __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(1, 2)))
+k_prolong(KArgs A, int level) {
   int blk;
   __shared__ __align__(16) SysDesc sdesc;
   const SysDesc& S = stage_desc(sys_of(A, blk), &sdesc);
@@ -1740,11 +1743,15 @@ __global__ void __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(
   const int top = g.levels - 1;
   // level and tile of this block
   int k = 0, t = blk;
-  while (k + 1 < top && t >= prolong_tiles(g.lv[k])) {
-    t -= prolong_tiles(g.lv[k]);
-    ++k;
+  if (ONE) {
+    k = level;
+  } else {
+    while (k + 1 < top && t >= prolong_tiles(g.lv[k])) {
+      t -= prolong_tiles(g.lv[k]);
+      ++k;
+    }
   }
-  float* __restrict__ xs = pbox + (top - k) * BOX;     // x-pass sums of the box being built
+  float* __restrict__ xs = pbox + (ONE ? 1 : top - k) * BOX;     // x-pass sums of the box being built
   const Level F = g.lv[k];
   const int ntx = (F.n[0] + kPX - 1) / kPX, nty = (F.n[1] + kPY - 1) / kPY;
   const int bx = t % ntx, by = (t / ntx) % nty, bz = t / (ntx * nty);
@@ -1758,7 +1765,7 @@ __global__ void __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(
   // u^{j,cut} for the others (the sum of the partials in group order where
   // grouped), zero outside the grids.  Every load of a round is issued before
   // the first sum; the per-level choices are uniform branches.
-  const int nlev = top - k;
+  const int nlev = ONE ? 1 : top - k;
   for (int j0 = 0; j0 < nlev; j0 += LV) {
     float fv[LV][SL];
     double pv[LV][SL][kLatMaxGroups];
@@ -1772,7 +1779,7 @@ __global__ void __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(
       int o[3], e[3];
       box_of<R>(k, j, to, o, e);
       const Level J = g.lv[j];
-      const int groups = (j == top || S.lat.b == 0 || j >= S.lat.n) ? 1 : S.lat.t[j].groups;
+      const int groups = (ONE || j == top || S.lat.b == 0 || j >= S.lat.n) ? 1 : S.lat.t[j].groups;
       ng[lv] = groups;
       const float inv_e0 = 1.f / (float)e[0], inv_e01 = 1.f / (float)(e[0] * e[1]);
       int jn[SL];
@@ -1787,7 +1794,7 @@ __global__ void __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(
         jn[sl] = J.off + (ok[lv][sl] ? (vz * J.n[1] + vy) * J.n[0] + vx : 0);
       }
       if (groups == 1) {
-        const float* __restrict__ src = (j == top) ? u : S.d.ucut;
+        const float* __restrict__ src = (ONE || j == top) ? u : S.d.ucut;   // finished u, or u^{j,cut}
 #pragma unroll
         for (int sl = 0; sl < SL; ++sl) fv[lv][sl] = src[jn[sl]];
       } else {
@@ -1822,7 +1829,7 @@ __global__ void __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(
   }
   __syncthreads();
   // levels top-1 .. k+1 in place: u^j = u^{j,cut} + prolongation of u^{j+1}
-  for (int j = top - 1; j > k; --j) {
+  for (int j = ONE ? k : top - 1; j > k; --j) {
     const Level J = g.lv[j];
     int jo[3], je[3], co[3], ce[3];
     box_of<R>(k, j, to, jo, je);
@@ -2265,6 +2272,8 @@ SysBlocks system_blocks(const Geom& g, const LatLaunch& lat, int n_partials) {
   return b;
 }
 
+int prolong_level_blocks(const Geom& g, int k) { return prolong_tiles(g.lv[k]); }
+
 hipError_t launch_init(const LaunchGeom& L, hipStream_t s) {
   if (L.zero.blocks > 0) k_zero_counts<<<L.zero.blocks, kBlock, 0, s>>>(KArgs{L.sys, L.zero.map, Io{}});
   return hipGetLastError();
@@ -2484,14 +2493,28 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
   mark(kStageProlong);
   if (lat0_side) join(cc->lattice0);                 // u^0 adds the level-0 cutoff potential
   beg(kStageProlong, s);
-  if (L.prolong.blocks > 0) {
+  if (L.prolong.blocks > 0 && L.prolong_split) {
+    // one launch per level, coarse to fine (a single system: no block tables)
+    const int lds = 2 * prolong_box(L.order) * (int)sizeof(float);             // one box + x-pass sums
+    for (int k = L.max_levels - 2; k >= 0; --k) {
+      const int nb = L.prolong_level[k];
+      if (nb == 0) continue;
+      const KArgs A{L.sys, nullptr, io};
+      if (L.order == 4)
+        k_prolong<4, true><<<nb, kPThreads, lds, s>>>(A, k);
+      else
+        k_prolong<6, true><<<nb, kPThreads, lds, s>>>(A, k);
+    }
+  } else if (L.prolong.blocks > 0) {
     const int lds = L.max_levels * prolong_box(L.order) * (int)sizeof(float);   // boxes + x-pass sums
     if (L.order == 4) {
-      (void)hipFuncSetAttribute((const void*)k_prolong<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-      k_prolong<4><<<L.prolong.blocks, kPThreads, lds, s>>>(args(L.prolong));
+      (void)hipFuncSetAttribute((const void*)k_prolong<4, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                lds);
+      k_prolong<4, false><<<L.prolong.blocks, kPThreads, lds, s>>>(args(L.prolong), 0);
     } else {
-      (void)hipFuncSetAttribute((const void*)k_prolong<6>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-      k_prolong<6><<<L.prolong.blocks, kPThreads, lds, s>>>(args(L.prolong));
+      (void)hipFuncSetAttribute((const void*)k_prolong<6, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                lds);
+      k_prolong<6, false><<<L.prolong.blocks, kPThreads, lds, s>>>(args(L.prolong), 0);
     }
   }
   end(kStageProlong, s);

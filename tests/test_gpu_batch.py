@@ -103,6 +103,26 @@ def test_batch_equals_single_system_path_bitwise(M, batch64, replicas):
         assert torch.equal(o["virial"].reshape(9), out["virial"][s]), s
 
 
+def test_per_level_prolongation_equals_one_launch_bitwise(M):
+    """The 1M-atom plan prolongs one level per launch (reading each finished
+    coarser level back from HBM); a batch holding the same system alone uses
+    the single launch in which every block rebuilds the coarser levels.  Same
+    tuning, same arithmetic: bitwise equal outputs."""
+    s = inputs.water_1m()
+    plan = M.plan_for(s)
+    assert plan.describe()["prolong_per_level"] == 1
+    b = M.batch_for([s])
+    assert b.describe().get("prolong_per_level", 0) == 0
+    d = plan.tuning()
+    b.tune(**d)
+    x, y, z, q = M.to_device(s)
+    o1 = {k: v.clone() for k, v in plan.compute(x, y, z, q).items()}
+    o2 = b.compute(x, y, z, q)
+    torch.cuda.synchronize()
+    assert torch.equal(o1["f"], o2["f"]) and torch.equal(o1["phi"], o2["phi"])
+    assert float(o1["energy"].item()) == float(o2["energy"][0].item())
+
+
 def test_batch_graph_replay_matches_eager(M, batch64):
     b, (x, y, z, q), ref = batch64
     out = b.outputs(virial=True)
