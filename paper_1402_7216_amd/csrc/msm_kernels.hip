@@ -1034,6 +1034,51 @@ __device__ __forceinline__ unsigned long long fixed36(float v) {
   return ((unsigned long long)(unsigned)(int)hi << 32) + (unsigned long long)(unsigned)lo;
 }
 
+// Whether the tile with corner n0 (floor indices) and extent T owns the atom
+// at p; f receives its tile-local floor indices.
+template <int ORDER>
+__device__ __forceinline__ bool owned(const Geom& g, const float4 p, const int* n0, const int* T, int* f) {
+  const float pp[3] = {p.x, p.y, p.z};
+  bool own = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    float r;
+    grid_coord(pp[d], g.lo_f[d], g.h, g.inv_h, g.fmax[d], f[d], r);
+    f[d] -= n0[d];
+    own = own && f[d] >= 0 && f[d] < T[d];
+  }
+  return own;
+}
+
+// One owned atom's ORDER^3 contributions to the tile's region (ex x ey x ...
+// nodes, x fastest) as 2^-36 fixed-point LDS atomics.
+template <int ORDER>
+__device__ __forceinline__ void anterp_scatter(const Geom& g, const float4 p, const int* n0, const int* T,
+                                               int ex, int ey, unsigned long long* acc) {
+  const float pp[3] = {p.x, p.y, p.z};
+  int f[3];
+  float r[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    grid_coord(pp[d], g.lo_f[d], g.h, g.inv_h, g.fmax[d], f[d], r[d]);
+    f[d] -= n0[d];
+  }
+  float w[3][ORDER], dw[3][ORDER];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) basis<ORDER>(r[d], w[d], dw[d]);
+#pragma unroll
+  for (int sz = 0; sz < ORDER; ++sz) {
+    const float qz = p.w * w[2][sz];
+#pragma unroll
+    for (int sy = 0; sy < ORDER; ++sy) {
+      const float qyz = qz * w[1][sy];
+      unsigned long long* rowp = acc + ((f[2] + sz) * ey + (f[1] + sy)) * ex + f[0];
+#pragma unroll
+      for (int sx = 0; sx < ORDER; ++sx) atomicAdd(rowp + sx, fixed36(qyz * w[0][sx]));
+    }
+  }
+}
+
 template <int ORDER>
 __global__ void __launch_bounds__(kAThreads) k_anterp(KArgs A) {
   int blk;
@@ -1043,6 +1088,13 @@ __global__ void __launch_bounds__(kAThreads) k_anterp(KArgs A) {
   const int* __restrict__ start = S.d.cell_start;
   extern __shared__ unsigned long long acc[];
   __shared__ int row_beg[64], row_pre[65];
+  // owned atoms wait here until a whole round of them (one per thread) is
+  // there, so the scatter runs with every lane busy (about a third of the
+  // candidates lie in the margin cells and belong to other tiles)
+  __shared__ float4 queue[2 * kAThreads];
+  __shared__ int wcount[kAThreads / kWave];
+  __shared__ int qlen;
+  if (threadIdx.x == 0) qlen = 0;
   const int T[3] = {g.at[0], g.at[1], g.at[2]};
   const int ex = T[0] + ORDER - 1, ey = T[1] + ORDER - 1;
   const int ext = g.at_ext;
@@ -1088,36 +1140,43 @@ __global__ void __launch_bounds__(kAThreads) k_anterp(KArgs A) {
     __syncthreads();
     const int ncand = row_pre[nr];
     int row = 0;
-    for (int t = threadIdx.x; t < ncand; t += kAThreads) {
-      while (row_pre[row + 1] <= t) ++row;
-      const float4 p = sorted[row_beg[row] + (t - row_pre[row])];
-      const float pp[3] = {p.x, p.y, p.z};
-      int f[3];
-      float r[3];
-      bool own = true;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        grid_coord(pp[d], g.lo_f[d], g.h, g.inv_h, g.fmax[d], f[d], r[d]);
-        f[d] -= n0[d];
-        own = own && f[d] >= 0 && f[d] < T[d];
+    for (int t0 = 0; t0 < ncand; t0 += kAThreads) {
+      // candidates of this round: the owned ones join the queue
+      const int t = t0 + (int)threadIdx.x;
+      float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
+      bool own = false;
+      if (t < ncand) {
+        while (row_pre[row + 1] <= t) ++row;
+        p = sorted[row_beg[row] + (t - row_pre[row])];
+        int f[3];
+        own = owned<ORDER>(g, p, n0, T, f);
       }
-      if (!own) continue;
-      float w[3][ORDER], dw[3][ORDER];
+      const unsigned long long m = __ballot(own);
+      const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+      if (lane == 0) wcount[wave] = __popcll(m);
+      __syncthreads();
+      int total = qlen, base = qlen;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) basis<ORDER>(r[d], w[d], dw[d]);
-#pragma unroll
-      for (int sz = 0; sz < ORDER; ++sz) {
-        const float qz = p.w * w[2][sz];
-#pragma unroll
-        for (int sy = 0; sy < ORDER; ++sy) {
-          const float qyz = qz * w[1][sy];
-          unsigned long long* rowp = acc + ((f[2] + sz) * ey + (f[1] + sy)) * ex + f[0];
-#pragma unroll
-          for (int sx = 0; sx < ORDER; ++sx) atomicAdd(rowp + sx, fixed36(qyz * w[0][sx]));
-        }
+      for (int w = 0; w < kAThreads / kWave; ++w) {
+        base += w < wave ? wcount[w] : 0;
+        total += wcount[w];
       }
+      if (own) queue[base + __popcll(m & ((1ull << lane) - 1))] = p;
+      __syncthreads();
+      if (total >= kAThreads) {
+        // a full round: one queued atom per thread, then the rest to the front
+        anterp_scatter<ORDER>(g, queue[threadIdx.x], n0, T, ex, ey, acc);
+        const int rest = total - kAThreads;
+        const float4 v = (int)threadIdx.x < rest ? queue[kAThreads + threadIdx.x] : p;
+        __syncthreads();
+        if ((int)threadIdx.x < rest) queue[threadIdx.x] = v;
+        total = rest;
+      }
+      if (threadIdx.x == 0) qlen = total;
+      __syncthreads();
     }
   }
+  if ((int)threadIdx.x < qlen) anterp_scatter<ORDER>(g, queue[threadIdx.x], n0, T, ex, ey, acc);
   __syncthreads();
   long long* __restrict__ out = S.d.ant_part + (size_t)blk * ext;
   for (int i = threadIdx.x; i < ext; i += kAThreads) out[i] = (long long)acc[i];
