@@ -254,8 +254,12 @@ __host__ __device__ inline int xcd_block(int b, int n) {
   return x * per + (x < rem ? x : rem) + i;
 }
 
-__device__ inline const SysDesc& sys_of(const KArgs& a, int& blk) {
-  const int b = xcd_block((int)blockIdx.x, (int)gridDim.x);
+// remap false keeps the dispatcher's round-robin over the dies: for launches
+// whose blocks differ in cost (the lattice cutoff holds every level's tiles
+// and the top-level blocks), contiguous ranges per die would load the dies
+// unevenly.
+__device__ inline const SysDesc& sys_of(const KArgs& a, int& blk, bool remap = true) {
+  const int b = remap ? xcd_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
   if (a.map) {
     const int2 m = a.map[b];
     blk = m.y;

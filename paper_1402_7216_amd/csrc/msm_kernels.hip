@@ -1506,7 +1506,7 @@ __device__ __forceinline__ void row_win_dispatch(int xr, float* acc, const float
 template <int B>
 __global__ void __launch_bounds__(kLatThreads, B <= 6 ? 8 : 4) k_lattice_win(KArgs A, int part) {
   int blk;
-  const SysDesc& S = sys_of(A, blk);
+  const SysDesc& S = sys_of(A, blk, false);
   const Geom& g = S.g;
   const LatLaunch& P = S.lat;
   {
