@@ -158,18 +158,45 @@ __device__ __forceinline__ int cell_index(const Geom& g, float x, float y, float
   return (cell_coord(g, z, 2) * g.nc[1] + cell_coord(g, y, 1)) * g.nc[0] + cell_coord(g, x, 0);
 }
 
+// Runs of equal cells among the lanes of a wave (consecutive input atoms —
+// the sites of one molecule — often share a cell): a lane heads a run when
+// its left neighbour (among the active lanes) has another cell.  Returns the
+// run's length for its head (0 for the other lanes) and, in head, the lane
+// of the run's head.  The whole wave must call it (inactive lanes pass
+// active = false).
+__device__ __forceinline__ int cell_run(int c, bool active, int& head) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int left = __shfl_up(c, 1);
+  const unsigned long long act = __ballot(active);
+  const bool starts = active && (lane == 0 || !((act >> (lane - 1)) & 1ull) || left != c);
+  const unsigned long long heads = __ballot(starts);
+  const unsigned long long upto = heads & (lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull));
+  head = upto ? 63 - __clzll(upto) : lane;
+  if (!starts) return 0;
+  // the run ends at the next head or at the first inactive lane after it
+  const unsigned long long stop = (heads | ~act) & (lane == kWave - 1 ? 0ull : ~((2ull << lane) - 1ull));
+  const int end = stop ? __ffsll(stop) - 1 : kWave;
+  return end - lane;
+}
+
 __global__ void k_bin_count(KArgs A) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
   const Geom& g = S.g;
+  if (g.bin_blocks || g.bin_row_blocks) return;
   const int i = blk * blockDim.x + threadIdx.x;
-  if (i >= g.n_atoms || g.bin_blocks || g.bin_row_blocks) return;
-  const float* x = A.io.x + S.atom_off;
-  const float* y = A.io.y + S.atom_off;
-  const float* z = A.io.z + S.atom_off;
-  const int c = cell_index(g, x[i], y[i], z[i]);
-  S.d.cell_of[i] = c;
-  atomicAdd(&S.d.counts[c], 1);
+  const bool active = i < g.n_atoms;
+  int c = -1;
+  if (active) {
+    const float* x = A.io.x + S.atom_off;
+    const float* y = A.io.y + S.atom_off;
+    const float* z = A.io.z + S.atom_off;
+    c = cell_index(g, x[i], y[i], z[i]);
+    S.d.cell_of[i] = c;
+  }
+  int head;
+  const int run = cell_run(c, active, head);
+  if (run > 0) atomicAdd(&S.d.counts[c], run);
 }
 
 // Exclusive scan of counts[0..n) into start[0..n] in two launches over tiles
@@ -261,20 +288,29 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(KArgs A) {
 __global__ void k_bin_scatter(KArgs A) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
+  if (S.g.bin_blocks || S.g.bin_row_blocks) return;
   const int i = blk * blockDim.x + threadIdx.x;
-  if (i >= S.g.n_atoms || S.g.bin_blocks || S.g.bin_row_blocks) return;
-  const float* x = A.io.x + S.atom_off;
-  const float* y = A.io.y + S.atom_off;
-  const float* z = A.io.z + S.atom_off;
-  const float* q = A.io.q + S.atom_off;
+  const bool active = i < S.g.n_atoms;
   const int* __restrict__ cell_of = S.d.cell_of;
   const int* __restrict__ start = S.d.cell_start;
   int* __restrict__ cursor = S.d.cursor;
   int* __restrict__ tmp = S.d.tmp;
   float4* __restrict__ tmp4 = S.d.fshort;   // coordinate copies until k_bin_place
+  const int c = active ? cell_of[i] : -1;
+  // one cursor atomic per run of equal cells; the run's lanes take
+  // consecutive slots after the head's
+  int head;
+  const int run = cell_run(c, active, head);
+  int base = 0;
+  if (run > 0) base = start[c] + atomicAdd(&cursor[c], run);
+  base = __shfl(base, head);
+  if (!active) return;
+  const float* x = A.io.x + S.atom_off;
+  const float* y = A.io.y + S.atom_off;
+  const float* z = A.io.z + S.atom_off;
+  const float* q = A.io.q + S.atom_off;
   const float4 p = make_float4(x[i], y[i], z[i], q[i]);
-  const int c = cell_of[i];
-  const int slot = start[c] + atomicAdd(&cursor[c], 1);
+  const int slot = base + ((int)(threadIdx.x & (kWave - 1)) - head);
   if ((unsigned)slot >= (unsigned)S.g.n_atoms) return;   // only a corrupted workspace gets here
   tmp[slot] = i;
   tmp4[slot] = p;
