@@ -893,7 +893,6 @@ __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, 
     pk[k] = v;
   }
   float4* jb = jbuf[wave];
-  if (lane < 4) jb[kShortSeg + lane] = make_float4(3e30f, 3e30f, 3e30f, 0.f);
   const int R = g.reach, side = 2 * R + 1, centre = (side * side) / 2;
   // the launch has g.short_blocks blocks; work items are strided over them
   const int item_lo = (int)((long long)n_items * lo_pm / 1000);
@@ -904,6 +903,9 @@ __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, 
     const int rowbase = (cz * g.nc[1] + cy) * g.nc[0];
     const int rb = start[rowbase], re = start[rowbase + g.nc[0]];
     for (int ic = rb + kk * kWave; ic < re; ic += g.row_items * kWave) {
+      // the far entries, rewritten for every chunk: the previous chunk's sums
+      // of the waves met in these buffers
+      if (lane < 4) jb[kShortSeg + lane] = make_float4(3e30f, 3e30f, 3e30f, 0.f);
       const int ie = min(ic + kWave, re);
       const int i = ic + lane;
       const bool live = i < ie;

@@ -266,3 +266,30 @@ def test_autotune_keeps_results_within_bars(M):
     r = oracle.system_msm(s0)
     assert rel_err(float(o["energy"].item()), r["energy"]) <= ENERGY_RTOL
     assert rel_rms(o["f"].double().cpu().numpy(), r["f"]) <= FORCE_RTOL
+
+
+def test_batch_with_fine_cells_equals_single_plans(M):
+    """Cells of edge a/4 (the finest cell_reach) in a batch: the batch equals
+    single plans with the same tuning bit for bit, and a replica stays within
+    the bars."""
+    systems = inputs.water_replicas(64)[:6]
+    print(f"case batch reach 4 n={[s.n for s in systems]}", flush=True)
+    b = M.batch_for(systems)
+    b.tune(cell_reach=4)
+    d = b.describe()
+    x, y, z, q = M.batch_to_device(systems)
+    out = b.compute(x, y, z, q)
+    torch.cuda.synchronize()
+    b.check()
+    for s, sys_ in enumerate(systems):
+        plan = M.plan_for(sys_)
+        plan.tune(d["lattice_b"], d["item_chunks_all"][s], cell_reach=4)
+        o = plan.compute(*M.to_device(sys_))
+        torch.cuda.synchronize()
+        a, e = b.offsets[s], b.offsets[s + 1]
+        assert torch.equal(o["f"], out["f"][:, a:e]), s
+        assert torch.equal(o["phi"], out["phi"][a:e]), s
+    r = oracle.system_msm(systems[1])
+    e, f, phi = _slice(out, b.offsets, 1)
+    assert rel_err(e, r["energy"]) <= ENERGY_RTOL
+    assert rel_rms(f, r["f"]) <= FORCE_RTOL and rel_rms(phi, r["phi"]) <= PHI_RTOL

@@ -428,6 +428,29 @@ def test_cell_reach_keeps_bars(M, reach):
         check_full(g, r, f"reach{reach}-{s.name}")
 
 
+@pytest.mark.parametrize("reach", [2, 4])
+def test_dense_cloud_with_long_row_windows(M, reach):
+    """A charge cloud four times denser than water: the union of a chunk's x
+    windows in one cell row exceeds the 256 atoms a wave stages at a time, so
+    every row is walked in several segments and lanes step past the end of a
+    segment onto its far-away entries (which must stay far away from one chunk
+    to the next).  A random +-q cloud: its energy and potentials are held
+    to the bar of such clouds (check_degenerate), forces to 1e-5."""
+    s = inputs.uniform_charges(20000, 36.0, seed=77, cutoff=12.0, spacing=2.0, order=4, levels=2)
+    print(f"case dense cloud reach {reach} n={s.n}", flush=True)
+    plan = M.plan_for(s)
+    plan.tune(cell_reach=reach)
+    x, y, z, q = M.to_device(s)
+    o = plan.compute(x, y, z, q)
+    torch.cuda.synchronize()
+    plan.check()
+    r = oracle.system_msm(s)
+    g = dict(energy=float(o["energy"].item()), f=o["f"].double().cpu().numpy(),
+             phi=o["phi"].double().cpu().numpy(), code=0, flags=0)
+    assert rel_rms(g["f"], r["f"]) <= FORCE_RTOL
+    check_degenerate(g, r, s, f"dense-reach{reach}")
+
+
 def test_output_buffers_are_validated(M):
     """The kernels write outputs through raw pointers, so the binding rejects
     buffers of the wrong dtype, size or layout instead of writing past them."""
