@@ -83,6 +83,16 @@ def lib():
         L.oracle_inside_f32.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp, dp, ctypes.c_double, ip]
         L.oracle_gamma_coeffs.restype = None
         L.oracle_gamma_coeffs.argtypes = [ctypes.c_int, dp]
+        L.oracle_msm_periodic.restype = ctypes.c_int
+        L.oracle_msm_periodic.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, dp, dp, dp, dp, dp, dp, dp,
+                                          dp, dp, dp, dp, dp, dp, dp, ctypes.c_int]
+        L.oracle_periodic_layout.restype = ctypes.c_int
+        L.oracle_periodic_layout.argtypes = [ctypes.POINTER(_Params), ip, ip]
+        L.oracle_periodic_top_kernel.restype = ctypes.c_int
+        L.oracle_periodic_top_kernel.argtypes = [ctypes.POINTER(_Params), dp, ctypes.c_int]
+        L.oracle_ewald.restype = ctypes.c_int
+        L.oracle_ewald.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp, dp, ctypes.c_double, dp, dp, dp, dp, dp,
+                                   ctypes.c_int]
         _lib = L
     return _lib
 
@@ -130,8 +140,73 @@ def split_grids(flat, n):
     return out
 
 
+def periodic_layout(**params):
+    """Periodic level count and nodes per level: (levels, n[L,3])."""
+    p = _params(**params)
+    n = np.zeros(3 * 16, dtype=np.int32)
+    lv = ctypes.c_int(0)
+    ip = ctypes.POINTER(ctypes.c_int)
+    rc = lib().oracle_periodic_layout(ctypes.byref(p), ctypes.byref(lv), n.ctypes.data_as(ip))
+    if rc:
+        raise OracleError(rc)
+    L = lv.value
+    return L, n[:3 * L].reshape(L, 3).copy()
+
+
+def periodic_top_kernel(**params):
+    """The periodic top-level kernel K at the node offsets of the top grid, [nz, ny, nx]."""
+    L, n = periodic_layout(**params)
+    top = n[L - 1]
+    K = np.zeros(int(np.prod(top)))
+    rc = lib().oracle_periodic_top_kernel(ctypes.byref(_params(**params)), _dptr(K), int(K.shape[0]))
+    if rc:
+        raise OracleError(rc)
+    return K.reshape(int(top[2]), int(top[1]), int(top[0]))
+
+
+def _msm_periodic(x, y, z, q, prm, grids, threads):
+    p = _params(**prm)
+    L, gn = periodic_layout(**prm)
+    n = int(x.shape[0])
+    ng = int(sum(int(np.prod(v)) for v in gn))
+    fx, fy, fz = np.zeros(n), np.zeros(n), np.zeros(n)
+    phi, phis = np.zeros(n), np.zeros(n)
+    e = np.zeros(1)
+    w = np.zeros(9)
+    qg = np.zeros(ng) if grids else None
+    uc = np.zeros(ng) if grids else None
+    ug = np.zeros(ng) if grids else None
+    rc = lib().oracle_msm_periodic(ctypes.byref(p), n, _dptr(x), _dptr(y), _dptr(z), _dptr(q), _dptr(fx),
+                                   _dptr(fy), _dptr(fz), _dptr(phi), _dptr(e), _dptr(w), _dptr(qg), _dptr(uc),
+                                   _dptr(ug), _dptr(phis), int(threads))
+    if rc:
+        raise OracleError(rc)
+    out = dict(f=np.stack([fx, fy, fz]), phi=phi, phis=phis, levels=L, gn=gn, energy=float(e[0]),
+               virial=w.reshape(3, 3))
+    if grids:
+        out["q"] = split_grids(qg, gn)
+        out["ucut"] = split_grids(uc, gn)
+        out["u"] = split_grids(ug, gn)
+    return out
+
+
+def ewald(x, y, z, q, *, box_lo, box_len, ke=1.0, threads=0):
+    """Ewald summation of point charges in the periodic box: the exact
+    periodic Coulomb energy, potentials phi[N] and forces f[3,N]."""
+    x, y, z, q = _f64(x), _f64(y), _f64(z), _f64(q)
+    n = int(x.shape[0])
+    lo, ln = _f64(box_lo), _f64(box_len)
+    fx, fy, fz, phi, e = np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(1)
+    rc = lib().oracle_ewald(n, _dptr(x), _dptr(y), _dptr(z), _dptr(q), _dptr(lo), _dptr(ln), float(ke),
+                            _dptr(fx), _dptr(fy), _dptr(fz), _dptr(phi), _dptr(e), int(threads))
+    if rc:
+        raise OracleError(rc)
+    return dict(f=np.stack([fx, fy, fz]), phi=phi, energy=float(e[0]))
+
+
 def msm(x, y, z, q, *, cutoff, spacing, order=4, split_m=0, levels=0, box_lo=(0, 0, 0),
-        box_len=(1, 1, 1), ke=1.0, grids=False, sample=None, short_mode=0, threads=0, exclusions=None):
+        box_len=(1, 1, 1), ke=1.0, grids=False, sample=None, short_mode=0, threads=0, exclusions=None,
+        periodic=False):
     """Run the FP64 oracle.
 
     Returns a dict with energy, forces f[3,N], potentials phi[N], virial[3,3],
@@ -140,11 +215,22 @@ def msm(x, y, z, q, *, cutoff, spacing, order=4, split_m=0, levels=0, box_lo=(0,
     With ``sample`` (atom indices) only those atoms' outputs are computed;
     energy and virial are then absent.  ``exclusions`` = (start, idx): bonded
     pairs left out (``exclusion_terms`` with kind "coulomb" taken off).
+    ``periodic``: the box repeats in every direction (every atom's images
+    interact; box_len / spacing must be an integer divisible by 2^(levels-1)
+    and 2 cutoff <= box_len); grids are then the periodic level grids.
     """
     x, y, z, q = _f64(x), _f64(y), _f64(z), _f64(q)
     n = int(x.shape[0])
     prm = dict(cutoff=cutoff, spacing=spacing, order=order, split_m=split_m, levels=levels,
                box_lo=box_lo, box_len=box_len, ke=ke)
+    if periodic:
+        if sample is not None or short_mode:
+            raise ValueError("periodic oracle: no sample or short_mode")
+        out = _msm_periodic(x, y, z, q, prm, grids, threads)
+        if exclusions is not None:
+            out = _minus_exclusions(out, x, y, z, q, exclusions, kind="coulomb", ke=ke, box_lo=box_lo,
+                                    box_len=box_len)
+        return out
     p = _params(**prm)
     L, glo, gn = layout(**prm)
     ng = int(sum(int(np.prod(v)) for v in gn))
@@ -180,7 +266,7 @@ def msm(x, y, z, q, *, cutoff, spacing, order=4, split_m=0, levels=0, box_lo=(0,
 
 
 def exclusion_terms(x, y, z, q, start, idx, *, kind="coulomb", cutoff=None, alpha=0.0, ke=1.0,
-                    f32_cut=False, box_lo=(0, 0, 0)):
+                    f32_cut=False, box_lo=(0, 0, 0), box_len=None):
     """The contribution of the listed (excluded) pairs, in FP64, to be taken
     off an evaluation: bonded pairs are left out of the Coulomb sum (Sec.
     "Calculation of Long-Range Interactions", before eq. (coulomb)).
@@ -190,15 +276,22 @@ def exclusion_terms(x, y, z, q, start, idx, *, kind="coulomb", cutoff=None, alph
     the exact smooth part).  A pair-method kind: that method's pair term e(r)
     for the pairs inside the cutoff (decided in float32 with f32_cut, as in
     ``pair``).  Partner lists in CSR form over input indices (start [N + 1],
-    idx), every pair listed from both sides.  Returns energy, f [3, N], phi [N]
-    and virial [3, 3] of those pairs."""
+    idx), every pair listed from both sides.  With ``box_len`` (periodic
+    boxes) each pair is taken at its nearest image and positions are mapped
+    into the box.  Returns energy, f [3, N], phi [N] and virial [3, 3] of
+    those pairs."""
     x, y, z, q = _f64(x), _f64(y), _f64(z), _f64(q)
     n = int(x.shape[0])
     start = np.asarray(start, dtype=np.int64)
     j = np.asarray(idx, dtype=np.int64)[:start[-1]]
     i = np.repeat(np.arange(n), np.diff(start))
     pos = np.stack([x, y, z])
+    if box_len is not None:
+        lo_, ln_ = np.asarray(box_lo, dtype=np.float64)[:, None], np.asarray(box_len, dtype=np.float64)[:, None]
+        pos = pos - ln_ * np.floor((pos - lo_) / ln_)
     d = pos[:, i] - pos[:, j]
+    if box_len is not None:
+        d = d - ln_ * np.rint(d / ln_)
     r = np.sqrt(np.sum(d * d, axis=0))
     if kind == "coulomb":
         e, de = 1.0 / r, -1.0 / (r * r)

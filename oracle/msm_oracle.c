@@ -895,3 +895,535 @@ int oracle_pair(int kind, double rc, double alpha, const double* lo, const doubl
   free(cell); free(start); free(list); free(ph); free(f3);
   return bad ? OR_ECOINCIDENT : OR_OK;
 }
+
+/* ========================================================================= */
+/* Periodic boundaries.                                                      */
+/* Reading (the thesis evaluates free-space systems and names periodicity    */
+/* only with the Fourier methods): the box is the unit cell of an infinite   */
+/* lattice of copies with periods len[d], and every sum of the method runs   */
+/* over the atoms of the central box and all their images:                   */
+/*   - short range: pairs (i, j, p) with |r_i - r_j + P p| < a, P = diag(len);*/
+/*     2a <= len[d], so at most one image of a pair is that close;           */
+/*   - level k is a periodic grid of n_k = (len / h) / 2^k nodes per         */
+/*     dimension (len / h an integer divisible by 2^(l-1)); anterpolation,   */
+/*     restriction, prolongation and interpolation take node indices modulo  */
+/*     n_k, and the lattice cutoff sums g^k over every image of a node pair;  */
+/*   - top level: K(r) = sum_p g^{l-1}(|r + P p|).  g^{l-1} decays as 1/r, so */
+/*     the lattice sum is taken in the Ewald convention (conducting boundary,*/
+/*     uniform neutralising background):                                     */
+/*       K(r) = Psi(r) - sum_p [1/|r + P p| - g^{l-1}(|r + P p|)],          */
+/*     Psi the Ewald lattice sum of 1/r; the bracket vanishes beyond         */
+/*     2^{l-1} a, where gamma(rho) = 1/rho.                                  */
+/* Atoms may lie anywhere; each is first mapped into [lo, lo + len).         */
+/* ========================================================================= */
+
+/* Ewald lattice sum of the Coulomb potential (Ewald 1921), splitting        */
+/* parameter beta:                                                           */
+/*   Psi(r) = sum_p erfc(beta |r + P p|)/|r + P p|                           */
+/*          + (4 pi / V) sum_{k != 0} exp(-k^2 / (4 beta^2)) / k^2 cos(k.r)  */
+/*          - pi / (V beta^2),                                               */
+/* k = 2 pi (n_x/len_x, n_y/len_y, n_z/len_z); and at r = 0 its regular part */
+/*   Psi_0 = lim_{r->0} (Psi(r) - 1/r)                                       */
+/*         = sum_{p != 0} erfc(beta |P p|)/|P p| + (4 pi / V) sum_k ...      */
+/*           - 2 beta / sqrt(pi) - pi / (V beta^2).                          */
+/* Terms are dropped below 1e-16 of the leading ones: images within          */
+/* 6.2 / beta, wave vectors with k^2 / (4 beta^2) <= 38.                     */
+typedef struct {
+  double len[3], V, beta, rc, kc2;
+  int pmax[3], kmax[3];
+} ewald_t;
+
+static void ewald_init(ewald_t* E, const double len[3], double beta) {
+  E->V = len[0] * len[1] * len[2];
+  E->beta = beta;
+  E->rc = 6.2 / beta;
+  E->kc2 = 4.0 * beta * beta * 38.0;
+  for (int d = 0; d < 3; ++d) {
+    E->len[d] = len[d];
+    E->pmax[d] = (int)ceil(E->rc / len[d]) + 1;
+    E->kmax[d] = (int)ceil(sqrt(E->kc2) * len[d] / (2.0 * OR_PI));
+  }
+}
+
+/* r: displacement; zero: r is a lattice point's own node (returns Psi_0) */
+static double ewald_psi(const ewald_t* E, const double r[3], int zero) {
+  double s = 0.0;
+  for (int pz = -E->pmax[2]; pz <= E->pmax[2]; ++pz)
+    for (int py = -E->pmax[1]; py <= E->pmax[1]; ++py)
+      for (int px = -E->pmax[0]; px <= E->pmax[0]; ++px) {
+        if (zero && px == 0 && py == 0 && pz == 0) continue;
+        double dx = r[0] + px * E->len[0], dy = r[1] + py * E->len[1], dz = r[2] + pz * E->len[2];
+        double rr = sqrt(dx * dx + dy * dy + dz * dz);
+        if (rr < E->rc) s += erfc(E->beta * rr) / rr;
+      }
+  double sk = 0.0;
+  for (int nz = -E->kmax[2]; nz <= E->kmax[2]; ++nz)
+    for (int ny = -E->kmax[1]; ny <= E->kmax[1]; ++ny)
+      for (int nx = -E->kmax[0]; nx <= E->kmax[0]; ++nx) {
+        if (nx == 0 && ny == 0 && nz == 0) continue;
+        double kx = 2.0 * OR_PI * nx / E->len[0], ky = 2.0 * OR_PI * ny / E->len[1];
+        double kz = 2.0 * OR_PI * nz / E->len[2];
+        double k2 = kx * kx + ky * ky + kz * kz;
+        if (k2 > E->kc2) continue;
+        sk += exp(-k2 / (4.0 * E->beta * E->beta)) / k2 * cos(kx * r[0] + ky * r[1] + kz * r[2]);
+      }
+  s += 4.0 * OR_PI / E->V * sk - OR_PI / (E->V * E->beta * E->beta);
+  if (zero) s -= 2.0 * E->beta / sqrt(OR_PI);
+  return s;
+}
+
+typedef struct {
+  ctx_t C;                         /* a, h, order, m, levels, lo, len, ke and gamma */
+  int n[OR_MAX_LEVELS][3];         /* nodes per level and dimension */
+  size_t off[OR_MAX_LEVELS + 1];   /* first node of each level in the concatenated grids */
+  double* K;                       /* top-level kernel, K[(dz n + dy) n + dx] for node offsets d */
+} pctx_t;
+
+static int wrapi(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+static size_t pidx(const pctx_t* P, int k, int ix, int iy, int iz) {
+  const int* n = P->n[k];
+  return P->off[k] + ((size_t)wrapi(iz, n[2]) * n[1] + (size_t)wrapi(iy, n[1])) * n[0] + (size_t)wrapi(ix, n[0]);
+}
+
+/* nodes per dimension (len / h, an integer) and level count: as given (every */
+/* level must halve), else the fewest levels whose top grid has at most 8     */
+/* nodes per side, stopping where a level cannot halve                         */
+static int periodic_shape(const oracle_params* p, int n0[3], int* levels) {
+  if (!(p->a > 0.0) || !(p->h > 0.0) || !isfinite(p->a) || !isfinite(p->h)) return OR_EINVAL;
+  for (int d = 0; d < 3; ++d) {
+    if (!(p->len[d] > 0.0) || !isfinite(p->len[d])) return OR_EINVAL;
+    double t = p->len[d] / p->h;
+    long r = lround(t);
+    if (r < 1 || fabs(t - (double)r) > 1e-9 * t || r > (1 << 20)) return OR_EINVAL;
+    if (2.0 * p->a > p->len[d]) return OR_EINVAL;
+    n0[d] = (int)r;
+  }
+  int l = p->levels;
+  if (l == 0) {
+    l = 1;
+    for (;;) {
+      int big = 0, even = 1;
+      for (int d = 0; d < 3; ++d) {
+        int nk = n0[d] >> (l - 1);
+        if (nk > 8) big = 1;
+        if (nk % 2) even = 0;
+      }
+      if (!big || !even || l == OR_MAX_LEVELS) break;
+      ++l;
+    }
+  }
+  if (l < 1 || l > OR_MAX_LEVELS) return OR_EINVAL;
+  for (int d = 0; d < 3; ++d)
+    if (n0[d] % (1 << (l - 1))) return OR_EINVAL;
+  *levels = l;
+  return OR_OK;
+}
+
+int oracle_periodic_layout(const oracle_params* p, int* levels, int* gn /* [L][3] */) {
+  int n0[3], l;
+  int rc = periodic_shape(p, n0, &l);
+  if (rc) return rc;
+  *levels = l;
+  for (int k = 0; k < l; ++k)
+    for (int d = 0; d < 3; ++d) gn[3 * k + d] = n0[d] >> k;
+  return OR_OK;
+}
+
+static int pctx_init(pctx_t* P, const oracle_params* p) {
+  memset(P, 0, sizeof(*P));
+  int n0[3], l;
+  int rc = periodic_shape(p, n0, &l);
+  if (rc) return rc;
+  oracle_params q = *p;
+  q.levels = l;
+  rc = ctx_init(&P->C, &q);           /* scalars and gamma; its free-space ranges go unused */
+  if (rc) return rc;
+  P->off[0] = 0;
+  for (int k = 0; k < l; ++k) {
+    for (int d = 0; d < 3; ++d) P->n[k][d] = n0[d] >> k;
+    P->off[k + 1] = P->off[k] + (size_t)P->n[k][0] * P->n[k][1] * P->n[k][2];
+  }
+  /* top-level kernel table */
+  const int t = l - 1;
+  const int* nt = P->n[t];
+  const size_t nn = (size_t)nt[0] * nt[1] * nt[2];
+  if (nn > 32768) return OR_EINVAL;
+  P->K = (double*)malloc(sizeof(double) * nn);
+  const double ht = ldexp(P->C.h, t), aL = ldexp(P->C.a, t);
+  double lmin = P->C.len[0];
+  for (int d = 1; d < 3; ++d) if (P->C.len[d] < lmin) lmin = P->C.len[d];
+  ewald_t E;
+  ewald_init(&E, P->C.len, 2.5 / lmin);
+  int im[3];
+  for (int d = 0; d < 3; ++d) im[d] = (int)ceil(aL / P->C.len[d]) + 1;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int e = 0; e < (int)nn; ++e) {
+    int dx = e % nt[0], dy = (e / nt[0]) % nt[1], dz = e / (nt[0] * nt[1]);
+    double r[3] = {ht * dx, ht * dy, ht * dz};
+    int zero = (dx == 0 && dy == 0 && dz == 0);
+    double s = ewald_psi(&E, r, zero);
+    if (zero) s += g_level(&P->C, t, 0.0);
+    for (int pz = -im[2]; pz <= im[2]; ++pz)
+      for (int py = -im[1]; py <= im[1]; ++py)
+        for (int px = -im[0]; px <= im[0]; ++px) {
+          if (zero && px == 0 && py == 0 && pz == 0) continue;
+          double vx = r[0] + px * P->C.len[0], vy = r[1] + py * P->C.len[1], vz = r[2] + pz * P->C.len[2];
+          double rho = sqrt(vx * vx + vy * vy + vz * vz);
+          if (rho < aL) s -= 1.0 / rho - g_level(&P->C, t, rho);
+        }
+    P->K[e] = s;
+  }
+  return OR_OK;
+}
+
+/* position mapped into [lo, lo + len) */
+static double wrap_pos(double x, double lo, double len) { return x - len * floor((x - lo) / len); }
+
+/* Periodic MSM: the stages above with node indices modulo n_k, the pair sum */
+/* over images and the top level through K.  Same outputs and conventions as */
+/* oracle_msm (grids: the periodic level grids, oracle_periodic_layout       */
+/* order, x fastest); the virial is sum_i (r_i - lo) F_i with r_i mapped     */
+/* into the box.                                                             */
+int oracle_msm_periodic(const oracle_params* p, int n, const double* x, const double* y, const double* z,
+                        const double* q, double* fx, double* fy, double* fz, double* phi, double* energy,
+                        double* virial, double* qgrid, double* ucut, double* ugrid, double* phis_out,
+                        int nthreads) {
+  pctx_t P;
+  int rc = pctx_init(&P, p);
+  if (rc) { free(P.K); return rc; }
+  const ctx_t* C = &P.C;
+  if (n < 0 || (n > 0 && (!x || !y || !z || !q))) { free(P.K); return OR_EINVAL; }
+  for (int i = 0; i < n; ++i)
+    if (!isfinite(x[i]) || !isfinite(y[i]) || !isfinite(z[i]) || !isfinite(q[i])) { free(P.K); return OR_ENONFINITE; }
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+  const int l = C->levels, no = C->order, half = C->order / 2, R = C->order - 1;
+  size_t na = (size_t)(n > 0 ? n : 1);
+  double* w3[3];
+  for (int d = 0; d < 3; ++d) w3[d] = (double*)malloc(sizeof(double) * na);
+  for (int i = 0; i < n; ++i) {
+    w3[0][i] = wrap_pos(x[i], C->lo[0], C->len[0]);
+    w3[1][i] = wrap_pos(y[i], C->lo[1], C->len[1]);
+    w3[2][i] = wrap_pos(z[i], C->lo[2], C->len[2]);
+  }
+  size_t ng = P.off[l];
+  double* qg = (double*)calloc(ng, sizeof(double));
+  double* uc = (double*)calloc(ng, sizeof(double));
+  double* ug = (double*)calloc(ng, sizeof(double));
+  double* ps = (double*)calloc(na, sizeof(double));
+  double* fs[3], *gl[3];
+  for (int d = 0; d < 3; ++d) { fs[d] = (double*)calloc(na, sizeof(double)); gl[d] = (double*)calloc(na, sizeof(double)); }
+  double* pl = (double*)calloc(na, sizeof(double));
+  int bad = 0;
+
+  /* short range: every pair at its nearest image, brute force */
+  const double a2 = C->a * C->a;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : bad)
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0, f[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < n; ++j) {
+      if (j == i) continue;
+      double dv[3], r2 = 0.0;
+      for (int d = 0; d < 3; ++d) {
+        dv[d] = w3[d][i] - w3[d][j];
+        dv[d] -= C->len[d] * nearbyint(dv[d] / C->len[d]);
+        r2 += dv[d] * dv[d];
+      }
+      if (r2 >= a2) continue;
+      if (r2 == 0.0) { bad = 1; continue; }
+      double rr = sqrt(r2);
+      s += q[j] * g_short(C, rr);
+      double w = -q[i] * q[j] * dg_short(C, rr) / rr;
+      for (int d = 0; d < 3; ++d) f[d] += w * dv[d];
+    }
+    ps[i] = s;
+    for (int d = 0; d < 3; ++d) fs[d][i] = f[d];
+  }
+  if (bad) { rc = OR_ECOINCIDENT; goto pdone; }
+
+  /* anterpolation (serial, atom order) */
+  for (int i = 0; i < n; ++i) {
+    double t[3], w[3][8];
+    int f[3];
+    for (int d = 0; d < 3; ++d) {
+      t[d] = (w3[d][i] - C->lo[d]) / C->h;
+      f[d] = (int)floor(t[d]);
+      for (int s = 0; s < no; ++s) w[d][s] = oracle_Phi(no, t[d] - (f[d] - (half - 1) + s));
+    }
+    for (int sz = 0; sz < no; ++sz)
+      for (int sy = 0; sy < no; ++sy)
+        for (int sx = 0; sx < no; ++sx)
+          qg[pidx(&P, 0, f[0] - (half - 1) + sx, f[1] - (half - 1) + sy, f[2] - (half - 1) + sz)] +=
+              q[i] * w[0][sx] * w[1][sy] * w[2][sz];
+  }
+  /* restriction */
+  for (int k = 0; k + 1 < l; ++k) {
+    const int* cn = P.n[k + 1];
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int mz = 0; mz < cn[2]; ++mz)
+      for (int my = 0; my < cn[1]; ++my)
+        for (int mx = 0; mx < cn[0]; ++mx) {
+          double s = 0.0;
+          for (int vz = 2 * mz - R; vz <= 2 * mz + R; ++vz) {
+            double wz = oracle_Phi(no, 0.5 * vz - mz);
+            for (int vy = 2 * my - R; vy <= 2 * my + R; ++vy) {
+              double wy = oracle_Phi(no, 0.5 * vy - my);
+              for (int vx = 2 * mx - R; vx <= 2 * mx + R; ++vx) {
+                double wx = oracle_Phi(no, 0.5 * vx - mx);
+                s += wx * wy * wz * qg[pidx(&P, k, vx, vy, vz)];
+              }
+            }
+          }
+          qg[pidx(&P, k + 1, mx, my, mz)] = s;
+        }
+  }
+  /* lattice cutoff below the top: every image of each node pair closer than 2^{k+1} a */
+  const int H = (int)ceil(2.0 * C->a / C->h);
+  for (int k = 0; k + 1 < l; ++k) {
+    const int* nk = P.n[k];
+    const double hk = ldexp(C->h, k), rcut = ldexp(C->a, k + 1);
+#pragma omp parallel for collapse(2) schedule(dynamic, 1)
+    for (int mz = 0; mz < nk[2]; ++mz)
+      for (int my = 0; my < nk[1]; ++my)
+        for (int mx = 0; mx < nk[0]; ++mx) {
+          double s = 0.0;
+          for (int sz = -H; sz <= H; ++sz)
+            for (int sy = -H; sy <= H; ++sy)
+              for (int sx = -H; sx <= H; ++sx) {
+                double d = hk * sqrt((double)(sx * sx + sy * sy + sz * sz));
+                if (d >= rcut) continue;
+                s += g_level(C, k, d) * qg[pidx(&P, k, mx + sx, my + sy, mz + sz)];
+              }
+          uc[pidx(&P, k, mx, my, mz)] = s;
+        }
+  }
+  /* top level through the periodic kernel */
+  {
+    const int t = l - 1;
+    const int* nt = P.n[t];
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int mz = 0; mz < nt[2]; ++mz)
+      for (int my = 0; my < nt[1]; ++my)
+        for (int mx = 0; mx < nt[0]; ++mx) {
+          double s = 0.0;
+          for (int vz = 0; vz < nt[2]; ++vz)
+            for (int vy = 0; vy < nt[1]; ++vy)
+              for (int vx = 0; vx < nt[0]; ++vx)
+                s += P.K[((size_t)wrapi(mz - vz, nt[2]) * nt[1] + wrapi(my - vy, nt[1])) * nt[0] +
+                         wrapi(mx - vx, nt[0])] * qg[pidx(&P, t, vx, vy, vz)];
+          uc[pidx(&P, t, mx, my, mz)] = s;
+        }
+  }
+  memcpy(ug, uc, ng * sizeof(double));
+  /* prolongation */
+  for (int k = l - 2; k >= 0; --k) {
+    const int* nk = P.n[k];
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int mz = 0; mz < nk[2]; ++mz)
+      for (int my = 0; my < nk[1]; ++my)
+        for (int mx = 0; mx < nk[0]; ++mx) {
+          double s = 0.0;
+          for (int vz = (mz - R + 1) >> 1; 2 * vz <= mz + R; ++vz) {
+            if (abs(mz - 2 * vz) > R) continue;
+            double wz = oracle_Phi(no, 0.5 * mz - vz);
+            for (int vy = (my - R + 1) >> 1; 2 * vy <= my + R; ++vy) {
+              if (abs(my - 2 * vy) > R) continue;
+              double wy = oracle_Phi(no, 0.5 * my - vy);
+              for (int vx = (mx - R + 1) >> 1; 2 * vx <= mx + R; ++vx) {
+                if (abs(mx - 2 * vx) > R) continue;
+                double wx = oracle_Phi(no, 0.5 * mx - vx);
+                s += wx * wy * wz * ug[pidx(&P, k + 1, vx, vy, vz)];
+              }
+            }
+          }
+          ug[pidx(&P, k, mx, my, mz)] += s;
+        }
+  }
+  /* interpolation */
+#pragma omp parallel for schedule(static)
+  for (int i = 0; i < n; ++i) {
+    double t[3], w[3][8], dw[3][8];
+    int f[3];
+    for (int d = 0; d < 3; ++d) {
+      t[d] = (w3[d][i] - C->lo[d]) / C->h;
+      f[d] = (int)floor(t[d]);
+      for (int e = 0; e < no; ++e) {
+        double u = t[d] - (f[d] - (half - 1) + e);
+        w[d][e] = oracle_Phi(no, u);
+        dw[d][e] = oracle_dPhi(no, u) / C->h;
+      }
+    }
+    double pv = 0.0, a0 = 0.0, a1 = 0.0, a2v = 0.0;
+    for (int sz = 0; sz < no; ++sz)
+      for (int sy = 0; sy < no; ++sy)
+        for (int sx = 0; sx < no; ++sx) {
+          double u = ug[pidx(&P, 0, f[0] - (half - 1) + sx, f[1] - (half - 1) + sy, f[2] - (half - 1) + sz)];
+          pv += w[0][sx] * w[1][sy] * w[2][sz] * u;
+          a0 += dw[0][sx] * w[1][sy] * w[2][sz] * u;
+          a1 += w[0][sx] * dw[1][sy] * w[2][sz] * u;
+          a2v += w[0][sx] * w[1][sy] * dw[2][sz] * u;
+        }
+    pl[i] = pv; gl[0][i] = a0; gl[1][i] = a1; gl[2][i] = a2v;
+  }
+  {
+    const double self = gamma_eval(C->c, C->m, 0.0) / C->a;
+    nsum_t e = {0.0, 0.0};
+    nsum_t w[9];
+    memset(w, 0, sizeof(w));
+    for (int i = 0; i < n; ++i) {
+      double ph = C->ke * (ps[i] + pl[i] - q[i] * self);
+      double f3[3], r3[3];
+      for (int d = 0; d < 3; ++d) {
+        f3[d] = C->ke * (fs[d][i] - q[i] * gl[d][i]);
+        r3[d] = w3[d][i] - C->lo[d];
+      }
+      if (phi) phi[i] = ph;
+      if (fx) fx[i] = f3[0];
+      if (fy) fy[i] = f3[1];
+      if (fz) fz[i] = f3[2];
+      if (phis_out) phis_out[i] = C->ke * ps[i];
+      nsum_add(&e, 0.5 * q[i] * ph);
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) nsum_add(&w[3 * a + b], r3[a] * f3[b]);
+    }
+    if (energy) *energy = e.s + e.c;
+    if (virial)
+      for (int t = 0; t < 9; ++t) virial[t] = w[t].s + w[t].c;
+  }
+  if (qgrid) memcpy(qgrid, qg, ng * sizeof(double));
+  if (ucut) memcpy(ucut, uc, ng * sizeof(double));
+  if (ugrid) memcpy(ugrid, ug, ng * sizeof(double));
+pdone:
+  free(P.K); free(qg); free(uc); free(ug); free(ps); free(pl);
+  for (int d = 0; d < 3; ++d) { free(w3[d]); free(fs[d]); free(gl[d]); }
+  return rc;
+}
+
+/* Periodic top-level kernel K at the node offsets of the top grid (the table */
+/* oracle_msm_periodic uses), for the pins.                                   */
+int oracle_periodic_top_kernel(const oracle_params* p, double* K, int cap) {
+  pctx_t P;
+  int rc = pctx_init(&P, p);
+  if (!rc) {
+    const int* nt = P.n[P.C.levels - 1];
+    size_t nn = (size_t)nt[0] * nt[1] * nt[2];
+    if ((size_t)cap < nn) rc = OR_EINVAL;
+    else memcpy(K, P.K, nn * sizeof(double));
+  }
+  free(P.K);
+  return rc;
+}
+
+/* Ewald summation of point charges in the periodic box (Ewald 1921): the    */
+/* exact periodic Coulomb energy, potentials and forces the periodic method  */
+/* approximates.  phi_i = sum_{(j,p) != (i,0)} q_j Psi-terms, E = 1/2 sum    */
+/* q_i phi_i, F_i = -q_i grad phi_i.  beta = 12 / min(len), so the real-space */
+/* part needs only each pair's nearest image (6.2 / beta < min(len) / 2).     */
+int oracle_ewald(int n, const double* x, const double* y, const double* z, const double* q,
+                 const double* lo, const double* len, double ke, double* fx, double* fy, double* fz,
+                 double* phi, double* energy, int nthreads) {
+  if (n < 0 || (n > 0 && (!x || !y || !z || !q)) || !lo || !len) return OR_EINVAL;
+  for (int d = 0; d < 3; ++d)
+    if (!(len[d] > 0.0) || !isfinite(len[d]) || !isfinite(lo[d])) return OR_EINVAL;
+  if (ke == 0.0) ke = 1.0;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+  double lmin = len[0];
+  for (int d = 1; d < 3; ++d) if (len[d] < lmin) lmin = len[d];
+  ewald_t E;
+  ewald_init(&E, len, 12.4 / lmin);
+  const double beta = E.beta, V = E.V;
+  size_t na = (size_t)(n > 0 ? n : 1);
+  double* r[3];
+  for (int d = 0; d < 3; ++d) r[d] = (double*)malloc(sizeof(double) * na);
+  for (int i = 0; i < n; ++i) {
+    r[0][i] = wrap_pos(x[i], lo[0], len[0]);
+    r[1][i] = wrap_pos(y[i], lo[1], len[1]);
+    r[2][i] = wrap_pos(z[i], lo[2], len[2]);
+  }
+  /* wave vectors and structure factors S(k) = sum_j q_j exp(i k.r_j) */
+  int nk = 0, cap = (2 * E.kmax[0] + 1) * (2 * E.kmax[1] + 1) * (2 * E.kmax[2] + 1);
+  double* kv = (double*)malloc(sizeof(double) * 4 * (size_t)cap);
+  for (int nz = -E.kmax[2]; nz <= E.kmax[2]; ++nz)
+    for (int ny = -E.kmax[1]; ny <= E.kmax[1]; ++ny)
+      for (int nx = -E.kmax[0]; nx <= E.kmax[0]; ++nx) {
+        if (nx == 0 && ny == 0 && nz == 0) continue;
+        double kx = 2.0 * OR_PI * nx / len[0], ky = 2.0 * OR_PI * ny / len[1], kz = 2.0 * OR_PI * nz / len[2];
+        double k2 = kx * kx + ky * ky + kz * kz;
+        if (k2 > E.kc2) continue;
+        kv[4 * nk] = kx; kv[4 * nk + 1] = ky; kv[4 * nk + 2] = kz;
+        kv[4 * nk + 3] = exp(-k2 / (4.0 * beta * beta)) / k2;
+        ++nk;
+      }
+  double* sre = (double*)calloc((size_t)(nk > 0 ? nk : 1), sizeof(double));
+  double* sim = (double*)calloc((size_t)(nk > 0 ? nk : 1), sizeof(double));
+#pragma omp parallel for schedule(static)
+  for (int t = 0; t < nk; ++t) {
+    double a = 0.0, b = 0.0;
+    for (int j = 0; j < n; ++j) {
+      double ph = kv[4 * t] * r[0][j] + kv[4 * t + 1] * r[1][j] + kv[4 * t + 2] * r[2][j];
+      a += q[j] * cos(ph);
+      b += q[j] * sin(ph);
+    }
+    sre[t] = a; sim[t] = b;
+  }
+  double Q = 0.0;
+  for (int j = 0; j < n; ++j) Q += q[j];
+  double* ph_ = (double*)malloc(sizeof(double) * na);
+  double* f_ = (double*)malloc(sizeof(double) * 3 * na);
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : bad)
+  for (int i = 0; i < n; ++i) {
+    double p = 0.0, f[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < n; ++j) {
+      if (j == i) continue;
+      double dv[3], r2 = 0.0;
+      for (int d = 0; d < 3; ++d) {
+        dv[d] = r[d][i] - r[d][j];
+        dv[d] -= len[d] * nearbyint(dv[d] / len[d]);
+        r2 += dv[d] * dv[d];
+      }
+      if (r2 == 0.0) { bad = 1; continue; }
+      double rr = sqrt(r2);
+      if (rr >= E.rc) continue;
+      double ec = erfc(beta * rr);
+      p += q[j] * ec / rr;
+      double w = q[j] * (ec / rr + 2.0 * beta / sqrt(OR_PI) * exp(-beta * beta * r2)) / r2;
+      for (int d = 0; d < 3; ++d) f[d] += w * dv[d];
+    }
+    double pk = 0.0, g[3] = {0.0, 0.0, 0.0};
+    for (int t = 0; t < nk; ++t) {
+      double th = kv[4 * t] * r[0][i] + kv[4 * t + 1] * r[1][i] + kv[4 * t + 2] * r[2][i];
+      double c = cos(th), s = sin(th);
+      /* Re(exp(-i th) S) = c Sre + s Sim;  Im(exp(-i th) S) = c Sim - s Sre */
+      double re = c * sre[t] + s * sim[t], im = c * sim[t] - s * sre[t];
+      pk += kv[4 * t + 3] * re;
+      for (int d = 0; d < 3; ++d) g[d] += kv[4 * t + 3] * kv[4 * t + d] * im;
+    }
+    p += 4.0 * OR_PI / V * pk - 2.0 * beta / sqrt(OR_PI) * q[i] - OR_PI * Q / (V * beta * beta);
+    ph_[i] = ke * p;
+    for (int d = 0; d < 3; ++d) f_[3 * (size_t)i + d] = ke * q[i] * (f[d] - 4.0 * OR_PI / V * g[d]);
+  }
+  nsum_t e = {0.0, 0.0};
+  for (int i = 0; i < n; ++i) {
+    nsum_add(&e, 0.5 * q[i] * ph_[i]);
+    if (phi) phi[i] = ph_[i];
+    if (fx) fx[i] = f_[3 * (size_t)i];
+    if (fy) fy[i] = f_[3 * (size_t)i + 1];
+    if (fz) fz[i] = f_[3 * (size_t)i + 2];
+  }
+  if (energy) *energy = e.s + e.c;
+  for (int d = 0; d < 3; ++d) free(r[d]);
+  free(kv); free(sre); free(sim); free(ph_); free(f_);
+  return bad ? OR_ECOINCIDENT : OR_OK;
+}
