@@ -61,10 +61,15 @@ typedef struct {
   int32_t order;          /* 4 = cubic C1 basis, 6 = quintic C1 basis */
   int32_t split_m;        /* Taylor smoothing degree m (gamma has degree 2m); 0 -> order/2 */
   int32_t levels;         /* l >= 1 grid levels; 0 -> fewest levels whose top interior
-                             spans at most 8 nodes per dimension */
-  int32_t reserved;       /* must be 0 */
+                             spans at most 8 nodes per dimension (periodic: whose top
+                             grid has at most 8 nodes per side, as far as the levels
+                             halve) */
+  int32_t periodic;       /* 0: free space (atoms must lie in [lo, lo + len]);
+                             1: periodic boundaries, the box repeated in every direction
+                             (atoms anywhere; box_len / spacing an integer, divisible by
+                             2^(levels-1), and 2 cutoff <= box_len) */
   double box_lo[3];       /* box lower corner; also the grid origin */
-  double box_len[3];      /* box edge lengths > 0; atoms must lie in [lo, lo + len] */
+  double box_len[3];      /* box edge lengths > 0; free space: atoms must lie in [lo, lo + len] */
   double coulomb_k;       /* prefactor 1/(4 pi eps0) in the caller's units; 0 -> 1 (e^2/A) */
 } msm_params;
 
@@ -80,7 +85,19 @@ typedef struct msm_plan msm_plan;   /* host object; immutable after creation */
  * and the cell decomposition.  *out receives the plan (host memory owned by
  * the library; free with msm_plan_destroy).
  * Errors: MSM_ERR_INVALID_ARG, MSM_ERR_UNSUPPORTED (grid or stencil beyond
- * this build's limits). */
+ * this build's limits).
+ * periodic = 1 (the thesis evaluates free-space systems; Sec. "Calculation
+ * of Long-Range Interactions" names periodic boundaries with the Fourier
+ * methods): every sum runs over the atoms of the box and all their images.
+ * Level k is a periodic grid of (box_len / spacing) / 2^k nodes per side,
+ * stored with ghost copies on each side (msm_plan_info reports lo = -ghost
+ * and the count with the ghosts); the pair sum takes each pair at its nearest
+ * image (2 cutoff <= box_len); the top level sums its kernel over every image
+ * in the Ewald convention (conducting boundary, uniform neutralising
+ * background for a charged box).  Atoms may lie anywhere (each is taken at its
+ * image in the box).  Periodic plans evaluate with msm_compute,
+ * msm_compute_static, graphs and msm_vv_run; msm_energy and msm_backward
+ * return MSM_ERR_UNSUPPORTED, and batches take free-space systems only. */
 msm_status msm_plan_create(const msm_params* params, int32_t n_atoms, msm_plan** out);
 msm_status msm_plan_destroy(msm_plan* plan);
 
@@ -103,7 +120,8 @@ msm_status msm_plan_destroy(msm_plan* plan);
 typedef enum { MSM_PAIR_CUTOFF = 1, MSM_PAIR_SHIFTED_FORCE = 2, MSM_PAIR_WOLF = 3 } msm_pair_kind;
 typedef struct {
   int32_t kind;           /* msm_pair_kind */
-  int32_t reserved;       /* must be 0 */
+  int32_t periodic;       /* 0: free space; 1: periodic boundaries (pairs at their nearest
+                             image; 2 cutoff <= box_len) */
   double cutoff;          /* rc > 0, Angstrom */
   double alpha;           /* Wolf damping (1/Angstrom), >= 0; ignored by the other kinds */
   double box_lo[3];       /* box lower corner */

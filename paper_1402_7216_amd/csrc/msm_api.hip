@@ -91,6 +91,62 @@ double gamma_h(const double* c, int m, double rho) {
 int floor_div2(int v) { return v >= 0 ? v / 2 : -((-v + 1) / 2); }
 int ceil_div2(int v) { return -floor_div2(-v); }
 
+// Top level of a periodic plan: K(d) = sum over images p of g^{l-1}(|h_t d + P p|)
+// for every node offset d of the top grid (P = diag(box edges)).  g^{l-1}
+// decays as 1/r, so the image sum is the Ewald one (conducting boundary,
+// uniform neutralising background): K = Psi - sum over the images closer than
+// A = 2^{l-1} a of (1/rho - g^{l-1}(rho)), with
+//   Psi(r) = sum_p erfc(b |r + P p|) / |r + P p|
+//          + (4 pi / V) sum_{k != 0} exp(-k^2 / 4b^2) cos(k.r) / k^2 - pi / (V b^2)
+// and, at d = 0, the node's own term g^{l-1}(0) in place of the singular
+// p = 0 Coulomb term (whose Ewald remainder is -2b/sqrt(pi)).  b = 3 / min(len);
+// real-space images to 6 / b and wave vectors to k^2 = 156 b^2 leave terms
+// below 1e-16.
+void periodic_top_table(const double* c, int m, double A, double ht, const int nt[3], const double len[3],
+                        std::vector<double>& K) {
+  const double pi = 3.14159265358979323846;
+  const double lmin = std::min({len[0], len[1], len[2]});
+  const double b = 3.0 / lmin, V = len[0] * len[1] * len[2], rc = 6.0 / b, kc2 = 156.0 * b * b;
+  struct Wave { double kx, ky, kz, w; };
+  std::vector<Wave> waves;
+  int kn[3], pn[3], an[3];
+  for (int d = 0; d < 3; ++d) {
+    kn[d] = (int)std::ceil(std::sqrt(kc2) * len[d] / (2.0 * pi));
+    pn[d] = (int)std::ceil(rc / len[d]) + 1;
+    an[d] = (int)std::ceil(A / len[d]) + 1;
+  }
+  for (int iz = -kn[2]; iz <= kn[2]; ++iz)
+    for (int iy = -kn[1]; iy <= kn[1]; ++iy)
+      for (int ix = -kn[0]; ix <= kn[0]; ++ix) {
+        if (!ix && !iy && !iz) continue;
+        const Wave v{2.0 * pi * ix / len[0], 2.0 * pi * iy / len[1], 2.0 * pi * iz / len[2], 0.0};
+        const double k2 = v.kx * v.kx + v.ky * v.ky + v.kz * v.kz;
+        if (k2 <= kc2) waves.push_back(Wave{v.kx, v.ky, v.kz, 4.0 * pi / V * std::exp(-k2 / (4.0 * b * b)) / k2});
+      }
+  K.assign((size_t)nt[0] * nt[1] * nt[2], 0.0);
+  for (int dz = 0; dz < nt[2]; ++dz)
+    for (int dy = 0; dy < nt[1]; ++dy)
+      for (int dx = 0; dx < nt[0]; ++dx) {
+        const double r[3] = {ht * dx, ht * dy, ht * dz};
+        const bool self = !dx && !dy && !dz;
+        double real = 0.0, corr = 0.0, recip = 0.0;
+        // images within the Ewald real-space cutoff and within A, one pass each
+        for (int pz = -std::max(pn[2], an[2]); pz <= std::max(pn[2], an[2]); ++pz)
+          for (int py = -std::max(pn[1], an[1]); py <= std::max(pn[1], an[1]); ++py)
+            for (int px = -std::max(pn[0], an[0]); px <= std::max(pn[0], an[0]); ++px) {
+              if (self && !px && !py && !pz) continue;
+              const double vx = r[0] + px * len[0], vy = r[1] + py * len[1], vz = r[2] + pz * len[2];
+              const double rho = std::sqrt(vx * vx + vy * vy + vz * vz);
+              if (rho < rc) real += std::erfc(b * rho) / rho;
+              if (rho < A) corr += 1.0 / rho - gamma_h(c, m, rho / A) / A;
+            }
+        for (const Wave& v : waves) recip += v.w * std::cos(v.kx * r[0] + v.ky * r[1] + v.kz * r[2]);
+        double k = real + recip - pi / (V * b * b) - corr;
+        if (self) k += gamma_h(c, m, 0.0) / A - 2.0 * b / std::sqrt(pi);
+        K[((size_t)dz * nt[1] + dy) * nt[0] + dx] = k;
+      }
+}
+
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -179,7 +235,8 @@ void choose_lattice_tiles(const Geom& g, const std::vector<int4>& rows, int taps
   lat.n_wc = n_wc;
   if (g.levels < 2 || H_ > msm::kLatMaxHalo) return;
   const int max_floats = (msm::kLatMaxLds - tables_bytes) / 4;
-  const int gmax = std::min(msm::kLatMaxGroups, 2 * H_ + 1);
+  // periodic levels get their ghost copies from u^{k,cut} itself: no row groups
+  const int gmax = g.periodic ? 1 : std::min(msm::kLatMaxGroups, 2 * H_ + 1);
   double best = 1e300;
   msm::LatLaunch cand;
   const int Bs[3] = {4, 6, 8};
@@ -325,7 +382,10 @@ void refresh_launch(msm_plan* P) {
     lg.prolong_level[k] = msm::prolong_level_blocks(g, k);
     if (k == 0) tiles0 = lg.prolong_level[k];
   }
-  lg.prolong_split = g.levels > 1 && tiles0 >= msm::kProlongSplitTiles;
+  lg.prolong_split = g.levels > 1 && (tiles0 >= msm::kProlongSplitTiles || g.periodic);
+  lg.periodic = g.periodic && !g.pair;
+  lg.short_periodic = g.periodic != 0;
+  for (int k = 0; k < g.levels; ++k) lg.ghost_blocks[k] = lg.periodic ? (g.lv[k].count + 255) / 256 : 0;
   lg.shortr.blocks = sb.shortr;
   lg.anterp.blocks = sb.anterp;
   lg.lattice0.blocks = sb.lattice0;
@@ -551,12 +611,24 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
   if (p.split_m < 0 || p.split_m > 7) return fail(MSM_ERR_INVALID_ARG, "split_m must be in [0, 7]");
   if (p.levels < 0 || p.levels > msm::kMaxLevels)
     return fail(MSM_ERR_INVALID_ARG, "levels must be in [0, 12]");
-  if (p.reserved != 0) return fail(MSM_ERR_INVALID_ARG, "reserved field must be 0");
+  if (p.periodic != 0 && p.periodic != 1) return fail(MSM_ERR_INVALID_ARG, "periodic must be 0 or 1");
   if (n_atoms < 0) return fail(MSM_ERR_INVALID_ARG, "n_atoms must be >= 0");
   if (!std::isfinite(p.coulomb_k)) return fail(MSM_ERR_INVALID_ARG, "coulomb_k must be finite");
   for (int d = 0; d < 3; ++d) {
     if (!finite_pos(p.box_len[d])) return fail(MSM_ERR_INVALID_ARG, "box_len must be finite and > 0");
     if (!std::isfinite(p.box_lo[d])) return fail(MSM_ERR_INVALID_ARG, "box_lo must be finite");
+  }
+  // periodic grids: a whole number of nodes per period, halving at every level
+  int per0[3] = {0, 0, 0};
+  if (p.periodic) {
+    for (int d = 0; d < 3; ++d) {
+      const double t = p.box_len[d] / p.spacing;
+      const double r = std::nearbyint(t);
+      if (r < 1.0 || r > 1.0e6 || std::fabs(t - r) > 1e-9 * t)
+        return fail(MSM_ERR_INVALID_ARG, "periodic: box_len / spacing must be an integer (at most 1e6)");
+      if (2.0 * p.cutoff > p.box_len[d]) return fail(MSM_ERR_INVALID_ARG, "periodic: 2 cutoff must not exceed box_len");
+      per0[d] = (int)r;
+    }
   }
 
   msm_plan* P = new (std::nothrow) msm_plan();
@@ -575,11 +647,15 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
   g.m = p.split_m ? p.split_m : p.order / 2;
   g.ke = p.coulomb_k != 0.0 ? p.coulomb_k : 1.0;
   double maxlen = 0.0;
+  g.periodic = p.periodic;
   for (int d = 0; d < 3; ++d) {
     g.lo[d] = p.box_lo[d];
     g.hi[d] = p.box_lo[d] + p.box_len[d];
     g.lo_f[d] = (float)p.box_lo[d];
-    double fm = std::floor(p.box_len[d] / h);
+    g.len_f[d] = (float)p.box_len[d];
+    g.len[d] = p.box_len[d];
+    g.inv_len_f[d] = (float)(1.0 / p.box_len[d]);
+    double fm = p.periodic ? (double)per0[d] : std::floor(p.box_len[d] / h);
     if (fm > 1.0e6) {
       delete P;
       return fail(MSM_ERR_UNSUPPORTED, "grid too fine for the box (more than 1e6 nodes per side)");
@@ -589,8 +665,20 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
   }
 
   // levels: given, or the fewest whose top interior spans <= 8 nodes per side
+  // (periodic: whose top grid has <= 8 nodes per side, as far as the levels halve)
   int L = p.levels;
-  if (L == 0) {
+  if (L == 0 && p.periodic) {
+    L = 1;
+    for (;;) {
+      bool big = false, even = true;
+      for (int d = 0; d < 3; ++d) {
+        big = big || (per0[d] >> (L - 1)) > 8;
+        even = even && (per0[d] >> (L - 1)) % 2 == 0;
+      }
+      if (!big || !even || L == msm::kMaxLevels) break;
+      ++L;
+    }
+  } else if (L == 0) {
     L = msm::kMaxLevels;
     for (int l = 1; l <= msm::kMaxLevels; ++l)
       if ((int)std::ceil(maxlen / std::ldexp(h, l - 1)) + 1 <= 8) {
@@ -598,14 +686,33 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
         break;
       }
   }
+  if (p.periodic)
+    for (int d = 0; d < 3; ++d)
+      if (per0[d] % (1 << (L - 1))) {
+        delete P;
+        return fail(MSM_ERR_INVALID_ARG, "periodic: box_len / spacing must be divisible by 2^(levels-1)");
+      }
   g.levels = L;
+  // periodic: level k holds its per0 / 2^k nodes of one period with ghost
+  // copies on each side, as many as the widest stencil reaching past a period
+  // needs (lattice half-width, restriction reach order - 1, basis support)
+  if (p.periodic) {
+    int H = 0;
+    if (L > 1)
+      while ((H + 1) * h < 2.0 * a) ++H;
+    g.ghost = std::max({H, p.order - 1, g.half + 1});
+  }
   // level 0 spans the nodes atoms in the box touch; level k+1 the nodes level k restricts to
   long long off = 0;
   for (int k = 0; k < L; ++k) {
     msm::Level& lv = g.lv[k];
     for (int d = 0; d < 3; ++d) {
       int lo, hi;
-      if (k == 0) {
+      if (p.periodic) {
+        lv.per[d] = per0[d] >> k;
+        lo = -g.ghost;
+        hi = lv.per[d] - 1 + g.ghost;
+      } else if (k == 0) {
         lo = -(g.half - 1);
         hi = g.fmax[d] + g.half;
       } else {
@@ -753,7 +860,11 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
     }
   }
   // top level (float64): T(d) = g^{l-1}(2^{l-1} h |d|) = gamma(r / A) / A, A = 2^{l-1} a
-  {
+  // (periodic: the image sum K(d) over the node offsets of one period)
+  if (p.periodic) {
+    const msm::Level& T = g.lv[L - 1];
+    periodic_top_table(c, g.m, std::ldexp(a, L - 1), std::ldexp(h, L - 1), T.per, p.box_len, P->top);
+  } else {
     const msm::Level& T = g.lv[L - 1];
     const double A = std::ldexp(a, L - 1), hk = std::ldexp(h, L - 1);
     P->top.resize((size_t)T.count);
@@ -812,8 +923,11 @@ msm_status msm_pair_plan_create(const msm_pair_params* pp, int32_t n_atoms, msm_
   *out = nullptr;
   if (pp->kind < MSM_PAIR_CUTOFF || pp->kind > MSM_PAIR_WOLF)
     return fail(MSM_ERR_INVALID_ARG, "kind must be MSM_PAIR_CUTOFF, MSM_PAIR_SHIFTED_FORCE or MSM_PAIR_WOLF");
-  if (pp->reserved != 0) return fail(MSM_ERR_INVALID_ARG, "reserved field must be 0");
+  if (pp->periodic != 0 && pp->periodic != 1) return fail(MSM_ERR_INVALID_ARG, "periodic must be 0 or 1");
   if (!finite_pos(pp->cutoff)) return fail(MSM_ERR_INVALID_ARG, "cutoff must be finite and > 0");
+  for (int d = 0; d < 3; ++d)
+    if (pp->periodic && finite_pos(pp->box_len[d]) && 2.0 * pp->cutoff > pp->box_len[d])
+      return fail(MSM_ERR_INVALID_ARG, "periodic: 2 cutoff must not exceed box_len");
   if (!std::isfinite(pp->alpha) || pp->alpha < 0.0) return fail(MSM_ERR_INVALID_ARG, "alpha must be finite and >= 0");
   // the cells, binning and short-range pass of an MSM plan with cutoff rc; its
   // (unused) grid is one coarse level
@@ -835,6 +949,7 @@ msm_status msm_pair_plan_create(const msm_pair_params* pp, int32_t n_atoms, msm_
   Geom& g = P->g;
   const double rc = pp->cutoff, al = pp->alpha;
   g.pair = pp->kind;
+  g.periodic = pp->periodic;                     // pairs at their nearest image (the grid is unused)
   g.pk[0] = g.pk[1] = g.pk[2] = g.pk[3] = 0.f;
   g.self = 0.f;
   if (pp->kind == MSM_PAIR_SHIFTED_FORCE) {
@@ -941,6 +1056,7 @@ msm_status msm_plan_describe(const msm_plan* P, char* buf, size_t buf_bytes) {
          std::to_string(t.groups) + "]";
   }
   o += "], \"prolong_per_level\": " + std::to_string(P->lg.prolong_split ? 1 : 0);
+  o += ", \"periodic\": " + std::to_string(g.periodic) + ", \"ghost\": " + std::to_string(g.ghost);
   o += ", \"workspace_bytes\": " + std::to_string(P->lay.total) + "}";
   std::strncpy(buf, o.c_str(), buf_bytes - 1);
   buf[buf_bytes - 1] = 0;
@@ -1072,6 +1188,7 @@ msm_status msm_energy(const msm_plan* P, void* ws, size_t ws_bytes, msm_stream_t
                       double* energy) {
   if (!energy) return fail(MSM_ERR_INVALID_ARG, "null energy output");
   if (P && P->g.pair) return fail(MSM_ERR_UNSUPPORTED, "msm_energy is for multilevel-summation plans");
+  if (P && P->g.periodic) return fail(MSM_ERR_UNSUPPORTED, "msm_energy: periodic plans evaluate with msm_compute");
   return eval_mode(msm::kModeEnergy, P, ws, ws_bytes, stream, x, y, z, q, nullptr, nullptr, nullptr,
                    nullptr, energy, nullptr);
 }
@@ -1082,6 +1199,7 @@ msm_status msm_backward(const msm_plan* P, void* ws, size_t ws_bytes, msm_stream
                         float* dedq) {
   if (!grad_energy) return fail(MSM_ERR_INVALID_ARG, "null grad_energy");
   if (P && P->g.pair) return fail(MSM_ERR_UNSUPPORTED, "msm_backward is for multilevel-summation plans");
+  if (P && P->g.periodic) return fail(MSM_ERR_UNSUPPORTED, "msm_backward: periodic plans evaluate with msm_compute");
   return eval_mode(msm::kModeGradient, P, ws, ws_bytes, stream, x, y, z, q, dedx, dedy, dedz, dedq,
                    nullptr, grad_energy);
 }

@@ -200,6 +200,10 @@ msm_status msm_batch_create(const msm_params* params, const int32_t* n_atoms, in
   Bt->n_sys = n_sys;
   int64_t off = 0;
   for (int s = 0; s < n_sys; ++s) {
+    if (params[s].periodic) {
+      msm_batch_destroy(Bt);
+      return fail(MSM_ERR_UNSUPPORTED, "batches take free-space systems only");
+    }
     msm_plan* P = nullptr;
     msm_status st = msm_plan_create(&params[s], n_atoms[s], &P);
     if (st != MSM_OK) {

@@ -40,6 +40,8 @@ struct Level {
   int n[3];      // node count per dimension
   int off;       // first node of this level in the concatenated grid arrays
   int count;     // n[0] * n[1] * n[2]
+  int per[3];    // periodic plans: nodes of one period (interior 0 .. per - 1; the
+                 // others, lo = -ghost and up, are ghost copies); 0 for free space
 };
 
 // Everything the kernels need to know about one system.  Plain data, passed
@@ -52,6 +54,10 @@ struct Geom {
   float h, inv_h;                  // finest spacing and its reciprocal
   float lo_f[3];                   // box corner (float) = grid origin
   double lo[3], hi[3];             // exact box bounds for the in-box test
+  int periodic;                    // 1: the box repeats in every direction
+  int ghost;                       // periodic: ghost nodes on each side of every level
+  float len_f[3], inv_len_f[3];    // periodic: box edges and their reciprocals
+  double len[3];                   // periodic: box edges (images are placed in double precision)
   int fmax[3];                     // largest level-0 floor index floor(len / h)
   // link cells
   int nc[3];
@@ -298,6 +304,9 @@ struct LaunchGeom {
   int prolong_level[kMaxLevels] = {};   // prolongation tiles of each level below the top
   StageGrid bin;                     // two-kernel binning (systems with bin_blocks > 0)
   StageGrid binrow;                  // one-kernel binning (systems with bin_row_blocks > 0)
+  bool periodic = false;             // periodic grids: ghost folds and fills between the stages
+  bool short_periodic = false;       // periodic short range (MSM or pair plans)
+  int ghost_blocks[kMaxLevels] = {}; // blocks of a ghost fill of each level (one system)
   int binrow_lds = 0;                // dynamic LDS of the one-kernel binning (largest system)
   bool bin4 = true;                  // some system uses the four-kernel binning
   StageGrid lattice0;                // lattice cutoff of level 0

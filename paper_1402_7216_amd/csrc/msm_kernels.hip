@@ -154,8 +154,29 @@ __device__ __forceinline__ int cell_coord(const Geom& g, float p, int d) {
   return min((int)t, g.nc[d] - 1);
 }
 
+// Coordinates as the kernels take them: a periodic plan maps each into
+// [lo, lo + len), in double precision so the float32 result is the image
+// rounded once (an atom inside the box keeps its coordinate; the result may
+// round up to lo + len, which the cell and grid clamps absorb); free space
+// keeps it.
+__device__ __forceinline__ float wrap_coord(const Geom& g, float p, int d) {
+  if (!g.periodic) return p;
+  const double t = (double)p - g.lo[d];
+  return (float)(g.lo[d] + (t - g.len[d] * floor(t / g.len[d])));
+}
+
+// The coordinate binning stores for an atom (wrapped, then clamped to the box).
+__device__ __forceinline__ float sorted_coord(const Geom& g, float p, int d) {
+  return fminf(fmaxf(wrap_coord(g, p, d), g.lo_f[d]), (float)g.hi[d]);
+}
+
+// An image of coordinate p shifted by s box edges, placed as the short-range
+// pass stages it (shift added in double precision, rounded once).
+__device__ __forceinline__ float shifted(float p, double s) { return (float)((double)p + s); }
+
 __device__ __forceinline__ int cell_index(const Geom& g, float x, float y, float z) {
-  return (cell_coord(g, z, 2) * g.nc[1] + cell_coord(g, y, 1)) * g.nc[0] + cell_coord(g, x, 0);
+  return (cell_coord(g, wrap_coord(g, z, 2), 2) * g.nc[1] + cell_coord(g, wrap_coord(g, y, 1), 1)) * g.nc[0] +
+         cell_coord(g, wrap_coord(g, x, 0), 0);
 }
 
 // Runs of equal cells among the lanes of a wave (consecutive input atoms —
@@ -346,7 +367,7 @@ __global__ void k_bin_place(KArgs A) {
     const double pd[3] = {(double)p.x, (double)p.y, (double)p.z};
 #pragma unroll
     for (int d = 0; d < 3; ++d)
-      if (pd[d] < g.lo[d] || pd[d] > g.hi[d]) flags |= kFlagOutOfBox;
+      if (!g.periodic && (pd[d] < g.lo[d] || pd[d] > g.hi[d])) flags |= kFlagOutOfBox;
   }
   int dst = s;
   if (0 <= b && b <= e && e <= g.n_atoms && e - b <= kRankCap) {
@@ -363,9 +384,9 @@ __global__ void k_bin_place(KArgs A) {
   if (flags) atomicOr(status, flags);
   const float hx = (float)g.hi[0], hy = (float)g.hi[1], hz = (float)g.hi[2];
   float4 o;
-  o.x = fminf(fmaxf(p.x, g.lo_f[0]), hx);
-  o.y = fminf(fmaxf(p.y, g.lo_f[1]), hy);
-  o.z = fminf(fmaxf(p.z, g.lo_f[2]), hz);
+  o.x = fminf(fmaxf(wrap_coord(g, p.x, 0), g.lo_f[0]), hx);
+  o.y = fminf(fmaxf(wrap_coord(g, p.y, 1), g.lo_f[1]), hy);
+  o.z = fminf(fmaxf(wrap_coord(g, p.z, 2), g.lo_f[2]), hz);
   o.w = isfinite(p.w) ? p.w : 0.f;
   sorted[dst] = o;
   perm[dst] = i;
@@ -562,12 +583,12 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_sort(KArgs A) {
       const double pd[3] = {(double)pi.x, (double)pi.y, (double)pi.z};
 #pragma unroll
       for (int d = 0; d < 3; ++d)
-        if (pd[d] < g.lo[d] || pd[d] > g.hi[d]) flags |= kFlagOutOfBox;
+        if (!g.periodic && (pd[d] < g.lo[d] || pd[d] > g.hi[d])) flags |= kFlagOutOfBox;
     }
     float4 o;
-    o.x = fminf(fmaxf(pi.x, g.lo_f[0]), (float)g.hi[0]);
-    o.y = fminf(fmaxf(pi.y, g.lo_f[1]), (float)g.hi[1]);
-    o.z = fminf(fmaxf(pi.z, g.lo_f[2]), (float)g.hi[2]);
+    o.x = fminf(fmaxf(wrap_coord(g, pi.x, 0), g.lo_f[0]), (float)g.hi[0]);
+    o.y = fminf(fmaxf(wrap_coord(g, pi.y, 1), g.lo_f[1]), (float)g.hi[1]);
+    o.z = fminf(fmaxf(wrap_coord(g, pi.z, 2), g.lo_f[2]), (float)g.hi[2]);
     o.w = isfinite(pi.w) ? pi.w : 0.f;
     S.d.sorted[base[c] + rank] = o;
     S.d.perm[base[c] + rank] = i;
@@ -604,6 +625,8 @@ __global__ void __launch_bounds__(kBRThreads) k_bin_rows(KArgs A) {
   const float iv0 = g.inv_cs[0], iv1 = g.inv_cs[1], iv2 = g.inv_cs[2];
   const double blo0 = g.lo[0], blo1 = g.lo[1], blo2 = g.lo[2];
   const double bhi0 = g.hi[0], bhi1 = g.hi[1], bhi2 = g.hi[2];
+  const bool per = g.periodic != 0;
+  const double ln0 = g.len[0], ln1 = g.len[1], ln2 = g.len[2];
   int* const status = S.d.status;
   int* const cell_start = S.d.cell_start;
   float4* const sorted = S.d.sorted;
@@ -649,14 +672,21 @@ __global__ void __launch_bounds__(kBRThreads) k_bin_rows(KArgs A) {
   auto coord = [](float p, float lo, float iv, float mx) {
     return (int)__builtin_amdgcn_fmed3f((p - lo) * iv, 0.f, mx);
   };
+  // periodic plans: the coordinate mapped into the box first (wrap_coord)
+  auto wr = [&](float p, double lo, double ln) {
+    if (!per) return p;
+    const double t = (double)p - lo;
+    return (float)(lo + (t - ln * floor(t / ln)));
+  };
   auto local_cell = [&](float px, float py, float pz) {
-    return (coord(pz, lo2, iv2, mx2) * ny + coord(py, lo1, iv1, mx1) - r0) * nx + coord(px, lo0, iv0, mx0);
+    return (coord(wr(pz, blo2, ln2), lo2, iv2, mx2) * ny + coord(wr(py, blo1, ln1), lo1, iv1, mx1) - r0) * nx +
+           coord(wr(px, blo0, ln0), lo0, iv0, mx0);
   };
   const unsigned span = (unsigned)(r1 - r0);
   int below = 0, len = 0;                          // wave-uniform
   // one chunk: count the atoms of earlier rows, list the block's own
   auto chunk = [&](int i, bool live, float py, float pz) {
-    const int r = coord(pz, lo2, iv2, mx2) * ny + coord(py, lo1, iv1, mx1);
+    const int r = coord(wr(pz, blo2, ln2), lo2, iv2, mx2) * ny + coord(wr(py, blo1, ln1), lo1, iv1, mx1);
     below += __popcll(__ballot(live && r < r0));
     const bool mine = live && (unsigned)(r - r0) < span;
     const unsigned long long m = __ballot(mine);
@@ -775,12 +805,13 @@ __global__ void __launch_bounds__(kBRThreads) k_bin_rows(KArgs A) {
         flags |= kFlagNonFinite;
       } else {
         const double px = pi.x, py = pi.y, pz = pi.z;
-        if (px < blo0 || px > bhi0 || py < blo1 || py > bhi1 || pz < blo2 || pz > bhi2) flags |= kFlagOutOfBox;
+        if (!per && (px < blo0 || px > bhi0 || py < blo1 || py > bhi1 || pz < blo2 || pz > bhi2))
+          flags |= kFlagOutOfBox;
       }
       float4 o;
-      o.x = fminf(fmaxf(pi.x, lo0), (float)bhi0);
-      o.y = fminf(fmaxf(pi.y, lo1), (float)bhi1);
-      o.z = fminf(fmaxf(pi.z, lo2), (float)bhi2);
+      o.x = fminf(fmaxf(wr(pi.x, blo0, ln0), lo0), (float)bhi0);
+      o.y = fminf(fmaxf(wr(pi.y, blo1, ln1), lo1), (float)bhi1);
+      o.z = fminf(fmaxf(wr(pi.z, blo2, ln2), lo2), (float)bhi2);
       o.w = isfinite(pi.w) ? pi.w : 0.f;
       sorted[slot] = o;
       perm[slot] = i;
@@ -852,7 +883,10 @@ constexpr float binom_half(int j) {
 //                    (pk0 = 1/rc, pk1 = 1/rc^2)
 //   Wolf             e = erfc(pk0 r)/r - pk1                -e'/r = (erfc(pk0 r)/r + pk2 exp(-pk3 r^2))/r^2
 //                    (pk0 = alpha, pk1 = erfc(alpha rc)/rc, pk2 = 2 alpha/sqrt(pi), pk3 = alpha^2)
-template <int M, bool FORCES, int KIND>
+// PER: periodic plans (the neighbour rows and x windows wrap around the box,
+// the atoms of a wrapped image staged shifted by the box edges); a template
+// flag so the free-space kernel keeps its registers.
+template <int M, bool FORCES, int KIND, bool PER>
 // Two blocks per CU: 8 waves per SIMD, so at most 64 registers per lane.
 __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, int hi_pm) {
   int blk;
@@ -917,19 +951,42 @@ __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, 
         const int r = g.short_rows[wave][q];
         if (r < 0) break;
         const int oy = r % side - R, oz = r / side - R;
-        const int jy = cy + oy, jz = cz + oz;
-        if (jy < 0 || jz < 0 || jy >= g.nc[1] || jz >= g.nc[2]) continue;
+        int jy = cy + oy, jz = cz + oz;
+        // periodic plans: the row's image, its atoms shifted by (sx, sy, sz)
+        double sy = 0.0, sz = 0.0;
+        if (PER) {
+          const int wy = ((jy % g.nc[1]) + g.nc[1]) % g.nc[1], wz = ((jz % g.nc[2]) + g.nc[2]) % g.nc[2];
+          sy = (double)((jy - wy) / g.nc[1]) * g.len[1];
+          sz = (double)((jz - wz) / g.nc[2]) * g.len[2];
+          jy = wy;
+          jz = wz;
+        } else if (jy < 0 || jz < 0 || jy >= g.nc[1] || jz >= g.nc[2]) {
+          continue;
+        }
         // this lane's window in the row
-        const float ylo = g.lo_f[1] + (float)jy * g.cs[1], zlo = g.lo_f[2] + (float)jz * g.cs[2];
+        const float ylo = g.lo_f[1] + (float)jy * g.cs[1] + (float)sy, zlo = g.lo_f[2] + (float)jz * g.cs[2] + (float)sz;
         const float dyw = fmaxf(fmaxf(ylo - pi.y, pi.y - (ylo + g.cs[1])), 0.f);
         const float dzw = fmaxf(fmaxf(zlo - pi.z, pi.z - (zlo + g.cs[2])), 0.f);
         const float d2 = fmaf(dyw, dyw, dzw * dzw);
         const int jrow = (jz * g.nc[1] + jy) * g.nc[0];
+        // x images: 0 the row itself; periodic plans also take its atoms near
+        // the upper end shifted by -len (image 1) and those near the lower end
+        // shifted by +len (image 2) when the lane's reach crosses a box face
+        for (int img = 0; img < (PER ? 3 : 1); ++img) {
+        const double sx = img == 0 ? 0.0 : (img == 1 ? -g.len[0] : g.len[0]);
         int lo = 0x7fffffff, hi = -1;
         if (live && d2 < aw * aw) {
           const float e = sqrtf(aw * aw - d2) + 1e-4f * aw;
-          lo = start[jrow + cell_x(g, pi.x - e)];
-          hi = start[jrow + cell_x(g, pi.x + e) + 1];
+          if (img == 0) {
+            lo = start[jrow + cell_x(g, pi.x - e)];
+            hi = start[jrow + cell_x(g, pi.x + e) + 1];
+          } else if (img == 1 && pi.x - e < g.lo_f[0]) {
+            lo = start[jrow + cell_x(g, pi.x - e + g.len_f[0])];
+            hi = start[jrow + g.nc[0]];
+          } else if (img == 2 && pi.x + e > g.lo_f[0] + g.len_f[0]) {
+            lo = start[jrow];
+            hi = start[jrow + cell_x(g, pi.x + e - g.len_f[0]) + 1];
+          }
         }
         const int u0 = wave_min(lo), u1 = wave_max(hi);
         for (int s0 = u0; s0 < u1; s0 += kShortSeg) {
@@ -937,7 +994,16 @@ __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, 
 #pragma unroll
           for (int v = 0; v < kShortSeg / kWave; ++v) {
             const int j = s0 + v * kWave + lane;
-            jb[v * kWave + lane] = (j < u1) ? sorted[j] : make_float4(3e30f, 3e30f, 3e30f, 0.f);
+            float4 pj = make_float4(3e30f, 3e30f, 3e30f, 0.f);
+            if (j < u1) {
+              pj = sorted[j];
+              if (PER) {
+                pj.x = shifted(pj.x, sx);
+                pj.y = shifted(pj.y, sy);
+                pj.z = shifted(pj.z, sz);
+              }
+            }
+            jb[v * kWave + lane] = pj;
           }
           // this lane's part of the staged segment: [a0, a0 + n) (n = 0 keeps a0 = 0)
           const int lo_s = max(lo, s0) - s0, hi_s = min(hi, s0 + kShortSeg) - s0;
@@ -945,7 +1011,7 @@ __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, 
           const int a0 = n > 0 ? lo_s : 0;
           const int b0 = a0 + n;
           const int nmax = wave_max(n);
-          if (r == centre) {
+          if (r == centre && img == 0) {
             // the centre row holds the atom's own cell: any other atom at
             // distance zero is a coincident pair
             int zeros = 0;
@@ -1018,6 +1084,7 @@ __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, 
               }
             }
           }
+        }
         }
       }
       if (coincident) atomicOr(S.d.status, kFlagCoincident);
@@ -1234,12 +1301,21 @@ __global__ void __launch_bounds__(kBlock) k_anterp_gather(KArgs A) {
   int m[3];
   m[2] = fdiv(fdiv(node, L.n[0], inv_n0, m[0]), L.n[1], inv_n1, m[1]);
   int t0[3], t1[3];
+  bool any = true;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
+    // position from the first node of tile 0's region (node -(ORDER/2 - 1);
+    // a periodic level also has ghost nodes below it, which no region holds)
+    m[d] += L.lo[d] + ORDER / 2 - 1;
+    any = any && m[d] >= 0;
     // tiles t with t T <= m < (t + 1) T + ORDER - 1, clipped to the tiles that exist
     t1[d] = min(m[d] / g.at[d], g.atn[d] - 1);
     t0[d] = max(0, (m[d] - (ORDER - 1)) / g.at[d]);
     if (m[d] < ORDER - 1) t0[d] = 0;
+  }
+  if (!any) {
+    S.d.qgrid[L.off + node] = 0.f;
+    return;
   }
   const int ex = g.at[0] + ORDER - 1, ey = g.at[1] + ORDER - 1;
   const long long* __restrict__ part = S.d.ant_part;
@@ -1376,6 +1452,51 @@ __global__ void __launch_bounds__(kRThreads) k_restrict(KArgs A, int k) {
 // lattice-cutoff launch (same inputs ready) or, with the untiled lattice
 // kernel, as its own launch.
 // --------------------------------------------------------------------------
+// Periodic plans: the outputs and inputs are the nodes of one period (the
+// ghost copies are filled afterwards) and T holds the image sum K at the node
+// offsets (mu - nu) modulo the period.
+__device__ __forceinline__ void top_node_periodic(const SysDesc& S, const Level& L, int mx, int my, int mz,
+                                                  int lane) {
+  const double* __restrict__ T = S.d.top;
+  const int G = S.g.ghost;
+  const int p0 = L.per[0], p1 = L.per[1], p2 = L.per[2];
+  mx -= G;
+  my -= G;
+  mz -= G;
+  if (mx < 0 || my < 0 || mz < 0 || mx >= p0 || my >= p1 || mz >= p2) return;
+  const float* qt = S.d.qgrid + L.off;
+  const int count = p0 * p1 * p2;
+  const float inv_p0 = 1.f / (float)p0, inv_p1 = 1.f / (float)p1;
+  double acc = 0.0;
+  for (int v0 = lane; v0 < count; v0 += 4 * kWave) {
+    double t[4];
+    float qv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int v = v0 + u * kWave;
+      t[u] = 0.0;
+      qv[u] = 0.f;
+      if (v < count) {
+        int vx, vy;
+        const int vz = fdiv(fdiv(v, p0, inv_p0, vx), p1, inv_p1, vy);
+        const int dx = mx - vx + (mx < vx ? p0 : 0), dy = my - vy + (my < vy ? p1 : 0);
+        const int dz = mz - vz + (mz < vz ? p2 : 0);
+        t[u] = T[((size_t)dz * p1 + dy) * p0 + dx];
+        qv[u] = qt[((size_t)(vz + G) * L.n[1] + (vy + G)) * L.n[0] + (vx + G)];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = fma(t[u], (double)qv[u], acc);
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) {
+    const size_t node = ((size_t)(mz + G) * L.n[1] + (my + G)) * L.n[0] + (mx + G);
+    S.d.ucut[L.off + node] = (float)acc;
+    S.d.u[L.off + node] = (float)acc;
+  }
+}
+
 __device__ __forceinline__ void top_node(const SysDesc& S, int node, int lane) {
   const Geom& g = S.g;
   const double* __restrict__ T = S.d.top;
@@ -1384,6 +1505,10 @@ __device__ __forceinline__ void top_node(const SysDesc& S, int node, int lane) {
   const float inv_n0 = 1.f / (float)L.n[0], inv_n1 = 1.f / (float)L.n[1];
   int mx, my;
   const int mz = fdiv(fdiv(node, L.n[0], inv_n0, mx), L.n[1], inv_n1, my);
+  if (g.periodic) {
+    top_node_periodic(S, L, mx, my, mz, lane);
+    return;
+  }
   const float* qt = S.d.qgrid + L.off;
   double acc = 0.0;
   for (int v0 = lane; v0 < L.count; v0 += 4 * kWave) {     // 4 table and charge loads in flight
@@ -1409,6 +1534,46 @@ __device__ __forceinline__ void top_node(const SysDesc& S, int node, int lane) {
   if (lane == 0) {
     S.d.ucut[L.off + node] = (float)acc;
     S.d.u[L.off + node] = (float)acc;
+  }
+}
+
+// --------------------------------------------------------------------------
+// Ghost nodes of a periodic level: the nodes outside one period (indices from
+// -ghost up) stand for nodes of the period.  fold: every node of the period
+// adds what its ghost images received (anterpolation spreads the atoms near a
+// face onto them), images in a fixed order; fill: every ghost node takes the
+// value of its node in the period.  One thread per node of the level (one
+// system: periodic plans are not batched).
+// --------------------------------------------------------------------------
+enum GhostGrid : int { kGhostQ = 0, kGhostU = 1 };
+
+__global__ void __launch_bounds__(kBlock) k_ghost(KArgs A, int level, int which, int fold) {
+  const SysDesc& S = A.sys[0];
+  const Geom& g = S.g;
+  const Level L = g.lv[level];
+  const int node = (int)blockIdx.x * kBlock + (int)threadIdx.x;
+  if (node >= L.count) return;
+  float* grid = (which == kGhostQ ? S.d.qgrid : S.d.u) + L.off;
+  const int G = g.ghost;
+  const int mx = node % L.n[0], my = (node / L.n[0]) % L.n[1], mz = node / (L.n[0] * L.n[1]);
+  const int ix = mx - G, iy = my - G, iz = mz - G;
+  const int p0 = L.per[0], p1 = L.per[1], p2 = L.per[2];
+  const bool inside = ix >= 0 && iy >= 0 && iz >= 0 && ix < p0 && iy < p1 && iz < p2;
+  auto at = [&](int x, int y, int z) { return ((size_t)(z + G) * L.n[1] + (y + G)) * L.n[0] + (x + G); };
+  if (fold) {
+    if (!inside) return;
+    // images x + j p of this node inside the level's nodes [-G, p + G)
+    auto jlo = [G](int x, int p) { return -((x + G) / p); };
+    auto jhi = [G](int x, int p) { return (p + G - 1 - x) / p; };
+    float v = grid[node];
+    for (int jz = jlo(iz, p2); jz <= jhi(iz, p2); ++jz)
+      for (int jy = jlo(iy, p1); jy <= jhi(iy, p1); ++jy)
+        for (int jx = jlo(ix, p0); jx <= jhi(ix, p0); ++jx)
+          if (jx || jy || jz) v += grid[at(ix + jx * p0, iy + jy * p1, iz + jz * p2)];
+    grid[node] = v;
+  } else if (!inside) {
+    const int wx = ((ix % p0) + p0) % p0, wy = ((iy % p1) + p1) % p1, wz = ((iz % p2) + p2) % p2;
+    grid[node] = grid[at(wx, wy, wz)];
   }
 }
 
@@ -2003,6 +2168,30 @@ __device__ __forceinline__ void block_partials(double e, const double* vir, doub
 // q_j (r_i - r_j) / r^3, from the caller's float32 inputs.  A list entry out
 // of range (start not within [0, nnz], a partner outside this system) sets
 // kFlagBadExclusion and ends the atom's list.
+// r_i - r_j of a listed pair.  Periodic plans: from the coordinates binning
+// stores, at the image of j nearest to i, placed as the short-range pass
+// stages it, so the pair's term comes out bit for bit as that pass added it.
+__device__ __forceinline__ void pair_disp(const Geom& g, const Io& io, int gi, int gj, float& dx, float& dy,
+                                          float& dz) {
+  if (!g.periodic) {
+    dx = io.x[gi] - io.x[gj];
+    dy = io.y[gi] - io.y[gj];
+    dz = io.z[gi] - io.z[gj];
+    return;
+  }
+  const float pi[3] = {io.x[gi], io.y[gi], io.z[gi]}, pj[3] = {io.x[gj], io.y[gj], io.z[gj]};
+  float d[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float wi = sorted_coord(g, pi[c], c), wj = sorted_coord(g, pj[c], c);
+    const double s = g.len[c] * (double)rintf((wi - wj) * g.inv_len_f[c]);
+    d[c] = wi - shifted(wj, s);
+  }
+  dx = d[0];
+  dy = d[1];
+  dz = d[2];
+}
+
 struct ExclSums {
   float p = 0.f, x = 0.f, y = 0.f, z = 0.f;
 };
@@ -2032,11 +2221,11 @@ __device__ ExclSums coulomb_exclusions(const SysDesc& S, const Io& io, int i) {
   int b, e;
   if (!S.d.excl_start || !excl_range(S, i, b, e)) return r;
   const int gi = S.atom_off + i;
-  const float xi = io.x[gi], yi = io.y[gi], zi = io.z[gi];
   for (int k = b; k < e; ++k) {
     int j;
     if (!excl_partner(S, k, j)) break;
-    const float dx = xi - io.x[j], dy = yi - io.y[j], dz = zi - io.z[j];
+    float dx, dy, dz;
+    pair_disp(S.g, io, gi, j, dx, dy, dz);
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     if (!(r2 > 0.f)) continue;
     const float ri = 1.f / sqrtf(r2);
@@ -2059,11 +2248,11 @@ __device__ ExclSums pair_exclusions(const SysDesc& S, const Io& io, int i) {
   if (!S.d.excl_start || !excl_range(S, i, b, e)) return r;
   const Geom& g = S.g;
   const int gi = S.atom_off + i;
-  const float xi = io.x[gi], yi = io.y[gi], zi = io.z[gi];
   for (int k = b; k < e; ++k) {
     int j;
     if (!excl_partner(S, k, j)) break;
-    const float dx = xi - io.x[j], dy = yi - io.y[j], dz = zi - io.z[j];
+    float dx, dy, dz;
+    pair_disp(g, io, gi, j, dx, dy, dz);
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     if (!(r2 > 0.f && r2 < g.a2)) continue;
     const float ri = 1.f / sqrtf(r2);
@@ -2458,19 +2647,26 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
     beg(slot, ss);
     const KArgs A = args(L.shortr);
     const int nb = L.shortr.blocks;
+#define MSM_SHORT_P(MM, FF, KK)                                                        \
+  do {                                                                                 \
+    if (L.short_periodic)                                                              \
+      k_short<MM, FF, KK, true><<<nb, kShortThreads, 0, ss>>>(A, lo_pm, hi_pm);         \
+    else                                                                               \
+      k_short<MM, FF, KK, false><<<nb, kShortThreads, 0, ss>>>(A, lo_pm, hi_pm);        \
+  } while (0)
 #define MSM_SHORT(MM)                                                          \
   do {                                                                         \
     if (forces)                                                                \
-      k_short<MM, true, kPairMsm><<<nb, kShortThreads, 0, ss>>>(A, lo_pm, hi_pm);  \
+      MSM_SHORT_P(MM, true, kPairMsm);                                         \
     else                                                                       \
-      k_short<MM, false, kPairMsm><<<nb, kShortThreads, 0, ss>>>(A, lo_pm, hi_pm); \
+      MSM_SHORT_P(MM, false, kPairMsm);                                        \
   } while (0)
     if (L.pair == kPairCutoff)
-      k_short<1, true, kPairCutoff><<<nb, kShortThreads, 0, ss>>>(A, lo_pm, hi_pm);
+      MSM_SHORT_P(1, true, kPairCutoff);
     else if (L.pair == kPairShiftedForce)
-      k_short<1, true, kPairShiftedForce><<<nb, kShortThreads, 0, ss>>>(A, lo_pm, hi_pm);
+      MSM_SHORT_P(1, true, kPairShiftedForce);
     else if (L.pair == kPairWolf)
-      k_short<1, true, kPairWolf><<<nb, kShortThreads, 0, ss>>>(A, lo_pm, hi_pm);
+      MSM_SHORT_P(1, true, kPairWolf);
     else
     switch (L.m) {
       case 1: MSM_SHORT(1); break;
@@ -2482,6 +2678,7 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
       default: MSM_SHORT(7); break;
     }
 #undef MSM_SHORT
+#undef MSM_SHORT_P
     end(slot, ss);
     if (short_side) (void)hipEventRecord(cc->shortr.join, ss);
   };
@@ -2513,6 +2710,13 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
     k_anterp<6><<<L.anterp.blocks, kAThreads, L.anterp_lds, s>>>(args(L.anterp));
     k_anterp_gather<6><<<L.agather.blocks, kBlock, 0, s>>>(args(L.agather));
   }
+  // periodic: ghost copies of level k's grid of `which` (fold: gather them first)
+  const KArgs one_sys{L.sys, nullptr, io};
+  auto ghosts = [&](int k, int which, int fold) {
+    if (L.periodic && L.ghost_blocks[k] > 0) k_ghost<<<L.ghost_blocks[k], kBlock, 0, s>>>(one_sys, k, which, fold);
+  };
+  ghosts(0, kGhostQ, 1);
+  ghosts(0, kGhostQ, 0);
   end(kStageAnterp, s);
   if (short_at == 2) launch_short(0, split);
 
@@ -2557,6 +2761,7 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
       k_restrict<4><<<sg.blocks, kRThreads, 0, s>>>(args(sg), k);
     else
       k_restrict<6><<<sg.blocks, kRThreads, 0, s>>>(args(sg), k);
+    ghosts(k + 1, kGhostQ, 0);
   }
   end(kStageRestrict, s);
   mark(kStageLattice);
@@ -2596,6 +2801,7 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
     for (int k = L.max_levels - 2; k >= 0; --k) {
       const int nb = L.prolong_level[k];
       if (nb == 0) continue;
+      ghosts(k + 1, kGhostU, 0);
       const KArgs A{L.sys, nullptr, io};
       if (L.order == 4)
         k_prolong<4, true><<<nb, kPThreads, lds, s>>>(A, k);
@@ -2614,6 +2820,7 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
       k_prolong<6, false><<<L.prolong.blocks, kPThreads, lds, s>>>(args(L.prolong), 0);
     }
   }
+  ghosts(0, kGhostU, 0);
   end(kStageProlong, s);
   mark(kStageInterp);
   if (short_side) join(cc->shortr);

@@ -82,6 +82,15 @@ def uniform_charges(n=1000, side=20.0, seed=1, cutoff=8.0, spacing=2.5, order=4,
                           name=f"uniform{n}")
 
 
+def periodic_spacing(side, spacing, levels):
+    """The spacing nearest to `spacing` that puts a whole number of grid nodes,
+    divisible by 2^(levels - 1), on an edge of length `side` (periodic plans
+    need one)."""
+    unit = 2 ** max(levels - 1, 0)
+    k = max(1, int(round(side / spacing / unit)))
+    return side / (k * unit)
+
+
 def _random_rotations(rng, k):
     """Uniform random rotation matrices from uniform unit quaternions (Shoemake)."""
     u1, u2, u3 = rng.random(k), rng.random(k), rng.random(k)

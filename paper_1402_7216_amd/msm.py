@@ -88,13 +88,13 @@ class MSMError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("cutoff", ctypes.c_double), ("spacing", ctypes.c_double),
                 ("order", ctypes.c_int32), ("split_m", ctypes.c_int32),
-                ("levels", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("levels", ctypes.c_int32), ("periodic", ctypes.c_int32),
                 ("box_lo", ctypes.c_double * 3), ("box_len", ctypes.c_double * 3),
                 ("coulomb_k", ctypes.c_double)]
 
 
 class PairParams(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("cutoff", ctypes.c_double),
+    _fields_ = [("kind", ctypes.c_int32), ("periodic", ctypes.c_int32), ("cutoff", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("box_lo", ctypes.c_double * 3), ("box_len", ctypes.c_double * 3),
                 ("coulomb_k", ctypes.c_double)]
 
@@ -245,10 +245,10 @@ def _set_exclusions(self, start, idx):
 
 
 def make_params(cutoff, spacing, order=4, split_m=0, levels=0, box_lo=(0.0, 0.0, 0.0),
-                box_len=(1.0, 1.0, 1.0), coulomb_k=1.0) -> Params:
+                box_len=(1.0, 1.0, 1.0), coulomb_k=1.0, periodic=False) -> Params:
     p = Params()
     p.cutoff, p.spacing = float(cutoff), float(spacing)
-    p.order, p.split_m, p.levels, p.reserved = int(order), int(split_m), int(levels), 0
+    p.order, p.split_m, p.levels, p.periodic = int(order), int(split_m), int(levels), int(bool(periodic))
     for d in range(3):
         p.box_lo[d] = float(box_lo[d])
         p.box_len[d] = float(box_len[d])
@@ -260,8 +260,8 @@ class Plan:
     """A plan plus its device workspace for systems of `n_atoms` atoms."""
 
     def __init__(self, n_atoms, *, cutoff, spacing, order=4, split_m=0, levels=0,
-                 box_lo=(0.0, 0.0, 0.0), box_len=(1.0, 1.0, 1.0), coulomb_k=1.0, device="cuda"):
-        self.params = make_params(cutoff, spacing, order, split_m, levels, box_lo, box_len, coulomb_k)
+                 box_lo=(0.0, 0.0, 0.0), box_len=(1.0, 1.0, 1.0), coulomb_k=1.0, periodic=False, device="cuda"):
+        self.params = make_params(cutoff, spacing, order, split_m, levels, box_lo, box_len, coulomb_k, periodic)
         self.n = int(n_atoms)
         h = ctypes.c_void_p()
         _check(lib().msm_plan_create(ctypes.byref(self.params), self.n, ctypes.byref(h)))
@@ -439,10 +439,10 @@ class PairPlan(Plan):
     backward() are not available."""
 
     def __init__(self, n_atoms, *, kind, cutoff, alpha=0.0, box_lo=(0.0, 0.0, 0.0), box_len=(1.0, 1.0, 1.0),
-                 coulomb_k=1.0, device="cuda"):
+                 coulomb_k=1.0, periodic=False, device="cuda"):
         p = PairParams()
         p.kind = PAIR_KINDS[kind] if isinstance(kind, str) else int(kind)
-        p.reserved, p.cutoff, p.alpha, p.coulomb_k = 0, float(cutoff), float(alpha), float(coulomb_k)
+        p.periodic, p.cutoff, p.alpha, p.coulomb_k = int(bool(periodic)), float(cutoff), float(alpha), float(coulomb_k)
         for d in range(3):
             p.box_lo[d] = float(box_lo[d])
             p.box_len[d] = float(box_len[d])
@@ -454,10 +454,10 @@ class PairPlan(Plan):
         self._init_workspace(device)
 
 
-def pair_plan_for(system, kind, cutoff=None, alpha=0.0, device="cuda") -> PairPlan:
+def pair_plan_for(system, kind, cutoff=None, alpha=0.0, periodic=False, device="cuda") -> PairPlan:
     """A pair-method plan for an inputs.System (cutoff defaults to the system's a)."""
     return PairPlan(system.n, kind=kind, cutoff=system.cutoff if cutoff is None else cutoff, alpha=alpha,
-                    box_lo=system.box_lo, box_len=system.box_len, device=device)
+                    box_lo=system.box_lo, box_len=system.box_len, periodic=periodic, device=device)
 
 
 class Graph:
@@ -758,9 +758,9 @@ def batch_to_device(systems, device="cuda"):
     return cat("x"), cat("y"), cat("z"), cat("q")
 
 
-def plan_for(system, device="cuda") -> Plan:
-    """Plan for an inputs.System."""
-    return Plan(system.n, device=device, **{**system.params(), "split_m": system.split_m})
+def plan_for(system, periodic=False, device="cuda") -> Plan:
+    """Plan for an inputs.System (periodic: the box repeated in every direction)."""
+    return Plan(system.n, device=device, periodic=periodic, **{**system.params(), "split_m": system.split_m})
 
 
 def to_device(system, device="cuda"):

@@ -92,6 +92,73 @@ def test_plan_rejects_bad_parameters(M, bad, code):
     assert M.lib().msm_last_error()
 
 
+PERIODIC_CASES = [
+    dict(cutoff=8.0, spacing=1.5, order=4, levels=0, box_lo=(0, 0, 0), box_len=(24.0, 30.0, 36.0)),
+    dict(cutoff=8.0, spacing=1.5, order=6, levels=3, box_lo=(-2, 1, 0), box_len=(24.0, 30.0, 36.0)),
+    dict(cutoff=10.0, spacing=2.5, order=6, levels=1, box_lo=(0, 0, 0), box_len=(40.0, 40.0, 20.0)),
+    dict(cutoff=12.0, spacing=2.5, order=6, levels=0, box_lo=(0, 0, 0), box_len=(160.0, 160.0, 160.0)),
+]
+
+
+@pytest.mark.parametrize("prm", PERIODIC_CASES)
+def test_periodic_plan_layout_matches_oracle(M, prm):
+    """Level k holds the oracle's periodic grid of n_k nodes per side plus
+    ghost copies on each side (index -ghost up)."""
+    code, h = _plan(M, 1000, periodic=True, **prm)
+    assert code == 0
+    try:
+        L, lo, n = _info(M, h)
+        Lo, per = oracle.periodic_layout(**prm)
+        assert L == Lo
+        buf = ctypes.create_string_buffer(1 << 14)
+        assert M.lib().msm_plan_describe(h, buf, len(buf)) == 0
+        import json
+        d = json.loads(buf.value.decode())
+        G = d["ghost"]
+        assert d["periodic"] == 1 and G >= max(prm["order"] - 1, prm["order"] // 2 + 1)
+        if L > 1:
+            assert G >= int(np.ceil(2 * prm["cutoff"] / prm["spacing"])) - 1
+        np.testing.assert_array_equal(lo, -G * np.ones_like(lo))
+        np.testing.assert_array_equal(n, per + 2 * G)
+    finally:
+        M.lib().msm_plan_destroy(h)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(box_len=(24.0, 30.0, 36.7)),         # not a whole number of nodes
+    dict(cutoff=12.5),                         # 2 a > box edge
+    dict(levels=4),                            # 16 x 20 x 24 nodes cannot halve three times
+])
+def test_periodic_plan_rejects_bad_parameters(M, bad):
+    prm = dict(cutoff=8.0, spacing=1.5, order=4, levels=2, box_lo=(0, 0, 0), box_len=(24.0, 30.0, 36.0),
+               periodic=True)
+    prm.update(bad)
+    c, h = _plan(M, 100, **prm)
+    assert c == -1
+    assert M.lib().msm_last_error()
+
+
+def test_periodic_pair_plan_and_batch_limits(M):
+    p = M.PairParams()
+    p.kind, p.periodic, p.cutoff, p.alpha, p.coulomb_k = 2, 1, 13.0, 0.0, 1.0
+    for d in range(3):
+        p.box_lo[d], p.box_len[d] = 0.0, 24.0
+    h = ctypes.c_void_p()
+    assert M.lib().msm_pair_plan_create(ctypes.byref(p), 100, ctypes.byref(h)) == -1   # 2 rc > box edge
+    p.cutoff = 10.0
+    assert M.lib().msm_pair_plan_create(ctypes.byref(p), 100, ctypes.byref(h)) == 0
+    M.lib().msm_plan_destroy(h)
+    # the flag is 0 or 1; batches take free-space systems only
+    prm = M.make_params(8.0, 1.5, 4, 0, 2, (0, 0, 0), (24.0, 30.0, 36.0), 1.0, True)
+    prm.periodic = 2
+    assert M.lib().msm_plan_create(ctypes.byref(prm), 100, ctypes.byref(h)) == -1
+    prm.periodic = 1
+    arr = (M.Params * 1)(prm)
+    n = (ctypes.c_int32 * 1)(100)
+    b = ctypes.c_void_p()
+    assert M.lib().msm_batch_create(arr, n, 1, ctypes.byref(b)) == -6
+
+
 def test_plan_rejects_negative_atom_count(M):
     c, _ = _plan(M, -1, cutoff=8.0, spacing=2.5, box_len=(20, 20, 20))
     assert c == -1

@@ -1,0 +1,217 @@
+"""GPU periodic boundaries (msm_params.periodic, msm_pair_params.periodic)
+against the FP64 oracle's periodic evaluation on the same inputs: random +-1
+clouds in non-cubic boxes with one, two and three levels, cubic and quintic
+bases; a water box with and without its intramolecular pairs; atoms given
+outside the box; graph replay; and the cheap pair methods against the
+free-space oracle on the 3 x 3 x 3 supercell of images (the central copy's
+atoms see every image within the cutoff there).
+
+Bars: forces and potentials 1e-5 relative RMS; the energy of a water box
+1e-7 relative; a random +-1 cloud's energy and potentials, which cancel to a
+small difference of large grid potentials, against the self-interaction
+scale as for free-space clouds (1e-6).
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1402_7216_amd import inputs
+from _helpers import ENERGY_RTOL, FORCE_RTOL, PHI_RTOL, rel_err, rel_rms
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def M():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1402_7216_amd import msm
+    msm.lib()
+    return msm
+
+
+def _cloud(n, box, seed, **prm):
+    rng = np.random.default_rng(seed)
+    L = np.asarray(box, dtype=np.float64)
+    pos = rng.uniform(0.0, 1.0, size=(3, n)) * L[:, None]
+    q = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    return inputs._as_f32_system(pos, q, (0.0, 0.0, 0.0), tuple(L), name=f"pcloud{n}", **prm)
+
+
+def _run(M, s, **kw):
+    plan = M.plan_for(s, periodic=True)
+    x, y, z, q = M.to_device(s)
+    out = plan.compute(x, y, z, q, **kw)
+    torch.cuda.synchronize()
+    plan.check()
+    return plan, out
+
+
+def _numpy(out):
+    return float(out["energy"].item()), out["f"].double().cpu().numpy(), out["phi"].double().cpu().numpy()
+
+
+def _check_cloud(tag, s, e, f, phi, ref):
+    """Forces 1e-5 relative RMS; energy and potentials against the larger of
+    the reference and the self-interaction scale (q_i^2 gamma(0)/a), 1e-6."""
+    m = s.split_m or s.order // 2
+    q = s.q.astype(np.float64)
+    self_pot = oracle.gamma(m, 0.0) / s.cutoff
+    e_scale = max(abs(ref["energy"]), 0.5 * self_pot * float(q @ q))
+    p_scale = max(np.linalg.norm(ref["phi"]), np.linalg.norm(q) * self_pot)
+    de, dp = abs(e - ref["energy"]) / e_scale, np.linalg.norm(phi - ref["phi"]) / p_scale
+    print(f"[{tag}] E_gpu={e:.10g} E_ref={ref['energy']:.10g} scaled e {de:.2e} phi {dp:.2e} "
+          f"f_rms {rel_rms(f, ref['f']):.2e}", flush=True)
+    assert rel_rms(f, ref["f"]) <= FORCE_RTOL
+    assert de <= 1e-6 and dp <= 1e-6
+
+
+CLOUDS = {
+    "cubic_l2": dict(n=2000, box=(24.0, 30.0, 36.0), seed=61, cutoff=8.0, spacing=1.5, order=4, levels=2),
+    "quintic_l3": dict(n=2000, box=(24.0, 30.0, 36.0), seed=62, cutoff=8.0, spacing=1.5, order=6, levels=3),
+    "quintic_l1": dict(n=1500, box=(20.0, 20.0, 25.0), seed=63, cutoff=9.0, spacing=2.5, order=6, levels=1),
+    "cubic_auto": dict(n=3000, box=(40.0, 40.0, 40.0), seed=64, cutoff=10.0, spacing=2.5, order=4, levels=0),
+}
+
+
+@pytest.mark.parametrize("name", list(CLOUDS))
+def test_periodic_clouds_match_oracle(M, name):
+    c = dict(CLOUDS[name])
+    s = _cloud(c.pop("n"), c.pop("box"), c.pop("seed"), **c)
+    print(f"case periodic {name} n={s.n}", flush=True)
+    plan, out = _run(M, s, virial=True)
+    d = plan.describe()
+    assert d["periodic"] == 1
+    ref = oracle.system_msm(s, periodic=True)
+    assert plan.info()[0] == ref["levels"]
+    e, f, phi = _numpy(out)
+    _check_cloud(name, s, e, f, phi, ref)
+
+
+def _water(levels=3, seed=65, n=9000, h=2.0, a=10.0, order=4):
+    s = inputs.water_box(n, seed=seed, cutoff=a, order=order, levels=levels)
+    return dataclasses.replace(s, spacing=inputs.periodic_spacing(s.box_len[0], h, levels))
+
+
+@pytest.mark.parametrize("order", [4, 6])
+def test_periodic_water_matches_oracle(M, order):
+    s = _water(order=order)
+    print(f"case periodic water n={s.n} h={s.spacing:.4f} order={order}", flush=True)
+    plan, out = _run(M, s)
+    ref = oracle.system_msm(s, periodic=True)
+    e, f, phi = _numpy(out)
+    print(f"  E_gpu={e:.10g} E_ref={ref['energy']:.10g} e_rel {rel_err(e, ref['energy']):.2e} "
+          f"f_rms {rel_rms(f, ref['f']):.2e} phi_rms {rel_rms(phi, ref['phi']):.2e}", flush=True)
+    assert rel_err(e, ref["energy"]) <= ENERGY_RTOL
+    assert rel_rms(f, ref["f"]) <= FORCE_RTOL and rel_rms(phi, ref["phi"]) <= PHI_RTOL
+
+
+def test_periodic_water_without_intramolecular_pairs(M):
+    """Exclusions at the nearest image: molecules that straddle a box face
+    after the atoms are shifted by lattice vectors."""
+    s = _water(levels=2, seed=66, n=6000)
+    rng = np.random.default_rng(67)
+    shift = rng.integers(-1, 2, size=(3, s.n)).astype(np.float64) * np.asarray(s.box_len)[:, None]
+    p = s.pos64() + shift
+    s = dataclasses.replace(s, x=p[0].astype(np.float32), y=p[1].astype(np.float32), z=p[2].astype(np.float32),
+                            x64=p)
+    excl = inputs.water_exclusions(s.n)
+    print(f"case periodic water exclusions n={s.n}", flush=True)
+    plan = M.plan_for(s, periodic=True)
+    plan.set_exclusions(*excl)
+    x, y, z, q = M.to_device(s)
+    out = plan.compute(x, y, z, q)
+    torch.cuda.synchronize()
+    plan.check()
+    ref = oracle.system_msm(s, periodic=True, exclusions=excl)
+    ex = oracle.exclusion_terms(s.x, s.y, s.z, s.q, *excl, box_lo=s.box_lo, box_len=s.box_len)
+    e, f, phi = _numpy(out)
+    scale = abs(ref["energy"]) + abs(ex["energy"])
+    print(f"  e_err/scale {abs(e - ref['energy']) / scale:.2e} f_rms {rel_rms(f, ref['f']):.2e} "
+          f"phi_rms {rel_rms(phi, ref['phi']):.2e}", flush=True)
+    assert abs(e - ref["energy"]) / scale <= 1e-7
+    assert rel_rms(f, ref["f"]) <= FORCE_RTOL and rel_rms(phi, ref["phi"]) <= PHI_RTOL
+
+
+def test_atoms_given_outside_the_box_are_their_images(M):
+    """A water box whose atoms are given shifted by random lattice vectors
+    (molecules straddle the faces): each atom is taken at its image in the
+    box, against the oracle on the same float32 inputs."""
+    s = _water(levels=2, seed=68, n=6000)
+    rng = np.random.default_rng(70)
+    k = rng.integers(-1, 2, size=(3, s.n)).astype(np.float64)
+    p = s.pos64() + k * np.asarray(s.box_len)[:, None]
+    s = dataclasses.replace(s, x=p[0].astype(np.float32), y=p[1].astype(np.float32), z=p[2].astype(np.float32),
+                            x64=p)
+    print(f"case periodic images n={s.n}", flush=True)
+    _, out = _run(M, s)
+    ref = oracle.system_msm(s, periodic=True)
+    e, f, phi = _numpy(out)
+    print(f"  e_rel {rel_err(e, ref['energy']):.2e} f_rms {rel_rms(f, ref['f']):.2e} "
+          f"phi_rms {rel_rms(phi, ref['phi']):.2e}", flush=True)
+    assert rel_err(e, ref["energy"]) <= ENERGY_RTOL
+    assert rel_rms(f, ref["f"]) <= FORCE_RTOL and rel_rms(phi, ref["phi"]) <= PHI_RTOL
+
+
+def test_periodic_graph_replay_and_unsupported_calls(M):
+    c = dict(CLOUDS["quintic_l3"])
+    s = _cloud(c.pop("n"), c.pop("box"), c.pop("seed"), **c)
+    print(f"case periodic graph n={s.n}", flush=True)
+    plan = M.plan_for(s, periodic=True)
+    x, y, z, q = M.to_device(s)
+    out = {"energy": torch.empty(1, dtype=torch.float64, device="cuda"),
+           "f": torch.empty((3, s.n), dtype=torch.float32, device="cuda"),
+           "phi": torch.empty(s.n, dtype=torch.float32, device="cuda")}
+    graph = M.Graph(plan, x, y, z, q, out)
+    for rep in range(3):
+        for t in out.values():
+            t.fill_(float("nan"))
+        graph.launch()
+        torch.cuda.synchronize()
+        got = {k: v.clone() for k, v in out.items()}
+        ref = plan.compute(x, y, z, q)          # eager work between the replays
+        torch.cuda.synchronize()
+        for k in ("energy", "f", "phi"):
+            assert torch.equal(got[k], ref[k]), (rep, k)
+    pos = torch.stack([x, y, z]).contiguous().requires_grad_(True)
+    with pytest.raises(M.MSMError) as err:
+        M.energy(plan, pos, q)
+    assert err.value.code == -6
+
+
+def _supercell(s):
+    """The 27 images of a system: the free-space picture of a periodic box
+    for the atoms of the central copy (index 13 of 27)."""
+    L = np.asarray(s.box_len, dtype=np.float64)
+    blocks = []
+    for iz in (-1, 0, 1):
+        for iy in (-1, 0, 1):
+            for ix in (-1, 0, 1):
+                blocks.append(s.pos64() + (np.array([ix, iy, iz]) * L)[:, None])
+    pos = np.concatenate(blocks, axis=1)
+    return pos, np.tile(s.q.astype(np.float64), 27), tuple(-L), tuple(3 * L)
+
+
+@pytest.mark.parametrize("kind", ["cutoff", "shifted_force", "wolf"])
+def test_periodic_pair_methods_match_the_supercell(M, kind):
+    s = _water(levels=1, seed=69, n=3000, a=9.0)
+    print(f"case periodic pair {kind} n={s.n}", flush=True)
+    plan = M.pair_plan_for(s, kind, alpha=0.2, periodic=True)
+    x, y, z, q = M.to_device(s)
+    out = plan.compute(x, y, z, q)
+    torch.cuda.synchronize()
+    plan.check()
+    pos, qq, lo, ln = _supercell(s)
+    ref = oracle.pair(*pos, qq, kind=kind, cutoff=s.cutoff, alpha=0.2, box_lo=lo, box_len=ln, f32_cut=True)
+    c = slice(13 * s.n, 14 * s.n)
+    f_ref, phi_ref = ref["f"][:, c], ref["phi"][c]
+    e_ref = 0.5 * float(s.q.astype(np.float64) @ phi_ref)
+    e, f, phi = _numpy(out)
+    print(f"  E_gpu={e:.10g} E_ref={e_ref:.10g} e_rel {rel_err(e, e_ref):.2e} f_rms {rel_rms(f, f_ref):.2e} "
+          f"phi_rms {rel_rms(phi, phi_ref):.2e}", flush=True)
+    assert rel_err(e, e_ref) <= ENERGY_RTOL
+    assert rel_rms(f, f_ref) <= FORCE_RTOL and rel_rms(phi, phi_ref) <= PHI_RTOL
