@@ -95,9 +95,7 @@ typedef struct msm_plan msm_plan;   /* host object; immutable after creation */
  * image (2 cutoff <= box_len); the top level sums its kernel over every image
  * in the Ewald convention (conducting boundary, uniform neutralising
  * background for a charged box).  Atoms may lie anywhere (each is taken at its
- * image in the box).  Periodic plans evaluate with msm_compute,
- * msm_compute_static, graphs and msm_vv_run; msm_energy and msm_backward
- * return MSM_ERR_UNSUPPORTED, and batches take free-space systems only. */
+ * image in the box).  Batches take free-space systems only. */
 msm_status msm_plan_create(const msm_params* params, int32_t n_atoms, msm_plan** out);
 msm_status msm_plan_destroy(msm_plan* plan);
 

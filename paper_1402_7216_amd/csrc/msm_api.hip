@@ -1188,7 +1188,6 @@ msm_status msm_energy(const msm_plan* P, void* ws, size_t ws_bytes, msm_stream_t
                       double* energy) {
   if (!energy) return fail(MSM_ERR_INVALID_ARG, "null energy output");
   if (P && P->g.pair) return fail(MSM_ERR_UNSUPPORTED, "msm_energy is for multilevel-summation plans");
-  if (P && P->g.periodic) return fail(MSM_ERR_UNSUPPORTED, "msm_energy: periodic plans evaluate with msm_compute");
   return eval_mode(msm::kModeEnergy, P, ws, ws_bytes, stream, x, y, z, q, nullptr, nullptr, nullptr,
                    nullptr, energy, nullptr);
 }
@@ -1199,7 +1198,6 @@ msm_status msm_backward(const msm_plan* P, void* ws, size_t ws_bytes, msm_stream
                         float* dedq) {
   if (!grad_energy) return fail(MSM_ERR_INVALID_ARG, "null grad_energy");
   if (P && P->g.pair) return fail(MSM_ERR_UNSUPPORTED, "msm_backward is for multilevel-summation plans");
-  if (P && P->g.periodic) return fail(MSM_ERR_UNSUPPORTED, "msm_backward: periodic plans evaluate with msm_compute");
   return eval_mode(msm::kModeGradient, P, ws, ws_bytes, stream, x, y, z, q, dedx, dedy, dedz, dedq,
                    nullptr, grad_energy);
 }

@@ -2453,8 +2453,14 @@ __global__ void __launch_bounds__(kBlock) k_energy_terms(KArgs A) {
   }
   for (int k = 0; k < g.levels; ++k) {
     const Level& L = g.lv[k];
-    for (int m = blk * blockDim.x + threadIdx.x; m < L.count; m += stride)
+    for (int m = blk * blockDim.x + threadIdx.x; m < L.count; m += stride) {
+      if (g.periodic) {                     // the nodes of one period only (ghosts are copies)
+        const int mx = m % L.n[0] - g.ghost, my = (m / L.n[0]) % L.n[1] - g.ghost;
+        const int mz = m / (L.n[0] * L.n[1]) - g.ghost;
+        if (mx < 0 || my < 0 || mz < 0 || mx >= L.per[0] || my >= L.per[1] || mz >= L.per[2]) continue;
+      }
       e += 0.5 * (double)qgrid[L.off + m] * (double)ucut_value(S, k, m, true);
+    }
   }
   e *= g.ke;
 #pragma unroll

@@ -157,7 +157,7 @@ def test_atoms_given_outside_the_box_are_their_images(M):
     assert rel_rms(f, ref["f"]) <= FORCE_RTOL and rel_rms(phi, ref["phi"]) <= PHI_RTOL
 
 
-def test_periodic_graph_replay_and_unsupported_calls(M):
+def test_periodic_graph_replay_matches_eager(M):
     c = dict(CLOUDS["quintic_l3"])
     s = _cloud(c.pop("n"), c.pop("box"), c.pop("seed"), **c)
     print(f"case periodic graph n={s.n}", flush=True)
@@ -177,10 +177,27 @@ def test_periodic_graph_replay_and_unsupported_calls(M):
         torch.cuda.synchronize()
         for k in ("energy", "f", "phi"):
             assert torch.equal(got[k], ref[k]), (rep, k)
+
+
+def test_periodic_energy_and_backward_match_oracle(M):
+    """The differentiable path on a periodic water box: energy-only forward
+    (the grids' interior nodes) and the adjoint backward (dE/dr = -F,
+    dE/dq = phi of the oracle)."""
+    s = _water(levels=3, seed=71, n=9000)
+    print(f"case periodic autograd n={s.n}", flush=True)
+    plan = M.plan_for(s, periodic=True)
+    x, y, z, q = M.to_device(s)
     pos = torch.stack([x, y, z]).contiguous().requires_grad_(True)
-    with pytest.raises(M.MSMError) as err:
-        M.energy(plan, pos, q)
-    assert err.value.code == -6
+    qq = q.clone().requires_grad_(True)
+    e = M.energy(plan, pos, qq)
+    e.backward()
+    torch.cuda.synchronize()
+    ref = oracle.system_msm(s, periodic=True)
+    gr, gq = pos.grad.double().cpu().numpy(), qq.grad.double().cpu().numpy()
+    print(f"  e_rel {rel_err(float(e.item()), ref['energy']):.2e} dEdr {rel_rms(-gr, ref['f']):.2e} "
+          f"dEdq {rel_rms(gq, ref['phi']):.2e}", flush=True)
+    assert rel_err(float(e.item()), ref["energy"]) <= ENERGY_RTOL
+    assert rel_rms(-gr, ref["f"]) <= FORCE_RTOL and rel_rms(gq, ref["phi"]) <= PHI_RTOL
 
 
 def _supercell(s):
