@@ -223,6 +223,40 @@ def cheap_msm_leg(msm, torch, workmodel, s, t_msm, work_f, steps, warmup, x, y, 
     return res
 
 
+def periodic_leg(msm, torch, s, t_msm, steps, warmup, x, y, z, q):
+    """The same atoms in a periodic box (the box repeated in every direction):
+    the spacing nearest to the free-space one that divides the box into whole
+    grid periods over 5 levels, automatic levels, the top level through its
+    Ewald image sum.  Timed forces evaluation (parity is tested against the
+    oracle's periodic evaluation at up to 9,000 atoms), and the shifted-force
+    cutoff with periodic images."""
+    import dataclasses
+    from paper_1402_7216_amd import inputs
+    v = dataclasses.replace(s, spacing=inputs.periodic_spacing(s.box_len[0], s.spacing, 5), levels=0)
+    plan = msm.plan_for(v, periodic=True)
+    out = plan.compute(x, y, z, q)
+    torch.cuda.synchronize()
+    plan.check()
+    autotune(plan, x, y, z, q, 10)
+    mean, med = event_timed(torch, lambda: plan.compute(x, y, z, q, out=out), steps, warmup)
+    plan.check()
+    levels, _, gn = plan.info()
+    d = plan.describe()
+    res = {"workload": f"{v.name} periodic: {v.n} atoms, box {v.box_len[0]:.2f} A, a = {v.cutoff} A, "
+                       f"h = {v.spacing:.4f} A, order {v.order}",
+           "levels": levels, "ghost_nodes": d["ghost"], "grid_nodes_with_ghosts": [list(n_) for n_ in gn],
+           "ms": round(mean * 1e3, 5), "ms_median": round(med * 1e3, 5),
+           "atom_evals_per_s": v.n / mean, "vs_free_space_ms": round(t_msm * 1e3, 5), "tuning": plan.tuning()}
+    pp = msm.pair_plan_for(v, "shifted_force", periodic=True)
+    o2 = pp.compute(x, y, z, q)
+    torch.cuda.synchronize()
+    pp.check()
+    autotune(pp, x, y, z, q, 10)
+    m2, md2 = event_timed(torch, lambda: pp.compute(x, y, z, q, out=o2), steps, warmup)
+    res["shifted_force_periodic_ms"] = round(m2 * 1e3, 5)
+    return res
+
+
 def parareal_leg(msm, torch, reps=3):
     """One parareal window on a 27,000-ion rock-salt cluster (a = 12 A, h = 2
     A, cubic): T = 8 slices of 5 velocity Verlet steps of 1 fs, fine
@@ -545,6 +579,7 @@ def main():
             "water24k": water24k_leg(msm, torch, max(args.steps, 50), args.warmup),
             "water100k_forward_backward": water100k_grad_leg(msm, torch, max(args.steps, 50), args.warmup),
             "parareal": parareal_leg(msm, torch),
+            "periodic": periodic_leg(msm, torch, s, sec, args.steps, args.warmup, x, y, z, q),
             "batched": batched_leg(msm, torch, workmodel, max(20, min(args.steps, 50)), 5,
                                    not args.no_autotune),
         }
