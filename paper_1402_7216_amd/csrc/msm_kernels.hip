@@ -1184,6 +1184,11 @@ __device__ __forceinline__ void anterp_scatter(const Geom& g, const float4 p, co
   }
 }
 
+// Queue entry of thread t in a scatter round: t with its 8 bits reversed (a
+// bijection of [0, 256)).
+static_assert(kAThreads == 256, "spread() permutes 8-bit thread indices");
+__device__ __forceinline__ int spread(unsigned t) { return (int)(__builtin_bitreverse32(t) >> 24); }
+
 template <int ORDER>
 __global__ void __launch_bounds__(kAThreads) k_anterp(KArgs A) {
   int blk;
@@ -1269,8 +1274,12 @@ __global__ void __launch_bounds__(kAThreads) k_anterp(KArgs A) {
       if (own) queue[base + __popcll(m & ((1ull << lane) - 1))] = p;
       __syncthreads();
       if (total >= kAThreads) {
-        // a full round: one queued atom per thread, then the rest to the front
-        anterp_scatter<ORDER>(g, queue[threadIdx.x], n0, T, ex, ey, acc);
+        // a full round: one queued atom per thread, then the rest to the front.
+        // Thread t takes entry bitrev(t): the queue is in cell order, and
+        // neighbouring atoms hit the same nodes, so consecutive lanes take
+        // atoms far apart in the queue (same-address atomics of one wave
+        // instruction serialise; the integer sums do not depend on order)
+        anterp_scatter<ORDER>(g, queue[spread(threadIdx.x)], n0, T, ex, ey, acc);
         const int rest = total - kAThreads;
         const float4 v = (int)threadIdx.x < rest ? queue[kAThreads + threadIdx.x] : p;
         __syncthreads();
@@ -1281,7 +1290,7 @@ __global__ void __launch_bounds__(kAThreads) k_anterp(KArgs A) {
       __syncthreads();
     }
   }
-  if ((int)threadIdx.x < qlen) anterp_scatter<ORDER>(g, queue[threadIdx.x], n0, T, ex, ey, acc);
+  if (spread(threadIdx.x) < qlen) anterp_scatter<ORDER>(g, queue[spread(threadIdx.x)], n0, T, ex, ey, acc);
   __syncthreads();
   long long* __restrict__ out = S.d.ant_part + (size_t)blk * ext;
   for (int i = threadIdx.x; i < ext; i += kAThreads) out[i] = (long long)acc[i];
