@@ -867,6 +867,50 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
+// Minimum / maximum over the 64 lanes of a wave (every lane active), returned
+// in a scalar register, with DPP moves instead of LDS permutes: row_shr 1, 2,
+// 4, 8 leave the extreme of each 16-lane row in its lane 15, row_bcast 15 and
+// row_bcast 31 carry it across the rows into lane 63.
+__device__ __forceinline__ int wave_min_s(int v) {
+  v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x111, 0xf, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x112, 0xf, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x114, 0xf, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x118, 0xf, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x142, 0xa, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x143, 0xc, 0xf, false));
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
+__device__ __forceinline__ int wave_max_s(int v) {
+  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x111, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x112, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x114, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x118, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x142, 0xa, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x143, 0xc, 0xf, false));
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Sum over the 64 lanes of a wave (every lane active) in a fixed order, the
+// same DPP pattern on the two halves of each double; the total is in lane 63.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_shift_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double wave_sum_d63(double v) {
+  v += dpp_shift_d<0x111, 0xf>(v);
+  v += dpp_shift_d<0x112, 0xf>(v);
+  v += dpp_shift_d<0x114, 0xf>(v);
+  v += dpp_shift_d<0x118, 0xf>(v);
+  v += dpp_shift_d<0x142, 0xa>(v);
+  v += dpp_shift_d<0x143, 0xc>(v);
+  return v;
+}
+
 // A launch takes the work items [n lo_pm / 1000, n hi_pm / 1000) of each system.
 // binom(-1/2, j): the coefficients of the Taylor polynomial of s^{-1/2} about
 // s = 1 in powers of (s - 1) (exact dyadic rationals).
@@ -2134,29 +2178,26 @@ k_prolong(KArgs A, int level) {
   if (!(S.lat.b == 0 || k >= S.lat.n) && S.lat.t[k].groups > 1) S.d.ucut[F.off + (size_t)node] = own;
 }
 
-// Fixed-order block reduction of one energy and 9 virial values per thread
-// (butterfly within the wave, then the waves in order) into the block's slot
-// of the float64 partials (component t at t * n_partials + blk).
+// Fixed-order block reduction of one energy and (with vir_on) 9 virial values
+// per thread (DPP sum within the wave, then the waves in order) into the
+// block's slot of the float64 partials (component t at t * n_partials + blk).
 __device__ __forceinline__ void block_partials(double e, const double* vir, double* partials, int n_partials,
-                                               int blk) {
+                                               int blk, bool vir_on) {
   __shared__ double red[10][kBlock / kWave];
+  const int nv = vir_on ? 10 : 1;
   double vals[10];
   vals[0] = e;
 #pragma unroll
   for (int t = 0; t < 9; ++t) vals[t + 1] = vir[t];
-#pragma unroll
-  for (int t = 0; t < 10; ++t) {
-    double v = vals[t];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-    vals[t] = v;
-  }
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  if (lane == 0)
 #pragma unroll
-    for (int t = 0; t < 10; ++t) red[t][wave] = vals[t];
+  for (int t = 0; t < 10; ++t)
+    if (t < nv) {
+      const double v = wave_sum_d63(vals[t]);
+      if (lane == kWave - 1) red[t][wave] = v;
+    }
   __syncthreads();
-  if (threadIdx.x < 10) {
+  if (threadIdx.x < nv) {
     double v = 0.0;
     for (int w = 0; w < kBlock / kWave; ++w) v += red[threadIdx.x][w];
     partials[(size_t)threadIdx.x * n_partials + blk] = v;
@@ -2287,6 +2328,8 @@ __device__ ExclSums pair_exclusions(const SysDesc& S, const Io& io, int i) {
   return r;
 }
 
+constexpr int kInterpBox = 2048;   // nodes of u^0 one wave stages in LDS (8 KB)
+
 template <int ORDER, int MODE>
 __global__ void __launch_bounds__(kBlock) k_interp(KArgs A) {
   int blk;
@@ -2305,37 +2348,39 @@ __global__ void __launch_bounds__(kBlock) k_interp(KArgs A) {
   const double* __restrict__ gscale = A.io.gscale ? A.io.gscale + S.index : nullptr;
   constexpr int H = ORDER / 2;
   const Level L = g.lv[0];
-  int s = blk * blockDim.x + threadIdx.x;
+  const int s = blk * blockDim.x + threadIdx.x;
+  const bool live = s < g.n_atoms;
   double e = 0.0, vir[9];
 #pragma unroll
   for (int t = 0; t < 9; ++t) vir[t] = 0.0;
-  if (s < g.n_atoms) {
-    float4 p = sorted[s];
-    float pp[3] = {p.x, p.y, p.z};
-    float w[3][ORDER], dw[3][ORDER];
-    int base[3];
+  // Every lane of the block takes part in the staging below (a lane past the
+  // last atom takes that atom's place and discards its result).
+  const float4 p = g.n_atoms > 0 ? sorted[live ? s : g.n_atoms - 1] : make_float4(0.f, 0.f, 0.f, 0.f);
+  const float pp[3] = {p.x, p.y, p.z};
+  float w[3][ORDER], dw[3][ORDER];
+  int base[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      int f;
-      float r;
-      grid_coord(pp[d], g.lo_f[d], g.h, g.inv_h, g.fmax[d], f, r);
-      basis<ORDER>(r, w[d], dw[d]);
-      base[d] = f - (H - 1) - L.lo[d];
-    }
-    const float* u0 = u + L.off;
-    float pl = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
-    // cubic: all 64 node values are loaded in one round (registers are not
-    // scarce in this small launch); quintic: one z plane at a time
+  for (int d = 0; d < 3; ++d) {
+    int f;
+    float r;
+    grid_coord(pp[d], g.lo_f[d], g.h, g.inv_h, g.fmax[d], f, r);
+    basis<ORDER>(r, w[d], dw[d]);
+    base[d] = f - (H - 1) - L.lo[d];
+  }
+  // sum_{sx,sy,sz} w_x w_y w_z u and its three partial derivatives over the
+  // ORDER^3 nodes from src (the node base of this atom), rows sy apart, planes sz
+  float pl = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+  auto gather = [&](const float* src, int sy_stride, int sz_stride) {
 #pragma unroll ORDER == 4 ? ORDER : 1
     for (int sz = 0; sz < ORDER; ++sz) {
       float py_ = 0.f, gxy = 0.f, gyy = 0.f;
 #pragma unroll
       for (int sy = 0; sy < ORDER; ++sy) {
-        const float* rowp = u0 + ((size_t)(base[2] + sz) * L.n[1] + (base[1] + sy)) * L.n[0] + base[0];
+        const float* rowp = src + sz * sz_stride + sy * sy_stride;
         float vx = 0.f, dvx = 0.f;
 #pragma unroll
         for (int sx = 0; sx < ORDER; ++sx) {
-          float uv = rowp[sx];
+          const float uv = rowp[sx];
           vx = fmaf(w[0][sx], uv, vx);
           dvx = fmaf(dw[0][sx], uv, dvx);
         }
@@ -2348,6 +2393,71 @@ __global__ void __launch_bounds__(kBlock) k_interp(KArgs A) {
       gy = fmaf(w[2][sz], gyy, gy);
       gz = fmaf(dw[2][sz], py_, gz);
     }
+  };
+  // The atoms of one link-cell row are consecutive in sorted order and close
+  // together, so the nodes they read form a small box of u^0: the lanes of a
+  // row stage their box in the wave's LDS slice with coalesced loads, then
+  // every lane reads its ORDER^3 nodes from there.  A wave whose atoms span
+  // several rows takes them one row at a time; a row whose box exceeds the
+  // slice reads u^0 directly.
+  __shared__ float stage[kBlock / kWave][kInterpBox];
+  const int lane = threadIdx.x & (kWave - 1);
+  float* box = stage[threadIdx.x / kWave];
+  const int row = cell_coord(g, p.z, 2) * g.nc[1] + cell_coord(g, p.y, 1);
+  const float* u0 = u + L.off;
+  const int n0 = L.n[0], n01 = L.n[0] * L.n[1];
+  for (unsigned long long pending = __ballot(live); pending;) {
+    const int lead = __ffsll((long long)pending) - 1;
+    const int grow = __builtin_amdgcn_readlane(row, lead);
+    const bool mine = ((pending >> lane) & 1ull) && row == grow;
+    pending &= ~__ballot(mine);
+    int lo3[3], ext[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      lo3[d] = wave_min_s(mine ? base[d] : INT_MAX);
+      ext[d] = wave_max_s(mine ? base[d] : INT_MIN) - lo3[d] + ORDER;
+    }
+    const int vol = ext[0] * ext[1] * ext[2];
+    // the box lies in the grid (every base does), checked before any load
+    const bool inside = lo3[0] >= 0 && lo3[1] >= 0 && lo3[2] >= 0 && lo3[0] + ext[0] <= L.n[0] &&
+                        lo3[1] + ext[1] <= L.n[1] && lo3[2] + ext[2] <= L.n[2];
+    if (inside && vol <= kInterpBox) {
+      const float inv0 = 1.f / (float)ext[0], inv1 = 1.f / (float)ext[1];
+      const float* corner = u0 + (size_t)lo3[2] * n01 + (size_t)lo3[1] * n0 + lo3[0];
+      // 16 loads per lane in flight at a time
+      for (int i0 = 0; i0 < vol; i0 += 16 * kWave) {
+        float v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const int i = i0 + k * kWave + lane;
+          v[k] = 0.f;
+          if (i < vol) {
+            int xx, yy;
+            const int zz = fdiv(fdiv(i, ext[0], inv0, xx), ext[1], inv1, yy);
+            v[k] = corner[zz * n01 + yy * n0 + xx];
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const int i = i0 + k * kWave + lane;
+          if (i < vol) box[i] = v[k];
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (mine)
+        gather(box + ((base[2] - lo3[2]) * ext[1] + (base[1] - lo3[1])) * ext[0] + (base[0] - lo3[0]), ext[0],
+               ext[0] * ext[1]);
+      // the next row's staging overwrites the slice
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else if (mine) {
+      gather(u0 + (size_t)base[2] * n01 + (size_t)base[1] * n0 + base[0], n0, n01);
+    }
+  }
+  if (live) {
     gx *= g.inv_h;
     gy *= g.inv_h;
     gz *= g.inv_h;
@@ -2392,7 +2502,7 @@ __global__ void __launch_bounds__(kBlock) k_interp(KArgs A) {
   }
   // gradient mode has no reductions: every thread of the block leaves here
   if (MODE == 1) return;
-  block_partials(e, vir, partials, n_partials, blk);
+  block_partials(e, vir, partials, n_partials, blk, A.io.virial != nullptr);
 }
 
 // Assembly of a cheap pair method evaluated on its own (no grids):
@@ -2437,7 +2547,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_finish(KArgs A) {
 #pragma unroll
       for (int b = 0; b < 3; ++b) vir[3 * a + b] = rr[a] * (double)of[b];
   }
-  block_partials(e, vir, S.d.partials, S.n_partials, blk);
+  block_partials(e, vir, S.d.partials, S.n_partials, blk, A.io.virial != nullptr);
 }
 
 // Energy without prolongation or interpolation (grid form):
@@ -2485,7 +2595,7 @@ __global__ void __launch_bounds__(kBlock) k_energy_terms(KArgs A) {
 }
 
 // Sum the per-block partials in a fixed order (one block): each thread adds
-// its strided share, then a butterfly per wave and the 4 waves in order.
+// its strided share, then a DPP sum per wave and the 4 waves in order.
 __global__ void __launch_bounds__(kBlock) k_reduce(KArgs A, int with_virial) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
@@ -2493,28 +2603,39 @@ __global__ void __launch_bounds__(kBlock) k_reduce(KArgs A, int with_virial) {
   const int n_partials = S.g.n_atoms > 0 ? S.n_partials : 0;
   double* __restrict__ energy = A.io.energy ? A.io.energy + S.index : nullptr;
   double* __restrict__ virial = (with_virial && A.io.virial) ? A.io.virial + 9 * (size_t)S.index : nullptr;
+  // the virial partials exist only when the evaluation asked for the virial
+  const int nv = A.io.virial ? 10 : 1;
   __shared__ double red[10][kBlock / kWave];
   double acc[10];
 #pragma unroll
   for (int t = 0; t < 10; ++t) acc[t] = 0.0;
-  for (int b = threadIdx.x; b < n_partials; b += kBlock) {
-    double v[10];
+  if (nv == 1) {
+    // energy only: 8 loads per thread in flight, added in index order
+    for (int b0 = threadIdx.x; b0 < n_partials; b0 += 8 * kBlock) {
+      double v[8];
 #pragma unroll
-    for (int t = 0; t < 10; ++t) v[t] = partials[(size_t)t * n_partials + b];
+      for (int u = 0; u < 8; ++u) v[u] = b0 + u * kBlock < n_partials ? partials[b0 + u * kBlock] : 0.0;
 #pragma unroll
-    for (int t = 0; t < 10; ++t) acc[t] += v[t];
-  }
+      for (int u = 0; u < 8; ++u) acc[0] += v[u];
+    }
+  } else {
+    for (int b = threadIdx.x; b < n_partials; b += kBlock) {
+      double v[10];
 #pragma unroll
-  for (int t = 0; t < 10; ++t) {
+      for (int t = 0; t < 10; ++t) v[t] = partials[(size_t)t * n_partials + b];
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) acc[t] += __shfl_xor(acc[t], off);
+      for (int t = 0; t < 10; ++t) acc[t] += v[t];
+    }
   }
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  if (lane == 0)
 #pragma unroll
-    for (int t = 0; t < 10; ++t) red[t][wave] = acc[t];
+  for (int t = 0; t < 10; ++t)
+    if (t < nv) {
+      const double v = wave_sum_d63(acc[t]);
+      if (lane == kWave - 1) red[t][wave] = v;
+    }
   __syncthreads();
-  if (threadIdx.x < 10) {
+  if (threadIdx.x < nv) {
     double v = 0.0;
     for (int w = 0; w < kBlock / kWave; ++w) v += red[threadIdx.x][w];
     if (threadIdx.x == 0) {
