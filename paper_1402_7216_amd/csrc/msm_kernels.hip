@@ -855,18 +855,6 @@ __device__ __forceinline__ int cell_x(const Geom& g, float x) {
   return min((int)t, g.nc[0] - 1);
 }
 
-__device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off));
-  return v;
-}
-
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off));
-  return v;
-}
-
 // Minimum / maximum over the 64 lanes of a wave (every lane active), returned
 // in a scalar register, with DPP moves instead of LDS permutes: row_shr 1, 2,
 // 4, 8 leave the extreme of each 16-lane row in its lane 15, row_bcast 15 and
@@ -1032,7 +1020,7 @@ __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, 
             hi = start[jrow + cell_x(g, pi.x + e - g.len_f[0]) + 1];
           }
         }
-        const int u0 = wave_min(lo), u1 = wave_max(hi);
+        const int u0 = wave_min_s(lo), u1 = wave_max_s(hi);
         for (int s0 = u0; s0 < u1; s0 += kShortSeg) {
           // stage the union of the windows, 256 atoms at a time
 #pragma unroll
@@ -1054,7 +1042,7 @@ __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, 
           const int n = (hi > lo && hi_s > lo_s) ? hi_s - lo_s : 0;
           const int a0 = n > 0 ? lo_s : 0;
           const int b0 = a0 + n;
-          const int nmax = wave_max(n);
+          const int nmax = wave_max_s(n);
           if (r == centre && img == 0) {
             // the centre row holds the atom's own cell: any other atom at
             // distance zero is a coincident pair
@@ -1183,6 +1171,17 @@ __device__ __forceinline__ unsigned long long fixed36(float v) {
   return ((unsigned long long)(unsigned)(int)hi << 32) + (unsigned long long)(unsigned)lo;
 }
 
+// The same integer from s = v 2^36 (exact in float32) for |v| < 2^15, in three
+// instructions: s + 1.5 2^52 in float64 is rounded once, to the nearest
+// integer (doubles in [2^52, 2^53) are spaced 1 apart; ties to even as above),
+// and since |s| < 2^51 its bit pattern is that of 1.5 2^52
+// (0x4338000000000000) plus the integer.  Taking the constant's pattern off
+// leaves the integer (its low word is 0, so only the high word changes).
+__device__ __forceinline__ unsigned long long fixed36_scaled(float s) {
+  const double t = (double)s + 6755399441055744.0;
+  return (unsigned long long)__double_as_longlong(t) - 0x4338000000000000ull;
+}
+
 // Whether the tile with corner n0 (floor indices) and extent T owns the atom
 // at p; f receives its tile-local floor indices.
 template <int ORDER>
@@ -1215,15 +1214,33 @@ __device__ __forceinline__ void anterp_scatter(const Geom& g, const float4 p, co
   float w[3][ORDER], dw[3][ORDER];
 #pragma unroll
   for (int d = 0; d < 3; ++d) basis<ORDER>(r[d], w[d], dw[d]);
+  // |Phi| <= 1, so every contribution of a charge below 2^15 in magnitude
+  // takes the short conversion, with 2^36 folded into the charge (scaling by
+  // a power of two commutes with the rounding of the products)
+  if (fabsf(p.w) < 32768.f) {
+    const float qs = p.w * (float)kFix;
 #pragma unroll
-  for (int sz = 0; sz < ORDER; ++sz) {
-    const float qz = p.w * w[2][sz];
+    for (int sz = 0; sz < ORDER; ++sz) {
+      const float qz = qs * w[2][sz];
 #pragma unroll
-    for (int sy = 0; sy < ORDER; ++sy) {
-      const float qyz = qz * w[1][sy];
-      unsigned long long* rowp = acc + ((f[2] + sz) * ey + (f[1] + sy)) * ex + f[0];
+      for (int sy = 0; sy < ORDER; ++sy) {
+        const float qyz = qz * w[1][sy];
+        unsigned long long* rowp = acc + ((f[2] + sz) * ey + (f[1] + sy)) * ex + f[0];
 #pragma unroll
-      for (int sx = 0; sx < ORDER; ++sx) atomicAdd(rowp + sx, fixed36(qyz * w[0][sx]));
+        for (int sx = 0; sx < ORDER; ++sx) atomicAdd(rowp + sx, fixed36_scaled(qyz * w[0][sx]));
+      }
+    }
+  } else {
+#pragma unroll
+    for (int sz = 0; sz < ORDER; ++sz) {
+      const float qz = p.w * w[2][sz];
+#pragma unroll
+      for (int sy = 0; sy < ORDER; ++sy) {
+        const float qyz = qz * w[1][sy];
+        unsigned long long* rowp = acc + ((f[2] + sz) * ey + (f[1] + sy)) * ex + f[0];
+#pragma unroll
+        for (int sx = 0; sx < ORDER; ++sx) atomicAdd(rowp + sx, fixed36(qyz * w[0][sx]));
+      }
     }
   }
 }
