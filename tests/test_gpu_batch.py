@@ -239,7 +239,9 @@ def test_autotune_keeps_results_within_bars(M):
     x, y, z, q = M.batch_to_device(systems)
     rep = b.autotune(x, y, z, q, trials=2)
     print(f"case batch autotune: best {rep['best']} of {len(rep['candidates'])}", flush=True)
-    assert 20 <= len(rep["candidates"]) <= 40
+    # 18 (B x chunks x two layouts) + up to 3 reaches + up to 14 layouts x
+    # block counts + up to 2 starts + 2 chunk counts + up to 3 splits
+    assert 20 <= len(rep["candidates"]) <= 42
     best = rep["best"]
     # the best is within 1% of the fastest (later candidates must win by more)
     assert best["ms"] <= 1.0101 * min(c["ms"] for c in rep["candidates"])
