@@ -369,7 +369,11 @@ void refresh_launch(msm_plan* P) {
   lg.bin.blocks = sb.bin;
   lg.binrow.blocks = sb.binrow;
   lg.binrow_lds = msm::bin_rows_lds(g);
-  lg.bin4 = g.bin_blocks == 0 && g.bin_row_blocks == 0;
+  lg.bin4 = g.bin_blocks == 0 && g.bin_row_blocks == 0 && g.binr_blocks == 0;
+  lg.rchunk.blocks = sb.rchunk;
+  lg.rscan.blocks = sb.rscan;
+  lg.rsort.blocks = sb.rsort;
+  lg.rsort_lds = msm::binr_sort_lds(g);
   lg.one.blocks = 1;
   lg.scan.blocks = sb.scan;
   lg.agather.blocks = sb.agather;
@@ -461,7 +465,8 @@ void set_short_blocks(Geom& g, int cap) {
 // assignment and work items, and the binning path the cells allow: one kernel
 // for small systems whose blocks own few enough cells (unless the plan prefers
 // the two-kernel path, as in batches), else two kernels when the cell counts of
-// every block fit (LDS, histogram size), else four.
+// every block fit (LDS, histogram size), else four by cell row when the rows
+// fit, else four over the cells.
 void set_cell_geometry(msm_plan* P, int reach) {
   Geom& g = P->g;
   const msm_params& p = P->p;
@@ -498,6 +503,10 @@ void set_cell_geometry(msm_plan* P, int reach) {
   const bool one = n_atoms > 0 && n_atoms <= msm::kBinRowAtoms && own <= msm::kBinRowCells;
   g.bin_row_blocks = (one && !(P->prefer_bin2 && P->bin2_blocks > 0)) ? nbr : 0;
   g.bin_blocks = g.bin_row_blocks == 0 ? P->bin2_blocks : 0;
+  // otherwise by cell row first, then within each row, when the rows fit the
+  // row binning's LDS histograms (else four kernels over the cells)
+  const bool by_rows = n_atoms > 0 && g.bin_row_blocks == 0 && g.bin_blocks == 0 && rows <= msm::kBinRowsMax;
+  g.binr_blocks = by_rows ? (int)((n_atoms + msm::kBinRChunk - 1) / msm::kBinRChunk) : 0;
   set_row_items(g, g.item_chunks);
   set_short_blocks(g, P->short_cap);
 }
@@ -896,7 +905,8 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
   // sized for the two-kernel binning wherever it is possible (a batch may
   // switch a system to it)
   lay.bytes[msm::kSecBinHist] = std::max<size_t>((size_t)P->max_bin_hist, 1) * sizeof(int);
-  lay.bytes[msm::kSecScan] = ((size_t)P->max_cells / msm::kScanTile + 1) * sizeof(int);
+  // tile totals of the four-kernel binning's scan, or the row starts of the row binning
+  lay.bytes[msm::kSecScan] = ((size_t)P->max_cells + 1) * sizeof(int);
   lay.bytes[msm::kSecAntPart] = (size_t)g.atn[0] * g.atn[1] * g.atn[2] * g.at_ext * sizeof(long long);
   lay.bytes[msm::kSecRows] = std::max<size_t>(P->rows.size(), 1) * sizeof(msm::StencilRow);
   lay.bytes[msm::kSecWeights] = std::max<size_t>(P->weights.size(), 1) * sizeof(float);
@@ -1040,7 +1050,8 @@ msm_status msm_plan_describe(const msm_plan* P, char* buf, size_t buf_bytes) {
   o += ", \"cells\": [" + std::to_string(g.nc[0]) + ", " + std::to_string(g.nc[1]) + ", " +
        std::to_string(g.nc[2]) + "], \"reach\": " + std::to_string(g.reach) +
        ", \"bin_blocks\": " + std::to_string(g.bin_blocks) +
-       ", \"bin_row_blocks\": " + std::to_string(g.bin_row_blocks) +
+       ", \"bin_row_blocks\": " + std::to_string(g.bin_row_blocks) + ", \"binr_blocks\": " +
+       std::to_string(g.binr_blocks) +
        ", \"item_chunks\": " + std::to_string(g.item_chunks) + ", \"short_blocks\": " + std::to_string(g.short_blocks) +
        ", \"streams\": " + std::to_string(P->streams) + ", \"short_after\": " + std::to_string(P->short_after) +
        ", \"short_split\": " + std::to_string(P->short_split);

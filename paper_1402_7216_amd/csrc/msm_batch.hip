@@ -25,7 +25,7 @@ namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-constexpr int kNumStages = 15 + msm::kMaxLevels;
+constexpr int kNumStages = 18 + msm::kMaxLevels;
 
 }  // namespace
 
@@ -54,7 +54,7 @@ namespace {
 // Stage order inside the map arrays.
 enum : int {
   kMZero = 0, kMAtoms, kMBin, kMOne, kMShort, kMAnterp, kMLattice0, kMLattice, kMLatticeAll, kMTop, kMEnergy,
-  kMProlong, kMBinRow, kMScan, kMAGather,
+  kMProlong, kMBinRow, kMScan, kMAGather, kMRChunk, kMRScan, kMRSort,
   kMRestrict0
 };
 
@@ -75,6 +75,9 @@ msm::StageGrid* stage_of(msm::LaunchGeom& L, int st) {
     case kMBinRow: return &L.binrow;
     case kMScan: return &L.scan;
     case kMAGather: return &L.agather;
+    case kMRChunk: return &L.rchunk;
+    case kMRScan: return &L.rscan;
+    case kMRSort: return &L.rsort;
     default: return &L.restrict_[st - kMRestrict0];
   }
 }
@@ -96,6 +99,9 @@ int blocks_of(const msm::SysBlocks& b, int st) {
     case kMBinRow: return b.binrow;
     case kMScan: return b.scan;
     case kMAGather: return b.agather;
+    case kMRChunk: return b.rchunk;
+    case kMRScan: return b.rscan;
+    case kMRSort: return b.rsort;
     default: return b.restrict_[st - kMRestrict0];
   }
 }
@@ -115,8 +121,9 @@ void rebuild_maps(msm_batch* Bt) {
   for (int st = 0; st < kNumStages; ++st) Bt->map[st].clear();
   for (int s = 0; s < Bt->n_sys; ++s) {
     const msm_plan* P = Bt->plans[s];
-    if (P->g.bin_blocks == 0 && P->g.bin_row_blocks == 0) L.bin4 = true;
+    if (P->g.bin_blocks == 0 && P->g.bin_row_blocks == 0 && P->g.binr_blocks == 0) L.bin4 = true;
     L.binrow_lds = std::max(L.binrow_lds, msm::bin_rows_lds(P->g));
+    L.rsort_lds = std::max(L.rsort_lds, msm::binr_sort_lds(P->g));
     L.anterp_lds = std::max(L.anterp_lds, msm::anterp_lds(P->g));
     L.max_levels = std::max(L.max_levels, P->g.levels);
     L.lat_b = std::max(L.lat_b, P->lat.b);

@@ -22,6 +22,9 @@ constexpr int kXSub = 4;                  // link cells are this many times fine
 constexpr int kBinMaxCells = 8192;        // cells the two-kernel binning keeps in LDS
 constexpr int kBinMaxHist = 1 << 20;      // block histogram entries of the two-kernel binning
 constexpr int kBinRowAtoms = 32768;       // atoms per system at most for the one-kernel binning
+constexpr int kBinRChunk = 4096;          // atoms per block of the row binning's count and scatter
+constexpr int kBinRowsMax = 8192;         // cell rows of a system at most for the row binning
+constexpr int kBinRSortCap = 1024;        // atoms of a cell row the row binning's sort keeps in LDS
 constexpr int kBinRowCells = 512;         // cells one block of the one-kernel binning owns at most
 constexpr int kBinRowMaxBlocks = 256;     // blocks of the one-kernel binning per system at most
 constexpr int kStatusWords = 64 + kBinRowMaxBlocks;   // [0]: flags; [64 + b]: flags of binning block b
@@ -65,6 +68,7 @@ struct Geom {
   int max_cells;                   // cells of the finest reach any tuning may select (sizes the cell arrays)
   int bin_blocks;                  // blocks of the two-kernel binning (0: another binning)
   int bin_row_blocks;              // blocks of the one-kernel binning (0: another binning)
+  int binr_blocks;                 // blocks (kBinRChunk atoms each) of the row binning (0: another binning)
   int reach;                       // neighbour cell rows per side in y and z
   float inv_cs[3];                 // 1 / cell edge
   float cs[3];                     // cell edge (x cells are kXSub times finer than y, z)
@@ -304,6 +308,10 @@ struct LaunchGeom {
   int prolong_level[kMaxLevels] = {};   // prolongation tiles of each level below the top
   StageGrid bin;                     // two-kernel binning (systems with bin_blocks > 0)
   StageGrid binrow;                  // one-kernel binning (systems with bin_row_blocks > 0)
+  StageGrid rchunk;                  // row binning: count and scatter (systems with binr_blocks > 0)
+  StageGrid rscan;                   // row binning: one block per system
+  StageGrid rsort;                   // row binning: one block per cell row
+  int rsort_lds = 0;                 // dynamic LDS of the row binning's sort (largest system)
   bool periodic = false;             // periodic grids: ghost folds and fills between the stages
   bool short_periodic = false;       // periodic short range (MSM or pair plans)
   int ghost_blocks[kMaxLevels] = {}; // blocks of a ghost fill of each level (one system)
@@ -320,6 +328,7 @@ struct LaunchGeom {
 struct SysBlocks {
   int zero, atoms, bin, binrow, shortr, anterp, lattice0, lattice, lattice_all, top, energy, scan;
   int agather;
+  int rchunk, rscan, rsort;          // row binning
   int restrict_[kMaxLevels];
   int prolong;                       // tiles of every level below the top
 };
@@ -334,6 +343,15 @@ inline int bin_rows_lds(const Geom& g) {
   const int own = (rows + g.bin_row_blocks - 1) / g.bin_row_blocks * g.nc[0];
   const int chunks = (g.n_atoms + 63) / 64;
   return 16 * own * 4 + 2 * 16 * 4 + chunks * 64 * 2;
+}
+
+// Dynamic LDS of the row binning's sort for one system: x-cell starts and
+// cursors, then (for rows of at most kBinRSortCap atoms) the row's atoms,
+// input indices and x cells in bucket order.
+inline int binr_sort_lds(const Geom& g) {
+  if (g.binr_blocks == 0) return 0;
+  const int ints = (2 * (g.nc[0] + 1) + 3) & ~3;
+  return ints * 4 + kBinRSortCap * (16 + 4 + 2);
 }
 
 // Dynamic LDS of the anterpolation of one system: its tile's private region

@@ -204,7 +204,7 @@ __global__ void k_bin_count(KArgs A) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
   const Geom& g = S.g;
-  if (g.bin_blocks || g.bin_row_blocks) return;
+  if (g.bin_blocks || g.bin_row_blocks || g.binr_blocks) return;
   const int i = blk * blockDim.x + threadIdx.x;
   const bool active = i < g.n_atoms;
   int c = -1;
@@ -253,7 +253,7 @@ __device__ __forceinline__ int4 load_counts4(const int* counts, int c, int n) {
 __global__ void __launch_bounds__(kScanThreads) k_scan_tiles(KArgs A) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
-  if (S.g.bin_blocks || S.g.bin_row_blocks) return;  // binned by another path
+  if (S.g.bin_blocks || S.g.bin_row_blocks || S.g.binr_blocks) return;  // binned by another path
   __shared__ int red[kScanThreads / kWave];
   const int n = S.g.n_cells;
   const int4 v = load_counts4(S.d.counts, blk * kScanTile + 4 * (int)threadIdx.x, n);
@@ -264,7 +264,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_tiles(KArgs A) {
 __global__ void __launch_bounds__(kScanThreads) k_scan_apply(KArgs A) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
-  if (S.g.bin_blocks || S.g.bin_row_blocks) return;
+  if (S.g.bin_blocks || S.g.bin_row_blocks || S.g.binr_blocks) return;
   __shared__ int red[kScanThreads / kWave];
   __shared__ int wsum[kScanThreads / kWave];
   int* __restrict__ counts = S.d.counts;
@@ -309,7 +309,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(KArgs A) {
 __global__ void k_bin_scatter(KArgs A) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
-  if (S.g.bin_blocks || S.g.bin_row_blocks) return;
+  if (S.g.bin_blocks || S.g.bin_row_blocks || S.g.binr_blocks) return;
   const int i = blk * blockDim.x + threadIdx.x;
   const bool active = i < S.g.n_atoms;
   const int* __restrict__ cell_of = S.d.cell_of;
@@ -347,7 +347,7 @@ __global__ void k_bin_place(KArgs A) {
   const SysDesc& S = sys_of(A, blk);
   const Geom& g = S.g;
   const int s = blk * blockDim.x + threadIdx.x;
-  if (s >= g.n_atoms || g.bin_blocks || g.bin_row_blocks) return;
+  if (s >= g.n_atoms || g.bin_blocks || g.bin_row_blocks || g.binr_blocks) return;
   const int* __restrict__ cell_of = S.d.cell_of;
   const int* __restrict__ start = S.d.cell_start;
   const int* __restrict__ tmp = S.d.tmp;
@@ -828,6 +828,316 @@ __global__ void __launch_bounds__(kBRThreads) k_bin_rows(KArgs A) {
     for (int v = 0; v < kBRWaves; ++v) f |= red[v];
     status[64 + blk] = f;
   }
+}
+
+// --------------------------------------------------------------------------
+// Link cells of a large system in four kernels, by cell row first: the cells
+// are numbered (cz ny + cy) nx + cx, so a cell row r = cz ny + cy is a
+// contiguous range of cells.
+//   k_binr_count   per block of kBinRChunk atoms: LDS counts of the rows, one
+//                  global add per row into counts[]
+//   k_binr_scan    row starts (exclusive scan of counts[]); clears counts[]
+//                  and the row cursors for the scatter and the next call
+//   k_binr_scatter the atoms into their row's segment (LDS counts give every
+//                  block a range per row; order inside it is arbitrary)
+//   k_binr_sort    one block per row: counting sort of the row's atoms by x
+//                  cell, each atom ranked in its cell by input index (the
+//                  order of the other binning paths), validation, the sorted
+//                  and box-clamped atoms and the row's cell starts.
+// The row starts live in the scan array.
+// --------------------------------------------------------------------------
+constexpr int kBRCThreads = 1024;
+constexpr int kBRCPer = kBinRChunk / kBRCThreads;
+constexpr int kBRSThreads = 256;
+static_assert(kBinRSortCap % kBRSThreads == 0 && kBinRSortCap <= kRankCap, "a cached row ranks every cell");
+static_assert(kBinRSortCap <= 65536 && kBinRowsMax <= 65536, "16-bit x cells and positions");
+
+__device__ __forceinline__ int cell_row(const Geom& g, float y, float z) {
+  return cell_coord(g, wrap_coord(g, z, 2), 2) * g.nc[1] + cell_coord(g, wrap_coord(g, y, 1), 1);
+}
+
+// Exclusive scan of a[0, n) in place by the block's NT threads (thread t
+// takes a contiguous run of ceil(n / NT) entries); returns the total.
+template <int NT>
+__device__ int block_exclusive_scan(int* a, int n, int* wsum) {
+  constexpr int NW = NT / kWave;
+  const int t = threadIdx.x, lane = t & (kWave - 1), wv = t / kWave;
+  const int per = (n + NT - 1) / NT;
+  const int b = min(t * per, n), e = min(b + per, n);
+  int own = 0;
+  for (int i = b; i < e; ++i) own += a[i];
+  int inc = own;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int u = __shfl_up(inc, off);
+    if (lane >= off) inc += u;
+  }
+  if (lane == kWave - 1) wsum[wv] = inc;
+  __syncthreads();
+  int run = inc - own, total = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const int v = wsum[w];
+    run += w < wv ? v : 0;
+    total += v;
+  }
+  for (int i = b; i < e; ++i) {
+    const int v = a[i];
+    a[i] = run;
+    run += v;
+  }
+  __syncthreads();
+  return total;
+}
+
+__global__ void __launch_bounds__(kBRCThreads) k_binr_count(KArgs A) {
+  int blk;
+  const SysDesc& S = sys_of(A, blk);
+  const Geom& g = S.g;
+  if (!g.binr_blocks) return;
+  __shared__ int hist[kBinRowsMax];
+  const int rows = g.nc[1] * g.nc[2];
+  for (int r = threadIdx.x; r < rows; r += kBRCThreads) hist[r] = 0;
+  __syncthreads();
+  const float* y = A.io.y + S.atom_off;
+  const float* z = A.io.z + S.atom_off;
+  const int i0 = blk * kBinRChunk;
+  float py[kBRCPer], pz[kBRCPer];
+#pragma unroll
+  for (int u = 0; u < kBRCPer; ++u) {
+    const int i = i0 + u * kBRCThreads + threadIdx.x;
+    py[u] = i < g.n_atoms ? y[i] : 0.f;
+    pz[u] = i < g.n_atoms ? z[i] : 0.f;
+  }
+#pragma unroll
+  for (int u = 0; u < kBRCPer; ++u)
+    if (i0 + u * kBRCThreads + (int)threadIdx.x < g.n_atoms) atomicAdd(&hist[cell_row(g, py[u], pz[u])], 1);
+  __syncthreads();
+  int* __restrict__ counts = S.d.counts;
+  for (int r = threadIdx.x; r < rows; r += kBRCThreads) {
+    const int c = hist[r];
+    if (c) atomicAdd(&counts[r], c);
+  }
+}
+
+__global__ void __launch_bounds__(kBRCThreads) k_binr_scan(KArgs A) {
+  int blk;
+  const SysDesc& S = sys_of(A, blk);
+  const Geom& g = S.g;
+  if (!g.binr_blocks) return;
+  __shared__ int wsum[kBRCThreads / kWave];
+  __shared__ int st[kBinRowsMax];
+  const int rows = g.nc[1] * g.nc[2];
+  int* __restrict__ counts = S.d.counts;
+  int* __restrict__ row_start = S.d.scan;
+  int* __restrict__ cursor = S.d.cursor;
+  for (int r = threadIdx.x; r < rows; r += kBRCThreads) {
+    st[r] = counts[r];
+    counts[r] = 0;
+    cursor[r] = 0;
+  }
+  if (threadIdx.x < 64) S.d.status[threadIdx.x] = 0;
+  __syncthreads();
+  const int total = block_exclusive_scan<kBRCThreads>(st, rows, wsum);
+  for (int r = threadIdx.x; r < rows; r += kBRCThreads) row_start[r] = st[r];
+  if (threadIdx.x == 0) {
+    row_start[rows] = total;
+    S.d.cell_start[g.n_cells] = total;
+  }
+}
+
+__global__ void __launch_bounds__(kBRCThreads) k_binr_scatter(KArgs A) {
+  int blk;
+  const SysDesc& S = sys_of(A, blk);
+  const Geom& g = S.g;
+  if (!g.binr_blocks) return;
+  __shared__ int hist[kBinRowsMax];
+  __shared__ int base[kBinRowsMax];
+  const int rows = g.nc[1] * g.nc[2];
+  for (int r = threadIdx.x; r < rows; r += kBRCThreads) hist[r] = 0;
+  __syncthreads();
+  const float* x = A.io.x + S.atom_off;
+  const float* y = A.io.y + S.atom_off;
+  const float* z = A.io.z + S.atom_off;
+  const float* q = A.io.q + S.atom_off;
+  const int i0 = blk * kBinRChunk;
+  float4 p[kBRCPer];
+  int rr[kBRCPer];
+#pragma unroll
+  for (int u = 0; u < kBRCPer; ++u) {
+    const int i = i0 + u * kBRCThreads + threadIdx.x;
+    p[u] = i < g.n_atoms ? make_float4(x[i], y[i], z[i], q[i]) : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+#pragma unroll
+  for (int u = 0; u < kBRCPer; ++u) {
+    const int i = i0 + u * kBRCThreads + threadIdx.x;
+    rr[u] = -1;
+    if (i < g.n_atoms) {
+      rr[u] = cell_row(g, p[u].y, p[u].z);
+      atomicAdd(&hist[rr[u]], 1);
+    }
+  }
+  __syncthreads();
+  // this block's range in every row it touches, then its counts become cursors
+  const int* __restrict__ row_start = S.d.scan;
+  int* __restrict__ cursor = S.d.cursor;
+  for (int r = threadIdx.x; r < rows; r += kBRCThreads) {
+    const int c = hist[r];
+    if (c) base[r] = row_start[r] + atomicAdd(&cursor[r], c);
+    hist[r] = 0;
+  }
+  __syncthreads();
+  int* __restrict__ tmp = S.d.tmp;
+  float4* __restrict__ tmp4 = S.d.fshort;   // coordinate copies until k_binr_sort
+#pragma unroll
+  for (int u = 0; u < kBRCPer; ++u)
+    if (rr[u] >= 0) {
+      const int slot = base[rr[u]] + atomicAdd(&hist[rr[u]], 1);
+      if ((unsigned)slot < (unsigned)g.n_atoms) {         // only a corrupted workspace fails this
+        tmp[slot] = i0 + u * kBRCThreads + threadIdx.x;
+        tmp4[slot] = p[u];
+      }
+    }
+}
+
+__global__ void __launch_bounds__(kBRSThreads) k_binr_sort(KArgs A) {
+  int blk;
+  const SysDesc& S = sys_of(A, blk);
+  const Geom& g = S.g;
+  if (!g.binr_blocks) return;
+  extern __shared__ int lds[];
+  __shared__ int wsum[kBRSThreads / kWave];
+  __shared__ int bflags;
+  const int nx = g.nc[0], n = g.n_atoms;
+  const int ints = (2 * (nx + 1) + 3) & ~3;
+  int* lstart = lds;                                   // [nx + 1] x-cell counts, then starts
+  int* lcur = lds + nx + 1;                            // [nx + 1] cursors of the bucket fill
+  // a row of at most kBinRSortCap atoms, in bucket (x cell) order
+  float4* bpos = reinterpret_cast<float4*>(lds + ints);                 // [cap] coordinates and charge
+  int* bid = reinterpret_cast<int*>(bpos + kBinRSortCap);               // [cap] input indices
+  unsigned short* bcx = reinterpret_cast<unsigned short*>(bid + kBinRSortCap);   // [cap] x cells
+  const int* __restrict__ row_start = S.d.scan;
+  const int* __restrict__ tmp = S.d.tmp;
+  const float4* __restrict__ tmp4 = S.d.fshort;
+  int* __restrict__ gord = S.d.cell_of;                // bucket order of a row too long for the LDS
+  const int r = blk;
+  const int rs = row_start[r], re = row_start[r + 1];
+  if (rs < 0 || re < rs || re > n) return;             // only a corrupted workspace gets here
+  const int cnt = re - rs;
+  const bool cached = cnt <= kBinRSortCap;
+  constexpr int kPer = kBinRSortCap / kBRSThreads;     // atoms per thread of a cached row
+  for (int c = threadIdx.x; c <= nx; c += kBRSThreads) {
+    lstart[c] = 0;
+    lcur[c] = 0;
+  }
+  if (threadIdx.x == 0) bflags = 0;
+  auto xcell = [&](const float4& p) { return cell_coord(g, wrap_coord(g, p.x, 0), 0); };
+  // a cached row's atoms stay in registers until the bucket fill
+  float4 mp[kPer];
+  int mid[kPer], mcx[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int t = u * kBRSThreads + threadIdx.x;
+    mcx[u] = -1;
+    if (cached && t < cnt) {
+      mp[u] = tmp4[rs + t];
+      mid[u] = tmp[rs + t];
+      mcx[u] = xcell(mp[u]);
+    }
+  }
+  __syncthreads();
+  if (cached) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u)
+      if (mcx[u] >= 0) atomicAdd(&lstart[mcx[u]], 1);
+  } else {
+    for (int t = threadIdx.x; t < cnt; t += kBRSThreads) atomicAdd(&lstart[xcell(tmp4[rs + t])], 1);
+  }
+  __syncthreads();
+  block_exclusive_scan<kBRSThreads>(lstart, nx, wsum);
+  if (threadIdx.x == 0) lstart[nx] = cnt;
+  __syncthreads();
+  int* __restrict__ cell_start = S.d.cell_start;
+  for (int c = threadIdx.x; c < nx; c += kBRSThreads) cell_start[r * nx + c] = rs + lstart[c];
+  // the output of one atom at its final slot
+  int flags = 0;
+  float4* __restrict__ sorted = S.d.sorted;
+  int* __restrict__ perm = S.d.perm;
+  auto place = [&](const float4& p, int i, int dst) {
+    if (!(isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(p.w))) {
+      flags |= kFlagNonFinite;
+    } else if (!g.periodic) {
+      const double pd[3] = {(double)p.x, (double)p.y, (double)p.z};
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        if (pd[d] < g.lo[d] || pd[d] > g.hi[d]) flags |= kFlagOutOfBox;
+    }
+    float4 o;
+    o.x = fminf(fmaxf(wrap_coord(g, p.x, 0), g.lo_f[0]), (float)g.hi[0]);
+    o.y = fminf(fmaxf(wrap_coord(g, p.y, 1), g.lo_f[1]), (float)g.hi[1]);
+    o.z = fminf(fmaxf(wrap_coord(g, p.z, 2), g.lo_f[2]), (float)g.hi[2]);
+    o.w = isfinite(p.w) ? p.w : 0.f;
+    sorted[dst] = o;
+    perm[dst] = i;
+  };
+  if (cached) {
+    // buckets by x cell (arrival order), then every atom ranked by input
+    // index among its cell's members (contiguous in LDS); coincident atoms
+    // share a cell.  A cached row is shorter than kRankCap.
+#pragma unroll
+    for (int u = 0; u < kPer; ++u)
+      if (mcx[u] >= 0) {
+        const int slot = lstart[mcx[u]] + atomicAdd(&lcur[mcx[u]], 1);
+        bpos[slot] = mp[u];
+        bid[slot] = mid[u];
+        bcx[slot] = (unsigned short)mcx[u];
+      }
+    __syncthreads();
+    for (int k = threadIdx.x; k < cnt; k += kBRSThreads) {
+      const int cx = bcx[k], b = lstart[cx], e = lstart[cx + 1];
+      const int i = bid[k];
+      const float4 p = bpos[k];
+      int rank = 0;
+      for (int k2 = b; k2 < e; ++k2) {
+        rank += (bid[k2] < i);
+        const float4 o = bpos[k2];
+        if (k2 != k && o.x == p.x && o.y == p.y && o.z == p.z) flags |= kFlagCoincident;
+      }
+      place(p, i, rs + b + rank);
+    }
+  } else {
+    // a long row: bucket order as row positions in global scratch; an atom
+    // of a cell longer than kRankCap stays at its arrival slot (as in the
+    // four kernels over the cells)
+    for (int t = threadIdx.x; t < cnt; t += kBRSThreads) {
+      const float4 p = tmp4[rs + t];
+      const int cx = xcell(p);
+      const int slot = lstart[cx] + atomicAdd(&lcur[cx], 1);
+      gord[rs + slot] = t;
+      if (lstart[cx + 1] - lstart[cx] > kRankCap) place(p, tmp[rs + t], rs + slot);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < cnt; t += kBRSThreads) {
+      const float4 p = tmp4[rs + t];
+      const int i = tmp[rs + t];
+      const int cx = xcell(p);
+      const int b = lstart[cx], e = lstart[cx + 1];
+      if (e - b > kRankCap) continue;
+      int rank = 0;
+      for (int k = b; k < e; ++k) {
+        const int u = gord[rs + k];
+        rank += (tmp[rs + u] < i);
+        if (u != t) {
+          const float4 o = tmp4[rs + u];
+          if (o.x == p.x && o.y == p.y && o.z == p.z) flags |= kFlagCoincident;
+        }
+      }
+      place(p, i, rs + b + rank);
+    }
+  }
+  if (flags) atomicOr(&bflags, flags);
+  __syncthreads();
+  if (threadIdx.x == 0 && bflags) atomicOr(S.d.status, bflags);
 }
 
 // --------------------------------------------------------------------------
@@ -2672,7 +2982,11 @@ int interp_partials(const Geom& g) { return std::max(1, blocks_for(g.n_atoms)); 
 SysBlocks system_blocks(const Geom& g, const LatLaunch& lat, int n_partials) {
   SysBlocks b{};
   b.zero = blocks_for(g.max_cells + 1);
-  b.scan = (g.bin_blocks == 0 && g.bin_row_blocks == 0) ? (g.n_cells + kScanTile - 1) / kScanTile : 0;
+  b.scan = (g.bin_blocks == 0 && g.bin_row_blocks == 0 && g.binr_blocks == 0)
+               ? (g.n_cells + kScanTile - 1) / kScanTile : 0;
+  b.rchunk = g.binr_blocks;
+  b.rscan = g.binr_blocks > 0 ? 1 : 0;
+  b.rsort = g.binr_blocks > 0 ? g.nc[1] * g.nc[2] : 0;
   b.atoms = g.n_atoms > 0 ? blocks_for(g.n_atoms) : 0;
   b.bin = g.bin_blocks;
   b.binrow = g.bin_row_blocks;
@@ -2777,6 +3091,13 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
   if (L.binrow.blocks > 0) {
     (void)hipFuncSetAttribute((const void*)k_bin_rows, hipFuncAttributeMaxDynamicSharedMemorySize, L.binrow_lds);
     k_bin_rows<<<L.binrow.blocks, kBRThreads, L.binrow_lds, s>>>(args(L.binrow));
+  }
+  if (L.rchunk.blocks > 0) {
+    k_binr_count<<<L.rchunk.blocks, kBRCThreads, 0, s>>>(args(L.rchunk));
+    k_binr_scan<<<L.rscan.blocks, kBRCThreads, 0, s>>>(args(L.rscan));
+    k_binr_scatter<<<L.rchunk.blocks, kBRCThreads, 0, s>>>(args(L.rchunk));
+    (void)hipFuncSetAttribute((const void*)k_binr_sort, hipFuncAttributeMaxDynamicSharedMemorySize, L.rsort_lds);
+    k_binr_sort<<<L.rsort.blocks, kBRSThreads, L.rsort_lds, s>>>(args(L.rsort));
   }
   end(kStageBin, s);
 
