@@ -148,7 +148,8 @@ __global__ void k_zero_counts(KArgs A) {
   if (i <= S.g.max_cells) S.d.counts[i] = 0;
 }
 
-__device__ __forceinline__ int cell_coord(const Geom& g, float p, int d) {
+template <class G>
+__device__ __forceinline__ int cell_coord(const G& g, float p, int d) {
   float t = (p - g.lo_f[d]) * g.inv_cs[d];
   t = fminf(fmaxf(t, 0.f), (float)(g.nc[d] - 1));   // NaN -> 0
   return min((int)t, g.nc[d] - 1);
@@ -159,7 +160,8 @@ __device__ __forceinline__ int cell_coord(const Geom& g, float p, int d) {
 // rounded once (an atom inside the box keeps its coordinate; the result may
 // round up to lo + len, which the cell and grid clamps absorb); free space
 // keeps it.
-__device__ __forceinline__ float wrap_coord(const Geom& g, float p, int d) {
+template <class G>
+__device__ __forceinline__ float wrap_coord(const G& g, float p, int d) {
   if (!g.periodic) return p;
   const double t = (double)p - g.lo[d];
   return (float)(g.lo[d] + (t - g.len[d] * floor(t / g.len[d])));
@@ -953,7 +955,7 @@ __global__ void __launch_bounds__(kBRCThreads) k_binr_scatter(KArgs A) {
   if (!g.binr_blocks) return;
   __shared__ int hist[kBinRowsMax];
   __shared__ int base[kBinRowsMax];
-  const int rows = g.nc[1] * g.nc[2];
+  const int rows = g.nc[1] * g.nc[2], n = g.n_atoms;
   for (int r = threadIdx.x; r < rows; r += kBRCThreads) hist[r] = 0;
   __syncthreads();
   const float* x = A.io.x + S.atom_off;
@@ -993,22 +995,69 @@ __global__ void __launch_bounds__(kBRCThreads) k_binr_scatter(KArgs A) {
   for (int u = 0; u < kBRCPer; ++u)
     if (rr[u] >= 0) {
       const int slot = base[rr[u]] + atomicAdd(&hist[rr[u]], 1);
-      if ((unsigned)slot < (unsigned)g.n_atoms) {         // only a corrupted workspace fails this
+      if ((unsigned)slot < (unsigned)n) {                 // only a corrupted workspace fails this
         tmp[slot] = i0 + u * kBRCThreads + threadIdx.x;
         tmp4[slot] = p[u];
       }
     }
 }
 
+// The binning geometry in registers: kernels that store to global memory in
+// a loop would otherwise reload every descriptor field after each store (the
+// compiler cannot rule out that the store changed it).
+struct BinGeo {
+  float lo_f[3], inv_cs[3];
+  double lo[3], hi[3], len[3];
+  int nc[3];
+  int periodic;
+};
+
+__device__ __forceinline__ BinGeo bin_geo(const Geom& s) {
+  BinGeo b;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    b.lo_f[d] = s.lo_f[d];
+    b.inv_cs[d] = s.inv_cs[d];
+    b.lo[d] = s.lo[d];
+    b.hi[d] = s.hi[d];
+    b.len[d] = s.len[d];
+    b.nc[d] = s.nc[d];
+  }
+  b.periodic = s.periodic;
+  return b;
+}
+
+// One validated, box-clamped atom of the row binning at its final slot;
+// returns its validation flags.
+__device__ __forceinline__ int binr_place(const BinGeo& g, const float4 p, int i, int dst, float4* sorted, int* perm) {
+  int flags = 0;
+  if (!(isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(p.w))) {
+    flags |= kFlagNonFinite;
+  } else if (!g.periodic) {
+    const double pd[3] = {(double)p.x, (double)p.y, (double)p.z};
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      if (pd[d] < g.lo[d] || pd[d] > g.hi[d]) flags |= kFlagOutOfBox;
+  }
+  float4 o;
+  o.x = fminf(fmaxf(wrap_coord(g, p.x, 0), g.lo_f[0]), (float)g.hi[0]);
+  o.y = fminf(fmaxf(wrap_coord(g, p.y, 1), g.lo_f[1]), (float)g.hi[1]);
+  o.z = fminf(fmaxf(wrap_coord(g, p.z, 2), g.lo_f[2]), (float)g.hi[2]);
+  o.w = isfinite(p.w) ? p.w : 0.f;
+  sorted[dst] = o;
+  perm[dst] = i;
+  return flags;
+}
+
 __global__ void __launch_bounds__(kBRSThreads) k_binr_sort(KArgs A) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
-  const Geom& g = S.g;
-  if (!g.binr_blocks) return;
+  if (!S.g.binr_blocks) return;
+  const BinGeo g = bin_geo(S.g);
   extern __shared__ int lds[];
   __shared__ int wsum[kBRSThreads / kWave];
   __shared__ int bflags;
-  const int nx = g.nc[0], n = g.n_atoms;
+  const int nx = g.nc[0], n = S.g.n_atoms;
   const int ints = (2 * (nx + 1) + 3) & ~3;
   int* lstart = lds;                                   // [nx + 1] x-cell counts, then starts
   int* lcur = lds + nx + 1;                            // [nx + 1] cursors of the bucket fill
@@ -1031,7 +1080,6 @@ __global__ void __launch_bounds__(kBRSThreads) k_binr_sort(KArgs A) {
     lcur[c] = 0;
   }
   if (threadIdx.x == 0) bflags = 0;
-  auto xcell = [&](const float4& p) { return cell_coord(g, wrap_coord(g, p.x, 0), 0); };
   // a cached row's atoms stay in registers until the bucket fill
   float4 mp[kPer];
   int mid[kPer], mcx[kPer];
@@ -1039,10 +1087,12 @@ __global__ void __launch_bounds__(kBRSThreads) k_binr_sort(KArgs A) {
   for (int u = 0; u < kPer; ++u) {
     const int t = u * kBRSThreads + threadIdx.x;
     mcx[u] = -1;
+    mp[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+    mid[u] = 0;
     if (cached && t < cnt) {
       mp[u] = tmp4[rs + t];
       mid[u] = tmp[rs + t];
-      mcx[u] = xcell(mp[u]);
+      mcx[u] = cell_coord(g, wrap_coord(g, mp[u].x, 0), 0);
     }
   }
   __syncthreads();
@@ -1051,7 +1101,7 @@ __global__ void __launch_bounds__(kBRSThreads) k_binr_sort(KArgs A) {
     for (int u = 0; u < kPer; ++u)
       if (mcx[u] >= 0) atomicAdd(&lstart[mcx[u]], 1);
   } else {
-    for (int t = threadIdx.x; t < cnt; t += kBRSThreads) atomicAdd(&lstart[xcell(tmp4[rs + t])], 1);
+    for (int t = threadIdx.x; t < cnt; t += kBRSThreads) atomicAdd(&lstart[cell_coord(g, wrap_coord(g, tmp4[rs + t].x, 0), 0)], 1);
   }
   __syncthreads();
   block_exclusive_scan<kBRSThreads>(lstart, nx, wsum);
@@ -1059,27 +1109,9 @@ __global__ void __launch_bounds__(kBRSThreads) k_binr_sort(KArgs A) {
   __syncthreads();
   int* __restrict__ cell_start = S.d.cell_start;
   for (int c = threadIdx.x; c < nx; c += kBRSThreads) cell_start[r * nx + c] = rs + lstart[c];
-  // the output of one atom at its final slot
   int flags = 0;
   float4* __restrict__ sorted = S.d.sorted;
   int* __restrict__ perm = S.d.perm;
-  auto place = [&](const float4& p, int i, int dst) {
-    if (!(isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(p.w))) {
-      flags |= kFlagNonFinite;
-    } else if (!g.periodic) {
-      const double pd[3] = {(double)p.x, (double)p.y, (double)p.z};
-#pragma unroll
-      for (int d = 0; d < 3; ++d)
-        if (pd[d] < g.lo[d] || pd[d] > g.hi[d]) flags |= kFlagOutOfBox;
-    }
-    float4 o;
-    o.x = fminf(fmaxf(wrap_coord(g, p.x, 0), g.lo_f[0]), (float)g.hi[0]);
-    o.y = fminf(fmaxf(wrap_coord(g, p.y, 1), g.lo_f[1]), (float)g.hi[1]);
-    o.z = fminf(fmaxf(wrap_coord(g, p.z, 2), g.lo_f[2]), (float)g.hi[2]);
-    o.w = isfinite(p.w) ? p.w : 0.f;
-    sorted[dst] = o;
-    perm[dst] = i;
-  };
   if (cached) {
     // buckets by x cell (arrival order), then every atom ranked by input
     // index among its cell's members (contiguous in LDS); coincident atoms
@@ -1103,7 +1135,7 @@ __global__ void __launch_bounds__(kBRSThreads) k_binr_sort(KArgs A) {
         const float4 o = bpos[k2];
         if (k2 != k && o.x == p.x && o.y == p.y && o.z == p.z) flags |= kFlagCoincident;
       }
-      place(p, i, rs + b + rank);
+      flags |= binr_place(g, p, i, rs + b + rank, sorted, perm);
     }
   } else {
     // a long row: bucket order as row positions in global scratch; an atom
@@ -1111,16 +1143,16 @@ __global__ void __launch_bounds__(kBRSThreads) k_binr_sort(KArgs A) {
     // four kernels over the cells)
     for (int t = threadIdx.x; t < cnt; t += kBRSThreads) {
       const float4 p = tmp4[rs + t];
-      const int cx = xcell(p);
+      const int cx = cell_coord(g, wrap_coord(g, p.x, 0), 0);
       const int slot = lstart[cx] + atomicAdd(&lcur[cx], 1);
       gord[rs + slot] = t;
-      if (lstart[cx + 1] - lstart[cx] > kRankCap) place(p, tmp[rs + t], rs + slot);
+      if (lstart[cx + 1] - lstart[cx] > kRankCap) flags |= binr_place(g, p, tmp[rs + t], rs + slot, sorted, perm);
     }
     __syncthreads();
     for (int t = threadIdx.x; t < cnt; t += kBRSThreads) {
       const float4 p = tmp4[rs + t];
       const int i = tmp[rs + t];
-      const int cx = xcell(p);
+      const int cx = cell_coord(g, wrap_coord(g, p.x, 0), 0);
       const int b = lstart[cx], e = lstart[cx + 1];
       if (e - b > kRankCap) continue;
       int rank = 0;
@@ -1132,7 +1164,7 @@ __global__ void __launch_bounds__(kBRSThreads) k_binr_sort(KArgs A) {
           if (o.x == p.x && o.y == p.y && o.z == p.z) flags |= kFlagCoincident;
         }
       }
-      place(p, i, rs + b + rank);
+      flags |= binr_place(g, p, i, rs + b + rank, sorted, perm);
     }
   }
   if (flags) atomicOr(&bflags, flags);
@@ -1652,7 +1684,7 @@ __global__ void __launch_bounds__(kAThreads) k_anterp(KArgs A) {
         // instruction serialise; the integer sums do not depend on order)
         anterp_scatter<ORDER>(g, queue[spread(threadIdx.x)], n0, T, ex, ey, acc);
         const int rest = total - kAThreads;
-        const float4 v = (int)threadIdx.x < rest ? queue[kAThreads + threadIdx.x] : p;
+        const float4 v = (int)threadIdx.x < rest ? queue[kAThreads + threadIdx.x] : make_float4(0.f, 0.f, 0.f, 0.f);
         __syncthreads();
         if ((int)threadIdx.x < rest) queue[threadIdx.x] = v;
         total = rest;
