@@ -28,6 +28,8 @@ constexpr int kBinRSortCap = 1024;        // atoms of a cell row the row binning
 constexpr int kBinRowCells = 512;         // cells one block of the one-kernel binning owns at most
 constexpr int kBinRowMaxBlocks = 256;     // blocks of the one-kernel binning per system at most
 constexpr int kStatusWords = 64 + kBinRowMaxBlocks;   // [0]: flags; [64 + b]: flags of binning block b
+constexpr int kStatusUnranked = 1;        // status word: some cell kept its scatter order (not checked for
+                                          // coincident atoms by binning)
 constexpr int kScanTile = 4096;           // cells per block of the four-kernel binning's scan
 constexpr int kXcds = 8;                  // accelerator dies of the chip, each with its own L2
 constexpr int kProlongSplitTiles = 1000;  // level-0 prolongation tiles from which each level gets its own launch

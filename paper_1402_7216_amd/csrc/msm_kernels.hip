@@ -372,6 +372,7 @@ __global__ void k_bin_place(KArgs A) {
       if (!g.periodic && (pd[d] < g.lo[d] || pd[d] > g.hi[d])) flags |= kFlagOutOfBox;
   }
   int dst = s;
+  if (s == b && e - b > kRankCap) atomicOr(status + kStatusUnranked, 1);
   if (0 <= b && b <= e && e <= g.n_atoms && e - b <= kRankCap) {
     int rank = 0;
 #pragma unroll 4
@@ -1146,7 +1147,10 @@ __global__ void __launch_bounds__(kBRSThreads) k_binr_sort(KArgs A) {
       const int cx = cell_coord(g, wrap_coord(g, p.x, 0), 0);
       const int slot = lstart[cx] + atomicAdd(&lcur[cx], 1);
       gord[rs + slot] = t;
-      if (lstart[cx + 1] - lstart[cx] > kRankCap) flags |= binr_place(g, p, tmp[rs + t], rs + slot, sorted, perm);
+      if (lstart[cx + 1] - lstart[cx] > kRankCap) {
+        flags |= binr_place(g, p, tmp[rs + t], rs + slot, sorted, perm);
+        if (slot == lstart[cx]) atomicOr(S.d.status + kStatusUnranked, 1);
+      }
     }
     __syncthreads();
     for (int t = threadIdx.x; t < cnt; t += kBRSThreads) {
@@ -1301,7 +1305,14 @@ __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, 
     pk[k] = v;
   }
   float4* jb = jbuf[wave];
-  const int R = g.reach, side = 2 * R + 1, centre = (side * side) / 2;
+  const int R = g.reach, side = 2 * R + 1;
+  // coincident atoms: the one- and two-kernel binnings leave them to this
+  // pass, and so does every periodic plan (atoms one box edge apart coincide
+  // once wrapped, which binning's comparison of the inputs does not see); the
+  // other binnings compare the atoms of each cell themselves, except in cells
+  // longer than kRankCap (status word 1 then set)
+  const bool coin = PER || g.bin_blocks || g.bin_row_blocks || S.d.status[kStatusUnranked] != 0;
+  const int centre = coin ? (side * side) / 2 : -1;
   // the launch has g.short_blocks blocks; work items are strided over them
   const int item_lo = (int)((long long)n_items * lo_pm / 1000);
   const int item_hi = (int)((long long)n_items * hi_pm / 1000);

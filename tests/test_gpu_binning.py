@@ -217,3 +217,20 @@ def test_cells_longer_than_the_rank_cap_keep_every_atom(M):
     small = counts[cells[perm]] <= 2048
     order = np.argsort(cells, kind="stable")
     assert np.array_equal(perm[small], order[small])
+
+
+def test_coincident_atoms_in_a_cell_over_the_rank_cap_are_flagged(M):
+    """Binning leaves a cell of more than 2048 atoms unchecked; the short-range
+    pass then checks it, so coincident atoms there are still reported."""
+    s = rod(60000, seed=17, width=1.0, length=20.0)
+    print(f"case coincident rod60k n={s.n}", flush=True)
+    plan = M.plan_for(s)
+    assert path_of(plan.describe()) == "rows"
+    x, y, z, q = M.to_device(s)
+    xb, yb, zb = x.clone(), y.clone(), z.clone()
+    j, k = 10, 31001
+    xb[k], yb[k], zb[k] = x[j], y[j], z[j]
+    plan.compute(xb, yb, zb, q)
+    assert plan.status()[0] == M.ERR_COINCIDENT
+    plan.compute(x, y, z, q)
+    assert plan.status()[0] == 0
