@@ -1598,10 +1598,53 @@ __device__ __forceinline__ void anterp_scatter(const Geom& g, const float4 p, co
   }
 }
 
-// Queue entry of thread t in a scatter round: t with its 8 bits reversed (a
-// bijection of [0, 256)).
-static_assert(kAThreads == 256, "spread() permutes 8-bit thread indices");
-__device__ __forceinline__ int spread(unsigned t) { return (int)(__builtin_bitreverse32(t) >> 24); }
+static_assert(kAThreads == 256, "bank_order() deals 256 entries to 8 half-waves");
+
+// The queue entry thread t takes in a scatter round of `count` entries (-1:
+// none).  The entries are sorted by the LDS bank pair of their region corner
+// (corner node mod 32: a 64-bit accumulator spans two of the 64 banks) and
+// dealt so that the 32 lanes of a half-wave take entries about count/32
+// apart in that order, mostly one per bank pair: every atomic of the
+// half-wave then hits distinct banks, and atoms with the same corner (same
+// addresses) fall in different instructions.  Any order gives the same
+// integer sums.
+template <int ORDER>
+__device__ __forceinline__ int bank_order(const Geom& g, const float4* queue, int count, const int* n0, int ex,
+                                          int ey, int* bcount, unsigned short* border) {
+  const int t = threadIdx.x;
+  if (t < 32) bcount[t] = 0;
+  __syncthreads();
+  int bucket = -1, pos = 0;
+  if (t < count) {
+    const float4 p = queue[t];
+    const float pp[3] = {p.x, p.y, p.z};
+    int f[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      float r;
+      grid_coord(pp[d], g.lo_f[d], g.h, g.inv_h, g.fmax[d], f[d], r);
+      f[d] -= n0[d];
+    }
+    bucket = ((f[2] * ey + f[1]) * ex + f[0]) & 31;
+    pos = atomicAdd(&bcount[bucket], 1);
+  }
+  __syncthreads();
+  if (t < kWave) {                                      // exclusive scan of the 32 bucket sizes
+    const int v = t < 32 ? bcount[t] : 0;
+    int inc = v;
+#pragma unroll
+    for (int off = 1; off < 32; off <<= 1) {
+      const int u = __shfl_up(inc, off);
+      if (t >= off) inc += u;
+    }
+    if (t < 32) bcount[t] = inc - v;
+  }
+  __syncthreads();
+  if (bucket >= 0) border[bcount[bucket] + pos] = (unsigned short)t;
+  __syncthreads();
+  const int j = (t & 31) * (kAThreads / 32) + (t >> 5);
+  return j < count ? (int)border[j] : -1;
+}
 
 template <int ORDER>
 __global__ void __launch_bounds__(kAThreads) k_anterp(KArgs A) {
@@ -1616,6 +1659,8 @@ __global__ void __launch_bounds__(kAThreads) k_anterp(KArgs A) {
   // there, so the scatter runs with every lane busy (about a third of the
   // candidates lie in the margin cells and belong to other tiles)
   __shared__ float4 queue[2 * kAThreads];
+  __shared__ int bcount[32];
+  __shared__ unsigned short border[kAThreads];
   __shared__ int wcount[kAThreads / kWave];
   __shared__ int qlen;
   if (threadIdx.x == 0) qlen = 0;
@@ -1688,12 +1733,10 @@ __global__ void __launch_bounds__(kAThreads) k_anterp(KArgs A) {
       if (own) queue[base + __popcll(m & ((1ull << lane) - 1))] = p;
       __syncthreads();
       if (total >= kAThreads) {
-        // a full round: one queued atom per thread, then the rest to the front.
-        // Thread t takes entry bitrev(t): the queue is in cell order, and
-        // neighbouring atoms hit the same nodes, so consecutive lanes take
-        // atoms far apart in the queue (same-address atomics of one wave
-        // instruction serialise; the integer sums do not depend on order)
-        anterp_scatter<ORDER>(g, queue[spread(threadIdx.x)], n0, T, ex, ey, acc);
+        // a full round: one queued atom per thread (in bank order), then the
+        // rest to the front
+        const int e = bank_order<ORDER>(g, queue, kAThreads, n0, ex, ey, bcount, border);
+        anterp_scatter<ORDER>(g, queue[e], n0, T, ex, ey, acc);
         const int rest = total - kAThreads;
         const float4 v = (int)threadIdx.x < rest ? queue[kAThreads + threadIdx.x] : make_float4(0.f, 0.f, 0.f, 0.f);
         __syncthreads();
@@ -1704,7 +1747,10 @@ __global__ void __launch_bounds__(kAThreads) k_anterp(KArgs A) {
       __syncthreads();
     }
   }
-  if (spread(threadIdx.x) < qlen) anterp_scatter<ORDER>(g, queue[spread(threadIdx.x)], n0, T, ex, ey, acc);
+  {
+    const int e = bank_order<ORDER>(g, queue, qlen, n0, ex, ey, bcount, border);
+    if (e >= 0) anterp_scatter<ORDER>(g, queue[e], n0, T, ex, ey, acc);
+  }
   __syncthreads();
   long long* __restrict__ out = S.d.ant_part + (size_t)blk * ext;
   for (int i = threadIdx.x; i < ext; i += kAThreads) out[i] = (long long)acc[i];
