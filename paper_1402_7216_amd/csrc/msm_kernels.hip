@@ -2219,29 +2219,41 @@ __global__ void __launch_bounds__(kLatThreads, B <= 6 ? 8 : 4) k_lattice_win(KAr
 
   for (int i = threadIdx.x; i < P.n_rows; i += kLatThreads) rows[i] = rows_g[i];
   for (int i = threadIdx.x; i < P.n_wc; i += kLatThreads) wc[i] = wc_g[i];
-  const int nwin = WZ * PY * WX;                       // < 2^16 (bounded by the LDS budget)
-  const float inv_wx = 1.f / (float)WX, inv_py = 1.f / (float)PY;
-  for (int i0 = 0; i0 < nwin; i0 += 8 * kLatThreads) {      // 8 loads in flight per thread
-    float v[8];
-    int dst[8];
+  // the window in runs of 4 consecutive x (index arithmetic and the y, z
+  // bounds once per run), 2 runs per thread at a time: 8 loads in flight
+  const int WXq = (WX + 3) >> 2;
+  const int nq = WZ * PY * WXq;                        // < 2^16 (bounded by the LDS budget)
+  const float inv_wq = 1.f / (float)WXq, inv_py = 1.f / (float)PY;
+  for (int i0 = 0; i0 < nq; i0 += 2 * kLatThreads) {
+    float v[2][4];
+    int dst[2], nx4[2];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 2; ++u) {
       const int i = i0 + u * kLatThreads + threadIdx.x;
-      v[u] = 0.f;
       dst[u] = -1;
-      if (i < nwin) {
-        int xx, yy;
-        const int r = fdiv(i, WX, inv_wx, xx);
-        const int zz = fdiv(r, PY, inv_py, yy);
+      nx4[u] = 0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[u][e] = 0.f;
+      if (i < nq) {
+        int xq, yy;
+        const int zz = fdiv(fdiv(i, WXq, inv_wq, xq), PY, inv_py, yy);
+        const int xx = 4 * xq;
         dst[u] = zz * PP + yy * PX + xx;
+        nx4[u] = min(4, WX - xx);
         const int gx = x0 - H + xx, gy = y0 - H + yy, gz = z0 + nz_lo + zz;
-        if (gx >= 0 && gx < NX && gy >= 0 && gy < NY && gz >= 0 && gz < NZ)
-          v[u] = qk[((size_t)gz * NY + gy) * NX + gx];
+        if (gy >= 0 && gy < NY && gz >= 0 && gz < NZ) {
+          const float* src = qk + ((size_t)gz * NY + gy) * NX;
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (e < nx4[u] && gx + e >= 0 && gx + e < NX) v[u][e] = src[gx + e];
+        }
       }
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (dst[u] >= 0) win[dst[u]] = v[u];
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (dst[u] >= 0 && e < nx4[u]) win[dst[u] + e] = v[u][e];
   }
   __syncthreads();
 
