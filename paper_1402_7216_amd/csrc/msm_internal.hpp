@@ -12,8 +12,8 @@
 namespace msm {
 
 constexpr int kMaxLevels = 12;
-constexpr int kShortWaves = 16;          // waves of a short-range block (they split the neighbour rows)
-constexpr int kShortRowsPerWave = 8;     // neighbour rows one wave can take
+constexpr int kShortWaves = 8;           // waves of a short-range block (they split the neighbour rows)
+constexpr int kShortRowsPerWave = 16;    // neighbour rows one wave can take
 constexpr int kMaxOrder = 6;
 constexpr int kMaxTopNodes = 1 << 17;     // all-pairs FP64 top level stays below ~1e10 pair terms
 constexpr int kRankCap = 2048;            // cells longer than this keep scatter order (see bin_place)
