@@ -1265,7 +1265,7 @@ constexpr float binom_half(int j) {
 // the atoms of a wrapped image staged shifted by the box edges); a template
 // flag so the free-space kernel keeps its registers.
 template <int M, bool FORCES, int KIND, bool PER>
-// Two blocks per CU: 8 waves per SIMD, so at most 64 registers per lane.
+// Four blocks per CU: 8 waves per SIMD, so at most 64 registers per lane.
 __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, int hi_pm) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
