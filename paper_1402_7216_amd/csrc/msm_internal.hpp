@@ -119,7 +119,7 @@ struct LatTile {
 
 constexpr int kLatMaxHalo = 16;          // windowed kernel handles stencil half-widths up to this
 constexpr int kLatMaxLds = 150 * 1024;   // LDS budget of one windowed block (bytes)
-constexpr int kLatWavesReduce = 16;      // waves per windowed block (their totals meet in LDS)
+constexpr int kLatWavesReduce = 8;       // waves per windowed block (their totals meet in LDS)
 constexpr int kLatMaxGroups = 8;         // row groups per tile
 
 struct LatLaunch {

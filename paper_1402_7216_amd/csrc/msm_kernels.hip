@@ -2120,7 +2120,7 @@ __global__ void __launch_bounds__(kBlock) k_lattice(KArgs A, int part) {
 // (nz, +ny), (nz, -ny) are processed together by adding their inputs first
 // (one FMA chain for both).
 // --------------------------------------------------------------------------
-constexpr int kLatThreads = 1024;
+constexpr int kLatThreads = kLatWavesReduce * kWave;
 constexpr int kLatWaves = kLatThreads / kWave;
 
 template <int B, int XR, bool PAIR>
