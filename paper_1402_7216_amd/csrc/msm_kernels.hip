@@ -2112,7 +2112,7 @@ __global__ void __launch_bounds__(kBlock) k_lattice(KArgs A, int part) {
 // tile of one level: xl lanes along x (B consecutive outputs each, kept in
 // registers), ty along y, tz along z.  The block stages its whole input
 // window ((tz + 2H) x (ty + 2H) x (xl B + 2H), zero outside the grid) in LDS
-// once, together with the stencil in compact form, then its 16 waves split a
+// once, together with the stencil in compact form, then its 8 waves split a
 // flat list of stencil rows with no further barriers.
 //
 // Compact stencil: W depends on |n| only, so a row (nz, ny) with taps
