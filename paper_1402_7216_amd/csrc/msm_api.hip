@@ -227,7 +227,7 @@ int split_rows(const std::vector<int4>& rows, int B, int G, short* grp) {
 // together) cover the 256 compute units with short blocks: the launch is
 // estimated as ceil(blocks / 256) times its longest block.
 void choose_lattice_tiles(const Geom& g, const std::vector<int4>& rows, int taps, int H_,
-                          int tables_bytes, msm::LatLaunch& lat, int force_b = 0) {
+                          int tables_bytes, msm::LatLaunch& lat, int force_b = 0, int force_waves = 0) {
   const int n_rows = lat.n_rows, n_wc = lat.n_wc;
   std::memset(&lat, 0, sizeof(lat));
   lat.H = H_;
@@ -315,6 +315,10 @@ void choose_lattice_tiles(const Geom& g, const std::vector<int4>& rows, int taps
       return est_best;
     };
     const double est = choose_groups(0, 1) + (g.levels > 2 ? choose_groups(1, g.levels - 1) : 0.0);
+    // waves per block: a grid of many tiles balances its stencil rows better
+    // over fewer waves per tile; a grid of few tiles needs every tile's waves
+    cand.waves = force_waves ? force_waves
+                             : (tiles[0] >= msm::kLatWavesTiles ? msm::kLatWavesFew : msm::kLatWavesMany);
     // padding, LDS, block and partial offsets
     long long blocks = 0;
     int lds_max = 0, part = 0;
@@ -322,7 +326,7 @@ void choose_lattice_tiles(const Geom& g, const std::vector<int4>& rows, int taps
       msm::LatTile& t = cand.t[k];
       const int planes = t.tz + span[t.groups];
       pad_window(t, B, H_, planes, max_floats);
-      const int lds = std::max(tables_bytes + planes * t.pp * 4, msm::kLatWavesReduce * 64 * B * 8);
+      const int lds = std::max(tables_bytes + planes * t.pp * 4, cand.waves * 64 * B * 8);
       lds_max = std::max(lds_max, lds);
       t.block0 = (int)blocks;
       blocks += tiles[k] * t.groups;
@@ -359,6 +363,7 @@ void refresh_launch(msm_plan* P) {
   lg.m = g.m;
   lg.pair = g.pair;
   lg.lat_b = P->lat.b;
+  lg.lat_waves = P->lat.b ? P->lat.waves : msm::kLatWavesMany;
   lg.lat_lds = P->lat.lds_bytes;
   lg.max_levels = g.levels;
   lg.streams = P->streams;
@@ -518,11 +523,19 @@ void set_cell_geometry(msm_plan* P, int reach) {
 // tries the finer cells.
 int default_reach(int) { return 2; }
 
+void set_lattice_waves(msm_plan* P, int waves) {
+  P->lat_waves = waves;
+  if (P->lat.b > 0 && P->lat.waves != waves) {
+    choose_lattice_tiles(P->g, P->rows_c, (int)P->weights.size(), P->lat.H, P->lat_tables, P->lat, P->lat.b, waves);
+    refresh_launch(P);
+  }
+}
+
 void retune(msm_plan* P, const msm_tuning& t) {
   if (t.cell_reach != 0 && t.cell_reach != P->g.reach) set_cell_geometry(P, t.cell_reach);
   if (t.lattice_b && P->lat.b && t.lattice_b != P->lat.b)
     choose_lattice_tiles(P->g, P->rows_c, (int)P->weights.size(), P->lat.H, P->lat_tables, P->lat,
-                         t.lattice_b);
+                         t.lattice_b, P->lat_waves);
   Geom& g = P->g;
   if (t.item_chunks > 0) set_row_items(g, t.item_chunks);
   if (t.short_blocks != 0) P->short_cap = t.short_blocks < 0 ? 0 : t.short_blocks;
@@ -858,11 +871,12 @@ msm_status msm_plan_create(const msm_params* prm, int32_t n_atoms, msm_plan** ou
       const int tables = P->lat.n_rows * 16 + P->lat.n_wc * 4;
       P->lat_tables = tables;
       // the partials section holds the largest need of any tuning
-      for (int b : {4, 6, 8}) {
-        choose_lattice_tiles(g, P->rows_c, (int)P->weights.size(), H, tables, P->lat, b);
-        P->lat_part_max = std::max(P->lat_part_max, P->lat.n_part);
-      }
-      choose_lattice_tiles(g, P->rows_c, (int)P->weights.size(), H, tables, P->lat);
+      for (int b : {4, 6, 8})
+        for (int w : {msm::kLatWavesFew, msm::kLatWavesMany}) {
+          choose_lattice_tiles(g, P->rows_c, (int)P->weights.size(), H, tables, P->lat, b, w);
+          P->lat_part_max = std::max(P->lat_part_max, P->lat.n_part);
+        }
+      choose_lattice_tiles(g, P->rows_c, (int)P->weights.size(), H, tables, P->lat, 0, P->lat_waves);
     } else {
       P->lat.b = 0;
       P->lat.H = H;
@@ -1056,7 +1070,8 @@ msm_status msm_plan_describe(const msm_plan* P, char* buf, size_t buf_bytes) {
        ", \"streams\": " + std::to_string(P->streams) + ", \"short_after\": " + std::to_string(P->short_after) +
        ", \"short_split\": " + std::to_string(P->short_split);
   o += ", \"taps\": " + std::to_string(P->weights.size()) + ", \"halo\": " + std::to_string(P->lat.H);
-  o += ", \"lattice_b\": " + std::to_string(P->lat.b) + ", \"lattice_lds\": " +
+  o += ", \"lattice_b\": " + std::to_string(P->lat.b) + ", \"lattice_waves\": " + std::to_string(P->lat.waves) +
+       ", \"lattice_lds\": " +
        std::to_string(P->lat.lds_bytes) + ", \"lattice_tiles\": [";
   for (int k = 0; k < P->lat.n; ++k) {
     const msm::LatTile& t = P->lat.t[k];

@@ -127,6 +127,7 @@ void rebuild_maps(msm_batch* Bt) {
     L.anterp_lds = std::max(L.anterp_lds, msm::anterp_lds(P->g));
     L.max_levels = std::max(L.max_levels, P->g.levels);
     L.lat_b = std::max(L.lat_b, P->lat.b);
+    L.lat_waves = P->lat.b ? P->lat.waves : L.lat_waves;
     L.lat_lds = std::max(L.lat_lds, P->lat.lds_bytes);
     const msm::SysBlocks sb = msm::system_blocks(P->g, P->lat, P->n_partials);
     for (int st = 0; st < kNumStages; ++st) {
@@ -236,6 +237,12 @@ msm_status msm_batch_create(const msm_params* params, const int32_t* n_atoms, in
       set_cell_geometry(P, P->g.reach);
       refresh_launch(P);
     }
+  // one lattice launch serves every system, so they share its block size:
+  // the smaller blocks only when every system's grid takes them on its own
+  // (a batch of one system computes as its plan does)
+  bool few = true;
+  for (const msm_plan* P : Bt->plans) few = few && (P->lat.b == 0 || P->lat.waves == msm::kLatWavesFew);
+  for (msm_plan* P : Bt->plans) set_lattice_waves(P, few ? msm::kLatWavesFew : msm::kLatWavesMany);
   const msm_plan* P0 = Bt->plans[0];
   bool tiled = P0->lat.b > 0 || P0->g.levels == 1;
   for (const msm_plan* P : Bt->plans) {
@@ -418,7 +425,8 @@ msm_status msm_batch_describe(const msm_batch* Bt, char* buf, size_t buf_bytes) 
                   ", \"atoms\": " + std::to_string(Bt->total_atoms) +
                   ", \"max_levels\": " + std::to_string(L.max_levels) +
                   ", \"lattice_b\": " + std::to_string(L.lat_b) +
-                  ", \"lattice_lds\": " + std::to_string(L.lat_lds) +
+                  ", \"lattice_waves\": " + std::to_string(L.lat_waves) + ", \"lattice_lds\": " +
+                  std::to_string(L.lat_lds) +
                   ", \"item_chunks\": " + std::to_string(Bt->plans[0]->g.item_chunks) +   // first system's
                   ", \"blocks\": {\"atoms\": " + std::to_string(L.atoms.blocks) +
                   ", \"short\": " + std::to_string(L.shortr.blocks) +

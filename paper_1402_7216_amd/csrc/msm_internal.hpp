@@ -119,7 +119,9 @@ struct LatTile {
 
 constexpr int kLatMaxHalo = 16;          // windowed kernel handles stencil half-widths up to this
 constexpr int kLatMaxLds = 150 * 1024;   // LDS budget of one windowed block (bytes)
-constexpr int kLatWavesReduce = 8;       // waves per windowed block (their totals meet in LDS)
+constexpr int kLatWavesFew = 8;          // waves per windowed block for grids of many tiles
+constexpr int kLatWavesMany = 16;        // and for grids of few tiles (their totals meet in LDS)
+constexpr int kLatWavesTiles = 1024;     // level-0 tiles from which the smaller blocks are used
 constexpr int kLatMaxGroups = 8;         // row groups per tile
 
 struct LatLaunch {
@@ -130,6 +132,7 @@ struct LatLaunch {
   int n_rows;              // compact rows (nz in [-H, H], ny >= 0)
   int n_wc;                // compact weights (floats, each row padded to a multiple of 4)
   int n_part;              // float64 partials of every grouped level
+  int waves;               // waves per block (kLatWavesFew or kLatWavesMany)
   // first compact row of group g when a tile has G groups: grp[G][g], g <= G
   short grp[kLatMaxGroups + 1][kLatMaxGroups + 1];
   LatTile t[kMaxLevels];
@@ -295,6 +298,7 @@ struct LaunchGeom {
   int m = 2;
   int pair = kPairMsm;               // pair method (common to every system of a launch)
   int lat_b = 0;                     // windowed lattice outputs per lane, 0 = untiled kernel
+  int lat_waves = kLatWavesMany;     // waves per windowed lattice block
   int lat_lds = 0;                   // dynamic LDS of the windowed kernel
   int max_levels = 1;
   int streams = 3;                   // 1: in order; 2: short range on a side stream; 3: also level-0 lattice

@@ -2120,8 +2120,6 @@ __global__ void __launch_bounds__(kBlock) k_lattice(KArgs A, int part) {
 // (nz, +ny), (nz, -ny) are processed together by adding their inputs first
 // (one FMA chain for both).
 // --------------------------------------------------------------------------
-constexpr int kLatThreads = kLatWavesReduce * kWave;
-constexpr int kLatWaves = kLatThreads / kWave;
 
 template <int B, int XR, bool PAIR>
 __device__ __forceinline__ void row_win(float* acc, const float* a, const float* b,
@@ -2175,8 +2173,9 @@ __device__ __forceinline__ void row_win_dispatch(int xr, float* acc, const float
 
 // part 0: the tiles of level 0; part 1: the tiles of levels 1 .. l-2 and the
 // top level; part 2: every tile and the top level.
-template <int B>
-__global__ void __launch_bounds__(kLatThreads, B <= 6 ? 8 : 4) k_lattice_win(KArgs A, int part) {
+template <int B, int W>
+__global__ void __launch_bounds__(W * kWave, B <= 6 ? 8 : 4) k_lattice_win(KArgs A, int part) {
+  constexpr int kLatWaves = W, kLatThreads = W * kWave;
   int blk;
   const SysDesc& S = sys_of(A, blk, false);
   const Geom& g = S.g;
@@ -2757,6 +2756,7 @@ __device__ ExclSums pair_exclusions(const SysDesc& S, const Io& io, int i) {
 }
 
 constexpr int kInterpBox = 2048;   // nodes of u^0 one wave stages in LDS (8 KB)
+constexpr int kInterpStageAtoms = 65536;   // systems from this size stage u^0 in LDS
 
 template <int ORDER, int MODE>
 __global__ void __launch_bounds__(kBlock) k_interp(KArgs A) {
@@ -2834,7 +2834,12 @@ __global__ void __launch_bounds__(kBlock) k_interp(KArgs A) {
   const int row = cell_coord(g, p.z, 2) * g.nc[1] + cell_coord(g, p.y, 1);
   const float* u0 = u + L.off;
   const int n0 = L.n[0], n01 = L.n[0] * L.n[1];
-  for (unsigned long long pending = __ballot(live); pending;) {
+  // (a system of fewer than kInterpStageAtoms atoms reads u^0 directly: its
+  // grid stays in the L2 and the staging round only adds latency)
+  if (g.n_atoms < kInterpStageAtoms) {
+    if (live) gather(u0 + (size_t)base[2] * n01 + (size_t)base[1] * n0 + base[0], n0, n01);
+  }
+  for (unsigned long long pending = g.n_atoms < kInterpStageAtoms ? 0ull : __ballot(live); pending;) {
     const int lead = __ffsll((long long)pending) - 1;
     const int grow = __builtin_amdgcn_readlane(row, lead);
     const bool mine = ((pending >> lane) & 1ull) && row == grow;
@@ -3115,7 +3120,7 @@ SysBlocks system_blocks(const Geom& g, const LatLaunch& lat, int n_partials) {
   const int top_nodes = g.lv[g.levels - 1].count;
   b.lattice_all = b.lattice0 + b.lattice;
   if (g.levels > 1 && lat.b > 0) {
-    const int tb = (top_nodes + kLatWaves - 1) / kLatWaves;  // top level rides in the coarse launch
+    const int tb = (top_nodes + lat.waves - 1) / lat.waves;  // top level rides in the coarse launch
     b.lattice += tb;
     b.lattice_all += tb;
     b.top = 0;
@@ -3301,21 +3306,23 @@ hipError_t launch_eval(int mode, const LaunchGeom& L, hipStream_t s, const Io& i
     if (sg.blocks == 0) return;
     const KArgs A = args(sg);
     const int nb = sg.blocks;
+#define MSM_LAT(BB, WW)                                                                                      \
+  do {                                                                                                      \
+    (void)hipFuncSetAttribute((const void*)k_lattice_win<BB, WW>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                              L.lat_lds);                                                                   \
+    k_lattice_win<BB, WW><<<nb, WW * kWave, L.lat_lds, ls>>>(A, part);                                       \
+  } while (0)
+    const bool few = L.lat_waves == kLatWavesFew;
     if (L.lat_b == 4) {
-      (void)hipFuncSetAttribute((const void*)k_lattice_win<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                L.lat_lds);
-      k_lattice_win<4><<<nb, kLatThreads, L.lat_lds, ls>>>(A, part);
+      if (few) MSM_LAT(4, kLatWavesFew); else MSM_LAT(4, kLatWavesMany);
     } else if (L.lat_b == 6) {
-      (void)hipFuncSetAttribute((const void*)k_lattice_win<6>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                L.lat_lds);
-      k_lattice_win<6><<<nb, kLatThreads, L.lat_lds, ls>>>(A, part);
+      if (few) MSM_LAT(6, kLatWavesFew); else MSM_LAT(6, kLatWavesMany);
     } else if (L.lat_b == 8) {
-      (void)hipFuncSetAttribute((const void*)k_lattice_win<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                L.lat_lds);
-      k_lattice_win<8><<<nb, kLatThreads, L.lat_lds, ls>>>(A, part);
+      if (few) MSM_LAT(8, kLatWavesFew); else MSM_LAT(8, kLatWavesMany);
     } else {
       k_lattice<<<nb, kBlock, 0, ls>>>(A, part);
     }
+#undef MSM_LAT
   };
   // level 0 needs only the anterpolated charges: it overlaps the coarse chain
   const bool lat0_side = concurrent && L.streams >= 3 && L.lattice0.blocks > 0;

@@ -31,6 +31,7 @@ struct msm_plan {
   int n_partials = 1;
   int bin2_blocks = 0;                       // blocks of the two-kernel binning where it is possible
   bool prefer_bin2 = false;                  // two-kernel binning over one kernel where both work (batches)
+  int lat_waves = 0;                         // waves per lattice block: 0 by the level-0 tiles (batches: 16)
   int max_cells = 0;                         // link cells of the finest cell reach (sizes the cell sections)
   long long max_bin_hist = 0;                // two-kernel histogram entries of any cell reach
   msm::LatLaunch lat;
@@ -93,6 +94,9 @@ msm_status batch_shape(const msm_batch* B, int32_t* n_sys, int32_t* total_atoms)
 // Apply tuning knobs (zero fields keep the current value).  Host-side only;
 // the caller re-uploads descriptors.
 void retune(msm_plan* P, const msm_tuning& t);
+// Waves per windowed lattice block for every later tile choice (0: by the
+// level-0 tile count); re-chooses the current tiles.  Host-side only.
+void set_lattice_waves(msm_plan* P, int waves);
 // Reject knob values outside their documented ranges.
 msm_status check_tuning(const msm_tuning* t);
 // Capture the work `launch` enqueues on a private stream into an instantiated graph.

@@ -94,6 +94,8 @@ def test_batch_equals_single_system_path_bitwise(M, batch64, replicas):
         sys_ = replicas[s]
         plan = M.plan_for(sys_)
         plan.tune(d["lattice_b"], d["item_chunks_all"][s])
+        # batch-size grids take the larger lattice blocks on their own too
+        assert plan.describe()["lattice_waves"] == d["lattice_waves"], s
         o = plan.compute(*M.to_device(sys_), virial=True)
         torch.cuda.synchronize()
         a, e = b.offsets[s], b.offsets[s + 1]
