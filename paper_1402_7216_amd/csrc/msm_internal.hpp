@@ -22,7 +22,7 @@ constexpr int kXSub = 4;                  // link cells are this many times fine
 constexpr int kBinMaxCells = 8192;        // cells the two-kernel binning keeps in LDS
 constexpr int kBinMaxHist = 1 << 20;      // block histogram entries of the two-kernel binning
 constexpr int kBinRowAtoms = 32768;       // atoms per system at most for the one-kernel binning
-constexpr int kBinRChunk = 4096;          // atoms per block of the row binning's count and scatter
+constexpr int kBinRChunk = 8192;          // atoms per block of the row binning's count and scatter
 constexpr int kBinRowsMax = 8192;         // cell rows of a system at most for the row binning
 constexpr int kBinRSortCap = 1024;        // atoms of a cell row the row binning's sort keeps in LDS
 constexpr int kBinRowCells = 512;         // cells one block of the one-kernel binning owns at most
