@@ -439,12 +439,13 @@ void assign_short_rows(Geom& g) {
   });
   double load[msm::kShortWaves] = {};
   int count[msm::kShortWaves] = {};
-  std::memset(g.short_rows, -1, sizeof(g.short_rows));
+  std::memset(g.short_rows, 0xff, sizeof(g.short_rows));
   for (const auto& c : cost) {
     int w = 0;
     for (int v = 1; v < msm::kShortWaves; ++v)
       if (count[v] < msm::kShortRowsPerWave && (count[w] >= msm::kShortRowsPerWave || load[v] < load[w])) w = v;
-    g.short_rows[w][count[w]++] = (signed char)c.second;
+    // row r = (oz + R) side + oy + R, stored as its two offsets (R <= 4)
+    g.short_rows[w][count[w]++] = (unsigned char)((c.second % side) | ((c.second / side) << 4));
     load[w] += c.first;
   }
 }

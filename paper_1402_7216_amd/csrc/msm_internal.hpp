@@ -75,8 +75,9 @@ struct Geom {
   float inv_cs[3];                 // 1 / cell edge
   float cs[3];                     // cell edge (x cells are kXSub times finer than y, z)
   float a_win;                     // cutoff with a margin, for the short-range x windows
-  signed char short_rows[kShortWaves][kShortRowsPerWave];   // neighbour rows of each short-range
-                                                           // wave (-1 ends a list)
+  unsigned char short_rows[kShortWaves][kShortRowsPerWave]; // neighbour rows of each short-range wave:
+                                                           // (oy + reach) | (oz + reach) << 4, 0xff
+                                                           // ends a list
   int item_chunks;                 // short-range 64-atom chunks of a cell row per work item
   int row_items;                   // short-range work items per cell row (chunks interleaved)
   int short_blocks;                // blocks of the short-range launch (work items strided over them)

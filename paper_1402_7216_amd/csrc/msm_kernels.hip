@@ -1305,14 +1305,14 @@ __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, 
     pk[k] = v;
   }
   float4* jb = jbuf[wave];
-  const int R = g.reach, side = 2 * R + 1;
+  const int R = g.reach;
   // coincident atoms: the one- and two-kernel binnings leave them to this
   // pass, and so does every periodic plan (atoms one box edge apart coincide
   // once wrapped, which binning's comparison of the inputs does not see); the
   // other binnings compare the atoms of each cell themselves, except in cells
   // longer than kRankCap (status word 1 then set)
   const bool coin = PER || g.bin_blocks || g.bin_row_blocks || S.d.status[kStatusUnranked] != 0;
-  const int centre = coin ? (side * side) / 2 : -1;
+  const int centre = coin ? (R | (R << 4)) : -1;      // the row of offsets (0, 0)
   // the launch has g.short_blocks blocks; work items are strided over them
   const int item_lo = (int)((long long)n_items * lo_pm / 1000);
   const int item_hi = (int)((long long)n_items * hi_pm / 1000);
@@ -1334,8 +1334,8 @@ __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, 
       bool coincident = false;
       for (int q = 0; q < kShortRowsPerWave; ++q) {
         const int r = g.short_rows[wave][q];
-        if (r < 0) break;
-        const int oy = r % side - R, oz = r / side - R;
+        if (r == 0xff) break;
+        const int oy = (r & 15) - R, oz = (r >> 4) - R;
         int jy = cy + oy, jz = cz + oz;
         // periodic plans: the row's image, its atoms shifted by (sx, sy, sz)
         double sy = 0.0, sz = 0.0;
