@@ -342,6 +342,84 @@ void choose_lattice_tiles(const Geom& g, const std::vector<int4>& rows, int taps
   }
 }
 
+// Least squares min |A c - b| over the columns of A (rows x cols, row-major)
+// by Householder reflections; A and b are overwritten.
+void householder_lsq(std::vector<double>& A, std::vector<double>& b, int rows, int cols, double* c) {
+  for (int k = 0; k < cols; ++k) {
+    double norm = 0.0;
+    for (int i = k; i < rows; ++i) norm += A[i * cols + k] * A[i * cols + k];
+    norm = std::sqrt(norm);
+    const double alpha = A[k * cols + k] > 0 ? -norm : norm;
+    std::vector<double> v(rows - k);
+    for (int i = k; i < rows; ++i) v[i - k] = A[i * cols + k];
+    v[0] -= alpha;
+    double vv = 0.0;
+    for (double e : v) vv += e * e;
+    if (vv == 0.0) continue;
+    for (int j = k; j < cols; ++j) {
+      double s = 0.0;
+      for (int i = k; i < rows; ++i) s += v[i - k] * A[i * cols + j];
+      s *= 2.0 / vv;
+      for (int i = k; i < rows; ++i) A[i * cols + j] -= s * v[i - k];
+    }
+    double s = 0.0;
+    for (int i = k; i < rows; ++i) s += v[i - k] * b[i];
+    s *= 2.0 / vv;
+    for (int i = k; i < rows; ++i) b[i] -= s * v[i - k];
+  }
+  for (int k = cols - 1; k >= 0; --k) {
+    double s = b[k];
+    for (int j = k + 1; j < cols; ++j) s -= A[k * cols + j] * c[j];
+    c[k] = A[k * cols + k] != 0.0 ? s / A[k * cols + k] : 0.0;
+  }
+}
+
+// The Wolf pair function's erfc on the device: erfc(x) = exp(-x^2) R(x), with
+// the smooth scaled function R(x) = erfc(x) exp(x^2) written as a polynomial
+// in t = 1 / (1 + x/2) (the substitution of Hastings' approximations in
+// Abramowitz and Stegun 7.1.25-28), fitted here in double over x in [0, x_hi]
+// by least squares in relative error.  The coefficients are rounded to float
+// one at a time from t^0 up, the later ones refitted after each rounding, so
+// the rounded polynomial keeps the fit's accuracy (about 1e-9 relative for
+// x_hi <= 6) instead of carrying a fixed float-rounding bias into every pair.
+// Returns the fitted polynomial's largest relative error on a fine grid.
+double fit_wolf_erfc(double x_hi, float* ec) {
+  constexpr int m = msm::kWolfTerms, n = 12 * msm::kWolfTerms;
+  const double tmin = 1.0 / (1.0 + 0.5 * x_hi);
+  std::vector<double> t(n), w(n);
+  for (int i = 0; i < n; ++i) {
+    const double z = std::cos(M_PI * (i + 0.5) / n);
+    t[i] = tmin + 0.5 * (z + 1.0) * (1.0 - tmin);
+    const double x = 2.0 * (1.0 / t[i] - 1.0);
+    w[i] = 1.0 / (std::erfc(x) * std::exp(x * x));
+  }
+  double fixed[m];
+  for (int k = 0; k < m; ++k) {
+    const int cols = m - k;
+    std::vector<double> A(n * cols), b(n);
+    for (int i = 0; i < n; ++i) {
+      double tp = 1.0, rhs = 1.0;
+      for (int j = 0; j < m; ++j, tp *= t[i]) {
+        if (j < k) rhs -= fixed[j] * tp * w[i];
+        else A[i * cols + (j - k)] = tp * w[i];
+      }
+      b[i] = rhs;
+    }
+    double c[m];
+    householder_lsq(A, b, n, cols, c);
+    fixed[k] = (double)(float)c[0];
+  }
+  double worst = 0.0;
+  for (int i = 0; i <= 4000; ++i) {
+    const double x = x_hi * i / 4000.0, tt = 1.0 / (1.0 + 0.5 * x);
+    double p = 0.0;
+    for (int k = m - 1; k >= 0; --k) p = p * tt + fixed[k];
+    worst = std::max(worst, std::fabs(p / (std::erfc(x) * std::exp(x * x)) - 1.0));
+  }
+  for (int k = 0; k < m; ++k) ec[k] = (float)fixed[k];
+  return worst;
+}
+
 }  // namespace
 
 void refresh_launch(msm_plan* P) {
@@ -985,7 +1063,15 @@ msm_status msm_pair_plan_create(const msm_pair_params* pp, int32_t n_atoms, msm_
     g.pk[0] = (float)al;
     g.pk[1] = (float)(std::erfc(al * rc) / rc);
     g.pk[2] = (float)(al * two_over_sqrt_pi);
-    g.pk[3] = (float)(al * al);
+    g.pk[3] = (float)(-al * al * 1.4426950408889634);   // -alpha^2 log2(e)
+    // every pair the device evaluates has alpha r <= alpha rc (the r < rc test,
+    // with float rounding to spare); below x = 1 the fit is as good and beyond
+    // x = 10 erfc(x) exp(-x^2) underflows float
+    const double x_hi = std::min(std::max(al * rc * (1.0 + 1e-3), 1.0), 10.0);
+    if (fit_wolf_erfc(x_hi, g.ec) > 1e-7) {
+      msm_plan_destroy(P);
+      return fail(MSM_ERR_UNSUPPORTED, "Wolf erfc fit failed");
+    }
     // phi_i gains 2 s q_i with s = -(erfc(alpha rc)/(2 rc) + alpha/sqrt(pi)); the
     // assembly subtracts q_i self
     g.self = (float)(std::erfc(al * rc) / rc + al * two_over_sqrt_pi);

@@ -39,6 +39,7 @@ enum DeviceFlag : int { kFlagOutOfBox = 1, kFlagNonFinite = 2, kFlagCoincident =
 // Pair function of the short-range pass: the MSM short-range kernel g*, or one
 // of the cheap pair methods evaluated on their own (values of msm_pair_kind).
 enum PairKind : int { kPairMsm = 0, kPairCutoff = 1, kPairShiftedForce = 2, kPairWolf = 3 };
+constexpr int kWolfTerms = 11;            // terms of the Wolf pair method's erfc polynomial
 
 struct Level {
   int lo[3];     // lowest node index per dimension
@@ -92,6 +93,7 @@ struct Geom {
   int at_ext;                      // nodes of a tile's private region (at[d] + order - 1 per dimension)
   int pair;                        // 0: MSM; else the cheap pair method evaluated alone (kPair*)
   float pk[4];                     // constants of the pair method (see k_short)
+  float ec[kWolfTerms];            // Wolf: erfc(x) exp(x^2) as a polynomial in t = 1 / (1 + x/2) (coefficients of t^0..)
   int m;                           // smoothing degree
   float self;                      // gamma(0) / a
   double ke;                       // energy prefactor

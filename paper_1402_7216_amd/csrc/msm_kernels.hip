@@ -1254,13 +1254,31 @@ constexpr float binom_half(int j) {
   return (float)v;
 }
 
+// erfc(x) for the Wolf pair function from ex = exp(-x^2): erfc(x) exp(x^2) is
+// a polynomial in t = 1 / (1 + x/2) whose coefficients ec the plan fits (in
+// double, rounded to float one at a time with the rest refitted); t takes the
+// hardware reciprocal and one Newton step (the raw instruction's error is
+// biased, as for the reciprocal square root).
+__device__ __forceinline__ float wolf_erfc(const float* ec, float x, float ex) {
+  const float d = fmaf(0.5f, x, 1.f);
+  float t = __builtin_amdgcn_rcpf(d);
+  t = fmaf(t, fmaf(-d, t, 1.f), t);
+  float p = ec[kWolfTerms - 1];
+#pragma unroll
+  for (int k = kWolfTerms - 2; k >= 0; --k) p = fmaf(p, t, ec[k]);
+  return p * ex;
+}
+
 // KIND selects the pair function: the MSM short-range kernel g* (gamma of
 // degree M), or a cheap pair method on its own with e(r) and -e'(r)/r
 //   plain cutoff     e = 1/r                                -e'/r = 1/r^3
 //   shifted force    e = 1/r + r pk1 - 2 pk0                -e'/r = (1/r^2 - pk1)/r
 //                    (pk0 = 1/rc, pk1 = 1/rc^2)
-//   Wolf             e = erfc(pk0 r)/r - pk1                -e'/r = (erfc(pk0 r)/r + pk2 exp(-pk3 r^2))/r^2
-//                    (pk0 = alpha, pk1 = erfc(alpha rc)/rc, pk2 = 2 alpha/sqrt(pi), pk3 = alpha^2)
+//   Wolf             e = erfc(pk0 r)/r - pk1                -e'/r = (erfc(pk0 r)/r + pk2 exp(-alpha^2 r^2))/r^2
+//                    (pk0 = alpha, pk1 = erfc(alpha rc)/rc, pk2 = 2 alpha/sqrt(pi), pk3 = -alpha^2 log2(e), so that
+//                    exp(-alpha^2 r^2) = 2^(pk3 r^2), the hardware exp2 (which may flush results
+//                    below 2^-126 to zero: there erfc(alpha r) < 1e-38); erfc from the plan's
+//                    polynomial and that one exponential)
 // PER: periodic plans (the neighbour rows and x windows wrap around the box,
 // the atoms of a wrapped image staged shifted by the box edges); a template
 // flag so the free-space kernel keeps its registers.
@@ -1303,6 +1321,12 @@ __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, 
     float v;
     asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(g.pk[k]));
     pk[k] = v;
+  }
+  float ec[kWolfTerms];
+  if (KIND == kPairWolf) {
+#pragma unroll
+    for (int k = 0; k < kWolfTerms; ++k)
+      ec[k] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(g.ec[k])));
   }
   float4* jb = jbuf[wave];
   const int R = g.reach;
@@ -1454,9 +1478,10 @@ __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, 
                     e = ri + fmaf(r2 * ri, pk[1], -2.f * pk[0]);
                     fr = ri * fmaf(ri, ri, -pk[1]);
                   } else {
-                    const float er = erfcf(pk[0] * (r2 * ri));
+                    const float ex = __builtin_amdgcn_exp2f(pk[3] * r2);
+                    const float er = wolf_erfc(ec, pk[0] * (r2 * ri), ex);
                     e = fmaf(er, ri, -pk[1]);
-                    fr = ri * ri * fmaf(er, ri, pk[2] * expf(-pk[3] * r2));
+                    fr = ri * ri * fmaf(er, ri, pk[2] * ex);
                   }
                   ap = fmaf(qj, e, ap);
                   if (FORCES) {
@@ -2741,9 +2766,10 @@ __device__ ExclSums pair_exclusions(const SysDesc& S, const Io& io, int i) {
       ev = ri + fmaf(r2 * ri, g.pk[1], -2.f * g.pk[0]);
       fr = ri * fmaf(ri, ri, -g.pk[1]);
     } else {
-      const float er = erfcf(g.pk[0] * (r2 * ri));
+      const float ex = __builtin_amdgcn_exp2f(g.pk[3] * r2);
+      const float er = wolf_erfc(g.ec, g.pk[0] * (r2 * ri), ex);
       ev = fmaf(er, ri, -g.pk[1]);
-      fr = ri * ri * fmaf(er, ri, g.pk[2] * expf(-g.pk[3] * r2));
+      fr = ri * ri * fmaf(er, ri, g.pk[2] * ex);
     }
     const float qj = io.q[j];
     r.p = fmaf(qj, ev, r.p);
