@@ -11,6 +11,7 @@
 #include <new>
 #include <set>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "msm_plan.hpp"
@@ -487,14 +488,18 @@ void refresh_launch(msm_plan* P) {
 }
 
 // Neighbour cell rows (offsets oy, oz in [-reach, reach], row index
-// (oz + reach) (2 reach + 1) + oy + reach) dealt to the 8 waves of a
+// (oz + reach) (2 reach + 1) + oy + reach) dealt to the 4 waves of a
 // short-range block, largest expected x window first, each to the wave with
 // the least work so far.  A row's expected window is the mean over atom
 // positions (y, z) in a cell of 2 sqrt(a^2 - d^2), d the distance to the row.
+// Free-space plans deal each row with its mirror (-oy, -oz) as one unit that
+// a wave walks together: an atom near one face of its cell has a long window
+// in the row beyond that face and a short one in the mirror row, so the sum
+// of the two varies far less over the 64 atoms of a chunk than either.
 void assign_short_rows(Geom& g) {
   const int R = g.reach, side = 2 * R + 1, nrows = side * side;
   const double a = g.a_win, cy = g.cs[1], cz = g.cs[2];
-  std::vector<std::pair<double, int>> cost;
+  std::vector<double> row_cost(nrows);
   for (int r = 0; r < nrows; ++r) {
     const int oy = r % side - R, oz = r / side - R;
     double sum = 0.0;
@@ -510,21 +515,34 @@ void assign_short_rows(Geom& g) {
         const double dy = gap(y, oy, cy), dz = gap(z, oz, cz), d2 = dy * dy + dz * dz;
         if (d2 < a * a) sum += 2.0 * std::sqrt(a * a - d2);
       }
-    cost.push_back({sum / (K * K) + 1.0, r});
+    row_cost[r] = sum / (K * K) + 1.0;
   }
-  std::sort(cost.begin(), cost.end(), [](const auto& x, const auto& y) {
-    return x.first > y.first || (x.first == y.first && x.second < y.second);
+  // units: (cost, first row, second row or -1); the mirror of row r is nrows - 1 - r
+  const bool pairs = !g.periodic;
+  std::vector<std::tuple<double, int, int>> units;
+  for (int r = 0; r < nrows; ++r) {
+    const int m = nrows - 1 - r;
+    if (pairs && m < r) continue;
+    if (pairs && m > r) units.emplace_back(row_cost[r] + row_cost[m], r, m);
+    else units.emplace_back(row_cost[r], r, -1);
+  }
+  std::sort(units.begin(), units.end(), [](const auto& x, const auto& y) {
+    return std::get<0>(x) > std::get<0>(y) || (std::get<0>(x) == std::get<0>(y) && std::get<1>(x) < std::get<1>(y));
   });
   double load[msm::kShortWaves] = {};
   int count[msm::kShortWaves] = {};
   std::memset(g.short_rows, 0xff, sizeof(g.short_rows));
-  for (const auto& c : cost) {
+  std::memset(g.short_pair, 0xff, sizeof(g.short_pair));
+  // a row r = (oz + R) side + oy + R is stored as its two offsets (R <= 4)
+  auto code = [&](int r) { return (unsigned char)((r % side) | ((r / side) << 4)); };
+  for (const auto& u : units) {
     int w = 0;
     for (int v = 1; v < msm::kShortWaves; ++v)
       if (count[v] < msm::kShortRowsPerWave && (count[w] >= msm::kShortRowsPerWave || load[v] < load[w])) w = v;
-    // row r = (oz + R) side + oy + R, stored as its two offsets (R <= 4)
-    g.short_rows[w][count[w]++] = (unsigned char)((c.second % side) | ((c.second / side) << 4));
-    load[w] += c.first;
+    g.short_rows[w][count[w]] = code(std::get<1>(u));
+    if (std::get<2>(u) >= 0) g.short_pair[w][count[w]] = code(std::get<2>(u));
+    ++count[w];
+    load[w] += std::get<0>(u);
   }
 }
 
@@ -1053,6 +1071,7 @@ msm_status msm_pair_plan_create(const msm_pair_params* pp, int32_t n_atoms, msm_
   const double rc = pp->cutoff, al = pp->alpha;
   g.pair = pp->kind;
   g.periodic = pp->periodic;                     // pairs at their nearest image (the grid is unused)
+  assign_short_rows(g);                          // periodic plans walk rows one at a time
   g.pk[0] = g.pk[1] = g.pk[2] = g.pk[3] = 0.f;
   g.self = 0.f;
   if (pp->kind == MSM_PAIR_SHIFTED_FORCE) {

@@ -12,8 +12,8 @@
 namespace msm {
 
 constexpr int kMaxLevels = 12;
-constexpr int kShortWaves = 8;           // waves of a short-range block (they split the neighbour rows)
-constexpr int kShortRowsPerWave = 16;    // neighbour rows one wave can take
+constexpr int kShortWaves = 4;           // waves of a short-range block (they split the neighbour rows)
+constexpr int kShortRowsPerWave = 24;    // neighbour rows one wave can take
 constexpr int kMaxOrder = 6;
 constexpr int kMaxTopNodes = 1 << 17;     // all-pairs FP64 top level stays below ~1e10 pair terms
 constexpr int kRankCap = 2048;            // cells longer than this keep scatter order (see bin_place)
@@ -79,6 +79,8 @@ struct Geom {
   unsigned char short_rows[kShortWaves][kShortRowsPerWave]; // neighbour rows of each short-range wave:
                                                            // (oy + reach) | (oz + reach) << 4, 0xff
                                                            // ends a list
+  unsigned char short_pair[kShortWaves][kShortRowsPerWave]; // the row walked together with short_rows
+                                                           // (its mirror (-oy, -oz)), 0xff: none
   int item_chunks;                 // short-range 64-atom chunks of a cell row per work item
   int row_items;                   // short-range work items per cell row (chunks interleaved)
   int short_blocks;                // blocks of the short-range launch (work items strided over them)

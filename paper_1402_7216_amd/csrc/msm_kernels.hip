@@ -1188,12 +1188,16 @@ __global__ void __launch_bounds__(kBRSThreads) k_binr_sort(KArgs A) {
 // within sqrt(a^2 - d^2) of the atom can hold partners, a contiguous range of
 // sorted atoms.  A wave stages the union of its lanes' windows in LDS (one
 // coalesced load per 256 atoms) and each lane walks its own range (gathered
-// LDS reads).  The rows are dealt to the block's 8 waves by expected window
-// length (fixed per plan); the waves' partial sums meet in LDS and are added
-// in wave order.
+// LDS reads).  In free space a row and its mirror row are walked as one unit
+// (both unions staged, each lane's two windows back to back), which evens out
+// the lanes' walk lengths; the units are dealt to the block's 4 waves by
+// expected window length (fixed per plan); the waves' partial sums meet in
+// LDS and are added in wave order.
 // --------------------------------------------------------------------------
 constexpr int kShortThreads = kShortWaves * kWave;
-constexpr int kShortSeg = 256;                   // j atoms a wave stages at a time
+constexpr int kShortSeg = 256;                   // j atoms a wave stages at a time (one row)
+constexpr int kShortBuf = 312;                   // entries of a wave's staging buffer (a row pair; 4 waves x 312 x 16 B: 8 blocks per CU)
+static_assert(kShortBuf >= kShortSeg + 4 && kShortSeg % kWave == 0, "short-range staging sizes");
 
 __device__ __forceinline__ int cell_x(const Geom& g, float x) {
   float t = (x - g.lo_f[0]) * g.inv_cs[0];
@@ -1282,8 +1286,99 @@ __device__ __forceinline__ float wolf_erfc(const float* ec, float x, float ex) {
 // PER: periodic plans (the neighbour rows and x windows wrap around the box,
 // the atoms of a wrapped image staged shifted by the box edges); a template
 // flag so the free-space kernel keeps its registers.
+// The lane's x window in the free-space neighbour row of offsets code r
+// ((oy + R) | (oz + R) << 4) around cell row (cy, cz): the sorted atoms of the
+// x cells within sqrt(aw^2 - d^2) of the atom, d its distance to the row in
+// (y, z); empty (lo > hi) outside the box, for a dead lane or a row beyond aw.
+__device__ __forceinline__ void row_window(const Geom& g, const int* start, int cy, int cz, int r, int R,
+                                           const float4& pi, bool live, float aw, int& lo, int& hi) {
+  lo = 0x7fffffff;
+  hi = -1;
+  const int jy = cy + (r & 15) - R, jz = cz + (r >> 4) - R;
+  if (!live || jy < 0 || jz < 0 || jy >= g.nc[1] || jz >= g.nc[2]) return;
+  const float ylo = g.lo_f[1] + (float)jy * g.cs[1], zlo = g.lo_f[2] + (float)jz * g.cs[2];
+  const float dyw = fmaxf(fmaxf(ylo - pi.y, pi.y - (ylo + g.cs[1])), 0.f);
+  const float dzw = fmaxf(fmaxf(zlo - pi.z, pi.z - (zlo + g.cs[2])), 0.f);
+  const float d2 = fmaf(dyw, dyw, dzw * dzw);
+  if (!(d2 < aw * aw)) return;
+  const float e = sqrtf(aw * aw - d2) + 1e-4f * aw;
+  const int jrow = (jz * g.nc[1] + jy) * g.nc[0];
+  lo = start[jrow + cell_x(g, pi.x - e)];
+  hi = start[jrow + cell_x(g, pi.x + e) + 1];
+}
+
+// Four staged j atoms against the lane's atom pi: the pair function of KIND
+// for each one with 0 < r^2 < a^2, added to the lane's sums.
+template <int M, bool FORCES, int KIND>
+__device__ __forceinline__ void short_pairs4(const float4* jp, const float4& pi, unsigned a2m1, float inv_a,
+                                             float inv_a2, const float* dc, const float* pk, const float* ec,
+                                             float& ax, float& ay, float& az, float& ap) {
+  float4 pj[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) pj[v] = jp[v];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const float dx = pi.x - pj[v].x, dy = pi.y - pj[v].y, dz = pi.z - pj[v].z;
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    // one predicate (non-short-circuit), so a single branch per pair
+    // 0 < r2 < a2 as one unsigned compare of the bit patterns (r2 >= +0)
+    if (__float_as_uint(r2) - 1u < a2m1) {
+      // hardware reciprocal square root plus one Newton step (the raw
+      // instruction's error is biased, which would bias the energy)
+      float ri = __builtin_amdgcn_rsqf(r2);
+      ri = fmaf(0.5f * ri, fmaf(-r2 * ri, ri, 1.f), ri);
+      const float qj = pj[v].w;
+      if (KIND == kPairMsm) {
+        // g*(r) = 1/r - gamma(r/a)/a with gamma the Taylor polynomial of
+        // s^{-1/2} in t = s - 1, s = (r/a)^2: exact coefficients and
+        // every term of one sign, then one rounding for the difference.
+        // (Horner in r^2 with the rounded coefficients c_k / a^{2k+1}
+        // leaves a fixed bias in every pair that does not average out
+        // over the pairs of rigid molecules.)
+        const float t = fmaf(r2, inv_a2, -1.f);
+        float gm = binom_half(M);
+#pragma unroll
+        for (int k = M - 1; k >= 0; --k) gm = fmaf(gm, t, binom_half(k));
+        ap = fmaf(qj, fmaf(-gm, inv_a, ri), ap);
+        // gamma'(r/a)/(a^2 r) as a polynomial in r^2
+        float dg = dc[M];
+#pragma unroll
+        for (int k = M - 1; k >= 1; --k) dg = fmaf(dg, r2, dc[k]);
+        if (FORCES) {
+          const float wq = qj * fmaf(ri, ri * ri, dg);  // q_j (-g*'(r)/r)
+          ax = fmaf(wq, dx, ax);
+          ay = fmaf(wq, dy, ay);
+          az = fmaf(wq, dz, az);
+        }
+      } else {
+        float e, fr;                                     // e(r), -e'(r)/r
+        if (KIND == kPairCutoff) {
+          e = ri;
+          fr = ri * ri * ri;
+        } else if (KIND == kPairShiftedForce) {
+          e = ri + fmaf(r2 * ri, pk[1], -2.f * pk[0]);
+          fr = ri * fmaf(ri, ri, -pk[1]);
+        } else {
+          const float ex = __builtin_amdgcn_exp2f(pk[3] * r2);
+          const float er = wolf_erfc(ec, pk[0] * (r2 * ri), ex);
+          e = fmaf(er, ri, -pk[1]);
+          fr = ri * ri * fmaf(er, ri, pk[2] * ex);
+        }
+        ap = fmaf(qj, e, ap);
+        if (FORCES) {
+          const float wq = qj * fr;
+          ax = fmaf(wq, dx, ax);
+          ay = fmaf(wq, dy, ay);
+          az = fmaf(wq, dz, az);
+        }
+      }
+    }
+  }
+}
+
 template <int M, bool FORCES, int KIND, bool PER>
-// Four blocks per CU: 8 waves per SIMD, so at most 64 registers per lane.
+// Eight 4-wave blocks per CU (LDS 20 KB each): 8 waves per SIMD, so at most 64
+// registers per lane.
 __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, int hi_pm) {
   int blk;
   const SysDesc& S = sys_of(A, blk);
@@ -1291,11 +1386,11 @@ __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, 
   const float4* __restrict__ sorted = S.d.sorted;
   const int* __restrict__ start = S.d.cell_start;
   float4* __restrict__ fshort = S.d.fshort;
-  // staged j atoms of each wave, then 4 far-away uncharged entries: a lane
-  // reads 4 entries from min(window start + t0, kShortSeg), and every entry past
-  // its window fails the cutoff test (same-row atoms beyond the window lie
-  // farther than a)
-  __shared__ float4 jbuf[kShortWaves][kShortSeg + 4];
+  // staged j atoms of each wave (one row segment, or a row pair) with 4
+  // far-away uncharged entries after each row: a lane reads 4 entries at a
+  // time, and every entry past its window fails the cutoff test (same-row
+  // atoms beyond the window lie farther than a)
+  __shared__ float4 jbuf[kShortWaves][kShortBuf];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int n_items = g.row_items * g.nc[1] * g.nc[2];
@@ -1346,9 +1441,6 @@ __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, 
     const int rowbase = (cz * g.nc[1] + cy) * g.nc[0];
     const int rb = start[rowbase], re = start[rowbase + g.nc[0]];
     for (int ic = rb + kk * kWave; ic < re; ic += g.row_items * kWave) {
-      // the far entries, rewritten for every chunk: the previous chunk's sums
-      // of the waves met in these buffers
-      if (lane < 4) jb[kShortSeg + lane] = make_float4(3e30f, 3e30f, 3e30f, 0.f);
       const int ie = min(ic + kWave, re);
       const int i = ic + lane;
       const bool live = i < ie;
@@ -1357,7 +1449,49 @@ __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, 
       float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;
       bool coincident = false;
       for (int q = 0; q < kShortRowsPerWave; ++q) {
-        const int r = g.short_rows[wave][q];
+        const int r0 = g.short_rows[wave][q];
+        if (r0 == 0xff) break;
+        const int r1 = g.short_pair[wave][q];
+        // a free-space row and its mirror walked together when both staged
+        // unions fit the wave's buffer: [0, LA) row A, 4 far entries, [LA + 4,
+        // E) row B, 4 far entries.  A lane walks its A window (its count
+        // rounded up to 4: the entries past it are A atoms beyond a or far
+        // entries), then its B window, then far entries (index clamped to E),
+        // for the wave's longest such walk.
+        if (!PER && r1 != 0xff) {
+          int loA, hiA, loB, hiB;
+          row_window(g, start, cy, cz, r0, R, pi, live, aw, loA, hiA);
+          row_window(g, start, cy, cz, r1, R, pi, live, aw, loB, hiB);
+          const int uA0 = wave_min_s(loA), uA1 = wave_max_s(hiA);
+          const int uB0 = wave_min_s(loB), uB1 = wave_max_s(hiB);
+          const int LA = max(uA1 - uA0, 0), LB = max(uB1 - uB0, 0);
+          if (LA + LB + 8 <= kShortBuf) {
+            const int E = LA + 4 + LB;
+#pragma unroll
+            for (int v = 0; v < (kShortBuf + kWave - 1) / kWave; ++v) {
+              const int sj = v * kWave + lane;
+              if (sj < E + 4) {
+                float4 pj = make_float4(3e30f, 3e30f, 3e30f, 0.f);
+                if (sj < LA) pj = sorted[uA0 + sj];
+                else if (sj >= LA + 4 && sj < E) pj = sorted[uB0 + (sj - LA - 4)];
+                jb[sj] = pj;
+              }
+            }
+            const int nA = hiA > loA ? hiA - loA : 0, nB = hiB > loB ? hiB - loB : 0;
+            const int a0A = nA > 0 ? loA - uA0 : 0;
+            const int a0B = LA + 4 + (nB > 0 ? loB - uB0 : 0);
+            const int c4A = (nA + 3) & ~3;
+            const int T = wave_max_s(c4A + nB);
+            for (int t0 = 0; t0 < T; t0 += 4) {
+              const int idx = t0 < c4A ? a0A + t0 : min(a0B + (t0 - c4A), E);
+              short_pairs4<M, FORCES, KIND>(jb + idx, pi, a2m1, inv_a, inv_a2, dc, pk, ec, ax, ay, az, ap);
+            }
+            continue;
+          }
+        }
+        // otherwise the unit's rows one at a time, in segments of kShortSeg
+        for (int h = 0; h < 2; ++h) {
+        const int r = h ? r1 : r0;
         if (r == 0xff) break;
         const int oy = (r & 15) - R, oz = (r >> 4) - R;
         int jy = cy + oy, jz = cz + oz;
@@ -1414,6 +1548,7 @@ __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, 
             }
             jb[v * kWave + lane] = pj;
           }
+          if (lane < 4) jb[kShortSeg + lane] = make_float4(3e30f, 3e30f, 3e30f, 0.f);
           // this lane's part of the staged segment: [a0, a0 + n) (n = 0 keeps a0 = 0)
           const int lo_s = max(lo, s0) - s0, hi_s = min(hi, s0 + kShortSeg) - s0;
           const int n = (hi > lo && hi_s > lo_s) ? hi_s - lo_s : 0;
@@ -1430,70 +1565,9 @@ __global__ void __launch_bounds__(kShortThreads, 8) k_short(KArgs A, int lo_pm, 
             }
             coincident |= zeros > ((i >= s0 + a0 && i < s0 + b0) ? 1 : 0);
           }
-          for (int t0 = 0; t0 < nmax; t0 += 4) {
-            const float4* jp = jb + min(a0 + t0, kShortSeg);
-            float4 pj[4];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) pj[v] = jp[v];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const float dx = pi.x - pj[v].x, dy = pi.y - pj[v].y, dz = pi.z - pj[v].z;
-              const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-              // one predicate (non-short-circuit), so a single branch per pair
-              // 0 < r2 < a2 as one unsigned compare of the bit patterns (r2 >= +0)
-              if (__float_as_uint(r2) - 1u < a2m1) {
-                // hardware reciprocal square root plus one Newton step (the raw
-                // instruction's error is biased, which would bias the energy)
-                float ri = __builtin_amdgcn_rsqf(r2);
-                ri = fmaf(0.5f * ri, fmaf(-r2 * ri, ri, 1.f), ri);
-                const float qj = pj[v].w;
-                if (KIND == kPairMsm) {
-                  // g*(r) = 1/r - gamma(r/a)/a with gamma the Taylor polynomial of
-                  // s^{-1/2} in t = s - 1, s = (r/a)^2: exact coefficients and
-                  // every term of one sign, then one rounding for the difference.
-                  // (Horner in r^2 with the rounded coefficients c_k / a^{2k+1}
-                  // leaves a fixed bias in every pair that does not average out
-                  // over the pairs of rigid molecules.)
-                  const float t = fmaf(r2, inv_a2, -1.f);
-                  float gm = binom_half(M);
-#pragma unroll
-                  for (int k = M - 1; k >= 0; --k) gm = fmaf(gm, t, binom_half(k));
-                  ap = fmaf(qj, fmaf(-gm, inv_a, ri), ap);
-                  // gamma'(r/a)/(a^2 r) as a polynomial in r^2
-                  float dg = dc[M];
-#pragma unroll
-                  for (int k = M - 1; k >= 1; --k) dg = fmaf(dg, r2, dc[k]);
-                  if (FORCES) {
-                    const float wq = qj * fmaf(ri, ri * ri, dg);  // q_j (-g*'(r)/r)
-                    ax = fmaf(wq, dx, ax);
-                    ay = fmaf(wq, dy, ay);
-                    az = fmaf(wq, dz, az);
-                  }
-                } else {
-                  float e, fr;                                     // e(r), -e'(r)/r
-                  if (KIND == kPairCutoff) {
-                    e = ri;
-                    fr = ri * ri * ri;
-                  } else if (KIND == kPairShiftedForce) {
-                    e = ri + fmaf(r2 * ri, pk[1], -2.f * pk[0]);
-                    fr = ri * fmaf(ri, ri, -pk[1]);
-                  } else {
-                    const float ex = __builtin_amdgcn_exp2f(pk[3] * r2);
-                    const float er = wolf_erfc(ec, pk[0] * (r2 * ri), ex);
-                    e = fmaf(er, ri, -pk[1]);
-                    fr = ri * ri * fmaf(er, ri, pk[2] * ex);
-                  }
-                  ap = fmaf(qj, e, ap);
-                  if (FORCES) {
-                    const float wq = qj * fr;
-                    ax = fmaf(wq, dx, ax);
-                    ay = fmaf(wq, dy, ay);
-                    az = fmaf(wq, dz, az);
-                  }
-                }
-              }
-            }
-          }
+          for (int t0 = 0; t0 < nmax; t0 += 4)
+            short_pairs4<M, FORCES, KIND>(jb + min(a0 + t0, kShortSeg), pi, a2m1, inv_a, inv_a2, dc, pk, ec, ax, ay, az, ap);
+        }
         }
         }
       }
